@@ -1,0 +1,368 @@
+"""Pins of the oracle's aperture sums and maps (oracle/aperture.py).
+
+Each test fixes the oracle against something other than itself:
+  * a 50-digit mpmath all-pairs brute force that builds the tangential
+    projection from tangent-plane vectors (not from the polar-angle formula);
+  * hand-derived sign conventions;
+  * the closed-form aperture mass of a singular isothermal sphere, integrated
+    by mpmath quadrature, against a catalogue laid on quadrature nodes;
+  * identities: B-mode nulling, E<->B duality, linearity, HEALPix symmetries,
+    pixel variant == galaxy variant on pixel centres;
+  * shape-noise statistics.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import aperture as A
+from oracle import filters as F
+from oracle import healpix_ref as hp
+from synth import small_catalogue
+
+DEG = math.pi / 180
+ARCMIN = DEG / 60
+
+
+# ----------------------------------------------------------------------------
+# helpers written independently of the oracle
+# ----------------------------------------------------------------------------
+
+def _mp_vec(ra, dec):
+    return [mp.cos(dec) * mp.cos(ra), mp.cos(dec) * mp.sin(ra), mp.sin(dec)]
+
+
+def _mp_q(kind, x):
+    if x >= 1:
+        return mp.mpf(0)
+    if kind == F.POLY:
+        return 6 / mp.pi * x * x * (1 - x * x)
+    t = x / mp.mpf("0.15")
+    r = mp.mpf(1) if t == 0 else mp.tanh(t) / t
+    return r / (1 + mp.exp(6 - 150 * x) + mp.exp(-47 + 50 * x))
+
+
+def mp_brute(cat, c_ra, c_dec, theta_ap, kind):
+    """All-pairs sums at 50 digits. The tangential shear is read off the
+    tangent plane of each galaxy: with d = r_centre - r_gal, x = d.e_East,
+    y = d.e_North, the bearing towards the centre is beta = atan2(x, y) and
+    a tangential shear pattern g = g_t exp(-2 i beta) must give g+ = g_t:
+    g+ = g1 cos 2beta - g2 sin 2beta, gx = g1 sin 2beta + g2 cos 2beta."""
+    mp.mp.dps = 50
+    th = mp.mpf(theta_ap)
+    C = 4 * mp.sin(th / 2) ** 2
+    out = np.zeros((len(c_ra), 5))
+    gv = [_mp_vec(mp.mpf(a), mp.mpf(d)) for a, d in zip(cat["ra"], cat["dec"])]
+    for k, (ca, cd) in enumerate(zip(c_ra, c_dec)):
+        rc = _mp_vec(mp.mpf(ca), mp.mpf(cd))
+        SE = SB = W = V = N = mp.mpf(0)
+        for i, r in enumerate(gv):
+            d = [rc[0] - r[0], rc[1] - r[1], rc[2] - r[2]]
+            c2 = d[0] ** 2 + d[1] ** 2 + d[2] ** 2
+            if not c2 < C:
+                continue
+            a = mp.mpf(cat["ra"][i])
+            de = mp.mpf(cat["dec"][i])
+            w = mp.mpf(float(cat["w"][i]))
+            g1 = mp.mpf(float(cat["g1"][i]))
+            g2 = mp.mpf(float(cat["g2"][i]))
+            theta = 2 * mp.asin(mp.sqrt(c2) / 2)
+            q = _mp_q(kind, theta / th)
+            if c2 == 0:
+                gp = gx = mp.mpf(0)
+            else:
+                eE = [-mp.sin(a), mp.cos(a), 0]
+                eN = [-mp.sin(de) * mp.cos(a), -mp.sin(de) * mp.sin(a), mp.cos(de)]
+                x = sum(d[j] * eE[j] for j in range(3))
+                y = sum(d[j] * eN[j] for j in range(3))
+                b = mp.atan2(x, y)
+                gp = g1 * mp.cos(2 * b) - g2 * mp.sin(2 * b)
+                gx = g1 * mp.sin(2 * b) + g2 * mp.cos(2 * b)
+            SE += w * q * gp
+            SB += w * q * gx
+            W += w
+            V += w * w * (g1 * g1 + g2 * g2) * q * q
+            N += 1
+        out[k] = [float(SE), float(SB), float(W), float(V), float(N)]
+    return out
+
+
+def _dest(ra0, dec0, theta, bearing):
+    """Point at great-circle distance theta along the initial bearing
+    (North through East) from (ra0, dec0), by rotating in the tangent frame."""
+    r0 = np.array([math.cos(dec0) * math.cos(ra0), math.cos(dec0) * math.sin(ra0), math.sin(dec0)])
+    eE = np.array([-math.sin(ra0), math.cos(ra0), 0.0])
+    eN = np.array([-math.sin(dec0) * math.cos(ra0), -math.sin(dec0) * math.sin(ra0), math.cos(dec0)])
+    t = np.cos(bearing)[:, None] * eN + np.sin(bearing)[:, None] * eE
+    r = np.cos(theta)[:, None] * r0 + np.sin(theta)[:, None] * t
+    return np.mod(np.arctan2(r[:, 1], r[:, 0]), 2 * math.pi), np.arcsin(np.clip(r[:, 2], -1, 1))
+
+
+def _tangential(ra, dec, ra0, dec0, gt):
+    """Shear of amplitude gt oriented tangentially about (ra0, dec0), from
+    tangent-plane vectors at each galaxy."""
+    r0 = np.array([math.cos(dec0) * math.cos(ra0), math.cos(dec0) * math.sin(ra0), math.sin(dec0)])
+    r = np.stack([np.cos(dec) * np.cos(ra), np.cos(dec) * np.sin(ra), np.sin(dec)], -1)
+    t = r0[None, :] - (r @ r0)[:, None] * r
+    eE = np.stack([-np.sin(ra), np.cos(ra), np.zeros_like(ra)], -1)
+    eN = np.stack([-np.sin(dec) * np.cos(ra), -np.sin(dec) * np.sin(ra), np.cos(dec)], -1)
+    b = np.arctan2((t * eE).sum(1), (t * eN).sum(1))
+    return gt * np.cos(2 * b), -gt * np.sin(2 * b)
+
+
+def _raw(cat, c_ra, c_dec, th, kind):
+    src = A.galaxy_sources(cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat["w"])
+    s = A.sums_kdtree(src, np.asarray(c_ra), np.asarray(c_dec), th, F.q_of(kind))
+    return np.stack([s["S_E"], s["S_B"], s["W"], s["V"], s["N"]], 1), s
+
+
+# ----------------------------------------------------------------------------
+# P1: brute force at 50 digits
+# ----------------------------------------------------------------------------
+
+SCENARIOS = [
+    # (name, centre of the catalogue cap, cap radius, theta_ap, filter)
+    ("midlat_poly_5deg", (1.0, 0.5), 9 * DEG, 5 * DEG, F.POLY),
+    ("pole_tanh_30deg", (0.3, 85 * DEG), 40 * DEG, 30 * DEG, F.TANH),
+    ("rawrap_tanh_5deg", (0.0, 0.0), 8 * DEG, 5 * DEG, F.TANH),
+    ("south_poly_30deg", (4.0, -60 * DEG), 35 * DEG, 30 * DEG, F.POLY),
+]
+
+
+@pytest.mark.parametrize("name,centre,capr,th,kind", SCENARIOS)
+def test_mp_bruteforce(name, centre, capr, th, kind):
+    cat = small_catalogue(220, seed=hash(name) % 1000, cap_radius=capr, centre=centre)
+    rng = np.random.default_rng(1)
+    sub = small_catalogue(6, seed=11, cap_radius=capr * 0.7, centre=centre, signal=False)
+    c_ra = np.concatenate([sub["ra"], cat["ra"][:2]])   # two centres sit on galaxies
+    c_dec = np.concatenate([sub["dec"], cat["dec"][:2]])
+    if name.startswith("pole"):
+        c_ra = np.append(c_ra, 1.234)
+        c_dec = np.append(c_dec, math.pi / 2)            # centre exactly at the pole
+    got, s = _raw(cat, c_ra, c_dec, th, kind)
+    assert not s["tie"].any()
+    ref = mp_brute(cat, c_ra, c_dec, th, kind)
+    assert ref[:, 4].min() > 5
+    for col in range(5):
+        scale = np.sqrt(np.mean(ref[:, col] ** 2)) + 1e-300
+        assert np.max(np.abs(got[:, col] - ref[:, col])) <= 1e-12 * scale, (name, col)
+    del rng
+
+
+def test_sign_convention_by_hand():
+    """g1 = 1 at a galaxy due East of the centre is radial (E-W elongation)
+    and gives g+ = -1; due North it is tangential and gives g+ = +1; at the
+    North-East diagonal g2 = 1 is radial and gives g+ = -1."""
+    ra0, dec0 = 1.0, 0.2
+    d = 1 * DEG
+    cases = [
+        (ra0 + d / math.cos(dec0), dec0, 1.0, 0.0, -1.0),
+        (ra0, dec0 + d, 1.0, 0.0, +1.0),
+    ]
+    for ra, dec, g1, g2, expect in cases:
+        psi = A.polar_angle(np.array([ra]), np.array([dec]), ra0, dec0)
+        gp, gx = A.tangential_cross(np.array([g1]), np.array([g2]), psi)
+        assert abs(gp[0] - expect) < 2e-2
+    # diagonal, near the equator where the frame is nearly flat
+    ra, dec = 0.01 * DEG, 0.01 * DEG
+    psi = A.polar_angle(np.array([ra]), np.array([dec]), 0.0, 0.0)
+    gp, _ = A.tangential_cross(np.array([0.0]), np.array([1.0]), psi)
+    assert abs(gp[0] + 1.0) < 1e-6
+
+
+# ----------------------------------------------------------------------------
+# P2/P3: closed-form SIS aperture mass on a quadrature catalogue
+# ----------------------------------------------------------------------------
+
+def _gl_catalogue(ra0, dec0, th, breaks, nodes, n_az, theta_e):
+    xs, ws = np.polynomial.legendre.leggauss(nodes)
+    radii, rw = [], []
+    for a, b in zip(breaks[:-1], breaks[1:]):
+        radii.append(0.5 * (b - a) * xs + 0.5 * (a + b))
+        rw.append(0.5 * (b - a) * ws)
+    radii = np.concatenate(radii) * th
+    rw = np.concatenate(rw) * th
+    az = 2 * math.pi * (np.arange(n_az) + 0.5) / n_az
+    R, B = np.meshgrid(radii, az, indexing="ij")
+    Wt = (rw * np.sin(radii))[:, None] * np.full((1, n_az), 2 * math.pi / n_az)
+    ra, dec = _dest(ra0, dec0, R.ravel(), B.ravel())
+    gt = theta_e / (2 * R.ravel())
+    g1, g2 = _tangential(ra, dec, ra0, dec0, gt)
+    return {"ra": ra, "dec": dec, "g1": g1, "g2": g2, "w": Wt.ravel()}
+
+
+@pytest.mark.parametrize("kind,th", [(F.POLY, 2 * DEG), (F.TANH, 10 * ARCMIN), (F.POLY, 20 * DEG)])
+def test_sis_closed_form(kind, th):
+    ra0, dec0 = 0.7, 0.4
+    theta_e = 2.0 * ARCMIN
+    if kind == F.POLY:
+        breaks = [0.0, 1.0]
+        nodes = 24
+    else:
+        breaks = [0.0, 0.02, 0.03, 0.036, 0.04, 0.044, 0.05, 0.06, 0.08, 0.12, 0.2, 0.35, 0.6, 0.85, 1.0]
+        nodes = 24
+    cat = _gl_catalogue(ra0, dec0, th, breaks, nodes, 48, theta_e)
+    # galaxies built exactly at the aperture edge are impossible (open interval)
+    out = A.aperture_mass_galaxy(cat, np.array([ra0]), np.array([dec0]), th, kind, A.NORM_SUMMED_CAP)
+    assert not out["tie"].any()
+    mp.mp.dps = 30
+    tt = mp.mpf(th)
+    f = lambda t: (mp.mpf(theta_e) / (2 * t)) * _mp_q(kind, t / tt) * mp.sin(t)
+    pts = [mp.mpf(b) * tt for b in breaks]
+    ref = 2 * mp.pi * mp.quad(f, pts) / tt ** 2
+    assert abs(out["W"][0] - 4 * math.pi * math.sin(th / 2) ** 2) < 1e-13 * out["W"][0]
+    assert abs(out["M_E"][0] - float(ref)) < 1e-11 * abs(float(ref))
+    assert abs(out["M_B"][0]) < 1e-13 * abs(float(ref))
+
+
+def test_b_nulling_random_tangential():
+    rng = np.random.default_rng(5)
+    ra0, dec0 = 2.0, -0.3
+    n = 5000
+    th = 3 * DEG
+    ra, dec = _dest(ra0, dec0, np.sqrt(rng.uniform(0, 1, n)) * th * 1.2, rng.uniform(0, 2 * math.pi, n))
+    g1, g2 = _tangential(ra, dec, ra0, dec0, rng.uniform(-0.3, 0.3, n))
+    cat = {"ra": ra, "dec": dec, "g1": g1, "g2": g2, "w": rng.uniform(0.5, 2, n)}
+    got, _ = _raw(cat, [ra0], [dec0], th, F.TANH)
+    assert abs(got[0, 1]) < 1e-13 * np.sum(np.abs(g1) + np.abs(g2))
+
+
+# ----------------------------------------------------------------------------
+# P4/P5: duality and linearity
+# ----------------------------------------------------------------------------
+
+def _rand_cat(seed, n=4000):
+    return small_catalogue(n, seed=seed, cap_radius=6 * DEG, centre=(3.0, -0.4))
+
+
+def test_eb_duality_and_linearity():
+    c = _rand_cat(1)
+    c2 = _rand_cat(2)
+    c2 = dict(c2, ra=c["ra"], dec=c["dec"], w=c["w"])
+    cen = small_catalogue(50, seed=3, cap_radius=4 * DEG, centre=(3.0, -0.4), signal=False)
+    th = 1.5 * DEG
+    a, _ = _raw(c, cen["ra"], cen["dec"], th, F.TANH)
+    rot = dict(c, g1=c["g2"], g2=-c["g1"])
+    b, _ = _raw(rot, cen["ra"], cen["dec"], th, F.TANH)
+    sc = np.abs(a[:, :2]).max()
+    assert np.max(np.abs(b[:, 0] - a[:, 1])) < 1e-12 * sc
+    assert np.max(np.abs(b[:, 1] + a[:, 0])) < 1e-12 * sc
+    al, be = 0.7, -1.9
+    f64 = lambda v: np.asarray(v, np.float64)
+    lin = dict(c, g1=al * f64(c["g1"]) + be * f64(c2["g1"]), g2=al * f64(c["g2"]) + be * f64(c2["g2"]))
+    d, _ = _raw(lin, cen["ra"], cen["dec"], th, F.TANH)
+    e, _ = _raw(c2, cen["ra"], cen["dec"], th, F.TANH)
+    for col in (0, 1):
+        assert np.max(np.abs(d[:, col] - (al * a[:, col] + be * e[:, col]))) < 1e-12 * sc
+    assert np.array_equal(d[:, 2], a[:, 2]) and np.array_equal(d[:, 4], a[:, 4])
+
+
+# ----------------------------------------------------------------------------
+# P6/P7: pixel variant: HEALPix symmetries, equality with the galaxy variant
+# ----------------------------------------------------------------------------
+
+def _rand_pixmap(nside, seed):
+    rng = np.random.default_rng(seed)
+    pix = np.arange(hp.npix(nside))
+    W = rng.poisson(20, pix.size).astype(np.float64)
+    W[rng.uniform(size=pix.size) < 0.05] = 0.0
+    G1 = np.where(W > 0, rng.normal(0, 1, pix.size) * np.sqrt(W), 0.0)
+    G2 = np.where(W > 0, rng.normal(0, 1, pix.size) * np.sqrt(W), 0.0)
+    E2 = np.where(W > 0, W * 0.135 + G1 * G1 * 0.01, 0.0)
+    return {"nside": nside, "pix": pix, "W": W, "G1": G1, "G2": G2, "E2": E2}
+
+
+def _rot90(nside, pix):
+    ring, j = hp.pix2ring(nside, pix)
+    rt = hp.ring_table(nside)
+    n = rt["n"][ring - 1]
+    return rt["first"][ring - 1] + np.mod(j + n // 4, n)
+
+
+def _mirror(nside, pix):
+    ring, j = hp.pix2ring(nside, pix)
+    rt = hp.ring_table(nside)
+    return rt["first"][4 * nside - ring - 1] + j
+
+
+@pytest.mark.parametrize("kind,th", [(F.TANH, 4 * DEG), (F.POLY, 9 * DEG)])
+def test_pixel_symmetries(kind, th):
+    nside = 16
+    m = _rand_pixmap(nside, 9)
+    rng = np.random.default_rng(2)
+    out = rng.choice(hp.npix(nside), 300, replace=False)
+    base = A.aperture_mass_pixel(m, out, th, kind)
+    # (i) azimuthal quarter turn maps the grid onto itself; values follow pixels
+    m1 = dict(m, pix=_rot90(nside, m["pix"]))
+    r1 = A.aperture_mass_pixel(m1, _rot90(nside, out), th, kind)
+    # (ii) reflection through the equator: g2 flips, E even, B odd
+    m2 = dict(m, pix=_mirror(nside, m["pix"]), G2=-m["G2"])
+    r2 = A.aperture_mass_pixel(m2, _mirror(nside, out), th, kind)
+    ok = ~(base["tie"] | r1["tie"] | r2["tie"])
+    assert ok.sum() > 250
+    sc = np.sqrt(np.mean(base["M_E"][ok] ** 2))
+    for k in ("M_E", "M_B", "sigma", "W", "N"):
+        assert np.max(np.abs(r1[k][ok] - base[k][ok])) < 1e-12 * max(sc, np.abs(base[k]).max()), k
+    assert np.max(np.abs(r2["M_E"][ok] - base["M_E"][ok])) < 1e-12 * sc
+    assert np.max(np.abs(r2["M_B"][ok] + base["M_B"][ok])) < 1e-12 * sc
+
+
+def test_pixel_equals_galaxy_on_centres():
+    nside = 32
+    m = _rand_pixmap(nside, 4)
+    m["W"] = np.maximum(m["W"], 1.0)
+    m["E2"] = m["G1"] ** 2 + m["G2"] ** 2
+    out = np.random.default_rng(0).choice(hp.npix(nside), 200, replace=False)
+    th = 5 * DEG
+    p = A.aperture_mass_pixel(m, out, th, F.TANH, norm=A.NORM_RAW)
+    ra, dec = hp.pix2radec(nside, m["pix"])
+    cat = {"ra": ra, "dec": dec, "g1": m["G1"] / m["W"], "g2": m["G2"] / m["W"], "w": m["W"]}
+    cra, cdec = hp.pix2radec(nside, out)
+    g = A.aperture_mass_galaxy(cat, cra, cdec, th, F.TANH, norm=A.NORM_RAW)
+    for k in ("M_E", "M_B", "sigma", "W", "N"):
+        sc = np.abs(g[k]).max()
+        assert np.max(np.abs(p[k] - g[k])) < 1e-12 * sc, k
+
+
+@pytest.mark.parametrize("nside,th", [(32, 6 * DEG), (64, 30 * DEG), (8, 50 * DEG)])
+def test_ring_candidates_match_kdtree(nside, th):
+    m = _rand_pixmap(nside, 1)
+    keep = np.random.default_rng(5).uniform(size=m["pix"].size) < 0.7   # a sparse map
+    m = {k: (v[keep] if isinstance(v, np.ndarray) else v) for k, v in m.items()}
+    out = np.concatenate([np.arange(0, 30), hp.npix(nside) - 1 - np.arange(30),
+                          np.random.default_rng(6).choice(hp.npix(nside), 100, replace=False)])
+    a = A.aperture_mass_pixel(m, out, th, F.POLY, candidates="rings")
+    b = A.aperture_mass_pixel(m, out, th, F.POLY, candidates="kdtree")
+    assert a["pairs"] == b["pairs"]
+    for k in ("M_E", "M_B", "sigma", "W", "N"):
+        assert np.max(np.abs(a[k] - b[k])) <= 1e-12 * (np.abs(b[k]).max() + 1e-300), k
+
+
+# ----------------------------------------------------------------------------
+# P9: shape-noise realisations
+# ----------------------------------------------------------------------------
+
+def test_noise_realisations_statistics():
+    """Rotating each pixel sum by a uniform spin-2 phase leaves W and V alone;
+    over realisations the mean of M_E vanishes and its variance equals
+    sigma^2 computed with E2 = |G|^2 (Eq. map_noise)."""
+    nside = 16
+    m = _rand_pixmap(nside, 8)
+    m["E2"] = m["G1"] ** 2 + m["G2"] ** 2
+    out = np.arange(0, hp.npix(nside), 37)
+    th = 8 * DEG
+    base = A.aperture_mass_pixel(m, out, th, F.POLY)
+    R = 400
+    acc = np.zeros((R, out.size))
+    for r in range(R):
+        u = np.random.default_rng([17, r]).random(m["pix"].size, dtype=np.float32)
+        G1, G2 = A.rotate_realisation(m["G1"], m["G2"], u)
+        mr = dict(m, G1=G1, G2=G2, E2=G1 ** 2 + G2 ** 2)
+        o = A.aperture_mass_pixel(mr, out, th, F.POLY)
+        assert np.allclose(o["sigma"], base["sigma"], rtol=1e-12)
+        acc[r] = o["M_E"]
+    var = acc.var(0)
+    ratio = var / base["sigma"] ** 2
+    assert abs(ratio.mean() - 1.0) < 4 * math.sqrt(2.0 / R) / math.sqrt(out.size) + 0.01
+    assert np.abs(acc.mean(0)).mean() < 4 * base["sigma"].mean() / math.sqrt(R)
