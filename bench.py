@@ -1,0 +1,216 @@
+"""Benchmark of the spherical aperture-mass hot path on one MI355X.
+
+Workload (default): the pixel-based variant at NSIDE 4096 over a 15000 deg^2
+field centred on the equator, 30 galaxies/arcmin^2 binned per pixel with
+shape noise 0.26 and SIS signal from 20000 halos; maps at every field pixel
+for theta_ap = 5', 10', 20' with the NFW-like (tanh) filter, FP32 filter and
+weight sums with FP64 geometry.
+
+One step = the whole path on the resident input: pixel-map ingest into the
+ring-range layout, plan creation (output list copy and validation) and the
+pair-sum kernels of the three scales (disc windows, geometry, filter,
+accumulation, normalisation). Inputs sit in HBM before the timed region.
+
+Prints one JSON line. `value` = pair evaluations per second (pairs of an
+aperture centre and an occupied source pixel inside the aperture, summed
+over the three scales). `roofline` reports the dominant kernel (the 20'
+scale) against the plain-ALU peak; `cpu_baseline` times the FP64 oracle on a
+bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+ARCMIN = math.pi / 10800.0
+# algorithmic work of one pair evaluation, in lane operations: FP64 chord and
+# test (7), FP32 rotation, filter and accumulation (24); see the design doc
+OPS_PER_PAIR = 31
+# plain-ALU peak: 256 CUs x 64 lanes x 2.4 GHz, one lane op per clock
+ALU_PEAK = 256 * 64 * 2.4e9
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--cpu-outputs", type=int, default=8000)
+    p.add_argument("--area", type=float, default=15000.0, help="field area in deg^2")
+    p.add_argument("--nside", type=int, default=4096)
+    return p.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pm, R, scales, n_out, seed=11):
+    """FP64 oracle on a patch of the same map: n_out apertures drawn in a
+    1-degree disc at a random point of the field, with the input pixels
+    that can reach them."""
+    from oracle import aperture as A
+    from oracle import filters as F
+    from oracle import healpix_ref as hp
+
+    nside = pm["nside"]
+    rng = np.random.default_rng(seed)
+    # patch centre: inside the field, away from its edge
+    while True:
+        ra0 = rng.uniform(-0.8 * R, 0.8 * R)
+        dec0 = rng.uniform(-0.8 * R, 0.8 * R)
+        if math.cos(dec0) * math.cos(ra0) > math.cos(0.8 * R):
+            break
+    c = np.array([math.cos(dec0) * math.cos(ra0), math.cos(dec0) * math.sin(ra0), math.sin(dec0)])
+    # candidate pixels: rings within the patch band, then exact distance
+    rt = hp.ring_table(nside)
+    colat0 = math.pi / 2 - dec0
+    reach = 1.0 * math.pi / 180 + max(scales) + 0.01
+    colat = np.arctan2(rt["sin"], rt["z"])
+    rings = np.nonzero(np.abs(colat - colat0) < reach)[0]
+    lo = rt["first"][rings[0]]
+    hi = rt["first"][rings[-1]] + rt["n"][rings[-1]]
+    sel = (pm["pix"] >= lo) & (pm["pix"] < hi)
+    pix = pm["pix"][sel]
+    v = hp.pix2vec(nside, pix)
+    d = np.arccos(np.clip(v @ c, -1, 1))
+    keep = d < reach
+    sub = {"nside": nside, "pix": pix[keep]}
+    for k in ("W", "G1", "G2", "E2"):
+        sub[k] = pm[k][sel][keep]
+    inner = sub["pix"][d[keep] < 1.0 * math.pi / 180]
+    out_pix = np.sort(rng.choice(inner, min(n_out, inner.size), replace=False))
+    t0 = time.perf_counter()
+    refs = []
+    pairs = 0
+    for th in scales:
+        r = A.aperture_mass_pixel(sub, out_pix, th, F.TANH)
+        refs.append(r)
+        pairs += int(r["N"].sum())
+    dt = time.perf_counter() - t0
+    return out_pix, refs, pairs, dt
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2609_11181_amd import api
+    from paper_2609_11181_amd import lib as L
+    from synth import config3_pixelmap
+
+    t = time.perf_counter()
+    pm, R = config3_pixelmap(area_deg2=args.area, nside=args.nside)
+    log(f"generated {pm['pix'].size} pixels in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda", 0)
+    scales = [5 * ARCMIN, 10 * ARCMIN, 20 * ARCMIN]
+    ctx = api.Context(0)
+    fid = ctx.filter(L.FILTER_TANH)
+    pix = torch.from_numpy(pm["pix"]).to(dev)
+    cols = [torch.from_numpy(pm[k]).to(dev) for k in ("W", "G1", "G2", "E2")]
+    n_out = pix.numel()
+    outs = [torch.empty(1, 5, n_out, dtype=torch.float32, device=dev) for _ in scales]
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+
+    def step(keep, ev=None):
+        data = ctx.pixel_map(args.nside, pix, *cols)
+        plans = [ctx.plan(data, L.VAR_PIXEL, args.nside, pix, [th], [fid]) for th in scales]
+        for k, p in enumerate(plans):
+            if ev is not None:
+                ev[k][0].record(stream)
+            p.run(L.NORM_SUMMED_PIXCOUNT, outs[k])
+            if ev is not None:
+                ev[k][1].record(stream)
+        keep.append((data, plans))
+
+    keep = []
+    for _ in range(args.warmup):
+        step(keep)
+    torch.cuda.synchronize()
+    keep.clear()
+    events = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in scales]
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(keep, events[s])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt * 1e3 / args.steps
+    pairs_scale = [p.last_pairs() for p in keep[-1][1]]
+    pairs = float(sum(pairs_scale))
+    kern_ms = [float(np.mean([events[s][k][0].elapsed_time(events[s][k][1]) for s in range(args.steps)]))
+               for k in range(len(scales))]
+    value = pairs / (ms_step / 1e3)
+    dom = int(np.argmax(kern_ms))
+    achieved = pairs_scale[dom] * OPS_PER_PAIR / (kern_ms[dom] / 1e3)
+    log(f"step {ms_step:.2f} ms; kernels {['%.2f' % k for k in kern_ms]} ms; pairs {pairs:.4e}")
+    res = {
+        "metric": "pair-evals/s at NSIDE 4096 (pixel-based aperture mass, 3 scales)",
+        "value": value,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"pixel-based sphS_pix, NSIDE {args.nside}, {args.area:g} deg2 cap, theta_ap 5/10/20 arcmin, "
+                        "tanh filter, summed normalisation",
+            "n_pixels": int(n_out),
+            "pairs_per_step": pairs,
+            "kernel_ms": kern_ms,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_pixel_f32 (20 arcmin)",
+            "achieved": achieved / 1e12,
+            "peak": ALU_PEAK / 1e12,
+            "unit": "Tlane-op/s",
+            "frac": achieved / ALU_PEAK,
+            "traffic": None,
+        },
+    }
+    # accuracy on the oracle sample + CPU baseline
+    if not args.no_cpu:
+        out_pix, refs, cpairs, cdt = cpu_baseline(pm, R, scales, args.cpu_outputs)
+        idx = np.searchsorted(pm["pix"], out_pix)
+        errs = []
+        for k, r in enumerate(refs):
+            g = outs[k][0, 0].cpu().numpy()[idx].astype(np.float64)
+            ok = ~r["tie"]
+            rms = math.sqrt(np.mean(r["M_E"][ok] ** 2))
+            errs.append(float(np.max(np.abs(g[ok] - r["M_E"][ok])) / rms))
+        res["max_rel_err_vs_oracle"] = errs
+        res["cpu_baseline"] = {
+            "value": cpairs / cdt,
+            "unit": "pair-evals/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"{out_pix.size} apertures x 3 scales in a 1-degree patch of the same map "
+                      f"({cpairs} pairs, {cdt:.1f} s, numpy FP64 single thread)",
+        }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * smartap.h - C ABI of libsmartap.so, spherical shear-based aperture-mass
+ * maps on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for every requested HEALPix pixel centre p and every
+ * aperture scale theta_ap, the filtered sums over the sources inside the
+ * aperture disc (great-circle distance < theta_ap):
+ *
+ *   S_E = sum q(theta/theta_ap) A+      S_B = sum q A x      (Eq. map_gammat,
+ *   W   = sum Wsrc                      V   = sum q^2 Vsrc    Eq. map,
+ *   N   = number of sources with Wsrc > 0 (pixel) / in the disc (galaxy)
+ *                                                             Eq. map_noise)
+ *
+ * with A+ = A1 cos 2psi + A2 sin 2psi and Ax = -A1 sin 2psi + A2 cos 2psi
+ * (Eq. gammat), psi the spherical polar angle of the source about the
+ * centre (Sect. 2.3). A source is a galaxy (A = w g, Wsrc = w,
+ * Vsrc = w^2 |g|^2; brute-force variant, Sect. 3.1) or a HEALPix pixel of a
+ * binned shear map (A = sum w g, Wsrc = sum w, Vsrc = sum w^2 |g|^2 placed
+ * at the pixel centre; pixel-based variant, Sect. 3.2). The summed
+ * normalisation (Sect. 2.4, Sect. 3.1 step 5) turns sums into maps:
+ *
+ *   M_E = (A_ap / theta_ap^2) S_E / W,   M_B likewise,
+ *   sigma = (A_ap / theta_ap^2) sqrt(V / 2) / W,
+ *
+ * A_ap = 2 pi (1 - cos theta_ap) (SMART_NORM_SUMMED_CAP) or N * Omega_pix
+ * (SMART_NORM_SUMMED_PIXCOUNT); W = 0 yields zeros.
+ *
+ * Conventions
+ *   - Angles in radians. Right ascension in [0, 2 pi), declination in
+ *     [-pi/2, pi/2]. Shear components in the local frame x = East (+ra),
+ *     y = North (+dec).
+ *   - Pixel numbers are HEALPix RING, int64, NSIDE a power of two.
+ *   - Pointers named d_* are DEVICE pointers owned by the caller; they must
+ *     stay valid until the work queued on `stream` has completed. Host
+ *     pointers are named h_* and are read before the call returns.
+ *   - Handles (smart_ctx, smart_data, smart_plan) are owned by the library
+ *     and released with the matching *_free call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls are asynchronous on it unless stated.
+ *   - Every int-returning call returns SMART_OK or a negative error code;
+ *     arguments are validated before any work is queued, nothing is
+ *     launched on error, and smart_last_error() returns a message for the
+ *     calling thread. No call aborts the process.
+ *   - A smart_ctx is bound to one device and must not be used from two
+ *     threads at once.
+ */
+#ifndef SMARTAP_H
+#define SMARTAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smart_ctx_s* smart_ctx;
+typedef struct smart_data_s* smart_data;
+typedef struct smart_plan_s* smart_plan;
+
+enum {
+  SMART_OK = 0,
+  SMART_EINVAL = -1,       /* invalid argument                           */
+  SMART_ENOMEM = -2,       /* device allocation failed                   */
+  SMART_EDEVICE = -3,      /* HIP runtime error                          */
+  SMART_EUNSUPPORTED = -4, /* valid but not supported by this build      */
+  SMART_EINTERNAL = -5
+};
+
+/* Filters q(x), x = theta / theta_ap, zero for x >= 1.                       */
+enum {
+  SMART_FILTER_POLY = 0, /* (6/pi) x^2 (1 - x^2); no parameters               */
+  SMART_FILTER_TANH = 1, /* tanh(x/xc)/(x/xc) / (1 + e^(a-bx) + e^(-c+dx));
+                            params = {xc, a, b, c, d}, or NULL for
+                            {0.15, 6, 150, 47, 50}                          */
+  SMART_FILTER_TABLE = 2 /* params = q at n_params >= 2 uniform nodes on [0,1]
+                            (last node = left limit at x = 1)               */
+};
+
+/* Variants (Table 1 of the paper).                                           */
+enum {
+  SMART_VAR_GALAXY = 0, /* brute force on galaxy positions (sphS_pos)         */
+  SMART_VAR_PIXEL = 1   /* shear summed per pixel, filter at pixel centres
+                           (sphS_pix)                                        */
+};
+
+/* Arithmetic of the pair sums.                                               */
+enum {
+  SMART_PREC_FP64 = 0,        /* everything in FP64; outputs are double      */
+  SMART_PREC_FP32_GEO64 = 1,  /* membership and separations in FP64, pair
+                                 terms in FP32, FP64 totals; outputs float  */
+  SMART_PREC_BF16X3 = 2       /* batched realisations only: split-BF16 MFMA
+                                 with FP32 accumulation                      */
+};
+
+enum {
+  SMART_NORM_SUMMED_CAP = 0,      /* A_ap = spherical cap area               */
+  SMART_NORM_SUMMED_PIXCOUNT = 1, /* A_ap = N * pixel area                   */
+  SMART_NORM_RAW = 2              /* channels are S_E, S_B, V, W, N          */
+};
+
+/* Output channel order of smart_run: [n_scales][5][n_out].                  */
+enum { SMART_CH_ME = 0, SMART_CH_MB = 1, SMART_CH_SIGMA = 2, SMART_CH_W = 3, SMART_CH_N = 4 };
+
+/* ------------------------------------------------------------------------ */
+/* Context                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Bind a context to HIP device `hip_device`. */
+int smart_init(int hip_device, smart_ctx* out);
+void smart_finalize(smart_ctx ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* smart_last_error(void);
+
+/* Library version string. */
+const char* smart_version(void);
+
+/* Define a filter (Sect. 3.1 step 3). Builds, on the host in FP64, a
+ * piecewise-cubic table in x with 2048 intervals (error below 1e-8 of the
+ * filter maximum for the built-in kinds) and uploads it. Synchronous.
+ * filter_id receives a small non-negative integer. */
+int smart_filter_define(smart_ctx ctx, int kind, const double* h_params, int n_params, int* filter_id);
+
+/* Copy a filter's table to the host: h_coef receives 4 * n_intervals floats
+ * (cubic coefficients c0..c3 in the local coordinate f in [0,1) of each
+ * interval); n_intervals receives the count. h_coef may be NULL to query. */
+int smart_filter_table(smart_ctx ctx, int filter_id, float* h_coef, int* n_intervals);
+
+/* ------------------------------------------------------------------------ */
+/* Input data                                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Partition a galaxy catalogue by HEALPix pixel (Sect. 3.4): assign each
+ * galaxy its RING pixel at nside_bin, sort stably by pixel, build the offset
+ * table (pixel n owns sorted rows [off[n], off[n+1])), and keep a sorted
+ * copy of positions and shears on the device. With want_pixel_sums != 0 it
+ * also forms the per-pixel sums W, G1, G2, E2 of Sect. 3.2 step 2, so the
+ * same handle can feed the pixel-based variant (at NSIDE = nside_bin).
+ *   d_ra, d_dec : n doubles (radians)
+ *   d_g1, d_g2  : n floats
+ *   d_w         : n floats, or NULL for unit weights
+ *   nside_bin   : power of two, 1 .. 8192
+ * Synchronises `stream` once (to size the sorted ring range). */
+int smart_bin_galaxies(smart_ctx ctx, int64_t n, const double* d_ra, const double* d_dec, const float* d_g1,
+                       const float* d_g2, const float* d_w, int nside_bin, int want_pixel_sums, void* stream,
+                       smart_data* out);
+
+/* Wrap an already binned shear map (Sect. 3.2 step 2) given as n entries of
+ * strictly increasing RING pixels with their sums. The library copies it
+ * into a dense ring-range layout it owns. Synchronises `stream` once.
+ *   d_ring_pix : n int64, strictly increasing, in [0, 12 nside^2)
+ *   d_W, d_G1, d_G2, d_E2 : n floats each */
+int smart_pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* d_ring_pix, const float* d_W,
+                    const float* d_G1, const float* d_G2, const float* d_E2, void* stream, smart_data* out);
+
+/* Query a data handle. Any output pointer may be NULL.
+ *   n_gal       : galaxies held (0 for a pixel map)
+ *   nside       : binning NSIDE
+ *   pix_first   : first RING pixel of the dense pixel range
+ *   n_dense     : length of the dense pixel range
+ *   r_bin       : largest galaxy-to-pixel-centre distance (radians) */
+int smart_data_info(smart_data data, int64_t* n_gal, int* nside, int64_t* pix_first, int64_t* n_dense,
+                    double* r_bin);
+
+/* Copy partition results to caller device buffers (any may be NULL):
+ *   d_order   : n_gal int64, catalogue index of each sorted row
+ *   d_offsets : 12 nside^2 + 1 int64 offset table
+ *   d_sums    : 4 * n_dense floats, per dense pixel (G1, G2, W, E2)
+ * Asynchronous on `stream`. */
+int smart_data_export(smart_data data, int64_t* d_order, int64_t* d_offsets, float* d_sums, void* stream);
+
+void smart_data_free(smart_data data);
+
+/* ------------------------------------------------------------------------ */
+/* Plans and runs                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Prepare maps at the centres of n_out RING pixels at nside_out, for
+ * n_scales apertures theta_ap_rad[k] with filters filter_ids[k].
+ *   variant   : SMART_VAR_GALAXY (data from smart_bin_galaxies) or
+ *               SMART_VAR_PIXEL (pixel sums; nside_out must equal the
+ *               data's NSIDE)
+ *   precision : SMART_PREC_FP64 or SMART_PREC_FP32_GEO64
+ *   d_out_pix : n_out int64 RING pixels (copied; any order, duplicates ok)
+ *   theta_ap  : 0 < theta_ap <= 0.25 rad (about 14.3 degrees)
+ * The plan references `data`, which must outlive it. Synchronises `stream`
+ * once (validation of the pixel list). */
+int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out, int64_t n_out,
+                      const int64_t* d_out_pix, int n_scales, const double* h_theta_ap, const int* h_filter_ids,
+                      int precision, void* stream, smart_plan* out);
+
+/* Compute the maps. out is a device buffer of n_scales * 5 * n_out values,
+ * float for SMART_PREC_FP32_GEO64 and double for SMART_PREC_FP64, laid out
+ * [scale][channel][output] with channels SMART_CH_*. */
+int smart_run(smart_plan plan, int norm, void* d_out, void* stream);
+
+/* Total number of source-centre pairs inside the apertures of the last
+ * smart_run (sum of the N channel over outputs and scales; the pixel
+ * variant counts occupied pixels). Synchronises `stream`. */
+int smart_last_pairs(smart_plan plan, void* stream, double* pairs);
+
+void smart_plan_free(smart_plan plan);
+
+/* ------------------------------------------------------------------------ */
+/* Shape-noise realisations (pixel variant)                                  */
+/* ------------------------------------------------------------------------ */
+
+/* n_real noise maps per scale: the pixel sums G_j are rotated by the spin-2
+ * phase exp(2 i pi u[r][j]) (random orientations, Sect. 1 and Sect. 5.3)
+ * and the E/B maps recomputed with the same apertures, weights and
+ * normalisation (W, V and N do not change under the rotation).
+ *   d_u    : n_real * n_dense floats in [0,1), row r for realisation r,
+ *            column = dense pixel index (see smart_data_info)
+ *   d_out  : float, [n_scales][n_real][2][n_out] (E then B)
+ *   precision : SMART_PREC_FP32_GEO64 (plain pair sums per realisation) or
+ *               SMART_PREC_BF16X3 (split-BF16 MFMA contraction)
+ * The plan must be a pixel-variant FP32 plan. */
+int smart_noise_batch(smart_plan plan, const float* d_u, int n_real, int norm, int precision, float* d_out,
+                      void* stream);
+
+/* Several plans in one persistent launch (pixel variant, FP32): a single
+ * kernel drains a work list holding the tiles of every plan and scale,
+ * longest first. outs[k] is the smart_run output buffer of plans[k]. */
+int smart_mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* d_outs,
+                      void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMARTAP_H */

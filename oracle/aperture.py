@@ -13,8 +13,8 @@ aperture (great-circle distance theta_pi < theta_ap; Sect. 3.1 step 1):
   atan2 of numerator and denominator both multiplied by cos d_0 > 0;
 * tangential and cross shear (Eq. gammat):
   g+ = g1 cos 2psi + g2 sin 2psi, gx = -g1 sin 2psi + g2 cos 2psi;
-  a source exactly at the centre has no defined psi and contributes
-  g+ = gx = 0 (it still counts in W, N and V);
+  a source at the centre (closer than 1e-10 rad) has no defined psi and
+  contributes g+ = gx = 0 (it still counts in W, N and V);
 * the filter q(theta/theta_ap) (Sect. 3.1 step 3).
 
 Sums over the aperture (Eq. map and Eq. map_noise, Sect. 3.1 step 4):
@@ -60,6 +60,11 @@ from . import healpix_ref as hp
 from .filters import q_of
 
 TIE_REL = 1e-10
+# A source within 1e-10 rad of the centre counts as coincident: its polar
+# angle is undefined (and the last-bit rounding of two unit vectors of the
+# same point already makes their difference nonzero), so it adds no shear
+# term; it still counts in W, N and V.
+COINCIDENT_C2 = 1e-20
 
 NORM_SUMMED_CAP = 0
 NORM_SUMMED_PIXCOUNT = 1
@@ -134,7 +139,7 @@ def _pair_sums(src: Sources, src_vec, cand_centre, cand_src, c_ra, c_dec, c_vec,
     q = qfun(theta / theta_ap)
     psi = polar_angle(src.ra[si], src.dec[si], c_ra[ci], c_dec[ci])
     gp, gx = tangential_cross(src.A1[si], src.A2[si], psi)
-    at_centre = c2 == 0.0
+    at_centre = c2 < COINCIDENT_C2
     gp = np.where(at_centre, 0.0, gp)
     gx = np.where(at_centre, 0.0, gx)
     out = {

@@ -1,0 +1,408 @@
+// C ABI of libsmartap (declared in include/smartap.h): argument checks,
+// handle management and launch sequencing. All device work lives in the
+// kernel translation units.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <cstdio>
+#include <string>
+
+#include "hpx_ring.h"
+#include "smart_internal.h"
+
+namespace smart {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace smart
+
+using namespace smart;
+
+namespace {
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+int set_device(smart_ctx ctx) {
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(SMART_EDEVICE, "hipSetDevice failed");
+  return SMART_OK;
+}
+
+#define CHECK_HIP(x)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(SMART_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* smart_last_error(void) { return g_last_error.c_str(); }
+
+const char* smart_version(void) { return "smartap 0.1 (gfx950)"; }
+
+int smart_init(int hip_device, smart_ctx* out) {
+  if (!out) return fail(SMART_EINVAL, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(SMART_EDEVICE, "no HIP device");
+  if (hip_device < 0 || hip_device >= count) return fail(SMART_EINVAL, "device index out of range");
+  if (hipSetDevice(hip_device) != hipSuccess) return fail(SMART_EDEVICE, "hipSetDevice failed");
+  smart_ctx c = new smart_ctx_s();
+  c->device = hip_device;
+  *out = c;
+  return SMART_OK;
+}
+
+void smart_finalize(smart_ctx ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  for (auto& f : ctx->filters) {
+    hipFree(f.d_table);
+    hipFree(f.d_table_lo);
+  }
+  if (ctx->d_temp) hipFree(ctx->d_temp);
+  delete ctx;
+}
+
+int smart_filter_define(smart_ctx ctx, int kind, const double* h_params, int n_params, int* filter_id) {
+  if (!ctx || !filter_id) return fail(SMART_EINVAL, "NULL context or filter_id");
+  FilterDef f;
+  f.kind = kind;
+  if (kind == SMART_FILTER_POLY) {
+    if (n_params != 0) return fail(SMART_EINVAL, "the polynomial filter takes no parameters");
+  } else if (kind == SMART_FILTER_TANH) {
+    const double def[5] = {0.15, 6.0, 150.0, 47.0, 50.0};
+    if (h_params == nullptr) {
+      memcpy(f.params, def, sizeof def);
+    } else {
+      if (n_params != 5) return fail(SMART_EINVAL, "the tanh filter takes 5 parameters");
+      for (int k = 0; k < 5; ++k) {
+        if (!isfinite(h_params[k])) return fail(SMART_EINVAL, "non-finite filter parameter");
+        f.params[k] = h_params[k];
+      }
+      if (!(f.params[0] > 0)) return fail(SMART_EINVAL, "tanh filter scale must be positive");
+    }
+  } else if (kind == SMART_FILTER_TABLE) {
+    if (!h_params || n_params < 2) return fail(SMART_EINVAL, "a table filter needs >= 2 samples");
+    f.samples.assign(h_params, h_params + n_params);
+    for (double v : f.samples)
+      if (!isfinite(v)) return fail(SMART_EINVAL, "non-finite filter sample");
+  } else {
+    return fail(SMART_EINVAL, "unknown filter kind");
+  }
+  int rc;
+  if ((rc = set_device(ctx))) return rc;
+  if ((rc = build_filter(f))) return rc;
+  ctx->filters.push_back(f);
+  *filter_id = (int)ctx->filters.size() - 1;
+  return SMART_OK;
+}
+
+int smart_filter_table(smart_ctx ctx, int filter_id, float* h_coef, int* n_intervals) {
+  if (!ctx || !n_intervals) return fail(SMART_EINVAL, "NULL argument");
+  if (filter_id < 0 || filter_id >= (int)ctx->filters.size()) return fail(SMART_EINVAL, "unknown filter id");
+  *n_intervals = kFilterIntervals;
+  if (h_coef) memcpy(h_coef, ctx->filters[filter_id].h_table.data(), sizeof(float) * 4 * kFilterIntervals);
+  return SMART_OK;
+}
+
+void smart_data_free(smart_data d) {
+  if (!d) return;
+  if (d->ctx) hipSetDevice(d->ctx->device);
+  hipFree(d->P);
+  hipFree(d->F);
+  hipFree(d->G);
+  hipFree(d->order);
+  hipFree(d->offsets);
+  hipFree(d->sums);
+  delete d;
+}
+
+int smart_bin_galaxies(smart_ctx ctx, int64_t n, const double* d_ra, const double* d_dec, const float* d_g1,
+                       const float* d_g2, const float* d_w, int nside_bin, int want_pixel_sums, void* stream,
+                       smart_data* out) {
+  if (!ctx || !out) return fail(SMART_EINVAL, "NULL context or out");
+  *out = nullptr;
+  if (n < 0 || n > 2000000000LL) return fail(SMART_EINVAL, "galaxy count must be in [0, 2e9]");
+  if (n > 0 && (!d_ra || !d_dec || !d_g1 || !d_g2)) return fail(SMART_EINVAL, "NULL catalogue column");
+  if (!is_pow2(nside_bin) || nside_bin > kMaxNside) return fail(SMART_EINVAL, "nside_bin must be a power of two <= 8192");
+  int rc;
+  if ((rc = set_device(ctx))) return rc;
+  smart_data d = new smart_data_s();
+  d->ctx = ctx;
+  d->kind = 0;
+  rc = bin_galaxies(ctx, n, d_ra, d_dec, d_g1, d_g2, d_w, nside_bin, want_pixel_sums, (hipStream_t)stream, d);
+  if (rc) {
+    smart_data_free(d);
+    return rc;
+  }
+  *out = d;
+  return SMART_OK;
+}
+
+int smart_pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* d_ring_pix, const float* d_W,
+                    const float* d_G1, const float* d_G2, const float* d_E2, void* stream, smart_data* out) {
+  if (!ctx || !out) return fail(SMART_EINVAL, "NULL context or out");
+  *out = nullptr;
+  if (!is_pow2(nside) || nside > kMaxNside) return fail(SMART_EINVAL, "nside must be a power of two <= 8192");
+  if (n <= 0 || n > 12LL * nside * nside) return fail(SMART_EINVAL, "pixel count must be in [1, 12 nside^2]");
+  if (!d_ring_pix || !d_W || !d_G1 || !d_G2 || !d_E2) return fail(SMART_EINVAL, "NULL pixel-map column");
+  int rc;
+  if ((rc = set_device(ctx))) return rc;
+  smart_data d = new smart_data_s();
+  d->ctx = ctx;
+  rc = pixel_map(ctx, nside, n, d_ring_pix, d_W, d_G1, d_G2, d_E2, (hipStream_t)stream, d);
+  if (rc) {
+    smart_data_free(d);
+    return rc;
+  }
+  *out = d;
+  return SMART_OK;
+}
+
+int smart_data_info(smart_data d, int64_t* n_gal, int* nside, int64_t* pix_first, int64_t* n_dense, double* r_bin) {
+  if (!d) return fail(SMART_EINVAL, "NULL data");
+  if (n_gal) *n_gal = d->n_gal;
+  if (nside) *nside = d->nside;
+  if (pix_first) *pix_first = d->pix_first;
+  if (n_dense) *n_dense = d->n_dense;
+  if (r_bin) *r_bin = d->r_bin;
+  return SMART_OK;
+}
+
+int smart_data_export(smart_data d, int64_t* d_order, int64_t* d_offsets, float* d_sums, void* stream) {
+  if (!d) return fail(SMART_EINVAL, "NULL data");
+  int rc;
+  if ((rc = set_device(d->ctx))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (d_order) {
+    if (!d->order) return fail(SMART_EINVAL, "data holds no catalogue order");
+    CHECK_HIP(hipMemcpyAsync(d_order, d->order, sizeof(int64_t) * d->n_gal, hipMemcpyDeviceToDevice, st));
+  }
+  if (d_offsets) {
+    if (!d->offsets) return fail(SMART_EINVAL, "data holds no offset table");
+    CHECK_HIP(hipMemcpyAsync(d_offsets, d->offsets, sizeof(int64_t) * (12LL * d->nside * d->nside + 1),
+                             hipMemcpyDeviceToDevice, st));
+  }
+  if (d_sums) {
+    if (!d->sums) return fail(SMART_EINVAL, "data holds no pixel sums");
+    CHECK_HIP(hipMemcpyAsync(d_sums, d->sums, sizeof(float4) * d->n_dense, hipMemcpyDeviceToDevice, st));
+  }
+  return SMART_OK;
+}
+
+void smart_plan_free(smart_plan p) {
+  if (!p) return;
+  if (p->ctx) hipSetDevice(p->ctx->device);
+  hipFree(p->out_pix);
+  hipFree(p->d_pairs);
+  hipFree(p->rot_map);
+  delete p;
+}
+
+int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out, int64_t n_out,
+                      const int64_t* d_out_pix, int n_scales, const double* h_theta_ap, const int* h_filter_ids,
+                      int precision, void* stream, smart_plan* out) {
+  if (!ctx || !data || !out) return fail(SMART_EINVAL, "NULL context, data or out");
+  *out = nullptr;
+  if (data->ctx != ctx) return fail(SMART_EINVAL, "data belongs to another context");
+  if (variant != SMART_VAR_GALAXY && variant != SMART_VAR_PIXEL) return fail(SMART_EINVAL, "unknown variant");
+  if (precision != SMART_PREC_FP64 && precision != SMART_PREC_FP32_GEO64)
+    return fail(SMART_EINVAL, "plan precision must be SMART_PREC_FP64 or SMART_PREC_FP32_GEO64");
+  if (!is_pow2(nside_out) || nside_out > kMaxNside) return fail(SMART_EINVAL, "nside_out must be a power of two <= 8192");
+  if (n_out < 0 || n_out > 12LL * nside_out * nside_out * 4) return fail(SMART_EINVAL, "bad output count");
+  if (n_out > 0 && !d_out_pix) return fail(SMART_EINVAL, "NULL output pixel list");
+  if (n_scales < 1 || n_scales > 64) return fail(SMART_EINVAL, "n_scales must be in [1, 64]");
+  if (!h_theta_ap || !h_filter_ids) return fail(SMART_EINVAL, "NULL scale arrays");
+  for (int k = 0; k < n_scales; ++k) {
+    if (!(h_theta_ap[k] > 0.0) || !(h_theta_ap[k] <= kMaxThetaAp))
+      return fail(SMART_EINVAL, "theta_ap must be in (0, 0.25] radians");
+    if (h_filter_ids[k] < 0 || h_filter_ids[k] >= (int)ctx->filters.size())
+      return fail(SMART_EINVAL, "unknown filter id");
+    if (precision == SMART_PREC_FP64 && ctx->filters[h_filter_ids[k]].kind == SMART_FILTER_TABLE)
+      return fail(SMART_EUNSUPPORTED, "table filters run in FP32 plans only");
+  }
+  if (variant == SMART_VAR_GALAXY) {
+    if (!data->offsets) return fail(SMART_EINVAL, "the galaxy variant needs a binned catalogue");
+  } else {
+    if (!data->sums) return fail(SMART_EINVAL, "the pixel variant needs pixel sums");
+    if (nside_out != data->nside) return fail(SMART_EINVAL, "the pixel variant needs nside_out == map NSIDE");
+  }
+  int rc;
+  if ((rc = set_device(ctx))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  smart_plan p = new smart_plan_s();
+  p->ctx = ctx;
+  p->data = data;
+  p->variant = variant;
+  p->precision = precision;
+  p->nside_out = nside_out;
+  p->n_out = n_out;
+  p->theta_ap.assign(h_theta_ap, h_theta_ap + n_scales);
+  p->filter_ids.assign(h_filter_ids, h_filter_ids + n_scales);
+  auto bail = [&](int code, const std::string& m) {
+    smart_plan_free(p);
+    return fail(code, m);
+  };
+  if (hipMalloc(&p->out_pix, sizeof(int64_t) * (n_out ? n_out : 1)) != hipSuccess ||
+      hipMalloc(&p->d_pairs, sizeof(double)) != hipSuccess)
+    return bail(SMART_ENOMEM, "device allocation failed for the plan");
+  if (n_out > 0) {
+    int* flag = nullptr;
+    if (hipMalloc(&flag, sizeof(int)) != hipSuccess) return bail(SMART_ENOMEM, "allocation failed");
+    int h = 0;
+    hipError_t e = hipMemcpyAsync(p->out_pix, d_out_pix, sizeof(int64_t) * n_out, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int), st);
+    // range check only: reuse the monotonic check and ignore its order bit
+    if (e == hipSuccess) e = launch_check_pixels(p->out_pix, n_out, 12LL * nside_out * nside_out, flag, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(flag);
+    if (e != hipSuccess) return bail(SMART_EDEVICE, std::string("plan validation failed: ") + hipGetErrorString(e));
+    if (h & 1) return bail(SMART_EINVAL, "output pixel out of range for nside_out");
+  }
+  *out = p;
+  return SMART_OK;
+}
+
+int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
+  if (!p || (!d_out && p->n_out > 0)) return fail(SMART_EINVAL, "NULL plan or output");
+  if (norm < SMART_NORM_SUMMED_CAP || norm > SMART_NORM_RAW) return fail(SMART_EINVAL, "unknown normalisation");
+  int rc;
+  if ((rc = set_device(p->ctx))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  smart_data d = p->data;
+  const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
+  for (int k = 0; k < (int)p->theta_ap.size(); ++k) {
+    const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);
+    hipError_t e;
+    if (p->variant == SMART_VAR_PIXEL) {
+      PixelArgs a{};
+      a.out_pix = p->out_pix;
+      a.n_out = p->n_out;
+      a.nside_out = p->nside_out;
+      a.map = d->sums;
+      a.nside_in = d->nside;
+      a.ring_lo = d->ring_lo;
+      a.ring_hi = d->ring_hi;
+      a.pix_first = d->pix_first;
+      a.out = d_out;
+      a.norm = norm;
+      a.scale = k;
+      e = launch_pixel(a, s, p->precision, st);
+    } else {
+      GalaxyArgs a{};
+      a.out_pix = p->out_pix;
+      a.n_out = p->n_out;
+      a.nside_out = p->nside_out;
+      a.P = d->P;
+      a.F = d->F;
+      a.G = d->G;
+      a.offsets = d->offsets;
+      a.nside_bin = d->nside;
+      a.r_bin = d->r_bin;
+      a.out = d_out;
+      a.norm = norm;
+      a.scale = k;
+      e = launch_galaxy(a, s, p->precision, st);
+    }
+    if (e != hipSuccess) return fail(SMART_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  }
+  p->last_out = d_out;
+  p->last_norm = norm;
+  return SMART_OK;
+}
+
+int smart_last_pairs(smart_plan p, void* stream, double* pairs) {
+  if (!p || !pairs) return fail(SMART_EINVAL, "NULL argument");
+  if (!p->last_out) return fail(SMART_EINVAL, "no run recorded on this plan");
+  int rc;
+  if ((rc = set_device(p->ctx))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  CHECK_HIP(launch_sum_n(p->last_out, p->precision, p->n_out, (int)p->theta_ap.size(), p->d_pairs, st));
+  CHECK_HIP(hipMemcpyAsync(pairs, p->d_pairs, sizeof(double), hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipStreamSynchronize(st));
+  return SMART_OK;
+}
+
+int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int precision, float* d_out,
+                      void* stream) {
+  if (!p || !d_u || !d_out) return fail(SMART_EINVAL, "NULL argument");
+  if (p->variant != SMART_VAR_PIXEL || p->precision != SMART_PREC_FP32_GEO64)
+    return fail(SMART_EINVAL, "noise batches need a pixel-variant FP32 plan");
+  if (n_real < 1) return fail(SMART_EINVAL, "n_real must be >= 1");
+  if (norm < SMART_NORM_SUMMED_CAP || norm > SMART_NORM_RAW) return fail(SMART_EINVAL, "unknown normalisation");
+  int rc;
+  if ((rc = set_device(p->ctx))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  smart_data d = p->data;
+  if (precision == SMART_PREC_BF16X3) return noise_bf16x3(p, d_u, n_real, norm, d_out, st);
+  if (precision != SMART_PREC_FP32_GEO64) return fail(SMART_EINVAL, "noise precision must be FP32 or BF16X3");
+  // plain path: rotate the map, then one ordinary pair-sum pass per realisation
+  if (p->rot_len < d->n_dense) {
+    hipFree(p->rot_map);
+    p->rot_map = nullptr;
+    p->rot_len = 0;
+    if (hipMalloc(&p->rot_map, sizeof(float4) * d->n_dense) != hipSuccess)
+      return fail(SMART_ENOMEM, "allocation failed for the rotated map");
+    p->rot_len = d->n_dense;
+  }
+  const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
+  const int ns = (int)p->theta_ap.size();
+  // each pass writes 5 channels; E and B are copied out of a staging buffer
+  float* stage = nullptr;
+  if (hipMallocAsync((void**)&stage, sizeof(float) * 5 * p->n_out, st) != hipSuccess)
+    return fail(SMART_ENOMEM, "allocation failed for staging");
+  for (int r = 0; r < n_real; ++r) {
+    hipError_t e = launch_rotate_map(d->sums, d_u + (int64_t)r * d->n_dense, d->n_dense, p->rot_map, st);
+    if (e != hipSuccess) return fail(SMART_EDEVICE, "rotation kernel failed");
+    for (int k = 0; k < ns; ++k) {
+      const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);
+      PixelArgs a{};
+      a.out_pix = p->out_pix;
+      a.n_out = p->n_out;
+      a.nside_out = p->nside_out;
+      a.map = p->rot_map;
+      a.nside_in = d->nside;
+      a.ring_lo = d->ring_lo;
+      a.ring_hi = d->ring_hi;
+      a.pix_first = d->pix_first;
+      a.out = stage;
+      a.norm = norm;
+      a.scale = 0;
+      e = launch_pixel(a, s, SMART_PREC_FP32_GEO64, st);
+      if (e != hipSuccess) return fail(SMART_EDEVICE, "pair kernel failed");
+      float* dst = d_out + (((int64_t)k * n_real + r) * 2) * p->n_out;
+      e = hipMemcpyAsync(dst, stage, sizeof(float) * 2 * p->n_out, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return fail(SMART_EDEVICE, "copy failed");
+    }
+  }
+  hipFreeAsync(stage, st);
+  return SMART_OK;
+}
+
+int smart_mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* d_outs,
+                      void* stream) {
+  if (!ctx || n_plans < 1 || !plans || !norms || !d_outs) return fail(SMART_EINVAL, "bad arguments");
+  for (int k = 0; k < n_plans; ++k) {
+    if (!plans[k] || !d_outs[k]) return fail(SMART_EINVAL, "NULL plan or output");
+    if (plans[k]->ctx != ctx) return fail(SMART_EINVAL, "plan belongs to another context");
+    if (plans[k]->variant != SMART_VAR_PIXEL || plans[k]->precision != SMART_PREC_FP32_GEO64)
+      return fail(SMART_EINVAL, "mixed batches take pixel-variant FP32 plans");
+    if (norms[k] < SMART_NORM_SUMMED_CAP || norms[k] > SMART_NORM_RAW) return fail(SMART_EINVAL, "unknown normalisation");
+  }
+  int rc;
+  if ((rc = set_device(ctx))) return rc;
+  return mixed_batch(ctx, n_plans, plans, norms, d_outs, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,304 @@
+// Catalogue partition and pixel sums.
+//
+// Partition (Sect. 3.4): every galaxy gets the RING pixel containing it,
+// the catalogue is sorted stably by that pixel so that the galaxies of one
+// pixel occupy a contiguous run of rows, and an offset table maps pixel n to
+// rows [off[n], off[n+1]). The sorted rows carry the FP64 unit vector, the
+// FP32 local frame (cos ra, sin ra, sin dec, cos dec) and (g1, g2, w).
+//
+// Pixel sums (Sect. 3.2 step 2): per pixel W = sum w, G = sum w g and
+// E2 = sum w^2 |g|^2 (for the noise estimate, Eq. map_noise), accumulated
+// in FP64 in catalogue order and stored as float4 (G1, G2, W, E2) over a
+// dense range of whole rings.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+#include <math.h>
+
+#include <string>
+
+#include "hpx_ring.h"
+#include "smart_internal.h"
+
+namespace smart {
+
+namespace {
+
+constexpr double kHalfPi = 1.57079632679489661923;
+
+__global__ void k_keys(int64_t n, const double* ra, const double* dec, int nside, uint32_t* keys, uint32_t* idx,
+                       int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = ra[i], d = dec[i];
+  if (!isfinite(a) || !isfinite(d) || d < -kHalfPi || d > kHalfPi) {
+    atomicOr(flag, 1);
+    keys[i] = 0;
+    idx[i] = (uint32_t)i;
+    return;
+  }
+  const double s = sin(0.5 * (kHalfPi - fabs(d)));
+  keys[i] = (uint32_t)pixel_of(nside, sin(d), 2.0 * s * s, a);
+  idx[i] = (uint32_t)i;
+}
+
+__global__ void k_count(int64_t n, const uint32_t* keys, uint32_t* counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&counts[keys[i]], 1u);
+}
+
+__global__ void k_gather(int64_t n, const uint32_t* skeys, const uint32_t* sidx, const double* ra, const double* dec,
+                         const float* g1, const float* g2, const float* w, int nside, double4* P, float4* F,
+                         float4* G, int64_t* order, unsigned int* max_chord_bits) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t i = sidx[k];
+  double sa, ca, sd, cd;
+  sincos(ra[i], &sa, &ca);
+  sincos(dec[i], &sd, &cd);
+  const double x = cd * ca, y = cd * sa, z = sd;
+  P[k] = make_double4(x, y, z, 0.0);
+  F[k] = make_float4((float)ca, (float)sa, (float)sd, (float)cd);
+  G[k] = make_float4(g1[i], g2[i], w ? w[i] : 1.0f, 0.0f);
+  order[k] = (int64_t)i;
+  // distance to the centre of the galaxy's pixel (bounds the disc search)
+  int rr, jj;
+  pixel_ring(nside, (int64_t)skeys[k], &rr, &jj);
+  const Ring R = ring_info(nside, rr);
+  double sp, cp;
+  sincospi((double)(2 * jj + R.twice_o) / (double)R.n, &sp, &cp);
+  const double dx = x - R.s * cp, dy = y - R.s * sp, dz = z - R.z;
+  const float c = (float)sqrt(dx * dx + dy * dy + dz * dz) * 1.0000002f;
+  atomicMax(max_chord_bits, __float_as_uint(c));
+}
+
+__global__ void k_sums(int64_t n_dense, int64_t pix_first, const int64_t* off, const double4* P, const float4* G,
+                       float4* sums) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_dense) return;
+  const int64_t a = off[pix_first + p], b = off[pix_first + p + 1];
+  double W = 0, G1 = 0, G2 = 0, E2 = 0;
+  for (int64_t k = a; k < b; ++k) {
+    const float4 g = G[k];
+    const double w = g.z, x = g.x, y = g.y;
+    W += w;
+    G1 += w * x;
+    G2 += w * y;
+    E2 += w * w * (x * x + y * y);
+  }
+  sums[p] = make_float4((float)G1, (float)G2, (float)W, (float)E2);
+  (void)P;
+}
+
+__global__ void k_check_pix(const int64_t* pix, int64_t n, int64_t npix, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t p = pix[i];
+  if (p < 0 || p >= npix) atomicOr(flag, 1);
+  if (i > 0 && pix[i - 1] >= p) atomicOr(flag, 2);
+}
+
+__global__ void k_scatter(int64_t n, const int64_t* pix, int64_t pix_first, const float* W, const float* G1,
+                          const float* G2, const float* E2, float4* sums) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  sums[pix[i] - pix_first] = make_float4(G1[i], G2[i], W[i], E2[i]);
+}
+
+__global__ void k_counts_to_offsets_tail(int64_t* off, int64_t npix, int64_t n) { off[npix] = n; }
+
+unsigned grid_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename T>
+int dmalloc(T** p, size_t count) {
+  if (hipMalloc((void**)p, sizeof(T) * (count ? count : 1)) != hipSuccess) {
+    *p = nullptr;
+    set_error("device allocation failed (" + std::to_string(sizeof(T) * count) + " bytes)");
+    return SMART_ENOMEM;
+  }
+  return SMART_OK;
+}
+
+int ensure_temp(smart_ctx ctx, size_t bytes) {
+  if (bytes <= ctx->temp_bytes) return SMART_OK;
+  if (ctx->d_temp) hipFree(ctx->d_temp);
+  ctx->d_temp = nullptr;
+  ctx->temp_bytes = 0;
+  if (hipMalloc(&ctx->d_temp, bytes) != hipSuccess) {
+    set_error("device allocation failed for sort workspace");
+    return SMART_ENOMEM;
+  }
+  ctx->temp_bytes = bytes;
+  return SMART_OK;
+}
+
+#define HIPCHK(x)                                                            \
+  do {                                                                       \
+    hipError_t e_ = (x);                                                     \
+    if (e_ != hipSuccess) {                                                  \
+      set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #x); \
+      return SMART_EDEVICE;                                                  \
+    }                                                                        \
+  } while (0)
+
+int ring_range(int nside, int64_t pmin, int64_t pmax, smart_data d) {
+  int r0, r1, j;
+  pixel_ring(nside, pmin, &r0, &j);
+  pixel_ring(nside, pmax, &r1, &j);
+  d->ring_lo = r0;
+  d->ring_hi = r1;
+  const Ring a = ring_info(nside, r0), b = ring_info(nside, r1);
+  d->pix_first = a.first;
+  d->n_dense = b.first + b.n - a.first;
+  return SMART_OK;
+}
+
+}  // namespace
+
+int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, const float* g1, const float* g2,
+                 const float* w, int nside, int want_sums, hipStream_t st, smart_data d) {
+  const int64_t npix = 12LL * nside * nside;
+  int nbits = 1;
+  while ((1LL << nbits) < npix) ++nbits;
+  uint32_t *keys = nullptr, *idx = nullptr, *skeys = nullptr, *sidx = nullptr, *counts = nullptr;
+  int* flag = nullptr;
+  unsigned int* mc = nullptr;
+  int rc = SMART_OK;
+  auto cleanup = [&]() {
+    (void)hipFree(keys);
+    (void)hipFree(idx);
+    (void)hipFree(skeys);
+    (void)hipFree(sidx);
+    (void)hipFree(counts);
+    (void)hipFree(flag);
+    (void)hipFree(mc);
+  };
+  if ((rc = dmalloc(&keys, n)) || (rc = dmalloc(&idx, n)) || (rc = dmalloc(&skeys, n)) || (rc = dmalloc(&sidx, n)) ||
+      (rc = dmalloc(&counts, npix + 1)) || (rc = dmalloc(&flag, 1)) || (rc = dmalloc(&mc, 1)) ||
+      (rc = dmalloc(&d->P, n)) || (rc = dmalloc(&d->F, n)) || (rc = dmalloc(&d->G, n)) ||
+      (rc = dmalloc(&d->order, n)) || (rc = dmalloc(&d->offsets, npix + 1))) {
+    cleanup();
+    return rc;
+  }
+  d->n_gal = n;
+  d->nside = nside;
+  auto fail = [&](int code) {
+    cleanup();
+    return code;
+  };
+  if (hipMemsetAsync(flag, 0, sizeof(int), st) != hipSuccess || hipMemsetAsync(mc, 0, sizeof(unsigned), st) != hipSuccess ||
+      hipMemsetAsync(counts, 0, sizeof(uint32_t) * (npix + 1), st) != hipSuccess) {
+    set_error("memset failed");
+    return fail(SMART_EDEVICE);
+  }
+  if (n > 0) {
+    hipLaunchKernelGGL(k_keys, dim3(grid_of(n)), dim3(kBlock), 0, st, n, ra, dec, nside, keys, idx, flag);
+    size_t tb = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, skeys, idx, sidx, (int)n, 0, nbits, st);
+    size_t tb2 = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, counts, d->offsets, (int)(npix + 1), st);
+    if ((rc = ensure_temp(ctx, tb > tb2 ? tb : tb2))) return fail(rc);
+    tb = ctx->temp_bytes;
+    if (hipcub::DeviceRadixSort::SortPairs(ctx->d_temp, tb, keys, skeys, idx, sidx, (int)n, 0, nbits, st) !=
+        hipSuccess) {
+      set_error("radix sort failed");
+      return fail(SMART_EDEVICE);
+    }
+    hipLaunchKernelGGL(k_count, dim3(grid_of(n)), dim3(kBlock), 0, st, n, skeys, counts);
+    hipLaunchKernelGGL(k_gather, dim3(grid_of(n)), dim3(kBlock), 0, st, n, skeys, sidx, ra, dec, g1, g2, w, nside,
+                       d->P, d->F, d->G, d->order, mc);
+  } else {
+    size_t tb2 = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, counts, d->offsets, (int)(npix + 1), st);
+    if ((rc = ensure_temp(ctx, tb2))) return fail(rc);
+  }
+  size_t tb = ctx->temp_bytes;
+  if (hipcub::DeviceScan::ExclusiveSum(ctx->d_temp, tb, counts, d->offsets, (int)(npix + 1), st) != hipSuccess) {
+    set_error("offset scan failed");
+    return fail(SMART_EDEVICE);
+  }
+  int hflag = 0;
+  unsigned hmc = 0;
+  uint32_t kmin = 0, kmax = 0;
+  if (hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&hmc, mc, sizeof(unsigned), hipMemcpyDeviceToHost, st) != hipSuccess) {
+    set_error("copy failed");
+    return fail(SMART_EDEVICE);
+  }
+  if (n > 0 && (hipMemcpyAsync(&kmin, skeys, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(&kmax, skeys + (n - 1), 4, hipMemcpyDeviceToHost, st) != hipSuccess)) {
+    set_error("copy failed");
+    return fail(SMART_EDEVICE);
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    set_error(std::string("binning failed: ") + hipGetErrorString(hipGetLastError()));
+    return fail(SMART_EDEVICE);
+  }
+  if (hflag) {
+    set_error("non-finite or out-of-range galaxy coordinates");
+    return fail(SMART_EINVAL);
+  }
+  float chord;
+  memcpy(&chord, &hmc, 4);
+  d->r_bin = 2.0 * asin(fmin(1.0, 0.5 * (double)chord));
+  if (n > 0) {
+    ring_range(nside, kmin, kmax, d);
+  } else {
+    d->ring_lo = 1;
+    d->ring_hi = 0;
+    d->pix_first = 0;
+    d->n_dense = 0;
+  }
+  if (want_sums && d->n_dense > 0) {
+    if ((rc = dmalloc(&d->sums, d->n_dense))) return fail(rc);
+    hipLaunchKernelGGL(k_sums, dim3(grid_of(d->n_dense)), dim3(kBlock), 0, st, d->n_dense, d->pix_first, d->offsets,
+                       d->P, d->G, d->sums);
+    if (hipGetLastError() != hipSuccess) {
+      set_error("pixel-sum kernel failed to launch");
+      return fail(SMART_EDEVICE);
+    }
+  }
+  cleanup();
+  return SMART_OK;
+}
+
+hipError_t launch_check_pixels(const int64_t* pix, int64_t n, int64_t npix, int* d_flag, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_pix, dim3(grid_of(n)), dim3(kBlock), 0, st, pix, n, npix, d_flag);
+  return hipGetLastError();
+}
+
+int pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const float* W, const float* G1,
+              const float* G2, const float* E2, hipStream_t st, smart_data d) {
+  (void)ctx;
+  const int64_t npix = 12LL * nside * nside;
+  int* flag = nullptr;
+  int rc;
+  if ((rc = dmalloc(&flag, 1))) return rc;
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
+  HIPCHK(launch_check_pixels(pix, n, npix, flag, st));
+  int hflag = 0;
+  int64_t pf = 0, pl = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&pf, pix, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&pl, pix + (n - 1), 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  (void)hipFree(flag);
+  if (hflag & 1) {
+    set_error("pixel number out of range for this NSIDE");
+    return SMART_EINVAL;
+  }
+  if (hflag & 2) {
+    set_error("pixel numbers must be strictly increasing");
+    return SMART_EINVAL;
+  }
+  d->kind = 1;
+  d->nside = nside;
+  ring_range(nside, pf, pl, d);
+  if ((rc = dmalloc(&d->sums, d->n_dense))) return rc;
+  HIPCHK(hipMemsetAsync(d->sums, 0, sizeof(float4) * d->n_dense, st));
+  hipLaunchKernelGGL(k_scatter, dim3(grid_of(n)), dim3(kBlock), 0, st, n, pix, d->pix_first, W, G1, G2, E2, d->sums);
+  HIPCHK(hipGetLastError());
+  return SMART_OK;
+}
+
+}  // namespace smart

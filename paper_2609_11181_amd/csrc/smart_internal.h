@@ -1,0 +1,167 @@
+// Internal declarations of libsmartap: handle layouts, kernel argument
+// blocks and launchers shared by the translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/smartap.h"
+
+namespace smart {
+
+constexpr int kFilterIntervals = 2048;  // cubic pieces per filter table
+constexpr int kMaxNside = 8192;
+constexpr double kMaxThetaAp = 0.25;    // radians
+constexpr int kBlock = 256;
+
+void set_error(const std::string& msg);
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+
+struct FilterDef {
+  int kind = 0;
+  double params[5] = {0, 0, 0, 0, 0};
+  std::vector<double> samples;  // SMART_FILTER_TABLE
+  float4* d_table = nullptr;    // kFilterIntervals cubic pieces (c0, c1, c2, c3) in FP32
+  float* d_table_lo = nullptr;  // FP32 remainder of c0 (c0 = hi + lo to about 1e-15)
+  std::vector<float> h_table;
+};
+
+}  // namespace smart
+
+struct smart_ctx_s {
+  int device = 0;
+  std::vector<smart::FilterDef> filters;
+  void* d_temp = nullptr;  // scratch for library sorts and scans
+  size_t temp_bytes = 0;
+};
+
+struct smart_data_s {
+  smart_ctx ctx = nullptr;
+  int kind = 0;  // 0 galaxies (+ optional pixel sums), 1 pixel map
+  int nside = 0;
+  int64_t n_gal = 0;
+  // galaxy partition (sorted rows)
+  double4* P = nullptr;   // unit vector (x, y, z, 0)
+  float4* F = nullptr;    // (cos ra, sin ra, sin dec, cos dec)
+  float4* G = nullptr;    // (g1, g2, w, 0)
+  int64_t* order = nullptr;
+  int64_t* offsets = nullptr;  // 12 nside^2 + 1
+  double r_bin = 0.0;
+  // dense pixel sums over whole rings [ring_lo, ring_hi]
+  int ring_lo = 0, ring_hi = -1;
+  int64_t pix_first = 0, n_dense = 0;
+  float4* sums = nullptr;  // (G1, G2, W, E2)
+};
+
+struct smart_plan_s {
+  smart_ctx ctx = nullptr;
+  smart_data data = nullptr;
+  int variant = 0;
+  int precision = 0;
+  int nside_out = 0;
+  int64_t n_out = 0;
+  int64_t* out_pix = nullptr;
+  std::vector<double> theta_ap;
+  std::vector<int> filter_ids;
+  // last run, for smart_last_pairs
+  const void* last_out = nullptr;
+  int last_norm = 0;
+  double* d_pairs = nullptr;
+  // scratch for the noise batch (rotated map), grown on demand
+  float4* rot_map = nullptr;
+  int64_t rot_len = 0;
+};
+
+namespace smart {
+
+// ---------------------------------------------------------------------------
+// kernel argument blocks
+// ---------------------------------------------------------------------------
+
+struct ScaleArgs {
+  double theta_ap;
+  double C_ap;       // 4 sin^2(theta_ap / 2): squared chord of the aperture
+  double area_cap;   // 2 pi (1 - cos theta_ap)
+  double inv_theta2; // 1 / theta_ap^2
+  double omega_pix;  // pixel area of the source map
+  int filter_kind;   // SMART_FILTER_POLY, or table otherwise
+  int big;           // 1 when theta_ap > 2 degrees (longer asin series)
+  const float4* table;
+  const float* table_lo;
+  double tpoly[7];   // asin(y)/y series in y^2, divided by theta_ap (x from sin theta)
+  double cpoly[7];   // 2 asin(c/2)/c series in c^2, divided by theta_ap (x from the chord c)
+  double tanh_p[5];  // FP64 path: tanh filter parameters
+  const double* samples;  // FP64 path: table filter samples (device)
+  int n_samples;
+};
+
+struct PixelArgs {
+  const int64_t* out_pix;
+  int64_t n_out;
+  int nside_out;
+  const float4* map;  // dense (G1, G2, W, E2)
+  int nside_in;
+  int ring_lo, ring_hi;
+  int64_t pix_first;
+  void* out;          // [scale][5][n_out]
+  int norm;
+  int scale;
+};
+
+struct GalaxyArgs {
+  const int64_t* out_pix;
+  int64_t n_out;
+  int nside_out;
+  const double4* P;
+  const float4* F;
+  const float4* G;
+  const int64_t* offsets;
+  int nside_bin;
+  double r_bin;
+  void* out;
+  int norm;
+  int scale;
+};
+
+// launchers (k_pairs.hip)
+hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, hipStream_t st);
+hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, hipStream_t st);
+hipError_t launch_sum_n(const void* out, int precision, int64_t n_out, int n_scales, double* d_acc,
+                        hipStream_t st);
+
+// binner (k_binner.hip)
+int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, const float* g1, const float* g2,
+                 const float* w, int nside_bin, int want_sums, hipStream_t st, smart_data d);
+int pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const float* W, const float* G1,
+              const float* G2, const float* E2, hipStream_t st, smart_data d);
+hipError_t launch_check_pixels(const int64_t* pix, int64_t n, int64_t npix, int* d_flag, hipStream_t st);
+
+// noise realisations (k_noise.hip)
+hipError_t launch_rotate_map(const float4* map, const float* u, int64_t n, float4* out, hipStream_t st);
+int noise_bf16x3(smart_plan plan, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st);
+
+// mixed batch (k_mixed.hip)
+int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,
+                hipStream_t st);
+
+// filter tables (filters.cpp)
+int build_filter(FilterDef& f);
+double filter_eval(const FilterDef& f, double x);
+ScaleArgs make_scale(smart_ctx ctx, double theta_ap, int filter_id, double omega_pix);
+
+// XCD-aware block order: the hardware deals consecutive workgroups to the
+// eight XCDs in turn; remap so that each XCD walks one contiguous range of
+// logical blocks and keeps neighbouring apertures in its own L2.
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb >> 3, r = nb & 7;
+  const int64_t x = b & 7, k = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
+}  // namespace smart

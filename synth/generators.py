@@ -13,8 +13,9 @@ Conventions of the produced arrays:
   weights W, the weighted shear sums G1, G2 and the sum of w^2 |g|^2 (E2).
 
 The lensing signal is a superposition of singular isothermal spheres (SIS):
-tangential shear theta_E / (2 theta) around each halo, truncated at
-``trunc`` radians for CPU cost (a generator parameter only; every consumer
+tangential shear theta_E / (2 theta) around each halo, held at 1/2 inside
+the Einstein radius theta_E (the weak-lensing regime) and truncated at
+``trunc`` radians for CPU cost (generator parameters only; every consumer
 reads the same arrays).
 
 Nothing here computes an aperture mass. The generator needs pixel centres to
@@ -55,6 +56,14 @@ def _bearing_shear(ra_g, dec_g, ra_h, dec_h, gamma_t):
     x = np.cos(dec_g) * np.sin(dec_h) - np.sin(dec_g) * np.cos(dec_h) * np.cos(dra)
     beta = np.arctan2(y, x)
     return gamma_t * np.cos(2 * beta), -gamma_t * np.sin(2 * beta)
+
+
+def _sis_gamma(theta_e, theta):
+    """Tangential shear of a singular isothermal sphere, theta_E / (2 theta),
+    held at its Einstein-radius value 1/2 inside theta_E: closer in, the
+    lens is strong and the weak-shear formula (which diverges at the centre)
+    no longer describes the sources."""
+    return theta_e / (2.0 * np.maximum(theta, theta_e))
 
 
 def _sep(ra1, dec1, ra2, dec2):
@@ -171,7 +180,7 @@ def _add_sis_banded(g1, g2, ra, dec, edges, offs, halos, trunc):
             if not m.any():
                 continue
             idx = np.nonzero(m)[0] + i0
-            gt = te / (2 * th[m])
+            gt = _sis_gamma(te, th[m])
             a, b_ = _bearing_shear(ra[idx], dec[idx], ha, hd, gt)
             g1[idx] += a
             g2[idx] += b_
@@ -192,7 +201,7 @@ def galaxy_catalogue(spec: CatalogueSpec):
             th = _sep(ra, dec, halos[0][k], halos[1][k])
             m = (th < spec.trunc) & (th > 0)
             idx = np.nonzero(m)[0]
-            a, b = _bearing_shear(ra[idx], dec[idx], halos[0][k], halos[1][k], halos[2][k] / (2 * th[m]))
+            a, b = _bearing_shear(ra[idx], dec[idx], halos[0][k], halos[1][k], _sis_gamma(halos[2][k], th[m]))
             g1[idx] += a
             g2[idx] += b
     else:
@@ -376,7 +385,7 @@ def pixel_level_map(spec: PixelMapSpec):
         m = (th < tr) & (th > 0)
         if not m.any():
             continue
-        gt = te / (2 * th[m])
+        gt = _sis_gamma(te, th[m])
         a, b = _bearing_shear(phi[m], dec[m], ha, hd, gt)
         d = (rt["start"][rix[m]] - base + jix[m]).astype(np.int64)
         np.add.at(g1s, d, a)

@@ -1,0 +1,292 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle,
+at sizes the oracle finishes in seconds that still span many workgroups and
+a ragged tail. Tolerances: FP32 plans <= 1e-6 of the map RMS (the accuracy
+target of the mixed-precision path); FP64 plans <= 3e-12 of the map RMS,
+the oracle's own accuracy: its polar-angle formula (the paper's, Sect. 2.3)
+subtracts O(1) products to get O(theta) numerator and denominator, so each
+term carries about 1e-16/theta relative error, and B-mode maps (sums with
+heavy cancellation) see it most. The FP64 path itself is checked against a
+50-digit reference at 1e-13 in test_fp64_vs_mp. W and N exact up to FP32
+rounding of W."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import aperture as A
+from oracle import binning as B
+from oracle import filters as F
+from oracle import healpix_ref as hp
+from synth import small_catalogue
+
+pytestmark = pytest.mark.gpu
+
+DEG = math.pi / 180
+ARCMIN = DEG / 60
+TOL64 = 3e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_11181_amd import api
+
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _L():
+    from paper_2609_11181_amd import lib
+
+    return lib
+
+
+def rel_err(gpu, ref, ok):
+    rms = math.sqrt(np.mean(ref[ok] ** 2)) if ok.any() else 1.0
+    if rms == 0:
+        rms = 1.0
+    return float(np.max(np.abs(gpu[ok] - ref[ok])) / rms) if ok.any() else 0.0
+
+
+def _pixmap(nside, seed, cap=None):
+    """Poisson-count pixel map over the whole sphere or a cap around (0, 0)."""
+    rng = np.random.default_rng(seed)
+    pix = np.arange(hp.npix(nside))
+    if cap is not None:
+        v = hp.pix2vec(nside, pix)
+        pix = pix[v[:, 0] > math.cos(cap)]
+    n = pix.size
+    W = rng.poisson(20, n).astype(np.float32)
+    G1 = (rng.normal(0, 0.26, n) * np.sqrt(W) + 0.02 * W).astype(np.float32)
+    G2 = (rng.normal(0, 0.26, n) * np.sqrt(W)).astype(np.float32)
+    E2 = (W * 2 * 0.26 ** 2).astype(np.float32)
+    return {"nside": nside, "pix": pix, "W": W, "G1": G1, "G2": G2, "E2": E2}
+
+
+def _compare(out, ref, norm, tol, prec64=False):
+    ok = ~ref["tie"]
+    errs = {}
+    for c, k in enumerate(["M_E", "M_B", "sigma"]):
+        errs[k] = rel_err(out[c].astype(np.float64), ref[k], ok)
+    assert errs["M_E"] <= tol and errs["M_B"] <= tol and errs["sigma"] <= tol, errs
+    wtol = 1e-12 if prec64 else 2e-7
+    assert np.max(np.abs(out[3][ok] - ref["W"][ok]) / np.maximum(ref["W"][ok], 1)) <= wtol
+    assert np.array_equal(out[4][ok].astype(np.float64), ref["N"][ok])
+    return errs
+
+
+PIX_CASES = [
+    # nside, theta_ap, filter, precision, norm
+    (64, 3 * DEG, F.TANH, 1, A.NORM_SUMMED_PIXCOUNT),
+    (64, 10 * DEG, F.POLY, 1, A.NORM_SUMMED_PIXCOUNT),
+    (64, 10 * DEG, F.TANH, 1, A.NORM_RAW),
+    (32, 14 * DEG, F.TANH, 1, A.NORM_SUMMED_CAP),
+    (64, 3 * DEG, F.TANH, 0, A.NORM_SUMMED_PIXCOUNT),
+    (64, 10 * DEG, F.POLY, 0, A.NORM_RAW),
+]
+
+
+def _out_pixels(nside, seed, n=2500):
+    rng = np.random.default_rng(seed)
+    npx = hp.npix(nside)
+    polar = np.concatenate([np.arange(0, 24), npx - 1 - np.arange(24)])
+    ring = hp.ring_table(nside)
+    belt = np.arange(ring["first"][2 * nside - 1], ring["first"][2 * nside - 1] + ring["n"][2 * nside - 1])
+    rnd = rng.choice(npx, n, replace=False)
+    return np.unique(np.concatenate([polar, belt, rnd]))
+
+
+@pytest.mark.parametrize("nside,th,kind,prec,norm", PIX_CASES)
+def test_pixel_variant_parity(ctx, nside, th, kind, prec, norm):
+    L = _L()
+    m = _pixmap(nside, 1)
+    out_pix = _out_pixels(nside, 2)
+    fid = ctx.filter(kind)
+    data = ctx.pixel_map(nside, m["pix"], m["W"], m["G1"], m["G2"], m["E2"])
+    plan = ctx.plan(data, L.VAR_PIXEL, nside, out_pix, [th], [fid], precision=prec)
+    out = plan.run(norm).cpu().numpy()[0]
+    ref = A.aperture_mass_pixel(m, out_pix, th, kind, norm=norm)
+    tol = TOL64 if prec == 0 else 1e-6
+    errs = _compare(out, ref, norm, tol, prec64=(prec == 0))
+    print(nside, th, kind, prec, norm, errs)
+    # pair count = sum of N
+    assert abs(plan.last_pairs() - ref["N"].sum()) < 0.5
+
+
+def test_pixel_variant_sparse_cap_multiscale(ctx):
+    """A map covering only a cap (dense range with empty pixels around it),
+    three scales in one plan, outputs at the cap edge and outside."""
+    L = _L()
+    nside = 256
+    m = _pixmap(nside, 3, cap=8 * DEG)
+    rng = np.random.default_rng(4)
+    out_pix = np.unique(np.concatenate([rng.choice(m["pix"], 3000, replace=False),
+                                        hp.radec2pix(nside, rng.uniform(-0.2, 0.2, 300), rng.uniform(-0.2, 0.2, 300))]))
+    ths = [20 * ARCMIN, 40 * ARCMIN, 90 * ARCMIN]
+    fids = [ctx.filter(F.TANH), ctx.filter(F.POLY), ctx.filter(F.TANH)]
+    data = ctx.pixel_map(nside, m["pix"], m["W"], m["G1"], m["G2"], m["E2"])
+    plan = ctx.plan(data, L.VAR_PIXEL, nside, out_pix, ths, fids)
+    out = plan.run(L.NORM_SUMMED_PIXCOUNT).cpu().numpy()
+    for k, (th, kind) in enumerate(zip(ths, [F.TANH, F.POLY, F.TANH])):
+        ref = A.aperture_mass_pixel(m, out_pix, th, kind)
+        _compare(out[k], ref, 1, 1e-6)
+
+
+def test_pixel_tiny_aperture_and_single_output(ctx):
+    """Aperture smaller than a pixel: only the centre pixel is a member
+    (coincident source: no shear term, W and V only)."""
+    L = _L()
+    nside = 64
+    m = _pixmap(nside, 5)
+    fid = ctx.filter(F.TANH)
+    data = ctx.pixel_map(nside, m["pix"], m["W"], m["G1"], m["G2"], m["E2"])
+    out_pix = np.array([12345])
+    plan = ctx.plan(data, L.VAR_PIXEL, nside, out_pix, [0.1 * DEG], [fid])
+    out = plan.run(L.NORM_RAW).cpu().numpy()[0]
+    assert out[0, 0] == 0 and out[1, 0] == 0
+    assert out[3, 0] == m["W"][12345] and out[4, 0] == 1
+    assert abs(out[2, 0] - F.q_tanh(0.0) ** 2 * m["E2"][12345]) < 1e-6 * m["E2"][12345]
+
+
+def test_empty_output_list(ctx):
+    L = _L()
+    import torch
+
+    m = _pixmap(16, 6)
+    data = ctx.pixel_map(16, m["pix"], m["W"], m["G1"], m["G2"], m["E2"])
+    plan = ctx.plan(data, L.VAR_PIXEL, 16, np.zeros(0, np.int64), [5 * DEG], [ctx.filter(F.POLY)])
+    out = plan.run(L.NORM_RAW)
+    torch.cuda.synchronize()
+    assert out.numel() == 0
+
+
+def test_invalid_inputs_rejected(ctx):
+    L = _L()
+    m = _pixmap(16, 6)
+    data = ctx.pixel_map(16, m["pix"], m["W"], m["G1"], m["G2"], m["E2"])
+    fid = ctx.filter(F.POLY)
+    with pytest.raises(L.SmartError):
+        ctx.plan(data, L.VAR_PIXEL, 16, np.array([12 * 16 * 16]), [5 * DEG], [fid])   # pixel out of range
+    with pytest.raises(L.SmartError):
+        ctx.plan(data, L.VAR_PIXEL, 16, np.array([0]), [0.3], [fid])                 # aperture too large
+    with pytest.raises(L.SmartError):
+        ctx.plan(data, L.VAR_PIXEL, 32, np.array([0]), [0.1], [fid])                 # NSIDE mismatch
+    with pytest.raises(L.SmartError):
+        ctx.pixel_map(16, np.array([5, 3]), *[np.ones(2, np.float32)] * 4)           # not increasing
+    with pytest.raises(L.SmartError):
+        ctx.bin_galaxies(np.array([0.1]), np.array([2.0]), np.zeros(1), np.zeros(1), nside_bin=16)  # dec > pi/2
+
+
+# ---------------------------------------------------------------------------
+# galaxy variant and the partition
+# ---------------------------------------------------------------------------
+
+def test_partition_and_pixel_sums(ctx):
+    nside = 256
+    cat = small_catalogue(300000, seed=7, cap_radius=6 * DEG, centre=(0.05, 0.1))
+    data = ctx.bin_galaxies(cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat["w"], nside_bin=nside, pixel_sums=True)
+    order, offs, sums = data.export(order=True, offsets=True, sums=True)
+    pix, o_ref, off_ref = B.partition(nside, cat["ra"], cat["dec"])
+    assert np.array_equal(order.cpu().numpy(), o_ref)
+    assert np.array_equal(offs.cpu().numpy(), off_ref)
+    inf = data.info()
+    u, W, G1, G2, E2 = B.pixel_sums(nside, cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat["w"])
+    s = sums.cpu().numpy().astype(np.float64)
+    k = u - inf["pix_first"]
+    assert k.min() >= 0 and k.max() < inf["n_dense"]
+    for col, ref in zip([2, 0, 1, 3], [W, G1, G2, E2]):
+        assert np.max(np.abs(s[k, col] - ref) / (np.abs(ref) + 1e-3)) < 1e-6
+    mask = np.ones(inf["n_dense"], bool)
+    mask[k] = False
+    assert np.all(s[mask] == 0)
+    # r_bin bounds every galaxy-to-centre distance
+    ra_c, dec_c = hp.pix2radec(nside, pix)
+    v = A.radec2vec(cat["ra"], cat["dec"])
+    vc = A.radec2vec(ra_c, dec_c)
+    d = 2 * np.arcsin(np.linalg.norm(v - vc, axis=1) / 2)
+    assert inf["r_bin"] >= d.max() and inf["r_bin"] < d.max() * 1.001 + 1e-9
+
+
+GAL_CASES = [
+    # n_gal, cap, nside_bin, nside_out, theta, filter, precision
+    (200000, 6 * DEG, 256, 128, 40 * ARCMIN, F.TANH, 1),
+    (200000, 6 * DEG, 512, 128, 40 * ARCMIN, F.POLY, 1),
+    (200000, 6 * DEG, 128, 128, 60 * ARCMIN, F.TANH, 0),
+    (50000, 30 * DEG, 64, 32, 5 * DEG, F.POLY, 0),
+]
+
+
+@pytest.mark.parametrize("n,cap,nb,no,th,kind,prec", GAL_CASES)
+def test_galaxy_variant_parity(ctx, n, cap, nb, no, th, kind, prec):
+    L = _L()
+    cat = small_catalogue(n, seed=n + nb, cap_radius=cap, centre=(0.02, 0.0))
+    data = ctx.bin_galaxies(cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat["w"], nside_bin=nb)
+    v = hp.pix2vec(no, np.arange(hp.npix(no)))
+    out_pix = np.nonzero(v[:, 0] > math.cos(cap + 0.5 * th))[0]      # includes partial edge apertures
+    if out_pix.size > 4000:
+        out_pix = np.sort(np.random.default_rng(1).choice(out_pix, 4000, replace=False))
+    fid = ctx.filter(kind)
+    plan = ctx.plan(data, L.VAR_GALAXY, no, out_pix, [th], [fid], precision=prec)
+    out = plan.run(L.NORM_SUMMED_CAP).cpu().numpy()[0]
+    ra_c, dec_c = hp.pix2radec(no, out_pix)
+    ref = A.aperture_mass_galaxy(cat, ra_c, dec_c, th, kind)
+    tol = TOL64 if prec == 0 else 1e-6
+    errs = _compare(out, ref, 0, tol, prec64=(prec == 0))
+    print(n, nb, no, th, kind, prec, errs)
+
+
+def test_galaxy_pole_and_seam(ctx):
+    """Galaxies around the north pole and across ra = 0; centres on the
+    polar rings, the disc containing the pole."""
+    L = _L()
+    cat = small_catalogue(60000, seed=9, cap_radius=12 * DEG, centre=(0.0, 88 * DEG))
+    data = ctx.bin_galaxies(cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat["w"], nside_bin=128)
+    out_pix = np.arange(0, 2 * 64 * 63)[:3000]  # north cap rings of NSIDE 64
+    fid = ctx.filter(F.TANH)
+    for prec, tol in [(1, 1e-6), (0, TOL64)]:
+        plan = ctx.plan(data, L.VAR_GALAXY, 64, out_pix, [3 * DEG], [fid], precision=prec)
+        out = plan.run(L.NORM_SUMMED_CAP).cpu().numpy()[0]
+        ra_c, dec_c = hp.pix2radec(64, out_pix)
+        ref = A.aperture_mass_galaxy(cat, ra_c, dec_c, 3 * DEG, F.TANH)
+        _compare(out, ref, 0, tol, prec64=(prec == 0))
+
+
+def test_filter_table_accuracy(ctx):
+    """Device filter tables: the piecewise cubic evaluated in FP64 from the
+    stored FP32 coefficients stays within 1e-7 of the filter maximum."""
+    for kind, qf in [(F.TANH, F.q_tanh), (F.POLY, F.q_poly)]:
+        tab = ctx.filter_table(ctx.filter(kind)).astype(np.float64)
+        K = tab.shape[0]
+        x = np.linspace(0, 1, 400001)[:-1]
+        i = np.minimum((x * K).astype(int), K - 1)
+        f = x * K - i
+        c = tab[i]
+        q = c[:, 0] + f * (c[:, 1] + f * (c[:, 2] + f * c[:, 3]))
+        assert np.max(np.abs(q - qf(x))) < 2e-7 * qf(x).max()
+
+
+def test_fp64_vs_mp(ctx):
+    """The FP64 galaxy path against the 50-digit all-pairs reference used to
+    pin the oracle (tests/test_oracle_aperture.py), on a small catalogue."""
+    from tests.test_oracle_aperture import mp_brute
+
+    L = _L()
+    cat = small_catalogue(250, seed=21, cap_radius=4 * DEG, centre=(1.0, 0.5))
+    data = ctx.bin_galaxies(cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat["w"], nside_bin=64)
+    nside = 256
+    v = hp.pix2vec(nside, np.arange(hp.npix(nside)))
+    c = A.radec2vec(1.0, 0.5)
+    out_pix = np.nonzero(v @ c > math.cos(2 * DEG))[0][::7][:12]
+    th = 2.5 * DEG
+    plan = ctx.plan(data, L.VAR_GALAXY, nside, out_pix, [th], [ctx.filter(F.TANH)], precision=0)
+    out = plan.run(L.NORM_RAW).cpu().numpy()[0]
+    ra_c, dec_c = hp.pix2radec(nside, out_pix)
+    ref = mp_brute(cat, ra_c, dec_c, th, F.TANH)
+    # RAW channels (S_E, S_B, V, W, N) against the reference columns (SE, SB, W, V, N)
+    for ch, col in [(0, 0), (1, 1), (2, 3), (3, 2), (4, 4)]:
+        rms = math.sqrt(np.mean(ref[:, col] ** 2))
+        assert np.max(np.abs(out[ch] - ref[:, col])) <= 1e-13 * rms, ch
