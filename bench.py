@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--cpu-outputs", type=int, default=8000)
     p.add_argument("--area", type=float, default=15000.0, help="field area in deg^2")
     p.add_argument("--nside", type=int, default=4096)
+    p.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                   help="only run a plain device copy of GIB GiB three times (HBM counter calibration)")
     return p.parse_args()
 
 
@@ -108,6 +110,16 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {n * 4} bytes x 3 (read {n * 4} B + write {n * 4} B per copy)")
+        return
 
     from paper_2609_11181_amd import api
     from paper_2609_11181_amd import lib as L
