@@ -205,6 +205,7 @@ void smart_plan_free(smart_plan p) {
   if (p->ctx) hipSetDevice(p->ctx->device);
   hipFree(p->out_pix);
   hipFree(p->d_pairs);
+  hipFree(p->d_work);
   hipFree(p->rot_map);
   delete p;
 }
@@ -254,7 +255,8 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
     return fail(code, m);
   };
   if (hipMalloc(&p->out_pix, sizeof(int64_t) * (n_out ? n_out : 1)) != hipSuccess ||
-      hipMalloc(&p->d_pairs, sizeof(double)) != hipSuccess)
+      hipMalloc(&p->d_pairs, sizeof(double)) != hipSuccess ||
+      hipMalloc(&p->d_work, sizeof(int) * pixel_work_ints(n_out)) != hipSuccess)
     return bail(SMART_ENOMEM, "device allocation failed for the plan");
   if (n_out > 0) {
     int* flag = nullptr;
@@ -298,7 +300,7 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.out = d_out;
       a.norm = norm;
       a.scale = k;
-      e = launch_pixel(a, s, p->precision, st);
+      e = launch_pixel(a, s, p->precision, st, p->d_work);
     } else {
       GalaxyArgs a{};
       a.out_pix = p->out_pix;
@@ -379,7 +381,7 @@ int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int 
       a.out = stage;
       a.norm = norm;
       a.scale = 0;
-      e = launch_pixel(a, s, SMART_PREC_FP32_GEO64, st);
+      e = launch_pixel(a, s, SMART_PREC_FP32_GEO64, st, p->d_work);
       if (e != hipSuccess) return fail(SMART_EDEVICE, "pair kernel failed");
       float* dst = d_out + (((int64_t)k * n_real + r) * 2) * p->n_out;
       e = hipMemcpyAsync(dst, stage, sizeof(float) * 2 * p->n_out, hipMemcpyDeviceToDevice, st);

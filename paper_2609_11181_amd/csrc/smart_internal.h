@@ -73,6 +73,7 @@ struct smart_plan_s {
   const void* last_out = nullptr;
   int last_norm = 0;
   double* d_pairs = nullptr;
+  int* d_work = nullptr;  // tile lists of the pixel kernels
   // scratch for the noise batch (rotated map), grown on demand
   float4* rot_map = nullptr;
   int64_t rot_len = 0;
@@ -130,7 +131,9 @@ struct GalaxyArgs {
 };
 
 // launchers (k_pairs.hip)
-hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, hipStream_t st);
+// d_work: device scratch of pixel_work_ints(n_out) ints (tile lists)
+hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, hipStream_t st, int* d_work);
+size_t pixel_work_ints(int64_t n_out);
 hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, hipStream_t st);
 hipError_t launch_sum_n(const void* out, int precision, int64_t n_out, int n_scales, double* d_acc,
                         hipStream_t st);

@@ -117,6 +117,30 @@ def test_pixel_variant_parity(ctx, nside, th, kind, prec, norm):
     assert abs(plan.last_pairs() - ref["N"].sum()) < 0.5
 
 
+@pytest.mark.parametrize("kind,th", [(F.TANH, 2 * DEG), (F.POLY, 6 * DEG)])
+def test_pixel_variant_runs_of_consecutive_centres(ctx, kind, th):
+    """Whole rings and ragged runs of consecutive centres: waves of 64
+    neighbours on one ring take the shared-stencil path (equal-size source
+    rings); runs crossing ring ends, cap rings and short tails do not."""
+    L = _L()
+    nside = 128
+    m = _pixmap(nside, 11)
+    rt = hp.ring_table(nside)
+    runs = []
+    for ring in (60, 128, 129, 256, 383, 450):          # cap, belt edge, belt, equator, belt, south cap
+        a, n = rt["first"][ring - 1], rt["n"][ring - 1]
+        runs.append(np.arange(a, a + n))
+    runs.append(np.arange(rt["first"][300] - 37, rt["first"][300] + 101))   # across a ring end
+    runs.append(np.arange(rt["first"][200] + 5, rt["first"][200] + 5 + 64 * 3 + 13))  # ragged tail
+    out_pix = np.unique(np.concatenate(runs))
+    data = ctx.pixel_map(nside, m["pix"], m["W"], m["G1"], m["G2"], m["E2"])
+    plan = ctx.plan(data, L.VAR_PIXEL, nside, out_pix, [th], [ctx.filter(kind)])
+    out = plan.run(L.NORM_SUMMED_PIXCOUNT).cpu().numpy()[0]
+    ref = A.aperture_mass_pixel(m, out_pix, th, kind)
+    errs = _compare(out, ref, 1, 1e-6)
+    print(kind, th, errs)
+
+
 def test_pixel_variant_sparse_cap_multiscale(ctx):
     """A map covering only a cap (dense range with empty pixels around it),
     three scales in one plan, outputs at the cap edge and outside."""
