@@ -48,6 +48,10 @@ def parse():
     p.add_argument("--cpu-outputs", type=int, default=8000)
     p.add_argument("--area", type=float, default=15000.0, help="field area in deg^2")
     p.add_argument("--nside", type=int, default=4096)
+    p.add_argument("--no-batched", action="store_true", help="skip the batched noise-realisation leg")
+    p.add_argument("--only-batched", action="store_true", help="run only the batched noise-realisation leg")
+    p.add_argument("--n-real", type=int, default=256, help="realisations of the batched leg")
+    p.add_argument("--plain-real", type=int, default=8, help="realisations timed on the plain FP32 path")
     p.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                    help="only run a plain device copy of GIB GiB three times (HBM counter calibration)")
     return p.parse_args()
@@ -103,6 +107,124 @@ def cpu_baseline(pm, R, scales, n_out, seed=11):
     return out_pix, refs, pairs, dt
 
 
+def batched_leg(ctx, args):
+    """Shape-noise realisations: galaxies of a 5000 deg^2 field (config-2
+    statistics, about 2.5e8 galaxies) binned at NSIDE 2048, 256 realisations
+    x 3 scales (5', 10', 20') = 768 noise maps, split-BF16 MFMA path against
+    the plain FP32 path (timed on a few realisations)."""
+    import torch
+
+    from paper_2609_11181_amd import lib as L
+    from synth import config4_catalogue
+
+    t = time.perf_counter()
+    cat, R4 = config4_catalogue()
+    log(f"batched leg: generated {cat['ra'].size} galaxies in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda", 0)
+    cols = [torch.from_numpy(cat[k]).to(dev) for k in ("ra", "dec", "g1", "g2")]
+    del cat
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream(dev)
+    ev0.record(stream)
+    data = ctx.bin_galaxies(*cols, None, nside_bin=2048, pixel_sums=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    bin_ms = ev0.elapsed_time(ev1)
+    n_gal = cols[0].numel()
+    del cols
+    src = data.sources()
+    n_src = src.numel()
+    scales = [5 * ARCMIN, 10 * ARCMIN, 20 * ARCMIN]
+    fid = ctx.filter(L.FILTER_TANH)
+    plan = ctx.plan(data, L.VAR_PIXEL, 2048, src, scales, [fid] * 3)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4)
+    R = args.n_real
+    u = torch.rand((R, n_src), generator=gen, device=dev, dtype=torch.float32)
+    out = torch.empty(3, R, 2, n_src, dtype=torch.float32, device=dev)
+    plan.noise_batch(u, R, L.NORM_SUMMED_PIXCOUNT, L.PREC_BF16X3, out)  # warm-up
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    plan.noise_batch(u, R, L.NORM_SUMMED_PIXCOUNT, L.PREC_BF16X3, out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_b = ev0.elapsed_time(ev1) / 1e3
+    # pairs of one realisation set (N summed over centres and scales)
+    main = plan.run(L.NORM_SUMMED_PIXCOUNT)
+    pairs1 = plan.last_pairs()
+    Rp = args.plain_real
+    outp = torch.empty(3, Rp, 2, n_src, dtype=torch.float32, device=dev)
+    plan.noise_batch(u[:1], 1, L.NORM_SUMMED_PIXCOUNT, L.PREC_FP32_GEO64, outp[:, :1])
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    plan.noise_batch(u[:Rp], Rp, L.NORM_SUMMED_PIXCOUNT, L.PREC_FP32_GEO64, outp)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_p = ev0.elapsed_time(ev1) / 1e3
+    maps_b = 3 * R / t_b
+    maps_p = 3 * Rp / t_p
+    flops = 8.0 * pairs1 * R  # one complex multiply-add per pair and realisation
+    res = {
+        "workload": f"{n_gal:.3g} galaxies in a 5000 deg2 field binned at NSIDE 2048 ({n_src} pixels), "
+                    f"{R} realisations x 3 scales (5/10/20 arcmin), tanh filter",
+        "maps": 3 * R,
+        "bf16x3_s": t_b,
+        "bf16x3_maps_per_s": maps_b,
+        "plain_fp32_maps_per_s": maps_p,
+        "plain_fp32_timed_realisations": Rp,
+        "speedup_vs_plain": maps_b / maps_p,
+        "realisation_pair_evals_per_s": pairs1 * R / t_b,
+        "mfma": {"bound": "mfma", "achieved": flops / t_b / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                 "frac": flops / t_b / 2.5e15,
+                 "note": "algorithmic 8 flop per (pair, realisation); split-BF16 issues 3 products per term"},
+        "binning_ms": bin_ms,
+    }
+    if not args.no_cpu:
+        res.update(batched_accuracy(data, src, u, out, outp, scales, R))
+    return res
+
+
+def batched_accuracy(data, src, u, out, outp, scales, R, n_check=512, seed=12):
+    """Oracle check of realisations 0, 1 and R-1 on a random sample of
+    centres inside a 1-degree patch."""
+    from oracle import aperture as A
+    from oracle import filters as F
+    from oracle import healpix_ref as hp
+
+    inf = data.info()
+    _, _, sums = data.export(sums=True)
+    srcs = src.cpu().numpy()
+    s = sums.cpu().numpy()[srcs - inf["pix_first"]]
+    rng = np.random.default_rng(seed)
+    c_pix = srcs[rng.integers(0, srcs.size)]
+    c = hp.pix2vec(2048, np.array([c_pix]))[0]
+    v = hp.pix2vec(2048, srcs)
+    d = np.arccos(np.clip(v @ c, -1, 1))
+    near = d < math.radians(1.0) + max(scales) + 0.01
+    inner = np.nonzero(d < math.radians(1.0))[0]
+    pick = np.sort(rng.choice(inner, min(n_check, inner.size), replace=False))
+    out_pix = srcs[pick]
+    sub = {"nside": 2048, "pix": srcs[near], "W": s[near, 2], "G1": s[near, 0], "G2": s[near, 1], "E2": s[near, 3]}
+    errs_b, errs_p = [], []
+    ob = out.cpu().numpy()
+    op = outp.cpu().numpy()
+    for r in (0, 1, R - 1):
+        ur = u[r].cpu().numpy()[near]
+        G1, G2 = A.rotate_realisation(sub["G1"], sub["G2"], ur)
+        mr = dict(sub, G1=G1, G2=G2)
+        for k, th in enumerate(scales):
+            ref = A.aperture_mass_pixel(mr, out_pix, th, F.TANH)
+            ok = ~ref["tie"]
+            for e, key in enumerate(("M_E", "M_B")):
+                rms = math.sqrt(np.mean(ref[key][ok] ** 2))
+                errs_b.append(float(np.max(np.abs(ob[k, r, e][pick][ok] - ref[key][ok])) / rms))
+                if r < op.shape[1]:
+                    errs_p.append(float(np.max(np.abs(op[k, r, e][pick][ok] - ref[key][ok])) / rms))
+    return {"max_rel_err_bf16x3": max(errs_b), "max_rel_err_plain_fp32": max(errs_p) if errs_p else None,
+            "accuracy_sample": f"{pick.size} centres x 3 scales x realisations (0, 1, {R - 1}), E and B"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -124,6 +246,10 @@ def main():
     from paper_2609_11181_amd import api
     from paper_2609_11181_amd import lib as L
     from synth import config3_pixelmap
+
+    if args.only_batched:
+        print(json.dumps({"batched": batched_leg(api.Context(0), args)}), flush=True)
+        return
 
     t = time.perf_counter()
     pm, R = config3_pixelmap(area_deg2=args.area, nside=args.nside)
@@ -221,6 +347,11 @@ def main():
             "sample": f"{out_pix.size} apertures x 3 scales in a 1-degree patch of the same map "
                       f"({cpairs} pairs, {cdt:.1f} s, numpy FP64 single thread)",
         }
+    if not args.no_batched:
+        keep.clear()
+        del outs, cols, pix
+        torch.cuda.empty_cache()
+        res["batched"] = batched_leg(ctx, args)
     print(json.dumps(res), flush=True)
 
 

@@ -86,8 +86,9 @@ enum {
 /* Arithmetic of the pair sums.                                               */
 enum {
   SMART_PREC_FP64 = 0,        /* everything in FP64; outputs are double      */
-  SMART_PREC_FP32_GEO64 = 1,  /* membership and separations in FP64, pair
-                                 terms in FP32, FP64 totals; outputs float  */
+  SMART_PREC_FP32_GEO64 = 1,  /* membership, geometry, spin-2 rotation and
+                                 E/B sums in FP64; filter table, W and V
+                                 sums in FP32; outputs float                */
   SMART_PREC_BF16X3 = 2       /* batched realisations only: split-BF16 MFMA
                                  with FP32 accumulation                      */
 };
@@ -162,6 +163,14 @@ int smart_pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* d_ring_p
 int smart_data_info(smart_data data, int64_t* n_gal, int* nside, int64_t* pix_first, int64_t* n_dense,
                     double* r_bin);
 
+/* Sources of the pixel variant: the occupied pixels of the map (for a map
+ * from smart_pixel_map, exactly the caller's pixel list; for binned
+ * galaxies, the pixels holding at least one galaxy), in increasing pixel
+ * order. n_src receives their number; d_src_pix (device, n_src int64, may
+ * be NULL) receives the pixels. Column j of the realisation angles of
+ * smart_noise_batch belongs to source j. Asynchronous on `stream`. */
+int smart_data_sources(smart_data data, int64_t* n_src, int64_t* d_src_pix, void* stream);
+
 /* Copy partition results to caller device buffers (any may be NULL):
  *   d_order   : n_gal int64, catalogue index of each sorted row
  *   d_offsets : 12 nside^2 + 1 int64 offset table
@@ -209,8 +218,8 @@ void smart_plan_free(smart_plan plan);
  * phase exp(2 i pi u[r][j]) (random orientations, Sect. 1 and Sect. 5.3)
  * and the E/B maps recomputed with the same apertures, weights and
  * normalisation (W, V and N do not change under the rotation).
- *   d_u    : n_real * n_dense floats in [0,1), row r for realisation r,
- *            column = dense pixel index (see smart_data_info)
+ *   d_u    : n_real * n_src floats in [0,1), row r for realisation r,
+ *            column j for source j (see smart_data_sources)
  *   d_out  : float, [n_scales][n_real][2][n_out] (E then B)
  *   precision : SMART_PREC_FP32_GEO64 (plain pair sums per realisation) or
  *               SMART_PREC_BF16X3 (split-BF16 MFMA contraction)

@@ -126,6 +126,14 @@ class Data:
         L.check(self.ctx.lib.smart_data_info(self.h, C.byref(n), C.byref(ns), C.byref(pf), C.byref(nd), C.byref(rb)))
         return {"n_gal": n.value, "nside": ns.value, "pix_first": pf.value, "n_dense": nd.value, "r_bin": rb.value}
 
+    def sources(self):
+        """Occupied source pixels of the pixel variant (device int64 tensor)."""
+        n = C.c_int64()
+        L.check(self.ctx.lib.smart_data_sources(self.h, C.byref(n), None, None))
+        t = torch.empty(n.value, dtype=torch.int64, device=self.ctx.device)
+        L.check(self.ctx.lib.smart_data_sources(self.h, C.byref(n), _ptr(t), _stream(self.ctx.device)))
+        return t
+
     def export(self, order=False, offsets=False, sums=False):
         inf = self.info()
         d = self.ctx.device

@@ -124,6 +124,8 @@ void smart_data_free(smart_data d) {
   hipFree(d->order);
   hipFree(d->offsets);
   hipFree(d->sums);
+  hipFree(d->cidx);
+  hipFree(d->src_pix);
   delete d;
 }
 
@@ -176,6 +178,19 @@ int smart_data_info(smart_data d, int64_t* n_gal, int* nside, int64_t* pix_first
   if (pix_first) *pix_first = d->pix_first;
   if (n_dense) *n_dense = d->n_dense;
   if (r_bin) *r_bin = d->r_bin;
+  return SMART_OK;
+}
+
+int smart_data_sources(smart_data d, int64_t* n_src, int64_t* d_src_pix, void* stream) {
+  if (!d || !n_src) return fail(SMART_EINVAL, "NULL argument");
+  if (!d->sums) return fail(SMART_EINVAL, "data holds no pixel sums");
+  *n_src = d->n_src;
+  if (d_src_pix && d->n_src > 0) {
+    int rc;
+    if ((rc = set_device(d->ctx))) return rc;
+    CHECK_HIP(hipMemcpyAsync(d_src_pix, d->src_pix, sizeof(int64_t) * d->n_src, hipMemcpyDeviceToDevice,
+                             (hipStream_t)stream));
+  }
   return SMART_OK;
 }
 
@@ -365,7 +380,7 @@ int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int 
   if (hipMallocAsync((void**)&stage, sizeof(float) * 5 * p->n_out, st) != hipSuccess)
     return fail(SMART_ENOMEM, "allocation failed for staging");
   for (int r = 0; r < n_real; ++r) {
-    hipError_t e = launch_rotate_map(d->sums, d_u + (int64_t)r * d->n_dense, d->n_dense, p->rot_map, st);
+    hipError_t e = launch_rotate_map(d->sums, d->cidx, d_u + (int64_t)r * d->n_src, d->n_dense, p->rot_map, st);
     if (e != hipSuccess) return fail(SMART_EDEVICE, "rotation kernel failed");
     for (int k = 0; k < ns; ++k) {
       const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);

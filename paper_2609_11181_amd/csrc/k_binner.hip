@@ -98,13 +98,29 @@ __global__ void k_check_pix(const int64_t* pix, int64_t n, int64_t npix, int* fl
 }
 
 __global__ void k_scatter(int64_t n, const int64_t* pix, int64_t pix_first, const float* W, const float* G1,
-                          const float* G2, const float* E2, float4* sums) {
+                          const float* G2, const float* E2, float4* sums, int* cidx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   sums[pix[i] - pix_first] = make_float4(G1[i], G2[i], W[i], E2[i]);
+  cidx[pix[i] - pix_first] = (int)i;
 }
 
-__global__ void k_counts_to_offsets_tail(int64_t* off, int64_t npix, int64_t n) { off[npix] = n; }
+__global__ void k_occupied(int64_t n_dense, int64_t pix_first, const int64_t* off, int* occ) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n_dense) occ[p] = off[pix_first + p + 1] > off[pix_first + p] ? 1 : 0;
+}
+
+__global__ void k_sources(int64_t n_dense, int64_t pix_first, const int* occ, const int* scan, int* cidx,
+                          int64_t* src_pix) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_dense) return;
+  if (occ[p]) {
+    cidx[p] = scan[p];
+    src_pix[scan[p]] = pix_first + p;
+  } else {
+    cidx[p] = -1;
+  }
+}
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -256,6 +272,36 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
       set_error("pixel-sum kernel failed to launch");
       return fail(SMART_EDEVICE);
     }
+    // source index of the occupied pixels
+    int *occ = nullptr, *scan = nullptr;
+    if ((rc = dmalloc(&occ, d->n_dense + 1)) || (rc = dmalloc(&scan, d->n_dense + 1)) ||
+        (rc = dmalloc(&d->cidx, d->n_dense)) || (rc = dmalloc(&d->src_pix, n))) {
+      (void)hipFree(occ);
+      (void)hipFree(scan);
+      return fail(rc);
+    }
+    hipLaunchKernelGGL(k_occupied, dim3(grid_of(d->n_dense)), dim3(kBlock), 0, st, d->n_dense, d->pix_first,
+                       d->offsets, occ);
+    size_t tb3 = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tb3, occ, scan, (int)d->n_dense, st);
+    if ((rc = ensure_temp(ctx, tb3))) return fail(rc);
+    tb3 = ctx->temp_bytes;
+    if (hipcub::DeviceScan::ExclusiveSum(ctx->d_temp, tb3, occ, scan, (int)d->n_dense, st) != hipSuccess) {
+      set_error("source scan failed");
+      return fail(SMART_EDEVICE);
+    }
+    hipLaunchKernelGGL(k_sources, dim3(grid_of(d->n_dense)), dim3(kBlock), 0, st, d->n_dense, d->pix_first, occ,
+                       scan, d->cidx, d->src_pix);
+    int last_scan = 0, last_occ = 0;
+    if (hipMemcpyAsync(&last_scan, scan + (d->n_dense - 1), 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&last_occ, occ + (d->n_dense - 1), 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("source count copy failed");
+      return fail(SMART_EDEVICE);
+    }
+    d->n_src = (int64_t)last_scan + last_occ;
+    (void)hipFree(occ);
+    (void)hipFree(scan);
   }
   cleanup();
   return SMART_OK;
@@ -294,9 +340,14 @@ int pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const flo
   d->kind = 1;
   d->nside = nside;
   ring_range(nside, pf, pl, d);
-  if ((rc = dmalloc(&d->sums, d->n_dense))) return rc;
+  if ((rc = dmalloc(&d->sums, d->n_dense)) || (rc = dmalloc(&d->cidx, d->n_dense)) || (rc = dmalloc(&d->src_pix, n)))
+    return rc;
+  d->n_src = n;
   HIPCHK(hipMemsetAsync(d->sums, 0, sizeof(float4) * d->n_dense, st));
-  hipLaunchKernelGGL(k_scatter, dim3(grid_of(n)), dim3(kBlock), 0, st, n, pix, d->pix_first, W, G1, G2, E2, d->sums);
+  HIPCHK(hipMemsetAsync(d->cidx, 0xff, sizeof(int) * d->n_dense, st));
+  HIPCHK(hipMemcpyAsync(d->src_pix, pix, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_scatter, dim3(grid_of(n)), dim3(kBlock), 0, st, n, pix, d->pix_first, W, G1, G2, E2, d->sums,
+                     d->cidx);
   HIPCHK(hipGetLastError());
   return SMART_OK;
 }

@@ -57,6 +57,10 @@ struct smart_data_s {
   int ring_lo = 0, ring_hi = -1;
   int64_t pix_first = 0, n_dense = 0;
   float4* sums = nullptr;  // (G1, G2, W, E2)
+  // sources of the pixel variant: occupied pixels in pixel order
+  int64_t n_src = 0;
+  int* cidx = nullptr;         // dense pixel -> source index, -1 when empty
+  int64_t* src_pix = nullptr;  // source index -> RING pixel
 };
 
 struct smart_plan_s {
@@ -146,7 +150,8 @@ int pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const flo
 hipError_t launch_check_pixels(const int64_t* pix, int64_t n, int64_t npix, int* d_flag, hipStream_t st);
 
 // noise realisations (k_noise.hip)
-hipError_t launch_rotate_map(const float4* map, const float* u, int64_t n, float4* out, hipStream_t st);
+hipError_t launch_rotate_map(const float4* map, const int* cidx, const float* u, int64_t n, float4* out,
+                             hipStream_t st);
 int noise_bf16x3(smart_plan plan, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st);
 
 // mixed batch (k_mixed.hip)

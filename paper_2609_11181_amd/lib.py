@@ -17,7 +17,8 @@ NORM_SUMMED_CAP, NORM_SUMMED_PIXCOUNT, NORM_RAW = 0, 1, 2
 
 EXPORTS = [
     "smart_init", "smart_finalize", "smart_last_error", "smart_version", "smart_filter_define",
-    "smart_filter_table", "smart_bin_galaxies", "smart_pixel_map", "smart_data_info", "smart_data_export",
+    "smart_filter_table", "smart_bin_galaxies", "smart_pixel_map", "smart_data_info", "smart_data_sources",
+    "smart_data_export",
     "smart_data_free", "smart_plan_create", "smart_run", "smart_last_pairs", "smart_plan_free",
     "smart_noise_batch", "smart_mixed_batch",
 ]
@@ -44,6 +45,7 @@ _SIGS = {
     "smart_pixel_map": (_int, [_vp, _int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
     "smart_data_info": (_int, [_vp, C.POINTER(_i64), C.POINTER(_int), C.POINTER(_i64), C.POINTER(_i64),
                                C.POINTER(C.c_double)]),
+    "smart_data_sources": (_int, [_vp, C.POINTER(_i64), _vp, _vp]),
     "smart_data_export": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "smart_data_free": (None, [_vp]),
     "smart_plan_create": (_int, [_vp, _vp, _int, _int, _i64, _vp, _int, C.POINTER(C.c_double),
