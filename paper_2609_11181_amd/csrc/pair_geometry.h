@@ -144,7 +144,7 @@ __device__ __forceinline__ void ring_xy(int m, double cphi, bool series, double 
 
 // ---- FP64 helpers ---------------------------------------------------------
 
-__device__ double filter_q64(double x, const ScaleArgs& s) {
+__device__ inline double filter_q64(double x, const ScaleArgs& s) {
   if (!(x < 1.0)) return 0.0;
   if (s.filter_kind == SMART_FILTER_POLY) return (6.0 / kPi) * x * x * (1.0 - x * x);
   const double* p = s.tanh_p;
