@@ -67,7 +67,7 @@ void smart_finalize(smart_ctx ctx) {
   hipSetDevice(ctx->device);
   for (auto& f : ctx->filters) {
     hipFree(f.d_table);
-    hipFree(f.d_table_lo);
+    hipFree(f.d_table_c0);
   }
   if (ctx->d_temp) hipFree(ctx->d_temp);
   delete ctx;
@@ -124,6 +124,7 @@ void smart_data_free(smart_data d) {
   hipFree(d->order);
   hipFree(d->offsets);
   hipFree(d->sums);
+  hipFree(d->wn);
   hipFree(d->cidx);
   hipFree(d->src_pix);
   delete d;
@@ -210,7 +211,12 @@ int smart_data_export(smart_data d, int64_t* d_order, int64_t* d_offsets, float*
   }
   if (d_sums) {
     if (!d->sums) return fail(SMART_EINVAL, "data holds no pixel sums");
-    CHECK_HIP(hipMemcpyAsync(d_sums, d->sums, sizeof(float4) * d->n_dense, hipMemcpyDeviceToDevice, st));
+    // stored as (G1, G2, E2, W); exported as (G1, G2, W, E2)
+    const float* s = (const float*)d->sums;
+    const size_t n = (size_t)d->n_dense, pitch = sizeof(float4);
+    CHECK_HIP(hipMemcpy2DAsync(d_sums, pitch, s, pitch, 2 * sizeof(float), n, hipMemcpyDeviceToDevice, st));
+    CHECK_HIP(hipMemcpy2DAsync(d_sums + 2, pitch, s + 3, pitch, sizeof(float), n, hipMemcpyDeviceToDevice, st));
+    CHECK_HIP(hipMemcpy2DAsync(d_sums + 3, pitch, s + 2, pitch, sizeof(float), n, hipMemcpyDeviceToDevice, st));
   }
   return SMART_OK;
 }
@@ -222,6 +228,7 @@ void smart_plan_free(smart_plan p) {
   hipFree(p->d_pairs);
   hipFree(p->d_work);
   hipFree(p->rot_map);
+  for (smart::PixelSched* sc : p->sched) delete sc;
   delete p;
 }
 
@@ -287,6 +294,15 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
     if (e != hipSuccess) return bail(SMART_EDEVICE, std::string("plan validation failed: ") + hipGetErrorString(e));
     if (h & 1) return bail(SMART_EINVAL, "output pixel out of range for nside_out");
   }
+  if (variant == SMART_VAR_PIXEL && precision == SMART_PREC_FP32_GEO64) {
+    for (int k = 0; k < n_scales; ++k) {
+      p->sched.push_back(new smart::PixelSched());
+      if ((rc = smart::build_pixel_sched(p, k, st, p->sched.back()))) {
+        smart_plan_free(p);
+        return rc;
+      }
+    }
+  }
   *out = p;
   return SMART_OK;
 }
@@ -308,6 +324,7 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.n_out = p->n_out;
       a.nside_out = p->nside_out;
       a.map = d->sums;
+      a.wn = d->wn;
       a.nside_in = d->nside;
       a.ring_lo = d->ring_lo;
       a.ring_hi = d->ring_hi;
@@ -315,7 +332,8 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.out = d_out;
       a.norm = norm;
       a.scale = k;
-      e = launch_pixel(a, s, p->precision, st, p->d_work);
+      e = p->precision == SMART_PREC_FP32_GEO64 ? launch_pixel_sched(a, s, *p->sched[k], st)
+                                                : launch_pixel(a, s, p->precision, st, p->d_work);
     } else {
       GalaxyArgs a{};
       a.out_pix = p->out_pix;
@@ -389,6 +407,7 @@ int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int 
       a.n_out = p->n_out;
       a.nside_out = p->nside_out;
       a.map = p->rot_map;
+      a.wn = d->wn;
       a.nside_in = d->nside;
       a.ring_lo = d->ring_lo;
       a.ring_hi = d->ring_hi;

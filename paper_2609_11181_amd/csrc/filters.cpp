@@ -92,11 +92,11 @@ int build_filter(FilterDef& f) {
   std::vector<double> qv(K + 1), dv(K + 1);
   for (int i = 0; i <= K; ++i) eval_both(f, i * h, &qv[i], &dv[i]);  // x = 1: left limit
   f.h_table.resize(4 * K);
-  std::vector<float> lo(K);
+  std::vector<double> c0(K);
   for (int i = 0; i < K; ++i) {
     const double q0 = qv[i], q1 = qv[i + 1], d0 = dv[i] * h, d1 = dv[i + 1] * h;
     f.h_table[4 * i + 0] = (float)q0;
-    lo[i] = (float)(q0 - (double)(float)q0);
+    c0[i] = q0;
     f.h_table[4 * i + 1] = (float)d0;
     f.h_table[4 * i + 2] = (float)(3.0 * (q1 - q0) - 2.0 * d0 - d1);
     f.h_table[4 * i + 3] = (float)(2.0 * (q0 - q1) + d0 + d1);
@@ -105,12 +105,12 @@ int build_filter(FilterDef& f) {
     set_error("hipMalloc failed for a filter table");
     return SMART_ENOMEM;
   }
-  if (hipMalloc(&f.d_table_lo, sizeof(float) * K) != hipSuccess) {
+  if (hipMalloc(&f.d_table_c0, sizeof(double) * K) != hipSuccess) {
     set_error("hipMalloc failed for a filter table");
     return SMART_ENOMEM;
   }
   if (hipMemcpy(f.d_table, f.h_table.data(), sizeof(float) * 4 * K, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(f.d_table_lo, lo.data(), sizeof(float) * K, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(f.d_table_c0, c0.data(), sizeof(double) * K, hipMemcpyHostToDevice) != hipSuccess) {
     set_error("copy of a filter table failed");
     return SMART_EDEVICE;
   }
@@ -129,13 +129,16 @@ ScaleArgs make_scale(smart_ctx ctx, double theta_ap, int filter_id, double omega
   s.filter_kind = f.kind;
   s.big = theta_ap > 2.0 * M_PI / 180.0 ? 1 : 0;
   s.table = f.d_table;
-  s.table_lo = f.d_table_lo;
-  // asin(y) / y = sum c_k y^(2k), divided by theta_ap so that x = y * P(y^2)
+  s.table_c0 = f.d_table_c0;
+  // asin(y) / y = sum c_k y^(2k), divided by theta_ap so that x = y * P(y^2);
+  // for tabulated filters also multiplied by the number of table pieces, so
+  // the series gives the table coordinate directly
   const double c[7] = {1.0, 1.0 / 6.0, 3.0 / 40.0, 5.0 / 112.0, 35.0 / 1152.0, 63.0 / 2816.0, 231.0 / 13312.0};
+  const double xs = (f.kind == SMART_FILTER_POLY ? 1.0 : (double)kFilterIntervals) / theta_ap;
   double f4 = 1.0;
   for (int k = 0; k < 7; ++k) {
-    s.tpoly[k] = c[k] / theta_ap;
-    s.cpoly[k] = c[k] / f4 / theta_ap;  // theta = c * P(c^2 / 4)
+    s.tpoly[k] = c[k] * xs;
+    s.cpoly[k] = c[k] / f4 * xs;  // theta = c * P(c^2 / 4)
     f4 *= 4.0;
   }
   for (int k = 0; k < 5; ++k) s.tanh_p[k] = f.params[k];

@@ -1,0 +1,268 @@
+// Belt tiles of the pixel variant (mixed precision).
+//
+// In the equatorial belt of the HEALPix grid (rings N .. 3N) every ring has
+// 4N pixels with the same azimuth step, so the pairs (centre i, source j) and
+// (centre i + t, source j + t) on the same two rings have the same
+// separation and the same polar angle (Sect. 3.2: the disc around a pixel is
+// a set of index intervals on the rings it crosses). For every belt ring that
+// hosts belt tiles, the sums over a disc therefore need one set of
+// coefficients (q cos 2psi, q sin 2psi, q^2) per disc member, the same for
+// every centre of the ring. They are built once per scale at plan creation:
+//
+//   k_belt_size  per centre ring: table rings and member count,
+//   (scan of the counts on the device, one copy of the totals to the host),
+//   k_belt_fill  per centre ring: ring entries and coefficients.
+//
+// The pair kernel k_pixel_belt then only streams the source records (one
+// load per four pairs, see belt_tile) and reads the coefficients through the
+// scalar cache: no geometry, no filter, no rotation per pair.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <string>
+
+#include "hpx_ring.h"
+#include "pair_geometry.h"
+#include "pixel_tiles.h"
+#include "smart_internal.h"
+
+namespace smart {
+
+namespace {
+
+// Disc rings of centre ring rp (a belt ring of the map grid) clipped to the
+// map's ring range.
+__device__ inline void belt_span(const PixelArgs& a, double theta_ap, int rp, int* lo, int* hi) {
+  const Ring R = ring_info(a.nside_in, rp);
+  ring_span(a.nside_in, atan2(R.s, R.z), theta_ap, lo, hi);
+  *lo = max(*lo, a.ring_lo);
+  *hi = min(*hi, a.ring_hi);
+}
+
+// cnts[rp - N] = (table rings, members) of every used centre ring.
+__global__ void k_belt_size(PixelArgs a, double theta_ap, double C_ap, const int* used, int2* cnts) {
+  const int N = a.nside_in;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx > 2 * N) return;
+  int2 c = make_int2(0, 0);
+  if (used[idx]) {
+    const int rp = N + idx;
+    const Ring R = ring_info(N, rp);
+    int lo, hi;
+    belt_span(a, theta_ap, rp, &lo, &hi);
+    const int nr = max(0, hi - lo + 1);
+    int total = 0;
+    for (int r = lo; r <= hi; ++r) {
+      int64_t jlo;
+      int cnt;
+      if (ring_window(R.z, R.s, R.twice_o, R.n, ring_info(N, r), C_ap, &jlo, &cnt)) total += cnt;
+    }
+    c = make_int2(nr, total);
+  }
+  cnts[idx] = c;
+}
+
+struct Sum2i {
+  __host__ __device__ int2 operator()(const int2& x, const int2& y) const { return make_int2(x.x + y.x, x.y + y.y); }
+};
+
+// One block per centre ring: ring entries, then the coefficients of every
+// member for the centre at azimuth index 0.
+template <bool TABLE, bool BIG>
+__global__ __launch_bounds__(kBlock) void k_belt_fill(PixelArgs a, ScaleArgs s, const int2* cnts, const int2* offs,
+                                                      int2* head, int4* info, double* qc, double* qs, float* q2) {
+  __shared__ int s_off[kRingCap + 1];
+  __shared__ int s_m0[kRingCap];
+  __shared__ double s_y0[kRingCap], s_kz[kRingCap];
+  const int N = a.nside_in, n = 4 * N;
+  const int idx = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int2 c = cnts[idx];
+  const int2 base = offs[idx];  // (first table ring, first coefficient)
+  if (tid == 0) head[idx] = make_int2(base.x, c.x);
+  if (c.x == 0) return;
+  const int rp = N + idx;
+  const Ring R = ring_info(N, rp);
+  int lo, hi;
+  belt_span(a, s.theta_ap, rp, &lo, &hi);
+  if (tid < c.x) {
+    const Ring Q = ring_info(N, lo + tid);
+    int64_t jlo = 0;
+    int cnt = 0;
+    if (!ring_window(R.z, R.s, R.twice_o, n, Q, s.C_ap, &jlo, &cnt)) {
+      jlo = 0;
+      cnt = 0;
+    }
+    s_off[tid + 1] = cnt;
+    s_m0[tid] = (int)((int64_t)R.twice_o * n - (2 * jlo + Q.twice_o) * (int64_t)n);
+    s_y0[tid] = ring_y0(Q.s, Q.z, R.z, R.s);
+    s_kz[tid] = 2.0 * Q.z * R.s;
+    info[base.x + tid] = make_int4(lo + tid, (int)jlo, cnt, 0);  // offset filled below
+  }
+  __syncthreads();
+  if (tid == 0) {
+    s_off[0] = 0;
+    for (int i = 0; i < c.x; ++i) s_off[i + 1] += s_off[i];
+  }
+  __syncthreads();
+  if (tid < c.x) info[base.x + tid].w = base.y + s_off[tid];
+  const double cphi = kPi / ((double)n * (double)n);
+  const int mstep = 2 * n;
+  double tp[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) tp[k] = s.tpoly[k];
+  const Tab tab{s.table, s.table_c0};
+  for (int f = tid; f < c.y; f += kBlock) {
+    int l = 0, h = c.x - 1;  // last ring with s_off <= f
+    while (l < h) {
+      const int mid = (l + h + 1) >> 1;
+      if (s_off[mid] <= f) l = mid;
+      else h = mid - 1;
+    }
+    const int k = f - s_off[l];
+    double xt, yt;
+    ring_xy(s_m0[l] - k * mstep, cphi, R.s, s_y0[l], s_kz[l], &xt, &yt);
+    const Coef cf = ring_coef<TABLE, BIG>(xt, yt, tp, tab);
+    qc[base.y + f] = cf.qc;
+    qs[base.y + f] = cf.qs;
+    q2[base.y + f] = cf.q2;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pixel_belt(PixelArgs a, ScaleArgs s, BeltTab t, const int* tiles,
+                                                       int n_tiles, int* cursors) {
+  for (;;) {
+    const int item = next_tile_wave(cursors, n_tiles);
+    if (item < 0) break;
+    belt_tile(a, s, t, (int64_t)tiles[item] * kBlock);
+  }
+}
+
+int grid_belt() {
+  static int grid = 0;
+  if (grid == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pixel_belt, kBlock, 0) != hipSuccess || per_cu <= 0)
+      per_cu = 2;
+    grid = std::max(cus, 1) * per_cu;
+  }
+  return grid;
+}
+
+}  // namespace
+
+hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int* list, int count,
+                       int* cursors, hipStream_t st) {
+  hipLaunchKernelGGL(k_pixel_belt, dim3(grid_belt()), dim3(kBlock), 0, st, a, s, t, list, count, cursors);
+  return hipGetLastError();
+}
+
+PixelSched::~PixelSched() {
+  (void)hipFree(list);
+  (void)hipFree(cursors);
+  (void)hipFree(head);
+  (void)hipFree(info);
+  (void)hipFree(qc);
+  (void)hipFree(qs);
+  (void)hipFree(q2);
+}
+
+#define BCHK(x)                                                                        \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) {                                                            \
+      (void)hipFree(used);                                                             \
+      (void)hipFree(flags);                                                            \
+      (void)hipFree(cnts);                                                             \
+      (void)hipFree(offs);                                                             \
+      set_error(std::string("plan schedule: ") + hipGetErrorString(e_) + " at " #x); \
+      return SMART_EDEVICE;                                                            \
+    }                                                                                  \
+  } while (0)
+
+int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
+  if (p->n_out == 0) return SMART_OK;  // nothing to schedule
+  smart_data d = p->data;
+  const int N = d->nside;
+  const double omega = 4.0 * M_PI / (12.0 * (double)N * (double)N);
+  const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);
+  PixelArgs a{};
+  a.out_pix = p->out_pix;
+  a.n_out = p->n_out;
+  a.nside_out = p->nside_out;
+  a.map = d->sums;
+  a.wn = d->wn;
+  a.nside_in = N;
+  a.ring_lo = d->ring_lo;
+  a.ring_hi = d->ring_hi;
+  a.pix_first = d->pix_first;
+  int* used = nullptr;
+  int* flags = nullptr;
+  int2* cnts = nullptr;
+  int2* offs = nullptr;
+  const int nb = 2 * N + 1;  // belt rings N .. 3N
+  const int nt = (int)((p->n_out + kBlock - 1) / kBlock);
+  sc->n_tiles = nt;
+  BCHK(hipMalloc((void**)&sc->list, sizeof(int) * (nt + 1)));
+  BCHK(hipMalloc((void**)&sc->cursors, sizeof(int) * 33));  // cursors, then the belt tile count
+  BCHK(hipMalloc((void**)&flags, sizeof(int) * (nt + 1)));
+  BCHK(hipMalloc((void**)&used, sizeof(int) * nb));
+  BCHK(hipMalloc((void**)&cnts, sizeof(int2) * nb));
+  BCHK(hipMalloc((void**)&offs, sizeof(int2) * nb));
+  BCHK(hipMalloc((void**)&sc->head, sizeof(int2) * nb));
+  BCHK(hipMemsetAsync(used, 0, sizeof(int) * nb, st));
+  // belt tiles first (ascending), then the general tiles
+  launch_classify(a, s.theta_ap, nt, flags, used, st);
+  BCHK(hipGetLastError());
+  size_t tb = 0, tb2 = 0;
+  hipcub::CountingInputIterator<int> ids(0);
+  BCHK(hipcub::DevicePartition::Flagged(nullptr, tb, ids, flags, sc->list, sc->cursors + 32, nt, st));
+  hipLaunchKernelGGL(k_belt_size, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.theta_ap, s.C_ap, used,
+                     cnts);
+  BCHK(hipGetLastError());
+  BCHK(hipcub::DeviceScan::ExclusiveScan(nullptr, tb2, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
+  if (ensure_temp(p->ctx, std::max(tb, tb2))) {
+    (void)hipFree(used);
+    (void)hipFree(flags);
+    (void)hipFree(cnts);
+    (void)hipFree(offs);
+    return SMART_ENOMEM;
+  }
+  tb = p->ctx->temp_bytes;
+  BCHK(hipcub::DevicePartition::Flagged(p->ctx->d_temp, tb, ids, flags, sc->list, sc->cursors + 32, nt, st));
+  tb = p->ctx->temp_bytes;
+  BCHK(hipcub::DeviceScan::ExclusiveScan(p->ctx->d_temp, tb, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
+  int n_belt = 0;
+  int2 last_c, last_o;
+  BCHK(hipMemcpyAsync(&n_belt, sc->cursors + 32, sizeof(int), hipMemcpyDeviceToHost, st));
+  BCHK(hipMemcpyAsync(&last_c, cnts + nb - 1, sizeof(int2), hipMemcpyDeviceToHost, st));
+  BCHK(hipMemcpyAsync(&last_o, offs + nb - 1, sizeof(int2), hipMemcpyDeviceToHost, st));
+  BCHK(hipStreamSynchronize(st));
+  sc->counts[0] = n_belt;
+  sc->counts[1] = nt - n_belt;
+  const int n_info = last_o.x + last_c.x, n_coef = last_o.y + last_c.y;
+  BCHK(hipMalloc((void**)&sc->info, sizeof(int4) * std::max(n_info, 1)));
+  BCHK(hipMalloc((void**)&sc->qc, sizeof(double) * std::max(n_coef, 1)));
+  BCHK(hipMalloc((void**)&sc->qs, sizeof(double) * std::max(n_coef, 1)));
+  BCHK(hipMalloc((void**)&sc->q2, sizeof(float) * std::max(n_coef, 1)));
+  const bool table = s.filter_kind != SMART_FILTER_POLY;
+  auto fill = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, a, s, cnts, offs, sc->head, sc->info, sc->qc, sc->qs,
+                       sc->q2);
+  };
+  if (table && s.big) fill(k_belt_fill<true, true>);
+  else if (table) fill(k_belt_fill<true, false>);
+  else if (s.big) fill(k_belt_fill<false, true>);
+  else fill(k_belt_fill<false, false>);
+  BCHK(hipGetLastError());
+  BCHK(hipStreamSynchronize(st));  // the scratch below is freed next
+  (void)hipFree(used);
+  (void)hipFree(flags);
+  (void)hipFree(cnts);
+  (void)hipFree(offs);
+  return SMART_OK;
+}
+
+}  // namespace smart

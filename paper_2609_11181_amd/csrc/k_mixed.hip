@@ -2,13 +2,15 @@
 // different NSIDE, field sizes, aperture radii and filters) drained by one
 // persistent launch.
 //
-// Each (plan, scale) is a job. Its tiles are classified as for a single run
-// (shared-stencil belt tiles and general tiles); the host orders the jobs by
-// estimated cost per tile, most expensive first (a longest-processing-time
-// order, so that the small jobs fill the tail of the launch), and a single
-// persistent kernel takes tiles from one global queue. Every tile runs the
-// same device code as the single-plan kernels, so results are identical to
-// smart_run.
+// Each (plan, scale) is a job whose tiles were classified at plan creation
+// (belt tiles with their ring tables, general tiles). Work items are
+// wave-sized: a whole belt tile (256 centres, four per lane) or a quarter of
+// a general tile (64 centres, one per lane). The host orders the item groups
+// by estimated cost per item, most expensive first (a longest-processing-time
+// order, so that the small items fill the tail of the launch), and every wave
+// of one persistent kernel takes items from one global queue. Every item runs
+// the same device code as the single-plan kernels, so results are identical
+// to smart_run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,69 +30,46 @@ namespace {
 struct MixJob {
   PixelArgs a;
   ScaleArgs s;
+  BeltTab t;
 };
 
-__global__ void k_classify_job(PixelArgs a, double theta_ap, int n_tiles, int* lists, int* counts) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  const int64_t o0 = (int64_t)t * kBlock;
-  bool ok = o0 + kBlock <= a.n_out && a.nside_in == a.nside_out;
-  if (ok) {
-    const int64_t p0 = a.out_pix[o0];
-    int rp, ip;
-    pixel_ring(a.nside_out, p0, &rp, &ip);
-    const Ring R = ring_info(a.nside_out, rp);
-    ok = ip + kBlock <= R.n && R.n == 4 * a.nside_in;
-    for (int k = 1; ok && k < kBlock; ++k) ok = a.out_pix[o0 + k] == p0 + k;
-    if (ok) {
-      int lo, hi;
-      ring_span(a.nside_in, atan2(R.s, R.z), theta_ap, &lo, &hi);
-      ok = lo >= a.nside_in && hi <= 3 * a.nside_in && hi - lo + 1 <= kRingCap;
-    }
-  }
-  const int which = ok ? 0 : 1;
-  const int slot = atomicAdd(&counts[which], 1);
-  lists[which * n_tiles + slot] = t;
-}
-
-// items[i] = (job, tile, kind): kind 0 = shared-stencil tile, 1 = general
+// items[i] = (job, tile, kind, part): kind 0 = belt tile, 1 = quarter `part`
+// of a general tile (each listed general tile expands into four items)
 __global__ void k_fill_items(const int* list, int count, int job, int kind, int4* items) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) items[i] = make_int4(job, list[i], kind, 0);
+  if (kind == 0) {
+    if (i < count) items[i] = make_int4(job, list[i], 0, 0);
+  } else {
+    if (i < 4 * count) items[i] = make_int4(job, list[i >> 2], 1, i & 3);
+  }
 }
 
 template <bool TABLE, bool BIG>
-__device__ __forceinline__ void run_item(const MixJob& J, int tile, int kind, Coef* coef, RingPar* rings) {
+__device__ __forceinline__ void general_quarter(const MixJob& J, int tile, int part) {
   double tp[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) tp[k] = J.s.tpoly[k];
-  if (kind == 0) {
-    stencil_tile<TABLE, BIG>(J.a, J.s, (int64_t)tile * kBlock, tp, coef, rings);
-  } else {
-    general_tile<TABLE, BIG>(J.a, J.s, tile, tp, Tab{J.s.table, J.s.table_lo});
-  }
+  const int64_t o = (int64_t)tile * kBlock + part * 64 + (threadIdx.x & 63);
+  general_centre<TABLE, BIG>(J.a, J.s, o, tp, Tab{J.s.table, J.s.table_c0});
 }
 
 __global__ __launch_bounds__(kBlock) void k_mixed(const MixJob* jobs, const int4* items, int n_items, int* counter) {
-  __shared__ Coef coef[kCoefCap];
-  __shared__ RingPar rings[kRingCap];
-  __shared__ int s_item;
   for (;;) {
-    if (threadIdx.x == 0) {
-      const int k = atomicAdd(counter, 1);
-      s_item = k < n_items ? k : -1;
-    }
-    __syncthreads();
-    const int it = s_item;
-    __syncthreads();
-    if (it < 0) break;
+    int it = 0;
+    if ((threadIdx.x & 63) == 0) it = atomicAdd(counter, 1);
+    it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+    if (it >= n_items) break;
     const int4 w = items[it];
     const MixJob& J = jobs[w.x];
-    const bool table = J.s.filter_kind != SMART_FILTER_POLY;
-    if (table && J.s.big) run_item<true, true>(J, w.y, w.z, coef, rings);
-    else if (table) run_item<true, false>(J, w.y, w.z, coef, rings);
-    else if (J.s.big) run_item<false, true>(J, w.y, w.z, coef, rings);
-    else run_item<false, false>(J, w.y, w.z, coef, rings);
+    if (w.z == 0) {
+      belt_tile(J.a, J.s, J.t, (int64_t)w.y * kBlock);
+    } else {
+      const bool table = J.s.filter_kind != SMART_FILTER_POLY;
+      if (table && J.s.big) general_quarter<true, true>(J, w.y, w.w);
+      else if (table) general_quarter<true, false>(J, w.y, w.w);
+      else if (J.s.big) general_quarter<false, true>(J, w.y, w.w);
+      else general_quarter<false, false>(J, w.y, w.w);
+    }
   }
 }
 
@@ -109,21 +88,28 @@ unsigned grid_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,
                 hipStream_t st) {
-  // jobs
+  // jobs and their item groups
+  struct Grp {
+    int job, kind, count;
+    const int* list;
+    double cost;  // estimated cost of one item
+  };
   std::vector<MixJob> jobs;
-  std::vector<int> job_tiles;
-  std::vector<double> job_cost;  // relative cost of one tile
+  std::vector<Grp> groups;
   for (int p = 0; p < n_plans; ++p) {
     const smart_plan P = plans[p];
     smart_data d = P->data;
+    if (P->n_out == 0) continue;
     const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
     for (int k = 0; k < (int)P->theta_ap.size(); ++k) {
+      const PixelSched& sc = *P->sched[k];
       MixJob J{};
       J.s = make_scale(ctx, P->theta_ap[k], P->filter_ids[k], omega);
       J.a.out_pix = P->out_pix;
       J.a.n_out = P->n_out;
       J.a.nside_out = P->nside_out;
       J.a.map = d->sums;
+      J.a.wn = d->wn;
       J.a.nside_in = d->nside;
       J.a.ring_lo = d->ring_lo;
       J.a.ring_hi = d->ring_hi;
@@ -131,57 +117,37 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
       J.a.out = outs[p];
       J.a.norm = norms[p];
       J.a.scale = k;
-      if (P->n_out == 0) continue;
+      J.t = sc.tab();
+      const int j = (int)jobs.size();
       jobs.push_back(J);
-      job_tiles.push_back((int)((P->n_out + kBlock - 1) / kBlock));
-      const double th = P->theta_ap[k];
-      job_cost.push_back(2.0 * M_PI * (1.0 - cos(th)) / omega);  // sources per disc
+      const double members = 2.0 * M_PI * (1.0 - cos(P->theta_ap[k])) / omega;  // sources per disc
+      // a belt pair costs about an eighth of a general pair
+      if (sc.counts[0] > 0) groups.push_back({j, 0, sc.counts[0], sc.lists(0), 256.0 * members});
+      if (sc.counts[1] > 0) groups.push_back({j, 1, sc.counts[1], sc.lists(1), 8.0 * 64.0 * members});
     }
   }
-  const int nj = (int)jobs.size();
-  if (nj == 0) return SMART_OK;
-  // classification of every job's tiles
-  std::vector<size_t> woff(nj + 1, 0);
-  for (int j = 0; j < nj; ++j) woff[j + 1] = woff[j] + 2 + 2 * (size_t)job_tiles[j];
-  int* work = nullptr;
-  MCHK(hipMallocAsync((void**)&work, sizeof(int) * woff[nj], st));
-  for (int j = 0; j < nj; ++j) {
-    int* w = work + woff[j];
-    MCHK(hipMemsetAsync(w, 0, 2 * sizeof(int), st));
-    hipLaunchKernelGGL(k_classify_job, dim3(grid_of(job_tiles[j])), dim3(kBlock), 0, st, jobs[j].a,
-                       jobs[j].s.theta_ap, job_tiles[j], w + 2, w);
-    MCHK(hipGetLastError());
-  }
-  std::vector<int> counts(2 * nj);
-  for (int j = 0; j < nj; ++j) MCHK(hipMemcpyAsync(&counts[2 * j], work + woff[j], 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-  MCHK(hipStreamSynchronize(st));
-  // longest first: general tiles cost about six times a stencil tile of the same disc
-  struct Grp {
-    int job, kind, count;
-    double cost;
-  };
-  std::vector<Grp> groups;
-  for (int j = 0; j < nj; ++j) {
-    if (counts[2 * j] > 0) groups.push_back({j, 0, counts[2 * j], job_cost[j]});
-    if (counts[2 * j + 1] > 0) groups.push_back({j, 1, counts[2 * j + 1], 6.0 * job_cost[j]});
-  }
+  if (groups.empty()) return SMART_OK;
   std::stable_sort(groups.begin(), groups.end(), [](const Grp& x, const Grp& y) { return x.cost > y.cost; });
-  int n_items = 0;
-  for (const Grp& g : groups) n_items += g.count;
+  int64_t n_items = 0;
+  for (const Grp& g : groups) n_items += g.kind == 0 ? g.count : 4 * (int64_t)g.count;
+  if (n_items > 0x7fffffff) {
+    set_error("mixed batch: too many work items");
+    return SMART_EINVAL;
+  }
   int4* items = nullptr;
   MixJob* d_jobs = nullptr;
   int* counter = nullptr;
-  MCHK(hipMallocAsync((void**)&items, sizeof(int4) * (size_t)std::max(n_items, 1), st));
-  MCHK(hipMallocAsync((void**)&d_jobs, sizeof(MixJob) * nj, st));
+  MCHK(hipMallocAsync((void**)&items, sizeof(int4) * (size_t)n_items, st));
+  MCHK(hipMallocAsync((void**)&d_jobs, sizeof(MixJob) * jobs.size(), st));
   MCHK(hipMallocAsync((void**)&counter, sizeof(int), st));
-  MCHK(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(MixJob) * nj, hipMemcpyHostToDevice, st));
+  MCHK(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(MixJob) * jobs.size(), hipMemcpyHostToDevice, st));
   MCHK(hipMemsetAsync(counter, 0, sizeof(int), st));
-  int off = 0;
+  int64_t off = 0;
   for (const Grp& g : groups) {
-    const int* list = work + woff[g.job] + 2 + (size_t)g.kind * job_tiles[g.job];
-    hipLaunchKernelGGL(k_fill_items, dim3(grid_of(g.count)), dim3(kBlock), 0, st, list, g.count, g.job, g.kind,
+    const int n = g.kind == 0 ? g.count : 4 * g.count;
+    hipLaunchKernelGGL(k_fill_items, dim3(grid_of(n)), dim3(kBlock), 0, st, g.list, g.count, g.job, g.kind,
                        items + off);
-    off += g.count;
+    off += n;
   }
   MCHK(hipGetLastError());
   static int grid = 0;
@@ -193,14 +159,11 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
       per_cu = 2;
     grid = std::max(cus, 1) * per_cu;
   }
-  if (n_items > 0) {
-    hipLaunchKernelGGL(k_mixed, dim3(grid), dim3(kBlock), 0, st, d_jobs, items, n_items, counter);
-    MCHK(hipGetLastError());
-  }
+  hipLaunchKernelGGL(k_mixed, dim3(grid), dim3(kBlock), 0, st, d_jobs, items, (int)n_items, counter);
+  MCHK(hipGetLastError());
   MCHK(hipFreeAsync(items, st));
   MCHK(hipFreeAsync(d_jobs, st));
   MCHK(hipFreeAsync(counter, st));
-  MCHK(hipFreeAsync(work, st));
   return SMART_OK;
 }
 

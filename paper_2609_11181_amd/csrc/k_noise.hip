@@ -121,7 +121,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_noise_mfma(NoiseArgs n, ScaleAr
   const int tile = n.tiles[blockIdx.x / n.n_grp];
   const int rb = (blockIdx.x % n.n_grp) * kWaves + wave;  // realisation block of this wave
   const int64_t o0 = (int64_t)tile * kNP;
-  const Tab tab{s.table, s.table_lo};
+  const Tab tab{s.table, s.table_c0};
   uint2* xs = xsm[wave];
   double tp[7];
 #pragma unroll
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_noise_mfma(NoiseArgs n, ScaleAr
     if (!ring_window(zp, sp, ip2_0, nr, Q, s.C_ap, &jlo, &cnt)) continue;  // block-uniform
     const int L = kNP + cnt - 1;  // slab: centre t uses slab pixels [t, t + cnt)
     const int m0 = (int)(ip2_0 * nr - (2 * jlo + Q.twice_o) * (int64_t)nr);
-    const double Y0 = Q.s * zp - Q.z * sp;
+    const double Y0 = ring_y0(Q.s, Q.z, zp, sp);
     const double Kz = 2.0 * Q.z * sp;
     const int64_t dbase = Q.first - a.pix_first;
     int j0 = (int)(jlo % nr);
@@ -163,14 +163,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_noise_mfma(NoiseArgs n, ScaleAr
     for (int k = tid; k < cnt; k += 64 * kWaves) {
       const int m = m0 - k * mstep;
       double xt, yt;
-      ring_xy(m, cphi, (double)abs(m) * cphi <= 0.5, sp, Y0, Kz, &xt, &yt);
+      ring_xy(m, cphi, sp, Y0, Kz, &xt, &yt);
       const Coef c = ring_coef<TABLE, BIG>(xt, yt, tp, tab);
       coefA[k] = split_pair((float)c.qc, (float)c.qs);
     }
     for (int k = tid; k < L; k += 64 * kWaves) {
       int j = j0 + k;
       j = j >= nr ? j - nr : j;
-      wsl[k] = a.map[dbase + j].z;
+      wsl[k] = a.map[dbase + j].w;
     }
     __syncthreads();
     if (tid < kNP) {
@@ -336,6 +336,7 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
     a.n_out = p->n_out;
     a.nside_out = p->nside_out;
     a.map = d->sums;
+    a.wn = d->wn;
     a.nside_in = d->nside;
     a.ring_lo = d->ring_lo;
     a.ring_hi = d->ring_hi;
@@ -401,6 +402,7 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
       b.out_pix = pix2;
       b.n_out = n_sub;
       b.map = p->rot_map;
+      b.wn = d->wn;
       b.out = stage;
       b.scale = 0;
       for (int r = 0; r < n_real; ++r) {

@@ -36,73 +36,63 @@ namespace smart {
 
 namespace {
 
-__global__ void k_classify(PixelArgs a, double theta_ap, int n_tiles, int* lists, int* counts) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per tile: the lanes compare the tile's 256 list entries with
+// consecutive pixel indices, then every lane takes the same decision.
+__global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_ap, int n_tiles, int* flags,
+                                                     int* used) {
+  const int t = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (t >= n_tiles) return;
   const int64_t o0 = (int64_t)t * kBlock;
   bool ok = o0 + kBlock <= a.n_out && a.nside_in == a.nside_out;
+  int rp = 0;
   if (ok) {
     const int64_t p0 = a.out_pix[o0];
-    int rp, ip;
-    pixel_ring(a.nside_out, p0, &rp, &ip);
-    const Ring R = ring_info(a.nside_out, rp);
-    ok = ip + kBlock <= R.n && R.n == 4 * a.nside_in;
-    for (int k = 1; ok && k < kBlock; ++k) ok = a.out_pix[o0 + k] == p0 + k;
+    bool run = true;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) run = run && a.out_pix[o0 + lane + 64 * k] == p0 + lane + 64 * k;
+    ok = __all(run);
     if (ok) {
-      int lo, hi;
-      ring_span(a.nside_in, atan2(R.s, R.z), theta_ap, &lo, &hi);
-      ok = lo >= a.nside_in && hi <= 3 * a.nside_in && hi - lo + 1 <= kRingCap;
+      int ip;
+      pixel_ring(a.nside_out, p0, &rp, &ip);
+      const Ring R = ring_info(a.nside_out, rp);
+      ok = ip + kBlock <= R.n && R.n == 4 * a.nside_in;
+      if (ok) {
+        int lo, hi;
+        ring_span(a.nside_in, atan2(R.s, R.z), theta_ap, &lo, &hi);
+        ok = lo >= a.nside_in && hi <= 3 * a.nside_in && hi - lo + 1 <= kRingCap;
+      }
     }
   }
-  const int which = ok ? 0 : 1;
-  const int slot = atomicAdd(&counts[which], 1);
-  lists[which * n_tiles + slot] = t;
+  if (lane == 0) {
+    flags[t] = ok ? 1 : 0;
+    if (ok) used[rp - a.nside_in] = 1;
+  }
 }
 
 // ---- pixel variant, mixed precision: general kernel -------------------------------
 
 template <bool TABLE, bool BIG>
-__global__ __launch_bounds__(kBlock) void k_pixel_f32(PixelArgs a, ScaleArgs s, const int* tiles, const int* count,
+__global__ __launch_bounds__(kBlock) void k_pixel_f32(PixelArgs a, ScaleArgs s, const int* tiles, int n_tiles,
                                                       int* cursors) {
   __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
-  __shared__ float tab_lo[TABLE ? kFilterIntervals : 1];
+  __shared__ double tab_c0[TABLE ? kFilterIntervals : 1];
   __shared__ int s_item;
-  const int n_tiles = *count;
-  if (n_tiles == 0) return;
   if (TABLE) {
     for (int k = threadIdx.x; k < kFilterIntervals; k += blockDim.x) {
       tab_c[k] = s.table[k];
-      tab_lo[k] = s.table_lo[k];
+      tab_c0[k] = s.table_c0[k];
     }
   }
-  const Tab tab{tab_c, tab_lo};
+  const Tab tab{tab_c, tab_c0};
   double tp[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) tp[k] = s.tpoly[k];
   for (;;) {
     const int item = next_tile(cursors, n_tiles, &s_item);  // also orders the table load
     if (item < 0) break;
-    general_tile<TABLE, BIG>(a, s, tiles[item], tp, tab);
-  }
-}
-
-// ---- pixel variant, mixed precision: stencil kernel --------------------------------
-
-template <bool TABLE, bool BIG>
-__global__ __launch_bounds__(kBlock) void k_pixel_stencil(PixelArgs a, ScaleArgs s, const int* tiles,
-                                                          const int* count, int* cursors) {
-  __shared__ Coef coef[kCoefCap];
-  __shared__ RingPar rings[kRingCap];
-  __shared__ int s_item;
-  const int n_tiles = *count;
-  if (n_tiles == 0) return;
-  double tp[7];
-#pragma unroll
-  for (int k = 0; k < 7; ++k) tp[k] = s.tpoly[k];
-  for (;;) {
-    const int item = next_tile(cursors, n_tiles, &s_item);
-    if (item < 0) break;
-    stencil_tile<TABLE, BIG>(a, s, (int64_t)tiles[item] * kBlock, tp, coef, rings);
+    const int tile = tiles ? tiles[item] : item;
+    general_centre<TABLE, BIG>(a, s, (int64_t)tile * kBlock + threadIdx.x, tp, tab);
   }
 }
 
@@ -130,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_pixel_f64(PixelArgs a, ScaleArgs s) 
     const int nq = Q.n;
     int64_t m = ip2 * nq - (2 * jlo + Q.twice_o) * (int64_t)np;
     const double cphi = kPi / ((double)np * (double)nq);
-    const double Y0 = Q.s * zp - Q.z * sp;
+    const double Y0 = ring_y0(Q.s, Q.z, zp, sp);
     const double Kz = 2.0 * Q.z * sp;
     int jw = (int)(((jlo % nq) + nq) % nq);
     const float4* base = a.map + (Q.first - a.pix_first);
@@ -138,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_pixel_f64(PixelArgs a, ScaleArgs s) 
       const float4 g = base[jw];
       double sh, ch;
       sincos(0.5 * (double)m * cphi, &sh, &ch);
-      pair_f64(sp * 2.0 * sh * ch, Y0 + Kz * sh * sh, g.x, g.y, g.z, g.w, g.z > 0.f ? 1.0 : 0.0, s, tot);
+      pair_f64(sp * 2.0 * sh * ch, Y0 + Kz * sh * sh, g.x, g.y, g.w, g.z, g.w > 0.f ? 1.0 : 0.0, s, tot);
       m -= 2 * np;
       jw = (jw + 1 == nq) ? 0 : jw + 1;
     }
@@ -181,15 +171,15 @@ __device__ __forceinline__ int ring_slices(const Ring& Q, int64_t jlo, int cnt, 
 template <bool TABLE, bool BIG>
 __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s) {
   __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
-  __shared__ float tab_lo[TABLE ? kFilterIntervals : 1];
+  __shared__ double tab_c0[TABLE ? kFilterIntervals : 1];
   if (TABLE) {
     for (int k = threadIdx.x; k < kFilterIntervals; k += blockDim.x) {
       tab_c[k] = s.table[k];
-      tab_lo[k] = s.table_lo[k];
+      tab_c0[k] = s.table_c0[k];
     }
     __syncthreads();
   }
-  const Tab tab{tab_c, tab_lo};
+  const Tab tab{tab_c, tab_c0};
   const int64_t o = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (o >= a.n_out) return;
   double cp[7];
@@ -357,15 +347,25 @@ static int persistent_grid(K kernel) {
 }
 
 template <bool TABLE, bool BIG>
-static hipError_t launch_pixel_t(const PixelArgs& a, const ScaleArgs& s, hipStream_t st, int n_tiles, int* counts,
-                                 int* lists, int* cursors) {
-  const dim3 block(kBlock);
-  static const int g_st = persistent_grid(k_pixel_stencil<TABLE, BIG>);
-  static const int g_gen = persistent_grid(k_pixel_f32<TABLE, BIG>);
-  hipLaunchKernelGGL((k_pixel_stencil<TABLE, BIG>), dim3(g_st), block, 0, st, a, s, lists, counts, cursors);
-  hipLaunchKernelGGL((k_pixel_f32<TABLE, BIG>), dim3(g_gen), block, 0, st, a, s, lists + n_tiles, counts + 1,
-                     cursors + 16);
+static hipError_t launch_general_t(const PixelArgs& a, const ScaleArgs& s, hipStream_t st, const int* list,
+                                   int count, int* cursors) {
+  static const int grid = persistent_grid(k_pixel_f32<TABLE, BIG>);
+  hipLaunchKernelGGL((k_pixel_f32<TABLE, BIG>), dim3(grid), dim3(kBlock), 0, st, a, s, list, count, cursors);
   return hipGetLastError();
+}
+
+static hipError_t launch_general(const PixelArgs& a, const ScaleArgs& s, hipStream_t st, const int* list, int count,
+                                 int* cursors) {
+  const bool table = s.filter_kind != SMART_FILTER_POLY;
+  if (table && s.big) return launch_general_t<true, true>(a, s, st, list, count, cursors);
+  if (table) return launch_general_t<true, false>(a, s, st, list, count, cursors);
+  if (s.big) return launch_general_t<false, true>(a, s, st, list, count, cursors);
+  return launch_general_t<false, false>(a, s, st, list, count, cursors);
+}
+
+__global__ void k_zero_ints(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, hipStream_t st, int* d_work) {
@@ -375,23 +375,30 @@ hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, h
     hipLaunchKernelGGL(k_pixel_f64, dim3((unsigned)blocks_for(a.n_out)), block, 0, st, a, s);
     return hipGetLastError();
   }
-  // d_work: 2 tile counts, 2 x 16 cursor words, then two tile lists
-  const int n_tiles = (int)blocks_for(a.n_out);
-  int* counts = d_work;
-  int* cursors = d_work + 2;
-  int* lists = d_work + 34;
-  hipError_t e = hipMemsetAsync(d_work, 0, 34 * sizeof(int), st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_classify, dim3((unsigned)blocks_for(n_tiles)), block, 0, st, a, s.theta_ap, n_tiles, lists,
-                     counts);
-  const bool table = s.filter_kind != SMART_FILTER_POLY;
-  if (table && s.big) return launch_pixel_t<true, true>(a, s, st, n_tiles, counts, lists, cursors);
-  if (table) return launch_pixel_t<true, false>(a, s, st, n_tiles, counts, lists, cursors);
-  if (s.big) return launch_pixel_t<false, true>(a, s, st, n_tiles, counts, lists, cursors);
-  return launch_pixel_t<false, false>(a, s, st, n_tiles, counts, lists, cursors);
+  // d_work: the 16 queue cursors; every tile takes the general kernel
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, d_work, 16);
+  return launch_general(a, s, st, nullptr, (int)blocks_for(a.n_out), d_work);
 }
 
-size_t pixel_work_ints(int64_t n_out) { return 34 + 2 * (size_t)blocks_for(n_out); }
+hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st) {
+  if (a.n_out == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, sc.cursors, 32);
+  hipError_t e = hipSuccess;
+  if (sc.counts[0] > 0) e = launch_belt(a, s, sc.tab(), sc.lists(0), sc.counts[0], sc.cursors, st);
+  if (e == hipSuccess && sc.counts[1] > 0) e = launch_general(a, s, st, sc.lists(1), sc.counts[1], sc.cursors + 16);
+  return e;
+}
+
+void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* flags, int* used, hipStream_t st) {
+  const unsigned blocks = (unsigned)((n_tiles + kBlock / 64 - 1) / (kBlock / 64));
+  if (n_tiles > 0)
+    hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(kBlock), 0, st, a, theta_ap, n_tiles, flags, used);
+}
+
+size_t pixel_work_ints(int64_t n_out) {
+  (void)n_out;
+  return 16;
+}
 
 hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, hipStream_t st) {
   const dim3 grid((unsigned)blocks_for(a.n_out)), block(kBlock);

@@ -38,7 +38,8 @@ struct Acc64 {
 };
 
 // theta / theta_ap = y * P(y^2) with P the series of asin(y)/y (y = sin
-// theta) or of 2 asin(y/2)/y (y = chord), pre-divided by theta_ap. Three
+// theta) or of 2 asin(y/2)/y (y = chord), pre-divided by theta_ap (and, for
+// tabulated filters, pre-multiplied by the number of table pieces). Three
 // terms reach 1e-10 for apertures up to 2 degrees, seven up to 0.25 rad.
 template <bool BIG>
 __device__ __forceinline__ double theta_ratio(double y, double y2, const double* c) {
@@ -56,23 +57,26 @@ __device__ __forceinline__ double theta_ratio(double y, double y2, const double*
   return y * p;
 }
 
-// Filter table in LDS: cubic pieces (c0, c1, c2, c3) in FP32 plus the FP32
-// remainder of c0, so that q = (c0 + c0_lo) + f (c1 + f (c2 + f c3)) is
-// good to the table's own interpolation error (1e-8 of the maximum).
+// Filter table: cubic pieces with c0 in FP64 and (c1, c2, c3) in FP32, so
+// that q = c0 + f (c1 + f (c2 + f c3)) is good to the table's own
+// interpolation error (1e-8 of the maximum).
 struct Tab {
-  const float4* c;
-  const float* lo;
+  const float4* c;   // (c0 rounded, c1, c2, c3)
+  const double* c0;  // c0
 };
 
+// q of a table coordinate t = x * kFilterIntervals (TABLE), or of x for the
+// polynomial filter.
 template <bool TABLE>
 __device__ __forceinline__ double filter_q(double x, Tab tab) {
   if (TABLE) {
-    const double t = fmin(x, 0.9999999999) * (double)kFilterIntervals;
+    const double t = fmin(x, (double)kFilterIntervals - 2e-7);
     const int i = (int)t;
-    const float f = (float)(t - (double)i);
+    const double fd = __builtin_amdgcn_fract(t);
+    const float f = (float)fd;
     const float4 c = tab.c[i];
     const float p = fmaf(f, fmaf(f, c.w, c.z), c.y);
-    return fma((double)f, (double)p, (double)c.x + (double)tab.lo[i]);
+    return fma(fd, (double)p, tab.c0[i]);
   } else {
     const double u = fmin(x * x, 1.0);
     const double k = 6.0 / kPi;
@@ -83,13 +87,13 @@ __device__ __forceinline__ double filter_q(double x, Tab tab) {
 // Filter-weighted rotation coefficients of one member: q cos 2psi and
 // q sin 2psi in FP64 (the spin-2 rotation and the E/B sums run in FP64,
 // full rate on this GPU, so a source with a large shear cannot leak the
-// rounding of its E term into B) and q.
+// rounding of its E term into B) and q^2 for the noise sum.
 struct Coef {
   double qc, qs;
-  float q, pad;
+  float q2, pad;
 };
 
-// Accumulation of one member: E/B in FP64; W, V and N in FP32 runs.
+// Accumulation of one galaxy member: E/B in FP64; W, V and N in FP32 runs.
 __device__ __forceinline__ void accumulate(double qc, double qs, float q, double a1, double a2, float Ws, float Vs,
                                            int occ, Acc64& tot, Acc32& acc) {
   tot.se = fma(qc, a1, fma(qs, a2, tot.se));
@@ -99,47 +103,151 @@ __device__ __forceinline__ void accumulate(double qc, double qs, float q, double
   acc.sn += occ;
 }
 
+// Accumulation of one pixel member: E/B in FP64, V in an FP32 run (W and
+// N of pixel runs come from the prefix sums, see run_wn).
+__device__ __forceinline__ void accumulate_pix(const Coef& c, float4 g, Acc64& tot, float& sv) {
+  const double a1 = (double)g.x, a2 = (double)g.y;
+  tot.se = fma(c.qc, a1, fma(c.qs, a2, tot.se));
+  tot.sb = fma(c.qc, a2, fma(-c.qs, a1, tot.sb));
+  sv = fmaf(c.q2, g.z, sv);
+}
+
+// Four interleaved partial E/B/V sums for runs of pixel members that share
+// precomputed coefficients: member u goes to partial u % 4, so consecutive
+// members do not wait on each other's FMA results.
+struct Part4 {
+  double se[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0};
+  float sv[4] = {0.f, 0.f, 0.f, 0.f};
+  __device__ __forceinline__ void add(int u, const Coef& c, float4 g) {
+    const double a1 = (double)g.x, a2 = (double)g.y;
+    se[u & 3] = fma(c.qc, a1, fma(c.qs, a2, se[u & 3]));
+    sb[u & 3] = fma(c.qc, a2, fma(-c.qs, a1, sb[u & 3]));
+    sv[u & 3] = fmaf(c.q2, g.z, sv[u & 3]);
+  }
+  __device__ __forceinline__ void flush_v(Acc64& tot) {
+    tot.sv += (double)((sv[0] + sv[1]) + (sv[2] + sv[3]));
+    sv[0] = sv[1] = sv[2] = sv[3] = 0.f;
+  }
+  __device__ __forceinline__ void flush(Acc64& tot) {
+    tot.se += (se[0] + se[1]) + (se[2] + se[3]);
+    tot.sb += (sb[0] + sb[1]) + (sb[2] + sb[3]);
+    flush_v(tot);
+  }
+};
+
+// W and N_occ of the dense pixels [d0, d0 + c) of one ring run.
+__device__ __forceinline__ void run_wn(const double2* wn, int64_t d0, int c, Acc64& tot) {
+  const double2 lo = wn[d0], hi = wn[d0 + c];
+  tot.sw += hi.x - lo.x;
+  tot.sn += hi.y - lo.y;
+}
+
 // Coefficients of a member from its FP64 tangent-plane components (xt, yt)
 // at the source; x^2 + y^2 = sin^2 theta. The reciprocal square root is
-// seeded by v_rsq_f32 and refined by one Newton step in FP64 (about 1e-14);
-// a source closer than 1e-10 rad to the centre has no defined polar angle
-// and gets no shear term.
+// seeded by v_rsq_f32 and refined by one Newton step in FP64 (about 1e-14).
+// A source closer than 1e-10 rad to the centre has no defined polar angle:
+// sin^2 theta is clamped at 1e-20 for the reciprocal, so the shear terms of
+// the coincident source (xt = yt = 0) vanish, and the filter sees theta = 0.
+// On a HEALPix grid no other source comes that close.
 template <bool TABLE, bool BIG>
 __device__ __forceinline__ Coef ring_coef(double xt, double yt, const double* tp, Tab tab) {
   const double S2 = fma(xt, xt, yt * yt);
-  const double r0 = (double)__builtin_amdgcn_rsqf((float)S2);
-  double r = r0 * fma(-0.5 * S2, r0 * r0, 1.5);
-  r = S2 >= (double)kCoincidentS2 ? r : 0.0;
-  const double inv = r * r;
+  const double S2c = fmax(S2, (double)kCoincidentS2);
+  const double r0 = (double)__builtin_amdgcn_rsqf((float)S2c);
+  const double r = r0 * fma(-0.5 * S2c, r0 * r0, 1.5);
   const double q = filter_q<TABLE>(theta_ratio<BIG>(S2 * r, S2, tp), tab);
+  const double qn = q * (r * r);  // q / sin^2 theta
   Coef c;
-  c.qc = q * (fma(yt, yt, -xt * xt) * inv);
-  c.qs = q * (-2.0 * xt * yt * inv);
-  c.q = (float)q;
+  c.qc = qn * fma(yt, yt, -xt * xt);
+  c.qs = qn * (-2.0 * xt * yt);
+  c.q2 = (float)(q * q);
   c.pad = 0.f;
   return c;
 }
 
+// sin(a) and sin^2(a/2) of an azimuth offset |a| <= pi. For |a| <= 1/2 the
+// Taylor series of both to degree 13/14 (relative error below 1e-16); beyond, b = a / 4 is
+// within pi/4, where the Taylor series of sin b and cos b to degree 15/16
+// are good to 1e-16, and the double-angle formulas give sin(a/2) = 2 sb cb,
+// cos(a/2) = 1 - 2 sb^2. (A general sincos carries a large-argument
+// reduction this bounded range never needs.)
+__device__ __forceinline__ void sin_hav(double av, double* sa, double* h) {
+  if (fabs(av) <= 0.5) {
+    const double a2 = av * av;
+    double ps = fma(a2, 1.0 / 6227020800.0, -1.0 / 39916800.0);
+    ps = fma(a2, ps, 1.0 / 362880.0);
+    ps = fma(a2, ps, -1.0 / 5040.0);
+    ps = fma(a2, ps, 1.0 / 120.0);
+    ps = fma(a2, ps, -1.0 / 6.0);
+    *sa = fma(av * a2, ps, av);
+    double ph = fma(a2, 1.0 / 174356582400.0, -1.0 / 958003200.0);
+    ph = fma(a2, ph, 1.0 / 7257600.0);
+    ph = fma(a2, ph, -1.0 / 80640.0);
+    ph = fma(a2, ph, 1.0 / 1440.0);
+    ph = fma(a2, ph, -1.0 / 48.0);
+    *h = a2 * fma(a2, ph, 0.25);
+  } else {
+    const double b = 0.25 * av, b2 = b * b;
+    double ps = fma(b2, -1.0 / 1307674368000.0, 1.0 / 6227020800.0);
+    ps = fma(b2, ps, -1.0 / 39916800.0);
+    ps = fma(b2, ps, 1.0 / 362880.0);
+    ps = fma(b2, ps, -1.0 / 5040.0);
+    ps = fma(b2, ps, 1.0 / 120.0);
+    ps = fma(b2, ps, -1.0 / 6.0);
+    const double sb = fma(b * b2, ps, b);
+    double pc = fma(b2, 1.0 / 20922789888000.0, -1.0 / 87178291200.0);
+    pc = fma(b2, pc, 1.0 / 479001600.0);
+    pc = fma(b2, pc, -1.0 / 3628800.0);
+    pc = fma(b2, pc, 1.0 / 40320.0);
+    pc = fma(b2, pc, -1.0 / 720.0);
+    pc = fma(b2, pc, 1.0 / 24.0);
+    pc = fma(b2, pc, -0.5);
+    const double cb = fma(b2, pc, 1.0);
+    const double sh = 2.0 * sb * cb;          // sin(a/2)
+    const double ch = fma(-2.0 * sb, sb, 1.0);  // cos(a/2)
+    *sa = 2.0 * sh * ch;
+    *h = sh * sh;
+  }
+}
+
 // Tangent-plane components of a ring source at azimuth offset
 // dphi = m * cphi from the centre: x = s_p sin(dphi),
-// y = Y0 + Kz sin^2(dphi/2). For |dphi| <= 1/2 Taylor series (error below
-// 1e-10 relative), otherwise sincos.
-__device__ __forceinline__ void ring_xy(int m, double cphi, bool series, double sp, double Y0, double Kz,
-                                        double* xt, double* yt) {
-  const double av = (double)m * cphi;
+// y = Y0 + Kz sin^2(dphi/2).
+__device__ __forceinline__ void ring_xy(int m, double cphi, double sp, double Y0, double Kz, double* xt,
+                                        double* yt) {
   double sa, h;
-  if (series) {
-    const double a2 = av * av;
-    sa = av * fma(a2, fma(a2, fma(a2, fma(a2, 1.0 / 362880.0, -1.0 / 5040.0), 1.0 / 120.0), -1.0 / 6.0), 1.0);
-    h = a2 * fma(a2, fma(a2, fma(a2, fma(a2, 1.0 / 7257600.0, -1.0 / 80640.0), 1.0 / 1440.0), -1.0 / 48.0), 0.25);
-  } else {
-    double sh, ch;
-    sincos(0.5 * av, &sh, &ch);
-    sa = 2.0 * sh * ch;
-    h = sh * sh;
-  }
+  sin_hav((double)m * cphi, &sa, &h);
   *xt = sp * sa;
   *yt = fma(Kz, h, Y0);
+}
+
+// Walk along a ring: (sin a, sin^2(a/2)) -> (sin(a - d), sin^2((a - d)/2))
+// for the ring step d, by the angle-difference identities with
+// sd = sin d, hd = sin^2(d/2), cd = cos d = 1 - 2 hd. Four FMAs; the
+// rounding error grows linearly with the number of steps (about 1e-13
+// relative after a few hundred).
+struct RingStep {
+  double cd, sd, sd2, hsd, hd;
+  __device__ __forceinline__ void init(double d) {
+    sin_hav(d, &sd, &hd);
+    cd = 1.0 - 2.0 * hd;
+    sd2 = 2.0 * sd;
+    hsd = 0.5 * sd;
+  }
+  __device__ __forceinline__ void advance(double* sa, double* h) const {
+    const double s1 = fma(*sa, cd, fma(sd2, *h, -sd));
+    *h = fma(*h, cd, fma(*sa, -hsd, hd));
+    *sa = s1;
+  }
+};
+
+// y of a source on ring (zq, sq) at zero azimuth offset from a centre at
+// (zp, sp): sq zp - zq sp = sin(theta_p - theta_q). Both products are
+// rounded before the difference (no FMA contraction), so a source on the
+// centre's own ring gets exactly 0.
+__device__ __forceinline__ double ring_y0(double sq, double zq, double zp, double sp) {
+#pragma clang fp contract(off)
+  return sq * zp - zq * sp;
 }
 
 // ---- FP64 helpers ---------------------------------------------------------

@@ -1,7 +1,7 @@
 // Tile bodies of the pixel-variant mixed-precision kernels, shared by the
-// single-plan launches (k_pairs.hip) and the mixed-batch launch
-// (k_mixed.hip): tile classification, the persistent tile queue, the
-// general per-centre tile and the shared-stencil belt tile.
+// single-plan launches (k_pairs.hip, k_belt.hip) and the mixed-batch launch
+// (k_mixed.hip): the persistent tile queues, the general per-centre walk and
+// the shared-stencil belt tile.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,52 +35,75 @@ __device__ __forceinline__ void write_out(void* out, int64_t n_out, int scale, i
   base[4 * n_out + o] = (T)t.sn;
 }
 
-// ---- pixel variant, mixed precision: tile classification ------------------------
+// ---- pixel variant, mixed precision: tiles ---------------------------------------
 //
-// Outputs are cut into tiles of 256 consecutive list entries. A tile takes the
-// stencil kernel when its 256 centres are consecutive pixels of one ring, the
+// Outputs are cut into tiles of 256 consecutive list entries. A tile is a
+// belt tile when its 256 centres are consecutive pixels of one ring, the
 // source grid is the output grid and every ring of the disc lies in the
 // equatorial belt (4N pixels each): then the geometry of (centre i + t,
-// source j + t) is the same for every t, so each disc offset is evaluated
-// once per tile. All other tiles take the general kernel.
+// source j + t) is the same for every t, and even the same for every tile
+// on that ring, so the disc coefficients of each belt ring are evaluated
+// once per scale into a table (k_belt.hip). All other tiles are general:
+// each centre evaluates its own pairs.
 
-constexpr int kRingCap = 160;   // rings of one disc held by the stencil kernel
-constexpr int kCoefCap = 1024;  // stencil coefficients per LDS pass (24 KB)
-constexpr int kBatch = 8;       // source loads in flight per lane
+constexpr int kRingCap = 160;  // rings of one belt disc
 
-// Persistent blocks drain a tile list. The list is cut into eight equal
-// contiguous shares, one per XCD (the dispatcher deals consecutive
+// Persistent blocks (or waves) drain a tile list. The list is cut into eight
+// equal contiguous shares, one per XCD (the dispatcher deals consecutive
 // workgroups to the XCDs in turn), so each XCD walks one region of the sky
-// and keeps it in its L2; a block whose share is exhausted takes tiles from
-// the other shares. Returns -1 when no tile is left; block-uniform.
-__device__ inline int next_tile(int* cursors, int count, int* s_item) {
-  if (threadIdx.x == 0) {
-    const int xcd = blockIdx.x & 7;
-    int item = -1;
-    for (int d = 0; d < 8 && item < 0; ++d) {
-      const int x = (xcd + d) & 7;
-      const int start = (int)((int64_t)count * x / 8);
-      const int end = (int)((int64_t)count * (x + 1) / 8);
-      if (start >= end || atomicAdd(&cursors[8 + x], 0) != 0) continue;
-      const int k = atomicAdd(&cursors[x], 1);
-      if (start + k < end) item = start + k;
-      else atomicExch(&cursors[8 + x], 1);  // share exhausted
-    }
-    *s_item = item;
+// and keeps it in its L2; a worker whose share is exhausted takes tiles from
+// the other shares. Returns -1 when no tile is left.
+__device__ inline int claim_tile(int* cursors, int count) {
+  const int xcd = blockIdx.x & 7;
+  int item = -1;
+  for (int d = 0; d < 8 && item < 0; ++d) {
+    const int x = (xcd + d) & 7;
+    const int start = (int)((int64_t)count * x / 8);
+    const int end = (int)((int64_t)count * (x + 1) / 8);
+    if (start >= end || atomicAdd(&cursors[8 + x], 0) != 0) continue;
+    const int k = atomicAdd(&cursors[x], 1);
+    if (start + k < end) item = start + k;
+    else atomicExch(&cursors[8 + x], 1);  // share exhausted
   }
+  return item;
+}
+
+// Block-uniform variant (the block shares one tile).
+__device__ inline int next_tile(int* cursors, int count, int* s_item) {
+  if (threadIdx.x == 0) *s_item = claim_tile(cursors, count);
   __syncthreads();
   const int item = *s_item;
   __syncthreads();
   return item;
 }
 
-// One general tile: the 256 centres of list entries [256 tile, 256 tile + 256),
-// each walking its own disc windows (any rings, any grid).
+// Wave-uniform variant (each wave takes its own tile).
+__device__ inline int next_tile_wave(int* cursors, int count) {
+  int item = 0;
+  if ((threadIdx.x & 63) == 0) item = claim_tile(cursors, count);
+  return __builtin_amdgcn_readfirstlane(__shfl(item, 0));
+}
+
+// One member of a general tile: tangent-plane components from the walk
+// state, coefficients, accumulation.
 template <bool TABLE, bool BIG>
-__device__ __forceinline__ void general_tile(const PixelArgs& a, const ScaleArgs& s, int tile, const double* tp,
-                                             Tab tab) {
-const int64_t o = (int64_t)tile * kBlock + threadIdx.x;
-if (o >= a.n_out) return;
+__device__ __forceinline__ void general_member(double sa, double h, double sp, double Y0, double Kz, float4 g,
+                                               const double* tp, Tab tab, Acc64& tot, float& sv) {
+  const double xt = sp * sa;
+  const double yt = fma(Kz, h, Y0);
+  accumulate_pix(ring_coef<TABLE, BIG>(xt, yt, tp, tab), g, tot, sv);
+}
+
+// One centre of a general tile (list entry o), walking its own disc windows
+// (any rings, any grid). Along a ring
+// window the azimuth offset drops by one ring step per member, so its sine
+// and haversine follow from the previous member's by the angle-difference
+// identities (RingStep) instead of a series per member. A window that wraps
+// past the ring's last pixel is walked as two contiguous runs.
+template <bool TABLE, bool BIG>
+__device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleArgs& s, int64_t o, const double* tp,
+                                               Tab tab) {
+  if (o >= a.n_out) return;
 
   int rp, ip;
   pixel_ring(a.nside_out, a.out_pix[o], &rp, &ip);
@@ -100,186 +123,222 @@ if (o >= a.n_out) return;
     int cnt;
     if (!ring_window(zp, sp, ip2, np, Q, s.C_ap, &jlo, &cnt)) continue;
     const int nq = Q.n;
-    const double cphi = kPi / ((double)np * (double)nq);
-    const double Y0 = Q.s * zp - Q.z * sp;
+    const double Y0 = ring_y0(Q.s, Q.z, zp, sp);
     const double Kz = 2.0 * Q.z * sp;
-    const int mstep = 2 * np;
-    const float4* base = a.map + (Q.first - a.pix_first);
-    // dphi_j = pi * m_j / (np nq), m_j = ip2 nq - (2 j + 2 o') np: exact integers
-    int m = (int)(ip2 * nq - (2 * jlo + Q.twice_o) * (int64_t)np);
+    // dphi of the first member = pi m / (np nq) with m an exact integer
+    const int64_t m = ip2 * nq - (2 * jlo + Q.twice_o) * (int64_t)np;
+    double sa, h;
+    sin_hav((double)m * (kPi / ((double)np * (double)nq)), &sa, &h);
+    RingStep step;
+    step.init(2.0 * kPi / (double)nq);
+    // the member at the centre itself (same ring, dphi = 0), if any: the walk
+    // restarts there from exact zeros, so its shear term vanishes exactly
+    const int64_t mstep = 2 * (int64_t)np;
+    const int kc = (Y0 == 0.0 && m >= 0 && m % mstep == 0 && m / mstep < cnt) ? (int)(m / mstep) : -1;
+    const int64_t dring = Q.first - a.pix_first;
     int jw = (int)(((jlo % nq) + nq) % nq);
-    const int mlast = m - (cnt - 1) * mstep;
-    const bool series = (double)max(abs(m), abs(mlast)) * cphi <= 0.5;
-    Acc32 acc;
-    for (int k = 0; k < cnt; ++k) {
-      if ((k & (kChunk - 1)) == kChunk - 1) {
-        tot.add(acc);
-        acc = Acc32();
+    int kdone = 0;
+    while (kdone < cnt) {
+      int run = min(cnt - kdone, nq - jw);
+      if (kc > kdone && kc < kdone + run) run = kc - kdone;
+      if (kdone == kc) {
+        sa = 0.0;
+        h = 0.0;
       }
-      const float4 g = base[jw];
-      double xt, yt;
-      ring_xy(m, cphi, series, sp, Y0, Kz, &xt, &yt);
-      const Coef c = ring_coef<TABLE, BIG>(xt, yt, tp, tab);
-      accumulate(c.qc, c.qs, c.q, (double)g.x, (double)g.y, g.z, g.w, g.z > 0.f ? 1 : 0, tot, acc);
-      m -= mstep;
-      jw = (jw + 1 == nq) ? 0 : jw + 1;
+      run_wn(a.wn, dring + jw, run, tot);
+      const float4* p = a.map + dring + jw;
+      for (int k0 = 0; k0 < run; k0 += kChunk) {
+        const int kn = min(run - k0, kChunk);
+        float sv = 0.f;
+        int k = 0;
+        for (; k + 4 <= kn; k += 4) {
+          float4 g[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) g[u] = p[k0 + k + u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            general_member<TABLE, BIG>(sa, h, sp, Y0, Kz, g[u], tp, tab, tot, sv);
+            step.advance(&sa, &h);
+          }
+        }
+        for (; k < kn; ++k) {
+          general_member<TABLE, BIG>(sa, h, sp, Y0, Kz, p[k0 + k], tp, tab, tot, sv);
+          step.advance(&sa, &h);
+        }
+        tot.sv += sv;
+      }
+      kdone += run;
+      jw += run;
+      if (jw == nq) jw = 0;
     }
-    tot.add(acc);
   }
   write_out<float>(a.out, a.n_out, a.scale, o, a.norm, tot, s);
 }
 
-// ---- pixel variant, mixed precision: stencil kernel --------------------------------
+// ---- pixel variant, mixed precision: belt tile ------------------------------------
 //
-// One tile of 256 consecutive centres of a belt ring. Thread t handles ring
-// lo + t of the disc and finds its window for the first centre (the window
-// of centre t is the same one shifted by t). The disc offsets of a group of
-// rings are evaluated once for the tile (all threads, table read from
-// global memory) into LDS; then every thread accumulates its own sources
-// with the shared coefficients.
+// One belt tile (256 consecutive centres o0 .. o0 + 255 of a belt ring) on one
+// wave: lane l takes the four centres o0 + 4 l + c, c = 0..3. Member k of
+// table ring i is source j0 + c + k of that ring for centre c (j0 = first
+// pixel of the window of the lane's first centre), so the lane slides a
+// window of four source records along the ring and every record it loads
+// serves four pairs. The coefficients (q cos 2psi, q sin 2psi, q^2) of member
+// k are the same for every centre of the ring and come from the table through
+// the scalar cache. W and N_occ of each window come from the prefix sums.
 
-struct RingPar {
-  int64_t first;  // first pixel of the ring
-  int jlo;        // first member for the tile's first centre
-  int cnt;        // members per centre
-  int off;        // offset of the ring's coefficients
-  int m0;         // azimuth offset of the first member, in units of pi / n^2
-  double Y0, Kz;
+typedef const __attribute__((address_space(4))) double cdouble_t;
+typedef const __attribute__((address_space(4))) float cfloat_t;
+typedef const __attribute__((address_space(4))) int cint_t;
+
+// Per-centre sums of a belt lane: E/B in FP64, V in FP32 runs of at most
+// kChunk members, W and N from prefix sums.
+struct BeltAcc {
+  double se[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0};
+  double sv[4] = {0.0, 0.0, 0.0, 0.0}, sw[4] = {0.0, 0.0, 0.0, 0.0}, sn[4] = {0.0, 0.0, 0.0, 0.0};
+  float v[4] = {0.f, 0.f, 0.f, 0.f};
+  __device__ __forceinline__ void flush_v() {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sv[c] += (double)v[c];
+      v[c] = 0.f;
+    }
+  }
 };
 
-template <bool TABLE, bool BIG>
-__device__ __forceinline__ void stencil_tile(const PixelArgs& a, const ScaleArgs& s, int64_t o0, const double* tp,
-                                             Coef* coef, RingPar* rings) {
-  const int tid = threadIdx.x;
-  const Tab tab{s.table, s.table_lo};
+// One source record converted once for the four pairs it serves.
+struct Rec {
+  double a1, a2;
+  float e2;
+  __device__ __forceinline__ void set(float4 g) {
+    a1 = (double)g.x;
+    a2 = (double)g.y;
+    e2 = g.z;
+  }
+};
 
+__device__ __forceinline__ void belt_pair(double qc, double qs, float q2, const Rec& r, double& se, double& sb,
+                                          float& v) {
+  se = fma(qc, r.a1, fma(qs, r.a2, se));
+  sb = fma(qc, r.a2, fma(-qs, r.a1, sb));
+  v = fmaf(q2, r.e2, v);
+}
+
+// Member k for the four centres: records w[0..3] are sources j0 + k + c.
+__device__ __forceinline__ void belt_member(const cdouble_t* qc, const cdouble_t* qs, const cfloat_t* q2, int k,
+                                            const Rec& r0, const Rec& r1, const Rec& r2, const Rec& r3, BeltAcc& A) {
+  const double c = qc[k], sq = qs[k];
+  const float q = q2[k];
+  belt_pair(c, sq, q, r0, A.se[0], A.sb[0], A.v[0]);
+  belt_pair(c, sq, q, r1, A.se[1], A.sb[1], A.v[1]);
+  belt_pair(c, sq, q, r2, A.se[2], A.sb[2], A.v[2]);
+  belt_pair(c, sq, q, r3, A.se[3], A.sb[3], A.v[3]);
+}
+
+// Sources j0 .. j0 + cnt + 2 of a ring, read through `at(j)` (a pointer or a
+// wrapped index); four members per step, the records of the next step in
+// flight while the current one is summed, V runs flushed every kChunk.
+template <typename At>
+__device__ __forceinline__ void belt_ring(const cdouble_t* qc, const cdouble_t* qs, const cfloat_t* q2, int cnt,
+                                          At at, BeltAcc& A) {
+  Rec w0, w1, w2;
+  w0.set(at(0));
+  w1.set(at(1));
+  w2.set(at(2));
+  int k = 0;
+  if (cnt >= 4) {
+    float4 n3 = at(3), n4 = at(4), n5 = at(5), n6 = at(6);
+    for (;;) {
+      Rec x3, x4, x5, x6;
+      x3.set(n3);
+      x4.set(n4);
+      x5.set(n5);
+      x6.set(n6);
+      const bool more = k + 8 <= cnt;  // records k + 7 .. k + 10 exist when the next step does
+      if (more) {
+        n3 = at(k + 7);
+        n4 = at(k + 8);
+        n5 = at(k + 9);
+        n6 = at(k + 10);
+      }
+      belt_member(qc, qs, q2, k, w0, w1, w2, x3, A);
+      belt_member(qc, qs, q2, k + 1, w1, w2, x3, x4, A);
+      belt_member(qc, qs, q2, k + 2, w2, x3, x4, x5, A);
+      belt_member(qc, qs, q2, k + 3, x3, x4, x5, x6, A);
+      w0 = x4;
+      w1 = x5;
+      w2 = x6;
+      if ((k & (kChunk - 1)) == kChunk - 4) A.flush_v();
+      k += 4;
+      if (!more) break;
+    }
+  }
+  for (; k < cnt; ++k) {
+    Rec x3;
+    x3.set(at(k + 3));
+    belt_member(qc, qs, q2, k, w0, w1, w2, x3, A);
+    w0 = w1;
+    w1 = w2;
+    w2 = x3;
+  }
+  A.flush_v();
+}
+
+__device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s, const BeltTab& T, int64_t o0) {
+  const int lane = threadIdx.x & 63;
+  const int N = a.nside_in, n = 4 * N;
   int rp, ip0;
-  pixel_ring(a.nside_out, a.out_pix[o0], &rp, &ip0);
-  const Ring R = ring_info(a.nside_out, rp);
-  const double zp = R.z, sp = R.s;
-  const int n = R.n;  // every ring of the disc has n pixels
-  const int64_t ip2_0 = 2 * (int64_t)ip0 + R.twice_o;
-  int lo, hi;
-  ring_span(a.nside_in, atan2(sp, zp), s.theta_ap, &lo, &hi);
-  lo = max(lo, a.ring_lo);
-  hi = min(hi, a.ring_hi);
-  const int nr = max(0, hi - lo + 1);
-  const double cphi = kPi / ((double)n * (double)n);
-  const int mstep = 2 * n;
-
-  if (tid < nr) {
-    const Ring Q = ring_info(a.nside_in, lo + tid);
-    int64_t jlo;
-    int cnt;
-    RingPar P;
-    P.first = Q.first;
-    if (ring_window(zp, sp, ip2_0, n, Q, s.C_ap, &jlo, &cnt)) {
-      P.jlo = (int)jlo;
-      P.cnt = cnt;
-      P.m0 = (int)(ip2_0 * n - (2 * jlo + Q.twice_o) * (int64_t)n);
+  pixel_ring(N, a.out_pix[o0], &rp, &ip0);
+  const cint_t* hd = (const cint_t*)T.head + 2 * (rp - N);  // (first table ring, ring count)
+  const int first = hd[0], nr = hd[1];
+  BeltAcc A;
+  for (int i = 0; i < nr; ++i) {
+    const cint_t* ip = (const cint_t*)T.info + 4 * (first + i);  // (ring, first member offset, count, coefficient offset)
+    const int4 inf = make_int4(ip[0], ip[1], ip[2], ip[3]);
+    const int cnt = inf.z;
+    if (cnt == 0) continue;
+    const Ring Q = ring_info(N, inf.x);
+    const int64_t dring = Q.first - a.pix_first;
+    int j0 = (ip0 + 4 * lane + inf.y) % n;
+    j0 = j0 < 0 ? j0 + n : j0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {  // W and N_occ of each centre's window
+      const int jc = j0 + c < n ? j0 + c : j0 + c - n;
+      const int run = min(cnt, n - jc);
+      const double2 lo = a.wn[dring + jc], hi = a.wn[dring + jc + run];
+      A.sw[c] += hi.x - lo.x;
+      A.sn[c] += hi.y - lo.y;
+      if (run < cnt) {
+        const double2 lo2 = a.wn[dring], hi2 = a.wn[dring + cnt - run];
+        A.sw[c] += hi2.x - lo2.x;
+        A.sn[c] += hi2.y - lo2.y;
+      }
+    }
+    const cdouble_t* qc = (const cdouble_t*)T.qc + inf.w;
+    const cdouble_t* qs = (const cdouble_t*)T.qs + inf.w;
+    const cfloat_t* q2 = (const cfloat_t*)T.q2 + inf.w;
+    const float4* row = a.map + dring;
+    if (j0 + cnt + 3 <= n) {
+      const float4* p = row + j0;
+      belt_ring(qc, qs, q2, cnt, [p](int j) { return p[j]; }, A);
     } else {
-      P.jlo = 0;
-      P.cnt = 0;
-      P.m0 = 0;
-    }
-    P.Y0 = Q.s * zp - Q.z * sp;
-    P.Kz = 2.0 * Q.z * sp;
-    P.off = 0;
-    rings[tid] = P;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int r = 0; r < nr; ++r) {
-      rings[r].off = acc;
-      acc += rings[r].cnt;
+      belt_ring(qc, qs, q2, cnt,
+                [row, j0, n](int j) {
+                  const int jj = j0 + j;
+                  return row[jj >= n ? jj - n : jj];
+                },
+                A);
     }
   }
-  __syncthreads();
-
-  Acc64 tot;
-  int g0 = 0;
-  while (g0 < nr) {
-    // group of rings whose coefficients fit in LDS (a single ring longer
-    // than kCoefCap is split into several passes)
-    const int base_off = rings[g0].off;
-    int g1 = g0 + 1;
-    while (g1 < nr && rings[g1].off + rings[g1].cnt - base_off <= kCoefCap) ++g1;
-    const RingPar& first_ring = rings[g0];
-    const int kstart_lim = (g1 == g0 + 1) ? first_ring.cnt : 0;
-    for (int kseg = 0; kseg == 0 || kseg < kstart_lim; kseg += kCoefCap) {
-      const int lim_end = (g1 == g0 + 1) ? min(first_ring.cnt, kseg + kCoefCap) : 0;
-      const int total = (g1 == g0 + 1) ? lim_end - kseg : rings[g1 - 1].off + rings[g1 - 1].cnt - base_off;
-      // coefficients of the group: flat index f -> (ring, k)
-      for (int f = tid; f < total; f += kBlock) {
-        int r, k;
-        if (g1 == g0 + 1) {
-          r = g0;
-          k = kseg + f;
-        } else {
-          int lo_r = g0, hi_r = g1 - 1;
-          while (lo_r < hi_r) {  // last ring with off <= base_off + f
-            const int mid = (lo_r + hi_r + 1) >> 1;
-            if (rings[mid].off - base_off <= f) lo_r = mid;
-            else hi_r = mid - 1;
-          }
-          r = lo_r;
-          k = base_off + f - rings[r].off;
-        }
-        const RingPar& P = rings[r];
-        const int m = P.m0 - k * mstep;
-        const bool series = (double)abs(m) * cphi <= 0.5;
-        double xt, yt;
-        ring_xy(m, cphi, series, sp, P.Y0, P.Kz, &xt, &yt);
-        coef[f] = ring_coef<TABLE, BIG>(xt, yt, tp, tab);
-      }
-      __syncthreads();
-      for (int r = g0; r < g1; ++r) {
-        const RingPar& P = rings[r];
-        const int k0 = (g1 == g0 + 1) ? kseg : 0;
-        const int k1 = (g1 == g0 + 1) ? lim_end : P.cnt;
-        const int cbase = (g1 == g0 + 1) ? -kseg : P.off - base_off;
-        const float4* src = a.map + (P.first - a.pix_first);
-        int jw = (P.jlo + tid + k0) % n;
-        jw = jw < 0 ? jw + n : jw;
-        Acc32 acc;
-        int k = k0;
-        for (; k + kBatch <= k1; k += kBatch) {
-          float4 g[kBatch];
 #pragma unroll
-          for (int u = 0; u < kBatch; ++u) {
-            int j = jw + u;
-            j = j >= n ? j - n : j;
-            g[u] = src[j];
-          }
-#pragma unroll
-          for (int u = 0; u < kBatch; ++u) {
-            const Coef c = coef[cbase + k + u];
-            accumulate(c.qc, c.qs, c.q, (double)g[u].x, (double)g[u].y, g[u].z, g[u].w, g[u].z > 0.f ? 1 : 0, tot,
-                       acc);
-          }
-          jw += kBatch;
-          jw = jw >= n ? jw - n : jw;
-          if (((k - k0) & (kChunk - 1)) == kChunk - kBatch) {
-            tot.add(acc);
-            acc = Acc32();
-          }
-        }
-        for (; k < k1; ++k) {
-          const Coef c = coef[cbase + k];
-          const float4 g = src[jw];
-          accumulate(c.qc, c.qs, c.q, (double)g.x, (double)g.y, g.z, g.w, g.z > 0.f ? 1 : 0, tot, acc);
-          jw = (jw + 1 == n) ? 0 : jw + 1;
-        }
-        tot.add(acc);
-      }
-      __syncthreads();
-      if (g1 != g0 + 1) break;
-    }
-    g0 = g1;
+  for (int c = 0; c < 4; ++c) {
+    Acc64 t;
+    t.se = A.se[c];
+    t.sb = A.sb[c];
+    t.sv = A.sv[c];
+    t.sw = A.sw[c];
+    t.sn = A.sn[c];
+    write_out<float>(a.out, a.n_out, a.scale, o0 + 4 * lane + c, a.norm, t, s);
   }
-  write_out<float>(a.out, a.n_out, a.scale, o0 + tid, a.norm, tot, s);
-  __syncthreads();  // rings[] and coef[] are rewritten by the next tile
 }
 
 }  // namespace smart

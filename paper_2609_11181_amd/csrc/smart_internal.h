@@ -28,7 +28,7 @@ struct FilterDef {
   double params[5] = {0, 0, 0, 0, 0};
   std::vector<double> samples;  // SMART_FILTER_TABLE
   float4* d_table = nullptr;    // kFilterIntervals cubic pieces (c0, c1, c2, c3) in FP32
-  float* d_table_lo = nullptr;  // FP32 remainder of c0 (c0 = hi + lo to about 1e-15)
+  double* d_table_c0 = nullptr;  // c0 of every piece in FP64
   std::vector<float> h_table;
 };
 
@@ -56,12 +56,19 @@ struct smart_data_s {
   // dense pixel sums over whole rings [ring_lo, ring_hi]
   int ring_lo = 0, ring_hi = -1;
   int64_t pix_first = 0, n_dense = 0;
-  float4* sums = nullptr;  // (G1, G2, W, E2)
+  float4* sums = nullptr;  // (G1, G2, E2, W): the pair kernels read the first three
+  // prefix sums over the dense range: wn[i] = (sum of W, number of pixels
+  // with W > 0) over dense pixels [0, i); n_dense + 1 entries
+  double2* wn = nullptr;
   // sources of the pixel variant: occupied pixels in pixel order
   int64_t n_src = 0;
   int* cidx = nullptr;         // dense pixel -> source index, -1 when empty
   int64_t* src_pix = nullptr;  // source index -> RING pixel
 };
+
+namespace smart {
+struct PixelSched;
+}
 
 struct smart_plan_s {
   smart_ctx ctx = nullptr;
@@ -77,7 +84,9 @@ struct smart_plan_s {
   const void* last_out = nullptr;
   int last_norm = 0;
   double* d_pairs = nullptr;
-  int* d_work = nullptr;  // tile lists of the pixel kernels
+  int* d_work = nullptr;  // tile lists of the pixel kernels (generic path)
+  // pixel variant, FP32: tile schedule and belt tables of every scale
+  std::vector<smart::PixelSched*> sched;
   // scratch for the noise batch (rotated map), grown on demand
   float4* rot_map = nullptr;
   int64_t rot_len = 0;
@@ -98,7 +107,7 @@ struct ScaleArgs {
   int filter_kind;   // SMART_FILTER_POLY, or table otherwise
   int big;           // 1 when theta_ap > 2 degrees (longer asin series)
   const float4* table;
-  const float* table_lo;
+  const double* table_c0;
   double tpoly[7];   // asin(y)/y series in y^2, divided by theta_ap (x from sin theta)
   double cpoly[7];   // 2 asin(c/2)/c series in c^2, divided by theta_ap (x from the chord c)
   double tanh_p[5];  // FP64 path: tanh filter parameters
@@ -110,7 +119,8 @@ struct PixelArgs {
   const int64_t* out_pix;
   int64_t n_out;
   int nside_out;
-  const float4* map;  // dense (G1, G2, W, E2)
+  const float4* map;  // dense (G1, G2, E2, W)
+  const double2* wn;  // prefix sums of (W, occupied) over the dense range
   int nside_in;
   int ring_lo, ring_hi;
   int64_t pix_first;
@@ -134,10 +144,49 @@ struct GalaxyArgs {
   int scale;
 };
 
+// Shared-stencil tables of one scale (built by k_belt.hip): for every belt
+// ring that hosts belt tiles, its disc rings and the coefficients of the
+// members of each, for a centre at azimuth index 0 (the same for every
+// centre of the ring, shifted).
+struct BeltTab {
+  const int2* head;  // [rp - nside] = (first table ring, ring count)
+  const int4* info;  // per table ring: (ring, first member offset, member count, coefficient offset)
+  const double* qc;  // q cos 2psi
+  const double* qs;  // q sin 2psi
+  const float* q2;   // q^2
+};
+
+// Tile schedule of one scale of a pixel-variant FP32 plan; owns its device
+// memory.
+struct PixelSched {
+  int n_tiles = 0;
+  int* list = nullptr;      // belt tiles in order, then the general tiles
+  int* cursors = nullptr;   // queue cursors: [0, 16) belt kernel, [16, 32) general kernel
+  int counts[2] = {0, 0};   // belt and general tile counts
+  int2* head = nullptr;
+  int4* info = nullptr;
+  double* qc = nullptr;
+  double* qs = nullptr;
+  float* q2 = nullptr;
+  BeltTab tab() const { return BeltTab{head, info, qc, qs, q2}; }
+  int* lists(int which) const { return list + (which ? counts[0] : 0); }
+  ~PixelSched();
+};
+
 // launchers (k_pairs.hip)
-// d_work: device scratch of pixel_work_ints(n_out) ints (tile lists)
+// Generic path (no belt tables): every tile takes the general kernel.
+// d_work: device scratch of pixel_work_ints(n_out) ints (queue cursors).
 hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, hipStream_t st, int* d_work);
 size_t pixel_work_ints(int64_t n_out);
+// Flags the belt tiles among the tiles of 256 list entries (flags[t] = 1)
+// and sets used[rp - nside] = 1 for the ring of every belt tile.
+void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* flags, int* used, hipStream_t st);
+// Scheduled path: belt tiles through the tables, general tiles as above.
+hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st);
+// belt kernels (k_belt.hip)
+int build_pixel_sched(smart_plan p, int scale, hipStream_t st, PixelSched* sc);
+hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int* list, int count,
+                       int* cursors, hipStream_t st);
 hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, hipStream_t st);
 hipError_t launch_sum_n(const void* out, int precision, int64_t n_out, int n_scales, double* d_acc,
                         hipStream_t st);
@@ -145,6 +194,10 @@ hipError_t launch_sum_n(const void* out, int precision, int64_t n_out, int n_sca
 // binner (k_binner.hip)
 int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, const float* g1, const float* g2,
                  const float* w, int nside_bin, int want_sums, hipStream_t st, smart_data d);
+// Grows the context's scratch for library sorts and scans to `bytes`.
+int ensure_temp(smart_ctx ctx, size_t bytes);
+// Builds d->wn from d->sums (smart_data_s::wn).
+int build_wn_prefix(smart_ctx ctx, smart_data d, hipStream_t st);
 int pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const float* W, const float* G1,
               const float* G2, const float* E2, hipStream_t st, smart_data d);
 hipError_t launch_check_pixels(const int64_t* pix, int64_t n, int64_t npix, int* d_flag, hipStream_t st);
