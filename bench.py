@@ -37,6 +37,10 @@ ARCMIN = math.pi / 10800.0
 OPS_PER_PAIR = 31
 # plain-ALU peak: 256 CUs x 64 lanes x 2.4 GHz, one lane op per clock
 ALU_PEAK = 256 * 64 * 2.4e9
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0)
+# counter runs, profiles/pixel_kernels_nside4096_15000deg2_3scales.md; valid for the kernel versions
+# profiled there and the default workload only
+TRAFFIC_BYTES = {"k_pixel_f32 (20 arcmin)": 2.17842e10}
 
 
 def parse():
@@ -265,10 +269,11 @@ def main():
     stream = torch.cuda.current_stream(dev)
     torch.cuda.synchronize()
 
-    def step(keep, ev=None):
+    def step(keep, ev=None, kms=None):
         data = ctx.pixel_map(args.nside, pix, *cols)
         plans = [ctx.plan(data, L.VAR_PIXEL, args.nside, pix, [th], [fid]) for th in scales]
         for k, p in enumerate(plans):
+            p.set_timing(True)
             if ev is not None:
                 ev[k][0].record(stream)
             p.run(L.NORM_SUMMED_PIXCOUNT, outs[k])
@@ -290,14 +295,27 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
-    pairs_scale = [p.last_pairs() for p in keep[-1][1]]
+    # per-kernel durations (HIP events recorded by the library on this stream around each pair kernel)
+    split_ms = np.mean([[plans[k].kernel_ms(0) for k in range(len(scales))] for _, plans in keep], axis=0)
+    last_plans = keep[-1][1]
+    pairs_scale = [p.last_pairs() for p in last_plans]
     pairs = float(sum(pairs_scale))
+    # pairs of the belt tiles (N channel summed over their centres); the rest are general-tile pairs
+    pairs_belt = []
+    for k, p in enumerate(last_plans):
+        nb, ng, tiles = p.tiles(0)
+        idx = (tiles[:nb].long()[:, None] * 256 + torch.arange(256, device=dev)).reshape(-1)
+        pairs_belt.append(float(outs[k][0, 4].double()[idx].sum()) if nb else 0.0)
     kern_ms = [float(np.mean([events[s][k][0].elapsed_time(events[s][k][1]) for s in range(args.steps)]))
                for k in range(len(scales))]
     value = pairs / (ms_step / 1e3)
-    dom = int(np.argmax(kern_ms))
-    achieved = pairs_scale[dom] * OPS_PER_PAIR / (kern_ms[dom] / 1e3)
-    log(f"step {ms_step:.2f} ms; kernels {['%.2f' % k for k in kern_ms]} ms; pairs {pairs:.4e}")
+    # dominant kernel: the longest of the belt/general pair kernels over the scales
+    cand = [(split_ms[k][j], k, j) for k in range(len(scales)) for j in range(2)]
+    dom_ms, dom, dom_kind = max(cand)
+    dom_pairs = pairs_belt[dom] if dom_kind == 0 else pairs_scale[dom] - pairs_belt[dom]
+    achieved = dom_pairs * OPS_PER_PAIR / (dom_ms / 1e3)
+    log(f"step {ms_step:.2f} ms; runs {['%.2f' % k for k in kern_ms]} ms; "
+        f"belt/general {[['%.2f' % x for x in r] for r in split_ms]} ms; pairs {pairs:.4e}")
     res = {
         "metric": "pair-evals/s at NSIDE 4096 (pixel-based aperture mass, 3 scales)",
         "value": value,
@@ -316,18 +334,26 @@ def main():
                         "tanh filter, summed normalisation",
             "n_pixels": int(n_out),
             "pairs_per_step": pairs,
-            "kernel_ms": kern_ms,
+            "run_ms": kern_ms,
+            "belt_general_kernel_ms": [[float(x) for x in r] for r in split_ms],
+            "belt_pairs": pairs_belt,
+            "general_pairs": [a - b for a, b in zip(pairs_scale, pairs_belt)],
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_pixel_f32 (20 arcmin)",
+            "kernel": ("k_pixel_belt" if dom_kind == 0 else "k_pixel_f32") + f" ({scales[dom] / ARCMIN:g} arcmin)",
             "achieved": achieved / 1e12,
             "peak": ALU_PEAK / 1e12,
             "unit": "Tlane-op/s",
             "frac": achieved / ALU_PEAK,
             "traffic": None,
+            "ops_per_pair": OPS_PER_PAIR,
+            "kernel_ms": dom_ms,
+            "pairs": dom_pairs,
         },
     }
+    default_workload = args.nside == 4096 and args.area == 15000.0
+    res["roofline"]["traffic"] = TRAFFIC_BYTES.get(res["roofline"]["kernel"]) if default_workload else None
     # accuracy on the oracle sample + CPU baseline
     if not args.no_cpu:
         out_pix, refs, cpairs, cdt = cpu_baseline(pm, R, scales, args.cpu_outputs)

@@ -193,7 +193,14 @@ void smart_data_free(smart_data data);
  *   d_out_pix : n_out int64 RING pixels (copied; any order, duplicates ok)
  *   theta_ap  : 0 < theta_ap <= 0.25 rad (about 14.3 degrees)
  * The plan references `data`, which must outlive it. Synchronises `stream`
- * once (validation of the pixel list). */
+ * (validation of the pixel list). Pixel-variant FP32 plans are also
+ * scheduled here (Sect. 3.2: discs as index intervals on rings): the outputs
+ * are cut into tiles of 256 list entries; a tile of 256 consecutive pixels
+ * of an equatorial-belt ring whose discs stay in the belt is a belt tile,
+ * whose pair coefficients are shared by every centre of its ring and built
+ * once per scale into a per-ring table; all other tiles are general. This
+ * costs one more synchronisation per scale and device memory of about
+ * (number of belt rings) x (pixels per disc) x 20 bytes per scale. */
 int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out, int64_t n_out,
                       const int64_t* d_out_pix, int n_scales, const double* h_theta_ap, const int* h_filter_ids,
                       int precision, void* stream, smart_plan* out);
@@ -209,6 +216,22 @@ int smart_run(smart_plan plan, int norm, void* d_out, void* stream);
 int smart_last_pairs(smart_plan plan, void* stream, double* pairs);
 
 void smart_plan_free(smart_plan plan);
+
+/* Tile schedule of scale `scale` of a pixel-variant FP32 plan: belt and
+ * general tile counts (tile t holds list entries [256 t, 256 t + 256)).
+ * With d_tiles non-NULL, copies the n_belt + n_general tile indices (belt
+ * tiles first) as int32 to device memory d_tiles on `stream`. Other plans
+ * report n_belt = 0 and every tile as general. */
+int smart_plan_tiles(smart_plan plan, int scale, int* n_belt, int* n_general, int* d_tiles, void* stream);
+
+/* Kernel timing (tracing). With enable != 0, later smart_run calls on a
+ * pixel-variant FP32 plan record HIP events on the run's stream around the
+ * belt-tile and general-tile pair kernels of every scale;
+ * smart_plan_kernel_ms waits for those events and returns the durations of
+ * the last run in milliseconds (0 for a kernel that did not run). Returns
+ * SMART_EINVAL when timing is off or no timed run exists. */
+int smart_plan_set_timing(smart_plan plan, int enable);
+int smart_plan_kernel_ms(smart_plan plan, int scale, double* belt_ms, double* general_ms);
 
 /* ------------------------------------------------------------------------ */
 /* Shape-noise realisations (pixel variant)                                  */

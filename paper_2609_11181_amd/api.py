@@ -179,6 +179,24 @@ class Plan:
         L.check(self.ctx.lib.smart_last_pairs(self.h, _stream(self.ctx.device), C.byref(v)))
         return v.value
 
+    def tiles(self, scale: int = 0):
+        """(n_belt, n_general, device int32 tensor of tile indices, belt tiles first)."""
+        nb, ng = C.c_int(), C.c_int()
+        L.check(self.ctx.lib.smart_plan_tiles(self.h, scale, C.byref(nb), C.byref(ng), None, None))
+        t = torch.empty(max(nb.value + ng.value, 1), dtype=torch.int32, device=self.ctx.device)
+        L.check(self.ctx.lib.smart_plan_tiles(self.h, scale, C.byref(nb), C.byref(ng), _ptr(t),
+                                              _stream(self.ctx.device)))
+        return nb.value, ng.value, t[: nb.value + ng.value]
+
+    def set_timing(self, enable: bool = True):
+        L.check(self.ctx.lib.smart_plan_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_ms(self, scale: int = 0):
+        """(belt kernel ms, general kernel ms) of the last timed run."""
+        b, g = C.c_double(), C.c_double()
+        L.check(self.ctx.lib.smart_plan_kernel_ms(self.h, scale, C.byref(b), C.byref(g)))
+        return b.value, g.value
+
     def noise_batch(self, u, n_real: int, norm: int, precision: int, out=None):
         if out is None:
             out = torch.empty(self.n_scales, n_real, 2, self.n_out, dtype=torch.float32, device=self.ctx.device)

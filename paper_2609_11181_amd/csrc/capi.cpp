@@ -229,6 +229,7 @@ void smart_plan_free(smart_plan p) {
   hipFree(p->d_work);
   hipFree(p->rot_map);
   for (smart::PixelSched* sc : p->sched) delete sc;
+  for (hipEvent_t e : p->events) hipEventDestroy(e);
   delete p;
 }
 
@@ -332,7 +333,8 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.out = d_out;
       a.norm = norm;
       a.scale = k;
-      e = p->precision == SMART_PREC_FP32_GEO64 ? launch_pixel_sched(a, s, *p->sched[k], st)
+      hipEvent_t* ev = p->timing ? &p->events[4 * k] : nullptr;
+      e = p->precision == SMART_PREC_FP32_GEO64 ? launch_pixel_sched(a, s, *p->sched[k], st, ev)
                                                 : launch_pixel(a, s, p->precision, st, p->d_work);
     } else {
       GalaxyArgs a{};
@@ -354,6 +356,61 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
   }
   p->last_out = d_out;
   p->last_norm = norm;
+  p->timed_run = p->timing && p->variant == SMART_VAR_PIXEL && p->precision == SMART_PREC_FP32_GEO64;
+  return SMART_OK;
+}
+
+int smart_plan_tiles(smart_plan p, int scale, int* n_belt, int* n_general, int* d_tiles, void* stream) {
+  if (!p || !n_belt || !n_general) return fail(SMART_EINVAL, "NULL argument");
+  if (scale < 0 || scale >= (int)p->theta_ap.size()) return fail(SMART_EINVAL, "scale out of range");
+  int rc;
+  if ((rc = set_device(p->ctx))) return rc;
+  const int nt = (int)((p->n_out + 255) / 256);
+  if (p->sched.empty() || !p->sched[scale]->list) {
+    *n_belt = 0;
+    *n_general = nt;
+    if (d_tiles && nt > 0) {
+      std::vector<int> ids(nt);
+      for (int t = 0; t < nt; ++t) ids[t] = t;
+      CHECK_HIP(hipMemcpyAsync(d_tiles, ids.data(), sizeof(int) * nt, hipMemcpyHostToDevice, (hipStream_t)stream));
+      CHECK_HIP(hipStreamSynchronize((hipStream_t)stream));
+    }
+    return SMART_OK;
+  }
+  const smart::PixelSched& sc = *p->sched[scale];
+  *n_belt = sc.counts[0];
+  *n_general = sc.counts[1];
+  if (d_tiles && nt > 0)
+    CHECK_HIP(hipMemcpyAsync(d_tiles, sc.list, sizeof(int) * nt, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SMART_OK;
+}
+
+int smart_plan_set_timing(smart_plan p, int enable) {
+  if (!p) return fail(SMART_EINVAL, "NULL plan");
+  int rc;
+  if ((rc = set_device(p->ctx))) return rc;
+  if (enable && p->events.empty()) {
+    p->events.resize(4 * p->theta_ap.size());
+    for (hipEvent_t& e : p->events) CHECK_HIP(hipEventCreate(&e));
+  }
+  p->timing = enable != 0;
+  p->timed_run = false;
+  return SMART_OK;
+}
+
+int smart_plan_kernel_ms(smart_plan p, int scale, double* belt_ms, double* general_ms) {
+  if (!p || !belt_ms || !general_ms) return fail(SMART_EINVAL, "NULL argument");
+  if (scale < 0 || scale >= (int)p->theta_ap.size()) return fail(SMART_EINVAL, "scale out of range");
+  if (!p->timed_run) return fail(SMART_EINVAL, "no timed run on this plan (smart_plan_set_timing)");
+  int rc;
+  if ((rc = set_device(p->ctx))) return rc;
+  hipEvent_t* ev = &p->events[4 * scale];
+  float b = 0.f, g = 0.f;
+  CHECK_HIP(hipEventSynchronize(ev[3]));
+  CHECK_HIP(hipEventElapsedTime(&b, ev[0], ev[1]));
+  CHECK_HIP(hipEventElapsedTime(&g, ev[2], ev[3]));
+  *belt_ms = b;
+  *general_ms = g;
   return SMART_OK;
 }
 
@@ -415,7 +472,7 @@ int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int 
       a.out = stage;
       a.norm = norm;
       a.scale = 0;
-      e = launch_pixel(a, s, SMART_PREC_FP32_GEO64, st, p->d_work);
+      e = launch_pixel_sched(a, s, *p->sched[k], st);
       if (e != hipSuccess) return fail(SMART_EDEVICE, "pair kernel failed");
       float* dst = d_out + (((int64_t)k * n_real + r) * 2) * p->n_out;
       e = hipMemcpyAsync(dst, stage, sizeof(float) * 2 * p->n_out, hipMemcpyDeviceToDevice, st);

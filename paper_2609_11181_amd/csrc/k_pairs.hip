@@ -380,12 +380,18 @@ hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, h
   return launch_general(a, s, st, nullptr, (int)blocks_for(a.n_out), d_work);
 }
 
-hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st) {
-  if (a.n_out == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, sc.cursors, 32);
+hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st,
+                              hipEvent_t* ev) {
   hipError_t e = hipSuccess;
-  if (sc.counts[0] > 0) e = launch_belt(a, s, sc.tab(), sc.lists(0), sc.counts[0], sc.cursors, st);
-  if (e == hipSuccess && sc.counts[1] > 0) e = launch_general(a, s, st, sc.lists(1), sc.counts[1], sc.cursors + 16);
+  if (a.n_out > 0) hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, sc.cursors, 32);
+  if (ev) e = hipEventRecord(ev[0], st);
+  if (e == hipSuccess && a.n_out > 0 && sc.counts[0] > 0)
+    e = launch_belt(a, s, sc.tab(), sc.lists(0), sc.counts[0], sc.cursors, st);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
+  if (e == hipSuccess && a.n_out > 0 && sc.counts[1] > 0)
+    e = launch_general(a, s, st, sc.lists(1), sc.counts[1], sc.cursors + 16);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
   return e;
 }
 

@@ -87,6 +87,9 @@ struct smart_plan_s {
   int* d_work = nullptr;  // tile lists of the pixel kernels (generic path)
   // pixel variant, FP32: tile schedule and belt tables of every scale
   std::vector<smart::PixelSched*> sched;
+  // kernel timing: 4 events per scale (belt start/stop, general start/stop)
+  bool timing = false, timed_run = false;
+  std::vector<hipEvent_t> events;
   // scratch for the noise batch (rotated map), grown on demand
   float4* rot_map = nullptr;
   int64_t rot_len = 0;
@@ -182,7 +185,9 @@ size_t pixel_work_ints(int64_t n_out);
 // and sets used[rp - nside] = 1 for the ring of every belt tile.
 void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* flags, int* used, hipStream_t st);
 // Scheduled path: belt tiles through the tables, general tiles as above.
-hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st);
+// ev: NULL, or 4 events recorded around the belt and the general kernel.
+hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st,
+                              hipEvent_t* ev = nullptr);
 // belt kernels (k_belt.hip)
 int build_pixel_sched(smart_plan p, int scale, hipStream_t st, PixelSched* sc);
 hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int* list, int count,

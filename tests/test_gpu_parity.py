@@ -314,3 +314,38 @@ def test_fp64_vs_mp(ctx):
     for ch, col in [(0, 0), (1, 1), (2, 3), (3, 2), (4, 4)]:
         rms = math.sqrt(np.mean(ref[:, col] ** 2))
         assert np.max(np.abs(out[ch] - ref[:, col])) <= 1e-13 * rms, ch
+
+
+def test_plan_schedule_and_kernel_timing(ctx):
+    """Tile schedule of a pixel plan (belt tiles first, every tile once) and
+    the per-kernel timing of a run; belt tiles hold 256 consecutive pixels
+    of one belt ring."""
+    import torch
+
+    L = _L()
+    nside = 128
+    m = _pixmap(nside, 13)
+    th = 1.5 * DEG
+    plan = ctx.plan(ctx.pixel_map(nside, m["pix"], m["W"], m["G1"], m["G2"], m["E2"]), L.VAR_PIXEL, nside,
+                    m["pix"], [th], [ctx.filter(F.TANH)])
+    with pytest.raises(L.SmartError):
+        plan.kernel_ms(0)
+    nb, ng, tiles = plan.tiles(0)
+    nt = (m["pix"].size + 255) // 256
+    assert nb > 0 and nb + ng == nt
+    t = tiles.cpu().numpy()
+    assert np.array_equal(np.sort(t), np.arange(nt))
+    rt = hp.ring_table(nside)
+    for tile in t[:nb]:
+        p = m["pix"][256 * tile: 256 * tile + 256]
+        assert np.all(np.diff(p) == 1)
+        ring = np.searchsorted(rt["first"], p[0], side="right") - 1
+        assert nside <= ring + 1 <= 3 * nside and p[-1] < rt["first"][ring] + rt["n"][ring]
+    plan.set_timing(True)
+    out = plan.run(L.NORM_SUMMED_PIXCOUNT)
+    torch.cuda.synchronize()
+    b, g = plan.kernel_ms(0)
+    assert b > 0.0 and g > 0.0
+    ref = A.aperture_mass_pixel(m, m["pix"][::97], th, F.TANH)
+    errs = _compare(out.cpu().numpy()[0][:, ::97], ref, A.NORM_SUMMED_PIXCOUNT, 1e-6)
+    print(nb, ng, b, g, errs)
