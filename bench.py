@@ -56,6 +56,10 @@ def parse():
     p.add_argument("--only-batched", action="store_true", help="run only the batched noise-realisation leg")
     p.add_argument("--n-real", type=int, default=256, help="realisations of the batched leg")
     p.add_argument("--plain-real", type=int, default=8, help="realisations timed on the plain FP32 path")
+    p.add_argument("--no-tune", action="store_true", help="keep the default launch choices (no autotuning)")
+    p.add_argument("--no-mixed", action="store_true", help="skip the uneven mixed-batch leg")
+    p.add_argument("--only-mixed", action="store_true", help="run only the uneven mixed-batch leg")
+    p.add_argument("--mixed-area-scale", type=float, default=1.0, help="scale of the mixed-batch cap areas")
     p.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                    help="only run a plain device copy of GIB GiB three times (HBM counter calibration)")
     return p.parse_args()
@@ -229,6 +233,105 @@ def batched_accuracy(data, src, u, out, outp, scales, R, n_check=512, seed=12):
             "accuracy_sample": f"{pick.size} centres x 3 scales x realisations (0, 1, {R - 1}), E and B"}
 
 
+def mixed_leg(ctx, args):
+    """Uneven mixed batch: the 64 instances of synth.config5_instances (NSIDE,
+    cap area, aperture and filter drawn per instance; pixel-level maps with
+    config-2 statistics, 13.9 gal/arcmin^2 and 0.5 halos/deg^2), all plans in
+    one smart_mixed_batch launch, against the same plans run one by one."""
+    import torch
+
+    from paper_2609_11181_amd import lib as L
+    from synth import PixelMapSpec, config5_instances, pixel_level_map
+    from synth.generators import cap_radius_from_area
+
+    dev = torch.device("cuda", 0)
+    inst = config5_instances()
+    t = time.perf_counter()
+    maps, plans, outs = [], [], []
+    for k, d in enumerate(inst):
+        R = cap_radius_from_area(d["area_deg2"] * args.mixed_area_scale)
+        m = pixel_level_map(PixelMapSpec(nside=d["nside"], cap_radius=R, density_arcmin2=13.9, halos_per_deg2=0.5,
+                                         seed=d["seed"]))
+        pix = torch.from_numpy(m["pix"]).to(dev)
+        data = ctx.pixel_map(d["nside"], pix, *[torch.from_numpy(m[c]).to(dev) for c in ("W", "G1", "G2", "E2")])
+        fid = ctx.filter(L.FILTER_POLY if d["filter"] == 0 else L.FILTER_TANH)
+        plan = ctx.plan(data, L.VAR_PIXEL, d["nside"], pix, [d["theta_ap"]], [fid])
+        plans.append(plan)
+        outs.append(plan.empty_out())
+        maps.append(m)
+    log(f"mixed leg: {sum(m['pix'].size for m in maps)} pixels in 64 maps, generated and planned in "
+        f"{time.perf_counter() - t:.1f}s")
+    norms = [L.NORM_SUMMED_PIXCOUNT] * len(plans)
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.mixed_batch(plans, norms, outs)  # warm-up
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    ctx.mixed_batch(plans, norms, outs)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_mix = ev0.elapsed_time(ev1) / 1e3
+    ev0.record(stream)
+    for p, o in zip(plans, outs):
+        p.run(L.NORM_SUMMED_PIXCOUNT, o)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_seq = ev0.elapsed_time(ev1) / 1e3
+    ctx.mixed_batch(plans, norms, outs)
+    pairs = float(sum(float(o[0, 4].double().sum()) for o in outs))
+    res = {
+        "workload": f"64 pixel maps (NSIDE 512-4096, caps 100-15000 deg2 x {args.mixed_area_scale:g}, "
+                    "theta_ap 2-40 arcmin, both filters), one persistent launch",
+        "pixels": int(sum(m["pix"].size for m in maps)),
+        "pairs": pairs,
+        "mixed_ms": t_mix * 1e3,
+        "pair_evals_per_s": pairs / t_mix,
+        "one_by_one_ms": t_seq * 1e3,
+    }
+    if not args.no_cpu:
+        res.update(mixed_accuracy(inst, maps, outs))
+    return res
+
+
+def mixed_accuracy(inst, maps, outs, n_check=256, seed=13):
+    """Oracle check of every instance on n_check centres around a random
+    pixel of its field (the oracle sees the pixels within reach)."""
+    from oracle import aperture as A
+    from oracle import filters as F
+    from oracle import healpix_ref as hp
+
+    rng = np.random.default_rng(seed)
+    errs = []
+    for d, m, o in zip(inst, maps, outs):
+        nside = d["nside"]
+        anchor = m["pix"][rng.integers(0, m["pix"].size)]
+        a = hp.pix2vec(nside, np.array([anchor]))[0]
+        # candidates: rings within reach of the anchor, then exact distance
+        rt = hp.ring_table(nside)
+        colat = np.arctan2(rt["sin"], rt["z"])
+        reach = 0.5 * math.pi / 180 + d["theta_ap"] + 0.01
+        rings = np.nonzero(np.abs(colat - math.acos(a[2])) < reach)[0]
+        lo = rt["first"][rings[0]]
+        hi = rt["first"][rings[-1]] + rt["n"][rings[-1]]
+        sel = np.nonzero((m["pix"] >= lo) & (m["pix"] < hi))[0]
+        v = hp.pix2vec(nside, m["pix"][sel])
+        dist = np.arccos(np.clip(v @ a, -1, 1))
+        near = sel[dist < reach]
+        sub = {"nside": nside, "pix": m["pix"][near]}
+        for c in ("W", "G1", "G2", "E2"):
+            sub[c] = m[c][near]
+        inner = sel[dist < 0.5 * math.pi / 180]
+        pick = np.sort(rng.choice(inner, min(n_check, inner.size), replace=False))
+        ref = A.aperture_mass_pixel(sub, m["pix"][pick], d["theta_ap"], F.POLY if d["filter"] == 0 else F.TANH)
+        ok = ~ref["tie"]
+        g = o[0, 0].cpu().numpy()[pick].astype(np.float64)
+        rms = math.sqrt(np.mean(ref["M_E"][ok] ** 2))
+        diff = float(np.max(np.abs(g[ok] - ref["M_E"][ok])))
+        errs.append(diff / rms if rms > 0 else diff)
+    return {"per_instance_max_rel_err": errs, "max_rel_err": max(errs),
+            "accuracy_sample": f"{n_check} centres within 0.5 deg of a random pixel of each instance, M_E"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -254,6 +357,9 @@ def main():
     if args.only_batched:
         print(json.dumps({"batched": batched_leg(api.Context(0), args)}), flush=True)
         return
+    if args.only_mixed:
+        print(json.dumps({"mixed": mixed_leg(api.Context(0), args)}), flush=True)
+        return
 
     t = time.perf_counter()
     pm, R = config3_pixelmap(area_deg2=args.area, nside=args.nside)
@@ -269,10 +375,16 @@ def main():
     stream = torch.cuda.current_stream(dev)
     torch.cuda.synchronize()
 
-    def step(keep, ev=None, kms=None):
+    import tempfile
+
+    tune_cache = os.path.join(tempfile.gettempdir(), f"smartap_tune_{os.getpid()}.txt")
+
+    def step(keep, ev=None, tune_budget=0):
         data = ctx.pixel_map(args.nside, pix, *cols)
         plans = [ctx.plan(data, L.VAR_PIXEL, args.nside, pix, [th], [fid]) for th in scales]
         for k, p in enumerate(plans):
+            if not args.no_tune:
+                p.autotune(tune_budget, tune_cache)  # budget 0: cached choices only
             p.set_timing(True)
             if ev is not None:
                 ev[k][0].record(stream)
@@ -282,9 +394,11 @@ def main():
         keep.append((data, plans))
 
     keep = []
-    for _ in range(args.warmup):
-        step(keep)
+    t = time.perf_counter()
+    for w in range(max(args.warmup, 1 if not args.no_tune else 0)):
+        step(keep, tune_budget=20000 if w == 0 else 0)  # the first warm-up step measures the launch choices
     torch.cuda.synchronize()
+    log(f"warm-up (with autotuning) {time.perf_counter() - t:.1f}s")
     keep.clear()
     events = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in scales]
               for _ in range(args.steps)]
@@ -378,6 +492,9 @@ def main():
         del outs, cols, pix
         torch.cuda.empty_cache()
         res["batched"] = batched_leg(ctx, args)
+    if not args.no_mixed:
+        torch.cuda.empty_cache()
+        res["mixed"] = mixed_leg(ctx, args)
     print(json.dumps(res), flush=True)
 
 

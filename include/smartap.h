@@ -224,6 +224,21 @@ void smart_plan_free(smart_plan plan);
  * report n_belt = 0 and every tile as general. */
 int smart_plan_tiles(smart_plan plan, int scale, int* n_belt, int* n_general, int* d_tiles, void* stream);
 
+/* Autotuner. For every scale of a pixel-variant FP32 plan, times the launch
+ * choices of its pair kernels on the plan's own data (HIP events on
+ * `stream`): the general kernel with its per-ring set-up inline or out of
+ * line, and the persistent grid (blocks per compute unit) of the general and
+ * belt kernels; the fastest stays in the plan for later smart_run and
+ * smart_mixed_batch calls. Results are identical for every choice. Stops
+ * measuring after about budget_ms of host time (scales not reached keep the
+ * defaults). With cache_path non-NULL, choices are first looked up in that
+ * text file (one line per workload and scale; the key holds NSIDE, n_out,
+ * the tile counts, theta_ap and the filter kind) and new results are
+ * appended to it; budget_ms = 0 only looks up. Synchronises `stream`;
+ * allocates one scratch output of 5 x n_out floats while measuring. Other
+ * plans return SMART_OK unchanged. */
+int smart_autotune(smart_plan plan, int budget_ms, const char* cache_path, void* stream);
+
 /* Kernel timing (tracing). With enable != 0, later smart_run calls on a
  * pixel-variant FP32 plan record HIP events on the run's stream around the
  * belt-tile and general-tile pair kernels of every scale;

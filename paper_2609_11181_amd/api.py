@@ -188,6 +188,11 @@ class Plan:
                                               _stream(self.ctx.device)))
         return nb.value, ng.value, t[: nb.value + ng.value]
 
+    def autotune(self, budget_ms: int = 2000, cache_path=None):
+        """Measure and keep the fastest launch choices of every scale (see smart_autotune)."""
+        path = None if cache_path is None else str(cache_path).encode()
+        L.check(self.ctx.lib.smart_autotune(self.h, int(budget_ms), path, _stream(self.ctx.device)))
+
     def set_timing(self, enable: bool = True):
         L.check(self.ctx.lib.smart_plan_set_timing(self.h, 1 if enable else 0))
 

@@ -385,6 +385,14 @@ int smart_plan_tiles(smart_plan p, int scale, int* n_belt, int* n_general, int* 
   return SMART_OK;
 }
 
+int smart_autotune(smart_plan p, int budget_ms, const char* cache_path, void* stream) {
+  if (!p) return fail(SMART_EINVAL, "NULL plan");
+  if (budget_ms < 0) return fail(SMART_EINVAL, "budget_ms must be >= 0");
+  int rc;
+  if ((rc = set_device(p->ctx))) return rc;
+  return smart::autotune(p, budget_ms, cache_path, (hipStream_t)stream);
+}
+
 int smart_plan_set_timing(smart_plan p, int enable) {
   if (!p) return fail(SMART_EINVAL, "NULL plan");
   int rc;

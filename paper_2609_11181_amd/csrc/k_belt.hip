@@ -62,6 +62,11 @@ __global__ void k_belt_size(PixelArgs a, double theta_ap, double C_ap, const int
   cnts[idx] = c;
 }
 
+__global__ void k_iota(int* v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+
 struct Sum2i {
   __host__ __device__ int2 operator()(const int2& x, const int2& y) const { return make_int2(x.x + y.x, x.y + y.y); }
 };
@@ -138,24 +143,23 @@ __global__ __launch_bounds__(kBlock) void k_pixel_belt(PixelArgs a, ScaleArgs s,
   }
 }
 
-int grid_belt() {
-  static int grid = 0;
-  if (grid == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pixel_belt, kBlock, 0) != hipSuccess || per_cu <= 0)
-      per_cu = 2;
-    grid = std::max(cus, 1) * per_cu;
-  }
-  return grid;
+int belt_per_cu() {
+  static int per_cu = 0;
+  if (per_cu == 0 &&
+      (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pixel_belt, kBlock, 0) != hipSuccess || per_cu <= 0))
+    per_cu = 2;
+  return per_cu;
 }
 
 }  // namespace
 
+int belt_blocks_max() { return belt_per_cu(); }
+
 hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int* list, int count,
-                       int* cursors, hipStream_t st) {
-  hipLaunchKernelGGL(k_pixel_belt, dim3(grid_belt()), dim3(kBlock), 0, st, a, s, t, list, count, cursors);
+                       int* cursors, int blocks_per_cu, hipStream_t st) {
+  const int per_cu = belt_per_cu();
+  const int grid = device_cus() * (blocks_per_cu > 0 ? std::min(blocks_per_cu, per_cu) : per_cu);
+  hipLaunchKernelGGL(k_pixel_belt, dim3(grid), dim3(kBlock), 0, st, a, s, t, list, count, cursors);
   return hipGetLastError();
 }
 
@@ -175,6 +179,8 @@ PixelSched::~PixelSched() {
     if (e_ != hipSuccess) {                                                            \
       (void)hipFree(used);                                                             \
       (void)hipFree(flags);                                                            \
+      (void)hipFree(keys);                                                             \
+      (void)hipFree(ids);                                                              \
       (void)hipFree(cnts);                                                             \
       (void)hipFree(offs);                                                             \
       set_error(std::string("plan schedule: ") + hipGetErrorString(e_) + " at " #x); \
@@ -202,36 +208,47 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   int* flags = nullptr;
   int2* cnts = nullptr;
   int2* offs = nullptr;
+  uint64_t* keys = nullptr;  // keys, sorted keys
+  int* ids = nullptr;        // 0 .. nt - 1
   const int nb = 2 * N + 1;  // belt rings N .. 3N
   const int nt = (int)((p->n_out + kBlock - 1) / kBlock);
   sc->n_tiles = nt;
   BCHK(hipMalloc((void**)&sc->list, sizeof(int) * (nt + 1)));
   BCHK(hipMalloc((void**)&sc->cursors, sizeof(int) * 33));  // cursors, then the belt tile count
   BCHK(hipMalloc((void**)&flags, sizeof(int) * (nt + 1)));
+  BCHK(hipMalloc((void**)&keys, sizeof(uint64_t) * 2 * (nt + 1)));
+  BCHK(hipMalloc((void**)&ids, sizeof(int) * (nt + 1)));
   BCHK(hipMalloc((void**)&used, sizeof(int) * nb));
   BCHK(hipMalloc((void**)&cnts, sizeof(int2) * nb));
   BCHK(hipMalloc((void**)&offs, sizeof(int2) * nb));
   BCHK(hipMalloc((void**)&sc->head, sizeof(int2) * nb));
   BCHK(hipMemsetAsync(used, 0, sizeof(int) * nb, st));
-  // belt tiles first (ascending), then the general tiles
-  launch_classify(a, s.theta_ap, nt, flags, used, st);
+  // order of the schedule: belt tiles column-major (tiles of one azimuth
+  // column on consecutive rings share their disc rows, so the tiles in flight
+  // on one XCD stay within its L2), then the general tiles in list order
+  launch_classify(a, s.theta_ap, nt, flags, used, keys, st);
   BCHK(hipGetLastError());
-  size_t tb = 0, tb2 = 0;
-  hipcub::CountingInputIterator<int> ids(0);
-  BCHK(hipcub::DevicePartition::Flagged(nullptr, tb, ids, flags, sc->list, sc->cursors + 32, nt, st));
+  hipLaunchKernelGGL(k_iota, dim3((nt + kBlock - 1) / kBlock), dim3(kBlock), 0, st, ids, nt);
+  size_t tb = 0, tb2 = 0, tb3 = 0;
+  BCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, keys + nt, ids, sc->list, nt, 0, 57, st));
+  BCHK(hipcub::DeviceReduce::Sum(nullptr, tb3, flags, sc->cursors + 32, nt, st));
   hipLaunchKernelGGL(k_belt_size, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.theta_ap, s.C_ap, used,
                      cnts);
   BCHK(hipGetLastError());
   BCHK(hipcub::DeviceScan::ExclusiveScan(nullptr, tb2, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
-  if (ensure_temp(p->ctx, std::max(tb, tb2))) {
+  if (ensure_temp(p->ctx, std::max(tb, std::max(tb2, tb3)))) {
     (void)hipFree(used);
     (void)hipFree(flags);
     (void)hipFree(cnts);
     (void)hipFree(offs);
+    (void)hipFree(keys);
+    (void)hipFree(ids);
     return SMART_ENOMEM;
   }
   tb = p->ctx->temp_bytes;
-  BCHK(hipcub::DevicePartition::Flagged(p->ctx->d_temp, tb, ids, flags, sc->list, sc->cursors + 32, nt, st));
+  BCHK(hipcub::DeviceRadixSort::SortPairs(p->ctx->d_temp, tb, keys, keys + nt, ids, sc->list, nt, 0, 57, st));
+  tb = p->ctx->temp_bytes;
+  BCHK(hipcub::DeviceReduce::Sum(p->ctx->d_temp, tb, flags, sc->cursors + 32, nt, st));
   tb = p->ctx->temp_bytes;
   BCHK(hipcub::DeviceScan::ExclusiveScan(p->ctx->d_temp, tb, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
   int n_belt = 0;
@@ -242,6 +259,8 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   BCHK(hipStreamSynchronize(st));
   sc->counts[0] = n_belt;
   sc->counts[1] = nt - n_belt;
+  // out-of-line per-ring set-up pays off for discs of many members per ring
+  sc->general_ool = s.theta_ap * (double)N >= 16.0 * 0.75 ? 1 : 0;
   const int n_info = last_o.x + last_c.x, n_coef = last_o.y + last_c.y;
   BCHK(hipMalloc((void**)&sc->info, sizeof(int4) * std::max(n_info, 1)));
   BCHK(hipMalloc((void**)&sc->qc, sizeof(double) * std::max(n_coef, 1)));
@@ -260,6 +279,8 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   BCHK(hipStreamSynchronize(st));  // the scratch below is freed next
   (void)hipFree(used);
   (void)hipFree(flags);
+  (void)hipFree(keys);
+  (void)hipFree(ids);
   (void)hipFree(cnts);
   (void)hipFree(offs);
   return SMART_OK;

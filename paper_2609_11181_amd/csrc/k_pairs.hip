@@ -39,13 +39,13 @@ namespace {
 // One wave per tile: the lanes compare the tile's 256 list entries with
 // consecutive pixel indices, then every lane takes the same decision.
 __global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_ap, int n_tiles, int* flags,
-                                                     int* used) {
+                                                     int* used, uint64_t* keys) {
   const int t = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= n_tiles) return;
   const int64_t o0 = (int64_t)t * kBlock;
   bool ok = o0 + kBlock <= a.n_out && a.nside_in == a.nside_out;
-  int rp = 0;
+  int rp = 0, ip = 0;
   if (ok) {
     const int64_t p0 = a.out_pix[o0];
     bool run = true;
@@ -53,7 +53,6 @@ __global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_a
     for (int k = 0; k < kBlock / 64; ++k) run = run && a.out_pix[o0 + lane + 64 * k] == p0 + lane + 64 * k;
     ok = __all(run);
     if (ok) {
-      int ip;
       pixel_ring(a.nside_out, p0, &rp, &ip);
       const Ring R = ring_info(a.nside_out, rp);
       ok = ip + kBlock <= R.n && R.n == 4 * a.nside_in;
@@ -67,12 +66,16 @@ __global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_a
   if (lane == 0) {
     flags[t] = ok ? 1 : 0;
     if (ok) used[rp - a.nside_in] = 1;
+    // belt tiles column-major (azimuth column of 256 pixels, then ring), then
+    // the general tiles in list order
+    keys[t] = ok ? ((uint64_t)(ip / kBlock) << 40) | ((uint64_t)rp << 24) | (uint64_t)(t & 0xffffff)
+                 : (1ull << 56) | (uint64_t)t;
   }
 }
 
 // ---- pixel variant, mixed precision: general kernel -------------------------------
 
-template <bool TABLE, bool BIG>
+template <bool TABLE, bool BIG, bool OOL>
 __global__ __launch_bounds__(kBlock) void k_pixel_f32(PixelArgs a, ScaleArgs s, const int* tiles, int n_tiles,
                                                       int* cursors) {
   __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_pixel_f32(PixelArgs a, ScaleArgs s, 
     const int item = next_tile(cursors, n_tiles, &s_item);  // also orders the table load
     if (item < 0) break;
     const int tile = tiles ? tiles[item] : item;
-    general_centre<TABLE, BIG>(a, s, (int64_t)tile * kBlock + threadIdx.x, tp, tab);
+    general_centre<TABLE, BIG, OOL>(a, s, (int64_t)tile * kBlock + threadIdx.x, tp, tab);
   }
 }
 
@@ -332,35 +335,67 @@ __global__ void k_sum_n(const void* out, int is_double, int64_t n_out, int n_sca
 
 static int64_t blocks_for(int64_t n) { return (n + kBlock - 1) / kBlock; }
 
-template <typename K>
-static int persistent_grid(K kernel) {
-  static int dev_cus = 0;
-  if (dev_cus == 0) {
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
     int dev = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (dev_cus <= 0) dev_cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 256;
   }
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu <= 0) per_cu = 2;
-  return dev_cus * per_cu;
+  return cus;
 }
 
-template <bool TABLE, bool BIG>
+template <typename K>
+static int persistent_per_cu(K kernel) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu <= 0) per_cu = 2;
+  return per_cu;
+}
+
+template <typename K>
+static int persistent_grid(K kernel) {
+  return device_cus() * persistent_per_cu(kernel);
+}
+
+template <bool TABLE, bool BIG, bool OOL>
 static hipError_t launch_general_t(const PixelArgs& a, const ScaleArgs& s, hipStream_t st, const int* list,
-                                   int count, int* cursors) {
-  static const int grid = persistent_grid(k_pixel_f32<TABLE, BIG>);
-  hipLaunchKernelGGL((k_pixel_f32<TABLE, BIG>), dim3(grid), dim3(kBlock), 0, st, a, s, list, count, cursors);
+                                   int count, int* cursors, int blocks_per_cu) {
+  static const int per_cu = persistent_per_cu(k_pixel_f32<TABLE, BIG, OOL>);
+  const int grid = device_cus() * (blocks_per_cu > 0 ? std::min(blocks_per_cu, per_cu) : per_cu);
+  hipLaunchKernelGGL((k_pixel_f32<TABLE, BIG, OOL>), dim3(grid), dim3(kBlock), 0, st, a, s, list, count, cursors);
   return hipGetLastError();
 }
 
 static hipError_t launch_general(const PixelArgs& a, const ScaleArgs& s, hipStream_t st, const int* list, int count,
-                                 int* cursors) {
+                                 int* cursors, int ool = 0, int blocks_per_cu = 0) {
   const bool table = s.filter_kind != SMART_FILTER_POLY;
-  if (table && s.big) return launch_general_t<true, true>(a, s, st, list, count, cursors);
-  if (table) return launch_general_t<true, false>(a, s, st, list, count, cursors);
-  if (s.big) return launch_general_t<false, true>(a, s, st, list, count, cursors);
-  return launch_general_t<false, false>(a, s, st, list, count, cursors);
+  const int c = (table ? 4 : 0) + (s.big ? 2 : 0) + (ool ? 1 : 0);
+  switch (c) {
+    case 0: return launch_general_t<false, false, false>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 1: return launch_general_t<false, false, true>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 2: return launch_general_t<false, true, false>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 3: return launch_general_t<false, true, true>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 4: return launch_general_t<true, false, false>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 5: return launch_general_t<true, false, true>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 6: return launch_general_t<true, true, false>(a, s, st, list, count, cursors, blocks_per_cu);
+    default: return launch_general_t<true, true, true>(a, s, st, list, count, cursors, blocks_per_cu);
+  }
+}
+
+int general_blocks_max(const ScaleArgs& s, int ool) {
+  const bool table = s.filter_kind != SMART_FILTER_POLY;
+  const int c = (table ? 4 : 0) + (s.big ? 2 : 0) + (ool ? 1 : 0);
+  switch (c) {
+    case 0: return persistent_per_cu(k_pixel_f32<false, false, false>);
+    case 1: return persistent_per_cu(k_pixel_f32<false, false, true>);
+    case 2: return persistent_per_cu(k_pixel_f32<false, true, false>);
+    case 3: return persistent_per_cu(k_pixel_f32<false, true, true>);
+    case 4: return persistent_per_cu(k_pixel_f32<true, false, false>);
+    case 5: return persistent_per_cu(k_pixel_f32<true, false, true>);
+    case 6: return persistent_per_cu(k_pixel_f32<true, true, false>);
+    default: return persistent_per_cu(k_pixel_f32<true, true, true>);
+  }
 }
 
 __global__ void k_zero_ints(int* p, int n) {
@@ -381,24 +416,25 @@ hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, h
 }
 
 hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st,
-                              hipEvent_t* ev) {
+                              hipEvent_t* ev, int kinds) {
   hipError_t e = hipSuccess;
   if (a.n_out > 0) hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, sc.cursors, 32);
   if (ev) e = hipEventRecord(ev[0], st);
-  if (e == hipSuccess && a.n_out > 0 && sc.counts[0] > 0)
-    e = launch_belt(a, s, sc.tab(), sc.lists(0), sc.counts[0], sc.cursors, st);
+  if (e == hipSuccess && a.n_out > 0 && sc.counts[0] > 0 && (kinds & 1))
+    e = launch_belt(a, s, sc.tab(), sc.lists(0), sc.counts[0], sc.cursors, sc.belt_blocks, st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
-  if (e == hipSuccess && a.n_out > 0 && sc.counts[1] > 0)
-    e = launch_general(a, s, st, sc.lists(1), sc.counts[1], sc.cursors + 16);
+  if (e == hipSuccess && a.n_out > 0 && sc.counts[1] > 0 && (kinds & 2))
+    e = launch_general(a, s, st, sc.lists(1), sc.counts[1], sc.cursors + 16, sc.general_ool, sc.general_blocks);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
   return e;
 }
 
-void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* flags, int* used, hipStream_t st) {
+void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* flags, int* used, uint64_t* keys,
+                     hipStream_t st) {
   const unsigned blocks = (unsigned)((n_tiles + kBlock / 64 - 1) / (kBlock / 64));
   if (n_tiles > 0)
-    hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(kBlock), 0, st, a, theta_ap, n_tiles, flags, used);
+    hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(kBlock), 0, st, a, theta_ap, n_tiles, flags, used, keys);
 }
 
 size_t pixel_work_ints(int64_t n_out) {

@@ -230,6 +230,10 @@ struct RingStep {
   double cd, sd, sd2, hsd, hd;
   __device__ __forceinline__ void init(double d) {
     sin_hav(d, &sd, &hd);
+    finish();
+  }
+  // derived terms once sd and hd are set
+  __device__ __forceinline__ void finish() {
     cd = 1.0 - 2.0 * hd;
     sd2 = 2.0 * sd;
     hsd = 0.5 * sd;

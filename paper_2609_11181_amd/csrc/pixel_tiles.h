@@ -84,6 +84,22 @@ __device__ inline int next_tile_wave(int* cursors, int count) {
   return __builtin_amdgcn_readfirstlane(__shfl(item, 0));
 }
 
+// Per-ring set-up of the general walk, out of line (OOL variant): the
+// library functions and series constants it needs are otherwise hoisted into
+// registers for the whole kernel, which costs occupancy; the calls cost
+// time per ring, so the inline variant wins for small discs.
+__device__ __attribute__((noinline)) void general_span(int nside, double sp, double zp, double theta_ap, int* lo,
+                                                      int* hi) {
+  ring_span(nside, atan2(sp, zp), theta_ap, lo, hi);
+}
+
+__device__ __attribute__((noinline)) bool general_window(double zp, double sp, int64_t ip2, int np, const Ring& Q,
+                                                        double C, int64_t* jlo, int* cnt) {
+  return ring_window(zp, sp, ip2, np, Q, C, jlo, cnt);
+}
+
+__device__ __attribute__((noinline)) void general_sin_hav(double av, double* sa, double* h) { sin_hav(av, sa, h); }
+
 // One member of a general tile: tangent-plane components from the walk
 // state, coefficients, accumulation.
 template <bool TABLE, bool BIG>
@@ -100,7 +116,7 @@ __device__ __forceinline__ void general_member(double sa, double h, double sp, d
 // and haversine follow from the previous member's by the angle-difference
 // identities (RingStep) instead of a series per member. A window that wraps
 // past the ring's last pixel is walked as two contiguous runs.
-template <bool TABLE, bool BIG>
+template <bool TABLE, bool BIG, bool OOL>
 __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleArgs& s, int64_t o, const double* tp,
                                                Tab tab) {
   if (o >= a.n_out) return;
@@ -112,7 +128,8 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
   const int np = R.n;
   const int64_t ip2 = 2 * (int64_t)ip + R.twice_o;
   int lo, hi;
-  ring_span(a.nside_in, atan2(sp, zp), s.theta_ap, &lo, &hi);
+  if (OOL) general_span(a.nside_in, sp, zp, s.theta_ap, &lo, &hi);
+  else ring_span(a.nside_in, atan2(sp, zp), s.theta_ap, &lo, &hi);
   lo = max(lo, a.ring_lo);
   hi = min(hi, a.ring_hi);
 
@@ -121,16 +138,22 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     const Ring Q = ring_info(a.nside_in, r);
     int64_t jlo;
     int cnt;
-    if (!ring_window(zp, sp, ip2, np, Q, s.C_ap, &jlo, &cnt)) continue;
+    const bool reached = OOL ? general_window(zp, sp, ip2, np, Q, s.C_ap, &jlo, &cnt)
+                             : ring_window(zp, sp, ip2, np, Q, s.C_ap, &jlo, &cnt);
+    if (!reached) continue;
     const int nq = Q.n;
     const double Y0 = ring_y0(Q.s, Q.z, zp, sp);
     const double Kz = 2.0 * Q.z * sp;
     // dphi of the first member = pi m / (np nq) with m an exact integer
     const int64_t m = ip2 * nq - (2 * jlo + Q.twice_o) * (int64_t)np;
     double sa, h;
-    sin_hav((double)m * (kPi / ((double)np * (double)nq)), &sa, &h);
+    const double av = (double)m * (kPi / ((double)np * (double)nq));
+    if (OOL) general_sin_hav(av, &sa, &h);
+    else sin_hav(av, &sa, &h);
     RingStep step;
-    step.init(2.0 * kPi / (double)nq);
+    if (OOL) general_sin_hav(2.0 * kPi / (double)nq, &step.sd, &step.hd);
+    else sin_hav(2.0 * kPi / (double)nq, &step.sd, &step.hd);
+    step.finish();
     // the member at the centre itself (same ring, dphi = 0), if any: the walk
     // restarts there from exact zeros, so its shear term vanishes exactly
     const int64_t mstep = 2 * (int64_t)np;
@@ -151,12 +174,13 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
         const int kn = min(run - k0, kChunk);
         float sv = 0.f;
         int k = 0;
-        for (; k + 4 <= kn; k += 4) {
-          float4 g[4];
+        constexpr int U = OOL ? 2 : 4;  // members in flight
+        for (; k + U <= kn; k += U) {
+          float4 g[U];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) g[u] = p[k0 + k + u];
+          for (int u = 0; u < U; ++u) g[u] = p[k0 + k + u];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < U; ++u) {
             general_member<TABLE, BIG>(sa, h, sp, Y0, Kz, g[u], tp, tab, tot, sv);
             step.advance(&sa, &h);
           }
@@ -296,10 +320,9 @@ __device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s
     const int4 inf = make_int4(ip[0], ip[1], ip[2], ip[3]);
     const int cnt = inf.z;
     if (cnt == 0) continue;
-    const Ring Q = ring_info(N, inf.x);
-    const int64_t dring = Q.first - a.pix_first;
-    int j0 = (ip0 + 4 * lane + inf.y) % n;
-    j0 = j0 < 0 ? j0 + n : j0;
+    // belt ring inf.x starts at pixel 2N(N-1) + 4N(r - N); n = 4N is a power of two
+    const int64_t dring = 2 * (int64_t)N * (N - 1) + (int64_t)n * (inf.x - N) - a.pix_first;
+    const int j0 = (ip0 + 4 * lane + inf.y) & (n - 1);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {  // W and N_occ of each centre's window
       const int jc = j0 + c < n ? j0 + c : j0 + c - n;

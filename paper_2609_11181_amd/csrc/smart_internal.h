@@ -166,6 +166,10 @@ struct PixelSched {
   int* list = nullptr;      // belt tiles in order, then the general tiles
   int* cursors = nullptr;   // queue cursors: [0, 16) belt kernel, [16, 32) general kernel
   int counts[2] = {0, 0};   // belt and general tile counts
+  // launch choices (defaults from the disc size; smart_autotune measures them)
+  int general_ool = 0;      // general kernel with out-of-line per-ring set-up
+  int belt_blocks = 0;      // persistent blocks per CU (0: occupancy maximum)
+  int general_blocks = 0;
   int2* head = nullptr;
   int4* info = nullptr;
   double* qc = nullptr;
@@ -181,17 +185,25 @@ struct PixelSched {
 // d_work: device scratch of pixel_work_ints(n_out) ints (queue cursors).
 hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, hipStream_t st, int* d_work);
 size_t pixel_work_ints(int64_t n_out);
-// Flags the belt tiles among the tiles of 256 list entries (flags[t] = 1)
-// and sets used[rp - nside] = 1 for the ring of every belt tile.
-void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* flags, int* used, hipStream_t st);
+// Flags the belt tiles among the tiles of 256 list entries (flags[t] = 1),
+// sets used[rp - nside] = 1 for the ring of every belt tile and writes the
+// schedule order key of every tile (belt tiles column-major, then general).
+void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* flags, int* used, uint64_t* keys,
+                     hipStream_t st);
 // Scheduled path: belt tiles through the tables, general tiles as above.
-// ev: NULL, or 4 events recorded around the belt and the general kernel.
+// ev: NULL, or 4 events recorded around the belt and the general kernel;
+// kinds: bit 0 runs the belt kernel, bit 1 the general kernel.
 hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st,
-                              hipEvent_t* ev = nullptr);
+                              hipEvent_t* ev = nullptr, int kinds = 3);
+// Occupancy maxima (blocks of 256 per CU) of the pair kernels.
+int belt_blocks_max();
+int general_blocks_max(const ScaleArgs& s, int ool);
 // belt kernels (k_belt.hip)
 int build_pixel_sched(smart_plan p, int scale, hipStream_t st, PixelSched* sc);
 hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int* list, int count,
-                       int* cursors, hipStream_t st);
+                       int* cursors, int blocks_per_cu, hipStream_t st);
+// Compute units of the current device.
+int device_cus();
 hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, hipStream_t st);
 hipError_t launch_sum_n(const void* out, int precision, int64_t n_out, int n_scales, double* d_acc,
                         hipStream_t st);
@@ -211,6 +223,9 @@ hipError_t launch_check_pixels(const int64_t* pix, int64_t n, int64_t npix, int*
 hipError_t launch_rotate_map(const float4* map, const int* cidx, const float* u, int64_t n, float4* out,
                              hipStream_t st);
 int noise_bf16x3(smart_plan plan, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st);
+
+// autotuner (tune.cpp)
+int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st);
 
 // mixed batch (k_mixed.hip)
 int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,

@@ -21,6 +21,7 @@ EXPORTS = [
     "smart_data_export",
     "smart_data_free", "smart_plan_create", "smart_run", "smart_last_pairs", "smart_plan_free",
     "smart_noise_batch", "smart_mixed_batch", "smart_plan_tiles", "smart_plan_set_timing", "smart_plan_kernel_ms",
+    "smart_autotune",
 ]
 
 
@@ -57,6 +58,7 @@ _SIGS = {
     "smart_mixed_batch": (_int, [_vp, _int, C.POINTER(_vp), C.POINTER(_int), C.POINTER(_vp), _vp]),
     "smart_plan_tiles": (_int, [_vp, _int, C.POINTER(_int), C.POINTER(_int), _vp, _vp]),
     "smart_plan_set_timing": (_int, [_vp, _int]),
+    "smart_autotune": (_int, [_vp, _int, C.c_char_p, _vp]),
     "smart_plan_kernel_ms": (_int, [_vp, _int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 }
 

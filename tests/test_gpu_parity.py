@@ -349,3 +349,30 @@ def test_plan_schedule_and_kernel_timing(ctx):
     ref = A.aperture_mass_pixel(m, m["pix"][::97], th, F.TANH)
     errs = _compare(out.cpu().numpy()[0][:, ::97], ref, A.NORM_SUMMED_PIXCOUNT, 1e-6)
     print(nb, ng, b, g, errs)
+
+
+def test_autotune_keeps_results_and_caches(ctx, tmp_path):
+    """The autotuner only changes launch choices: maps are bit-identical
+    before and after tuning; a second plan of the same workload takes the
+    cached choices without measuring (budget 0)."""
+    import torch
+
+    L = _L()
+    nside = 256
+    m = _pixmap(nside, 17, cap=40 * DEG)
+    data = ctx.pixel_map(nside, m["pix"], m["W"], m["G1"], m["G2"], m["E2"])
+    ths = [0.3 * DEG, 1.0 * DEG]
+    fid = ctx.filter(F.TANH)
+    plan = ctx.plan(data, L.VAR_PIXEL, nside, m["pix"], ths, [fid, fid])
+    before = plan.run(L.NORM_SUMMED_PIXCOUNT).cpu().numpy()
+    cache = tmp_path / "tune.txt"
+    plan.autotune(budget_ms=5000, cache_path=cache)
+    after = plan.run(L.NORM_SUMMED_PIXCOUNT).cpu().numpy()
+    assert np.array_equal(before, after)
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 2 and all(ln.startswith("key=%d/" % nside) for ln in lines)
+    plan2 = ctx.plan(data, L.VAR_PIXEL, nside, m["pix"], ths, [fid, fid])
+    plan2.autotune(budget_ms=0, cache_path=cache)
+    assert np.array_equal(plan2.run(L.NORM_SUMMED_PIXCOUNT).cpu().numpy(), before)
+    assert len(cache.read_text().strip().splitlines()) == 2
+    torch.cuda.synchronize()
