@@ -49,7 +49,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    p.add_argument("--cpu-outputs", type=int, default=8000)
+    p.add_argument("--cpu-outputs", type=int, default=32000)
     p.add_argument("--area", type=float, default=15000.0, help="field area in deg^2")
     p.add_argument("--nside", type=int, default=4096)
     p.add_argument("--no-batched", action="store_true", help="skip the batched noise-realisation leg")
@@ -69,14 +69,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pm, R, scales, n_out, seed=11):
-    """FP64 oracle on a patch of the same map: n_out apertures drawn in a
-    1-degree disc at a random point of the field, with the input pixels
-    that can reach them."""
+_CPU_SUB = None  # sub-map shared with the forked oracle workers
+
+
+def _oracle_chunk(task):
     from oracle import aperture as A
     from oracle import filters as F
+
+    out_pix, th = task
+    r = A.aperture_mass_pixel(_CPU_SUB, out_pix, th, F.TANH)
+    return {k: r[k] for k in ("M_E", "M_B", "sigma", "W", "N", "tie")}
+
+
+def cpu_baseline(pm, R, scales, n_out, workers, seed=11):
+    """FP64 oracle on a patch of the same map: n_out apertures drawn in a
+    2-degree disc at a random point of the field, with the input pixels that
+    can reach them; the apertures are split over `workers` forked processes
+    (the oracle itself is unchanged). Runs before the GPU is touched."""
+    import multiprocessing as mp
+
     from oracle import healpix_ref as hp
 
+    global _CPU_SUB
     nside = pm["nside"]
     rng = np.random.default_rng(seed)
     # patch centre: inside the field, away from its edge
@@ -89,7 +103,8 @@ def cpu_baseline(pm, R, scales, n_out, seed=11):
     # candidate pixels: rings within the patch band, then exact distance
     rt = hp.ring_table(nside)
     colat0 = math.pi / 2 - dec0
-    reach = 1.0 * math.pi / 180 + max(scales) + 0.01
+    patch = 2.0 * math.pi / 180
+    reach = patch + max(scales) + 0.01
     colat = np.arctan2(rt["sin"], rt["z"])
     rings = np.nonzero(np.abs(colat - colat0) < reach)[0]
     lo = rt["first"][rings[0]]
@@ -102,16 +117,22 @@ def cpu_baseline(pm, R, scales, n_out, seed=11):
     sub = {"nside": nside, "pix": pix[keep]}
     for k in ("W", "G1", "G2", "E2"):
         sub[k] = pm[k][sel][keep]
-    inner = sub["pix"][d[keep] < 1.0 * math.pi / 180]
+    inner = sub["pix"][d[keep] < patch]
     out_pix = np.sort(rng.choice(inner, min(n_out, inner.size), replace=False))
+    _CPU_SUB = sub
+    chunks = np.array_split(out_pix, workers)
+    tasks = [(ch, th) for th in scales for ch in chunks]
     t0 = time.perf_counter()
-    refs = []
-    pairs = 0
-    for th in scales:
-        r = A.aperture_mass_pixel(sub, out_pix, th, F.TANH)
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_oracle_chunk, tasks, chunksize=1)
+    dt = time.perf_counter() - t0
+    refs, pairs = [], 0
+    for k in range(len(scales)):
+        ps = parts[k * workers:(k + 1) * workers]
+        r = {key: np.concatenate([q[key] for q in ps]) for key in ps[0]}
         refs.append(r)
         pairs += int(r["N"].sum())
-    dt = time.perf_counter() - t0
+    _CPU_SUB = None
     return out_pix, refs, pairs, dt
 
 
@@ -350,9 +371,21 @@ def main():
         log(f"copied {n * 4} bytes x 3 (read {n * 4} B + write {n * 4} B per copy)")
         return
 
+    from synth import config3_pixelmap
+
+    if not (args.only_batched or args.only_mixed):
+        t = time.perf_counter()
+        pm, R = config3_pixelmap(area_deg2=args.area, nside=args.nside)
+        log(f"generated {pm['pix'].size} pixels in {time.perf_counter() - t:.1f}s")
+        scales = [5 * ARCMIN, 10 * ARCMIN, 20 * ARCMIN]
+        cpu = None
+        if not args.no_cpu:  # on the host cores, before the GPU is touched (the workers are forked)
+            workers = max(1, min(len(os.sched_getaffinity(0)), 16))
+            cpu = cpu_baseline(pm, R, scales, args.cpu_outputs, workers) + (workers,)
+            log(f"oracle baseline: {cpu[2]} pairs in {cpu[3]:.1f}s on {workers} processes")
+
     from paper_2609_11181_amd import api
     from paper_2609_11181_amd import lib as L
-    from synth import config3_pixelmap
 
     if args.only_batched:
         print(json.dumps({"batched": batched_leg(api.Context(0), args)}), flush=True)
@@ -361,11 +394,7 @@ def main():
         print(json.dumps({"mixed": mixed_leg(api.Context(0), args)}), flush=True)
         return
 
-    t = time.perf_counter()
-    pm, R = config3_pixelmap(area_deg2=args.area, nside=args.nside)
-    log(f"generated {pm['pix'].size} pixels in {time.perf_counter() - t:.1f}s")
     dev = torch.device("cuda", 0)
-    scales = [5 * ARCMIN, 10 * ARCMIN, 20 * ARCMIN]
     ctx = api.Context(0)
     fid = ctx.filter(L.FILTER_TANH)
     pix = torch.from_numpy(pm["pix"]).to(dev)
@@ -469,8 +498,8 @@ def main():
     default_workload = args.nside == 4096 and args.area == 15000.0
     res["roofline"]["traffic"] = TRAFFIC_BYTES.get(res["roofline"]["kernel"]) if default_workload else None
     # accuracy on the oracle sample + CPU baseline
-    if not args.no_cpu:
-        out_pix, refs, cpairs, cdt = cpu_baseline(pm, R, scales, args.cpu_outputs)
+    if cpu is not None:
+        out_pix, refs, cpairs, cdt, workers = cpu
         idx = np.searchsorted(pm["pix"], out_pix)
         errs = []
         for k, r in enumerate(refs):
@@ -482,10 +511,10 @@ def main():
         res["cpu_baseline"] = {
             "value": cpairs / cdt,
             "unit": "pair-evals/s",
-            "cores": 1,
+            "cores": workers,
             "kind": "oracle",
-            "sample": f"{out_pix.size} apertures x 3 scales in a 1-degree patch of the same map "
-                      f"({cpairs} pairs, {cdt:.1f} s, numpy FP64 single thread)",
+            "sample": f"{out_pix.size} apertures x 3 scales in a 2-degree patch of the same map "
+                      f"({cpairs} pairs, {cdt:.1f} s wall, numpy FP64, apertures split over {workers} processes)",
         }
     if not args.no_batched:
         keep.clear()

@@ -171,6 +171,11 @@ PixelSched::~PixelSched() {
   (void)hipFree(qc);
   (void)hipFree(qs);
   (void)hipFree(q2);
+  (void)hipFree(noise_seg_o);
+  (void)hipFree(noise_stacks);
+  (void)hipFree(noise_rest);
+  (void)hipFree(noise_stage);
+  (void)hipFree(noise_work);
 }
 
 #define BCHK(x)                                                                        \

@@ -11,14 +11,22 @@
 // i.e. in real arithmetic
 //   [E B] = [Qc Qs] [[X1  X2], [X2  -X1]]
 // a sparse aperture operator (outputs x 2 inputs) times a dense realisation
-// matrix (2 inputs x 2 realisations). On a belt tile of 32 consecutive
-// centres the operator restricted to one source ring is a band (Toeplitz)
-// matrix built from that ring's disc coefficients, so the contraction is
-// tiled as MFMA 32x32x16 BF16 products with each operand split into two
-// BF16 words (hi + lo) and three products per step (hi.hi + hi.lo + lo.hi),
-// accumulated in FP32: about 2^-16 relative per term.
+// matrix (2 inputs x 2 realisations). On a segment of 32 consecutive centres
+// of a belt ring the operator restricted to one source ring is a band
+// (Toeplitz) matrix of that ring's disc coefficients, which the plan's belt
+// table holds. The contraction runs as MFMA 32x32x16 BF16 products with each
+// operand split into two BF16 words (hi + lo) and three products per step
+// (hi.hi + hi.lo + lo.hi), accumulated in FP32: about 2^-16 relative per term.
+//
+// A block owns a stack of four segments (the same 32-pixel column of four
+// consecutive belt rings, one per wave) and 32 realisations. The realisations
+// of a source ring's slab are generated once per block into LDS and used by
+// every wave whose disc reaches that ring, so each (pixel, realisation) value
+// is generated once per stack and disc ring instead of once per segment.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -33,10 +41,11 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kNP = 32;        // centres per tile (MFMA rows)
-constexpr int kNR = 32;        // realisations per block (E and B: 64 MFMA columns)
-constexpr int kXC = 32;        // source pixels per generated chunk of realisations
-constexpr int kCoefMax = 256;  // disc coefficients per ring held in LDS
+constexpr int kNP = 32;     // centres per segment (MFMA rows)
+constexpr int kNR = 32;     // realisations per block (E and B: two 32-column MFMA halves)
+constexpr int kStack = 4;   // segments per block, one per wave
+constexpr int kCntMax = 96;                    // members per disc ring of an eligible segment
+constexpr int kSlabMax = kNP + kCntMax + 16;   // union slab of the four windows on one ring
 
 __global__ void k_rotate(const float4* map, const int* cidx, const float* u, int64_t n, float4* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -48,49 +57,77 @@ __global__ void k_rotate(const float4* map, const int* cidx, const float* u, int
   out[i] = make_float4(g.x * c - g.y * s, g.x * s + g.y * c, g.z, g.w);
 }
 
-// Tiles of 32 list entries that are consecutive pixels of one belt ring
-// with the whole disc in the belt and a window that fits kCoefMax.
-__global__ void k_classify32(PixelArgs a, double theta_ap, double C_ap, int n_tiles, int* lists, int* counts) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  const int64_t o0 = (int64_t)t * kNP;
-  bool ok = o0 + kNP <= a.n_out;
+// Segment (belt ring N + i, column c: pixels 32c .. 32c + 31 of the ring) is
+// eligible when its ring has a belt table whose windows hold at most kCntMax
+// members, and its 32 pixels are consecutive entries of the (sorted) output
+// list; seg_o = list position of its first pixel, or -1.
+__global__ void k_noise_segs(PixelArgs a, BeltTab t, int ncol, int* seg_o) {
+  const int N = a.nside_in;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)(2 * N + 1) * ncol) return;
+  const int i = (int)(id / ncol), c = (int)(id % ncol);
+  int o = -1;
+  const int first = t.head[i].x, nr = t.head[i].y;
+  bool ok = nr > 0;
+  for (int k = 0; ok && k < nr; ++k) ok = t.info[first + k].z <= kCntMax;
   if (ok) {
-    const int64_t p0 = a.out_pix[o0];
-    int rp, ip;
-    pixel_ring(a.nside_out, p0, &rp, &ip);
-    const Ring R = ring_info(a.nside_out, rp);
-    ok = ip + kNP <= R.n && R.n == 4 * a.nside_in;
-    for (int k = 1; ok && k < kNP; ++k) ok = a.out_pix[o0 + k] == p0 + k;
-    if (ok) {
-      int lo, hi;
-      ring_span(a.nside_in, atan2(R.s, R.z), theta_ap, &lo, &hi);
-      ok = lo >= a.nside_in && hi <= 3 * a.nside_in;
-      // the widest window is on the centre's own ring
-      int64_t jlo;
-      int cnt;
-      if (ok && ring_window(R.z, R.s, 2 * (int64_t)ip + R.twice_o, R.n, R, C_ap, &jlo, &cnt))
-        ok = cnt + 2 <= kCoefMax;
+    const int64_t p0 = 2 * (int64_t)N * (N - 1) + 4 * (int64_t)N * i + kNP * (int64_t)c;
+    int64_t l = 0, h = a.n_out;  // first entry >= p0
+    while (l < h) {
+      const int64_t m = (l + h) >> 1;
+      if (a.out_pix[m] < p0) l = m + 1;
+      else h = m;
+    }
+    ok = l + kNP <= a.n_out;
+    for (int k = 0; ok && k < kNP; ++k) ok = a.out_pix[l + k] == p0 + k;
+    if (ok) o = (int)l;
+  }
+  seg_o[id] = o;
+}
+
+// Stack (column c, ring group g): flag when any of its segments is eligible,
+// and mark the list entries its segments cover.
+__global__ void k_noise_stacks(int n_groups, int ncol, int n_rings, const int* seg_o, int* flags, int* covered) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)n_groups * ncol) return;
+  const int c = (int)(id / n_groups), g = (int)(id % n_groups);  // column-major order
+  int any = 0;
+  for (int w = 0; w < kStack; ++w) {
+    const int i = kStack * g + w;
+    if (i >= n_rings) break;
+    const int o = seg_o[(int64_t)i * ncol + c];
+    if (o >= 0) {
+      any = 1;
+      for (int k = 0; k < kNP; ++k) covered[o + k] = 1;
     }
   }
-  const int which = ok ? 0 : 1;
-  const int slot = atomicAdd(&counts[which], 1);
-  lists[which * n_tiles + slot] = t;
+  flags[id] = any;
+}
+
+// outputs outside every stack: list positions and pixels
+__global__ void k_noise_rest(const int* covered, const int64_t* out_pix, int64_t n_out, int* flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_out) flags[i] = covered[i] ? 0 : 1;
+}
+
+__global__ void k_noise_rest_pix(const int64_t* pos, int n, const int64_t* out_pix, int64_t* pix) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pix[i] = out_pix[pos[i]];
 }
 
 struct NoiseArgs {
   PixelArgs a;
-  const float* u;   // [n_real][n_src]
-  const int* cidx;  // dense pixel -> source index
+  BeltTab t;
+  const int* seg_o;   // [(2N+1) * ncol]
+  const int* stacks;  // column * n_groups + group
+  int ncol, n_groups;
+  const float* u;     // [n_real][n_src]
+  const int* cidx;    // dense pixel -> source index
   int64_t n_src;
   int n_real;
-  int n_grp;        // groups of kWaves realisation blocks
-  float* out;       // [n_scales][n_real][2][n_out]
-  int n_scales;
-  const int* tiles;
+  int n_grp;          // realisation blocks of kNR
+  float* out;         // [n_scales][n_real][2][n_out]
 };
-
-constexpr int kWaves = 4;  // waves per block, one realisation block each
 
 // two BF16 words per 32-bit lane of an MFMA operand
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
@@ -107,126 +144,126 @@ __device__ __forceinline__ uint2 split_pair(float a, float b) {
   return make_uint2(hi, pack_bf16(a - bf16_lo_word(hi), b - bf16_hi_word(hi)));
 }
 
+// (X1, X2) -> (X2, -X1) in a packed word: the B-mode column
+__device__ __forceinline__ uint32_t bmode(uint32_t x) { return ((x >> 16) | (x << 16)) ^ 0x80000000u; }
+
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <bool TABLE, bool BIG>
-__global__ __launch_bounds__(64 * kWaves) void k_noise_mfma(NoiseArgs n, ScaleArgs s) {
-  __shared__ uint2 coefA[kCoefMax];           // (Qc, Qs) hi words, lo words
-  __shared__ float wsl[kCoefMax + kNP];
-  __shared__ float fnorm[kNP];
-  __shared__ uint2 xsm[kWaves][kXC * kNR];    // per wave: (X1, X2) hi words, lo words; reused for output staging
+__global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleArgs s) {
+  __shared__ uint2 xs[kSlabMax * kNR];         // slab realisations: (X1, X2) hi words, lo words
+  __shared__ uint2 coefA[kStack][kCntMax];     // per wave: (Qc, Qs) hi words, lo words
+  __shared__ int s_ws[kStack], s_we[kStack];   // per wave window [start, end) on the current ring
+  __shared__ float fnorm[kStack][kNP];
   const PixelArgs& a = n.a;
+  const int N = a.nside_in, nring = 4 * N;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int tile = n.tiles[blockIdx.x / n.n_grp];
-  const int rb = (blockIdx.x % n.n_grp) * kWaves + wave;  // realisation block of this wave
-  const int64_t o0 = (int64_t)tile * kNP;
-  const Tab tab{s.table, s.table_c0};
-  uint2* xs = xsm[wave];
-  double tp[7];
-#pragma unroll
-  for (int k = 0; k < 7; ++k) tp[k] = s.tpoly[k];
-
-  int rp, ip0;
-  pixel_ring(a.nside_out, a.out_pix[o0], &rp, &ip0);
-  const Ring R = ring_info(a.nside_out, rp);
-  const double zp = R.z, sp = R.s;
-  const int nr = R.n;
-  const int64_t ip2_0 = 2 * (int64_t)ip0 + R.twice_o;
-  int lo, hi;
-  ring_span(a.nside_in, atan2(sp, zp), s.theta_ap, &lo, &hi);
-  lo = max(lo, a.ring_lo);
-  hi = min(hi, a.ring_hi);
-  const double cphi = 3.14159265358979323846 / ((double)nr * (double)nr);
-  const int mstep = 2 * nr;
+  const int sid = n.stacks[blockIdx.x / n.n_grp];
+  const int rg = blockIdx.x % n.n_grp;  // realisation block
+  const int c = sid / n.n_groups, g = sid % n.n_groups;
+  const int iw = kStack * g + wave;     // belt ring index of this wave (ring N + iw)
+  const int o_w = iw <= 2 * N ? n.seg_o[(int64_t)iw * n.ncol + c] : -1;
+  const bool active = o_w >= 0;
+  const int hfirst = active ? n.t.head[iw].x : 0, hnr = active ? n.t.head[iw].y : 0;
+  const int lo_w = active ? n.t.info[hfirst].x : 0x7fffffff;
+  // union of the four discs' rings
+  __shared__ int s_lo[kStack], s_hi[kStack];
+  if (lane == 0) {
+    s_lo[wave] = active ? lo_w : 0x7fffffff;
+    s_hi[wave] = active ? lo_w + hnr - 1 : -1;
+  }
+  __syncthreads();
+  int lo = s_lo[0], hi = s_hi[0];
+  for (int w = 1; w < kStack; ++w) {
+    lo = min(lo, s_lo[w]);
+    hi = max(hi, s_hi[w]);
+  }
 
   f32x16 acc0 = {0}, acc1 = {0};
-  float wp = 0.f;  // threads 0..31: W and occupied count of centre o0 + tid
-  int np_occ = 0;
-  const int col = lane & 31;   // MFMA row (A) / column (B)
-  const int half = lane >> 5;  // k-slice of the lane
-  // realisation-generation role: pixel lane%32 of a chunk, realisations 2t + lane/32
-  const int gj = lane & 31, gr = lane >> 5;
+  double wp = 0.0, np_occ = 0.0;  // lanes 0..31: W and N_occ of centre o_w + lane
+  const int col = lane & 31;      // MFMA row (A) / column (B)
+  const int half = lane >> 5;     // k-slice of the lane
 
   for (int r = lo; r <= hi; ++r) {
-    const Ring Q = ring_info(a.nside_in, r);
-    int64_t jlo;
-    int cnt;
-    if (!ring_window(zp, sp, ip2_0, nr, Q, s.C_ap, &jlo, &cnt)) continue;  // block-uniform
-    const int L = kNP + cnt - 1;  // slab: centre t uses slab pixels [t, t + cnt)
-    const int m0 = (int)(ip2_0 * nr - (2 * jlo + Q.twice_o) * (int64_t)nr);
-    const double Y0 = ring_y0(Q.s, Q.z, zp, sp);
-    const double Kz = 2.0 * Q.z * sp;
-    const int64_t dbase = Q.first - a.pix_first;
-    int j0 = (int)(jlo % nr);
-    j0 = j0 < 0 ? j0 + nr : j0;
-    for (int k = tid; k < cnt; k += 64 * kWaves) {
-      const int m = m0 - k * mstep;
-      double xt, yt;
-      ring_xy(m, cphi, sp, Y0, Kz, &xt, &yt);
-      const Coef c = ring_coef<TABLE, BIG>(xt, yt, tp, tab);
-      coefA[k] = split_pair((float)c.qc, (float)c.qs);
+    // this wave's window on ring r for its first centre (pixel 32c of ring N + iw)
+    int cnt = 0, coff = 0, ws = 0;
+    if (active && r >= lo_w && r < lo_w + hnr) {
+      const int4 inf = n.t.info[hfirst + (r - lo_w)];
+      cnt = inf.z;
+      coff = inf.w;
+      ws = kNP * c + inf.y;
     }
-    for (int k = tid; k < L; k += 64 * kWaves) {
-      int j = j0 + k;
-      j = j >= nr ? j - nr : j;
-      wsl[k] = a.map[dbase + j].w;
+    const int we = cnt > 0 ? ws + kNP + cnt - 1 : ws;
+    if (lane == 0) {
+      s_ws[wave] = cnt > 0 ? ws : 0x7fffffff;
+      s_we[wave] = cnt > 0 ? we : -0x7fffffff;
+    }
+    // coefficients of the band
+    for (int k = lane; k < cnt; k += 64) coefA[wave][k] = split_pair((float)n.t.qc[coff + k], (float)n.t.qs[coff + k]);
+    const int64_t dring = 2 * (int64_t)N * (N - 1) + (int64_t)nring * (r - N) - a.pix_first;
+    if (cnt > 0 && lane < kNP) {  // W and N_occ of the window of centre `lane`
+      const int j0 = (ws + lane) & (nring - 1);
+      const int run = min(cnt, nring - j0);
+      const double2 l1 = a.wn[dring + j0], h1 = a.wn[dring + j0 + run];
+      wp += h1.x - l1.x;
+      np_occ += h1.y - l1.y;
+      if (run < cnt) {
+        const double2 l2 = a.wn[dring], h2 = a.wn[dring + cnt - run];
+        wp += h2.x - l2.x;
+        np_occ += h2.y - l2.y;
+      }
     }
     __syncthreads();
-    if (tid < kNP) {
-      for (int k = 0; k < cnt; ++k) {
-        const float w = wsl[tid + k];
-        wp += w;
-        np_occ += w > 0.f ? 1 : 0;
+    int us = s_ws[0], ue = s_we[0];
+    for (int w = 1; w < kStack; ++w) {
+      us = min(us, s_ws[w]);
+      ue = max(ue, s_we[w]);
+    }
+    if (ue <= us) {  // no wave reaches ring r
+      __syncthreads();
+      continue;
+    }
+    // every window holds at most 32 + kCntMax - 1 pixels and the four windows
+    // are centred within half a pixel of each other, so the union fits
+    const int Lu = min(ue - us, kSlabMax);
+    // realisations of the union slab: wave w generates realisations w, w + 4, ...
+    for (int s0 = 0; s0 < Lu; s0 += 64) {
+      const int sl = s0 + lane;
+      if (sl < Lu) {
+        const int j = (us + sl) & (nring - 1);
+        const int ci = n.cidx[dring + j];
+        const float4 gr = ci >= 0 ? a.map[dring + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int t = 0; t < kNR / kStack; ++t) {
+          const int rr = wave + kStack * t;
+          const int rreal = rg * kNR + rr;
+          const float uu = (ci >= 0 && rreal < n.n_real) ? n.u[(int64_t)rreal * n.n_src + ci] : 0.f;
+          const float sn = __builtin_amdgcn_sinf(uu), cs = __builtin_amdgcn_cosf(uu);  // of 2 pi u
+          xs[sl * kNR + rr] = split_pair(gr.x * cs - gr.y * sn, gr.x * sn + gr.y * cs);
+        }
       }
     }
-    // slab in chunks of kXC pixels: each wave generates its 32 rotated
-    // realisations of the chunk, then contracts 8 pixels (16 k) per MFMA step
-    for (int c0 = 0; c0 < L; c0 += kXC) {
-      {
-        int j = j0 + c0 + gj;
-        j = j >= nr ? j - nr : j;
-        const int ci = (c0 + gj < L) ? n.cidx[dbase + j] : -1;
-        float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-        float uu[kNR / 2];
-#pragma unroll
-        for (int t = 0; t < kNR / 2; ++t) {
-          const int rg = rb * kNR + 2 * t + gr;
-          uu[t] = (ci >= 0 && rg < n.n_real) ? n.u[(int64_t)rg * n.n_src + ci] : 0.f;
-        }
-        if (ci >= 0) g = a.map[dbase + j];
-#pragma unroll
-        for (int t = 0; t < kNR / 2; ++t) {
-          const float sn = __builtin_amdgcn_sinf(uu[t]), cs = __builtin_amdgcn_cosf(uu[t]);  // of 2 pi u
-          const float x1 = g.x * cs - g.y * sn;
-          const float x2 = g.x * sn + g.y * cs;
-          xs[gj * kNR + 2 * t + gr] = split_pair(x1, x2);
-        }
-      }
-      __syncthreads();
-      for (int s0 = 0; s0 < kXC && c0 + s0 < L; s0 += 8) {
+    __syncthreads();
+    if (cnt > 0) {
+      const int base = ws - us;       // slab slot of this wave's first window pixel
+      const int L = kNP + cnt - 1;    // centre t uses window pixels [t, t + cnt)
+      for (int s0 = 0; s0 < L; s0 += 8) {
         u32x4 ah, al, b0h, b0l, b1h, b1l;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int js = s0 + half * 4 + q;  // pixel within the chunk
-          const int ks = c0 + js - col;      // disc offset for centre `col`
-          const uint2 w = (c0 + js < L && ks >= 0 && ks < cnt) ? coefA[ks] : make_uint2(0u, 0u);
+          const int js = s0 + half * 4 + q;  // pixel within the window
+          const int ks = js - col;           // disc offset for centre `col`
+          const uint2 w = (js < L && ks >= 0 && ks < cnt) ? coefA[wave][ks] : make_uint2(0u, 0u);
           ah[q] = w.x;
           al[q] = w.y;
-          // B column col = 2 r' + e: rows (X1, X2) for e = 0, (X2, -X1) for e = 1
-          const uint2 x0 = xs[js * kNR + (col >> 1)];
-          const uint2 x1v = xs[js * kNR + 16 + (col >> 1)];
-          if ((col & 1) == 0) {
-            b0h[q] = x0.x;
-            b0l[q] = x0.y;
-            b1h[q] = x1v.x;
-            b1l[q] = x1v.y;
-          } else {
-            b0h[q] = ((x0.x >> 16) | (x0.x << 16)) ^ 0x80000000u;
-            b0l[q] = ((x0.y >> 16) | (x0.y << 16)) ^ 0x80000000u;
-            b1h[q] = ((x1v.x >> 16) | (x1v.x << 16)) ^ 0x80000000u;
-            b1l[q] = ((x1v.y >> 16) | (x1v.y << 16)) ^ 0x80000000u;
-          }
+          const int slot = min(base + js, Lu - 1);  // beyond the window A is zero
+          const uint2 x0 = xs[slot * kNR + (col >> 1)];
+          const uint2 x1v = xs[slot * kNR + 16 + (col >> 1)];
+          const bool e = col & 1;  // B column 2 r' + e: rows (X1, X2) for E, (X2, -X1) for B
+          b0h[q] = e ? bmode(x0.x) : x0.x;
+          b0l[q] = e ? bmode(x0.y) : x0.y;
+          b1h[q] = e ? bmode(x1v.x) : x1v.x;
+          b1l[q] = e ? bmode(x1v.y) : x1v.y;
         }
         const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah), Al = __builtin_bit_cast(bf16x8, al);
         const bf16x8 B0h = __builtin_bit_cast(bf16x8, b0h), B0l = __builtin_bit_cast(bf16x8, b0l);
@@ -238,34 +275,34 @@ __global__ __launch_bounds__(64 * kWaves) void k_noise_mfma(NoiseArgs n, ScaleAr
         acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, B0h, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, B1h, acc1, 0, 0, 0);
       }
-      __syncthreads();  // xs is regenerated for the next chunk
     }
-    // coefA and wsl are rewritten for the next ring (after the barrier above)
+    __syncthreads();  // xs, coefA and the windows are rewritten for the next ring
   }
 
   // epilogue: summed normalisation per centre, staged for coalesced writes
-  if (tid < kNP) {
+  if (lane < kNP) {
     float f = 1.f;
     if (a.norm != SMART_NORM_RAW) {
-      const double area = a.norm == SMART_NORM_SUMMED_CAP ? s.area_cap : (double)np_occ * s.omega_pix;
-      f = wp > 0.f ? (float)(area * s.inv_theta2 / (double)wp) : 0.f;
+      const double area = a.norm == SMART_NORM_SUMMED_CAP ? s.area_cap : np_occ * s.omega_pix;
+      f = wp > 0.0 ? (float)(area * s.inv_theta2 / wp) : 0.f;
     }
-    fnorm[tid] = f;
+    fnorm[wave][lane] = f;
   }
   __syncthreads();
-  float* cst = reinterpret_cast<float*>(xs);  // [2 kNR][kNP] of this wave
+  float* cst = reinterpret_cast<float*>(xs) + wave * (2 * kNR * kNP);  // [2 kNR][kNP] of this wave
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int row = 8 * (i / 4) + 4 * half + (i % 4);  // centre
-    cst[col * kNP + row] = acc0[i] * fnorm[row];        // column 2 r' + e, r' < 16
-    cst[(32 + col) * kNP + row] = acc1[i] * fnorm[row]; // r' >= 16
+    cst[col * kNP + row] = acc0[i] * fnorm[wave][row];        // column 2 r' + e, r' < 16
+    cst[(32 + col) * kNP + row] = acc1[i] * fnorm[wave][row]; // r' >= 16
   }
   __syncthreads();
-  for (int v = lane; v < 2 * kNR * kNP; v += 64) {
-    const int cidx = v / kNP, p = v % kNP;
-    const int rr = rb * kNR + (cidx >> 1), e = cidx & 1;
-    if (rr < n.n_real)
-      n.out[(((int64_t)a.scale * n.n_real + rr) * 2 + e) * a.n_out + o0 + p] = cst[v];
+  if (active) {
+    for (int v = lane; v < 2 * kNR * kNP; v += 64) {
+      const int ci = v / kNP, pp = v % kNP;
+      const int rr = rg * kNR + (ci >> 1), e = ci & 1;
+      if (rr < n.n_real) n.out[(((int64_t)a.scale * n.n_real + rr) * 2 + e) * a.n_out + o_w + pp] = cst[v];
+    }
   }
 }
 
@@ -278,26 +315,6 @@ __global__ void k_scatter_noise(const float* stage, const int64_t* pos, int64_t 
   const int64_t base = ((int64_t)scale * n_real + r) * 2 * n_out;
   out[base + pos[i]] = stage[i];
   out[base + n_out + pos[i]] = stage[n_sub + i];
-}
-
-// centres of the general tiles: list positions and pixels
-__global__ void k_expand_tiles(const int* tiles, int n_tiles, const int64_t* out_pix, int64_t n_out, int64_t* pos,
-                               int64_t* pix) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)n_tiles * kNP) return;
-  const int64_t o = (int64_t)tiles[i / kNP] * kNP + i % kNP;
-  pos[i] = o < n_out ? o : -1;
-  pix[i] = o < n_out ? out_pix[o] : -1;
-}
-
-__global__ void k_compact(const int64_t* pos, const int64_t* pix, int64_t n, int64_t* pos_out, int64_t* pix_out,
-                          int* count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || pos[i] < 0) return;
-  // order does not matter: every centre is written back to its own position
-  const int k = atomicAdd(count, 1);
-  pos_out[k] = pos[i];
-  pix_out[k] = pix[i];
 }
 
 unsigned grid_of(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
@@ -320,16 +337,69 @@ hipError_t launch_rotate_map(const float4* map, const int* cidx, const float* u,
     }                                                                           \
   } while (0)
 
+// Noise schedule of one scale (built on the first batched call, kept in the
+// plan): eligible segments, stacks in column-major order, the outputs left
+// to the plain path.
+static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, hipStream_t st) {
+  const int N = a.nside_in;
+  const int ncol = (4 * N) / kNP;
+  const int n_rings = 2 * N + 1;
+  const int n_groups = (n_rings + kStack - 1) / kStack;
+  const int64_t n_seg = (int64_t)n_rings * ncol, n_stk = (int64_t)n_groups * ncol;
+  int *flags = nullptr, *covered = nullptr, *cnt = nullptr;
+  int64_t* pos = nullptr;
+  NCHK(hipMalloc((void**)&sc.noise_seg_o, sizeof(int) * n_seg));
+  NCHK(hipMalloc((void**)&sc.noise_stacks, sizeof(int) * (n_stk + 1)));
+  NCHK(hipMallocAsync((void**)&flags, sizeof(int) * (std::max(n_stk, p->n_out) + 1), st));
+  NCHK(hipMallocAsync((void**)&covered, sizeof(int) * (p->n_out + 1), st));
+  NCHK(hipMallocAsync((void**)&cnt, sizeof(int) * 2, st));
+  NCHK(hipMallocAsync((void**)&pos, sizeof(int64_t) * (p->n_out + 1), st));
+  NCHK(hipMemsetAsync(covered, 0, sizeof(int) * (p->n_out + 1), st));
+  hipLaunchKernelGGL(k_noise_segs, dim3(grid_of(n_seg)), dim3(kBlock), 0, st, a, sc.tab(), ncol, sc.noise_seg_o);
+  hipLaunchKernelGGL(k_noise_stacks, dim3(grid_of(n_stk)), dim3(kBlock), 0, st, n_groups, ncol, n_rings,
+                     sc.noise_seg_o, flags, covered);
+  NCHK(hipGetLastError());
+  size_t tb = 0, tb2 = 0;
+  hipcub::CountingInputIterator<int> ids(0);
+  hipcub::CountingInputIterator<int64_t> ids64(0);
+  NCHK(hipcub::DeviceSelect::Flagged(nullptr, tb, ids, flags, sc.noise_stacks, cnt, (int)n_stk, st));
+  NCHK(hipcub::DeviceSelect::Flagged(nullptr, tb2, ids64, flags, pos, cnt + 1, (int)p->n_out, st));
+  if (ensure_temp(p->ctx, std::max(tb, tb2))) return SMART_ENOMEM;
+  tb = p->ctx->temp_bytes;
+  NCHK(hipcub::DeviceSelect::Flagged(p->ctx->d_temp, tb, ids, flags, sc.noise_stacks, cnt, (int)n_stk, st));
+  hipLaunchKernelGGL(k_noise_rest, dim3(grid_of(p->n_out)), dim3(kBlock), 0, st, covered, p->out_pix, p->n_out,
+                     flags);
+  tb = p->ctx->temp_bytes;
+  NCHK(hipcub::DeviceSelect::Flagged(p->ctx->d_temp, tb, ids64, flags, pos, cnt + 1, (int)p->n_out, st));
+  int h[2] = {0, 0};
+  NCHK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+  NCHK(hipStreamSynchronize(st));
+  sc.noise_n_stacks = h[0];
+  sc.noise_n_rest = h[1];
+  sc.noise_ncol = ncol;
+  sc.noise_n_groups = n_groups;
+  if (h[1] > 0) {
+    NCHK(hipMalloc((void**)&sc.noise_rest, sizeof(int64_t) * 2 * (size_t)h[1]));
+    NCHK(hipMemcpyAsync(sc.noise_rest, pos, sizeof(int64_t) * h[1], hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_noise_rest_pix, dim3(grid_of(h[1])), dim3(kBlock), 0, st, sc.noise_rest, h[1], p->out_pix,
+                       sc.noise_rest + h[1]);
+    NCHK(hipGetLastError());
+  }
+  NCHK(hipFreeAsync(flags, st));
+  NCHK(hipFreeAsync(covered, st));
+  NCHK(hipFreeAsync(cnt, st));
+  NCHK(hipFreeAsync(pos, st));
+  sc.noise_built = 1;
+  return SMART_OK;
+}
+
 int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st) {
   smart_data d = p->data;
   const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
   const int ns = (int)p->theta_ap.size();
-  const int n_tiles = (int)((p->n_out + kNP - 1) / kNP);
   if (p->n_out == 0) return SMART_OK;
-  int* work = nullptr;  // 2 counts + 2 lists
-  int64_t* sub = nullptr;
-  NCHK(hipMallocAsync((void**)&work, sizeof(int) * (2 + 2 * (size_t)n_tiles), st));
   for (int k = 0; k < ns; ++k) {
+    PixelSched& sc = *p->sched[k];
     const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);
     PixelArgs a{};
     a.out_pix = p->out_pix;
@@ -343,51 +413,41 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
     a.pix_first = d->pix_first;
     a.norm = norm;
     a.scale = k;
-    int* counts = work;
-    int* lists = work + 2;
-    NCHK(hipMemsetAsync(counts, 0, 2 * sizeof(int), st));
-    hipLaunchKernelGGL(k_classify32, dim3(grid_of(n_tiles)), dim3(kBlock), 0, st, a, s.theta_ap, s.C_ap, n_tiles,
-                       lists, counts);
-    int h[2] = {0, 0};
-    NCHK(hipMemcpyAsync(h, counts, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    NCHK(hipStreamSynchronize(st));
-    NoiseArgs na{};
-    na.a = a;
-    na.u = d_u;
-    na.cidx = d->cidx;
-    na.n_src = d->n_src;
-    na.n_real = n_real;
-    na.n_grp = (n_real + kNR * kWaves - 1) / (kNR * kWaves);
-    na.out = d_out;
-    na.n_scales = ns;
-    na.tiles = lists;
-    if (h[0] > 0) {
-      const dim3 grid((unsigned)((int64_t)h[0] * na.n_grp)), block(64 * kWaves);
-      const bool table = s.filter_kind != SMART_FILTER_POLY;
-      if (table && s.big) hipLaunchKernelGGL((k_noise_mfma<true, true>), grid, block, 0, st, na, s);
-      else if (table) hipLaunchKernelGGL((k_noise_mfma<true, false>), grid, block, 0, st, na, s);
-      else if (s.big) hipLaunchKernelGGL((k_noise_mfma<false, true>), grid, block, 0, st, na, s);
-      else hipLaunchKernelGGL((k_noise_mfma<false, false>), grid, block, 0, st, na, s);
+    if (!sc.noise_built) {
+      const int rc = sc.counts[0] > 0 ? build_noise_sched(p, sc, a, st) : SMART_OK;
+      if (rc) return rc;
+      if (sc.counts[0] == 0) {  // no belt tables: every output takes the plain path
+        sc.noise_n_rest = (int)p->n_out;
+        NCHK(hipMalloc((void**)&sc.noise_rest, sizeof(int64_t) * 2 * (size_t)p->n_out));
+        std::vector<int64_t> pos(p->n_out);
+        for (int64_t i = 0; i < p->n_out; ++i) pos[i] = i;
+        NCHK(hipMemcpy(sc.noise_rest, pos.data(), sizeof(int64_t) * p->n_out, hipMemcpyHostToDevice));
+        NCHK(hipMemcpyAsync(sc.noise_rest + p->n_out, p->out_pix, sizeof(int64_t) * p->n_out,
+                            hipMemcpyDeviceToDevice, st));
+        sc.noise_built = 1;
+      }
+    }
+    if (sc.noise_n_stacks > 0) {
+      NoiseArgs na{};
+      na.a = a;
+      na.t = sc.tab();
+      na.seg_o = sc.noise_seg_o;
+      na.stacks = sc.noise_stacks;
+      na.ncol = sc.noise_ncol;
+      na.n_groups = sc.noise_n_groups;
+      na.u = d_u;
+      na.cidx = d->cidx;
+      na.n_src = d->n_src;
+      na.n_real = n_real;
+      na.n_grp = (n_real + kNR - 1) / kNR;
+      na.out = d_out;
+      const dim3 grid((unsigned)((int64_t)sc.noise_n_stacks * na.n_grp)), block(64 * kStack);
+      hipLaunchKernelGGL(k_noise_stack, grid, block, 0, st, na, s);
       NCHK(hipGetLastError());
     }
-    if (h[1] > 0) {
-      // other tiles: plain pair sums per realisation on the rotated map
-      const int64_t n_exp = (int64_t)h[1] * kNP;
-      int64_t *pos = nullptr, *pix = nullptr, *pos2 = nullptr, *pix2 = nullptr;
-      int* cnt = nullptr;
-      float* stage = nullptr;
-      NCHK(hipMallocAsync((void**)&pos, sizeof(int64_t) * 4 * n_exp, st));
-      pix = pos + n_exp;
-      pos2 = pix + n_exp;
-      pix2 = pos2 + n_exp;
-      NCHK(hipMallocAsync((void**)&cnt, sizeof(int), st));
-      NCHK(hipMemsetAsync(cnt, 0, sizeof(int), st));
-      hipLaunchKernelGGL(k_expand_tiles, dim3(grid_of(n_exp)), dim3(kBlock), 0, st, lists + n_tiles, h[1],
-                         p->out_pix, p->n_out, pos, pix);
-      hipLaunchKernelGGL(k_compact, dim3(grid_of(n_exp)), dim3(kBlock), 0, st, pos, pix, n_exp, pos2, pix2, cnt);
-      int n_sub = 0;
-      NCHK(hipMemcpyAsync(&n_sub, cnt, sizeof(int), hipMemcpyDeviceToHost, st));
-      NCHK(hipStreamSynchronize(st));
+    if (sc.noise_n_rest > 0) {
+      // other outputs: plain pair sums per realisation on the rotated map
+      const int n_sub = sc.noise_n_rest;
       if (p->rot_len < d->n_dense) {
         (void)hipFree(p->rot_map);
         p->rot_map = nullptr;
@@ -395,31 +455,27 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
         NCHK(hipMalloc(&p->rot_map, sizeof(float4) * d->n_dense));
         p->rot_len = d->n_dense;
       }
-      int* subwork = nullptr;
-      NCHK(hipMallocAsync((void**)&stage, sizeof(float) * 5 * (size_t)n_sub, st));
-      NCHK(hipMallocAsync((void**)&subwork, sizeof(int) * pixel_work_ints(n_sub), st));
+      if (!sc.noise_stage) {
+        NCHK(hipMalloc((void**)&sc.noise_stage, sizeof(float) * 5 * (size_t)n_sub));
+        NCHK(hipMalloc((void**)&sc.noise_work, sizeof(int) * pixel_work_ints(n_sub)));
+      }
+      float* stage = sc.noise_stage;
+      int* subwork = sc.noise_work;
       PixelArgs b = a;
-      b.out_pix = pix2;
+      b.out_pix = sc.noise_rest + n_sub;
       b.n_out = n_sub;
       b.map = p->rot_map;
-      b.wn = d->wn;
       b.out = stage;
       b.scale = 0;
       for (int r = 0; r < n_real; ++r) {
         NCHK(launch_rotate_map(d->sums, d->cidx, d_u + (int64_t)r * d->n_src, d->n_dense, p->rot_map, st));
         NCHK(launch_pixel(b, s, SMART_PREC_FP32_GEO64, st, subwork));
-        hipLaunchKernelGGL(k_scatter_noise, dim3(grid_of(n_sub)), dim3(kBlock), 0, st, stage, pos2, n_sub, d_out,
-                           p->n_out, k, n_real, r);
+        hipLaunchKernelGGL(k_scatter_noise, dim3(grid_of(n_sub)), dim3(kBlock), 0, st, stage, sc.noise_rest, n_sub,
+                           d_out, p->n_out, k, n_real, r);
         NCHK(hipGetLastError());
       }
-      NCHK(hipFreeAsync(stage, st));
-      NCHK(hipFreeAsync(subwork, st));
-      NCHK(hipFreeAsync(cnt, st));
-      NCHK(hipFreeAsync(pos, st));
     }
   }
-  NCHK(hipFreeAsync(work, st));
-  (void)sub;
   return SMART_OK;
 }
 

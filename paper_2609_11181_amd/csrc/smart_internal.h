@@ -175,6 +175,14 @@ struct PixelSched {
   double* qc = nullptr;
   double* qs = nullptr;
   float* q2 = nullptr;
+  // batched noise schedule (built on the first batched call; k_noise.hip)
+  int noise_built = 0;
+  int noise_n_stacks = 0, noise_n_rest = 0, noise_ncol = 0, noise_n_groups = 0;
+  int* noise_seg_o = nullptr;      // list position of every eligible belt segment, -1 otherwise
+  int* noise_stacks = nullptr;     // stacks of segments, column-major
+  int64_t* noise_rest = nullptr;   // [2][noise_n_rest]: list positions and pixels of the other outputs
+  float* noise_stage = nullptr;    // [5][noise_n_rest] staging of the plain passes
+  int* noise_work = nullptr;       // queue cursors of the plain passes
   BeltTab tab() const { return BeltTab{head, info, qc, qs, q2}; }
   int* lists(int which) const { return list + (which ? counts[0] : 0); }
   ~PixelSched();
