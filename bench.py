@@ -443,12 +443,17 @@ def main():
     last_plans = keep[-1][1]
     pairs_scale = [p.last_pairs() for p in last_plans]
     pairs = float(sum(pairs_scale))
-    # pairs of the belt tiles (N channel summed over their centres); the rest are general-tile pairs
+    # pairs of the belt items (N channel summed over their centres); the rest are general-tile pairs
     pairs_belt = []
     for k, p in enumerate(last_plans):
-        nb, ng, tiles = p.tiles(0)
-        idx = (tiles[:nb].long()[:, None] * 256 + torch.arange(256, device=dev)).reshape(-1)
-        pairs_belt.append(float(outs[k][0, 4].double()[idx].sum()) if nb else 0.0)
+        belt, _ = p.tiles(0)
+        mark = torch.zeros(n_out + 1, dtype=torch.int32, device=dev)
+        if belt.shape[0]:
+            b = belt.long()
+            mark.index_add_(0, b[:, 0], torch.ones_like(b[:, 0], dtype=torch.int32))
+            mark.index_add_(0, b[:, 0] + b[:, 1], -torch.ones_like(b[:, 0], dtype=torch.int32))
+        sel = torch.cumsum(mark[:n_out], 0) > 0
+        pairs_belt.append(float(outs[k][0, 4].double()[sel].sum()))
     kern_ms = [float(np.mean([events[s][k][0].elapsed_time(events[s][k][1]) for s in range(args.steps)]))
                for k in range(len(scales))]
     value = pairs / (ms_step / 1e3)

@@ -217,12 +217,16 @@ int smart_last_pairs(smart_plan plan, void* stream, double* pairs);
 
 void smart_plan_free(smart_plan plan);
 
-/* Tile schedule of scale `scale` of a pixel-variant FP32 plan: belt and
- * general tile counts (tile t holds list entries [256 t, 256 t + 256)).
- * With d_tiles non-NULL, copies the n_belt + n_general tile indices (belt
- * tiles first) as int32 to device memory d_tiles on `stream`. Other plans
- * report n_belt = 0 and every tile as general. */
-int smart_plan_tiles(smart_plan plan, int scale, int* n_belt, int* n_general, int* d_tiles, void* stream);
+/* Schedule of scale `scale` of a pixel-variant FP32 plan. Belt items are
+ * runs of up to 256 consecutive list entries that are consecutive pixels of
+ * one belt ring (whose discs stay in the belt); general tiles are tiles of
+ * 256 list entries (tile t holds entries [256 t, 256 t + 256)) handled per
+ * centre. Returns the counts; with d_belt non-NULL copies the items as
+ * n_belt (list position, length) int32 pairs, with d_general non-NULL the
+ * n_general tile indices, to device memory on `stream`. Other plans report
+ * no belt items and every tile as general. */
+int smart_plan_tiles(smart_plan plan, int scale, int* n_belt, int* n_general, int* d_belt, int* d_general,
+                     void* stream);
 
 /* Autotuner. For every scale of a pixel-variant FP32 plan, times the launch
  * choices of its pair kernels on the plan's own data (HIP events on

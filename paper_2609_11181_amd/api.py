@@ -180,13 +180,14 @@ class Plan:
         return v.value
 
     def tiles(self, scale: int = 0):
-        """(n_belt, n_general, device int32 tensor of tile indices, belt tiles first)."""
+        """(belt items as an [n, 2] int32 tensor of (list position, length), general tile indices)."""
         nb, ng = C.c_int(), C.c_int()
-        L.check(self.ctx.lib.smart_plan_tiles(self.h, scale, C.byref(nb), C.byref(ng), None, None))
-        t = torch.empty(max(nb.value + ng.value, 1), dtype=torch.int32, device=self.ctx.device)
-        L.check(self.ctx.lib.smart_plan_tiles(self.h, scale, C.byref(nb), C.byref(ng), _ptr(t),
+        L.check(self.ctx.lib.smart_plan_tiles(self.h, scale, C.byref(nb), C.byref(ng), None, None, None))
+        b = torch.empty(max(nb.value, 1), 2, dtype=torch.int32, device=self.ctx.device)
+        g = torch.empty(max(ng.value, 1), dtype=torch.int32, device=self.ctx.device)
+        L.check(self.ctx.lib.smart_plan_tiles(self.h, scale, C.byref(nb), C.byref(ng), _ptr(b), _ptr(g),
                                               _stream(self.ctx.device)))
-        return nb.value, ng.value, t[: nb.value + ng.value]
+        return b[: nb.value], g[: ng.value]
 
     def autotune(self, budget_ms: int = 2000, cache_path=None):
         """Measure and keep the fastest launch choices of every scale (see smart_autotune)."""

@@ -360,28 +360,32 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
   return SMART_OK;
 }
 
-int smart_plan_tiles(smart_plan p, int scale, int* n_belt, int* n_general, int* d_tiles, void* stream) {
+int smart_plan_tiles(smart_plan p, int scale, int* n_belt, int* n_general, int* d_belt, int* d_general,
+                     void* stream) {
   if (!p || !n_belt || !n_general) return fail(SMART_EINVAL, "NULL argument");
   if (scale < 0 || scale >= (int)p->theta_ap.size()) return fail(SMART_EINVAL, "scale out of range");
   int rc;
   if ((rc = set_device(p->ctx))) return rc;
+  hipStream_t st = (hipStream_t)stream;
   const int nt = (int)((p->n_out + 255) / 256);
-  if (p->sched.empty() || !p->sched[scale]->list) {
+  if (p->sched.empty() || !p->sched[scale]->general) {
     *n_belt = 0;
     *n_general = nt;
-    if (d_tiles && nt > 0) {
+    if (d_general && nt > 0) {
       std::vector<int> ids(nt);
       for (int t = 0; t < nt; ++t) ids[t] = t;
-      CHECK_HIP(hipMemcpyAsync(d_tiles, ids.data(), sizeof(int) * nt, hipMemcpyHostToDevice, (hipStream_t)stream));
-      CHECK_HIP(hipStreamSynchronize((hipStream_t)stream));
+      CHECK_HIP(hipMemcpyAsync(d_general, ids.data(), sizeof(int) * nt, hipMemcpyHostToDevice, st));
+      CHECK_HIP(hipStreamSynchronize(st));
     }
     return SMART_OK;
   }
   const smart::PixelSched& sc = *p->sched[scale];
   *n_belt = sc.counts[0];
   *n_general = sc.counts[1];
-  if (d_tiles && nt > 0)
-    CHECK_HIP(hipMemcpyAsync(d_tiles, sc.list, sizeof(int) * nt, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  if (d_belt && sc.counts[0] > 0)
+    CHECK_HIP(hipMemcpyAsync(d_belt, sc.belt, sizeof(int2) * sc.counts[0], hipMemcpyDeviceToDevice, st));
+  if (d_general && sc.counts[1] > 0)
+    CHECK_HIP(hipMemcpyAsync(d_general, sc.general, sizeof(int) * sc.counts[1], hipMemcpyDeviceToDevice, st));
   return SMART_OK;
 }
 

@@ -67,6 +67,16 @@ __global__ void k_iota(int* v, int n) {
   if (i < n) v[i] = i;
 }
 
+__global__ void k_is_zero(const int* v, int* z, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = v[i] == 0 ? 1 : 0;
+}
+
+__global__ void k_gather_items(const int2* items, const int* slots, int n, int2* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = items[slots[i]];
+}
+
 struct Sum2i {
   __host__ __device__ int2 operator()(const int2& x, const int2& y) const { return make_int2(x.x + y.x, x.y + y.y); }
 };
@@ -134,12 +144,13 @@ __global__ __launch_bounds__(kBlock) void k_belt_fill(PixelArgs a, ScaleArgs s, 
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_pixel_belt(PixelArgs a, ScaleArgs s, BeltTab t, const int* tiles,
-                                                       int n_tiles, int* cursors) {
+__global__ __launch_bounds__(kBlock) void k_pixel_belt(PixelArgs a, ScaleArgs s, BeltTab t, const int2* items,
+                                                       int n_items, int* cursors) {
   for (;;) {
-    const int item = next_tile_wave(cursors, n_tiles);
+    const int item = next_tile_wave(cursors, n_items);
     if (item < 0) break;
-    belt_tile(a, s, t, (int64_t)tiles[item] * kBlock);
+    const int2 it = items[item];
+    belt_tile(a, s, t, it.x, it.y);
   }
 }
 
@@ -155,7 +166,7 @@ int belt_per_cu() {
 
 int belt_blocks_max() { return belt_per_cu(); }
 
-hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int* list, int count,
+hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int2* list, int count,
                        int* cursors, int blocks_per_cu, hipStream_t st) {
   const int per_cu = belt_per_cu();
   const int grid = device_cus() * (blocks_per_cu > 0 ? std::min(blocks_per_cu, per_cu) : per_cu);
@@ -164,14 +175,15 @@ hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t,
 }
 
 PixelSched::~PixelSched() {
-  (void)hipFree(list);
+  (void)hipFree(belt);
+  (void)hipFree(general);
   (void)hipFree(cursors);
   (void)hipFree(head);
   (void)hipFree(info);
   (void)hipFree(qc);
   (void)hipFree(qs);
   (void)hipFree(q2);
-  (void)hipFree(noise_seg_o);
+  (void)hipFree(noise_seg);
   (void)hipFree(noise_stacks);
   (void)hipFree(noise_rest);
   (void)hipFree(noise_stage);
@@ -186,6 +198,8 @@ PixelSched::~PixelSched() {
       (void)hipFree(flags);                                                            \
       (void)hipFree(keys);                                                             \
       (void)hipFree(ids);                                                              \
+      (void)hipFree(gflags);                                                           \
+      (void)hipFree(items);                                                            \
       (void)hipFree(cnts);                                                             \
       (void)hipFree(offs);                                                             \
       set_error(std::string("plan schedule: ") + hipGetErrorString(e_) + " at " #x); \
@@ -210,60 +224,77 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   a.ring_hi = d->ring_hi;
   a.pix_first = d->pix_first;
   int* used = nullptr;
-  int* flags = nullptr;
+  int* flags = nullptr;      // per tile: number of belt runs (0: general tile)
   int2* cnts = nullptr;
   int2* offs = nullptr;
-  uint64_t* keys = nullptr;  // keys, sorted keys
-  int* ids = nullptr;        // 0 .. nt - 1
+  uint64_t* keys = nullptr;  // keys, sorted keys of the kRuns item slots per tile
+  int* ids = nullptr;        // slot ids, sorted slot ids
+  int2* items = nullptr;     // item slots
+  int* gflags = nullptr;     // per tile: 1 when general
   const int nb = 2 * N + 1;  // belt rings N .. 3N
   const int nt = (int)((p->n_out + kBlock - 1) / kBlock);
+  const int ns = kRuns * nt;  // item slots
   sc->n_tiles = nt;
-  BCHK(hipMalloc((void**)&sc->list, sizeof(int) * (nt + 1)));
-  BCHK(hipMalloc((void**)&sc->cursors, sizeof(int) * 33));  // cursors, then the belt tile count
+  BCHK(hipMalloc((void**)&sc->cursors, sizeof(int) * 34));  // cursors, then the two counts
+  BCHK(hipMalloc((void**)&sc->general, sizeof(int) * (nt + 1)));
   BCHK(hipMalloc((void**)&flags, sizeof(int) * (nt + 1)));
-  BCHK(hipMalloc((void**)&keys, sizeof(uint64_t) * 2 * (nt + 1)));
-  BCHK(hipMalloc((void**)&ids, sizeof(int) * (nt + 1)));
+  BCHK(hipMalloc((void**)&gflags, sizeof(int) * (nt + 1)));
+  BCHK(hipMalloc((void**)&keys, sizeof(uint64_t) * 2 * (ns + 1)));
+  BCHK(hipMalloc((void**)&ids, sizeof(int) * 2 * (ns + 1)));
+  BCHK(hipMalloc((void**)&items, sizeof(int2) * (ns + 1)));
   BCHK(hipMalloc((void**)&used, sizeof(int) * nb));
   BCHK(hipMalloc((void**)&cnts, sizeof(int2) * nb));
   BCHK(hipMalloc((void**)&offs, sizeof(int2) * nb));
   BCHK(hipMalloc((void**)&sc->head, sizeof(int2) * nb));
   BCHK(hipMemsetAsync(used, 0, sizeof(int) * nb, st));
-  // order of the schedule: belt tiles column-major (tiles of one azimuth
-  // column on consecutive rings share their disc rows, so the tiles in flight
-  // on one XCD stay within its L2), then the general tiles in list order
-  launch_classify(a, s.theta_ap, nt, flags, used, keys, st);
+  // order of the schedule: belt items column-major (items of one azimuth
+  // column on consecutive rings share their disc rows, so the items in flight
+  // on one XCD stay within its L2); general tiles in list order
+  launch_classify(a, s.theta_ap, nt, flags, items, keys, used, st);
   BCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_iota, dim3((nt + kBlock - 1) / kBlock), dim3(kBlock), 0, st, ids, nt);
-  size_t tb = 0, tb2 = 0, tb3 = 0;
-  BCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, keys + nt, ids, sc->list, nt, 0, 57, st));
+  hipLaunchKernelGGL(k_iota, dim3((ns + kBlock - 1) / kBlock), dim3(kBlock), 0, st, ids, ns);
+  hipLaunchKernelGGL(k_is_zero, dim3((nt + kBlock - 1) / kBlock), dim3(kBlock), 0, st, flags, gflags, nt);
+  size_t tb = 0, tb2 = 0, tb3 = 0, tb4 = 0;
+  hipcub::CountingInputIterator<int> tile_ids(0);
+  BCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, keys + ns, ids, ids + ns, ns, 0, 57, st));
   BCHK(hipcub::DeviceReduce::Sum(nullptr, tb3, flags, sc->cursors + 32, nt, st));
+  BCHK(hipcub::DeviceSelect::Flagged(nullptr, tb4, tile_ids, gflags, sc->general, sc->cursors + 33, nt, st));
   hipLaunchKernelGGL(k_belt_size, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.theta_ap, s.C_ap, used,
                      cnts);
   BCHK(hipGetLastError());
   BCHK(hipcub::DeviceScan::ExclusiveScan(nullptr, tb2, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
-  if (ensure_temp(p->ctx, std::max(tb, std::max(tb2, tb3)))) {
+  if (ensure_temp(p->ctx, std::max(std::max(tb, tb4), std::max(tb2, tb3)))) {
     (void)hipFree(used);
     (void)hipFree(flags);
+    (void)hipFree(gflags);
     (void)hipFree(cnts);
     (void)hipFree(offs);
     (void)hipFree(keys);
     (void)hipFree(ids);
+    (void)hipFree(items);
     return SMART_ENOMEM;
   }
   tb = p->ctx->temp_bytes;
-  BCHK(hipcub::DeviceRadixSort::SortPairs(p->ctx->d_temp, tb, keys, keys + nt, ids, sc->list, nt, 0, 57, st));
+  BCHK(hipcub::DeviceRadixSort::SortPairs(p->ctx->d_temp, tb, keys, keys + ns, ids, ids + ns, ns, 0, 57, st));
   tb = p->ctx->temp_bytes;
   BCHK(hipcub::DeviceReduce::Sum(p->ctx->d_temp, tb, flags, sc->cursors + 32, nt, st));
   tb = p->ctx->temp_bytes;
+  BCHK(hipcub::DeviceSelect::Flagged(p->ctx->d_temp, tb, tile_ids, gflags, sc->general, sc->cursors + 33, nt, st));
+  tb = p->ctx->temp_bytes;
   BCHK(hipcub::DeviceScan::ExclusiveScan(p->ctx->d_temp, tb, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
-  int n_belt = 0;
+  int counts[2] = {0, 0};
   int2 last_c, last_o;
-  BCHK(hipMemcpyAsync(&n_belt, sc->cursors + 32, sizeof(int), hipMemcpyDeviceToHost, st));
+  BCHK(hipMemcpyAsync(counts, sc->cursors + 32, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   BCHK(hipMemcpyAsync(&last_c, cnts + nb - 1, sizeof(int2), hipMemcpyDeviceToHost, st));
   BCHK(hipMemcpyAsync(&last_o, offs + nb - 1, sizeof(int2), hipMemcpyDeviceToHost, st));
   BCHK(hipStreamSynchronize(st));
-  sc->counts[0] = n_belt;
-  sc->counts[1] = nt - n_belt;
+  sc->counts[0] = counts[0];
+  sc->counts[1] = counts[1];
+  BCHK(hipMalloc((void**)&sc->belt, sizeof(int2) * (counts[0] + 1)));
+  if (counts[0] > 0)
+    hipLaunchKernelGGL(k_gather_items, dim3((counts[0] + kBlock - 1) / kBlock), dim3(kBlock), 0, st, items,
+                       ids + ns, counts[0], sc->belt);
+  BCHK(hipGetLastError());
   // out-of-line per-ring set-up pays off for discs of many members per ring
   sc->general_ool = s.theta_ap * (double)N >= 16.0 * 0.75 ? 1 : 0;
   const int n_info = last_o.x + last_c.x, n_coef = last_o.y + last_c.y;
@@ -284,8 +315,10 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   BCHK(hipStreamSynchronize(st));  // the scratch below is freed next
   (void)hipFree(used);
   (void)hipFree(flags);
+  (void)hipFree(gflags);
   (void)hipFree(keys);
   (void)hipFree(ids);
+  (void)hipFree(items);
   (void)hipFree(cnts);
   (void)hipFree(offs);
   return SMART_OK;

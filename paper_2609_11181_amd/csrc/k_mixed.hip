@@ -4,8 +4,8 @@
 //
 // Each (plan, scale) is a job whose tiles were classified at plan creation
 // (belt tiles with their ring tables, general tiles). Work items are
-// wave-sized: a whole belt tile (256 centres, four per lane) or a quarter of
-// a general tile (64 centres, one per lane). The host orders the item groups
+// wave-sized: a belt item (a run of up to 256 centres, four per lane) or a
+// quarter of a general tile (64 centres, one per lane). The host orders the item groups
 // by estimated cost per item, most expensive first (a longest-processing-time
 // order, so that the small items fill the tail of the launch), and every wave
 // of one persistent kernel takes items from one global queue. Every item runs
@@ -33,15 +33,17 @@ struct MixJob {
   BeltTab t;
 };
 
-// items[i] = (job, tile, kind, part): kind 0 = belt tile, 1 = quarter `part`
-// of a general tile (each listed general tile expands into four items)
-__global__ void k_fill_items(const int* list, int count, int job, int kind, int4* items) {
+// items[i] = (job, list position, 0, length) of a belt item, or
+// (job, tile, 1, part) of quarter `part` of a general tile (each general
+// tile expands into four items)
+__global__ void k_fill_belt(const int2* list, int count, int job, int4* items) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (kind == 0) {
-    if (i < count) items[i] = make_int4(job, list[i], 0, 0);
-  } else {
-    if (i < 4 * count) items[i] = make_int4(job, list[i >> 2], 1, i & 3);
-  }
+  if (i < count) items[i] = make_int4(job, list[i].x, 0, list[i].y);
+}
+
+__global__ void k_fill_general(const int* list, int count, int job, int4* items) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 4 * count) items[i] = make_int4(job, list[i >> 2], 1, i & 3);
 }
 
 template <bool TABLE, bool BIG>
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_mixed(const MixJob* jobs, const int4
     const int4 w = items[it];
     const MixJob& J = jobs[w.x];
     if (w.z == 0) {
-      belt_tile(J.a, J.s, J.t, (int64_t)w.y * kBlock);
+      belt_tile(J.a, J.s, J.t, w.y, w.w);
     } else {
       const bool table = J.s.filter_kind != SMART_FILTER_POLY;
       if (table && J.s.big) general_quarter<true, true>(J, w.y, w.w);
@@ -91,7 +93,7 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
   // jobs and their item groups
   struct Grp {
     int job, kind, count;
-    const int* list;
+    const void* list;
     double cost;  // estimated cost of one item
   };
   std::vector<MixJob> jobs;
@@ -122,8 +124,8 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
       jobs.push_back(J);
       const double members = 2.0 * M_PI * (1.0 - cos(P->theta_ap[k])) / omega;  // sources per disc
       // a belt pair costs about an eighth of a general pair
-      if (sc.counts[0] > 0) groups.push_back({j, 0, sc.counts[0], sc.lists(0), 256.0 * members});
-      if (sc.counts[1] > 0) groups.push_back({j, 1, sc.counts[1], sc.lists(1), 8.0 * 64.0 * members});
+      if (sc.counts[0] > 0) groups.push_back({j, 0, sc.counts[0], sc.belt, 256.0 * members});
+      if (sc.counts[1] > 0) groups.push_back({j, 1, sc.counts[1], sc.general, 8.0 * 64.0 * members});
     }
   }
   if (groups.empty()) return SMART_OK;
@@ -145,8 +147,12 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
   int64_t off = 0;
   for (const Grp& g : groups) {
     const int n = g.kind == 0 ? g.count : 4 * g.count;
-    hipLaunchKernelGGL(k_fill_items, dim3(grid_of(n)), dim3(kBlock), 0, st, g.list, g.count, g.job, g.kind,
-                       items + off);
+    if (g.kind == 0)
+      hipLaunchKernelGGL(k_fill_belt, dim3(grid_of(n)), dim3(kBlock), 0, st, (const int2*)g.list, g.count, g.job,
+                         items + off);
+    else
+      hipLaunchKernelGGL(k_fill_general, dim3(grid_of(n)), dim3(kBlock), 0, st, (const int*)g.list, g.count, g.job,
+                         items + off);
     off += n;
   }
   MCHK(hipGetLastError());

@@ -59,14 +59,16 @@ __global__ void k_rotate(const float4* map, const int* cidx, const float* u, int
 
 // Segment (belt ring N + i, column c: pixels 32c .. 32c + 31 of the ring) is
 // eligible when its ring has a belt table whose windows hold at most kCntMax
-// members, and its 32 pixels are consecutive entries of the (sorted) output
-// list; seg_o = list position of its first pixel, or -1.
-__global__ void k_noise_segs(PixelArgs a, BeltTab t, int ncol, int* seg_o) {
+// members and the (sorted) output list holds a run of its pixels
+// [32c + a, 32c + b) as consecutive entries: seg = (list position of pixel
+// 32c + a, a, b), or o = -1. Pixels of the segment outside the run take the
+// plain path.
+__global__ void k_noise_segs(PixelArgs a, BeltTab t, int ncol, int4* seg) {
   const int N = a.nside_in;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)(2 * N + 1) * ncol) return;
   const int i = (int)(id / ncol), c = (int)(id % ncol);
-  int o = -1;
+  int4 r = make_int4(-1, 0, 0, 0);
   const int first = t.head[i].x, nr = t.head[i].y;
   bool ok = nr > 0;
   for (int k = 0; ok && k < nr; ++k) ok = t.info[first + k].z <= kCntMax;
@@ -78,16 +80,19 @@ __global__ void k_noise_segs(PixelArgs a, BeltTab t, int ncol, int* seg_o) {
       if (a.out_pix[m] < p0) l = m + 1;
       else h = m;
     }
-    ok = l + kNP <= a.n_out;
-    for (int k = 0; ok && k < kNP; ++k) ok = a.out_pix[l + k] == p0 + k;
-    if (ok) o = (int)l;
+    if (l < a.n_out && a.out_pix[l] < p0 + kNP) {
+      const int a0 = (int)(a.out_pix[l] - p0);
+      int b0 = a0 + 1;
+      while (b0 < kNP && l + (b0 - a0) < a.n_out && a.out_pix[l + (b0 - a0)] == p0 + b0) ++b0;
+      r = make_int4((int)l, a0, b0, 0);
+    }
   }
-  seg_o[id] = o;
+  seg[id] = r;
 }
 
 // Stack (column c, ring group g): flag when any of its segments is eligible,
 // and mark the list entries its segments cover.
-__global__ void k_noise_stacks(int n_groups, int ncol, int n_rings, const int* seg_o, int* flags, int* covered) {
+__global__ void k_noise_stacks(int n_groups, int ncol, int n_rings, const int4* seg, int* flags, int* covered) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)n_groups * ncol) return;
   const int c = (int)(id / n_groups), g = (int)(id % n_groups);  // column-major order
@@ -95,10 +100,10 @@ __global__ void k_noise_stacks(int n_groups, int ncol, int n_rings, const int* s
   for (int w = 0; w < kStack; ++w) {
     const int i = kStack * g + w;
     if (i >= n_rings) break;
-    const int o = seg_o[(int64_t)i * ncol + c];
-    if (o >= 0) {
+    const int4 sg = seg[(int64_t)i * ncol + c];
+    if (sg.x >= 0) {
       any = 1;
-      for (int k = 0; k < kNP; ++k) covered[o + k] = 1;
+      for (int k = 0; k < sg.z - sg.y; ++k) covered[sg.x + k] = 1;
     }
   }
   flags[id] = any;
@@ -118,7 +123,7 @@ __global__ void k_noise_rest_pix(const int64_t* pos, int n, const int64_t* out_p
 struct NoiseArgs {
   PixelArgs a;
   BeltTab t;
-  const int* seg_o;   // [(2N+1) * ncol]
+  const int4* seg;    // [(2N+1) * ncol]: (list position, first, end) of each segment's run
   const int* stacks;  // column * n_groups + group
   int ncol, n_groups;
   const float* u;     // [n_real][n_src]
@@ -162,7 +167,8 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
   const int rg = blockIdx.x % n.n_grp;  // realisation block
   const int c = sid / n.n_groups, g = sid % n.n_groups;
   const int iw = kStack * g + wave;     // belt ring index of this wave (ring N + iw)
-  const int o_w = iw <= 2 * N ? n.seg_o[(int64_t)iw * n.ncol + c] : -1;
+  const int4 sg = iw <= 2 * N ? n.seg[(int64_t)iw * n.ncol + c] : make_int4(-1, 0, 0, 0);
+  const int o_w = sg.x;
   const bool active = o_w >= 0;
   const int hfirst = active ? n.t.head[iw].x : 0, hnr = active ? n.t.head[iw].y : 0;
   const int lo_w = active ? n.t.info[hfirst].x : 0x7fffffff;
@@ -297,11 +303,12 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
     cst[(32 + col) * kNP + row] = acc1[i] * fnorm[wave][row]; // r' >= 16
   }
   __syncthreads();
-  if (active) {
+  if (active) {  // centres sg.y .. sg.z - 1 of the segment are list entries o_w, o_w + 1, ...
     for (int v = lane; v < 2 * kNR * kNP; v += 64) {
       const int ci = v / kNP, pp = v % kNP;
       const int rr = rg * kNR + (ci >> 1), e = ci & 1;
-      if (rr < n.n_real) n.out[(((int64_t)a.scale * n.n_real + rr) * 2 + e) * a.n_out + o_w + pp] = cst[v];
+      if (rr < n.n_real && pp >= sg.y && pp < sg.z)
+        n.out[(((int64_t)a.scale * n.n_real + rr) * 2 + e) * a.n_out + o_w + (pp - sg.y)] = cst[v];
     }
   }
 }
@@ -348,16 +355,16 @@ static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, h
   const int64_t n_seg = (int64_t)n_rings * ncol, n_stk = (int64_t)n_groups * ncol;
   int *flags = nullptr, *covered = nullptr, *cnt = nullptr;
   int64_t* pos = nullptr;
-  NCHK(hipMalloc((void**)&sc.noise_seg_o, sizeof(int) * n_seg));
+  NCHK(hipMalloc((void**)&sc.noise_seg, sizeof(int4) * n_seg));
   NCHK(hipMalloc((void**)&sc.noise_stacks, sizeof(int) * (n_stk + 1)));
   NCHK(hipMallocAsync((void**)&flags, sizeof(int) * (std::max(n_stk, p->n_out) + 1), st));
   NCHK(hipMallocAsync((void**)&covered, sizeof(int) * (p->n_out + 1), st));
   NCHK(hipMallocAsync((void**)&cnt, sizeof(int) * 2, st));
   NCHK(hipMallocAsync((void**)&pos, sizeof(int64_t) * (p->n_out + 1), st));
   NCHK(hipMemsetAsync(covered, 0, sizeof(int) * (p->n_out + 1), st));
-  hipLaunchKernelGGL(k_noise_segs, dim3(grid_of(n_seg)), dim3(kBlock), 0, st, a, sc.tab(), ncol, sc.noise_seg_o);
+  hipLaunchKernelGGL(k_noise_segs, dim3(grid_of(n_seg)), dim3(kBlock), 0, st, a, sc.tab(), ncol, sc.noise_seg);
   hipLaunchKernelGGL(k_noise_stacks, dim3(grid_of(n_stk)), dim3(kBlock), 0, st, n_groups, ncol, n_rings,
-                     sc.noise_seg_o, flags, covered);
+                     sc.noise_seg, flags, covered);
   NCHK(hipGetLastError());
   size_t tb = 0, tb2 = 0;
   hipcub::CountingInputIterator<int> ids(0);
@@ -431,7 +438,7 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
       NoiseArgs na{};
       na.a = a;
       na.t = sc.tab();
-      na.seg_o = sc.noise_seg_o;
+      na.seg = sc.noise_seg;
       na.stacks = sc.noise_stacks;
       na.ncol = sc.noise_ncol;
       na.n_groups = sc.noise_n_groups;

@@ -36,40 +36,78 @@ namespace smart {
 
 namespace {
 
-// One wave per tile: the lanes compare the tile's 256 list entries with
-// consecutive pixel indices, then every lane takes the same decision.
-__global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_ap, int n_tiles, int* flags,
-                                                     int* used, uint64_t* keys) {
+// A belt ring whose discs stay inside the belt and span at most kRingCap rings.
+__device__ inline bool belt_ring_ok(const PixelArgs& a, double theta_ap, int rp) {
+  if (a.nside_in != a.nside_out || rp < a.nside_in || rp > 3 * a.nside_in) return false;
+  const Ring R = ring_info(a.nside_out, rp);
+  int lo, hi;
+  ring_span(a.nside_in, atan2(R.s, R.z), theta_ap, &lo, &hi);
+  return lo >= a.nside_in && hi <= 3 * a.nside_in && hi - lo + 1 <= kRingCap;
+}
+
+// One wave per tile. The tile's list entries are cut into runs of
+// consecutive pixels of one ring; when there are at most kRuns runs and each
+// lies on a qualifying belt ring, the tile becomes kRuns belt items (list
+// position, length) with their schedule keys (column-major: azimuth column
+// of 256 pixels, then ring), else it is a general tile. Every qualifying
+// belt ring that holds an output gets a table (the batched noise path also
+// uses the tables of rings without belt items): every entry lies in a run,
+// and the ring of each run is checked at the run's first entry.
+__global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_ap, int n_tiles, int* nrun,
+                                                     int2* items, uint64_t* keys, int* used) {
   const int t = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= n_tiles) return;
   const int64_t o0 = (int64_t)t * kBlock;
-  bool ok = o0 + kBlock <= a.n_out && a.nside_in == a.nside_out;
-  int rp = 0, ip = 0;
-  if (ok) {
-    const int64_t p0 = a.out_pix[o0];
-    bool run = true;
+  const int64_t oe = min(o0 + kBlock, a.n_out);
+  const bool same_grid = a.nside_in == a.nside_out;
+  uint64_t starts[kBlock / 64];
+  bool bad = false;  // a run start on a ring that does not qualify
 #pragma unroll
-    for (int k = 0; k < kBlock / 64; ++k) run = run && a.out_pix[o0 + lane + 64 * k] == p0 + lane + 64 * k;
-    ok = __all(run);
-    if (ok) {
-      pixel_ring(a.nside_out, p0, &rp, &ip);
-      const Ring R = ring_info(a.nside_out, rp);
-      ok = ip + kBlock <= R.n && R.n == 4 * a.nside_in;
-      if (ok) {
-        int lo, hi;
-        ring_span(a.nside_in, atan2(R.s, R.z), theta_ap, &lo, &hi);
-        ok = lo >= a.nside_in && hi <= 3 * a.nside_in && hi - lo + 1 <= kRingCap;
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const int64_t pos = o0 + lane + 64 * k;
+    bool st = false;
+    if (pos < oe) {
+      const int64_t p = a.out_pix[pos];
+      int rl, il;
+      pixel_ring(a.nside_out, p, &rl, &il);
+      st = pos == o0 || a.out_pix[pos - 1] + 1 != p || il == 0;
+      if (st) {
+        if (same_grid && belt_ring_ok(a, theta_ap, rl)) used[rl - a.nside_in] = 1;
+        else bad = true;
       }
     }
+    starts[k] = __ballot(st);
   }
+  const bool any_bad = __any(bad);
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) n += __popcll(starts[k]);
+  const int runs = (!any_bad && n <= kRuns) ? n : 0;
   if (lane == 0) {
-    flags[t] = ok ? 1 : 0;
-    if (ok) used[rp - a.nside_in] = 1;
-    // belt tiles column-major (azimuth column of 256 pixels, then ring), then
-    // the general tiles in list order
-    keys[t] = ok ? ((uint64_t)(ip / kBlock) << 40) | ((uint64_t)rp << 24) | (uint64_t)(t & 0xffffff)
-                 : (1ull << 56) | (uint64_t)t;
+    nrun[t] = runs;
+    int r = 0;
+    int64_t prev = -1;
+    for (int k = 0; k < kBlock / 64; ++k) {
+      uint64_t m = starts[k];
+      while (m) {
+        const int bit = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int64_t pos = o0 + 64 * k + bit;
+        if (r < kRuns && runs > 0) {
+          if (prev >= 0) items[t * kRuns + r - 1].y = (int)(pos - prev);
+          int rp, ip;
+          pixel_ring(a.nside_out, a.out_pix[pos], &rp, &ip);
+          items[t * kRuns + r] = make_int2((int)pos, 0);
+          keys[t * kRuns + r] = ((uint64_t)(ip / kBlock) << 40) | ((uint64_t)rp << 24) |
+                                (uint64_t)((t * kRuns + r) & 0xffffff);
+        }
+        prev = pos;
+        ++r;
+      }
+    }
+    if (runs > 0) items[t * kRuns + runs - 1].y = (int)(oe - prev);
+    for (int q = runs; q < kRuns; ++q) keys[t * kRuns + q] = (1ull << 56) | (uint64_t)(t * kRuns + q);
   }
 }
 
@@ -421,20 +459,20 @@ hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const Pixe
   if (a.n_out > 0) hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, sc.cursors, 32);
   if (ev) e = hipEventRecord(ev[0], st);
   if (e == hipSuccess && a.n_out > 0 && sc.counts[0] > 0 && (kinds & 1))
-    e = launch_belt(a, s, sc.tab(), sc.lists(0), sc.counts[0], sc.cursors, sc.belt_blocks, st);
+    e = launch_belt(a, s, sc.tab(), sc.belt, sc.counts[0], sc.cursors, sc.belt_blocks, st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
   if (e == hipSuccess && a.n_out > 0 && sc.counts[1] > 0 && (kinds & 2))
-    e = launch_general(a, s, st, sc.lists(1), sc.counts[1], sc.cursors + 16, sc.general_ool, sc.general_blocks);
+    e = launch_general(a, s, st, sc.general, sc.counts[1], sc.cursors + 16, sc.general_ool, sc.general_blocks);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
   return e;
 }
 
-void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* flags, int* used, uint64_t* keys,
-                     hipStream_t st) {
+void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* nrun, int2* items, uint64_t* keys,
+                     int* used, hipStream_t st) {
   const unsigned blocks = (unsigned)((n_tiles + kBlock / 64 - 1) / (kBlock / 64));
   if (n_tiles > 0)
-    hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(kBlock), 0, st, a, theta_ap, n_tiles, flags, used, keys);
+    hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(kBlock), 0, st, a, theta_ap, n_tiles, nrun, items, keys, used);
 }
 
 size_t pixel_work_ints(int64_t n_out) {

@@ -201,8 +201,10 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
 
 // ---- pixel variant, mixed precision: belt tile ------------------------------------
 //
-// One belt tile (256 consecutive centres o0 .. o0 + 255 of a belt ring) on one
-// wave: lane l takes the four centres o0 + 4 l + c, c = 0..3. Member k of
+// One belt item (a run of len <= 256 consecutive centres o0 .. o0 + len - 1
+// of a belt ring) on one wave: lane l takes the four centres o0 + 4 l + c,
+// c = 0..3 (those past the run are computed on the ring's next pixels and
+// dropped). Member k of
 // table ring i is source j0 + c + k of that ring for centre c (j0 = first
 // pixel of the window of the lane's first centre), so the lane slides a
 // window of four source records along the ring and every record it loads
@@ -307,7 +309,8 @@ __device__ __forceinline__ void belt_ring(const cdouble_t* qc, const cdouble_t* 
   A.flush_v();
 }
 
-__device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s, const BeltTab& T, int64_t o0) {
+__device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s, const BeltTab& T, int64_t o0,
+                                          int len = kBlock) {
   const int lane = threadIdx.x & 63;
   const int N = a.nside_in, n = 4 * N;
   int rp, ip0;
@@ -354,6 +357,7 @@ __device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
+    if (4 * lane + c >= len) break;  // centres past a short run are computed but not written
     Acc64 t;
     t.se = A.se[c];
     t.sb = A.sb[c];

@@ -163,9 +163,10 @@ struct BeltTab {
 // memory.
 struct PixelSched {
   int n_tiles = 0;
-  int* list = nullptr;      // belt tiles in order, then the general tiles
+  int2* belt = nullptr;     // belt items (list position, length <= 256): runs of one belt ring, column-major
+  int* general = nullptr;   // general tiles (tile t = list entries [256 t, 256 t + 256)), ascending
   int* cursors = nullptr;   // queue cursors: [0, 16) belt kernel, [16, 32) general kernel
-  int counts[2] = {0, 0};   // belt and general tile counts
+  int counts[2] = {0, 0};   // belt items, general tiles
   // launch choices (defaults from the disc size; smart_autotune measures them)
   int general_ool = 0;      // general kernel with out-of-line per-ring set-up
   int belt_blocks = 0;      // persistent blocks per CU (0: occupancy maximum)
@@ -178,13 +179,12 @@ struct PixelSched {
   // batched noise schedule (built on the first batched call; k_noise.hip)
   int noise_built = 0;
   int noise_n_stacks = 0, noise_n_rest = 0, noise_ncol = 0, noise_n_groups = 0;
-  int* noise_seg_o = nullptr;      // list position of every eligible belt segment, -1 otherwise
+  int4* noise_seg = nullptr;       // per belt segment: (list position of its run, first, end), or -1
   int* noise_stacks = nullptr;     // stacks of segments, column-major
   int64_t* noise_rest = nullptr;   // [2][noise_n_rest]: list positions and pixels of the other outputs
   float* noise_stage = nullptr;    // [5][noise_n_rest] staging of the plain passes
   int* noise_work = nullptr;       // queue cursors of the plain passes
   BeltTab tab() const { return BeltTab{head, info, qc, qs, q2}; }
-  int* lists(int which) const { return list + (which ? counts[0] : 0); }
   ~PixelSched();
 };
 
@@ -193,11 +193,12 @@ struct PixelSched {
 // d_work: device scratch of pixel_work_ints(n_out) ints (queue cursors).
 hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, hipStream_t st, int* d_work);
 size_t pixel_work_ints(int64_t n_out);
-// Flags the belt tiles among the tiles of 256 list entries (flags[t] = 1),
-// sets used[rp - nside] = 1 for the ring of every belt tile and writes the
-// schedule order key of every tile (belt tiles column-major, then general).
-void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* flags, int* used, uint64_t* keys,
-                     hipStream_t st);
+// Runs of every tile of 256 list entries (k_classify): nrun[t] belt items
+// (0: general tile) in items[kRuns t ..] with their sort keys, and
+// used[rp - nside] = 1 for every belt ring that gets a table.
+constexpr int kRuns = 4;
+void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* nrun, int2* items, uint64_t* keys,
+                     int* used, hipStream_t st);
 // Scheduled path: belt tiles through the tables, general tiles as above.
 // ev: NULL, or 4 events recorded around the belt and the general kernel;
 // kinds: bit 0 runs the belt kernel, bit 1 the general kernel.
@@ -208,7 +209,7 @@ int belt_blocks_max();
 int general_blocks_max(const ScaleArgs& s, int ool);
 // belt kernels (k_belt.hip)
 int build_pixel_sched(smart_plan p, int scale, hipStream_t st, PixelSched* sc);
-hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int* list, int count,
+hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int2* items, int count,
                        int* cursors, int blocks_per_cu, hipStream_t st);
 // Compute units of the current device.
 int device_cus();

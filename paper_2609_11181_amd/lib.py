@@ -56,7 +56,7 @@ _SIGS = {
     "smart_plan_free": (None, [_vp]),
     "smart_noise_batch": (_int, [_vp, _vp, _int, _int, _int, _vp, _vp]),
     "smart_mixed_batch": (_int, [_vp, _int, C.POINTER(_vp), C.POINTER(_int), C.POINTER(_vp), _vp]),
-    "smart_plan_tiles": (_int, [_vp, _int, C.POINTER(_int), C.POINTER(_int), _vp, _vp]),
+    "smart_plan_tiles": (_int, [_vp, _int, C.POINTER(_int), C.POINTER(_int), _vp, _vp, _vp]),
     "smart_plan_set_timing": (_int, [_vp, _int]),
     "smart_autotune": (_int, [_vp, _int, C.c_char_p, _vp]),
     "smart_plan_kernel_ms": (_int, [_vp, _int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),

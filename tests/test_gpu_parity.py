@@ -317,9 +317,10 @@ def test_fp64_vs_mp(ctx):
 
 
 def test_plan_schedule_and_kernel_timing(ctx):
-    """Tile schedule of a pixel plan (belt tiles first, every tile once) and
-    the per-kernel timing of a run; belt tiles hold 256 consecutive pixels
-    of one belt ring."""
+    """Schedule of a pixel plan: belt items (runs of consecutive pixels of
+    one belt ring, at most 256 entries, never crossing a tile) and general
+    tiles together cover every list entry exactly once; and the per-kernel
+    timing of a run."""
     import torch
 
     L = _L()
@@ -330,17 +331,25 @@ def test_plan_schedule_and_kernel_timing(ctx):
                     m["pix"], [th], [ctx.filter(F.TANH)])
     with pytest.raises(L.SmartError):
         plan.kernel_ms(0)
-    nb, ng, tiles = plan.tiles(0)
-    nt = (m["pix"].size + 255) // 256
-    assert nb > 0 and nb + ng == nt
-    t = tiles.cpu().numpy()
-    assert np.array_equal(np.sort(t), np.arange(nt))
+    belt, gen = plan.tiles(0)
+    n = m["pix"].size
+    nt = (n + 255) // 256
+    assert belt.shape[0] > 0
+    cover = np.zeros(n, dtype=np.int64)
     rt = hp.ring_table(nside)
-    for tile in t[:nb]:
-        p = m["pix"][256 * tile: 256 * tile + 256]
+    for o0, ln in belt.cpu().numpy():
+        assert 0 < ln <= 256 and o0 // 256 == (o0 + ln - 1) // 256
+        cover[o0: o0 + ln] += 1
+        p = m["pix"][o0: o0 + ln]
         assert np.all(np.diff(p) == 1)
         ring = np.searchsorted(rt["first"], p[0], side="right") - 1
         assert nside <= ring + 1 <= 3 * nside and p[-1] < rt["first"][ring] + rt["n"][ring]
+    g = gen.cpu().numpy()
+    assert np.unique(g).size == g.size and np.all((g >= 0) & (g < nt))
+    for t in g:
+        cover[256 * t: 256 * t + 256] += 1
+    assert np.all(cover == 1)
+    nb, ng = belt.shape[0], g.size
     plan.set_timing(True)
     out = plan.run(L.NORM_SUMMED_PIXCOUNT)
     torch.cuda.synchronize()
