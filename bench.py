@@ -40,7 +40,7 @@ ALU_PEAK = 256 * 64 * 2.4e9
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0)
 # counter runs, profiles/pixel_kernels_nside4096_15000deg2_3scales.md; valid for the kernel versions
 # profiled there and the default workload only
-TRAFFIC_BYTES = {"k_pixel_f32 (20 arcmin)": 2.17842e10}
+TRAFFIC_BYTES = {}
 
 
 def parse():

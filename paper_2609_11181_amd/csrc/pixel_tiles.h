@@ -261,42 +261,45 @@ __device__ __forceinline__ void belt_member(const cdouble_t* qc, const cdouble_t
 }
 
 // Sources j0 .. j0 + cnt + 2 of a ring, read through `at(j)` (a pointer or a
-// wrapped index); four members per step, the records of the next step in
-// flight while the current one is summed, V runs flushed every kChunk.
+// wrapped index). The main loop takes eight members per iteration: the
+// eight new records are requested at the top, the first four members wait
+// only for the first four of them, and no record is copied between
+// registers (only the three-record window is carried to the next
+// iteration, already converted). V runs are flushed every kChunk members.
 template <typename At>
 __device__ __forceinline__ void belt_ring(const cdouble_t* qc, const cdouble_t* qs, const cfloat_t* q2, int cnt,
                                           At at, BeltAcc& A) {
-  Rec w0, w1, w2;
+  Rec w0, w1, w2;  // records k, k + 1, k + 2
   w0.set(at(0));
   w1.set(at(1));
   w2.set(at(2));
   int k = 0;
-  if (cnt >= 4) {
-    float4 n3 = at(3), n4 = at(4), n5 = at(5), n6 = at(6);
-    for (;;) {
-      Rec x3, x4, x5, x6;
-      x3.set(n3);
-      x4.set(n4);
-      x5.set(n5);
-      x6.set(n6);
-      const bool more = k + 8 <= cnt;  // records k + 7 .. k + 10 exist when the next step does
-      if (more) {
-        n3 = at(k + 7);
-        n4 = at(k + 8);
-        n5 = at(k + 9);
-        n6 = at(k + 10);
-      }
-      belt_member(qc, qs, q2, k, w0, w1, w2, x3, A);
-      belt_member(qc, qs, q2, k + 1, w1, w2, x3, x4, A);
-      belt_member(qc, qs, q2, k + 2, w2, x3, x4, x5, A);
-      belt_member(qc, qs, q2, k + 3, x3, x4, x5, x6, A);
-      w0 = x4;
-      w1 = x5;
-      w2 = x6;
-      if ((k & (kChunk - 1)) == kChunk - 4) A.flush_v();
-      k += 4;
-      if (!more) break;
-    }
+  for (; k + 8 <= cnt; k += 8) {
+    // flushed at the top, so that the body below is one basic block
+    if (k > 0 && (k & (kChunk - 1)) == 0) A.flush_v();
+    const float4 p0 = at(k + 3), p1 = at(k + 4), p2 = at(k + 5), p3 = at(k + 6);
+    const float4 u0 = at(k + 7), u1 = at(k + 8), u2 = at(k + 9), u3 = at(k + 10);  // k + 10 <= cnt + 2
+    Rec a3, a4, a5, a6;
+    a3.set(p0);
+    a4.set(p1);
+    a5.set(p2);
+    a6.set(p3);
+    belt_member(qc, qs, q2, k, w0, w1, w2, a3, A);
+    belt_member(qc, qs, q2, k + 1, w1, w2, a3, a4, A);
+    belt_member(qc, qs, q2, k + 2, w2, a3, a4, a5, A);
+    belt_member(qc, qs, q2, k + 3, a3, a4, a5, a6, A);
+    Rec b7, b8, b9, b10;
+    b7.set(u0);
+    b8.set(u1);
+    b9.set(u2);
+    b10.set(u3);
+    belt_member(qc, qs, q2, k + 4, a4, a5, a6, b7, A);
+    belt_member(qc, qs, q2, k + 5, a5, a6, b7, b8, A);
+    belt_member(qc, qs, q2, k + 6, a6, b7, b8, b9, A);
+    belt_member(qc, qs, q2, k + 7, b7, b8, b9, b10, A);
+    w0 = b8;
+    w1 = b9;
+    w2 = b10;
   }
   for (; k < cnt; ++k) {
     Rec x3;
@@ -326,17 +329,29 @@ __device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s
     // belt ring inf.x starts at pixel 2N(N-1) + 4N(r - N); n = 4N is a power of two
     const int64_t dring = 2 * (int64_t)N * (N - 1) + (int64_t)n * (inf.x - N) - a.pix_first;
     const int j0 = (ip0 + 4 * lane + inf.y) & (n - 1);
+    // W and N_occ of each centre's window: the run from jc to the ring's end
+    // (or the window's end), with its eight prefix loads in flight together,
+    // plus the wrapped part from the ring's start for the (rare) windows
+    // that pass the ring's end
+    {
+      double2 lo[4], hi[4];
+      int run[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {  // W and N_occ of each centre's window
-      const int jc = j0 + c < n ? j0 + c : j0 + c - n;
-      const int run = min(cnt, n - jc);
-      const double2 lo = a.wn[dring + jc], hi = a.wn[dring + jc + run];
-      A.sw[c] += hi.x - lo.x;
-      A.sn[c] += hi.y - lo.y;
-      if (run < cnt) {
-        const double2 lo2 = a.wn[dring], hi2 = a.wn[dring + cnt - run];
-        A.sw[c] += hi2.x - lo2.x;
-        A.sn[c] += hi2.y - lo2.y;
+      for (int c = 0; c < 4; ++c) {
+        const int jc = j0 + c < n ? j0 + c : j0 + c - n;
+        run[c] = min(cnt, n - jc);
+        lo[c] = a.wn[dring + jc];
+        hi[c] = a.wn[dring + jc + run[c]];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        A.sw[c] += hi[c].x - lo[c].x;
+        A.sn[c] += hi[c].y - lo[c].y;
+        if (run[c] < cnt) {
+          const double2 lo2 = a.wn[dring], hi2 = a.wn[dring + cnt - run[c]];
+          A.sw[c] += hi2.x - lo2.x;
+          A.sn[c] += hi2.y - lo2.y;
+        }
       }
     }
     const cdouble_t* qc = (const cdouble_t*)T.qc + inf.w;

@@ -37,6 +37,8 @@ struct Choice {
   int ool, belt, general;
 };
 
+constexpr float kOolMargin = 0.97f;
+
 std::string tune_key(smart_plan p, int k) {
   const PixelSched& sc = *p->sched[k];
   char buf[256];
@@ -145,8 +147,8 @@ int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st
     bool ok = true, complete = true;
     // general kernel: set-up inline / out of line, grid from the occupancy maximum down
     if (sc.counts[1] > 0) {
-      float best = 1e30f;
-      Choice bc{sc.general_ool, sc.belt_blocks, sc.general_blocks};
+      float best[2] = {1e30f, 1e30f};
+      int best_b[2] = {sc.general_blocks, sc.general_blocks};
       for (int ool = 0; ool < 2 && ok; ++ool) {
         const int mx = general_blocks_max(s, ool);
         for (int b = mx; b >= 1 && b >= mx - 1 && ok; --b) {
@@ -158,15 +160,17 @@ int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st
           sc.general_blocks = b;
           float ms = 0.f;
           ok = time_kind(2, &ms);
-          if (ok && ms < best) {
-            best = ms;
-            bc.ool = ool;
-            bc.general = b;
+          if (ok && ms < best[ool]) {
+            best[ool] = ms;
+            best_b[ool] = b;
           }
         }
       }
-      sc.general_ool = bc.ool;
-      sc.general_blocks = bc.general;
+      // out-of-line set-up keeps call frames in scratch memory (HBM writes
+      // of the order of the pair count): taken only when clearly faster
+      const int ool = best[1] < kOolMargin * best[0] ? 1 : 0;
+      sc.general_ool = ool;
+      sc.general_blocks = best_b[ool];
     }
     // belt kernel: grid from the occupancy maximum down to half of it
     if (ok && sc.counts[0] > 0) {
