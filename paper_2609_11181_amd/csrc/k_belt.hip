@@ -235,7 +235,7 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   const int nt = (int)((p->n_out + kBlock - 1) / kBlock);
   const int ns = kRuns * nt;  // item slots
   sc->n_tiles = nt;
-  BCHK(hipMalloc((void**)&sc->cursors, sizeof(int) * 34));  // cursors, then the two counts
+  BCHK(hipMalloc((void**)&sc->cursors, sizeof(int) * (2 * kQueueInts + 2)));  // cursors, then the two counts
   BCHK(hipMalloc((void**)&sc->general, sizeof(int) * (nt + 1)));
   BCHK(hipMalloc((void**)&flags, sizeof(int) * (nt + 1)));
   BCHK(hipMalloc((void**)&gflags, sizeof(int) * (nt + 1)));
@@ -257,8 +257,9 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   size_t tb = 0, tb2 = 0, tb3 = 0, tb4 = 0;
   hipcub::CountingInputIterator<int> tile_ids(0);
   BCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, keys + ns, ids, ids + ns, ns, 0, 57, st));
-  BCHK(hipcub::DeviceReduce::Sum(nullptr, tb3, flags, sc->cursors + 32, nt, st));
-  BCHK(hipcub::DeviceSelect::Flagged(nullptr, tb4, tile_ids, gflags, sc->general, sc->cursors + 33, nt, st));
+  BCHK(hipcub::DeviceReduce::Sum(nullptr, tb3, flags, sc->cursors + 2 * kQueueInts, nt, st));
+  BCHK(hipcub::DeviceSelect::Flagged(nullptr, tb4, tile_ids, gflags, sc->general, sc->cursors + 2 * kQueueInts + 1,
+                                     nt, st));
   hipLaunchKernelGGL(k_belt_size, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.theta_ap, s.C_ap, used,
                      cnts);
   BCHK(hipGetLastError());
@@ -277,14 +278,15 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   tb = p->ctx->temp_bytes;
   BCHK(hipcub::DeviceRadixSort::SortPairs(p->ctx->d_temp, tb, keys, keys + ns, ids, ids + ns, ns, 0, 57, st));
   tb = p->ctx->temp_bytes;
-  BCHK(hipcub::DeviceReduce::Sum(p->ctx->d_temp, tb, flags, sc->cursors + 32, nt, st));
+  BCHK(hipcub::DeviceReduce::Sum(p->ctx->d_temp, tb, flags, sc->cursors + 2 * kQueueInts, nt, st));
   tb = p->ctx->temp_bytes;
-  BCHK(hipcub::DeviceSelect::Flagged(p->ctx->d_temp, tb, tile_ids, gflags, sc->general, sc->cursors + 33, nt, st));
+  BCHK(hipcub::DeviceSelect::Flagged(p->ctx->d_temp, tb, tile_ids, gflags, sc->general,
+                                     sc->cursors + 2 * kQueueInts + 1, nt, st));
   tb = p->ctx->temp_bytes;
   BCHK(hipcub::DeviceScan::ExclusiveScan(p->ctx->d_temp, tb, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
   int counts[2] = {0, 0};
   int2 last_c, last_o;
-  BCHK(hipMemcpyAsync(counts, sc->cursors + 32, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  BCHK(hipMemcpyAsync(counts, sc->cursors + 2 * kQueueInts, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   BCHK(hipMemcpyAsync(&last_c, cnts + nb - 1, sizeof(int2), hipMemcpyDeviceToHost, st));
   BCHK(hipMemcpyAsync(&last_o, offs + nb - 1, sizeof(int2), hipMemcpyDeviceToHost, st));
   BCHK(hipStreamSynchronize(st));

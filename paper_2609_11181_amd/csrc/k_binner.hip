@@ -309,40 +309,131 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
   return SMART_OK;
 }
 
-struct WnOf {
-  __host__ __device__ double2 operator()(const float4& v) const {
-    return make_double2((double)v.w, v.w > 0.f ? 1.0 : 0.0);
-  }
-};
-
-struct Sum2 {
-  __host__ __device__ double2 operator()(const double2& a, const double2& b) const {
-    return make_double2(a.x + b.x, a.y + b.y);
-  }
-};
-
 // Prefix sums of the pixel weights and occupancy over the dense range, so
 // that a kernel gets W and N_occ of any run of consecutive pixels of a ring
 // from two lookups. In FP64: the difference of two prefixes keeps a relative
 // error near 1e-16 * (total W / run W), below 1e-9 for any map that fits.
+//
+// Three passes over chunks of kScanChunk pixels (reduce, scan of the chunk
+// totals, rescan and write); the two reading passes stream the map's records
+// coalesced, the writing pass scans contiguous runs of kScanPer pixels per
+// thread from LDS.
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = kBlock * kScanPer;
+
+namespace {
+
+__device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+__device__ __forceinline__ double2 block_sum2(double2 v, double2* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_down(v.x, o);
+    v.y += __shfl_down(v.y, o);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double2 t = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) t = add2(t, red[w]);
+  return t;
+}
+
+// Exclusive scan of one value per thread over the block, plus `carry`
+// (every thread passes the same carry).
+__device__ __forceinline__ double2 block_exscan2(double2 v, double2 carry, double2* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double2 inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const double x = __shfl_up(inc.x, o), y = __shfl_up(inc.y, o);
+    if (lane >= o) inc = add2(inc, make_double2(x, y));
+  }
+  if (lane == 63) red[wave] = inc;
+  __syncthreads();
+  double2 off = carry;
+  for (int w = 0; w < wave; ++w) off = add2(off, red[w]);
+  __syncthreads();
+  return add2(off, make_double2(inc.x - v.x, inc.y - v.y));
+}
+
+__global__ __launch_bounds__(kBlock) void k_wn_reduce(const float4* sums, int64_t n, double2* blk) {
+  __shared__ double2 red[kBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  double2 v = make_double2(0.0, 0.0);
+#pragma unroll 4
+  for (int j = 0; j < kScanPer; ++j) {
+    const int64_t i = base + j * kBlock + threadIdx.x;
+    if (i < n) {
+      const float w = sums[i].w;
+      v.x += (double)w;
+      v.y += w > 0.f ? 1.0 : 0.0;
+    }
+  }
+  const double2 t = block_sum2(v, red);
+  if (threadIdx.x == 0) blk[blockIdx.x] = t;
+}
+
+// exclusive scan of the nb chunk totals, in place, by one block
+__global__ __launch_bounds__(kBlock) void k_wn_scan_blocks(double2* blk, int nb) {
+  __shared__ double2 red[kBlock / 64];
+  const int per = (nb + kBlock - 1) / kBlock;
+  const int lo = min(nb, (int)threadIdx.x * per), hi = min(nb, lo + per);
+  double2 v = make_double2(0.0, 0.0);
+  for (int i = lo; i < hi; ++i) v = add2(v, blk[i]);
+  double2 run = block_exscan2(v, make_double2(0.0, 0.0), red);
+  for (int i = lo; i < hi; ++i) {
+    const double2 x = blk[i];
+    blk[i] = run;
+    run = add2(run, x);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_wn_write(const float4* sums, int64_t n, const double2* blk,
+                                                     double2* wn) {
+  __shared__ float w[kBlock * (kScanPer + 1)];  // thread t's run at t * (kScanPer + 1): no bank conflicts
+  __shared__ double2 red[kBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+#pragma unroll 4
+  for (int j = 0; j < kScanPer; ++j) {
+    const int e = j * kBlock + threadIdx.x;  // element of the chunk
+    const int64_t i = base + e;
+    w[(e / kScanPer) * (kScanPer + 1) + e % kScanPer] = i < n ? sums[i].w : 0.f;
+  }
+  __syncthreads();
+  const float* mine = w + threadIdx.x * (kScanPer + 1);
+  double2 v = make_double2(0.0, 0.0);
+  for (int j = 0; j < kScanPer; ++j) {
+    v.x += (double)mine[j];
+    v.y += mine[j] > 0.f ? 1.0 : 0.0;
+  }
+  double2 run = block_exscan2(v, blk[blockIdx.x], red);
+  const int64_t first = base + (int64_t)threadIdx.x * kScanPer;
+  for (int j = 0; j < kScanPer; ++j) {
+    if (first + j >= n) break;
+    run = make_double2(run.x + (double)mine[j], run.y + (mine[j] > 0.f ? 1.0 : 0.0));
+    wn[first + j + 1] = run;
+  }
+}
+
+}  // namespace
+
 int build_wn_prefix(smart_ctx ctx, smart_data d, hipStream_t st) {
+  (void)ctx;
   if (d->n_dense <= 0) return SMART_OK;
   if (hipMalloc((void**)&d->wn, sizeof(double2) * (d->n_dense + 1)) != hipSuccess) {
     set_error("out of device memory (prefix sums)");
     return SMART_ENOMEM;
   }
-  if (hipMemsetAsync(d->wn, 0, sizeof(double2), st) != hipSuccess) {
-    set_error("prefix-sum clear failed");
-    return SMART_EDEVICE;
+  const int64_t nb = (d->n_dense + kScanChunk - 1) / kScanChunk;
+  double2* blk = nullptr;
+  if (nb > 0x7fffffff || hipMallocAsync((void**)&blk, sizeof(double2) * nb, st) != hipSuccess) {
+    set_error("out of device memory (prefix sums)");
+    return SMART_ENOMEM;
   }
-  hipcub::TransformInputIterator<double2, WnOf, const float4*> in(d->sums, WnOf());
-  size_t tb = 0;
-  (void)hipcub::DeviceScan::InclusiveScan(nullptr, tb, in, d->wn + 1, Sum2(), (int)d->n_dense, st);
-  int rc = ensure_temp(ctx, tb);
-  if (rc) return rc;
-  tb = ctx->temp_bytes;
-  if (hipcub::DeviceScan::InclusiveScan(ctx->d_temp, tb, in, d->wn + 1, Sum2(), (int)d->n_dense, st) !=
-      hipSuccess) {
+  hipLaunchKernelGGL(k_wn_reduce, dim3((unsigned)nb), dim3(kBlock), 0, st, d->sums, d->n_dense, blk);
+  hipLaunchKernelGGL(k_wn_scan_blocks, dim3(1), dim3(kBlock), 0, st, blk, (int)nb);
+  hipLaunchKernelGGL(k_wn_write, dim3((unsigned)nb), dim3(kBlock), 0, st, d->sums, d->n_dense, blk, d->wn);
+  if (hipMemsetAsync(d->wn, 0, sizeof(double2), st) != hipSuccess || hipGetLastError() != hipSuccess ||
+      hipFreeAsync(blk, st) != hipSuccess) {
     set_error("prefix-sum scan failed");
     return SMART_EDEVICE;
   }

@@ -8,7 +8,7 @@
 // quarter of a general tile (64 centres, one per lane). The host orders the item groups
 // by estimated cost per item, most expensive first (a longest-processing-time
 // order, so that the small items fill the tail of the launch), and every wave
-// of one persistent kernel takes items from one global queue. Every item runs
+// of one persistent kernel takes items from that queue. Every item runs
 // the same device code as the single-plan kernels, so results are identical
 // to smart_run.
 #include <hip/hip_runtime.h>
@@ -55,14 +55,39 @@ __device__ __forceinline__ void general_quarter(const MixJob& J, int tile, int p
   general_centre<TABLE, BIG, true>(J.a, J.s, o, tp, Tab{J.s.table, J.s.table_c0});
 }
 
-__global__ __launch_bounds__(kBlock) void k_mixed(const MixJob* jobs, const int4* items, int n_items, int* counter) {
+// Item claims: the list is cut into chunks of kMixChunk consecutive items,
+// dealt round-robin to eight shares (chunk 8 c + x to share x), so every
+// share keeps the cost order while the items of one chunk (neighbouring
+// tiles of one job, sharing source rows) run on one XCD and its L2. Share x
+// counts its claims on its own cache line, cursors[x * kCursorStride], and
+// a wave starts with the share of its XCD. Returns n_items when all are
+// taken.
+constexpr int kMixChunk = 32;
+
+__device__ inline int claim_mixed(int* cursors, int n_items) {
+  const int xcd = blockIdx.x & 7;
+  for (int d = 0; d < 8; ++d) {
+    const int x = (xcd + d) & 7;
+    const int k = atomicAdd(&cursors[x * kCursorStride], 1);
+    const int64_t it = ((int64_t)(k / kMixChunk) * 8 + x) * kMixChunk + k % kMixChunk;
+    if (it < n_items) return (int)it;
+  }
+  return n_items;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mixed(const MixJob* jobs, const int4* items, int n_items, int* cursors) {
   for (;;) {
     int it = 0;
-    if ((threadIdx.x & 63) == 0) it = atomicAdd(counter, 1);
+    if ((threadIdx.x & 63) == 0) it = claim_mixed(cursors, n_items);
     it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
     if (it >= n_items) break;
-    const int4 w = items[it];
-    const MixJob& J = jobs[w.x];
+    // the item through the scalar cache (wave-uniform values)
+    const cint_t* wi = (const cint_t*)items + 4 * (int64_t)it;
+    const int4 w = make_int4(wi[0], wi[1], wi[2], wi[3]);
+    // the job through the scalar cache too: its fields are wave-uniform
+    // and can be reloaded instead of held in vector registers
+    MixJob J;
+    __builtin_memcpy(&J, (const void*)((const __attribute__((address_space(4))) MixJob*)jobs + w.x), sizeof(MixJob));
     if (w.z == 0) {
       belt_tile(J.a, J.s, J.t, w.y, w.w);
     } else {
@@ -141,9 +166,9 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
   int* counter = nullptr;
   MCHK(hipMallocAsync((void**)&items, sizeof(int4) * (size_t)n_items, st));
   MCHK(hipMallocAsync((void**)&d_jobs, sizeof(MixJob) * jobs.size(), st));
-  MCHK(hipMallocAsync((void**)&counter, sizeof(int), st));
+  MCHK(hipMallocAsync((void**)&counter, sizeof(int) * kQueueInts, st));
   MCHK(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(MixJob) * jobs.size(), hipMemcpyHostToDevice, st));
-  MCHK(hipMemsetAsync(counter, 0, sizeof(int), st));
+  MCHK(hipMemsetAsync(counter, 0, sizeof(int) * kQueueInts, st));
   int64_t off = 0;
   for (const Grp& g : groups) {
     const int n = g.kind == 0 ? g.count : 4 * g.count;

@@ -448,22 +448,23 @@ hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, h
     hipLaunchKernelGGL(k_pixel_f64, dim3((unsigned)blocks_for(a.n_out)), block, 0, st, a, s);
     return hipGetLastError();
   }
-  // d_work: the 16 queue cursors; every tile takes the general kernel
-  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, d_work, 16);
+  // d_work: one queue of cursors; every tile takes the general kernel
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(kQueueInts), 0, st, d_work, kQueueInts);
   return launch_general(a, s, st, nullptr, (int)blocks_for(a.n_out), d_work);
 }
 
 hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st,
                               hipEvent_t* ev, int kinds) {
   hipError_t e = hipSuccess;
-  if (a.n_out > 0) hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, sc.cursors, 32);
+  if (a.n_out > 0) hipLaunchKernelGGL(k_zero_ints, dim3(2), dim3(kQueueInts), 0, st, sc.cursors, 2 * kQueueInts);
   if (ev) e = hipEventRecord(ev[0], st);
   if (e == hipSuccess && a.n_out > 0 && sc.counts[0] > 0 && (kinds & 1))
     e = launch_belt(a, s, sc.tab(), sc.belt, sc.counts[0], sc.cursors, sc.belt_blocks, st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
   if (e == hipSuccess && a.n_out > 0 && sc.counts[1] > 0 && (kinds & 2))
-    e = launch_general(a, s, st, sc.general, sc.counts[1], sc.cursors + 16, sc.general_ool, sc.general_blocks);
+    e = launch_general(a, s, st, sc.general, sc.counts[1], sc.cursors + kQueueInts, sc.general_ool,
+                       sc.general_blocks);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
   return e;
 }
@@ -477,7 +478,7 @@ void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* nrun
 
 size_t pixel_work_ints(int64_t n_out) {
   (void)n_out;
-  return 16;
+  return kQueueInts;
 }
 
 hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, hipStream_t st) {

@@ -52,20 +52,20 @@ constexpr int kRingCap = 160;  // rings of one belt disc
 // equal contiguous shares, one per XCD (the dispatcher deals consecutive
 // workgroups to the XCDs in turn), so each XCD walks one region of the sky
 // and keeps it in its L2; a worker whose share is exhausted takes tiles from
-// the other shares. Returns -1 when no tile is left.
+// the other shares. Share x counts its claims in cursors[x * kCursorStride]
+// (a cursor past the share's end means exhausted). Returns -1 when no tile
+// is left.
 __device__ inline int claim_tile(int* cursors, int count) {
   const int xcd = blockIdx.x & 7;
-  int item = -1;
-  for (int d = 0; d < 8 && item < 0; ++d) {
+  for (int d = 0; d < 8; ++d) {
     const int x = (xcd + d) & 7;
     const int start = (int)((int64_t)count * x / 8);
     const int end = (int)((int64_t)count * (x + 1) / 8);
-    if (start >= end || atomicAdd(&cursors[8 + x], 0) != 0) continue;
-    const int k = atomicAdd(&cursors[x], 1);
-    if (start + k < end) item = start + k;
-    else atomicExch(&cursors[8 + x], 1);  // share exhausted
+    if (start >= end) continue;
+    const int k = atomicAdd(&cursors[x * kCursorStride], 1);
+    if (start + k < end) return start + k;
   }
-  return item;
+  return -1;
 }
 
 // Block-uniform variant (the block shares one tile).

@@ -16,6 +16,10 @@ constexpr int kFilterIntervals = 2048;  // cubic pieces per filter table
 constexpr int kMaxNside = 8192;
 constexpr double kMaxThetaAp = 0.25;    // radians
 constexpr int kBlock = 256;
+// Persistent-queue cursors: one per XCD share, each on its own 128-byte line
+// (atomics on one line are serialised), so one queue takes kQueueInts ints.
+constexpr int kCursorStride = 32;
+constexpr int kQueueInts = 8 * kCursorStride;
 
 void set_error(const std::string& msg);
 
@@ -165,7 +169,7 @@ struct PixelSched {
   int n_tiles = 0;
   int2* belt = nullptr;     // belt items (list position, length <= 256): runs of one belt ring, column-major
   int* general = nullptr;   // general tiles (tile t = list entries [256 t, 256 t + 256)), ascending
-  int* cursors = nullptr;   // queue cursors: [0, 16) belt kernel, [16, 32) general kernel
+  int* cursors = nullptr;   // queue cursors: belt kernel, general kernel (kQueueInts each), then the two counts
   int counts[2] = {0, 0};   // belt items, general tiles
   // launch choices (defaults from the disc size; smart_autotune measures them)
   int general_ool = 0;      // general kernel with out-of-line per-ring set-up
