@@ -186,8 +186,6 @@ PixelSched::~PixelSched() {
   (void)hipFree(noise_seg);
   (void)hipFree(noise_stacks);
   (void)hipFree(noise_rest);
-  (void)hipFree(noise_stage);
-  (void)hipFree(noise_work);
 }
 
 #define BCHK(x)                                                                        \

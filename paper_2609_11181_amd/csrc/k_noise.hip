@@ -23,6 +23,10 @@
 // of a source ring's slab are generated once per block into LDS and used by
 // every wave whose disc reaches that ring, so each (pixel, realisation) value
 // is generated once per stack and disc ring instead of once per segment.
+//
+// Outputs outside every stack (polar-cap rings, discs that leave the belt,
+// windows wider than kCntMax) walk their own discs with the general pair
+// geometry, sixteen realisations per thread, in FP32 (k_noise_rest_walk).
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -61,8 +65,8 @@ __global__ void k_rotate(const float4* map, const int* cidx, const float* u, int
 // eligible when its ring has a belt table whose windows hold at most kCntMax
 // members and the (sorted) output list holds a run of its pixels
 // [32c + a, 32c + b) as consecutive entries: seg = (list position of pixel
-// 32c + a, a, b), or o = -1. Pixels of the segment outside the run take the
-// plain path.
+// 32c + a, a, b), or o = -1. Outputs of the segment outside the run are
+// left to the per-output walk.
 __global__ void k_noise_segs(PixelArgs a, BeltTab t, int ncol, int4* seg) {
   const int N = a.nside_in;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -313,15 +317,127 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
   }
 }
 
-// scatter E and B of a plain pass over a sub-list of centres into the batch
-// output layout
-__global__ void k_scatter_noise(const float* stage, const int64_t* pos, int64_t n_sub, float* out, int64_t n_out,
-                                int scale, int n_real, int r) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_sub) return;
-  const int64_t base = ((int64_t)scale * n_real + r) * 2 * n_out;
-  out[base + pos[i]] = stage[i];
-  out[base + n_out + pos[i]] = stage[n_sub + i];
+// Outputs outside every stack: one thread per output walks its own disc as
+// the general pixel kernel does (ring windows, azimuth-step recurrence,
+// coefficients from the FP64 tangent-plane components) and applies each
+// member's coefficients to kRestReal realisations at once, rotating the
+// member's shear by each realisation's angle on the fly (the hardware
+// sine and cosine of 2 pi u, as for the stack slabs). Neighbouring threads
+// hold neighbouring outputs, so the angle loads u[r][source] of one member
+// step are contiguous across the wave. E/B sums per realisation in FP32.
+constexpr int kRestReal = 16;
+
+struct RestArgs {
+  PixelArgs a;
+  const int64_t* pos;  // [n_rest] list positions
+  int64_t n_rest;
+  const float* u;      // [n_real][n_src]
+  const int* cidx;     // dense pixel -> source index (-1: empty)
+  int64_t n_src;
+  int n_real;
+  float* out;          // [n_scales][n_real][2][n_out]
+};
+
+template <bool TABLE, bool BIG>
+__global__ __launch_bounds__(kBlock) void k_noise_rest_walk(RestArgs n, ScaleArgs s) {
+  __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
+  __shared__ double tab_c0[TABLE ? kFilterIntervals : 1];
+  if (TABLE) {
+    for (int k = threadIdx.x; k < kFilterIntervals; k += blockDim.x) {
+      tab_c[k] = s.table[k];
+      tab_c0[k] = s.table_c0[k];
+    }
+    __syncthreads();
+  }
+  const Tab tab{tab_c, tab_c0};
+  const PixelArgs& a = n.a;
+  const int64_t nob = (n.n_rest + kBlock - 1) / kBlock;
+  const int64_t i = (blockIdx.x % nob) * kBlock + threadIdx.x;
+  const int r0 = (int)(blockIdx.x / nob) * kRestReal;  // first realisation of this block
+  if (i >= n.n_rest) return;
+  double tp[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) tp[k] = s.tpoly[k];
+  const int64_t o = n.pos[i];
+  int rp, ip;
+  pixel_ring(a.nside_out, a.out_pix[o], &rp, &ip);
+  const Ring R = ring_info(a.nside_out, rp);
+  const double zp = R.z, sp = R.s;
+  const int np = R.n;
+  const int64_t ip2 = 2 * (int64_t)ip + R.twice_o;
+  int lo, hi;
+  ring_span(a.nside_in, atan2(sp, zp), s.theta_ap, &lo, &hi);
+  lo = max(lo, a.ring_lo);
+  hi = min(hi, a.ring_hi);
+  const int nr = min(kRestReal, n.n_real - r0);
+  float se[kRestReal], sb[kRestReal];
+#pragma unroll
+  for (int q = 0; q < kRestReal; ++q) se[q] = sb[q] = 0.f;
+  Acc64 tot;
+  for (int r = lo; r <= hi; ++r) {
+    const Ring Q = ring_info(a.nside_in, r);
+    int64_t jlo;
+    int cnt;
+    if (!ring_window(zp, sp, ip2, np, Q, s.C_ap, &jlo, &cnt)) continue;
+    const int nq = Q.n;
+    const double Y0 = ring_y0(Q.s, Q.z, zp, sp);
+    const double Kz = 2.0 * Q.z * sp;
+    const int64_t m = ip2 * nq - (2 * jlo + Q.twice_o) * (int64_t)np;
+    double sa, h;
+    sin_hav((double)m * (kPi / ((double)np * (double)nq)), &sa, &h);
+    RingStep step;
+    step.init(2.0 * kPi / (double)nq);
+    const int64_t mstep = 2 * (int64_t)np;
+    const int kc = (Y0 == 0.0 && m >= 0 && m % mstep == 0 && m / mstep < cnt) ? (int)(m / mstep) : -1;
+    const int64_t dring = Q.first - a.pix_first;
+    int jw = (int)(((jlo % nq) + nq) % nq);
+    int kdone = 0;
+    while (kdone < cnt) {
+      int run = min(cnt - kdone, nq - jw);
+      if (kc > kdone && kc < kdone + run) run = kc - kdone;
+      if (kdone == kc) {
+        sa = 0.0;
+        h = 0.0;
+      }
+      run_wn(a.wn, dring + jw, run, tot);
+      for (int k = 0; k < run; ++k) {
+        const Coef c = ring_coef<TABLE, BIG>(sp * sa, fma(Kz, h, Y0), tp, tab);
+        step.advance(&sa, &h);
+        const int64_t d = dring + jw + k;
+        const int ci = n.cidx[d];
+        if (ci < 0) continue;  // empty pixel: no shear
+        const float4 g = a.map[d];
+        const float qc = (float)c.qc, qs = (float)c.qs;
+        const float* up = n.u + (int64_t)r0 * n.n_src + ci;
+#pragma unroll
+        for (int q = 0; q < kRestReal; ++q) {
+          if (q < nr) {
+            const float uu = up[(int64_t)q * n.n_src];
+            const float sn = __builtin_amdgcn_sinf(uu), cs = __builtin_amdgcn_cosf(uu);  // of 2 pi u
+            const float x1 = g.x * cs - g.y * sn, x2 = g.x * sn + g.y * cs;
+            se[q] = fmaf(qc, x1, fmaf(qs, x2, se[q]));
+            sb[q] = fmaf(qc, x2, fmaf(-qs, x1, sb[q]));
+          }
+        }
+      }
+      kdone += run;
+      jw += run;
+      if (jw == nq) jw = 0;
+    }
+  }
+  float f = 1.f;
+  if (a.norm != SMART_NORM_RAW) {
+    const double area = a.norm == SMART_NORM_SUMMED_CAP ? s.area_cap : tot.sn * s.omega_pix;
+    f = tot.sw > 0.0 ? (float)(area * s.inv_theta2 / tot.sw) : 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < kRestReal; ++q) {
+    if (q < nr) {
+      const int64_t base = ((int64_t)a.scale * n.n_real + r0 + q) * 2 * a.n_out;
+      n.out[base + o] = f * se[q];
+      n.out[base + a.n_out + o] = f * sb[q];
+    }
+  }
 }
 
 unsigned grid_of(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
@@ -346,7 +462,7 @@ hipError_t launch_rotate_map(const float4* map, const int* cidx, const float* u,
 
 // Noise schedule of one scale (built on the first batched call, kept in the
 // plan): eligible segments, stacks in column-major order, the outputs left
-// to the plain path.
+// to the per-output walk.
 static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, hipStream_t st) {
   const int N = a.nside_in;
   const int ncol = (4 * N) / kNP;
@@ -423,7 +539,7 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
     if (!sc.noise_built) {
       const int rc = sc.counts[0] > 0 ? build_noise_sched(p, sc, a, st) : SMART_OK;
       if (rc) return rc;
-      if (sc.counts[0] == 0) {  // no belt tables: every output takes the plain path
+      if (sc.counts[0] == 0) {  // no belt tables: every output takes the per-output walk
         sc.noise_n_rest = (int)p->n_out;
         NCHK(hipMalloc((void**)&sc.noise_rest, sizeof(int64_t) * 2 * (size_t)p->n_out));
         std::vector<int64_t> pos(p->n_out);
@@ -453,34 +569,28 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
       NCHK(hipGetLastError());
     }
     if (sc.noise_n_rest > 0) {
-      // other outputs: plain pair sums per realisation on the rotated map
-      const int n_sub = sc.noise_n_rest;
-      if (p->rot_len < d->n_dense) {
-        (void)hipFree(p->rot_map);
-        p->rot_map = nullptr;
-        p->rot_len = 0;
-        NCHK(hipMalloc(&p->rot_map, sizeof(float4) * d->n_dense));
-        p->rot_len = d->n_dense;
+      // other outputs: their own disc walks, kRestReal realisations per thread
+      RestArgs ra{};
+      ra.a = a;
+      ra.pos = sc.noise_rest;
+      ra.n_rest = sc.noise_n_rest;
+      ra.u = d_u;
+      ra.cidx = d->cidx;
+      ra.n_src = d->n_src;
+      ra.n_real = n_real;
+      ra.out = d_out;
+      const int64_t blocks = (int64_t)grid_of(ra.n_rest) * ((n_real + kRestReal - 1) / kRestReal);
+      if (blocks > 0x7fffffff) {
+        set_error("noise batch: too many outputs outside the stacks");
+        return SMART_EINVAL;
       }
-      if (!sc.noise_stage) {
-        NCHK(hipMalloc((void**)&sc.noise_stage, sizeof(float) * 5 * (size_t)n_sub));
-        NCHK(hipMalloc((void**)&sc.noise_work, sizeof(int) * pixel_work_ints(n_sub)));
-      }
-      float* stage = sc.noise_stage;
-      int* subwork = sc.noise_work;
-      PixelArgs b = a;
-      b.out_pix = sc.noise_rest + n_sub;
-      b.n_out = n_sub;
-      b.map = p->rot_map;
-      b.out = stage;
-      b.scale = 0;
-      for (int r = 0; r < n_real; ++r) {
-        NCHK(launch_rotate_map(d->sums, d->cidx, d_u + (int64_t)r * d->n_src, d->n_dense, p->rot_map, st));
-        NCHK(launch_pixel(b, s, SMART_PREC_FP32_GEO64, st, subwork));
-        hipLaunchKernelGGL(k_scatter_noise, dim3(grid_of(n_sub)), dim3(kBlock), 0, st, stage, sc.noise_rest, n_sub,
-                           d_out, p->n_out, k, n_real, r);
-        NCHK(hipGetLastError());
-      }
+      const dim3 grid((unsigned)blocks), block(kBlock);
+      const bool table = s.filter_kind != SMART_FILTER_POLY;
+      if (table && s.big) hipLaunchKernelGGL((k_noise_rest_walk<true, true>), grid, block, 0, st, ra, s);
+      else if (table) hipLaunchKernelGGL((k_noise_rest_walk<true, false>), grid, block, 0, st, ra, s);
+      else if (s.big) hipLaunchKernelGGL((k_noise_rest_walk<false, true>), grid, block, 0, st, ra, s);
+      else hipLaunchKernelGGL((k_noise_rest_walk<false, false>), grid, block, 0, st, ra, s);
+      NCHK(hipGetLastError());
     }
   }
   return SMART_OK;

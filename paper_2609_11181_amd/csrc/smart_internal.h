@@ -186,8 +186,6 @@ struct PixelSched {
   int4* noise_seg = nullptr;       // per belt segment: (list position of its run, first, end), or -1
   int* noise_stacks = nullptr;     // stacks of segments, column-major
   int64_t* noise_rest = nullptr;   // [2][noise_n_rest]: list positions and pixels of the other outputs
-  float* noise_stage = nullptr;    // [5][noise_n_rest] staging of the plain passes
-  int* noise_work = nullptr;       // queue cursors of the plain passes
   BeltTab tab() const { return BeltTab{head, info, qc, qs, q2}; }
   ~PixelSched();
 };
