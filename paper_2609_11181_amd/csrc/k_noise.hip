@@ -49,7 +49,6 @@ constexpr int kNP = 32;     // centres per segment (MFMA rows)
 constexpr int kNR = 32;     // realisations per block (E and B: two 32-column MFMA halves)
 constexpr int kStack = 4;   // segments per block, one per wave
 constexpr int kCntMax = 96;                    // members per disc ring of an eligible segment
-constexpr int kSlabMax = kNP + kCntMax + 16;   // union slab of the four windows on one ring
 
 __global__ void k_rotate(const float4* map, const int* cidx, const float* u, int64_t n, float4* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -67,7 +66,7 @@ __global__ void k_rotate(const float4* map, const int* cidx, const float* u, int
 // [32c + a, 32c + b) as consecutive entries: seg = (list position of pixel
 // 32c + a, a, b), or o = -1. Outputs of the segment outside the run are
 // left to the per-output walk.
-__global__ void k_noise_segs(PixelArgs a, BeltTab t, int ncol, int4* seg) {
+__global__ void k_noise_segs(PixelArgs a, BeltTab t, int ncol, int4* seg, int* cnt_max) {
   const int N = a.nside_in;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)(2 * N + 1) * ncol) return;
@@ -75,7 +74,13 @@ __global__ void k_noise_segs(PixelArgs a, BeltTab t, int ncol, int4* seg) {
   int4 r = make_int4(-1, 0, 0, 0);
   const int first = t.head[i].x, nr = t.head[i].y;
   bool ok = nr > 0;
-  for (int k = 0; ok && k < nr; ++k) ok = t.info[first + k].z <= kCntMax;
+  int mx = 0;
+  for (int k = 0; ok && k < nr; ++k) {
+    const int z = t.info[first + k].z;
+    ok = z <= kCntMax;
+    mx = max(mx, z);
+  }
+  if (ok && c == 0) atomicMax(cnt_max, mx);  // widest window of an eligible ring
   if (ok) {
     const int64_t p0 = 2 * (int64_t)N * (N - 1) + 4 * (int64_t)N * i + kNP * (int64_t)c;
     int64_t l = 0, h = a.n_out;  // first entry >= p0
@@ -158,9 +163,29 @@ __device__ __forceinline__ uint32_t bmode(uint32_t x) { return ((x >> 16) | (x <
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleArgs s) {
-  __shared__ uint2 xs[kSlabMax * kNR];         // slab realisations: (X1, X2) hi words, lo words
-  __shared__ uint2 coefA[kStack][kCntMax];     // per wave: (Qc, Qs) hi words, lo words
+// Dynamic LDS of one stack block for windows of at most cnt_max members:
+// the slab, [slot][2 kNR] split words with the E form (X1, X2) of
+// realisation r at 2 r and its B form (X2, -X1) at 2 r + 1 (also the
+// epilogue's staging of the four waves' [2 kNR][kNP] outputs), then each
+// wave's coefficient band, zero-padded by kPadL entries before and kPadR
+// after, so that the operand loads need no range tests.
+constexpr int kPadL = 32, kPadR = 48;
+__host__ __device__ constexpr int stack_slab(int cnt_max) { return kNP + cnt_max + 16; }
+__host__ __device__ constexpr int stack_band(int cnt_max) { return kPadL + cnt_max + kPadR; }
+__host__ __device__ constexpr size_t stack_slab_bytes(int cnt_max) {
+  return (size_t)stack_slab(cnt_max) * 2 * kNR * sizeof(uint2) > (size_t)kStack * 2 * kNR * kNP * sizeof(float)
+             ? (size_t)stack_slab(cnt_max) * 2 * kNR * sizeof(uint2)
+             : (size_t)kStack * 2 * kNR * kNP * sizeof(float);
+}
+__host__ __device__ constexpr size_t stack_lds_bytes(int cnt_max) {
+  return stack_slab_bytes(cnt_max) + (size_t)kStack * stack_band(cnt_max) * sizeof(uint2);
+}
+
+__global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleArgs s, int cnt_max) {
+  extern __shared__ uint2 smem[];
+  const int slab_max = stack_slab(cnt_max), band = stack_band(cnt_max);
+  uint2* xs = smem;                                                    // [slab_max][2 kNR]
+  uint2* coefP = smem + stack_slab_bytes(cnt_max) / sizeof(uint2);    // [kStack][band]
   __shared__ int s_ws[kStack], s_we[kStack];   // per wave window [start, end) on the current ring
   __shared__ float fnorm[kStack][kNP];
   const PixelArgs& a = n.a;
@@ -176,6 +201,7 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
   const bool active = o_w >= 0;
   const int hfirst = active ? n.t.head[iw].x : 0, hnr = active ? n.t.head[iw].y : 0;
   const int lo_w = active ? n.t.info[hfirst].x : 0x7fffffff;
+  uint2* myband = coefP + wave * band;
   // union of the four discs' rings
   __shared__ int s_lo[kStack], s_hi[kStack];
   if (lane == 0) {
@@ -208,8 +234,12 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
       s_ws[wave] = cnt > 0 ? ws : 0x7fffffff;
       s_we[wave] = cnt > 0 ? we : -0x7fffffff;
     }
-    // coefficients of the band
-    for (int k = lane; k < cnt; k += 64) coefA[wave][k] = split_pair((float)n.t.qc[coff + k], (float)n.t.qs[coff + k]);
+    // the band's coefficients, zero outside [0, cnt)
+    for (int k = lane; k < band; k += 64) {
+      const int m = k - kPadL;
+      myband[k] = (m >= 0 && m < cnt) ? split_pair((float)n.t.qc[coff + m], (float)n.t.qs[coff + m])
+                                      : make_uint2(0u, 0u);
+    }
     const int64_t dring = 2 * (int64_t)N * (N - 1) + (int64_t)nring * (r - N) - a.pix_first;
     if (cnt > 0 && lane < kNP) {  // W and N_occ of the window of centre `lane`
       const int j0 = (ws + lane) & (nring - 1);
@@ -233,9 +263,9 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
       __syncthreads();
       continue;
     }
-    // every window holds at most 32 + kCntMax - 1 pixels and the four windows
+    // every window holds at most 32 + cnt_max - 1 pixels and the four windows
     // are centred within half a pixel of each other, so the union fits
-    const int Lu = min(ue - us, kSlabMax);
+    const int Lu = min(ue - us, slab_max);
     // realisations of the union slab: wave w generates realisations w, w + 4, ...
     for (int s0 = 0; s0 < Lu; s0 += 64) {
       const int sl = s0 + lane;
@@ -249,7 +279,9 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
           const int rreal = rg * kNR + rr;
           const float uu = (ci >= 0 && rreal < n.n_real) ? n.u[(int64_t)rreal * n.n_src + ci] : 0.f;
           const float sn = __builtin_amdgcn_sinf(uu), cs = __builtin_amdgcn_cosf(uu);  // of 2 pi u
-          xs[sl * kNR + rr] = split_pair(gr.x * cs - gr.y * sn, gr.x * sn + gr.y * cs);
+          const uint2 e = split_pair(gr.x * cs - gr.y * sn, gr.x * sn + gr.y * cs);
+          xs[sl * 2 * kNR + 2 * rr] = e;
+          xs[sl * 2 * kNR + 2 * rr + 1] = make_uint2(bmode(e.x), bmode(e.y));
         }
       }
     }
@@ -257,23 +289,25 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
     if (cnt > 0) {
       const int base = ws - us;       // slab slot of this wave's first window pixel
       const int L = kNP + cnt - 1;    // centre t uses window pixels [t, t + cnt)
+      // B column col: realisation col / 2 (E form for even col, B form for
+      // odd) in slab entry col, realisation 16 + col / 2 in entry 32 + col
+      const uint2* bp = xs + col;
+      const uint2* ap = myband + kPadL - col;  // A row col: coefficient js - col
       for (int s0 = 0; s0 < L; s0 += 8) {
         u32x4 ah, al, b0h, b0l, b1h, b1l;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int js = s0 + half * 4 + q;  // pixel within the window
-          const int ks = js - col;           // disc offset for centre `col`
-          const uint2 w = (js < L && ks >= 0 && ks < cnt) ? coefA[wave][ks] : make_uint2(0u, 0u);
+          const uint2 w = ap[js];            // zero where js - col is outside [0, cnt)
           ah[q] = w.x;
           al[q] = w.y;
           const int slot = min(base + js, Lu - 1);  // beyond the window A is zero
-          const uint2 x0 = xs[slot * kNR + (col >> 1)];
-          const uint2 x1v = xs[slot * kNR + 16 + (col >> 1)];
-          const bool e = col & 1;  // B column 2 r' + e: rows (X1, X2) for E, (X2, -X1) for B
-          b0h[q] = e ? bmode(x0.x) : x0.x;
-          b0l[q] = e ? bmode(x0.y) : x0.y;
-          b1h[q] = e ? bmode(x1v.x) : x1v.x;
-          b1l[q] = e ? bmode(x1v.y) : x1v.y;
+          const uint2 x0 = bp[slot * 2 * kNR];
+          const uint2 x1v = bp[slot * 2 * kNR + 32];
+          b0h[q] = x0.x;
+          b0l[q] = x0.y;
+          b1h[q] = x1v.x;
+          b1l[q] = x1v.y;
         }
         const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah), Al = __builtin_bit_cast(bf16x8, al);
         const bf16x8 B0h = __builtin_bit_cast(bf16x8, b0h), B0l = __builtin_bit_cast(bf16x8, b0l);
@@ -286,7 +320,7 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, B1h, acc1, 0, 0, 0);
       }
     }
-    __syncthreads();  // xs, coefA and the windows are rewritten for the next ring
+    __syncthreads();  // xs, the bands and the windows are rewritten for the next ring
   }
 
   // epilogue: summed normalisation per centre, staged for coalesced writes
@@ -475,10 +509,12 @@ static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, h
   NCHK(hipMalloc((void**)&sc.noise_stacks, sizeof(int) * (n_stk + 1)));
   NCHK(hipMallocAsync((void**)&flags, sizeof(int) * (std::max(n_stk, p->n_out) + 1), st));
   NCHK(hipMallocAsync((void**)&covered, sizeof(int) * (p->n_out + 1), st));
-  NCHK(hipMallocAsync((void**)&cnt, sizeof(int) * 2, st));
+  NCHK(hipMallocAsync((void**)&cnt, sizeof(int) * 3, st));
+  NCHK(hipMemsetAsync(cnt, 0, sizeof(int) * 3, st));
   NCHK(hipMallocAsync((void**)&pos, sizeof(int64_t) * (p->n_out + 1), st));
   NCHK(hipMemsetAsync(covered, 0, sizeof(int) * (p->n_out + 1), st));
-  hipLaunchKernelGGL(k_noise_segs, dim3(grid_of(n_seg)), dim3(kBlock), 0, st, a, sc.tab(), ncol, sc.noise_seg);
+  hipLaunchKernelGGL(k_noise_segs, dim3(grid_of(n_seg)), dim3(kBlock), 0, st, a, sc.tab(), ncol, sc.noise_seg,
+                     cnt + 2);
   hipLaunchKernelGGL(k_noise_stacks, dim3(grid_of(n_stk)), dim3(kBlock), 0, st, n_groups, ncol, n_rings,
                      sc.noise_seg, flags, covered);
   NCHK(hipGetLastError());
@@ -494,11 +530,17 @@ static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, h
                      flags);
   tb = p->ctx->temp_bytes;
   NCHK(hipcub::DeviceSelect::Flagged(p->ctx->d_temp, tb, ids64, flags, pos, cnt + 1, (int)p->n_out, st));
-  int h[2] = {0, 0};
+  int h[3] = {0, 0, 0};
   NCHK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
   NCHK(hipStreamSynchronize(st));
   sc.noise_n_stacks = h[0];
   sc.noise_n_rest = h[1];
+  sc.noise_cnt_max = h[2];
+  if (h[0] > 0) {  // the stack kernel's LDS is sized from the widest window
+    static_assert(stack_lds_bytes(kCntMax) <= 160 * 1024 - 1024, "LDS of the widest stack");
+    NCHK(hipFuncSetAttribute((const void*)k_noise_stack, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)stack_lds_bytes(kCntMax)));
+  }
   sc.noise_ncol = ncol;
   sc.noise_n_groups = n_groups;
   if (h[1] > 0) {
@@ -565,7 +607,8 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
       na.n_grp = (n_real + kNR - 1) / kNR;
       na.out = d_out;
       const dim3 grid((unsigned)((int64_t)sc.noise_n_stacks * na.n_grp)), block(64 * kStack);
-      hipLaunchKernelGGL(k_noise_stack, grid, block, 0, st, na, s);
+      hipLaunchKernelGGL(k_noise_stack, grid, block, stack_lds_bytes(sc.noise_cnt_max), st, na, s,
+                         sc.noise_cnt_max);
       NCHK(hipGetLastError());
     }
     if (sc.noise_n_rest > 0) {

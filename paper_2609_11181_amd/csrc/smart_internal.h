@@ -182,7 +182,7 @@ struct PixelSched {
   float* q2 = nullptr;
   // batched noise schedule (built on the first batched call; k_noise.hip)
   int noise_built = 0;
-  int noise_n_stacks = 0, noise_n_rest = 0, noise_ncol = 0, noise_n_groups = 0;
+  int noise_n_stacks = 0, noise_n_rest = 0, noise_ncol = 0, noise_n_groups = 0, noise_cnt_max = 0;
   int4* noise_seg = nullptr;       // per belt segment: (list position of its run, first, end), or -1
   int* noise_stacks = nullptr;     // stacks of segments, column-major
   int64_t* noise_rest = nullptr;   // [2][noise_n_rest]: list positions and pixels of the other outputs
