@@ -273,6 +273,7 @@ __device__ __forceinline__ void belt_ring(const cdouble_t* qc, const cdouble_t* 
   w0.set(at(0));
   w1.set(at(1));
   w2.set(at(2));
+  const int last = cnt + 2;  // last record of the window
   int k = 0;
   for (; k + 8 <= cnt; k += 8) {
     // flushed at the top, so that the body below is one basic block
@@ -301,13 +302,23 @@ __device__ __forceinline__ void belt_ring(const cdouble_t* qc, const cdouble_t* 
     w1 = b9;
     w2 = b10;
   }
-  for (; k < cnt; ++k) {
-    Rec x3;
-    x3.set(at(k + 3));
-    belt_member(qc, qs, q2, k, w0, w1, w2, x3, A);
-    w0 = w1;
-    w1 = w2;
-    w2 = x3;
+  // the last cnt - k < 8 members: their records (clamped to the window, the
+  // clamped ones unused) are all requested before the first is used
+  if (k < cnt) {
+    float4 t[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) t[j] = at(min(k + 3 + j, last));
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      if (k + j < cnt) {
+        Rec x3;
+        x3.set(t[j]);
+        belt_member(qc, qs, q2, k + j, w0, w1, w2, x3, A);
+        w0 = w1;
+        w1 = w2;
+        w2 = x3;
+      }
+    }
   }
   A.flush_v();
 }
