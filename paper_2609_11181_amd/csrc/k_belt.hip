@@ -40,6 +40,11 @@ __device__ inline void belt_span(const PixelArgs& a, double theta_ap, int rp, in
 }
 
 // cnts[rp - N] = (table rings, members) of every used centre ring.
+__global__ void k_info_cnt_max(const int4* info, int n, int* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && info[i].z > 0) atomicMax(out, info[i].z);
+}
+
 __global__ void k_belt_size(PixelArgs a, double theta_ap, double C_ap, const int* used, int2* cnts) {
   const int N = a.nside_in;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,33 +149,64 @@ __global__ __launch_bounds__(kBlock) void k_belt_fill(PixelArgs a, ScaleArgs s, 
   }
 }
 
+// One wave per belt item; J > 0: source spans of 64 J records staged in the
+// wave's LDS (windows of at most 64 J - 263 members), J = 0: records read
+// from global memory.
+template <int J>
 __global__ __launch_bounds__(kBlock) void k_pixel_belt(PixelArgs a, ScaleArgs s, BeltTab t, const int2* items,
                                                        int n_items, int* cursors) {
+  constexpr int JS = J > 0 ? J : 1;
+  __shared__ BeltSpan<JS> spans[J > 0 ? kBlock / 64 : 1];
   for (;;) {
     const int item = next_tile_wave(cursors, n_items);
     if (item < 0) break;
     const int2 it = items[item];
-    belt_tile(a, s, t, it.x, it.y);
+    if constexpr (J > 0) belt_tile_staged<JS>(a, s, t, it.x, it.y, spans[threadIdx.x >> 6]);
+    else belt_tile(a, s, t, it.x, it.y);
   }
 }
 
-int belt_per_cu() {
+// staged span width (in 64-record units) for windows of at most cnt_max members, 0 for none
+int belt_span_j(int cnt_max) {
+  const int need = 263 + cnt_max;
+  return need <= 320 ? 5 : need <= 384 ? 6 : need <= 448 ? 7 : 0;
+}
+
+template <int J>
+int belt_per_cu_t() {
   static int per_cu = 0;
-  if (per_cu == 0 &&
-      (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pixel_belt, kBlock, 0) != hipSuccess || per_cu <= 0))
+  if (per_cu == 0 && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pixel_belt<J>, kBlock, 0) !=
+                          hipSuccess ||
+                      per_cu <= 0))
     per_cu = 2;
   return per_cu;
 }
 
+int belt_per_cu(int J) {
+  switch (J) {
+    case 5: return belt_per_cu_t<5>();
+    case 6: return belt_per_cu_t<6>();
+    case 7: return belt_per_cu_t<7>();
+    default: return belt_per_cu_t<0>();
+  }
+}
+
 }  // namespace
 
-int belt_blocks_max() { return belt_per_cu(); }
+int belt_blocks_max(int cnt_max) { return belt_per_cu(belt_span_j(cnt_max)); }
 
 hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int2* list, int count,
-                       int* cursors, int blocks_per_cu, hipStream_t st) {
-  const int per_cu = belt_per_cu();
+                       int* cursors, int blocks_per_cu, int cnt_max, hipStream_t st) {
+  const int J = belt_span_j(cnt_max);
+  const int per_cu = belt_per_cu(J);
   const int grid = device_cus() * (blocks_per_cu > 0 ? std::min(blocks_per_cu, per_cu) : per_cu);
-  hipLaunchKernelGGL(k_pixel_belt, dim3(grid), dim3(kBlock), 0, st, a, s, t, list, count, cursors);
+  const dim3 g(grid), b(kBlock);
+  switch (J) {
+    case 5: hipLaunchKernelGGL(k_pixel_belt<5>, g, b, 0, st, a, s, t, list, count, cursors); break;
+    case 6: hipLaunchKernelGGL(k_pixel_belt<6>, g, b, 0, st, a, s, t, list, count, cursors); break;
+    case 7: hipLaunchKernelGGL(k_pixel_belt<7>, g, b, 0, st, a, s, t, list, count, cursors); break;
+    default: hipLaunchKernelGGL(k_pixel_belt<0>, g, b, 0, st, a, s, t, list, count, cursors); break;
+  }
   return hipGetLastError();
 }
 
@@ -233,7 +269,8 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   const int nt = (int)((p->n_out + kBlock - 1) / kBlock);
   const int ns = kRuns * nt;  // item slots
   sc->n_tiles = nt;
-  BCHK(hipMalloc((void**)&sc->cursors, sizeof(int) * (2 * kQueueInts + 2)));  // cursors, then the two counts
+  // cursors, then the two counts and the widest window
+  BCHK(hipMalloc((void**)&sc->cursors, sizeof(int) * (2 * kQueueInts + 3)));
   BCHK(hipMalloc((void**)&sc->general, sizeof(int) * (nt + 1)));
   BCHK(hipMalloc((void**)&flags, sizeof(int) * (nt + 1)));
   BCHK(hipMalloc((void**)&gflags, sizeof(int) * (nt + 1)));
@@ -312,6 +349,14 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   else if (s.big) fill(k_belt_fill<false, true>);
   else fill(k_belt_fill<false, false>);
   BCHK(hipGetLastError());
+  // widest window of the tables (sizes the belt kernel's LDS spans)
+  int* cmax = sc->cursors + 2 * kQueueInts + 2;
+  BCHK(hipMemsetAsync(cmax, 0, sizeof(int), st));
+  if (n_info > 0)
+    hipLaunchKernelGGL(k_info_cnt_max, dim3((n_info + kBlock - 1) / kBlock), dim3(kBlock), 0, st, sc->info, n_info,
+                       cmax);
+  BCHK(hipGetLastError());
+  BCHK(hipMemcpyAsync(&sc->belt_cnt_max, cmax, sizeof(int), hipMemcpyDeviceToHost, st));
   BCHK(hipStreamSynchronize(st));  // the scratch below is freed next
   (void)hipFree(used);
   (void)hipFree(flags);

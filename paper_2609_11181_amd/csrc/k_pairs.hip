@@ -459,7 +459,7 @@ hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const Pixe
   if (a.n_out > 0) hipLaunchKernelGGL(k_zero_ints, dim3(2), dim3(kQueueInts), 0, st, sc.cursors, 2 * kQueueInts);
   if (ev) e = hipEventRecord(ev[0], st);
   if (e == hipSuccess && a.n_out > 0 && sc.counts[0] > 0 && (kinds & 1))
-    e = launch_belt(a, s, sc.tab(), sc.belt, sc.counts[0], sc.cursors, sc.belt_blocks, st);
+    e = launch_belt(a, s, sc.tab(), sc.belt, sc.counts[0], sc.cursors, sc.belt_blocks, sc.belt_cnt_max, st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
   if (e == hipSuccess && a.n_out > 0 && sc.counts[1] > 0 && (kinds & 2))

@@ -240,6 +240,11 @@ struct Rec {
     a2 = (double)g.y;
     e2 = g.z;
   }
+  __device__ __forceinline__ void set(float g1, float g2, float v) {
+    a1 = (double)g1;
+    a2 = (double)g2;
+    e2 = v;
+  }
 };
 
 __device__ __forceinline__ void belt_pair(double qc, double qs, float q2, const Rec& r, double& se, double& sb,
@@ -380,6 +385,145 @@ __device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s
                 },
                 A);
     }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (4 * lane + c >= len) break;  // centres past a short run are computed but not written
+    Acc64 t;
+    t.se = A.se[c];
+    t.sb = A.sb[c];
+    t.sv = A.sv[c];
+    t.sw = A.sw[c];
+    t.sn = A.sn[c];
+    write_out<float>(a.out, a.n_out, a.scale, o0 + 4 * lane + c, a.norm, t, s);
+  }
+}
+
+// ---- belt item with the source rows staged in LDS --------------------------------
+//
+// The same sums as belt_tile, member for member in the same order, with the
+// records read from LDS: for each table ring the wave copies the span of
+// 64 J consecutive records that its 256 centres' windows cover (coalesced
+// float4 loads) into its own LDS (G1, G2, E2 as separate arrays, so that a
+// lane's four consecutive records are one conflict-free 16-byte read). The
+// next ring's span and this ring's prefix lookups are requested before this
+// ring's members are summed, so their latency is hidden by the FMAs.
+
+template <int J>
+struct BeltSpan {
+  float g1[64 * J], g2[64 * J], e2[64 * J];
+};
+
+__device__ __forceinline__ float comp(const float4* c, int r) {
+  const float4 q = c[r >> 2];
+  return (r & 3) == 0 ? q.x : (r & 3) == 1 ? q.y : (r & 3) == 2 ? q.z : q.w;
+}
+
+// Four members k .. k + 3 per step for the lane's four centres (lane base
+// b): records b + k .. b + k + 6, two 16-byte reads of each array. V runs
+// are flushed at the same members as in belt_ring.
+template <int J>
+__device__ __forceinline__ void belt_ring_lds(const cdouble_t* qc, const cdouble_t* qs, const cfloat_t* q2, int cnt,
+                                              const BeltSpan<J>& sp, int b, BeltAcc& A) {
+  for (int k = 0; k < cnt; k += 4) {
+    if (k > 0 && (k & (kChunk - 1)) == 0 && k + 8 <= cnt) A.flush_v();
+    float4 x1[2], x2[2], v[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      x1[q] = *(const float4*)(sp.g1 + b + k + 4 * q);
+      x2[q] = *(const float4*)(sp.g2 + b + k + 4 * q);
+      v[q] = *(const float4*)(sp.e2 + b + k + 4 * q);
+    }
+    Rec r[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) r[m].set(comp(x1, m), comp(x2, m), comp(v, m));
+    if (k + 4 <= cnt) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) belt_member(qc, qs, q2, k + m, r[m], r[m + 1], r[m + 2], r[m + 3], A);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        if (k + m < cnt) belt_member(qc, qs, q2, k + m, r[m], r[m + 1], r[m + 2], r[m + 3], A);
+    }
+  }
+  A.flush_v();
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int J>
+__device__ __forceinline__ void belt_tile_staged(const PixelArgs& a, const ScaleArgs& s, const BeltTab& T, int64_t o0,
+                                                 int len, BeltSpan<J>& sp) {
+  const int lane = threadIdx.x & 63;
+  const int N = a.nside_in, n = 4 * N;
+  int rp, ip0;
+  pixel_ring(N, a.out_pix[o0], &rp, &ip0);
+  const cint_t* hd = (const cint_t*)T.head + 2 * (rp - N);  // (first table ring, ring count)
+  const int first = hd[0], nr = hd[1];
+  BeltAcc A;
+  float4 st[J];
+  // span of table ring i: records ip0 + off .. ip0 + off + 64 J - 1 of its ring (wrapped)
+  auto fetch = [&](int i) {
+    const cint_t* ip = (const cint_t*)T.info + 4 * (first + i);
+    const int64_t dring = 2 * (int64_t)N * (N - 1) + (int64_t)n * (ip[0] - N) - a.pix_first;
+    const int S = ip0 + ip[1];
+#pragma unroll
+    for (int j = 0; j < J; ++j) st[j] = a.map[dring + ((S + lane + 64 * j) & (n - 1))];
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int t = lane + 64 * j;
+      sp.g1[t] = st[j].x;
+      sp.g2[t] = st[j].y;
+      sp.e2[t] = st[j].z;
+    }
+  };
+  if (nr > 0) {
+    fetch(0);
+    commit();
+  }
+  wave_lds_sync();
+  for (int i = 0; i < nr; ++i) {
+    const cint_t* ip = (const cint_t*)T.info + 4 * (first + i);  // (ring, first member offset, count, coefficient offset)
+    const int4 inf = make_int4(ip[0], ip[1], ip[2], ip[3]);
+    const int cnt = inf.z;
+    const int64_t dring = 2 * (int64_t)N * (N - 1) + (int64_t)n * (inf.x - N) - a.pix_first;
+    const int j0 = (ip0 + 4 * lane + inf.y) & (n - 1);
+    // W and N_occ of each centre's window: prefix lookups now, sums after the members
+    double2 lo[4], hi[4];
+    int run[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int jc = j0 + c < n ? j0 + c : j0 + c - n;
+      run[c] = min(cnt, n - jc);
+      lo[c] = a.wn[dring + jc];
+      hi[c] = a.wn[dring + jc + run[c]];
+    }
+    if (i + 1 < nr) fetch(i + 1);
+    if (cnt > 0) {
+      const cdouble_t* qc = (const cdouble_t*)T.qc + inf.w;
+      const cdouble_t* qs = (const cdouble_t*)T.qs + inf.w;
+      const cfloat_t* q2 = (const cfloat_t*)T.q2 + inf.w;
+      belt_ring_lds(qc, qs, q2, cnt, sp, 4 * lane, A);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        A.sw[c] += hi[c].x - lo[c].x;
+        A.sn[c] += hi[c].y - lo[c].y;
+        if (run[c] < cnt) {
+          const double2 lo2 = a.wn[dring], hi2 = a.wn[dring + cnt - run[c]];
+          A.sw[c] += hi2.x - lo2.x;
+          A.sn[c] += hi2.y - lo2.y;
+        }
+      }
+    }
+    wave_lds_sync();  // every lane is done with this span
+    if (i + 1 < nr) commit();
+    wave_lds_sync();
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {

@@ -174,6 +174,7 @@ struct PixelSched {
   // launch choices (defaults from the disc size; smart_autotune measures them)
   int general_ool = 0;      // general kernel with out-of-line per-ring set-up
   int belt_blocks = 0;      // persistent blocks per CU (0: occupancy maximum)
+  int belt_cnt_max = 0;     // widest window (members per table ring) of the belt tables
   int general_blocks = 0;
   int2* head = nullptr;
   int4* info = nullptr;
@@ -207,12 +208,12 @@ void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* nrun
 hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st,
                               hipEvent_t* ev = nullptr, int kinds = 3);
 // Occupancy maxima (blocks of 256 per CU) of the pair kernels.
-int belt_blocks_max();
+int belt_blocks_max(int cnt_max);  // occupancy maximum of the belt kernel for the widest window
 int general_blocks_max(const ScaleArgs& s, int ool);
 // belt kernels (k_belt.hip)
 int build_pixel_sched(smart_plan p, int scale, hipStream_t st, PixelSched* sc);
 hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int2* items, int count,
-                       int* cursors, int blocks_per_cu, hipStream_t st);
+                       int* cursors, int blocks_per_cu, int cnt_max, hipStream_t st);
 // Compute units of the current device.
 int device_cus();
 hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, hipStream_t st);

@@ -176,7 +176,7 @@ int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st
     if (ok && sc.counts[0] > 0) {
       float best = 1e30f;
       int bb = sc.belt_blocks;
-      const int mx = belt_blocks_max();
+      const int mx = belt_blocks_max(sc.belt_cnt_max);
       for (int b = mx; b >= 1 && b >= (mx + 1) / 2 && ok; --b) {
         if (spent_ms() > budget_ms) {
           complete = false;
