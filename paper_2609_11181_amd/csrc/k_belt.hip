@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_belt_fill(PixelArgs a, ScaleArgs s, 
 // wave's LDS (windows of at most 64 J - 263 members), J = 0: records read
 // from global memory.
 template <int J>
-__global__ __launch_bounds__(kBlock) void k_pixel_belt(PixelArgs a, ScaleArgs s, BeltTab t, const int2* items,
+__global__ __launch_bounds__(kBlock, 4) void k_pixel_belt(PixelArgs a, ScaleArgs s, BeltTab t, const int2* items,
                                                        int n_items, int* cursors) {
   constexpr int JS = J > 0 ? J : 1;
   __shared__ BeltSpan<JS> spans[J > 0 ? kBlock / 64 : 1];
@@ -336,9 +336,14 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   sc->general_ool = s.theta_ap * (double)N >= 16.0 * 0.75 ? 1 : 0;
   const int n_info = last_o.x + last_c.x, n_coef = last_o.y + last_c.y;
   BCHK(hipMalloc((void**)&sc->info, sizeof(int4) * std::max(n_info, 1)));
-  BCHK(hipMalloc((void**)&sc->qc, sizeof(double) * std::max(n_coef, 1)));
-  BCHK(hipMalloc((void**)&sc->qs, sizeof(double) * std::max(n_coef, 1)));
-  BCHK(hipMalloc((void**)&sc->q2, sizeof(float) * std::max(n_coef, 1)));
+  // coefficient tables with kCoefPad entries of padding (the belt kernel
+  // requests the next four members' coefficients ahead of their use)
+  BCHK(hipMalloc((void**)&sc->qc, sizeof(double) * (n_coef + kCoefPad)));
+  BCHK(hipMalloc((void**)&sc->qs, sizeof(double) * (n_coef + kCoefPad)));
+  BCHK(hipMalloc((void**)&sc->q2, sizeof(float) * (n_coef + kCoefPad)));
+  BCHK(hipMemsetAsync(sc->qc + n_coef, 0, sizeof(double) * kCoefPad, st));
+  BCHK(hipMemsetAsync(sc->qs + n_coef, 0, sizeof(double) * kCoefPad, st));
+  BCHK(hipMemsetAsync(sc->q2 + n_coef, 0, sizeof(float) * kCoefPad, st));
   const bool table = s.filter_kind != SMART_FILTER_POLY;
   auto fill = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, a, s, cnts, offs, sc->head, sc->info, sc->qc, sc->qs,

@@ -47,6 +47,7 @@ __device__ __forceinline__ void write_out(void* out, int64_t n_out, int scale, i
 // each centre evaluates its own pairs.
 
 constexpr int kRingCap = 160;  // rings of one belt disc
+constexpr int kCoefPad = 8;    // padding entries after the belt coefficient tables
 
 // Persistent blocks (or waves) drain a tile list. The list is cut into eight
 // equal contiguous shares, one per XCD (the dispatcher deals consecutive
@@ -220,7 +221,8 @@ typedef const __attribute__((address_space(4))) int cint_t;
 // kChunk members, W and N from prefix sums.
 struct BeltAcc {
   double se[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0};
-  double sv[4] = {0.0, 0.0, 0.0, 0.0}, sw[4] = {0.0, 0.0, 0.0, 0.0}, sn[4] = {0.0, 0.0, 0.0, 0.0};
+  double sv[4] = {0.0, 0.0, 0.0, 0.0}, sw[4] = {0.0, 0.0, 0.0, 0.0};
+  int sn[4] = {0, 0, 0, 0};  // occupied pixels: prefix differences are exact integers
   float v[4] = {0.f, 0.f, 0.f, 0.f};
   __device__ __forceinline__ void flush_v() {
 #pragma unroll
@@ -362,11 +364,11 @@ __device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         A.sw[c] += hi[c].x - lo[c].x;
-        A.sn[c] += hi[c].y - lo[c].y;
+        A.sn[c] += (int)(hi[c].y - lo[c].y);
         if (run[c] < cnt) {
           const double2 lo2 = a.wn[dring], hi2 = a.wn[dring + cnt - run[c]];
           A.sw[c] += hi2.x - lo2.x;
-          A.sn[c] += hi2.y - lo2.y;
+          A.sn[c] += (int)(hi2.y - lo2.y);
         }
       }
     }
@@ -394,7 +396,7 @@ __device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s
     t.sb = A.sb[c];
     t.sv = A.sv[c];
     t.sw = A.sw[c];
-    t.sn = A.sn[c];
+    t.sn = (double)A.sn[c];
     write_out<float>(a.out, a.n_out, a.scale, o0 + 4 * lane + c, a.norm, t, s);
   }
 }
@@ -406,8 +408,8 @@ __device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s
 // 64 J consecutive records that its 256 centres' windows cover (coalesced
 // float4 loads) into its own LDS (G1, G2, E2 as separate arrays, so that a
 // lane's four consecutive records are one conflict-free 16-byte read). The
-// next ring's span and this ring's prefix lookups are requested before this
-// ring's members are summed, so their latency is hidden by the FMAs.
+// next ring's span is requested before this ring's members are summed, so
+// its latency is hidden by the FMAs.
 
 template <int J>
 struct BeltSpan {
@@ -494,30 +496,30 @@ __device__ __forceinline__ void belt_tile_staged(const PixelArgs& a, const Scale
     const int cnt = inf.z;
     const int64_t dring = 2 * (int64_t)N * (N - 1) + (int64_t)n * (inf.x - N) - a.pix_first;
     const int j0 = (ip0 + 4 * lane + inf.y) & (n - 1);
-    // W and N_occ of each centre's window: prefix lookups now, sums after the members
-    double2 lo[4], hi[4];
-    int run[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int jc = j0 + c < n ? j0 + c : j0 + c - n;
-      run[c] = min(cnt, n - jc);
-      lo[c] = a.wn[dring + jc];
-      hi[c] = a.wn[dring + jc + run[c]];
-    }
     if (i + 1 < nr) fetch(i + 1);
     if (cnt > 0) {
       const cdouble_t* qc = (const cdouble_t*)T.qc + inf.w;
       const cdouble_t* qs = (const cdouble_t*)T.qs + inf.w;
       const cfloat_t* q2 = (const cfloat_t*)T.q2 + inf.w;
       belt_ring_lds(qc, qs, q2, cnt, sp, 4 * lane, A);
+      // W and N_occ of each centre's window (prefix lookups, all in flight together)
+      double2 lo[4], hi[4];
+      int run[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int jc = j0 + c < n ? j0 + c : j0 + c - n;
+        run[c] = min(cnt, n - jc);
+        lo[c] = a.wn[dring + jc];
+        hi[c] = a.wn[dring + jc + run[c]];
+      }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         A.sw[c] += hi[c].x - lo[c].x;
-        A.sn[c] += hi[c].y - lo[c].y;
+        A.sn[c] += (int)(hi[c].y - lo[c].y);
         if (run[c] < cnt) {
           const double2 lo2 = a.wn[dring], hi2 = a.wn[dring + cnt - run[c]];
           A.sw[c] += hi2.x - lo2.x;
-          A.sn[c] += hi2.y - lo2.y;
+          A.sn[c] += (int)(hi2.y - lo2.y);
         }
       }
     }
@@ -533,7 +535,7 @@ __device__ __forceinline__ void belt_tile_staged(const PixelArgs& a, const Scale
     t.sb = A.sb[c];
     t.sv = A.sv[c];
     t.sw = A.sw[c];
-    t.sn = A.sn[c];
+    t.sn = (double)A.sn[c];
     write_out<float>(a.out, a.n_out, a.scale, o0 + 4 * lane + c, a.norm, t, s);
   }
 }
