@@ -424,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_noise_rest_walk(RestArgs n, ScaleArg
     const int64_t mstep = 2 * (int64_t)np;
     const int kc = (Y0 == 0.0 && m >= 0 && m % mstep == 0 && m / mstep < cnt) ? (int)(m / mstep) : -1;
     const int64_t dring = Q.first - a.pix_first;
-    int jw = (int)(((jlo % nq) + nq) % nq);
+    int jw = window_start(jlo, nq);
     int kdone = 0;
     while (kdone < cnt) {
       int run = min(cnt - kdone, nq - jw);

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_pixel_f64(PixelArgs a, ScaleArgs s) 
     const double cphi = kPi / ((double)np * (double)nq);
     const double Y0 = ring_y0(Q.s, Q.z, zp, sp);
     const double Kz = 2.0 * Q.z * sp;
-    int jw = (int)(((jlo % nq) + nq) % nq);
+    int jw = window_start(jlo, nq);
     const float4* base = a.map + (Q.first - a.pix_first);
     for (int k = 0; k < cnt; ++k) {
       const float4 g = base[jw];

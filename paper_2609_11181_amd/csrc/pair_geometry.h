@@ -287,6 +287,17 @@ __device__ __forceinline__ void pair_f64(double xt, double yt, double A1, double
 
 // ---- shared pieces --------------------------------------------------------
 
+// Ring index of the first window member. ring_window returns jlo in
+// [-nq/2, nq] (the centre's azimuth u0 lies in [-1/2, nq) ring steps and the
+// window's half-width is at most nq/2), so one conditional step brings it
+// into [0, nq) without a 64-bit remainder.
+__device__ __forceinline__ int window_start(int64_t jlo, int nq) {
+  int j = (int)jlo;
+  if (j < 0) j += nq;
+  else if (j >= nq) j -= nq;
+  return j;
+}
+
 // Members of ring Q for a centre at azimuth index ip2 / 2 (ip2 = 2 i + 2 o)
 // of a ring with np pixels: first unwrapped index and count. `C` is the
 // squared chord of the radius. Returns false when the ring is not reached.
@@ -299,19 +310,20 @@ __device__ __forceinline__ bool ring_window(double zp, double sp, int64_t ip2, i
   const int nq = Q.n;
   // azimuth of the centre in units of the ring step, minus the ring offset
   const double u0 = (double)ip2 * (double)nq / (2.0 * (double)np) - 0.5 * (double)Q.twice_o;
+  // (window bounds within [-nq, 2 nq]: 32-bit conversions suffice)
   if (num >= den) {
-    *jlo = (int64_t)ceil(u0 - 0.5 * nq);
+    *jlo = (int)ceil(u0 - 0.5 * nq);
     *cnt = nq;
     return true;
   }
   // |dphi| < 2 asin(sqrt(num/den)); in ring steps: asin(.) * nq / pi
   const double w = asin(sqrt(num / den)) * ((double)nq / kPi);
-  const int64_t jl = (int64_t)floor(u0 - w) + 1;
-  const int64_t jh = (int64_t)ceil(u0 + w) - 1;
-  int64_t c = jh - jl + 1;
+  const int jl = (int)floor(u0 - w) + 1;
+  const int jh = (int)ceil(u0 + w) - 1;
+  int c = jh - jl + 1;
   if (c > nq) c = nq;
   *jlo = jl;
-  *cnt = (int)c;
+  *cnt = c;
   return c > 0;
 }
 

@@ -160,7 +160,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     const int64_t mstep = 2 * (int64_t)np;
     const int kc = (Y0 == 0.0 && m >= 0 && m % mstep == 0 && m / mstep < cnt) ? (int)(m / mstep) : -1;
     const int64_t dring = Q.first - a.pix_first;
-    int jw = (int)(((jlo % nq) + nq) % nq);
+    int jw = window_start(jlo, nq);
     int kdone = 0;
     while (kdone < cnt) {
       int run = min(cnt - kdone, nq - jw);
