@@ -166,11 +166,6 @@ __global__ __launch_bounds__(kBlock, 4) void k_pixel_belt(PixelArgs a, ScaleArgs
   }
 }
 
-// staged span width (in 64-record units) for windows of at most cnt_max members, 0 for none
-int belt_span_j(int cnt_max) {
-  const int need = 263 + cnt_max;
-  return need <= 320 ? 5 : need <= 384 ? 6 : need <= 448 ? 7 : 0;
-}
 
 template <int J>
 int belt_per_cu_t() {
@@ -192,6 +187,13 @@ int belt_per_cu(int J) {
 }
 
 }  // namespace
+
+// staged span width (in 64-record units) for windows of at most cnt_max
+// members (the spans cover 256 centres + cnt_max + 7 records), 0 for none
+int belt_span_j(int cnt_max) {
+  const int need = 263 + cnt_max;
+  return need <= 320 ? 5 : need <= 384 ? 6 : need <= 448 ? 7 : 0;
+}
 
 int belt_blocks_max(int cnt_max) { return belt_per_cu(belt_span_j(cnt_max)); }
 

@@ -75,7 +75,14 @@ __device__ inline int claim_mixed(int* cursors, int n_items) {
   return n_items;
 }
 
-__global__ __launch_bounds__(kBlock) void k_mixed(const MixJob* jobs, const int4* items, int n_items, int* cursors) {
+// J > 0: belt items stage their source spans in the wave's LDS (as the
+// single-plan belt kernel does; every job's windows fit 64 J records).
+template <int J>
+// (at most 168 VGPRs: three waves per SIMD)
+__global__ __launch_bounds__(kBlock, 3) void k_mixed(const MixJob* jobs, const int4* items, int n_items,
+                                                     int* cursors) {
+  constexpr int JS = J > 0 ? J : 1;
+  __shared__ BeltSpan<JS> spans[J > 0 ? kBlock / 64 : 1];
   for (;;) {
     int it = 0;
     if ((threadIdx.x & 63) == 0) it = claim_mixed(cursors, n_items);
@@ -86,21 +93,37 @@ __global__ __launch_bounds__(kBlock) void k_mixed(const MixJob* jobs, const int4
     const int4 w = make_int4(wi[0], wi[1], wi[2], wi[3]);
     // the job through the scalar cache too: its fields are wave-uniform
     // and can be reloaded instead of held in vector registers
-    MixJob J;
-    __builtin_memcpy(&J, (const void*)((const __attribute__((address_space(4))) MixJob*)jobs + w.x), sizeof(MixJob));
+    MixJob Jb;
+    __builtin_memcpy(&Jb, (const void*)((const __attribute__((address_space(4))) MixJob*)jobs + w.x), sizeof(MixJob));
     if (w.z == 0) {
-      belt_tile(J.a, J.s, J.t, w.y, w.w);
+      if constexpr (J > 0) belt_tile_staged<JS>(Jb.a, Jb.s, Jb.t, w.y, w.w, spans[threadIdx.x >> 6]);
+      else belt_tile(Jb.a, Jb.s, Jb.t, w.y, w.w);
     } else {
-      const bool table = J.s.filter_kind != SMART_FILTER_POLY;
-      if (table && J.s.big) general_quarter<true, true>(J, w.y, w.w);
-      else if (table) general_quarter<true, false>(J, w.y, w.w);
-      else if (J.s.big) general_quarter<false, true>(J, w.y, w.w);
-      else general_quarter<false, false>(J, w.y, w.w);
+      const bool table = Jb.s.filter_kind != SMART_FILTER_POLY;
+      if (table && Jb.s.big) general_quarter<true, true>(Jb, w.y, w.w);
+      else if (table) general_quarter<true, false>(Jb, w.y, w.w);
+      else if (Jb.s.big) general_quarter<false, true>(Jb, w.y, w.w);
+      else general_quarter<false, false>(Jb, w.y, w.w);
     }
   }
 }
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// persistent grid: the occupancy maximum on every compute unit
+template <int J>
+int mixed_grid() {
+  static int grid = 0;
+  if (grid == 0) {
+    int cus = 0, per_cu = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mixed<J>, kBlock, 0) != hipSuccess || per_cu <= 0)
+      per_cu = 2;
+    grid = std::max(cus, 1) * per_cu;
+  }
+  return grid;
+}
 
 }  // namespace
 
@@ -123,6 +146,8 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
   };
   std::vector<MixJob> jobs;
   std::vector<Grp> groups;
+  std::vector<smart_plan> plans_of_job;
+  std::vector<int> scale_of_job;
   for (int p = 0; p < n_plans; ++p) {
     const smart_plan P = plans[p];
     smart_data d = P->data;
@@ -147,6 +172,8 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
       J.t = sc.tab();
       const int j = (int)jobs.size();
       jobs.push_back(J);
+      plans_of_job.push_back(P);
+      scale_of_job.push_back(k);
       const double members = 2.0 * M_PI * (1.0 - cos(P->theta_ap[k])) / omega;  // sources per disc
       // a belt pair costs about an eighth of a general pair
       if (sc.counts[0] > 0) groups.push_back({j, 0, sc.counts[0], sc.belt, 256.0 * members});
@@ -181,16 +208,22 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
     off += n;
   }
   MCHK(hipGetLastError());
-  static int grid = 0;
-  if (grid == 0) {
-    int cus = 0, per_cu = 0, dev = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mixed, kBlock, 0) != hipSuccess || per_cu <= 0)
-      per_cu = 2;
-    grid = std::max(cus, 1) * per_cu;
+  // LDS spans wide enough for every job's windows (or none when one is too wide)
+  int span_j = 5;
+  for (const Grp& g : groups)
+    if (g.kind == 0) {
+      const int j = belt_span_j(plans_of_job[g.job]->sched[scale_of_job[g.job]]->belt_cnt_max);
+      span_j = j == 0 ? 0 : (span_j == 0 ? 0 : std::max(span_j, j));
+    }
+  auto launch = [&](auto kern, int grid) {
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, st, d_jobs, items, (int)n_items, counter);
+  };
+  switch (span_j) {
+    case 5: launch(k_mixed<5>, mixed_grid<5>()); break;
+    case 6: launch(k_mixed<6>, mixed_grid<6>()); break;
+    case 7: launch(k_mixed<7>, mixed_grid<7>()); break;
+    default: launch(k_mixed<0>, mixed_grid<0>());
   }
-  hipLaunchKernelGGL(k_mixed, dim3(grid), dim3(kBlock), 0, st, d_jobs, items, (int)n_items, counter);
   MCHK(hipGetLastError());
   MCHK(hipFreeAsync(items, st));
   MCHK(hipFreeAsync(d_jobs, st));

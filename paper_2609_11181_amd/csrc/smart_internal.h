@@ -209,6 +209,7 @@ hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const Pixe
                               hipEvent_t* ev = nullptr, int kinds = 3);
 // Occupancy maxima (blocks of 256 per CU) of the pair kernels.
 int belt_blocks_max(int cnt_max);  // occupancy maximum of the belt kernel for the widest window
+int belt_span_j(int cnt_max);      // LDS span width (64-record units) of the belt kernel, 0: unstaged
 int general_blocks_max(const ScaleArgs& s, int ool);
 // belt kernels (k_belt.hip)
 int build_pixel_sched(smart_plan p, int scale, hipStream_t st, PixelSched* sc);
