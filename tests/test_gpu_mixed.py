@@ -37,6 +37,8 @@ INSTANCES = [
     (512, 30.0, [8.0], F.TANH),
     (1024, 200.0, [10.0], F.TANH),
     (512, 600.0, [20.0, 40.0], F.POLY),
+    # belt windows of about 65 members per ring: the belt kernels' wider LDS spans
+    (256, 1500.0, [660.0], F.TANH),
 ]
 
 
@@ -52,6 +54,8 @@ def test_mixed_batch_equals_single_runs_and_oracle(ctx):
         th = [t * ARCMIN for t in ths]
         plan = ctx.plan(data, L.VAR_PIXEL, nside, m["pix"], th, [ctx.filter(kind)] * len(th))
         outs_single.append(plan.run(L.NORM_SUMMED_PIXCOUNT).cpu().numpy())
+        if ths == [660.0]:  # the wide-window instance runs on the belt path
+            assert plan.tiles(0)[0].shape[0] > 0
         plans.append(plan)
         maps.append((m, th, kind))
     outs = [p.empty_out().fill_(np.nan) for p in plans]
