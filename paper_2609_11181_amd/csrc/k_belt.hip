@@ -39,12 +39,13 @@ __device__ inline void belt_span(const PixelArgs& a, double theta_ap, int rp, in
   *hi = min(*hi, a.ring_hi);
 }
 
-// cnts[rp - N] = (table rings, members) of every used centre ring.
+// widest window (members of one table ring) of the tables
 __global__ void k_info_cnt_max(const int4* info, int n, int* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n && info[i].z > 0) atomicMax(out, info[i].z);
 }
 
+// cnts[rp - N] = (table rings, members) of every used centre ring.
 __global__ void k_belt_size(PixelArgs a, double theta_ap, double C_ap, const int* used, int2* cnts) {
   const int N = a.nside_in;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;

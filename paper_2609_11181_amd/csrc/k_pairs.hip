@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_a
 // ---- pixel variant, mixed precision: general kernel -------------------------------
 
 template <bool TABLE, bool BIG, bool OOL>
-__global__ __launch_bounds__(kBlock) void k_pixel_f32(PixelArgs a, ScaleArgs s, const int* tiles, int n_tiles,
+__global__ __launch_bounds__(kBlock, 3) void k_pixel_f32(PixelArgs a, ScaleArgs s, const int* tiles, int n_tiles,
                                                       int* cursors) {
   __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
   __shared__ double tab_c0[TABLE ? kFilterIntervals : 1];

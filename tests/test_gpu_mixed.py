@@ -38,7 +38,7 @@ INSTANCES = [
     (1024, 200.0, [10.0], F.TANH),
     (512, 600.0, [20.0, 40.0], F.POLY),
     # belt windows of about 65 members per ring: the belt kernels' wider LDS spans
-    (256, 1500.0, [660.0], F.TANH),
+    (256, 3000.0, [660.0], F.TANH),
 ]
 
 
