@@ -195,12 +195,14 @@ void smart_data_free(smart_data data);
  * The plan references `data`, which must outlive it. Synchronises `stream`
  * (validation of the pixel list). Pixel-variant FP32 plans are also
  * scheduled here (Sect. 3.2: discs as index intervals on rings): the outputs
- * are cut into tiles of 256 list entries; a tile of 256 consecutive pixels
- * of an equatorial-belt ring whose discs stay in the belt is a belt tile,
- * whose pair coefficients are shared by every centre of its ring and built
- * once per scale into a per-ring table; all other tiles are general. This
- * costs one more synchronisation per scale and device memory of about
- * (number of belt rings) x (pixels per disc) x 20 bytes per scale. */
+ * are cut into tiles of 256 list entries; a tile made of at most four runs
+ * of consecutive pixels of equatorial-belt rings whose discs stay in the
+ * belt becomes belt items, whose pair coefficients are shared by every
+ * centre of their ring and built once per scale into a per-ring table; all
+ * other tiles are general. This costs one more synchronisation per scale
+ * and device memory of about (number of belt rings) x (pixels per disc) x
+ * 20 bytes per scale; the tables are filled asynchronously on `stream`, so
+ * the plan is used on `stream` (or after synchronising it). */
 int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out, int64_t n_out,
                       const int64_t* d_out_pix, int n_scales, const double* h_theta_ap, const int* h_filter_ids,
                       int precision, void* stream, smart_plan* out);

@@ -283,15 +283,15 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
     return bail(SMART_ENOMEM, "device allocation failed for the plan");
   if (n_out > 0) {
     int* flag = nullptr;
-    if (hipMalloc(&flag, sizeof(int)) != hipSuccess) return bail(SMART_ENOMEM, "allocation failed");
+    if (hipMallocAsync((void**)&flag, sizeof(int), st) != hipSuccess) return bail(SMART_ENOMEM, "allocation failed");
     int h = 0;
     hipError_t e = hipMemcpyAsync(p->out_pix, d_out_pix, sizeof(int64_t) * n_out, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int), st);
     // range check only: reuse the monotonic check and ignore its order bit
     if (e == hipSuccess) e = launch_check_pixels(p->out_pix, n_out, 12LL * nside_out * nside_out, flag, st);
     if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipFreeAsync(flag, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipFree(flag);
     if (e != hipSuccess) return bail(SMART_EDEVICE, std::string("plan validation failed: ") + hipGetErrorString(e));
     if (h & 1) return bail(SMART_EINVAL, "output pixel out of range for nside_out");
   }

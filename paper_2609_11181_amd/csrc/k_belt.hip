@@ -39,14 +39,9 @@ __device__ inline void belt_span(const PixelArgs& a, double theta_ap, int rp, in
   *hi = min(*hi, a.ring_hi);
 }
 
-// widest window (members of one table ring) of the tables
-__global__ void k_info_cnt_max(const int4* info, int n, int* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && info[i].z > 0) atomicMax(out, info[i].z);
-}
-
 // cnts[rp - N] = (table rings, members) of every used centre ring.
-__global__ void k_belt_size(PixelArgs a, double theta_ap, double C_ap, const int* used, int2* cnts) {
+// and the widest window (members of one table ring) of all tables in *cnt_max
+__global__ void k_belt_size(PixelArgs a, double theta_ap, double C_ap, const int* used, int2* cnts, int* cnt_max) {
   const int N = a.nside_in;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx > 2 * N) return;
@@ -57,13 +52,17 @@ __global__ void k_belt_size(PixelArgs a, double theta_ap, double C_ap, const int
     int lo, hi;
     belt_span(a, theta_ap, rp, &lo, &hi);
     const int nr = max(0, hi - lo + 1);
-    int total = 0;
+    int total = 0, widest = 0;
     for (int r = lo; r <= hi; ++r) {
       int64_t jlo;
       int cnt;
-      if (ring_window(R.z, R.s, R.twice_o, R.n, ring_info(N, r), C_ap, &jlo, &cnt)) total += cnt;
+      if (ring_window(R.z, R.s, R.twice_o, R.n, ring_info(N, r), C_ap, &jlo, &cnt)) {
+        total += cnt;
+        widest = max(widest, cnt);
+      }
     }
     c = make_int2(nr, total);
+    if (widest > 0) atomicMax(cnt_max, widest);
   }
   cnts[idx] = c;
 }
@@ -227,18 +226,13 @@ PixelSched::~PixelSched() {
   (void)hipFree(noise_rest);
 }
 
+// scratch of the schedule build: stream-ordered (pool) allocations, released
+// in stream order, so the build synchronises only to read the item counts
 #define BCHK(x)                                                                        \
   do {                                                                                 \
     hipError_t e_ = (x);                                                               \
     if (e_ != hipSuccess) {                                                            \
-      (void)hipFree(used);                                                             \
-      (void)hipFree(flags);                                                            \
-      (void)hipFree(keys);                                                             \
-      (void)hipFree(ids);                                                              \
-      (void)hipFree(gflags);                                                           \
-      (void)hipFree(items);                                                            \
-      (void)hipFree(cnts);                                                             \
-      (void)hipFree(offs);                                                             \
+      free_scratch();                                                                  \
       set_error(std::string("plan schedule: ") + hipGetErrorString(e_) + " at " #x); \
       return SMART_EDEVICE;                                                            \
     }                                                                                  \
@@ -272,19 +266,25 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   const int nt = (int)((p->n_out + kBlock - 1) / kBlock);
   const int ns = kRuns * nt;  // item slots
   sc->n_tiles = nt;
+  auto free_scratch = [&]() {
+    for (void* q : {(void*)used, (void*)flags, (void*)gflags, (void*)keys, (void*)ids, (void*)items, (void*)cnts,
+                    (void*)offs})
+      if (q) (void)hipFreeAsync(q, st);
+  };
   // cursors, then the two counts and the widest window
   BCHK(hipMalloc((void**)&sc->cursors, sizeof(int) * (2 * kQueueInts + 3)));
   BCHK(hipMalloc((void**)&sc->general, sizeof(int) * (nt + 1)));
-  BCHK(hipMalloc((void**)&flags, sizeof(int) * (nt + 1)));
-  BCHK(hipMalloc((void**)&gflags, sizeof(int) * (nt + 1)));
-  BCHK(hipMalloc((void**)&keys, sizeof(uint64_t) * 2 * (ns + 1)));
-  BCHK(hipMalloc((void**)&ids, sizeof(int) * 2 * (ns + 1)));
-  BCHK(hipMalloc((void**)&items, sizeof(int2) * (ns + 1)));
-  BCHK(hipMalloc((void**)&used, sizeof(int) * nb));
-  BCHK(hipMalloc((void**)&cnts, sizeof(int2) * nb));
-  BCHK(hipMalloc((void**)&offs, sizeof(int2) * nb));
   BCHK(hipMalloc((void**)&sc->head, sizeof(int2) * nb));
+  BCHK(hipMallocAsync((void**)&flags, sizeof(int) * (nt + 1), st));
+  BCHK(hipMallocAsync((void**)&gflags, sizeof(int) * (nt + 1), st));
+  BCHK(hipMallocAsync((void**)&keys, sizeof(uint64_t) * 2 * (ns + 1), st));
+  BCHK(hipMallocAsync((void**)&ids, sizeof(int) * 2 * (ns + 1), st));
+  BCHK(hipMallocAsync((void**)&items, sizeof(int2) * (ns + 1), st));
+  BCHK(hipMallocAsync((void**)&used, sizeof(int) * nb, st));
+  BCHK(hipMallocAsync((void**)&cnts, sizeof(int2) * nb, st));
+  BCHK(hipMallocAsync((void**)&offs, sizeof(int2) * nb, st));
   BCHK(hipMemsetAsync(used, 0, sizeof(int) * nb, st));
+  BCHK(hipMemsetAsync(sc->cursors + 2 * kQueueInts + 2, 0, sizeof(int), st));  // widest window
   // order of the schedule: belt items column-major (items of one azimuth
   // column on consecutive rings share their disc rows, so the items in flight
   // on one XCD stay within its L2); general tiles in list order
@@ -299,18 +299,11 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   BCHK(hipcub::DeviceSelect::Flagged(nullptr, tb4, tile_ids, gflags, sc->general, sc->cursors + 2 * kQueueInts + 1,
                                      nt, st));
   hipLaunchKernelGGL(k_belt_size, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.theta_ap, s.C_ap, used,
-                     cnts);
+                     cnts, sc->cursors + 2 * kQueueInts + 2);
   BCHK(hipGetLastError());
   BCHK(hipcub::DeviceScan::ExclusiveScan(nullptr, tb2, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
   if (ensure_temp(p->ctx, std::max(std::max(tb, tb4), std::max(tb2, tb3)))) {
-    (void)hipFree(used);
-    (void)hipFree(flags);
-    (void)hipFree(gflags);
-    (void)hipFree(cnts);
-    (void)hipFree(offs);
-    (void)hipFree(keys);
-    (void)hipFree(ids);
-    (void)hipFree(items);
+    free_scratch();
     return SMART_ENOMEM;
   }
   tb = p->ctx->temp_bytes;
@@ -322,14 +315,15 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
                                      sc->cursors + 2 * kQueueInts + 1, nt, st));
   tb = p->ctx->temp_bytes;
   BCHK(hipcub::DeviceScan::ExclusiveScan(p->ctx->d_temp, tb, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
-  int counts[2] = {0, 0};
+  int counts[3] = {0, 0, 0};  // belt items, general tiles, widest window
   int2 last_c, last_o;
-  BCHK(hipMemcpyAsync(counts, sc->cursors + 2 * kQueueInts, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  BCHK(hipMemcpyAsync(counts, sc->cursors + 2 * kQueueInts, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
   BCHK(hipMemcpyAsync(&last_c, cnts + nb - 1, sizeof(int2), hipMemcpyDeviceToHost, st));
   BCHK(hipMemcpyAsync(&last_o, offs + nb - 1, sizeof(int2), hipMemcpyDeviceToHost, st));
   BCHK(hipStreamSynchronize(st));
   sc->counts[0] = counts[0];
   sc->counts[1] = counts[1];
+  sc->belt_cnt_max = counts[2];
   BCHK(hipMalloc((void**)&sc->belt, sizeof(int2) * (counts[0] + 1)));
   if (counts[0] > 0)
     hipLaunchKernelGGL(k_gather_items, dim3((counts[0] + kBlock - 1) / kBlock), dim3(kBlock), 0, st, items,
@@ -357,23 +351,7 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   else if (s.big) fill(k_belt_fill<false, true>);
   else fill(k_belt_fill<false, false>);
   BCHK(hipGetLastError());
-  // widest window of the tables (sizes the belt kernel's LDS spans)
-  int* cmax = sc->cursors + 2 * kQueueInts + 2;
-  BCHK(hipMemsetAsync(cmax, 0, sizeof(int), st));
-  if (n_info > 0)
-    hipLaunchKernelGGL(k_info_cnt_max, dim3((n_info + kBlock - 1) / kBlock), dim3(kBlock), 0, st, sc->info, n_info,
-                       cmax);
-  BCHK(hipGetLastError());
-  BCHK(hipMemcpyAsync(&sc->belt_cnt_max, cmax, sizeof(int), hipMemcpyDeviceToHost, st));
-  BCHK(hipStreamSynchronize(st));  // the scratch below is freed next
-  (void)hipFree(used);
-  (void)hipFree(flags);
-  (void)hipFree(gflags);
-  (void)hipFree(keys);
-  (void)hipFree(ids);
-  (void)hipFree(items);
-  (void)hipFree(cnts);
-  (void)hipFree(offs);
+  free_scratch();
   return SMART_OK;
 }
 

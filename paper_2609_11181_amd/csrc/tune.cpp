@@ -15,7 +15,9 @@
 //
 // Cache: a text file, one line per tuned (workload, scale):
 //   key=<nside>/<n_out>/<n_belt>/<n_general>/<theta_ap %.9g>/<filter kind> ool=<0|1> belt=<n> general=<n>
-// Lookups match the whole key; new results are appended.
+// Lookups match the whole key; new results are appended. A file is read
+// once per process; entries written to it by other processes afterwards are
+// not seen.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +25,8 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -47,11 +51,22 @@ std::string tune_key(smart_plan p, int k) {
   return buf;
 }
 
-bool cache_lookup(const char* path, const std::string& key, Choice* c) {
-  if (!path) return false;
+// Entries of each cache file, read once per process and kept in memory
+// (lookups happen on every plan of a benchmark step); stores append to the
+// file and to the memory copy.
+std::map<std::string, std::map<std::string, Choice>>& cache_mem() {
+  static std::map<std::string, std::map<std::string, Choice>> m;
+  return m;
+}
+std::mutex cache_mu;
+
+std::map<std::string, Choice>& cache_entries(const char* path) {
+  auto& m = cache_mem();
+  auto it = m.find(path);
+  if (it != m.end()) return it->second;
+  std::map<std::string, Choice>& e = m[path];
   std::ifstream f(path);
   std::string line;
-  bool found = false;
   while (std::getline(f, line)) {
     std::istringstream ls(line);
     std::string kv, k;
@@ -65,16 +80,25 @@ bool cache_lookup(const char* path, const std::string& key, Choice* c) {
       else if (name == "belt") x.belt = atoi(val.c_str());
       else if (name == "general") x.general = atoi(val.c_str());
     }
-    if (k == key && x.ool >= 0 && x.belt >= 0 && x.general >= 0) {
-      *c = x;  // the last entry of a key wins
-      found = true;
-    }
+    if (!k.empty() && x.ool >= 0 && x.belt >= 0 && x.general >= 0) e[k] = x;  // the last entry of a key wins
   }
-  return found;
+  return e;
+}
+
+bool cache_lookup(const char* path, const std::string& key, Choice* c) {
+  if (!path) return false;
+  std::lock_guard<std::mutex> lock(cache_mu);
+  const auto& e = cache_entries(path);
+  const auto it = e.find(key);
+  if (it == e.end()) return false;
+  *c = it->second;
+  return true;
 }
 
 void cache_store(const char* path, const std::string& key, const Choice& c) {
   if (!path) return;
+  std::lock_guard<std::mutex> lock(cache_mu);
+  cache_entries(path)[key] = c;
   std::ofstream f(path, std::ios::app);
   f << "key=" << key << " ool=" << c.ool << " belt=" << c.belt << " general=" << c.general << "\n";
 }
