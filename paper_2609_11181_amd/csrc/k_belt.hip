@@ -39,6 +39,60 @@ __device__ inline void belt_span(const PixelArgs& a, double theta_ap, int rp, in
   *hi = min(*hi, a.ring_hi);
 }
 
+// General-walk tables. gt_head[rp] for every centre ring: (entries of the
+// ring pairs, first source ring, last source ring), the same source rings
+// as the per-centre walk (ring span of the disc, clipped to the map's rings).
+__global__ void k_gen_span(PixelArgs a, double theta_ap, int4* head, int* cnt) {
+  const int rp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rp >= 4 * a.nside_out) return;
+  int lo = 0, hi = -1;
+  if (rp >= 1) {
+    const Ring R = ring_info(a.nside_out, rp);
+    ring_span(a.nside_in, atan2(R.s, R.z), theta_ap, &lo, &hi);
+    lo = max(lo, a.ring_lo);
+    hi = min(hi, a.ring_hi);
+  }
+  head[rp] = make_int4(0, lo, hi, 0);
+  cnt[rp] = max(0, hi - lo + 1);
+}
+
+__global__ void k_gen_fill(PixelArgs a, double C_ap, const int* off, int4* head, GenPair* pairs) {
+  const int rp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rp >= 4 * a.nside_out) return;
+  int4 h = head[rp];
+  h.x = off[rp];
+  head[rp] = h;
+  if (rp < 1) return;
+  const Ring R = ring_info(a.nside_out, rp);
+  for (int r = h.y; r <= h.z; ++r) {
+    const Ring Q = ring_info(a.nside_in, r);
+    const PairWin pw = ring_pair_window(R.z, R.s, Q, C_ap);
+    GenPair e;
+    e.w = pw.w;
+    e.kind = pw.kind;
+    e.pad = 0;
+    e.Y0 = ring_y0(Q.s, Q.z, R.z, R.s);
+    e.Kz = 2.0 * Q.z * R.s;
+    pairs[h.x + (r - h.y)] = e;
+  }
+}
+
+__global__ void k_gen_rings(int nside, GenRingC* rings) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 4 * nside) return;
+  GenRingC c{};
+  if (r >= 1) {
+    const Ring Q = ring_info(nside, r);
+    c.z = Q.z;
+    c.s = Q.s;
+    c.first = Q.first;
+    c.n = Q.n;
+    c.twice_o = Q.twice_o;
+    sin_hav(2.0 * kPi / (double)Q.n, &c.sd, &c.hd);
+  }
+  rings[r] = c;
+}
+
 // cnts[rp - N] = (table rings, members) of every used centre ring.
 // and the widest window (members of one table ring) of all tables in *cnt_max
 __global__ void k_belt_size(PixelArgs a, double theta_ap, double C_ap, const int* used, int2* cnts, int* cnt_max) {
@@ -213,6 +267,9 @@ hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t,
 }
 
 PixelSched::~PixelSched() {
+  (void)hipFree(gt_head);
+  (void)hipFree(gt_pair);
+  (void)hipFree(gt_ring);
   (void)hipFree(belt);
   (void)hipFree(general);
   (void)hipFree(cursors);
@@ -238,6 +295,9 @@ PixelSched::~PixelSched() {
     }                                                                                  \
   } while (0)
 
+// general-walk ring-pair entries kept at most (32 B each)
+constexpr int64_t kGenPairMax = int64_t(1) << 25;
+
 int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   if (p->n_out == 0) return SMART_OK;  // nothing to schedule
   smart_data d = p->data;
@@ -262,13 +322,15 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   int* ids = nullptr;        // slot ids, sorted slot ids
   int2* items = nullptr;     // item slots
   int* gflags = nullptr;     // per tile: 1 when general
+  int* gcnt = nullptr;       // per centre ring: source rings of the general walk, then their offsets
   const int nb = 2 * N + 1;  // belt rings N .. 3N
+  const int nr4 = 4 * N;     // centre rings 1 .. 4N - 1 (index 0 unused)
   const int nt = (int)((p->n_out + kBlock - 1) / kBlock);
   const int ns = kRuns * nt;  // item slots
   sc->n_tiles = nt;
   auto free_scratch = [&]() {
     for (void* q : {(void*)used, (void*)flags, (void*)gflags, (void*)keys, (void*)ids, (void*)items, (void*)cnts,
-                    (void*)offs})
+                    (void*)offs, (void*)gcnt})
       if (q) (void)hipFreeAsync(q, st);
   };
   // cursors, then the two counts and the widest window
@@ -283,8 +345,15 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   BCHK(hipMallocAsync((void**)&used, sizeof(int) * nb, st));
   BCHK(hipMallocAsync((void**)&cnts, sizeof(int2) * nb, st));
   BCHK(hipMallocAsync((void**)&offs, sizeof(int2) * nb, st));
+  BCHK(hipMallocAsync((void**)&gcnt, sizeof(int) * 2 * nr4, st));
+  BCHK(hipMalloc((void**)&sc->gt_head, sizeof(int4) * nr4));
+  BCHK(hipMalloc((void**)&sc->gt_ring, sizeof(GenRingC) * nr4));
   BCHK(hipMemsetAsync(used, 0, sizeof(int) * nb, st));
   BCHK(hipMemsetAsync(sc->cursors + 2 * kQueueInts + 2, 0, sizeof(int), st));  // widest window
+  hipLaunchKernelGGL(k_gen_span, dim3((nr4 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.theta_ap, sc->gt_head,
+                     gcnt);
+  hipLaunchKernelGGL(k_gen_rings, dim3((nr4 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, N, sc->gt_ring);
+  BCHK(hipGetLastError());
   // order of the schedule: belt items column-major (items of one azimuth
   // column on consecutive rings share their disc rows, so the items in flight
   // on one XCD stay within its L2); general tiles in list order
@@ -302,6 +371,9 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
                      cnts, sc->cursors + 2 * kQueueInts + 2);
   BCHK(hipGetLastError());
   BCHK(hipcub::DeviceScan::ExclusiveScan(nullptr, tb2, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
+  size_t tb5 = 0;
+  BCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb5, gcnt, gcnt + nr4, nr4, st));
+  tb2 = std::max(tb2, tb5);
   if (ensure_temp(p->ctx, std::max(std::max(tb, tb4), std::max(tb2, tb3)))) {
     free_scratch();
     return SMART_ENOMEM;
@@ -315,8 +387,13 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
                                      sc->cursors + 2 * kQueueInts + 1, nt, st));
   tb = p->ctx->temp_bytes;
   BCHK(hipcub::DeviceScan::ExclusiveScan(p->ctx->d_temp, tb, cnts, offs, Sum2i(), make_int2(0, 0), nb, st));
+  tb = p->ctx->temp_bytes;
+  BCHK(hipcub::DeviceScan::ExclusiveSum(p->ctx->d_temp, tb, gcnt, gcnt + nr4, nr4, st));
   int counts[3] = {0, 0, 0};  // belt items, general tiles, widest window
   int2 last_c, last_o;
+  int gt_last[2] = {0, 0};  // count and offset of the last centre ring's entries
+  BCHK(hipMemcpyAsync(&gt_last[0], gcnt + nr4 - 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  BCHK(hipMemcpyAsync(&gt_last[1], gcnt + 2 * nr4 - 1, sizeof(int), hipMemcpyDeviceToHost, st));
   BCHK(hipMemcpyAsync(counts, sc->cursors + 2 * kQueueInts, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
   BCHK(hipMemcpyAsync(&last_c, cnts + nb - 1, sizeof(int2), hipMemcpyDeviceToHost, st));
   BCHK(hipMemcpyAsync(&last_o, offs + nb - 1, sizeof(int2), hipMemcpyDeviceToHost, st));
@@ -324,6 +401,19 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   sc->counts[0] = counts[0];
   sc->counts[1] = counts[1];
   sc->belt_cnt_max = counts[2];
+  // ring-pair entries of the general walk (kept only when they fit kGenPairMax)
+  const int64_t n_pairs = (int64_t)gt_last[0] + gt_last[1];
+  if (counts[1] > 0 && n_pairs <= kGenPairMax) {
+    BCHK(hipMalloc((void**)&sc->gt_pair, sizeof(GenPair) * std::max<int64_t>(n_pairs, 1)));
+    hipLaunchKernelGGL(k_gen_fill, dim3((nr4 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.C_ap, gcnt + nr4,
+                       sc->gt_head, sc->gt_pair);
+    BCHK(hipGetLastError());
+  } else {
+    (void)hipFree(sc->gt_head);
+    (void)hipFree(sc->gt_ring);
+    sc->gt_head = nullptr;
+    sc->gt_ring = nullptr;
+  }
   BCHK(hipMalloc((void**)&sc->belt, sizeof(int2) * (counts[0] + 1)));
   if (counts[0] > 0)
     hipLaunchKernelGGL(k_gather_items, dim3((counts[0] + kBlock - 1) / kBlock), dim3(kBlock), 0, st, items,

@@ -169,6 +169,9 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
       J.a.out = outs[p];
       J.a.norm = norms[p];
       J.a.scale = k;
+      J.a.gt_head = sc.gt_head;
+      J.a.gt_pair = sc.gt_pair;
+      J.a.gt_ring = sc.gt_ring;
       J.t = sc.tab();
       const int j = (int)jobs.size();
       jobs.push_back(J);

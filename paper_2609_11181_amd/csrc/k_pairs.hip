@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_a
 
 // ---- pixel variant, mixed precision: general kernel -------------------------------
 
-template <bool TABLE, bool BIG, bool OOL>
+template <bool TABLE, bool BIG, bool OOL, int GT>
 __global__ __launch_bounds__(kBlock, 3) void k_pixel_f32(PixelArgs a, ScaleArgs s, const int* tiles, int n_tiles,
                                                       int* cursors) {
   __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_pixel_f32(PixelArgs a, ScaleArgs 
     const int item = next_tile(cursors, n_tiles, &s_item);  // also orders the table load
     if (item < 0) break;
     const int tile = tiles ? tiles[item] : item;
-    general_centre<TABLE, BIG, OOL>(a, s, (int64_t)tile * kBlock + threadIdx.x, tp, tab);
+    general_centre<TABLE, BIG, OOL, GT>(a, s, (int64_t)tile * kBlock + threadIdx.x, tp, tab);
   }
 }
 
@@ -396,44 +396,58 @@ static int persistent_grid(K kernel) {
   return device_cus() * persistent_per_cu(kernel);
 }
 
-template <bool TABLE, bool BIG, bool OOL>
+template <bool TABLE, bool BIG, bool OOL, int GT>
 static hipError_t launch_general_t(const PixelArgs& a, const ScaleArgs& s, hipStream_t st, const int* list,
                                    int count, int* cursors, int blocks_per_cu) {
-  static const int per_cu = persistent_per_cu(k_pixel_f32<TABLE, BIG, OOL>);
+  static const int per_cu = persistent_per_cu(k_pixel_f32<TABLE, BIG, OOL, GT>);
   const int grid = device_cus() * (blocks_per_cu > 0 ? std::min(blocks_per_cu, per_cu) : per_cu);
-  hipLaunchKernelGGL((k_pixel_f32<TABLE, BIG, OOL>), dim3(grid), dim3(kBlock), 0, st, a, s, list, count, cursors);
+  hipLaunchKernelGGL((k_pixel_f32<TABLE, BIG, OOL, GT>), dim3(grid), dim3(kBlock), 0, st, a, s, list, count,
+                     cursors);
   return hipGetLastError();
+}
+
+// kernel variant: filter table, long asin series, out-of-line set-up, ring-pair tables
+template <int GT>
+static hipError_t launch_general_g(const PixelArgs& a, const ScaleArgs& s, hipStream_t st, const int* list,
+                                   int count, int* cursors, int ool, int blocks_per_cu) {
+  const bool table = s.filter_kind != SMART_FILTER_POLY;
+  const int c = (table ? 4 : 0) + (s.big ? 2 : 0) + (ool ? 1 : 0);
+  switch (c) {
+    case 0: return launch_general_t<false, false, false, GT>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 1: return launch_general_t<false, false, true, GT>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 2: return launch_general_t<false, true, false, GT>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 3: return launch_general_t<false, true, true, GT>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 4: return launch_general_t<true, false, false, GT>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 5: return launch_general_t<true, false, true, GT>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 6: return launch_general_t<true, true, false, GT>(a, s, st, list, count, cursors, blocks_per_cu);
+    default: return launch_general_t<true, true, true, GT>(a, s, st, list, count, cursors, blocks_per_cu);
+  }
 }
 
 static hipError_t launch_general(const PixelArgs& a, const ScaleArgs& s, hipStream_t st, const int* list, int count,
                                  int* cursors, int ool = 0, int blocks_per_cu = 0) {
+  return a.gt_head ? launch_general_g<1>(a, s, st, list, count, cursors, ool, blocks_per_cu)
+                   : launch_general_g<0>(a, s, st, list, count, cursors, ool, blocks_per_cu);
+}
+
+template <int GT>
+static int general_blocks_max_g(const ScaleArgs& s, int ool) {
   const bool table = s.filter_kind != SMART_FILTER_POLY;
   const int c = (table ? 4 : 0) + (s.big ? 2 : 0) + (ool ? 1 : 0);
   switch (c) {
-    case 0: return launch_general_t<false, false, false>(a, s, st, list, count, cursors, blocks_per_cu);
-    case 1: return launch_general_t<false, false, true>(a, s, st, list, count, cursors, blocks_per_cu);
-    case 2: return launch_general_t<false, true, false>(a, s, st, list, count, cursors, blocks_per_cu);
-    case 3: return launch_general_t<false, true, true>(a, s, st, list, count, cursors, blocks_per_cu);
-    case 4: return launch_general_t<true, false, false>(a, s, st, list, count, cursors, blocks_per_cu);
-    case 5: return launch_general_t<true, false, true>(a, s, st, list, count, cursors, blocks_per_cu);
-    case 6: return launch_general_t<true, true, false>(a, s, st, list, count, cursors, blocks_per_cu);
-    default: return launch_general_t<true, true, true>(a, s, st, list, count, cursors, blocks_per_cu);
+    case 0: return persistent_per_cu(k_pixel_f32<false, false, false, GT>);
+    case 1: return persistent_per_cu(k_pixel_f32<false, false, true, GT>);
+    case 2: return persistent_per_cu(k_pixel_f32<false, true, false, GT>);
+    case 3: return persistent_per_cu(k_pixel_f32<false, true, true, GT>);
+    case 4: return persistent_per_cu(k_pixel_f32<true, false, false, GT>);
+    case 5: return persistent_per_cu(k_pixel_f32<true, false, true, GT>);
+    case 6: return persistent_per_cu(k_pixel_f32<true, true, false, GT>);
+    default: return persistent_per_cu(k_pixel_f32<true, true, true, GT>);
   }
 }
 
-int general_blocks_max(const ScaleArgs& s, int ool) {
-  const bool table = s.filter_kind != SMART_FILTER_POLY;
-  const int c = (table ? 4 : 0) + (s.big ? 2 : 0) + (ool ? 1 : 0);
-  switch (c) {
-    case 0: return persistent_per_cu(k_pixel_f32<false, false, false>);
-    case 1: return persistent_per_cu(k_pixel_f32<false, false, true>);
-    case 2: return persistent_per_cu(k_pixel_f32<false, true, false>);
-    case 3: return persistent_per_cu(k_pixel_f32<false, true, true>);
-    case 4: return persistent_per_cu(k_pixel_f32<true, false, false>);
-    case 5: return persistent_per_cu(k_pixel_f32<true, false, true>);
-    case 6: return persistent_per_cu(k_pixel_f32<true, true, false>);
-    default: return persistent_per_cu(k_pixel_f32<true, true, true>);
-  }
+int general_blocks_max(const ScaleArgs& s, int ool, bool tables) {
+  return tables ? general_blocks_max_g<1>(s, ool) : general_blocks_max_g<0>(s, ool);
 }
 
 __global__ void k_zero_ints(int* p, int n) {
@@ -453,8 +467,12 @@ hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, h
   return launch_general(a, s, st, nullptr, (int)blocks_for(a.n_out), d_work);
 }
 
-hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const PixelSched& sc, hipStream_t st,
+hipError_t launch_pixel_sched(const PixelArgs& a0, const ScaleArgs& s, const PixelSched& sc, hipStream_t st,
                               hipEvent_t* ev, int kinds) {
+  PixelArgs a = a0;  // with the schedule's general-walk tables
+  a.gt_head = sc.gt_head;
+  a.gt_pair = sc.gt_pair;
+  a.gt_ring = sc.gt_ring;
   hipError_t e = hipSuccess;
   if (a.n_out > 0) hipLaunchKernelGGL(k_zero_ints, dim3(2), dim3(kQueueInts), 0, st, sc.cursors, 2 * kQueueInts);
   if (ev) e = hipEventRecord(ev[0], st);

@@ -298,33 +298,53 @@ __device__ __forceinline__ int window_start(int64_t jlo, int nq) {
   return j;
 }
 
-// Members of ring Q for a centre at azimuth index ip2 / 2 (ip2 = 2 i + 2 o)
-// of a ring with np pixels: first unwrapped index and count. `C` is the
-// squared chord of the radius. Returns false when the ring is not reached.
-__device__ __forceinline__ bool ring_window(double zp, double sp, int64_t ip2, int np, const Ring& Q, double C,
-                                            int64_t* jlo, int* cnt) {
+// Window of ring Q for a centre ring (zp, sp), independent of the centre's
+// azimuth: kind 0 when no point of Q is within the chord C, 2 when the
+// whole ring is, else 1 with the half-width w in ring steps:
+// |dphi| < 2 asin(sqrt(num/den)) from |r_p - r_j|^2 = (z_p - z')^2 +
+// (s_p - s')^2 + 4 s_p s' sin^2(dphi/2).
+struct PairWin {
+  double w;
+  int kind;
+};
+
+__host__ __device__ __forceinline__ PairWin ring_pair_window(double zp, double sp, const Ring& Q, double C) {
   const double dz = zp - Q.z, ds = sp - Q.s;
   const double num = C - (dz * dz + ds * ds);
-  if (!(num > 0.0)) return false;
+  if (!(num > 0.0)) return PairWin{0.0, 0};
   const double den = 4.0 * sp * Q.s;
-  const int nq = Q.n;
+  if (num >= den) return PairWin{0.0, 2};
+  return PairWin{asin(sqrt(num / den)) * ((double)Q.n / kPi), 1};
+}
+
+// Members of a ring of nq pixels (azimuth offset twice_o / 2) for a centre
+// at azimuth index ip2 / 2 (ip2 = 2 i + 2 o) of a ring with np pixels:
+// first unwrapped index and count (window bounds within [-nq, 2 nq]: 32-bit
+// conversions suffice). Returns false when the ring is not reached.
+__device__ __forceinline__ bool window_at(const PairWin& pw, int64_t ip2, int np, int nq, int twice_o, int64_t* jlo,
+                                          int* cnt) {
+  if (pw.kind == 0) return false;
   // azimuth of the centre in units of the ring step, minus the ring offset
-  const double u0 = (double)ip2 * (double)nq / (2.0 * (double)np) - 0.5 * (double)Q.twice_o;
-  // (window bounds within [-nq, 2 nq]: 32-bit conversions suffice)
-  if (num >= den) {
+  const double u0 = (double)ip2 * (double)nq / (2.0 * (double)np) - 0.5 * (double)twice_o;
+  if (pw.kind == 2) {
     *jlo = (int)ceil(u0 - 0.5 * nq);
     *cnt = nq;
     return true;
   }
-  // |dphi| < 2 asin(sqrt(num/den)); in ring steps: asin(.) * nq / pi
-  const double w = asin(sqrt(num / den)) * ((double)nq / kPi);
-  const int jl = (int)floor(u0 - w) + 1;
-  const int jh = (int)ceil(u0 + w) - 1;
+  const int jl = (int)floor(u0 - pw.w) + 1;
+  const int jh = (int)ceil(u0 + pw.w) - 1;
   int c = jh - jl + 1;
   if (c > nq) c = nq;
   *jlo = jl;
   *cnt = c;
   return c > 0;
+}
+
+// Members of ring Q for a centre at azimuth index ip2 / 2 of a ring
+// (zp, sp) with np pixels. `C` is the squared chord of the radius.
+__device__ __forceinline__ bool ring_window(double zp, double sp, int64_t ip2, int np, const Ring& Q, double C,
+                                            int64_t* jlo, int* cnt) {
+  return window_at(ring_pair_window(zp, sp, Q, C), ip2, np, Q.n, Q.twice_o, jlo, cnt);
 }
 
 }  // namespace smart

@@ -117,7 +117,9 @@ __device__ __forceinline__ void general_member(double sa, double h, double sp, d
 // and haversine follow from the previous member's by the angle-difference
 // identities (RingStep) instead of a series per member. A window that wraps
 // past the ring's last pixel is walked as two contiguous runs.
-template <bool TABLE, bool BIG, bool OOL>
+// GT: 1 = the plan's ring-pair tables are present, 0 = absent, 2 = test at
+// run time.
+template <bool TABLE, bool BIG, bool OOL, int GT = 2>
 __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleArgs& s, int64_t o, const double* tp,
                                                Tab tab) {
   if (o >= a.n_out) return;
@@ -128,38 +130,65 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
   const double zp = R.z, sp = R.s;
   const int np = R.n;
   const int64_t ip2 = 2 * (int64_t)ip + R.twice_o;
-  int lo, hi;
-  if (OOL) general_span(a.nside_in, sp, zp, s.theta_ap, &lo, &hi);
-  else ring_span(a.nside_in, atan2(sp, zp), s.theta_ap, &lo, &hi);
-  lo = max(lo, a.ring_lo);
-  hi = min(hi, a.ring_hi);
+  // the centre ring's source rings and their ring-pair terms come from the
+  // plan's tables when it has them (the same values, computed once per ring
+  // pair instead of once per centre)
+  const bool gt = GT == 2 ? a.gt_head != nullptr : GT == 1;
+  int lo, hi, e0 = 0;
+  if (gt) {
+    const int4 h = a.gt_head[rp];
+    e0 = h.x - h.y;
+    lo = h.y;
+    hi = h.z;
+  } else {
+    if (OOL) general_span(a.nside_in, sp, zp, s.theta_ap, &lo, &hi);
+    else ring_span(a.nside_in, atan2(sp, zp), s.theta_ap, &lo, &hi);
+    lo = max(lo, a.ring_lo);
+    hi = min(hi, a.ring_hi);
+  }
 
   Acc64 tot;
   for (int r = lo; r <= hi; ++r) {
-    const Ring Q = ring_info(a.nside_in, r);
-    int64_t jlo;
-    int cnt;
-    const bool reached = OOL ? general_window(zp, sp, ip2, np, Q, s.C_ap, &jlo, &cnt)
-                             : ring_window(zp, sp, ip2, np, Q, s.C_ap, &jlo, &cnt);
-    if (!reached) continue;
-    const int nq = Q.n;
-    const double Y0 = ring_y0(Q.s, Q.z, zp, sp);
-    const double Kz = 2.0 * Q.z * sp;
+    int64_t jlo, first;
+    int cnt, nq, twice_o;
+    double Y0, Kz;
+    RingStep step;
+    if (gt) {
+      const GenPair e = a.gt_pair[e0 + r];
+      const GenRingC q = a.gt_ring[r];
+      nq = q.n;
+      twice_o = q.twice_o;
+      if (!window_at(PairWin{e.w, e.kind}, ip2, np, nq, twice_o, &jlo, &cnt)) continue;
+      Y0 = e.Y0;
+      Kz = e.Kz;
+      first = q.first;
+      step.sd = q.sd;
+      step.hd = q.hd;
+    } else {
+      const Ring Q = ring_info(a.nside_in, r);
+      const bool reached = OOL ? general_window(zp, sp, ip2, np, Q, s.C_ap, &jlo, &cnt)
+                               : ring_window(zp, sp, ip2, np, Q, s.C_ap, &jlo, &cnt);
+      if (!reached) continue;
+      nq = Q.n;
+      twice_o = Q.twice_o;
+      Y0 = ring_y0(Q.s, Q.z, zp, sp);
+      Kz = 2.0 * Q.z * sp;
+      first = Q.first;
+      if (OOL) general_sin_hav(2.0 * kPi / (double)nq, &step.sd, &step.hd);
+      else sin_hav(2.0 * kPi / (double)nq, &step.sd, &step.hd);
+    }
+    step.finish();
     // dphi of the first member = pi m / (np nq) with m an exact integer
-    const int64_t m = ip2 * nq - (2 * jlo + Q.twice_o) * (int64_t)np;
+    const int64_t m = ip2 * nq - (2 * jlo + twice_o) * (int64_t)np;
     double sa, h;
     const double av = (double)m * (kPi / ((double)np * (double)nq));
     if (OOL) general_sin_hav(av, &sa, &h);
     else sin_hav(av, &sa, &h);
-    RingStep step;
-    if (OOL) general_sin_hav(2.0 * kPi / (double)nq, &step.sd, &step.hd);
-    else sin_hav(2.0 * kPi / (double)nq, &step.sd, &step.hd);
-    step.finish();
     // the member at the centre itself (same ring, dphi = 0), if any: the walk
     // restarts there from exact zeros, so its shear term vanishes exactly
     const int64_t mstep = 2 * (int64_t)np;
     const int kc = (Y0 == 0.0 && m >= 0 && m % mstep == 0 && m / mstep < cnt) ? (int)(m / mstep) : -1;
-    const int64_t dring = Q.first - a.pix_first;
+    const int64_t dring = first - a.pix_first;
     int jw = window_start(jlo, nq);
     int kdone = 0;
     while (kdone < cnt) {

@@ -122,6 +122,24 @@ struct ScaleArgs {
   int n_samples;
 };
 
+// Ring-pair table of the general walk (built at plan creation): for a
+// centre ring and a source ring, the window half-width in ring steps (kind
+// 1), a whole-ring window (kind 2) or no member (kind 0), and the two ring
+// terms of the tangent-plane y component.
+struct GenPair {
+  double w, Y0, Kz;
+  int kind, pad;
+};
+
+// Source-ring constants of the general walk: colatitude cosine and sine,
+// the sine and haversine of one azimuth step, first pixel, pixel count,
+// twice the azimuth offset.
+struct GenRingC {
+  double z, s, sd, hd;
+  int64_t first;
+  int n, twice_o;
+};
+
 struct PixelArgs {
   const int64_t* out_pix;
   int64_t n_out;
@@ -134,6 +152,10 @@ struct PixelArgs {
   void* out;          // [scale][5][n_out]
   int norm;
   int scale;
+  // general-walk tables of the scale (null: computed per centre)
+  const int4* gt_head;      // [centre ring] = (first pair entry, first source ring, last source ring)
+  const GenPair* gt_pair;
+  const GenRingC* gt_ring;  // [source ring]
 };
 
 struct GalaxyArgs {
@@ -175,6 +197,9 @@ struct PixelSched {
   int general_ool = 0;      // general kernel with out-of-line per-ring set-up
   int belt_blocks = 0;      // persistent blocks per CU (0: occupancy maximum)
   int belt_cnt_max = 0;     // widest window (members per table ring) of the belt tables
+  int4* gt_head = nullptr;  // general-walk tables (see GenPair), or null when too large
+  GenPair* gt_pair = nullptr;
+  GenRingC* gt_ring = nullptr;
   int general_blocks = 0;
   int2* head = nullptr;
   int4* info = nullptr;
@@ -210,7 +235,7 @@ hipError_t launch_pixel_sched(const PixelArgs& a, const ScaleArgs& s, const Pixe
 // Occupancy maxima (blocks of 256 per CU) of the pair kernels.
 int belt_blocks_max(int cnt_max);  // occupancy maximum of the belt kernel for the widest window
 int belt_span_j(int cnt_max);      // LDS span width (64-record units) of the belt kernel, 0: unstaged
-int general_blocks_max(const ScaleArgs& s, int ool);
+int general_blocks_max(const ScaleArgs& s, int ool, bool tables);
 // belt kernels (k_belt.hip)
 int build_pixel_sched(smart_plan p, int scale, hipStream_t st, PixelSched* sc);
 hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t, const int2* items, int count,

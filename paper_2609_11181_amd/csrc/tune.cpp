@@ -174,7 +174,7 @@ int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st
       float best[2] = {1e30f, 1e30f};
       int best_b[2] = {sc.general_blocks, sc.general_blocks};
       for (int ool = 0; ool < 2 && ok; ++ool) {
-        const int mx = general_blocks_max(s, ool);
+        const int mx = general_blocks_max(s, ool, sc.gt_head != nullptr);
         for (int b = mx; b >= 1 && b >= mx - 1 && ok; --b) {
           if (spent_ms() > budget_ms) {
             complete = false;
