@@ -506,7 +506,7 @@ def main():
     if cpu is not None:
         out_pix, refs, cpairs, cdt, workers = cpu
         idx = np.searchsorted(pm["pix"], out_pix)
-        errs, errs_patch, floor = [], [], []
+        errs, errs_patch, floor, errs_f32 = [], [], [], []
         for k, r in enumerate(refs):
             full = outs[k][0, 0].double()
             map_rms = float(torch.sqrt(torch.mean(full * full)))  # RMS of the whole M_E map
@@ -519,11 +519,13 @@ def main():
             # the FP32 output format alone: the oracle values rounded to float
             f32 = r["M_E"][ok].astype(np.float32).astype(np.float64)
             floor.append(float(np.max(np.abs(f32 - r["M_E"][ok]))) / map_rms)
+            errs_f32.append(float(np.max(np.abs(g[ok] - f32))) / map_rms)
         res["max_rel_err_vs_oracle"] = errs
         res["accuracy"] = {
             "metric": "max |M_E - oracle| over the sample / RMS of the whole M_E map, per scale",
             "max_err_over_patch_rms": errs_patch,
             "f32_output_rounding_floor": floor,
+            "max_err_vs_oracle_rounded_to_f32": errs_f32,
             "sample": f"{out_pix.size} apertures in a 2-degree patch, 5/10/20 arcmin",
         }
         res["cpu_baseline"] = {
