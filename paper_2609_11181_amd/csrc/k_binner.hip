@@ -315,9 +315,7 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
 // error near 1e-16 * (total W / run W), below 1e-9 for any map that fits.
 //
 // Three passes over chunks of kScanChunk pixels (reduce, scan of the chunk
-// totals, rescan and write); the two reading passes stream the map's records
-// coalesced, the writing pass scans contiguous runs of kScanPer pixels per
-// thread from LDS.
+// totals, rescan and write); every pass streams the map's records coalesced.
 constexpr int kScanPer = 16;
 constexpr int kScanChunk = kBlock * kScanPer;
 
@@ -387,30 +385,33 @@ __global__ __launch_bounds__(kBlock) void k_wn_scan_blocks(double2* blk, int nb)
   }
 }
 
+// Rows of kBlock consecutive pixels (coalesced loads and stores): each row
+// is scanned across the block (wave scans, then the four wave totals) and
+// carried into the next row.
 __global__ __launch_bounds__(kBlock) void k_wn_write(const float4* sums, int64_t n, const double2* blk,
                                                      double2* wn) {
-  __shared__ float w[kBlock * (kScanPer + 1)];  // thread t's run at t * (kScanPer + 1): no bank conflicts
   __shared__ double2 red[kBlock / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-#pragma unroll 4
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double2 carry = blk[blockIdx.x];
   for (int j = 0; j < kScanPer; ++j) {
-    const int e = j * kBlock + threadIdx.x;  // element of the chunk
-    const int64_t i = base + e;
-    w[(e / kScanPer) * (kScanPer + 1) + e % kScanPer] = i < n ? sums[i].w : 0.f;
-  }
-  __syncthreads();
-  const float* mine = w + threadIdx.x * (kScanPer + 1);
-  double2 v = make_double2(0.0, 0.0);
-  for (int j = 0; j < kScanPer; ++j) {
-    v.x += (double)mine[j];
-    v.y += mine[j] > 0.f ? 1.0 : 0.0;
-  }
-  double2 run = block_exscan2(v, blk[blockIdx.x], red);
-  const int64_t first = base + (int64_t)threadIdx.x * kScanPer;
-  for (int j = 0; j < kScanPer; ++j) {
-    if (first + j >= n) break;
-    run = make_double2(run.x + (double)mine[j], run.y + (mine[j] > 0.f ? 1.0 : 0.0));
-    wn[first + j + 1] = run;
+    const int64_t i = base + (int64_t)j * kBlock + threadIdx.x;
+    const float w = i < n ? sums[i].w : 0.f;
+    const double2 v = make_double2((double)w, w > 0.f ? 1.0 : 0.0);
+    double2 inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const double x = __shfl_up(inc.x, o), y = __shfl_up(inc.y, o);
+      if (lane >= o) inc = add2(inc, make_double2(x, y));
+    }
+    if (lane == 63) red[wave] = inc;
+    __syncthreads();
+    double2 off = carry;
+    for (int q = 0; q < wave; ++q) off = add2(off, red[q]);
+    double2 row = carry;
+    for (int q = 0; q < kBlock / 64; ++q) row = add2(row, red[q]);
+    __syncthreads();
+    if (i < n) wn[i + 1] = add2(off, inc);
+    carry = row;
   }
 }
 
