@@ -112,29 +112,6 @@ __device__ __forceinline__ void accumulate_pix(const Coef& c, float4 g, Acc64& t
   sv = fmaf(c.q2, g.z, sv);
 }
 
-// Four interleaved partial E/B/V sums for runs of pixel members that share
-// precomputed coefficients: member u goes to partial u % 4, so consecutive
-// members do not wait on each other's FMA results.
-struct Part4 {
-  double se[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0};
-  float sv[4] = {0.f, 0.f, 0.f, 0.f};
-  __device__ __forceinline__ void add(int u, const Coef& c, float4 g) {
-    const double a1 = (double)g.x, a2 = (double)g.y;
-    se[u & 3] = fma(c.qc, a1, fma(c.qs, a2, se[u & 3]));
-    sb[u & 3] = fma(c.qc, a2, fma(-c.qs, a1, sb[u & 3]));
-    sv[u & 3] = fmaf(c.q2, g.z, sv[u & 3]);
-  }
-  __device__ __forceinline__ void flush_v(Acc64& tot) {
-    tot.sv += (double)((sv[0] + sv[1]) + (sv[2] + sv[3]));
-    sv[0] = sv[1] = sv[2] = sv[3] = 0.f;
-  }
-  __device__ __forceinline__ void flush(Acc64& tot) {
-    tot.se += (se[0] + se[1]) + (se[2] + se[3]);
-    tot.sb += (sb[0] + sb[1]) + (sb[2] + sb[3]);
-    flush_v(tot);
-  }
-};
-
 // W and N_occ of the dense pixels [d0, d0 + c) of one ring run.
 __device__ __forceinline__ void run_wn(const double2* wn, int64_t d0, int c, Acc64& tot) {
   const double2 lo = wn[d0], hi = wn[d0 + c];
