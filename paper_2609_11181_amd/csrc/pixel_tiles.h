@@ -1,7 +1,7 @@
 // Tile bodies of the pixel-variant mixed-precision kernels, shared by the
 // single-plan launches (k_pairs.hip, k_belt.hip) and the mixed-batch launch
 // (k_mixed.hip): the persistent tile queues, the general per-centre walk and
-// the shared-stencil belt tile.
+// the belt items (shared per-ring coefficient tables).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,14 +37,14 @@ __device__ __forceinline__ void write_out(void* out, int64_t n_out, int scale, i
 
 // ---- pixel variant, mixed precision: tiles ---------------------------------------
 //
-// Outputs are cut into tiles of 256 consecutive list entries. A tile is a
-// belt tile when its 256 centres are consecutive pixels of one ring, the
-// source grid is the output grid and every ring of the disc lies in the
-// equatorial belt (4N pixels each): then the geometry of (centre i + t,
-// source j + t) is the same for every t, and even the same for every tile
-// on that ring, so the disc coefficients of each belt ring are evaluated
-// once per scale into a table (k_belt.hip). All other tiles are general:
-// each centre evaluates its own pairs.
+// Outputs are cut into tiles of 256 consecutive list entries. A tile whose
+// entries form at most four runs of consecutive pixels of belt rings (the
+// source grid is the output grid and every ring of the runs' discs lies in
+// the equatorial belt, 4N pixels each) becomes belt items, one per run: on
+// such a ring the geometry of (centre i + t, source j + t) is the same for
+// every t, so the disc coefficients of each belt ring are evaluated once per
+// scale into a table (k_belt.hip). All other tiles are general: each centre
+// evaluates its own pairs.
 
 constexpr int kRingCap = 160;  // rings of one belt disc
 constexpr int kCoefPad = 8;    // padding entries after the belt coefficient tables

@@ -173,10 +173,10 @@ struct GalaxyArgs {
   int scale;
 };
 
-// Shared-stencil tables of one scale (built by k_belt.hip): for every belt
-// ring that hosts belt tiles, its disc rings and the coefficients of the
-// members of each, for a centre at azimuth index 0 (the same for every
-// centre of the ring, shifted).
+// Belt tables of one scale (built by k_belt.hip): for every belt ring that
+// holds outputs, its disc rings and the coefficients of the members of each,
+// for a centre at azimuth index 0 (the same for every centre of the ring,
+// shifted).
 struct BeltTab {
   const int2* head;  // [rp - nside] = (first table ring, ring count)
   const int4* info;  // per table ring: (ring, first member offset, member count, coefficient offset)

@@ -119,8 +119,8 @@ def test_pixel_variant_parity(ctx, nside, th, kind, prec, norm):
 
 @pytest.mark.parametrize("kind,th", [(F.TANH, 2 * DEG), (F.POLY, 6 * DEG)])
 def test_pixel_variant_runs_of_consecutive_centres(ctx, kind, th):
-    """Whole rings and ragged runs of consecutive centres: waves of 64
-    neighbours on one ring take the shared-stencil path (equal-size source
+    """Whole rings and ragged runs of consecutive centres: runs on belt rings
+    take the belt path (shared per-ring coefficient tables, equal-size source
     rings); runs crossing ring ends, cap rings and short tails do not."""
     L = _L()
     nside = 128
