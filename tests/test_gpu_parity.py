@@ -121,7 +121,9 @@ def test_pixel_variant_parity(ctx, nside, th, kind, prec, norm):
 def test_pixel_variant_runs_of_consecutive_centres(ctx, kind, th):
     """Whole rings and ragged runs of consecutive centres: runs on belt rings
     take the belt path (shared per-ring coefficient tables, equal-size source
-    rings); runs crossing ring ends, cap rings and short tails do not."""
+    rings; a run across a ring end is split there, short tails are short
+    items); cap rings and rings whose discs leave the belt take the general
+    path."""
     L = _L()
     nside = 128
     m = _pixmap(nside, 11)
