@@ -170,11 +170,15 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // wave's coefficient band, zero-padded by kPadL entries before and kPadR
 // after, so that the operand loads need no range tests.
 constexpr int kPadL = 32, kPadR = 48;
+// slab row stride in entries: one entry of padding after the 2 kNR entries
+// of a slot, so the 64 lanes of a wave writing 64 consecutive slots spread
+// over the LDS banks
+constexpr int kRowE = 2 * kNR + 1;
 __host__ __device__ constexpr int stack_slab(int cnt_max) { return kNP + cnt_max + 16; }
 __host__ __device__ constexpr int stack_band(int cnt_max) { return kPadL + cnt_max + kPadR; }
 __host__ __device__ constexpr size_t stack_slab_bytes(int cnt_max) {
-  return (size_t)stack_slab(cnt_max) * 2 * kNR * sizeof(uint2) > (size_t)kStack * 2 * kNR * kNP * sizeof(float)
-             ? (size_t)stack_slab(cnt_max) * 2 * kNR * sizeof(uint2)
+  return (size_t)stack_slab(cnt_max) * kRowE * sizeof(uint2) > (size_t)kStack * 2 * kNR * kNP * sizeof(float)
+             ? (size_t)stack_slab(cnt_max) * kRowE * sizeof(uint2)
              : (size_t)kStack * 2 * kNR * kNP * sizeof(float);
 }
 __host__ __device__ constexpr size_t stack_lds_bytes(int cnt_max) {
@@ -184,7 +188,7 @@ __host__ __device__ constexpr size_t stack_lds_bytes(int cnt_max) {
 __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleArgs s, int cnt_max) {
   extern __shared__ uint2 smem[];
   const int slab_max = stack_slab(cnt_max), band = stack_band(cnt_max);
-  uint2* xs = smem;                                                    // [slab_max][2 kNR]
+  uint2* xs = smem;                                                    // [slab_max][kRowE]
   uint2* coefP = smem + stack_slab_bytes(cnt_max) / sizeof(uint2);    // [kStack][band]
   __shared__ int s_ws[kStack], s_we[kStack];   // per wave window [start, end) on the current ring
   __shared__ float fnorm[kStack][kNP];
@@ -280,8 +284,8 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
           const float uu = (ci >= 0 && rreal < n.n_real) ? n.u[(int64_t)rreal * n.n_src + ci] : 0.f;
           const float sn = __builtin_amdgcn_sinf(uu), cs = __builtin_amdgcn_cosf(uu);  // of 2 pi u
           const uint2 e = split_pair(gr.x * cs - gr.y * sn, gr.x * sn + gr.y * cs);
-          xs[sl * 2 * kNR + 2 * rr] = e;
-          xs[sl * 2 * kNR + 2 * rr + 1] = make_uint2(bmode(e.x), bmode(e.y));
+          xs[sl * kRowE + 2 * rr] = e;
+          xs[sl * kRowE + 2 * rr + 1] = make_uint2(bmode(e.x), bmode(e.y));
         }
       }
     }
@@ -302,8 +306,8 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
           ah[q] = w.x;
           al[q] = w.y;
           const int slot = min(base + js, Lu - 1);  // beyond the window A is zero
-          const uint2 x0 = bp[slot * 2 * kNR];
-          const uint2 x1v = bp[slot * 2 * kNR + 32];
+          const uint2 x0 = bp[slot * kRowE];
+          const uint2 x1v = bp[slot * kRowE + 32];
           b0h[q] = x0.x;
           b0l[q] = x0.y;
           b1h[q] = x1v.x;
