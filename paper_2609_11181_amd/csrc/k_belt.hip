@@ -83,8 +83,7 @@ __global__ void k_gen_rings(int nside, GenRingC* rings) {
   GenRingC c{};
   if (r >= 1) {
     const Ring Q = ring_info(nside, r);
-    c.z = Q.z;
-    c.s = Q.s;
+    c.rn = 1.0 / (double)Q.n;
     c.first = Q.first;
     c.n = Q.n;
     c.twice_o = Q.twice_o;

@@ -142,14 +142,21 @@ __device__ __forceinline__ Coef ring_coef(double xt, double yt, const double* tp
   return c;
 }
 
-// sin(a) and sin^2(a/2) of an azimuth offset |a| <= pi. For |a| <= 1/2 the
-// Taylor series of both to degree 13/14 (relative error below 1e-16); beyond, b = a / 4 is
+// sin(a) and sin^2(a/2) of an azimuth offset |a| <= pi. For |a| <= 1/32
+// the Taylor series of both to degree 7/8, for |a| <= 1/2 to degree 13/14
+// (relative error below 1e-16 in both ranges); beyond, b = a / 4 is
 // within pi/4, where the Taylor series of sin b and cos b to degree 15/16
 // are good to 1e-16, and the double-angle formulas give sin(a/2) = 2 sb cb,
 // cos(a/2) = 1 - 2 sb^2. (A general sincos carries a large-argument
 // reduction this bounded range never needs.)
 __device__ __forceinline__ void sin_hav(double av, double* sa, double* h) {
-  if (fabs(av) <= 0.5) {
+  if (fabs(av) <= 0.03125) {
+    const double a2 = av * av;
+    const double ps = fma(a2, fma(a2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0);
+    *sa = fma(av * a2, ps, av);
+    const double ph = fma(a2, fma(a2, -1.0 / 80640.0, 1.0 / 1440.0), -1.0 / 48.0);
+    *h = a2 * fma(a2, ph, 0.25);
+  } else if (fabs(av) <= 0.5) {
     const double a2 = av * av;
     double ps = fma(a2, 1.0 / 6227020800.0, -1.0 / 39916800.0);
     ps = fma(a2, ps, 1.0 / 362880.0);
@@ -294,15 +301,12 @@ __host__ __device__ __forceinline__ PairWin ring_pair_window(double zp, double s
   return PairWin{asin(sqrt(num / den)) * ((double)Q.n / kPi), 1};
 }
 
-// Members of a ring of nq pixels (azimuth offset twice_o / 2) for a centre
-// at azimuth index ip2 / 2 (ip2 = 2 i + 2 o) of a ring with np pixels:
-// first unwrapped index and count (window bounds within [-nq, 2 nq]: 32-bit
-// conversions suffice). Returns false when the ring is not reached.
-__device__ __forceinline__ bool window_at(const PairWin& pw, int64_t ip2, int np, int nq, int twice_o, int64_t* jlo,
-                                          int* cnt) {
+// Members of a ring of nq pixels for a centre at azimuth u0, in units of
+// the ring's step and counted from its first pixel centre: first unwrapped
+// index and count (window bounds within [-nq, 2 nq]: 32-bit conversions
+// suffice). Returns false when the ring is not reached.
+__device__ __forceinline__ bool window_at_u(const PairWin& pw, double u0, int nq, int64_t* jlo, int* cnt) {
   if (pw.kind == 0) return false;
-  // azimuth of the centre in units of the ring step, minus the ring offset
-  const double u0 = (double)ip2 * (double)nq / (2.0 * (double)np) - 0.5 * (double)twice_o;
   if (pw.kind == 2) {
     *jlo = (int)ceil(u0 - 0.5 * nq);
     *cnt = nq;
@@ -315,6 +319,14 @@ __device__ __forceinline__ bool window_at(const PairWin& pw, int64_t ip2, int np
   *jlo = jl;
   *cnt = c;
   return c > 0;
+}
+
+// The same for a centre at azimuth index ip2 / 2 (ip2 = 2 i + 2 o) of a
+// ring with np pixels, the source ring's azimuth offset being twice_o / 2.
+__device__ __forceinline__ bool window_at(const PairWin& pw, int64_t ip2, int np, int nq, int twice_o, int64_t* jlo,
+                                          int* cnt) {
+  const double u0 = (double)ip2 * (double)nq / (2.0 * (double)np) - 0.5 * (double)twice_o;
+  return window_at_u(pw, u0, nq, jlo, cnt);
 }
 
 // Members of ring Q for a centre at azimuth index ip2 / 2 of a ring

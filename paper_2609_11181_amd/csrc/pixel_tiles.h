@@ -102,13 +102,32 @@ __device__ __attribute__((noinline)) bool general_window(double zp, double sp, i
 __device__ __attribute__((noinline)) void general_sin_hav(double av, double* sa, double* h) { sin_hav(av, sa, h); }
 
 // One member of a general tile: tangent-plane components from the walk
-// state, coefficients, accumulation.
+// state, coefficients, accumulation. The coefficients are those of
+// ring_coef, arranged for fewer operations: y^2 - x^2 = 2 y^2 - sin^2 theta,
+// and the factor -2 of q sin 2psi is applied once to its sums (E gets
+// sum qc g1 - 2 sum qh g2, B gets sum qc g2 + 2 sum qh g1 with
+// qh = q x y / sin^2 theta; doubling is exact).
 template <bool TABLE, bool BIG>
 __device__ __forceinline__ void general_member(double sa, double h, double sp, double Y0, double Kz, float4 g,
-                                               const double* tp, Tab tab, Acc64& tot, float& sv) {
+                                               const double* tp, Tab tab, Acc64& tot, double& e2, double& b2,
+                                               float& sv) {
   const double xt = sp * sa;
   const double yt = fma(Kz, h, Y0);
-  accumulate_pix(ring_coef<TABLE, BIG>(xt, yt, tp, tab), g, tot, sv);
+  const double yy = yt * yt;
+  const double S2 = fma(xt, xt, yy);
+  const double S2c = fmax(S2, (double)kCoincidentS2);
+  const double r0 = (double)__builtin_amdgcn_rsqf((float)S2c);
+  const double r = r0 * fma(-0.5 * S2c, r0 * r0, 1.5);
+  const double q = filter_q<TABLE>(theta_ratio<BIG>(S2 * r, S2, tp), tab);
+  const double qn = q * (r * r);
+  const double qc = qn * fma(2.0, yy, -S2);
+  const double qh = qn * (xt * yt);
+  const double a1 = (double)g.x, a2 = (double)g.y;
+  tot.se = fma(qc, a1, tot.se);
+  e2 = fma(qh, a2, e2);
+  tot.sb = fma(qc, a2, tot.sb);
+  b2 = fma(qh, a1, b2);
+  sv = fmaf((float)(q * q), g.z, sv);
 }
 
 // One centre of a general tile (list entry o), walking its own disc windows
@@ -133,6 +152,10 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
   // the centre ring's source rings and their ring-pair terms come from the
   // plan's tables when it has them (the same values, computed once per ring
   // pair instead of once per centre)
+  // 1 / (2 np) and pi / np for the window start and the first azimuth
+  // offset of every ring
+  const double h2np = 0.5 / (double)np;
+  const double pinp = (2.0 * kPi) * h2np;
   const bool gt = GT == 2 ? a.gt_head != nullptr : GT == 1;
   int lo, hi, e0 = 0;
   if (gt) {
@@ -148,17 +171,20 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
   }
 
   Acc64 tot;
+  double e2 = 0.0, b2 = 0.0;
   for (int r = lo; r <= hi; ++r) {
     int64_t jlo, first;
     int cnt, nq, twice_o;
-    double Y0, Kz;
+    double Y0, Kz, rnq;
     RingStep step;
     if (gt) {
       const GenPair e = a.gt_pair[e0 + r];
       const GenRingC q = a.gt_ring[r];
       nq = q.n;
       twice_o = q.twice_o;
-      if (!window_at(PairWin{e.w, e.kind}, ip2, np, nq, twice_o, &jlo, &cnt)) continue;
+      rnq = q.rn;
+      const double u0 = (double)ip2 * ((double)nq * h2np) - 0.5 * (double)twice_o;
+      if (!window_at_u(PairWin{e.w, e.kind}, u0, nq, &jlo, &cnt)) continue;
       Y0 = e.Y0;
       Kz = e.Kz;
       first = q.first;
@@ -171,6 +197,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
       if (!reached) continue;
       nq = Q.n;
       twice_o = Q.twice_o;
+      rnq = 1.0 / (double)nq;
       Y0 = ring_y0(Q.s, Q.z, zp, sp);
       Kz = 2.0 * Q.z * sp;
       first = Q.first;
@@ -181,7 +208,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     // dphi of the first member = pi m / (np nq) with m an exact integer
     const int64_t m = ip2 * nq - (2 * jlo + twice_o) * (int64_t)np;
     double sa, h;
-    const double av = (double)m * (kPi / ((double)np * (double)nq));
+    const double av = (double)m * (pinp * rnq);
     if (OOL) general_sin_hav(av, &sa, &h);
     else sin_hav(av, &sa, &h);
     // the member at the centre itself (same ring, dphi = 0), if any: the walk
@@ -211,12 +238,12 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
           for (int u = 0; u < U; ++u) g[u] = p[k0 + k + u];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            general_member<TABLE, BIG>(sa, h, sp, Y0, Kz, g[u], tp, tab, tot, sv);
+            general_member<TABLE, BIG>(sa, h, sp, Y0, Kz, g[u], tp, tab, tot, e2, b2, sv);
             step.advance(&sa, &h);
           }
         }
         for (; k < kn; ++k) {
-          general_member<TABLE, BIG>(sa, h, sp, Y0, Kz, p[k0 + k], tp, tab, tot, sv);
+          general_member<TABLE, BIG>(sa, h, sp, Y0, Kz, p[k0 + k], tp, tab, tot, e2, b2, sv);
           step.advance(&sa, &h);
         }
         tot.sv += sv;
@@ -226,6 +253,8 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
       if (jw == nq) jw = 0;
     }
   }
+  tot.se = fma(-2.0, e2, tot.se);
+  tot.sb = fma(2.0, b2, tot.sb);
   write_out<float>(a.out, a.n_out, a.scale, o, a.norm, tot, s);
 }
 

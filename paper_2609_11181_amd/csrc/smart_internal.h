@@ -131,11 +131,11 @@ struct GenPair {
   int kind, pad;
 };
 
-// Source-ring constants of the general walk: colatitude cosine and sine,
-// the sine and haversine of one azimuth step, first pixel, pixel count,
-// twice the azimuth offset.
+// Source-ring constants of the general walk: reciprocal of the pixel
+// count, the sine and haversine of one azimuth step, first pixel, pixel
+// count, twice the azimuth offset.
 struct GenRingC {
-  double z, s, sd, hd;
+  double rn, sd, hd;
   int64_t first;
   int n, twice_o;
 };
