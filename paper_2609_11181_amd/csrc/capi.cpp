@@ -68,6 +68,7 @@ void smart_finalize(smart_ctx ctx) {
   for (auto& f : ctx->filters) {
     hipFree(f.d_table);
     hipFree(f.d_table_c0);
+    hipFree(f.d_pieces);
   }
   if (ctx->d_temp) hipFree(ctx->d_temp);
   delete ctx;

@@ -93,6 +93,7 @@ int build_filter(FilterDef& f) {
   for (int i = 0; i <= K; ++i) eval_both(f, i * h, &qv[i], &dv[i]);  // x = 1: left limit
   f.h_table.resize(4 * K);
   std::vector<double> c0(K);
+  std::vector<FilterPiece> pieces(K + 1);
   for (int i = 0; i < K; ++i) {
     const double q0 = qv[i], q1 = qv[i + 1], d0 = dv[i] * h, d1 = dv[i + 1] * h;
     f.h_table[4 * i + 0] = (float)q0;
@@ -100,7 +101,9 @@ int build_filter(FilterDef& f) {
     f.h_table[4 * i + 1] = (float)d0;
     f.h_table[4 * i + 2] = (float)(3.0 * (q1 - q0) - 2.0 * d0 - d1);
     f.h_table[4 * i + 3] = (float)(2.0 * (q0 - q1) + d0 + d1);
+    pieces[i] = FilterPiece{q0, f.h_table[4 * i + 1], f.h_table[4 * i + 2], f.h_table[4 * i + 3], 0.f};
   }
+  pieces[K] = FilterPiece{qv[K], 0.f, 0.f, 0.f, 0.f};
   if (hipMalloc(&f.d_table, sizeof(float) * 4 * K) != hipSuccess) {
     set_error("hipMalloc failed for a filter table");
     return SMART_ENOMEM;
@@ -109,8 +112,13 @@ int build_filter(FilterDef& f) {
     set_error("hipMalloc failed for a filter table");
     return SMART_ENOMEM;
   }
+  if (hipMalloc(&f.d_pieces, sizeof(FilterPiece) * (K + 1)) != hipSuccess) {
+    set_error("hipMalloc failed for a filter table");
+    return SMART_ENOMEM;
+  }
   if (hipMemcpy(f.d_table, f.h_table.data(), sizeof(float) * 4 * K, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(f.d_table_c0, c0.data(), sizeof(double) * K, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(f.d_table_c0, c0.data(), sizeof(double) * K, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(f.d_pieces, pieces.data(), sizeof(FilterPiece) * (K + 1), hipMemcpyHostToDevice) != hipSuccess) {
     set_error("copy of a filter table failed");
     return SMART_EDEVICE;
   }
@@ -130,6 +138,7 @@ ScaleArgs make_scale(smart_ctx ctx, double theta_ap, int filter_id, double omega
   s.big = theta_ap > 2.0 * M_PI / 180.0 ? 1 : 0;
   s.table = f.d_table;
   s.table_c0 = f.d_table_c0;
+  s.pieces = f.d_pieces;
   // asin(y) / y = sum c_k y^(2k), divided by theta_ap so that x = y * P(y^2);
   // for tabulated filters also multiplied by the number of table pieces, so
   // the series gives the table coordinate directly

@@ -52,7 +52,7 @@ __device__ __forceinline__ void general_quarter(const MixJob& J, int tile, int p
 #pragma unroll
   for (int k = 0; k < 7; ++k) tp[k] = J.s.tpoly[k];
   const int64_t o = (int64_t)tile * kBlock + part * 64 + (threadIdx.x & 63);
-  general_centre<TABLE, BIG, true>(J.a, J.s, o, tp, Tab{J.s.table, J.s.table_c0});
+  general_centre<TABLE, BIG, true>(J.a, J.s, o, tp, J.s.pieces);
 }
 
 // Item claims: the list is cut into chunks of kMixChunk consecutive items,

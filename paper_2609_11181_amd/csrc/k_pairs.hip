@@ -116,16 +116,11 @@ __global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_a
 template <bool TABLE, bool BIG, bool OOL, int GT>
 __global__ __launch_bounds__(kBlock, 3) void k_pixel_f32(PixelArgs a, ScaleArgs s, const int* tiles, int n_tiles,
                                                       int* cursors) {
-  __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
-  __shared__ double tab_c0[TABLE ? kFilterIntervals : 1];
+  __shared__ FilterPiece tab[TABLE ? kFilterIntervals + 1 : 1];
   __shared__ int s_item;
   if (TABLE) {
-    for (int k = threadIdx.x; k < kFilterIntervals; k += blockDim.x) {
-      tab_c[k] = s.table[k];
-      tab_c0[k] = s.table_c0[k];
-    }
+    for (int k = threadIdx.x; k <= kFilterIntervals; k += blockDim.x) tab[k] = s.pieces[k];
   }
-  const Tab tab{tab_c, tab_c0};
   double tp[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) tp[k] = s.tpoly[k];

@@ -84,6 +84,28 @@ __device__ __forceinline__ double filter_q(double x, Tab tab) {
   }
 }
 
+// q from a table of FilterPiece records (TABLE; t = x * kFilterIntervals),
+// or of x for the polynomial filter. Below BIG apertures x stays within
+// 1e-9 of [0, 1] (exact windows, series error below 1e-10), so t indexes at
+// most the table's constant last record and needs no clamp.
+template <bool TABLE, bool BIG>
+__device__ __forceinline__ double filter_piece(double t, const FilterPiece* tab) {
+  if (TABLE) {
+    const double tc = BIG ? fmin(t, (double)kFilterIntervals - 2e-7) : t;
+    const int i = (int)tc;  // 0 <= i <= kFilterIntervals: a 24-bit product gives the offset
+    const double fd = __builtin_amdgcn_fract(tc);
+    const float f = (float)fd;
+    const FilterPiece c =
+        *(const FilterPiece*)((const char*)tab + __umul24((unsigned)i, (unsigned)sizeof(FilterPiece)));
+    const float p = fmaf(f, fmaf(f, c.c3, c.c2), c.c1);
+    return fma(fd, (double)p, c.c0);
+  } else {
+    const double u = fmin(t * t, 1.0);
+    const double k = 6.0 / kPi;
+    return u * fma(-k, u, k);
+  }
+}
+
 // Filter-weighted rotation coefficients of one member: q cos 2psi and
 // q sin 2psi in FP64 (the spin-2 rotation and the E/B sums run in FP64,
 // full rate on this GPU, so a source with a large shear cannot leak the
@@ -226,6 +248,25 @@ struct RingStep {
     const double s1 = fma(*sa, cd, fma(sd2, *h, -sd));
     *h = fma(*h, cd, fma(*sa, -hsd, hd));
     *sa = s1;
+  }
+};
+
+// The same walk carried on x = s_p sin(a) instead of sin(a) (x is the
+// tangent-plane component the coefficients need): with rsp = 1 / s_p,
+// x' = x cd + 2 s_p sd h - s_p sd and h' = h cd - (sd / 2) rsp x + hd.
+struct XStep {
+  double cd, xs2, xs1, hx, hd;
+  __device__ __forceinline__ void init(double sd, double hd_, double sp, double rsp) {
+    hd = hd_;
+    cd = 1.0 - 2.0 * hd;
+    xs1 = sp * sd;
+    xs2 = 2.0 * xs1;
+    hx = (0.5 * sd) * rsp;
+  }
+  __device__ __forceinline__ void advance(double* x, double* h) const {
+    const double x1 = fma(*x, cd, fma(xs2, *h, -xs1));
+    *h = fma(*h, cd, fma(*x, -hx, hd));
+    *x = x1;
   }
 };
 

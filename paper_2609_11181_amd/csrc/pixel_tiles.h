@@ -108,17 +108,16 @@ __device__ __attribute__((noinline)) void general_sin_hav(double av, double* sa,
 // sum qc g1 - 2 sum qh g2, B gets sum qc g2 + 2 sum qh g1 with
 // qh = q x y / sin^2 theta; doubling is exact).
 template <bool TABLE, bool BIG>
-__device__ __forceinline__ void general_member(double sa, double h, double sp, double Y0, double Kz, float4 g,
-                                               const double* tp, Tab tab, Acc64& tot, double& e2, double& b2,
+__device__ __forceinline__ void general_member(double xt, double h, double Y0, double Kz, float4 g, const double* tp,
+                                               const FilterPiece* tab, Acc64& tot, double& e2, double& b2,
                                                float& sv) {
-  const double xt = sp * sa;
   const double yt = fma(Kz, h, Y0);
   const double yy = yt * yt;
   const double S2 = fma(xt, xt, yy);
   const double S2c = fmax(S2, (double)kCoincidentS2);
   const double r0 = (double)__builtin_amdgcn_rsqf((float)S2c);
   const double r = r0 * fma(-0.5 * S2c, r0 * r0, 1.5);
-  const double q = filter_q<TABLE>(theta_ratio<BIG>(S2 * r, S2, tp), tab);
+  const double q = filter_piece<TABLE, BIG>(theta_ratio<BIG>(S2 * r, S2, tp), tab);
   const double qn = q * (r * r);
   const double qc = qn * fma(2.0, yy, -S2);
   const double qh = qn * (xt * yt);
@@ -132,15 +131,16 @@ __device__ __forceinline__ void general_member(double sa, double h, double sp, d
 
 // One centre of a general tile (list entry o), walking its own disc windows
 // (any rings, any grid). Along a ring
-// window the azimuth offset drops by one ring step per member, so its sine
-// and haversine follow from the previous member's by the angle-difference
-// identities (RingStep) instead of a series per member. A window that wraps
+// window the azimuth offset drops by one ring step per member, so the
+// member's x = s_p sin(dphi) and sin^2(dphi / 2) follow from the previous
+// member's by the angle-difference identities (XStep) instead of a series
+// per member. A window that wraps
 // past the ring's last pixel is walked as two contiguous runs.
 // GT: 1 = the plan's ring-pair tables are present, 0 = absent, 2 = test at
 // run time.
 template <bool TABLE, bool BIG, bool OOL, int GT = 2>
 __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleArgs& s, int64_t o, const double* tp,
-                                               Tab tab) {
+                                               const FilterPiece* tab) {
   if (o >= a.n_out) return;
 
   int rp, ip;
@@ -156,6 +156,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
   // offset of every ring
   const double h2np = 0.5 / (double)np;
   const double pinp = (2.0 * kPi) * h2np;
+  const double rsp = 1.0 / sp;
   const bool gt = GT == 2 ? a.gt_head != nullptr : GT == 1;
   int lo, hi, e0 = 0;
   if (gt) {
@@ -175,8 +176,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
   for (int r = lo; r <= hi; ++r) {
     int64_t jlo, first;
     int cnt, nq, twice_o;
-    double Y0, Kz, rnq;
-    RingStep step;
+    double Y0, Kz, rnq, sd, hd;
     if (gt) {
       const GenPair e = a.gt_pair[e0 + r];
       const GenRingC q = a.gt_ring[r];
@@ -188,8 +188,8 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
       Y0 = e.Y0;
       Kz = e.Kz;
       first = q.first;
-      step.sd = q.sd;
-      step.hd = q.hd;
+      sd = q.sd;
+      hd = q.hd;
     } else {
       const Ring Q = ring_info(a.nside_in, r);
       const bool reached = OOL ? general_window(zp, sp, ip2, np, Q, s.C_ap, &jlo, &cnt)
@@ -201,16 +201,18 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
       Y0 = ring_y0(Q.s, Q.z, zp, sp);
       Kz = 2.0 * Q.z * sp;
       first = Q.first;
-      if (OOL) general_sin_hav(2.0 * kPi / (double)nq, &step.sd, &step.hd);
-      else sin_hav(2.0 * kPi / (double)nq, &step.sd, &step.hd);
+      if (OOL) general_sin_hav(2.0 * kPi / (double)nq, &sd, &hd);
+      else sin_hav(2.0 * kPi / (double)nq, &sd, &hd);
     }
-    step.finish();
+    XStep step;
+    step.init(sd, hd, sp, rsp);
     // dphi of the first member = pi m / (np nq) with m an exact integer
     const int64_t m = ip2 * nq - (2 * jlo + twice_o) * (int64_t)np;
     double sa, h;
     const double av = (double)m * (pinp * rnq);
     if (OOL) general_sin_hav(av, &sa, &h);
     else sin_hav(av, &sa, &h);
+    double xs = sp * sa;
     // the member at the centre itself (same ring, dphi = 0), if any: the walk
     // restarts there from exact zeros, so its shear term vanishes exactly
     const int64_t mstep = 2 * (int64_t)np;
@@ -222,7 +224,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
       int run = min(cnt - kdone, nq - jw);
       if (kc > kdone && kc < kdone + run) run = kc - kdone;
       if (kdone == kc) {
-        sa = 0.0;
+        xs = 0.0;
         h = 0.0;
       }
       run_wn(a.wn, dring + jw, run, tot);
@@ -238,13 +240,13 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
           for (int u = 0; u < U; ++u) g[u] = p[k0 + k + u];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            general_member<TABLE, BIG>(sa, h, sp, Y0, Kz, g[u], tp, tab, tot, e2, b2, sv);
-            step.advance(&sa, &h);
+            general_member<TABLE, BIG>(xs, h, Y0, Kz, g[u], tp, tab, tot, e2, b2, sv);
+            step.advance(&xs, &h);
           }
         }
         for (; k < kn; ++k) {
-          general_member<TABLE, BIG>(sa, h, sp, Y0, Kz, p[k0 + k], tp, tab, tot, e2, b2, sv);
-          step.advance(&sa, &h);
+          general_member<TABLE, BIG>(xs, h, Y0, Kz, p[k0 + k], tp, tab, tot, e2, b2, sv);
+          step.advance(&xs, &h);
         }
         tot.sv += sv;
       }

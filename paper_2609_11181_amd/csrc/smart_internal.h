@@ -27,12 +27,25 @@ void set_error(const std::string& msg);
 // handles
 // ---------------------------------------------------------------------------
 
+// One cubic piece of a filter table in a single 24-byte record (the general
+// pixel walk reads it with one address computation): q = c0 + f (c1 +
+// f (c2 + f c3)) for f in [0, 1).
+struct FilterPiece {
+  double c0;
+  float c1, c2, c3, unused;
+};
+static_assert(sizeof(FilterPiece) == 24, "filter piece layout");
+
 struct FilterDef {
   int kind = 0;
   double params[5] = {0, 0, 0, 0, 0};
   std::vector<double> samples;  // SMART_FILTER_TABLE
   float4* d_table = nullptr;    // kFilterIntervals cubic pieces (c0, c1, c2, c3) in FP32
   double* d_table_c0 = nullptr;  // c0 of every piece in FP64
+  // the same pieces as FilterPiece records, plus a constant piece
+  // q = q(1) at index kFilterIntervals, so that x = 1 (and the rounding
+  // just above it) needs no clamp
+  FilterPiece* d_pieces = nullptr;
   std::vector<float> h_table;
 };
 
@@ -115,6 +128,7 @@ struct ScaleArgs {
   int big;           // 1 when theta_ap > 2 degrees (longer asin series)
   const float4* table;
   const double* table_c0;
+  const FilterPiece* pieces;  // kFilterIntervals + 1 records
   double tpoly[7];   // asin(y)/y series in y^2, divided by theta_ap (x from sin theta)
   double cpoly[7];   // 2 asin(c/2)/c series in c^2, divided by theta_ap (x from the chord c)
   double tanh_p[5];  // FP64 path: tanh filter parameters
