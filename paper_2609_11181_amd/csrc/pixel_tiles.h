@@ -132,8 +132,8 @@ __device__ __forceinline__ void general_member(double xt, double h, double Y0, d
 // One centre of a general tile (list entry o), walking its own disc windows
 // (any rings, any grid). Along a ring
 // window the azimuth offset drops by one ring step per member, so the
-// member's x = s_p sin(dphi) and sin^2(dphi / 2) follow from the previous
-// member's by the angle-difference identities (XStep) instead of a series
+// member's x = s_p sin(dphi) and sin^2(dphi / 2) follow from the two
+// previous members' by a three-term recurrence (XWalk3) instead of a series
 // per member. A window that wraps
 // past the ring's last pixel is walked as two contiguous runs.
 // GT: 1 = the plan's ring-pair tables are present, 0 = absent, 2 = test at
@@ -212,7 +212,8 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     const double av = (double)m * (pinp * rnq);
     if (OOL) general_sin_hav(av, &sa, &h);
     else sin_hav(av, &sa, &h);
-    double xs = sp * sa;
+    XWalk3 w;
+    w.start(step, sp * sa, h);
     // the member at the centre itself (same ring, dphi = 0), if any: the walk
     // restarts there from exact zeros, so its shear term vanishes exactly
     const int64_t mstep = 2 * (int64_t)np;
@@ -223,10 +224,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     while (kdone < cnt) {
       int run = min(cnt - kdone, nq - jw);
       if (kc > kdone && kc < kdone + run) run = kc - kdone;
-      if (kdone == kc) {
-        xs = 0.0;
-        h = 0.0;
-      }
+      if (kdone == kc) w.restart(step);
       run_wn(a.wn, dring + jw, run, tot);
       const float4* p = a.map + dring + jw;
       for (int k0 = 0; k0 < run; k0 += kChunk) {
@@ -240,13 +238,13 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
           for (int u = 0; u < U; ++u) g[u] = p[k0 + k + u];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            general_member<TABLE, BIG>(xs, h, Y0, Kz, g[u], tp, tab, tot, e2, b2, sv);
-            step.advance(&xs, &h);
+            general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, g[u], tp, tab, tot, e2, b2, sv);
+            w.advance();
           }
         }
         for (; k < kn; ++k) {
-          general_member<TABLE, BIG>(xs, h, Y0, Kz, p[k0 + k], tp, tab, tot, e2, b2, sv);
-          step.advance(&xs, &h);
+          general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, p[k0 + k], tp, tab, tot, e2, b2, sv);
+          w.advance();
         }
         tot.sv += sv;
       }
