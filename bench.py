@@ -422,25 +422,42 @@ def main():
                 ev[k][1].record(stream)
         keep.append((data, plans))
 
+    splits = []
+
+    def retire(keep):
+        """Kernel durations of the previous step's plans, then free its handles
+        (a batch loop frees the previous batch's map and plans; the library
+        keeps their device blocks for the next ones)."""
+        for data, plans in keep:
+            splits.append([p.kernel_ms(0) for p in plans])
+            for p in plans:
+                p.free()
+            data.free()
+        keep.clear()
+
     keep = []
     t = time.perf_counter()
     for w in range(max(args.warmup, 1 if not args.no_tune else 0)):
+        retire(keep)
         step(keep, tune_budget=20000 if w == 0 else 0)  # the first warm-up step measures the launch choices
     torch.cuda.synchronize()
     log(f"warm-up (with autotuning) {time.perf_counter() - t:.1f}s")
-    keep.clear()
+    retire(keep)
+    splits.clear()
     events = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in scales]
               for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
+        retire(keep)
         step(keep, events[s])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
     # per-kernel durations (HIP events recorded by the library on this stream around each pair kernel)
-    split_ms = np.mean([[plans[k].kernel_ms(0) for k in range(len(scales))] for _, plans in keep], axis=0)
     last_plans = keep[-1][1]
+    splits.append([p.kernel_ms(0) for p in last_plans])
+    split_ms = np.mean(splits, axis=0)
     pairs_scale = [p.last_pairs() for p in last_plans]
     pairs = float(sum(pairs_scale))
     # pairs of the belt items (N channel summed over their centres); the rest are general-tile pairs

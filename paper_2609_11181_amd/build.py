@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsmartap.so")
 ARCH = "gfx950"
 
-SOURCES = ["capi.cpp", "filters.cpp", "tune.cpp", "k_pairs.hip", "k_belt.hip", "k_binner.hip", "k_noise.hip",
+SOURCES = ["capi.cpp", "devmem.cpp", "filters.cpp", "tune.cpp", "k_pairs.hip", "k_belt.hip", "k_binner.hip", "k_noise.hip",
            "k_mixed.hip"]
 
 FLAGS = [

@@ -71,6 +71,8 @@ void smart_finalize(smart_ctx ctx) {
     hipFree(f.d_pieces);
   }
   if (ctx->d_temp) hipFree(ctx->d_temp);
+  (void)hipDeviceSynchronize();
+  smart::dev_trim(ctx->device);  // cached handle blocks go back to HIP
   delete ctx;
 }
 
@@ -119,15 +121,11 @@ int smart_filter_table(smart_ctx ctx, int filter_id, float* h_coef, int* n_inter
 void smart_data_free(smart_data d) {
   if (!d) return;
   if (d->ctx) hipSetDevice(d->ctx->device);
-  hipFree(d->P);
-  hipFree(d->F);
-  hipFree(d->G);
-  hipFree(d->order);
-  hipFree(d->offsets);
-  hipFree(d->sums);
-  hipFree(d->wn);
-  hipFree(d->cidx);
-  hipFree(d->src_pix);
+  // the blocks go back to the library's cache: no work may still use them
+  (void)hipDeviceSynchronize();
+  for (void* q : {(void*)d->P, (void*)d->F, (void*)d->G, (void*)d->order, (void*)d->offsets, (void*)d->sums,
+                  (void*)d->wn, (void*)d->cidx, (void*)d->src_pix})
+    smart::dev_release(q);
   delete d;
 }
 
@@ -225,10 +223,12 @@ int smart_data_export(smart_data d, int64_t* d_order, int64_t* d_offsets, float*
 void smart_plan_free(smart_plan p) {
   if (!p) return;
   if (p->ctx) hipSetDevice(p->ctx->device);
-  hipFree(p->out_pix);
-  hipFree(p->d_pairs);
-  hipFree(p->d_work);
-  hipFree(p->rot_map);
+  // the blocks go back to the library's cache: no work may still use them
+  (void)hipDeviceSynchronize();
+  smart::dev_release(p->out_pix);
+  smart::dev_release(p->d_pairs);
+  smart::dev_release(p->d_work);
+  smart::dev_release(p->rot_map);
   for (smart::PixelSched* sc : p->sched) delete sc;
   for (hipEvent_t e : p->events) hipEventDestroy(e);
   delete p;
@@ -278,20 +278,20 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
     smart_plan_free(p);
     return fail(code, m);
   };
-  if (hipMalloc(&p->out_pix, sizeof(int64_t) * (n_out ? n_out : 1)) != hipSuccess ||
-      hipMalloc(&p->d_pairs, sizeof(double)) != hipSuccess ||
-      hipMalloc(&p->d_work, sizeof(int) * pixel_work_ints(n_out)) != hipSuccess)
+  if (dev_alloc(&p->out_pix, sizeof(int64_t) * (n_out ? n_out : 1)) != hipSuccess ||
+      dev_alloc(&p->d_pairs, sizeof(double)) != hipSuccess ||
+      dev_alloc(&p->d_work, sizeof(int) * pixel_work_ints(n_out)) != hipSuccess)
     return bail(SMART_ENOMEM, "device allocation failed for the plan");
   if (n_out > 0) {
     int* flag = nullptr;
-    if (hipMallocAsync((void**)&flag, sizeof(int), st) != hipSuccess) return bail(SMART_ENOMEM, "allocation failed");
+    if (scratch_alloc(&flag, sizeof(int), st) != hipSuccess) return bail(SMART_ENOMEM, "allocation failed");
     int h = 0;
     hipError_t e = hipMemcpyAsync(p->out_pix, d_out_pix, sizeof(int64_t) * n_out, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int), st);
     // range check only: reuse the monotonic check and ignore its order bit
     if (e == hipSuccess) e = launch_check_pixels(p->out_pix, n_out, 12LL * nside_out * nside_out, flag, st);
     if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st);
-    (void)hipFreeAsync(flag, st);
+    scratch_free(flag, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(SMART_EDEVICE, std::string("plan validation failed: ") + hipGetErrorString(e));
     if (h & 1) return bail(SMART_EINVAL, "output pixel out of range for nside_out");
@@ -465,7 +465,7 @@ int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int 
   const int ns = (int)p->theta_ap.size();
   // each pass writes 5 channels; E and B are copied out of a staging buffer
   float* stage = nullptr;
-  if (hipMallocAsync((void**)&stage, sizeof(float) * 5 * p->n_out, st) != hipSuccess)
+  if (scratch_alloc(&stage, sizeof(float) * 5 * p->n_out, st) != hipSuccess)
     return fail(SMART_ENOMEM, "allocation failed for staging");
   for (int r = 0; r < n_real; ++r) {
     hipError_t e = launch_rotate_map(d->sums, d->cidx, d_u + (int64_t)r * d->n_src, d->n_dense, p->rot_map, st);
@@ -492,7 +492,7 @@ int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int 
       if (e != hipSuccess) return fail(SMART_EDEVICE, "copy failed");
     }
   }
-  hipFreeAsync(stage, st);
+  scratch_free(stage, st);
   return SMART_OK;
 }
 

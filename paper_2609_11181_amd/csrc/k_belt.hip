@@ -266,20 +266,11 @@ hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t,
 }
 
 PixelSched::~PixelSched() {
-  (void)hipFree(gt_head);
-  (void)hipFree(gt_pair);
-  (void)hipFree(gt_ring);
-  (void)hipFree(belt);
-  (void)hipFree(general);
-  (void)hipFree(cursors);
-  (void)hipFree(head);
-  (void)hipFree(info);
-  (void)hipFree(qc);
-  (void)hipFree(qs);
-  (void)hipFree(q2);
-  (void)hipFree(noise_seg);
-  (void)hipFree(noise_stacks);
-  (void)hipFree(noise_rest);
+  // the owning plan's free has synchronised the device
+  for (void* q : {(void*)gt_head, (void*)gt_pair, (void*)gt_ring, (void*)belt, (void*)general, (void*)cursors,
+                  (void*)head, (void*)info, (void*)qc, (void*)qs, (void*)q2, (void*)noise_seg, (void*)noise_stacks,
+                  (void*)noise_rest})
+    dev_release(q);
 }
 
 // scratch of the schedule build: stream-ordered (pool) allocations, released
@@ -330,23 +321,23 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   auto free_scratch = [&]() {
     for (void* q : {(void*)used, (void*)flags, (void*)gflags, (void*)keys, (void*)ids, (void*)items, (void*)cnts,
                     (void*)offs, (void*)gcnt})
-      if (q) (void)hipFreeAsync(q, st);
+      scratch_free(q, st);
   };
   // cursors, then the two counts and the widest window
-  BCHK(hipMalloc((void**)&sc->cursors, sizeof(int) * (2 * kQueueInts + 3)));
-  BCHK(hipMalloc((void**)&sc->general, sizeof(int) * (nt + 1)));
-  BCHK(hipMalloc((void**)&sc->head, sizeof(int2) * nb));
-  BCHK(hipMallocAsync((void**)&flags, sizeof(int) * (nt + 1), st));
-  BCHK(hipMallocAsync((void**)&gflags, sizeof(int) * (nt + 1), st));
-  BCHK(hipMallocAsync((void**)&keys, sizeof(uint64_t) * 2 * (ns + 1), st));
-  BCHK(hipMallocAsync((void**)&ids, sizeof(int) * 2 * (ns + 1), st));
-  BCHK(hipMallocAsync((void**)&items, sizeof(int2) * (ns + 1), st));
-  BCHK(hipMallocAsync((void**)&used, sizeof(int) * nb, st));
-  BCHK(hipMallocAsync((void**)&cnts, sizeof(int2) * nb, st));
-  BCHK(hipMallocAsync((void**)&offs, sizeof(int2) * nb, st));
-  BCHK(hipMallocAsync((void**)&gcnt, sizeof(int) * 2 * nr4, st));
-  BCHK(hipMalloc((void**)&sc->gt_head, sizeof(int4) * nr4));
-  BCHK(hipMalloc((void**)&sc->gt_ring, sizeof(GenRingC) * nr4));
+  BCHK(dev_alloc(&sc->cursors, sizeof(int) * (2 * kQueueInts + 3)));
+  BCHK(dev_alloc(&sc->general, sizeof(int) * (nt + 1)));
+  BCHK(dev_alloc(&sc->head, sizeof(int2) * nb));
+  BCHK(scratch_alloc(&flags, sizeof(int) * (nt + 1), st));
+  BCHK(scratch_alloc(&gflags, sizeof(int) * (nt + 1), st));
+  BCHK(scratch_alloc(&keys, sizeof(uint64_t) * 2 * (ns + 1), st));
+  BCHK(scratch_alloc(&ids, sizeof(int) * 2 * (ns + 1), st));
+  BCHK(scratch_alloc(&items, sizeof(int2) * (ns + 1), st));
+  BCHK(scratch_alloc(&used, sizeof(int) * nb, st));
+  BCHK(scratch_alloc(&cnts, sizeof(int2) * nb, st));
+  BCHK(scratch_alloc(&offs, sizeof(int2) * nb, st));
+  BCHK(scratch_alloc(&gcnt, sizeof(int) * 2 * nr4, st));
+  BCHK(dev_alloc(&sc->gt_head, sizeof(int4) * nr4));
+  BCHK(dev_alloc(&sc->gt_ring, sizeof(GenRingC) * nr4));
   BCHK(hipMemsetAsync(used, 0, sizeof(int) * nb, st));
   BCHK(hipMemsetAsync(sc->cursors + 2 * kQueueInts + 2, 0, sizeof(int), st));  // widest window
   hipLaunchKernelGGL(k_gen_span, dim3((nr4 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.theta_ap, sc->gt_head,
@@ -403,17 +394,17 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   // ring-pair entries of the general walk (kept only when they fit kGenPairMax)
   const int64_t n_pairs = (int64_t)gt_last[0] + gt_last[1];
   if (counts[1] > 0 && n_pairs <= kGenPairMax) {
-    BCHK(hipMalloc((void**)&sc->gt_pair, sizeof(GenPair) * std::max<int64_t>(n_pairs, 1)));
+    BCHK(dev_alloc(&sc->gt_pair, sizeof(GenPair) * std::max<int64_t>(n_pairs, 1)));
     hipLaunchKernelGGL(k_gen_fill, dim3((nr4 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.C_ap, gcnt + nr4,
                        sc->gt_head, sc->gt_pair);
     BCHK(hipGetLastError());
   } else {
-    (void)hipFree(sc->gt_head);
-    (void)hipFree(sc->gt_ring);
+    dev_release(sc->gt_head);  // idle after the synchronisation above
+    dev_release(sc->gt_ring);
     sc->gt_head = nullptr;
     sc->gt_ring = nullptr;
   }
-  BCHK(hipMalloc((void**)&sc->belt, sizeof(int2) * (counts[0] + 1)));
+  BCHK(dev_alloc(&sc->belt, sizeof(int2) * (counts[0] + 1)));
   if (counts[0] > 0)
     hipLaunchKernelGGL(k_gather_items, dim3((counts[0] + kBlock - 1) / kBlock), dim3(kBlock), 0, st, items,
                        ids + ns, counts[0], sc->belt);
@@ -421,12 +412,12 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   // out-of-line per-ring set-up pays off for discs of many members per ring
   sc->general_ool = s.theta_ap * (double)N >= 16.0 * 0.75 ? 1 : 0;
   const int n_info = last_o.x + last_c.x, n_coef = last_o.y + last_c.y;
-  BCHK(hipMalloc((void**)&sc->info, sizeof(int4) * std::max(n_info, 1)));
+  BCHK(dev_alloc(&sc->info, sizeof(int4) * std::max(n_info, 1)));
   // coefficient tables with kCoefPad entries of padding (the belt kernel
   // requests the next four members' coefficients ahead of their use)
-  BCHK(hipMalloc((void**)&sc->qc, sizeof(double) * (n_coef + kCoefPad)));
-  BCHK(hipMalloc((void**)&sc->qs, sizeof(double) * (n_coef + kCoefPad)));
-  BCHK(hipMalloc((void**)&sc->q2, sizeof(float) * (n_coef + kCoefPad)));
+  BCHK(dev_alloc(&sc->qc, sizeof(double) * (n_coef + kCoefPad)));
+  BCHK(dev_alloc(&sc->qs, sizeof(double) * (n_coef + kCoefPad)));
+  BCHK(dev_alloc(&sc->q2, sizeof(float) * (n_coef + kCoefPad)));
   BCHK(hipMemsetAsync(sc->qc + n_coef, 0, sizeof(double) * kCoefPad, st));
   BCHK(hipMemsetAsync(sc->qs + n_coef, 0, sizeof(double) * kCoefPad, st));
   BCHK(hipMemsetAsync(sc->q2 + n_coef, 0, sizeof(float) * kCoefPad, st));

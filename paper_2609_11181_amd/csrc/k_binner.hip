@@ -124,9 +124,10 @@ __global__ void k_sources(int64_t n_dense, int64_t pix_first, const int* occ, co
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// device arrays of `count` elements from the library's block cache
 template <typename T>
 int dmalloc(T** p, size_t count) {
-  if (hipMalloc((void**)p, sizeof(T) * (count ? count : 1)) != hipSuccess) {
+  if (dev_alloc(p, sizeof(T) * (count ? count : 1)) != hipSuccess) {
     *p = nullptr;
     set_error("device allocation failed (" + std::to_string(sizeof(T) * count) + " bytes)");
     return SMART_ENOMEM;
@@ -181,13 +182,9 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
   unsigned int* mc = nullptr;
   int rc = SMART_OK;
   auto cleanup = [&]() {
-    (void)hipFree(keys);
-    (void)hipFree(idx);
-    (void)hipFree(skeys);
-    (void)hipFree(sidx);
-    (void)hipFree(counts);
-    (void)hipFree(flag);
-    (void)hipFree(mc);
+    (void)hipDeviceSynchronize();  // the blocks go back to the cache idle
+    for (void* q : {(void*)keys, (void*)idx, (void*)skeys, (void*)sidx, (void*)counts, (void*)flag, (void*)mc})
+      dev_release(q);
   };
   if ((rc = dmalloc(&keys, n)) || (rc = dmalloc(&idx, n)) || (rc = dmalloc(&skeys, n)) || (rc = dmalloc(&sidx, n)) ||
       (rc = dmalloc(&counts, npix + 1)) || (rc = dmalloc(&flag, 1)) || (rc = dmalloc(&mc, 1)) ||
@@ -277,8 +274,8 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
     int *occ = nullptr, *scan = nullptr;
     if ((rc = dmalloc(&occ, d->n_dense + 1)) || (rc = dmalloc(&scan, d->n_dense + 1)) ||
         (rc = dmalloc(&d->cidx, d->n_dense)) || (rc = dmalloc(&d->src_pix, n))) {
-      (void)hipFree(occ);
-      (void)hipFree(scan);
+      dev_release(occ);  // nothing has used them yet
+      dev_release(scan);
       return fail(rc);
     }
     hipLaunchKernelGGL(k_occupied, dim3(grid_of(d->n_dense)), dim3(kBlock), 0, st, d->n_dense, d->pix_first,
@@ -301,8 +298,8 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
       return fail(SMART_EDEVICE);
     }
     d->n_src = (int64_t)last_scan + last_occ;
-    (void)hipFree(occ);
-    (void)hipFree(scan);
+    dev_release(occ);  // idle after the synchronisation above
+    dev_release(scan);
     if ((rc = build_wn_prefix(ctx, d, st))) return fail(rc);
   }
   cleanup();
@@ -420,13 +417,13 @@ __global__ __launch_bounds__(kBlock) void k_wn_write(const float4* sums, int64_t
 int build_wn_prefix(smart_ctx ctx, smart_data d, hipStream_t st) {
   (void)ctx;
   if (d->n_dense <= 0) return SMART_OK;
-  if (hipMalloc((void**)&d->wn, sizeof(double2) * (d->n_dense + 1)) != hipSuccess) {
+  if (dev_alloc(&d->wn, sizeof(double2) * (d->n_dense + 1)) != hipSuccess) {
     set_error("out of device memory (prefix sums)");
     return SMART_ENOMEM;
   }
   const int64_t nb = (d->n_dense + kScanChunk - 1) / kScanChunk;
   double2* blk = nullptr;
-  if (nb > 0x7fffffff || hipMallocAsync((void**)&blk, sizeof(double2) * nb, st) != hipSuccess) {
+  if (nb > 0x7fffffff || scratch_alloc(&blk, sizeof(double2) * nb, st) != hipSuccess) {
     set_error("out of device memory (prefix sums)");
     return SMART_ENOMEM;
   }
@@ -461,7 +458,7 @@ int pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const flo
   HIPCHK(hipMemcpyAsync(&pf, pix, 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(&pl, pix + (n - 1), 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  (void)hipFree(flag);
+  dev_release(flag);
   if (hflag & 1) {
     set_error("pixel number out of range for this NSIDE");
     return SMART_EINVAL;

@@ -194,9 +194,9 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
   int4* items = nullptr;
   MixJob* d_jobs = nullptr;
   int* counter = nullptr;
-  MCHK(hipMallocAsync((void**)&items, sizeof(int4) * (size_t)n_items, st));
-  MCHK(hipMallocAsync((void**)&d_jobs, sizeof(MixJob) * jobs.size(), st));
-  MCHK(hipMallocAsync((void**)&counter, sizeof(int) * kQueueInts, st));
+  MCHK(scratch_alloc(&items, sizeof(int4) * (size_t)n_items, st));
+  MCHK(scratch_alloc(&d_jobs, sizeof(MixJob) * jobs.size(), st));
+  MCHK(scratch_alloc(&counter, sizeof(int) * kQueueInts, st));
   MCHK(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(MixJob) * jobs.size(), hipMemcpyHostToDevice, st));
   MCHK(hipMemsetAsync(counter, 0, sizeof(int) * kQueueInts, st));
   int64_t off = 0;
@@ -228,9 +228,9 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
     default: launch(k_mixed<0>, mixed_grid<0>());
   }
   MCHK(hipGetLastError());
-  MCHK(hipFreeAsync(items, st));
-  MCHK(hipFreeAsync(d_jobs, st));
-  MCHK(hipFreeAsync(counter, st));
+  scratch_free(items, st);
+  scratch_free(d_jobs, st);
+  scratch_free(counter, st);
   return SMART_OK;
 }
 

@@ -509,13 +509,13 @@ static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, h
   const int64_t n_seg = (int64_t)n_rings * ncol, n_stk = (int64_t)n_groups * ncol;
   int *flags = nullptr, *covered = nullptr, *cnt = nullptr;
   int64_t* pos = nullptr;
-  NCHK(hipMalloc((void**)&sc.noise_seg, sizeof(int4) * n_seg));
-  NCHK(hipMalloc((void**)&sc.noise_stacks, sizeof(int) * (n_stk + 1)));
-  NCHK(hipMallocAsync((void**)&flags, sizeof(int) * (std::max(n_stk, p->n_out) + 1), st));
-  NCHK(hipMallocAsync((void**)&covered, sizeof(int) * (p->n_out + 1), st));
-  NCHK(hipMallocAsync((void**)&cnt, sizeof(int) * 3, st));
+  NCHK(dev_alloc(&sc.noise_seg, sizeof(int4) * n_seg));
+  NCHK(dev_alloc(&sc.noise_stacks, sizeof(int) * (n_stk + 1)));
+  NCHK(scratch_alloc(&flags, sizeof(int) * (std::max(n_stk, p->n_out) + 1), st));
+  NCHK(scratch_alloc(&covered, sizeof(int) * (p->n_out + 1), st));
+  NCHK(scratch_alloc(&cnt, sizeof(int) * 3, st));
   NCHK(hipMemsetAsync(cnt, 0, sizeof(int) * 3, st));
-  NCHK(hipMallocAsync((void**)&pos, sizeof(int64_t) * (p->n_out + 1), st));
+  NCHK(scratch_alloc(&pos, sizeof(int64_t) * (p->n_out + 1), st));
   NCHK(hipMemsetAsync(covered, 0, sizeof(int) * (p->n_out + 1), st));
   hipLaunchKernelGGL(k_noise_segs, dim3(grid_of(n_seg)), dim3(kBlock), 0, st, a, sc.tab(), ncol, sc.noise_seg,
                      cnt + 2);
@@ -548,16 +548,16 @@ static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, h
   sc.noise_ncol = ncol;
   sc.noise_n_groups = n_groups;
   if (h[1] > 0) {
-    NCHK(hipMalloc((void**)&sc.noise_rest, sizeof(int64_t) * 2 * (size_t)h[1]));
+    NCHK(dev_alloc(&sc.noise_rest, sizeof(int64_t) * 2 * (size_t)h[1]));
     NCHK(hipMemcpyAsync(sc.noise_rest, pos, sizeof(int64_t) * h[1], hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_noise_rest_pix, dim3(grid_of(h[1])), dim3(kBlock), 0, st, sc.noise_rest, h[1], p->out_pix,
                        sc.noise_rest + h[1]);
     NCHK(hipGetLastError());
   }
-  NCHK(hipFreeAsync(flags, st));
-  NCHK(hipFreeAsync(covered, st));
-  NCHK(hipFreeAsync(cnt, st));
-  NCHK(hipFreeAsync(pos, st));
+  scratch_free(flags, st);
+  scratch_free(covered, st);
+  scratch_free(cnt, st);
+  scratch_free(pos, st);
   sc.noise_built = 1;
   return SMART_OK;
 }
@@ -587,7 +587,7 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
       if (rc) return rc;
       if (sc.counts[0] == 0) {  // no belt tables: every output takes the per-output walk
         sc.noise_n_rest = (int)p->n_out;
-        NCHK(hipMalloc((void**)&sc.noise_rest, sizeof(int64_t) * 2 * (size_t)p->n_out));
+        NCHK(dev_alloc(&sc.noise_rest, sizeof(int64_t) * 2 * (size_t)p->n_out));
         std::vector<int64_t> pos(p->n_out);
         for (int64_t i = 0; i < p->n_out; ++i) pos[i] = i;
         NCHK(hipMemcpy(sc.noise_rest, pos.data(), sizeof(int64_t) * p->n_out, hipMemcpyHostToDevice));

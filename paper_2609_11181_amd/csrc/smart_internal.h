@@ -23,6 +23,27 @@ constexpr int kQueueInts = 8 * kCursorStride;
 
 void set_error(const std::string& msg);
 
+// Device memory (devmem.cpp). Handle memory: dev_alloc hands out a cached
+// block of the request's size class when one is free; dev_release returns a
+// block to the cache, and its caller has made the device idle for the block
+// (handle frees synchronise the device first). dev_trim gives a device's
+// cached blocks back to HIP. Scratch allocated and freed in stream order
+// within a call: scratch_alloc / scratch_free, from a per-device pool that
+// keeps its memory.
+hipError_t dev_alloc(void** p, size_t bytes);
+void dev_release(void* p);
+void dev_trim(int device);
+hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t st);
+void scratch_free(void* p, hipStream_t st);
+template <typename T>
+hipError_t dev_alloc(T** p, size_t bytes) {
+  return dev_alloc((void**)p, bytes);
+}
+template <typename T>
+hipError_t scratch_alloc(T** p, size_t bytes, hipStream_t st) {
+  return scratch_alloc((void**)p, bytes, st);
+}
+
 // ---------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------
