@@ -124,7 +124,7 @@ void smart_data_free(smart_data d) {
   // the blocks go back to the library's cache: no work may still use them
   (void)hipDeviceSynchronize();
   for (void* q : {(void*)d->P, (void*)d->F, (void*)d->G, (void*)d->order, (void*)d->offsets, (void*)d->sums,
-                  (void*)d->wn, (void*)d->cidx, (void*)d->src_pix})
+                  (void*)d->wd, (void*)d->wn, (void*)d->cidx, (void*)d->src_pix})
     smart::dev_release(q);
   delete d;
 }

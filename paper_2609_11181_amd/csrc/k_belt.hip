@@ -353,7 +353,7 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   hipLaunchKernelGGL(k_is_zero, dim3((nt + kBlock - 1) / kBlock), dim3(kBlock), 0, st, flags, gflags, nt);
   size_t tb = 0, tb2 = 0, tb3 = 0, tb4 = 0;
   hipcub::CountingInputIterator<int> tile_ids(0);
-  BCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, keys + ns, ids, ids + ns, ns, 0, 57, st));
+  BCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, keys + ns, ids, ids + ns, ns, 0, kKeyBits, st));
   BCHK(hipcub::DeviceReduce::Sum(nullptr, tb3, flags, sc->cursors + 2 * kQueueInts, nt, st));
   BCHK(hipcub::DeviceSelect::Flagged(nullptr, tb4, tile_ids, gflags, sc->general, sc->cursors + 2 * kQueueInts + 1,
                                      nt, st));
@@ -369,7 +369,7 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
     return SMART_ENOMEM;
   }
   tb = p->ctx->temp_bytes;
-  BCHK(hipcub::DeviceRadixSort::SortPairs(p->ctx->d_temp, tb, keys, keys + ns, ids, ids + ns, ns, 0, 57, st));
+  BCHK(hipcub::DeviceRadixSort::SortPairs(p->ctx->d_temp, tb, keys, keys + ns, ids, ids + ns, ns, 0, kKeyBits, st));
   tb = p->ctx->temp_bytes;
   BCHK(hipcub::DeviceReduce::Sum(p->ctx->d_temp, tb, flags, sc->cursors + 2 * kQueueInts, nt, st));
   tb = p->ctx->temp_bytes;

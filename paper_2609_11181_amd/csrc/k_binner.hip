@@ -98,11 +98,14 @@ __global__ void k_check_pix(const int64_t* pix, int64_t n, int64_t npix, int* fl
 }
 
 __global__ void k_scatter(int64_t n, const int64_t* pix, int64_t pix_first, const float* W, const float* G1,
-                          const float* G2, const float* E2, float4* sums, int* cidx) {
+                          const float* G2, const float* E2, float4* sums, float* wd, int* cidx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  sums[pix[i] - pix_first] = make_float4(G1[i], G2[i], E2[i], W[i]);
-  cidx[pix[i] - pix_first] = (int)i;
+  const int64_t j = pix[i] - pix_first;
+  const float w = W[i];
+  sums[j] = make_float4(G1[i], G2[i], E2[i], w);
+  wd[j] = w;
+  cidx[j] = (int)i;
 }
 
 __global__ void k_occupied(int64_t n_dense, int64_t pix_first, const int64_t* off, int* occ) {
@@ -412,6 +415,66 @@ __global__ __launch_bounds__(kBlock) void k_wn_write(const float4* sums, int64_t
   }
 }
 
+// The same two passes over a dense weight array (one float per pixel) for
+// pixel maps: 16-byte loads of four weights.
+__device__ __forceinline__ float4 load_w4(const float* w, int64_t i, int64_t n) {
+  if (i + 3 < n) return *(const float4*)(w + i);
+  float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (i < n) q.x = w[i];
+  if (i + 1 < n) q.y = w[i + 1];
+  if (i + 2 < n) q.z = w[i + 2];
+  return q;
+}
+
+__device__ __forceinline__ double2 wn_of(float w) { return make_double2((double)w, w > 0.f ? 1.0 : 0.0); }
+
+__global__ __launch_bounds__(kBlock) void k_wn_reduce_w(const float* w, int64_t n, double2* blk) {
+  __shared__ double2 red[kBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < kScanPer / 4; ++j) {
+    const float4 q = load_w4(w, base + 4 * ((int64_t)j * kBlock + threadIdx.x), n);
+    v = add2(v, add2(add2(wn_of(q.x), wn_of(q.y)), add2(wn_of(q.z), wn_of(q.w))));
+  }
+  const double2 t = block_sum2(v, red);
+  if (threadIdx.x == 0) blk[blockIdx.x] = t;
+}
+
+// Rows of 4 kBlock pixels: thread t scans its four consecutive pixels, the
+// block scans the thread totals, and the row's prefixes pass through LDS so
+// that the stores are coalesced.
+__global__ __launch_bounds__(kBlock) void k_wn_write_w(const float* w, int64_t n, const double2* blk,
+                                                       double2* wn) {
+  __shared__ double2 red[kBlock / 64];
+  __shared__ double2 row[4 * kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  double2 carry = blk[blockIdx.x];
+  for (int j = 0; j < kScanPer / 4; ++j) {
+    const int64_t r0 = base + (int64_t)j * 4 * kBlock;
+    const float4 q = load_w4(w, r0 + 4 * threadIdx.x, n);
+    const double2 p0 = wn_of(q.x);
+    const double2 p1 = add2(p0, wn_of(q.y));
+    const double2 p2 = add2(p1, wn_of(q.z));
+    const double2 p3 = add2(p2, wn_of(q.w));
+    const double2 off = block_exscan2(p3, carry, red);
+    double2 tot = carry;
+    for (int k = 0; k < kBlock / 64; ++k) tot = add2(tot, red[k]);
+    row[4 * threadIdx.x + 0] = add2(off, p0);
+    row[4 * threadIdx.x + 1] = add2(off, p1);
+    row[4 * threadIdx.x + 2] = add2(off, p2);
+    row[4 * threadIdx.x + 3] = add2(off, p3);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t o = r0 + k * kBlock + threadIdx.x;
+      if (o < n) wn[o + 1] = row[k * kBlock + threadIdx.x];
+    }
+    carry = tot;
+    __syncthreads();  // row and red are rewritten by the next row
+  }
+}
+
 }  // namespace
 
 int build_wn_prefix(smart_ctx ctx, smart_data d, hipStream_t st) {
@@ -427,9 +490,15 @@ int build_wn_prefix(smart_ctx ctx, smart_data d, hipStream_t st) {
     set_error("out of device memory (prefix sums)");
     return SMART_ENOMEM;
   }
-  hipLaunchKernelGGL(k_wn_reduce, dim3((unsigned)nb), dim3(kBlock), 0, st, d->sums, d->n_dense, blk);
-  hipLaunchKernelGGL(k_wn_scan_blocks, dim3(1), dim3(kBlock), 0, st, blk, (int)nb);
-  hipLaunchKernelGGL(k_wn_write, dim3((unsigned)nb), dim3(kBlock), 0, st, d->sums, d->n_dense, blk, d->wn);
+  if (d->wd) {
+    hipLaunchKernelGGL(k_wn_reduce_w, dim3((unsigned)nb), dim3(kBlock), 0, st, d->wd, d->n_dense, blk);
+    hipLaunchKernelGGL(k_wn_scan_blocks, dim3(1), dim3(kBlock), 0, st, blk, (int)nb);
+    hipLaunchKernelGGL(k_wn_write_w, dim3((unsigned)nb), dim3(kBlock), 0, st, d->wd, d->n_dense, blk, d->wn);
+  } else {
+    hipLaunchKernelGGL(k_wn_reduce, dim3((unsigned)nb), dim3(kBlock), 0, st, d->sums, d->n_dense, blk);
+    hipLaunchKernelGGL(k_wn_scan_blocks, dim3(1), dim3(kBlock), 0, st, blk, (int)nb);
+    hipLaunchKernelGGL(k_wn_write, dim3((unsigned)nb), dim3(kBlock), 0, st, d->sums, d->n_dense, blk, d->wn);
+  }
   if (hipMemsetAsync(d->wn, 0, sizeof(double2), st) != hipSuccess || hipGetLastError() != hipSuccess ||
       hipFreeAsync(blk, st) != hipSuccess) {
     set_error("prefix-sum scan failed");
@@ -470,14 +539,16 @@ int pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const flo
   d->kind = 1;
   d->nside = nside;
   ring_range(nside, pf, pl, d);
-  if ((rc = dmalloc(&d->sums, d->n_dense)) || (rc = dmalloc(&d->cidx, d->n_dense)) || (rc = dmalloc(&d->src_pix, n)))
+  if ((rc = dmalloc(&d->sums, d->n_dense)) || (rc = dmalloc(&d->wd, d->n_dense)) ||
+      (rc = dmalloc(&d->cidx, d->n_dense)) || (rc = dmalloc(&d->src_pix, n)))
     return rc;
   d->n_src = n;
   HIPCHK(hipMemsetAsync(d->sums, 0, sizeof(float4) * d->n_dense, st));
+  HIPCHK(hipMemsetAsync(d->wd, 0, sizeof(float) * d->n_dense, st));
   HIPCHK(hipMemsetAsync(d->cidx, 0xff, sizeof(int) * d->n_dense, st));
   HIPCHK(hipMemcpyAsync(d->src_pix, pix, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
   hipLaunchKernelGGL(k_scatter, dim3(grid_of(n)), dim3(kBlock), 0, st, n, pix, d->pix_first, W, G1, G2, E2, d->sums,
-                     d->cidx);
+                     d->wd, d->cidx);
   HIPCHK(hipGetLastError());
   return build_wn_prefix(ctx, d, st);
 }

@@ -99,15 +99,14 @@ __global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_a
           int rp, ip;
           pixel_ring(a.nside_out, a.out_pix[pos], &rp, &ip);
           items[t * kRuns + r] = make_int2((int)pos, 0);
-          keys[t * kRuns + r] = ((uint64_t)(ip / kBlock) << 40) | ((uint64_t)rp << 24) |
-                                (uint64_t)((t * kRuns + r) & 0xffffff);
+          keys[t * kRuns + r] = ((uint64_t)(ip / kBlock) << kKeyRingBits) | (uint64_t)rp;
         }
         prev = pos;
         ++r;
       }
     }
     if (runs > 0) items[t * kRuns + runs - 1].y = (int)(oe - prev);
-    for (int q = runs; q < kRuns; ++q) keys[t * kRuns + q] = (1ull << 56) | (uint64_t)(t * kRuns + q);
+    for (int q = runs; q < kRuns; ++q) keys[t * kRuns + q] = 1ull << (kKeyBits - 1);
   }
 }
 

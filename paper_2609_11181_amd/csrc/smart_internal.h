@@ -95,6 +95,7 @@ struct smart_data_s {
   int ring_lo = 0, ring_hi = -1;
   int64_t pix_first = 0, n_dense = 0;
   float4* sums = nullptr;  // (G1, G2, E2, W): the pair kernels read the first three
+  float* wd = nullptr;     // pixel maps: W of the dense range again, contiguous (prefix-sum input)
   // prefix sums over the dense range: wn[i] = (sum of W, number of pixels
   // with W > 0) over dense pixels [0, i); n_dense + 1 entries
   double2* wn = nullptr;
@@ -260,6 +261,12 @@ size_t pixel_work_ints(int64_t n_out);
 // (0: general tile) in items[kRuns t ..] with their sort keys, and
 // used[rp - nside] = 1 for every belt ring that gets a table.
 constexpr int kRuns = 4;
+// Sort key of an item slot: (azimuth column ip / 256, ring), unused slots
+// last (top bit). The radix sort is stable and the slots enter in list
+// order, so items with equal keys keep their list order.
+constexpr int kKeyRingBits = 15;  // ring < 4 nside <= 2^15
+constexpr int kKeyBits = kKeyRingBits + 7 + 1;
+static_assert(4 * kMaxNside <= (1 << kKeyRingBits) && 4 * kMaxNside / kBlock <= (1 << 7), "item key fields");
 void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* nrun, int2* items, uint64_t* keys,
                      int* used, hipStream_t st);
 // Scheduled path: belt tiles through the tables, general tiles as above.
