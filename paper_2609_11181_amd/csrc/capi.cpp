@@ -68,10 +68,10 @@ void smart_finalize(smart_ctx ctx) {
   for (auto& f : ctx->filters) {
     hipFree(f.d_table);
     hipFree(f.d_table_c0);
-    hipFree(f.d_pieces);
   }
   if (ctx->d_temp) hipFree(ctx->d_temp);
   (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->sin_pieces) smart::dev_release(kv.second);
   smart::dev_trim(ctx->device);  // cached handle blocks go back to HIP
   delete ctx;
 }

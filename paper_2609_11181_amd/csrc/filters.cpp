@@ -8,6 +8,7 @@
 // below 1e-8 of the filter maximum (the fourth derivative of the steepest
 // part, the logistic switch of slope 150 in the NFW-like filter, bounds it).
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <string>
@@ -93,7 +94,6 @@ int build_filter(FilterDef& f) {
   for (int i = 0; i <= K; ++i) eval_both(f, i * h, &qv[i], &dv[i]);  // x = 1: left limit
   f.h_table.resize(4 * K);
   std::vector<double> c0(K);
-  std::vector<FilterPiece> pieces(K + 1);
   for (int i = 0; i < K; ++i) {
     const double q0 = qv[i], q1 = qv[i + 1], d0 = dv[i] * h, d1 = dv[i + 1] * h;
     f.h_table[4 * i + 0] = (float)q0;
@@ -101,9 +101,7 @@ int build_filter(FilterDef& f) {
     f.h_table[4 * i + 1] = (float)d0;
     f.h_table[4 * i + 2] = (float)(3.0 * (q1 - q0) - 2.0 * d0 - d1);
     f.h_table[4 * i + 3] = (float)(2.0 * (q0 - q1) + d0 + d1);
-    pieces[i] = FilterPiece{q0, f.h_table[4 * i + 1], f.h_table[4 * i + 2], f.h_table[4 * i + 3], 0.f};
   }
-  pieces[K] = FilterPiece{qv[K], 0.f, 0.f, 0.f, 0.f};
   if (hipMalloc(&f.d_table, sizeof(float) * 4 * K) != hipSuccess) {
     set_error("hipMalloc failed for a filter table");
     return SMART_ENOMEM;
@@ -112,17 +110,47 @@ int build_filter(FilterDef& f) {
     set_error("hipMalloc failed for a filter table");
     return SMART_ENOMEM;
   }
-  if (hipMalloc(&f.d_pieces, sizeof(FilterPiece) * (K + 1)) != hipSuccess) {
-    set_error("hipMalloc failed for a filter table");
-    return SMART_ENOMEM;
-  }
   if (hipMemcpy(f.d_table, f.h_table.data(), sizeof(float) * 4 * K, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(f.d_table_c0, c0.data(), sizeof(double) * K, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(f.d_pieces, pieces.data(), sizeof(FilterPiece) * (K + 1), hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(f.d_table_c0, c0.data(), sizeof(double) * K, hipMemcpyHostToDevice) != hipSuccess) {
     set_error("copy of a filter table failed");
     return SMART_EDEVICE;
   }
   return SMART_OK;
+}
+
+// The filter of one aperture as a table in y = sin(theta) for the general
+// pixel walk, which gets sin(theta) of every pair from its tangent-plane
+// components: Hermite pieces over [0, sin theta_ap] from the exact values
+// q(asin(y) / theta_ap) and derivatives dq/dx / (theta_ap cos theta), and a
+// constant piece q(1) at index kFilterIntervals (y = sin theta_ap exactly,
+// and its rounding, index no further). Device copy, or null on failure.
+FilterPiece* build_sin_pieces(const FilterDef& f, double theta_ap) {
+  const int K = kFilterIntervals;
+  const double ymax = sin(theta_ap), h = ymax / K;
+  std::vector<double> qv(K + 1), dv(K + 1);
+  for (int i = 0; i <= K; ++i) {
+    const double y = i == K ? ymax : i * h;
+    const double x = i == K ? 1.0 : asin(y) / theta_ap;  // x = 1: left limit
+    double q, dq;
+    eval_both(f, x, &q, &dq);
+    qv[i] = q;
+    dv[i] = dq / (theta_ap * sqrt(1.0 - y * y));
+  }
+  std::vector<FilterPiece> pieces(K + 1);
+  for (int i = 0; i < K; ++i) {
+    const double q0 = qv[i], q1 = qv[i + 1], d0 = dv[i] * h, d1 = dv[i + 1] * h;
+    pieces[i] = FilterPiece{q0, (float)d0, (float)(3.0 * (q1 - q0) - 2.0 * d0 - d1),
+                            (float)(2.0 * (q0 - q1) + d0 + d1), 0.f};
+  }
+  pieces[K] = FilterPiece{qv[K], 0.f, 0.f, 0.f, 0.f};
+  FilterPiece* d = nullptr;
+  if (dev_alloc(&d, sizeof(FilterPiece) * (K + 1)) != hipSuccess) return nullptr;
+  if (hipMemcpy(d, pieces.data(), sizeof(FilterPiece) * (K + 1), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipDeviceSynchronize();
+    dev_release(d);
+    return nullptr;
+  }
+  return d;
 }
 
 ScaleArgs make_scale(smart_ctx ctx, double theta_ap, int filter_id, double omega_pix) {
@@ -138,7 +166,15 @@ ScaleArgs make_scale(smart_ctx ctx, double theta_ap, int filter_id, double omega
   s.big = theta_ap > 2.0 * M_PI / 180.0 ? 1 : 0;
   s.table = f.d_table;
   s.table_c0 = f.d_table_c0;
-  s.pieces = f.d_pieces;
+  s.pieces = nullptr;
+  s.t_sin = (double)kFilterIntervals / sin(theta_ap);
+  if (f.kind != SMART_FILTER_POLY) {
+    uint64_t bits;
+    memcpy(&bits, &theta_ap, sizeof bits);
+    auto& slot = ctx->sin_pieces[{filter_id, bits}];
+    if (!slot) slot = build_sin_pieces(f, theta_ap);
+    s.pieces = slot;
+  }
   // asin(y) / y = sum c_k y^(2k), divided by theta_ap so that x = y * P(y^2);
   // for tabulated filters also multiplied by the number of table pieces, so
   // the series gives the table coordinate directly

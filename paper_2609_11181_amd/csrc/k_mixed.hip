@@ -157,6 +157,10 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
       const PixelSched& sc = *P->sched[k];
       MixJob J{};
       J.s = make_scale(ctx, P->theta_ap[k], P->filter_ids[k], omega);
+      if (J.s.filter_kind != SMART_FILTER_POLY && !J.s.pieces) {
+        set_error("mixed batch: no device memory for a filter table");
+        return SMART_ENOMEM;
+      }
       J.a.out_pix = P->out_pix;
       J.a.n_out = P->n_out;
       J.a.nside_out = P->nside_out;

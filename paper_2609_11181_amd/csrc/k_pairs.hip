@@ -420,6 +420,7 @@ static hipError_t launch_general_g(const PixelArgs& a, const ScaleArgs& s, hipSt
 
 static hipError_t launch_general(const PixelArgs& a, const ScaleArgs& s, hipStream_t st, const int* list, int count,
                                  int* cursors, int ool = 0, int blocks_per_cu = 0) {
+  if (s.filter_kind != SMART_FILTER_POLY && !s.pieces) return hipErrorOutOfMemory;  // its sin(theta) table
   return a.gt_head ? launch_general_g<1>(a, s, st, list, count, cursors, ool, blocks_per_cu)
                    : launch_general_g<0>(a, s, st, list, count, cursors, ool, blocks_per_cu);
 }

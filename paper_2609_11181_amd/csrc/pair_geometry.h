@@ -84,16 +84,17 @@ __device__ __forceinline__ double filter_q(double x, Tab tab) {
   }
 }
 
-// q from a table of FilterPiece records (TABLE; t = x * kFilterIntervals),
-// or of x for the polynomial filter. Below BIG apertures x stays within
-// 1e-9 of [0, 1] (exact windows, series error below 1e-10), so t indexes at
-// most the table's constant last record and needs no clamp.
-template <bool TABLE, bool BIG>
+// q from a table of FilterPiece records at the table coordinate t (TABLE),
+// or of t = theta / theta_ap for the polynomial filter. The general pixel
+// walk's tables are in t = sin(theta) * kFilterIntervals / sin(theta_ap):
+// inside the exact windows t exceeds kFilterIntervals by rounding at most
+// (sin theta to 1e-14), where the table's constant last piece holds q(1),
+// so the index needs no clamp.
+template <bool TABLE>
 __device__ __forceinline__ double filter_piece(double t, const FilterPiece* tab) {
   if (TABLE) {
-    const double tc = BIG ? fmin(t, (double)kFilterIntervals - 2e-7) : t;
-    const int i = (int)tc;  // 0 <= i <= kFilterIntervals: a 24-bit product gives the offset
-    const double fd = __builtin_amdgcn_fract(tc);
+    const int i = (int)t;  // 0 <= i <= kFilterIntervals: a 24-bit product gives the offset
+    const double fd = __builtin_amdgcn_fract(t);
     const float f = (float)fd;
     const FilterPiece c =
         *(const FilterPiece*)((const char*)tab + __umul24((unsigned)i, (unsigned)sizeof(FilterPiece)));

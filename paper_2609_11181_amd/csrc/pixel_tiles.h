@@ -109,15 +109,17 @@ __device__ __attribute__((noinline)) void general_sin_hav(double av, double* sa,
 // qh = q x y / sin^2 theta; doubling is exact).
 template <bool TABLE, bool BIG>
 __device__ __forceinline__ void general_member(double xt, double h, double Y0, double Kz, float4 g, const double* tp,
-                                               const FilterPiece* tab, Acc64& tot, double& e2, double& b2,
-                                               float& sv) {
+                                               const FilterPiece* tab, double t_sin, Acc64& tot, double& e2,
+                                               double& b2, float& sv) {
   const double yt = fma(Kz, h, Y0);
   const double yy = yt * yt;
   const double S2 = fma(xt, xt, yy);
   const double S2c = fmax(S2, (double)kCoincidentS2);
   const double r0 = (double)__builtin_amdgcn_rsqf((float)S2c);
   const double r = r0 * fma(-0.5 * S2c, r0 * r0, 1.5);
-  const double q = filter_piece<TABLE, BIG>(theta_ratio<BIG>(S2 * r, S2, tp), tab);
+  // table filters: q from the table in sin(theta); the polynomial filter
+  // takes theta / theta_ap from the asin series
+  const double q = filter_piece<TABLE>(TABLE ? (S2 * r) * t_sin : theta_ratio<BIG>(S2 * r, S2, tp), tab);
   const double qn = q * (r * r);
   const double qc = qn * fma(2.0, yy, -S2);
   const double qh = qn * (xt * yt);
@@ -238,12 +240,12 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
           for (int u = 0; u < U; ++u) g[u] = p[k0 + k + u];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, g[u], tp, tab, tot, e2, b2, sv);
+            general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, g[u], tp, tab, s.t_sin, tot, e2, b2, sv);
             w.advance();
           }
         }
         for (; k < kn; ++k) {
-          general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, p[k0 + k], tp, tab, tot, e2, b2, sv);
+          general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, p[k0 + k], tp, tab, s.t_sin, tot, e2, b2, sv);
           w.advance();
         }
         tot.sv += sv;

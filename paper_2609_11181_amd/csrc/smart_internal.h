@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/smartap.h"
@@ -63,10 +65,6 @@ struct FilterDef {
   std::vector<double> samples;  // SMART_FILTER_TABLE
   float4* d_table = nullptr;    // kFilterIntervals cubic pieces (c0, c1, c2, c3) in FP32
   double* d_table_c0 = nullptr;  // c0 of every piece in FP64
-  // the same pieces as FilterPiece records, plus a constant piece
-  // q = q(1) at index kFilterIntervals, so that x = 1 (and the rounding
-  // just above it) needs no clamp
-  FilterPiece* d_pieces = nullptr;
   std::vector<float> h_table;
 };
 
@@ -77,6 +75,9 @@ struct smart_ctx_s {
   std::vector<smart::FilterDef> filters;
   void* d_temp = nullptr;  // scratch for library sorts and scans
   size_t temp_bytes = 0;
+  // filter tables in sin(theta) of the general pixel walk, one per (filter,
+  // aperture bits), built on first use (filters.cpp)
+  std::map<std::pair<int, uint64_t>, smart::FilterPiece*> sin_pieces;
 };
 
 struct smart_data_s {
@@ -150,7 +151,11 @@ struct ScaleArgs {
   int big;           // 1 when theta_ap > 2 degrees (longer asin series)
   const float4* table;
   const double* table_c0;
-  const FilterPiece* pieces;  // kFilterIntervals + 1 records
+  // the filter as a table in t = sin(theta) * t_sin (kFilterIntervals
+  // pieces over [0, sin theta_ap] plus the constant piece q(1)), for the
+  // general pixel walk; null if it could not be built
+  const FilterPiece* pieces;
+  double t_sin;
   double tpoly[7];   // asin(y)/y series in y^2, divided by theta_ap (x from sin theta)
   double cpoly[7];   // 2 asin(c/2)/c series in c^2, divided by theta_ap (x from the chord c)
   double tanh_p[5];  // FP64 path: tanh filter parameters
