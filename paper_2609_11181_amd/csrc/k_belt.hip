@@ -42,8 +42,12 @@ __device__ inline void belt_span(const PixelArgs& a, double theta_ap, int rp, in
 // General-walk tables. gt_head[rp] for every centre ring: (entries of the
 // ring pairs, first source ring, last source ring), the same source rings
 // as the per-centre walk (ring span of the disc, clipped to the map's rings).
-__global__ void k_gen_span(PixelArgs a, double theta_ap, int4* head, int* cnt) {
+// Also clears the per-belt-ring flags `used` (nb entries) and the widest-window
+// cell that k_classify and k_belt_size fill next.
+__global__ void k_gen_span(PixelArgs a, double theta_ap, int4* head, int* cnt, int* used, int nb, int* widest) {
   const int rp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rp < nb) used[rp] = 0;
+  if (rp == 0) *widest = 0;
   if (rp >= 4 * a.nside_out) return;
   int lo = 0, hi = -1;
   if (rp >= 1) {
@@ -143,7 +147,8 @@ struct Sum2i {
 // member for the centre at azimuth index 0.
 template <bool TABLE, bool BIG>
 __global__ __launch_bounds__(kBlock) void k_belt_fill(PixelArgs a, ScaleArgs s, const int2* cnts, const int2* offs,
-                                                      int2* head, int4* info, double* qc, double* qs, float* q2) {
+                                                      int2* head, int4* info, double* qc, double* qs, float* q2,
+                                                      int n_coef) {
   __shared__ int s_off[kRingCap + 1];
   __shared__ int s_m0[kRingCap];
   __shared__ double s_y0[kRingCap], s_kz[kRingCap];
@@ -153,6 +158,11 @@ __global__ __launch_bounds__(kBlock) void k_belt_fill(PixelArgs a, ScaleArgs s, 
   const int2 c = cnts[idx];
   const int2 base = offs[idx];  // (first table ring, first coefficient)
   if (tid == 0) head[idx] = make_int2(base.x, c.x);
+  if (idx == 0 && tid < kCoefPad) {  // the zero padding after the last coefficient
+    qc[n_coef + tid] = 0.0;
+    qs[n_coef + tid] = 0.0;
+    q2[n_coef + tid] = 0.f;
+  }
   if (c.x == 0) return;
   const int rp = N + idx;
   const Ring R = ring_info(N, rp);
@@ -318,30 +328,39 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   const int nt = (int)((p->n_out + kBlock - 1) / kBlock);
   const int ns = kRuns * nt;  // item slots
   sc->n_tiles = nt;
-  auto free_scratch = [&]() {
-    for (void* q : {(void*)used, (void*)flags, (void*)gflags, (void*)keys, (void*)ids, (void*)items, (void*)cnts,
-                    (void*)offs, (void*)gcnt})
-      scratch_free(q, st);
-  };
+  char* scratch = nullptr;  // the arrays above, carved from one stream-ordered block
+  auto free_scratch = [&]() { scratch_free(scratch, st); };
   // cursors, then the two counts and the widest window
   BCHK(dev_alloc(&sc->cursors, sizeof(int) * (2 * kQueueInts + 3)));
   BCHK(dev_alloc(&sc->general, sizeof(int) * (nt + 1)));
   BCHK(dev_alloc(&sc->head, sizeof(int2) * nb));
-  BCHK(scratch_alloc(&flags, sizeof(int) * (nt + 1), st));
-  BCHK(scratch_alloc(&gflags, sizeof(int) * (nt + 1), st));
-  BCHK(scratch_alloc(&keys, sizeof(uint64_t) * 2 * (ns + 1), st));
-  BCHK(scratch_alloc(&ids, sizeof(int) * 2 * (ns + 1), st));
-  BCHK(scratch_alloc(&items, sizeof(int2) * (ns + 1), st));
-  BCHK(scratch_alloc(&used, sizeof(int) * nb, st));
-  BCHK(scratch_alloc(&cnts, sizeof(int2) * nb, st));
-  BCHK(scratch_alloc(&offs, sizeof(int2) * nb, st));
-  BCHK(scratch_alloc(&gcnt, sizeof(int) * 2 * nr4, st));
+  {
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+      const size_t o = off;
+      off += (bytes + 255) & ~(size_t)255;
+      return o;
+    };
+    const size_t o_flags = carve(sizeof(int) * (nt + 1)), o_gflags = carve(sizeof(int) * (nt + 1));
+    const size_t o_keys = carve(sizeof(uint64_t) * 2 * (ns + 1)), o_ids = carve(sizeof(int) * 2 * (ns + 1));
+    const size_t o_items = carve(sizeof(int2) * (ns + 1)), o_used = carve(sizeof(int) * nb);
+    const size_t o_cnts = carve(sizeof(int2) * nb), o_offs = carve(sizeof(int2) * nb);
+    const size_t o_gcnt = carve(sizeof(int) * 2 * nr4);
+    BCHK(scratch_alloc(&scratch, off, st));
+    flags = (int*)(scratch + o_flags);
+    gflags = (int*)(scratch + o_gflags);
+    keys = (uint64_t*)(scratch + o_keys);
+    ids = (int*)(scratch + o_ids);
+    items = (int2*)(scratch + o_items);
+    used = (int*)(scratch + o_used);
+    cnts = (int2*)(scratch + o_cnts);
+    offs = (int2*)(scratch + o_offs);
+    gcnt = (int*)(scratch + o_gcnt);
+  }
   BCHK(dev_alloc(&sc->gt_head, sizeof(int4) * nr4));
   BCHK(dev_alloc(&sc->gt_ring, sizeof(GenRingC) * nr4));
-  BCHK(hipMemsetAsync(used, 0, sizeof(int) * nb, st));
-  BCHK(hipMemsetAsync(sc->cursors + 2 * kQueueInts + 2, 0, sizeof(int), st));  // widest window
   hipLaunchKernelGGL(k_gen_span, dim3((nr4 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.theta_ap, sc->gt_head,
-                     gcnt);
+                     gcnt, used, nb, sc->cursors + 2 * kQueueInts + 2);
   hipLaunchKernelGGL(k_gen_rings, dim3((nr4 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, N, sc->gt_ring);
   BCHK(hipGetLastError());
   // order of the schedule: belt items column-major (items of one azimuth
@@ -418,13 +437,10 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   BCHK(dev_alloc(&sc->qc, sizeof(double) * (n_coef + kCoefPad)));
   BCHK(dev_alloc(&sc->qs, sizeof(double) * (n_coef + kCoefPad)));
   BCHK(dev_alloc(&sc->q2, sizeof(float) * (n_coef + kCoefPad)));
-  BCHK(hipMemsetAsync(sc->qc + n_coef, 0, sizeof(double) * kCoefPad, st));
-  BCHK(hipMemsetAsync(sc->qs + n_coef, 0, sizeof(double) * kCoefPad, st));
-  BCHK(hipMemsetAsync(sc->q2 + n_coef, 0, sizeof(float) * kCoefPad, st));
   const bool table = s.filter_kind != SMART_FILTER_POLY;
   auto fill = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, a, s, cnts, offs, sc->head, sc->info, sc->qc, sc->qs,
-                       sc->q2);
+                       sc->q2, n_coef);
   };
   if (table && s.big) fill(k_belt_fill<true, true>);
   else if (table) fill(k_belt_fill<true, false>);
