@@ -154,10 +154,8 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
   // the centre ring's source rings and their ring-pair terms come from the
   // plan's tables when it has them (the same values, computed once per ring
   // pair instead of once per centre)
-  // 1 / (2 np) and pi / np for the window start and the first azimuth
-  // offset of every ring
+  // 1 / (2 np) for the centre's azimuth in the ring steps of every ring
   const double h2np = 0.5 / (double)np;
-  const double pinp = (2.0 * kPi) * h2np;
   const double rsp = 1.0 / sp;
   const bool gt = GT == 2 ? a.gt_head != nullptr : GT == 1;
   int lo, hi, e0 = 0;
@@ -178,14 +176,20 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
   for (int r = lo; r <= hi; ++r) {
     int64_t jlo, first;
     int cnt, nq, twice_o;
-    double Y0, Kz, rnq, sd, hd;
+    double Y0, Kz, rnq, sd, hd, u0;
     if (gt) {
-      const GenPair e = a.gt_pair[e0 + r];
+      GenPair e;  // one 32-byte entry: two 16-byte loads
+      {
+        const uint4* src = (const uint4*)(a.gt_pair + e0 + r);
+        const uint4 lo4 = src[0], hi4 = src[1];
+        __builtin_memcpy(&e, &lo4, 16);
+        __builtin_memcpy((char*)&e + 16, &hi4, 16);
+      }
       const GenRingC q = a.gt_ring[r];
       nq = q.n;
       twice_o = q.twice_o;
       rnq = q.rn;
-      const double u0 = (double)ip2 * ((double)nq * h2np) - 0.5 * (double)twice_o;
+      u0 = (double)ip2 * ((double)nq * h2np) - 0.5 * (double)twice_o;
       if (!window_at_u(PairWin{e.w, e.kind}, u0, nq, &jlo, &cnt)) continue;
       Y0 = e.Y0;
       Kz = e.Kz;
@@ -199,6 +203,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
       if (!reached) continue;
       nq = Q.n;
       twice_o = Q.twice_o;
+      u0 = (double)ip2 * ((double)nq * h2np) - 0.5 * (double)twice_o;
       rnq = 1.0 / (double)nq;
       Y0 = ring_y0(Q.s, Q.z, zp, sp);
       Kz = 2.0 * Q.z * sp;
@@ -208,18 +213,23 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     }
     XStep step;
     step.init(sd, hd, sp, rsp);
-    // dphi of the first member = pi m / (np nq) with m an exact integer
-    const int64_t m = ip2 * nq - (2 * jlo + twice_o) * (int64_t)np;
+    // azimuth offset of the first member: 2 pi (u0 - jlo) / nq (u0 to an
+    // ulp, about 1e-15 rad here, far below any pixel separation)
     double sa, h;
-    const double av = (double)m * (pinp * rnq);
+    const double av = (u0 - (double)jlo) * ((2.0 * kPi) * rnq);
     if (OOL) general_sin_hav(av, &sa, &h);
     else sin_hav(av, &sa, &h);
     XWalk3 w;
     w.start(step, sp * sa, h);
-    // the member at the centre itself (same ring, dphi = 0), if any: the walk
-    // restarts there from exact zeros, so its shear term vanishes exactly
-    const int64_t mstep = 2 * (int64_t)np;
-    const int kc = (Y0 == 0.0 && m >= 0 && m % mstep == 0 && m / mstep < cnt) ? (int)(m / mstep) : -1;
+    // the member at the centre itself (same colatitude, dphi = 0), if any,
+    // from the exact integer offset pi m / (np nq): the walk restarts there
+    // from exact zeros, so its shear term vanishes exactly
+    int kc = -1;
+    if (Y0 == 0.0) {
+      const int64_t m = ip2 * nq - (2 * jlo + twice_o) * (int64_t)np;
+      const int64_t mstep = 2 * (int64_t)np;
+      if (m >= 0 && m % mstep == 0 && m / mstep < cnt) kc = (int)(m / mstep);
+    }
     const int64_t dring = first - a.pix_first;
     int jw = window_start(jlo, nq);
     int kdone = 0;
