@@ -110,7 +110,7 @@ __device__ __attribute__((noinline)) void general_sin_hav(double av, double* sa,
 template <bool TABLE, bool BIG>
 __device__ __forceinline__ void general_member(double xt, double h, double Y0, double Kz, float4 g, const double* tp,
                                                const FilterPiece* tab, double t_sin, Acc64& tot, double& e2,
-                                               double& b2, float& sv) {
+                                               double& b2) {
   const double yt = fma(Kz, h, Y0);
   const double yy = yt * yt;
   const double S2 = fma(xt, xt, yy);
@@ -128,7 +128,7 @@ __device__ __forceinline__ void general_member(double xt, double h, double Y0, d
   e2 = fma(qh, a2, e2);
   tot.sb = fma(qc, a2, tot.sb);
   b2 = fma(qh, a1, b2);
-  sv = fmaf((float)(q * q), g.z, sv);
+  tot.sv = fma(q * q, (double)g.z, tot.sv);
 }
 
 // One centre of a general tile (list entry o), walking its own disc windows
@@ -239,26 +239,21 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
       if (kdone == kc) w.restart(step);
       run_wn(a.wn, dring + jw, run, tot);
       const float4* p = a.map + dring + jw;
-      for (int k0 = 0; k0 < run; k0 += kChunk) {
-        const int kn = min(run - k0, kChunk);
-        float sv = 0.f;
-        int k = 0;
-        constexpr int U = OOL ? 2 : 4;  // members in flight
-        for (; k + U <= kn; k += U) {
-          float4 g[U];
+      int k = 0;
+      constexpr int U = OOL ? 2 : 4;  // members in flight
+      for (; k + U <= run; k += U) {
+        float4 g[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) g[u] = p[k0 + k + u];
+        for (int u = 0; u < U; ++u) g[u] = p[k + u];
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, g[u], tp, tab, s.t_sin, tot, e2, b2, sv);
-            w.advance();
-          }
-        }
-        for (; k < kn; ++k) {
-          general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, p[k0 + k], tp, tab, s.t_sin, tot, e2, b2, sv);
+        for (int u = 0; u < U; ++u) {
+          general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, g[u], tp, tab, s.t_sin, tot, e2, b2);
           w.advance();
         }
-        tot.sv += sv;
+      }
+      for (; k < run; ++k) {
+        general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, p[k], tp, tab, s.t_sin, tot, e2, b2);
+        w.advance();
       }
       kdone += run;
       jw += run;
