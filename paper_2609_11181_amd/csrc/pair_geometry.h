@@ -271,37 +271,41 @@ struct XStep {
   }
 };
 
-// Three-term form of the same walk: with c = cos d, both x and cos(a)
-// satisfy v(k + 1) = 2 c v(k) - v(k - 1), so sin^2(a/2) = (1 - cos a) / 2
-// follows h(k + 1) = 2 c h(k) - h(k - 1) + 2 hd: three FMAs per member for
-// the pair (x, h), holding members k and k + 1. A rounding error made at
+// Three-term form of the walk, carried on the tangent-plane components
+// themselves: with c = cos d, x and cos(a) satisfy v(k + 1) = 2 c v(k) -
+// v(k - 1), so sin^2(a/2) = (1 - cos a) / 2 follows h(k + 1) = 2 c h(k) -
+// h(k - 1) + 2 hd, and y = Y0 + Kz h follows y(k + 1) = 2 c y(k) - y(k - 1)
+// + 2 hd (2 Y0 + Kz) (using 1 - c = 2 hd): three operations per member for
+// the pair (x, y), holding members k and k + 1. A rounding error made at
 // step j reaches step k multiplied by sin((k - j) d) / sin d <= k - j, so
-// the error after k members is of order k^2 ulp (below 1e-11 relative for
-// the few hundred members of a window).
-struct XWalk3 {
-  double c2, hd2, x0, x1, h0, h1;
-  // members k, k + 1 from member k's (x, h)
-  __device__ __forceinline__ void start(const XStep& st, double x, double h) {
+// the error after k members is of order k^2 ulp of x and y (below 1e-11
+// relative for the few hundred members of a window).
+struct XYWalk3 {
+  double c2, cy, x0, x1, y0, y1;
+  // members k, k + 1 from member k's x and sin^2(a/2)
+  __device__ __forceinline__ void start(const XStep& st, double x, double h, double Y0, double Kz) {
     c2 = 2.0 * st.cd;
-    hd2 = 2.0 * st.hd;
+    cy = (2.0 * st.hd) * fma(2.0, Y0, Kz);
+    double h1 = h;
     x0 = x1 = x;
-    h0 = h1 = h;
     st.advance(&x1, &h1);
+    y0 = fma(Kz, h, Y0);
+    y1 = fma(Kz, h1, Y0);
   }
-  // restart at an azimuth offset of exactly zero
-  __device__ __forceinline__ void restart(const XStep& st) {
+  // restart at an azimuth offset of exactly zero (then y = Y0)
+  __device__ __forceinline__ void restart(const XStep& st, double Y0, double Kz) {
     x0 = 0.0;
-    h0 = 0.0;
+    y0 = Y0;
     x1 = -st.xs1;
-    h1 = st.hd;
+    y1 = fma(Kz, st.hd, Y0);
   }
   __device__ __forceinline__ void advance() {
     const double x2 = fma(c2, x1, -x0);
-    const double h2 = fma(c2, h1, hd2) - h0;
+    const double y2 = fma(c2, y1, cy) - y0;
     x0 = x1;
     x1 = x2;
-    h0 = h1;
-    h1 = h2;
+    y0 = y1;
+    y1 = y2;
   }
 };
 

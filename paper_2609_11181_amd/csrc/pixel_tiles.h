@@ -108,10 +108,9 @@ __device__ __attribute__((noinline)) void general_sin_hav(double av, double* sa,
 // sum qc g1 - 2 sum qh g2, B gets sum qc g2 + 2 sum qh g1 with
 // qh = q x y / sin^2 theta; doubling is exact).
 template <bool TABLE, bool BIG>
-__device__ __forceinline__ void general_member(double xt, double h, double Y0, double Kz, float4 g, const double* tp,
+__device__ __forceinline__ void general_member(double xt, double yt, float4 g, const double* tp,
                                                const FilterPiece* tab, double t_sin, Acc64& tot, double& e2,
                                                double& b2) {
-  const double yt = fma(Kz, h, Y0);
   const double yy = yt * yt;
   const double S2 = fma(xt, xt, yy);
   const double S2c = fmax(S2, (double)kCoincidentS2);
@@ -134,9 +133,9 @@ __device__ __forceinline__ void general_member(double xt, double h, double Y0, d
 // One centre of a general tile (list entry o), walking its own disc windows
 // (any rings, any grid). Along a ring
 // window the azimuth offset drops by one ring step per member, so the
-// member's x = s_p sin(dphi) and sin^2(dphi / 2) follow from the two
-// previous members' by a three-term recurrence (XWalk3) instead of a series
-// per member. A window that wraps
+// member's tangent-plane components x = s_p sin(dphi) and y follow from the
+// two previous members' by a three-term recurrence (XYWalk3) instead of a
+// series per member. A window that wraps
 // past the ring's last pixel is walked as two contiguous runs.
 // GT: 1 = the plan's ring-pair tables are present, 0 = absent, 2 = test at
 // run time.
@@ -219,8 +218,8 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     const double av = (u0 - (double)jlo) * ((2.0 * kPi) * rnq);
     if (OOL) general_sin_hav(av, &sa, &h);
     else sin_hav(av, &sa, &h);
-    XWalk3 w;
-    w.start(step, sp * sa, h);
+    XYWalk3 w;
+    w.start(step, sp * sa, h, Y0, Kz);
     // the member at the centre itself (same colatitude, dphi = 0), if any,
     // from the exact integer offset pi m / (np nq): the walk restarts there
     // from exact zeros, so its shear term vanishes exactly
@@ -236,7 +235,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     while (kdone < cnt) {
       int run = min(cnt - kdone, nq - jw);
       if (kc > kdone && kc < kdone + run) run = kc - kdone;
-      if (kdone == kc) w.restart(step);
+      if (kdone == kc) w.restart(step, Y0, Kz);
       run_wn(a.wn, dring + jw, run, tot);
       const float4* p = a.map + dring + jw;
       int k = 0;
@@ -247,12 +246,12 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
         for (int u = 0; u < U; ++u) g[u] = p[k + u];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, g[u], tp, tab, s.t_sin, tot, e2, b2);
+          general_member<TABLE, BIG>(w.x0, w.y0, g[u], tp, tab, s.t_sin, tot, e2, b2);
           w.advance();
         }
       }
       for (; k < run; ++k) {
-        general_member<TABLE, BIG>(w.x0, w.h0, Y0, Kz, p[k], tp, tab, s.t_sin, tot, e2, b2);
+        general_member<TABLE, BIG>(w.x0, w.y0, p[k], tp, tab, s.t_sin, tot, e2, b2);
         w.advance();
       }
       kdone += run;
