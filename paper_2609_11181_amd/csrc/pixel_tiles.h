@@ -568,22 +568,36 @@ __device__ __forceinline__ void belt_tile_staged(const PixelArgs& a, const Scale
       belt_ring_lds(qc, qs, q2, cnt, sp, 4 * lane, A);
       // W and N_occ of each centre's window (prefix lookups, all in flight together)
       double2 lo[4], hi[4];
-      int run[4];
+      if (j0 + 3 + cnt <= n) {  // no window passes the ring's end: two base addresses
+        const double2* w0 = a.wn + dring + j0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int jc = j0 + c < n ? j0 + c : j0 + c - n;
-        run[c] = min(cnt, n - jc);
-        lo[c] = a.wn[dring + jc];
-        hi[c] = a.wn[dring + jc + run[c]];
-      }
+        for (int c = 0; c < 4; ++c) {
+          lo[c] = w0[c];
+          hi[c] = w0[c + cnt];
+        }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        A.sw[c] += hi[c].x - lo[c].x;
-        A.sn[c] += (int)(hi[c].y - lo[c].y);
-        if (run[c] < cnt) {
-          const double2 lo2 = a.wn[dring], hi2 = a.wn[dring + cnt - run[c]];
-          A.sw[c] += hi2.x - lo2.x;
-          A.sn[c] += (int)(hi2.y - lo2.y);
+        for (int c = 0; c < 4; ++c) {
+          A.sw[c] += hi[c].x - lo[c].x;
+          A.sn[c] += (int)(hi[c].y - lo[c].y);
+        }
+      } else {
+        int run[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int jc = j0 + c < n ? j0 + c : j0 + c - n;
+          run[c] = min(cnt, n - jc);
+          lo[c] = a.wn[dring + jc];
+          hi[c] = a.wn[dring + jc + run[c]];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          A.sw[c] += hi[c].x - lo[c].x;
+          A.sn[c] += (int)(hi[c].y - lo[c].y);
+          if (run[c] < cnt) {
+            const double2 lo2 = a.wn[dring], hi2 = a.wn[dring + cnt - run[c]];
+            A.sw[c] += hi2.x - lo2.x;
+            A.sn[c] += (int)(hi2.y - lo2.y);
+          }
         }
       }
     }
