@@ -108,6 +108,10 @@ enum { SMART_CH_ME = 0, SMART_CH_MB = 1, SMART_CH_SIGMA = 2, SMART_CH_W = 3, SMA
 
 /* Bind a context to HIP device `hip_device`. */
 int smart_init(int hip_device, smart_ctx* out);
+/* Release the context: its filters, the per-aperture filter tables of the
+ * general pixel walk, and (after synchronising the device) the device blocks
+ * that freed maps and plans left in the library's cache for this device.
+ * Free the context's maps and plans first. */
 void smart_finalize(smart_ctx ctx);
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -178,6 +182,11 @@ int smart_data_sources(smart_data data, int64_t* n_src, int64_t* d_src_pix, void
  * Asynchronous on `stream`. */
 int smart_data_export(smart_data data, int64_t* d_order, int64_t* d_offsets, float* d_sums, void* stream);
 
+/* Release a map. Synchronises the device (no queued work may still use it,
+ * on any stream), then keeps its device blocks in the library's per-device
+ * cache, which hands them to the next maps and plans of the same sizes (a
+ * batch loop that frees each batch's handles maps no new device memory); the
+ * cache holds at most a quarter of the device memory. */
 void smart_data_free(smart_data data);
 
 /* ------------------------------------------------------------------------ */
@@ -202,7 +211,9 @@ void smart_data_free(smart_data data);
  * other tiles are general. This costs one more synchronisation per scale
  * and device memory of about (number of belt rings) x (pixels per disc) x
  * 20 bytes per scale; the tables are filled asynchronously on `stream`, so
- * the plan is used on `stream` (or after synchronising it). */
+ * the plan is used on `stream` (or after synchronising it). Table filters
+ * also get a 48 KB table in sin(theta) per (filter, aperture), built on the
+ * host at its first use and kept by the context. */
 int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out, int64_t n_out,
                       const int64_t* d_out_pix, int n_scales, const double* h_theta_ap, const int* h_filter_ids,
                       int precision, void* stream, smart_plan* out);
@@ -217,6 +228,8 @@ int smart_run(smart_plan plan, int norm, void* d_out, void* stream);
  * variant counts occupied pixels). Synchronises `stream`. */
 int smart_last_pairs(smart_plan plan, void* stream, double* pairs);
 
+/* Release a plan: the same synchronisation and reuse of its device blocks as
+ * smart_data_free. */
 void smart_plan_free(smart_plan plan);
 
 /* Schedule of scale `scale` of a pixel-variant FP32 plan. Belt items are
