@@ -229,6 +229,7 @@ void smart_plan_free(smart_plan p) {
   smart::dev_release(p->d_pairs);
   smart::dev_release(p->d_work);
   smart::dev_release(p->rot_map);
+  smart::dev_release(p->runs_block);
   for (smart::PixelSched* sc : p->sched) delete sc;
   for (hipEvent_t e : p->events) hipEventDestroy(e);
   delete p;

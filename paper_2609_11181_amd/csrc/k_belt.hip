@@ -42,11 +42,9 @@ __device__ inline void belt_span(const PixelArgs& a, double theta_ap, int rp, in
 // General-walk tables. gt_head[rp] for every centre ring: (entries of the
 // ring pairs, first source ring, last source ring), the same source rings
 // as the per-centre walk (ring span of the disc, clipped to the map's rings).
-// Also clears the per-belt-ring flags `used` (nb entries) and the widest-window
-// cell that k_classify and k_belt_size fill next.
-__global__ void k_gen_span(PixelArgs a, double theta_ap, int4* head, int* cnt, int* used, int nb, int* widest) {
+// Also clears the widest-window cell that k_belt_size fills next.
+__global__ void k_gen_span(PixelArgs a, double theta_ap, int4* head, int* cnt, int* widest) {
   const int rp = blockIdx.x * blockDim.x + threadIdx.x;
-  if (rp < nb) used[rp] = 0;
   if (rp == 0) *widest = 0;
   if (rp >= 4 * a.nside_out) return;
   int lo = 0, hi = -1;
@@ -298,6 +296,28 @@ PixelSched::~PixelSched() {
 // general-walk ring-pair entries kept at most (32 B each)
 constexpr int64_t kGenPairMax = int64_t(1) << 25;
 
+// Layout of a plan's run-structure block for nt tiles and nb belt rings
+// (byte offsets, 256-byte aligned), and its TileRuns view.
+static size_t tile_runs_layout(int nt, int nb, size_t off[5]) {
+  size_t o = 0;
+  const size_t bytes[5] = {sizeof(int) * (size_t)nt, sizeof(int) * (size_t)kRuns * nt,
+                           sizeof(int2) * (size_t)kRuns * nt, sizeof(uint64_t) * (size_t)kRuns * nt,
+                           sizeof(int) * (size_t)nb};
+  for (int i = 0; i < 5; ++i) {
+    off[i] = o;
+    o += (bytes[i] + 255) & ~(size_t)255;
+  }
+  return o;
+}
+
+static TileRuns tile_runs_view(void* block, int nt, int nb) {
+  size_t off[5];
+  tile_runs_layout(nt, nb, off);
+  char* b = (char*)block;
+  return TileRuns{(int*)(b + off[0]), (int*)(b + off[1]), (int2*)(b + off[2]), (uint64_t*)(b + off[3]),
+                  (int*)(b + off[4])};
+}
+
 int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   if (p->n_out == 0) return SMART_OK;  // nothing to schedule
   smart_data d = p->data;
@@ -320,7 +340,7 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   int2* offs = nullptr;
   uint64_t* keys = nullptr;  // keys, sorted keys of the kRuns item slots per tile
   int* ids = nullptr;        // slot ids, sorted slot ids
-  int2* items = nullptr;     // item slots
+  int* ringok = nullptr;     // per belt ring: qualifies for this aperture
   int* gflags = nullptr;     // per tile: 1 when general
   int* gcnt = nullptr;       // per centre ring: source rings of the general walk, then their offsets
   const int nb = 2 * N + 1;  // belt rings N .. 3N
@@ -334,6 +354,16 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   BCHK(dev_alloc(&sc->cursors, sizeof(int) * (2 * kQueueInts + 3)));
   BCHK(dev_alloc(&sc->general, sizeof(int) * (nt + 1)));
   BCHK(dev_alloc(&sc->head, sizeof(int2) * nb));
+  // the tiles' run structure: built with the first scale, shared by all
+  if (!p->runs_block) {
+    size_t off[5];
+    BCHK(dev_alloc(&p->runs_block, tile_runs_layout(nt, nb, off)));
+    const TileRuns R0 = tile_runs_view(p->runs_block, nt, nb);
+    BCHK(hipMemsetAsync(R0.has_start, 0, sizeof(int) * nb, st));
+    launch_tile_runs(a, nt, R0, st);
+    BCHK(hipGetLastError());
+  }
+  const TileRuns R = tile_runs_view(p->runs_block, nt, nb);
   {
     size_t off = 0;
     auto carve = [&](size_t bytes) {
@@ -343,7 +373,7 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
     };
     const size_t o_flags = carve(sizeof(int) * (nt + 1)), o_gflags = carve(sizeof(int) * (nt + 1));
     const size_t o_keys = carve(sizeof(uint64_t) * 2 * (ns + 1)), o_ids = carve(sizeof(int) * 2 * (ns + 1));
-    const size_t o_items = carve(sizeof(int2) * (ns + 1)), o_used = carve(sizeof(int) * nb);
+    const size_t o_ringok = carve(sizeof(int) * nb), o_used = carve(sizeof(int) * nb);
     const size_t o_cnts = carve(sizeof(int2) * nb), o_offs = carve(sizeof(int2) * nb);
     const size_t o_gcnt = carve(sizeof(int) * 2 * nr4);
     BCHK(scratch_alloc(&scratch, off, st));
@@ -351,7 +381,7 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
     gflags = (int*)(scratch + o_gflags);
     keys = (uint64_t*)(scratch + o_keys);
     ids = (int*)(scratch + o_ids);
-    items = (int2*)(scratch + o_items);
+    ringok = (int*)(scratch + o_ringok);
     used = (int*)(scratch + o_used);
     cnts = (int2*)(scratch + o_cnts);
     offs = (int2*)(scratch + o_offs);
@@ -360,13 +390,13 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   BCHK(dev_alloc(&sc->gt_head, sizeof(int4) * nr4));
   BCHK(dev_alloc(&sc->gt_ring, sizeof(GenRingC) * nr4));
   hipLaunchKernelGGL(k_gen_span, dim3((nr4 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, s.theta_ap, sc->gt_head,
-                     gcnt, used, nb, sc->cursors + 2 * kQueueInts + 2);
+                     gcnt, sc->cursors + 2 * kQueueInts + 2);
   hipLaunchKernelGGL(k_gen_rings, dim3((nr4 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, N, sc->gt_ring);
   BCHK(hipGetLastError());
   // order of the schedule: belt items column-major (items of one azimuth
   // column on consecutive rings share their disc rows, so the items in flight
   // on one XCD stay within its L2); general tiles in list order
-  launch_classify(a, s.theta_ap, nt, flags, items, keys, used, st);
+  launch_classify_scale(a, s.theta_ap, nt, R, nb, ringok, used, flags, keys, st);
   BCHK(hipGetLastError());
   hipLaunchKernelGGL(k_iota, dim3((ns + kBlock - 1) / kBlock), dim3(kBlock), 0, st, ids, ns);
   hipLaunchKernelGGL(k_is_zero, dim3((nt + kBlock - 1) / kBlock), dim3(kBlock), 0, st, flags, gflags, nt);
@@ -425,7 +455,7 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   }
   BCHK(dev_alloc(&sc->belt, sizeof(int2) * (counts[0] + 1)));
   if (counts[0] > 0)
-    hipLaunchKernelGGL(k_gather_items, dim3((counts[0] + kBlock - 1) / kBlock), dim3(kBlock), 0, st, items,
+    hipLaunchKernelGGL(k_gather_items, dim3((counts[0] + kBlock - 1) / kBlock), dim3(kBlock), 0, st, R.items,
                        ids + ns, counts[0], sc->belt);
   BCHK(hipGetLastError());
   // out-of-line per-ring set-up pays off for discs of many members per ring

@@ -45,24 +45,24 @@ __device__ inline bool belt_ring_ok(const PixelArgs& a, double theta_ap, int rp)
   return lo >= a.nside_in && hi <= 3 * a.nside_in && hi - lo + 1 <= kRingCap;
 }
 
-// One wave per tile. The tile's list entries are cut into runs of
-// consecutive pixels of one ring; when there are at most kRuns runs and each
-// lies on a qualifying belt ring, the tile becomes kRuns belt items (list
-// position, length) with their schedule keys (column-major: azimuth column
-// of 256 pixels, then ring), else it is a general tile. Every qualifying
-// belt ring that holds an output gets a table (the batched noise path also
-// uses the tables of rings without belt items): every entry lies in a run,
-// and the ring of each run is checked at the run's first entry.
-__global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_ap, int n_tiles, int* nrun,
-                                                     int2* items, uint64_t* keys, int* used) {
+// Run structure of the tiles, independent of the aperture (one wave per
+// tile, once per plan). A tile's list entries are cut into runs of
+// consecutive pixels of one ring (a run starts at the tile's first entry,
+// after a gap in the pixel numbers and at a ring's first pixel). For a tile
+// of at most kRuns runs: each run's ring, item (list position, length) and
+// schedule key (column-major: azimuth column of 256 pixels, then ring).
+// Every belt ring holding a run start is marked in has_start: each such
+// ring that qualifies for an aperture gets a table (the batched noise path
+// also uses the tables of rings without belt items).
+__global__ __launch_bounds__(kBlock) void k_tile_runs(PixelArgs a, int n_tiles, TileRuns R) {
   const int t = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= n_tiles) return;
   const int64_t o0 = (int64_t)t * kBlock;
   const int64_t oe = min(o0 + kBlock, a.n_out);
+  const int N = a.nside_in;
   const bool same_grid = a.nside_in == a.nside_out;
   uint64_t starts[kBlock / 64];
-  bool bad = false;  // a run start on a ring that does not qualify
 #pragma unroll
   for (int k = 0; k < kBlock / 64; ++k) {
     const int64_t pos = o0 + lane + 64 * k;
@@ -72,42 +72,69 @@ __global__ __launch_bounds__(kBlock) void k_classify(PixelArgs a, double theta_a
       int rl, il;
       pixel_ring(a.nside_out, p, &rl, &il);
       st = pos == o0 || a.out_pix[pos - 1] + 1 != p || il == 0;
-      if (st) {
-        if (same_grid && belt_ring_ok(a, theta_ap, rl)) used[rl - a.nside_in] = 1;
-        else bad = true;
-      }
+      if (st && same_grid && rl >= N && rl <= 3 * N) R.has_start[rl - N] = 1;
     }
     starts[k] = __ballot(st);
   }
-  const bool any_bad = __any(bad);
   int n = 0;
 #pragma unroll
   for (int k = 0; k < kBlock / 64; ++k) n += __popcll(starts[k]);
-  const int runs = (!any_bad && n <= kRuns) ? n : 0;
   if (lane == 0) {
-    nrun[t] = runs;
-    int r = 0;
-    int64_t prev = -1;
-    for (int k = 0; k < kBlock / 64; ++k) {
-      uint64_t m = starts[k];
-      while (m) {
-        const int bit = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        const int64_t pos = o0 + 64 * k + bit;
-        if (r < kRuns && runs > 0) {
-          if (prev >= 0) items[t * kRuns + r - 1].y = (int)(pos - prev);
+    R.nruns[t] = min(n, kRuns + 1);
+    if (n <= kRuns) {
+      int r = 0;
+      int64_t prev = -1;
+      for (int k = 0; k < kBlock / 64; ++k) {
+        uint64_t m = starts[k];
+        while (m) {
+          const int bit = __ffsll((unsigned long long)m) - 1;
+          m &= m - 1;
+          const int64_t pos = o0 + 64 * k + bit;
+          if (prev >= 0) R.items[t * kRuns + r - 1].y = (int)(pos - prev);
           int rp, ip;
           pixel_ring(a.nside_out, a.out_pix[pos], &rp, &ip);
-          items[t * kRuns + r] = make_int2((int)pos, 0);
-          keys[t * kRuns + r] = ((uint64_t)(ip / kBlock) << kKeyRingBits) | (uint64_t)rp;
+          R.ring[t * kRuns + r] = rp;
+          R.items[t * kRuns + r] = make_int2((int)pos, 0);
+          R.keys[t * kRuns + r] = ((uint64_t)(ip / kBlock) << kKeyRingBits) | (uint64_t)rp;
+          prev = pos;
+          ++r;
         }
-        prev = pos;
-        ++r;
       }
+      R.items[t * kRuns + n - 1].y = (int)(oe - prev);
     }
-    if (runs > 0) items[t * kRuns + runs - 1].y = (int)(oe - prev);
-    for (int q = runs; q < kRuns; ++q) keys[t * kRuns + q] = 1ull << (kKeyBits - 1);
   }
+}
+
+// Belt rings of one aperture: ringok[i] = ring N + i qualifies, used[i] =
+// it qualifies and holds a run start (it gets a table).
+__global__ void k_ring_ok(PixelArgs a, double theta_ap, const int* has_start, int nb, int* ringok, int* used) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const bool ok = belt_ring_ok(a, theta_ap, a.nside_in + i);
+  ringok[i] = ok ? 1 : 0;
+  used[i] = ok && has_start[i] ? 1 : 0;
+}
+
+// Classification of the tiles for one aperture (one thread per tile): a
+// tile of at most kRuns runs that all lie on qualifying belt rings becomes
+// its runs' belt items (nrun[t] of them, with their keys), any other tile is
+// a general tile (nrun[t] = 0, unused key slots sort last).
+__global__ void k_classify_scale(PixelArgs a, int n_tiles, TileRuns R, const int* ringok, int* nrun,
+                                 uint64_t* keys) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int N = a.nside_in;
+  const int n = R.nruns[t];
+  bool ok = n <= kRuns;
+  for (int q = 0; q < kRuns; ++q) {
+    if (ok && q < n) {
+      const int rl = R.ring[t * kRuns + q];
+      ok = rl >= N && rl <= 3 * N && ringok[rl - N] != 0;
+    }
+  }
+  const int runs = ok ? n : 0;
+  nrun[t] = runs;
+  for (int q = 0; q < kRuns; ++q) keys[t * kRuns + q] = q < runs ? R.keys[t * kRuns + q] : 1ull << (kKeyBits - 1);
 }
 
 // ---- pixel variant, mixed precision: general kernel -------------------------------
@@ -482,11 +509,18 @@ hipError_t launch_pixel_sched(const PixelArgs& a0, const ScaleArgs& s, const Pix
   return e;
 }
 
-void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* nrun, int2* items, uint64_t* keys,
-                     int* used, hipStream_t st) {
+void launch_tile_runs(const PixelArgs& a, int n_tiles, const TileRuns& R, hipStream_t st) {
   const unsigned blocks = (unsigned)((n_tiles + kBlock / 64 - 1) / (kBlock / 64));
+  if (n_tiles > 0) hipLaunchKernelGGL(k_tile_runs, dim3(blocks), dim3(kBlock), 0, st, a, n_tiles, R);
+}
+
+void launch_classify_scale(const PixelArgs& a, double theta_ap, int n_tiles, const TileRuns& R, int nb, int* ringok,
+                           int* used, int* nrun, uint64_t* keys, hipStream_t st) {
+  hipLaunchKernelGGL(k_ring_ok, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, theta_ap, R.has_start, nb,
+                     ringok, used);
   if (n_tiles > 0)
-    hipLaunchKernelGGL(k_classify, dim3(blocks), dim3(kBlock), 0, st, a, theta_ap, n_tiles, nrun, items, keys, used);
+    hipLaunchKernelGGL(k_classify_scale, dim3((n_tiles + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a, n_tiles, R,
+                       ringok, nrun, keys);
 }
 
 size_t pixel_work_ints(int64_t n_out) {

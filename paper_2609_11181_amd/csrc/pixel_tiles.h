@@ -215,7 +215,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     // azimuth offset of the first member: 2 pi (u0 - jlo) / nq (u0 to an
     // ulp, about 1e-15 rad here, far below any pixel separation)
     double sa, h;
-    const double av = (u0 - (double)jlo) * ((2.0 * kPi) * rnq);
+    const double av = (u0 - (double)(int)jlo) * ((2.0 * kPi) * rnq);  // jlo in [-nq, 2 nq]
     if (OOL) general_sin_hav(av, &sa, &h);
     else sin_hav(av, &sa, &h);
     XYWalk3 w;

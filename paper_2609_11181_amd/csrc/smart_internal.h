@@ -130,6 +130,9 @@ struct smart_plan_s {
   // kernel timing: 4 events per scale (belt start/stop, general start/stop)
   bool timing = false, timed_run = false;
   std::vector<hipEvent_t> events;
+  // device block of the tiles' run structure (pixel FP32 plans, shared by
+  // the scales' schedules)
+  void* runs_block = nullptr;
   // scratch for the noise batch (rotated map), grown on demand
   float4* rot_map = nullptr;
   int64_t rot_len = 0;
@@ -262,9 +265,10 @@ struct PixelSched {
 // d_work: device scratch of pixel_work_ints(n_out) ints (queue cursors).
 hipError_t launch_pixel(const PixelArgs& a, const ScaleArgs& s, int precision, hipStream_t st, int* d_work);
 size_t pixel_work_ints(int64_t n_out);
-// Runs of every tile of 256 list entries (k_classify): nrun[t] belt items
-// (0: general tile) in items[kRuns t ..] with their sort keys, and
-// used[rp - nside] = 1 for every belt ring that gets a table.
+// Runs of the tiles of 256 list entries: the aperture-independent run
+// structure once per plan (k_tile_runs), then per aperture the belt rings
+// that qualify (used[rp - nside] = 1 for every one that gets a table) and
+// the classification: nrun[t] belt items (0: general tile), their sort keys.
 constexpr int kRuns = 4;
 // Sort key of an item slot: (azimuth column ip / 256, ring), unused slots
 // last (top bit). The radix sort is stable and the slots enter in list
@@ -272,8 +276,16 @@ constexpr int kRuns = 4;
 constexpr int kKeyRingBits = 15;  // ring < 4 nside <= 2^15
 constexpr int kKeyBits = kKeyRingBits + 7 + 1;
 static_assert(4 * kMaxNside <= (1 << kKeyRingBits) && 4 * kMaxNside / kBlock <= (1 << 7), "item key fields");
-void launch_classify(const PixelArgs& a, double theta_ap, int n_tiles, int* nrun, int2* items, uint64_t* keys,
-                     int* used, hipStream_t st);
+struct TileRuns {
+  int* nruns;      // [n_tiles] runs per tile (kRuns + 1: more)
+  int* ring;       // [kRuns n_tiles] ring of each run (tiles of at most kRuns runs)
+  int2* items;     // [kRuns n_tiles] (list position, length) of each run
+  uint64_t* keys;  // [kRuns n_tiles] schedule key of each run
+  int* has_start;  // [2 nside + 1] belt ring nside + i holds a run start
+};
+void launch_tile_runs(const PixelArgs& a, int n_tiles, const TileRuns& R, hipStream_t st);
+void launch_classify_scale(const PixelArgs& a, double theta_ap, int n_tiles, const TileRuns& R, int nb, int* ringok,
+                           int* used, int* nrun, uint64_t* keys, hipStream_t st);
 // Scheduled path: belt tiles through the tables, general tiles as above.
 // ev: NULL, or 4 events recorded around the belt and the general kernel;
 // kinds: bit 0 runs the belt kernel, bit 1 the general kernel.
