@@ -18,9 +18,9 @@
 // operand split into two BF16 words (hi + lo) and three products per step
 // (hi.hi + hi.lo + lo.hi), accumulated in FP32: about 2^-16 relative per term.
 //
-// A block owns a stack of four segments (the same 32-pixel column of four
-// consecutive belt rings, one per wave) and 32 realisations. The realisations
-// of a source ring's slab are generated once per block into LDS and used by
+// A block owns a stack of kStack = 8 segments (the same 32-pixel column of
+// eight consecutive belt rings, one per wave) and 32 realisations. The
+// realisations of a source ring's slab are generated once per block into LDS and used by
 // every wave whose disc reaches that ring, so each (pixel, realisation) value
 // is generated once per stack and disc ring instead of once per segment.
 //
@@ -47,7 +47,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kNP = 32;     // centres per segment (MFMA rows)
 constexpr int kNR = 32;     // realisations per block (E and B: two 32-column MFMA halves)
-constexpr int kStack = 4;   // segments per block, one per wave
+constexpr int kStack = 8;   // segments per block, one per wave
 constexpr int kCntMax = 96;                    // members per disc ring of an eligible segment
 
 __global__ void k_rotate(const float4* map, const int* cidx, const float* u, int64_t n, float4* out) {
@@ -166,7 +166,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Dynamic LDS of one stack block for windows of at most cnt_max members:
 // the slab, [slot][2 kNR] split words with the E form (X1, X2) of
 // realisation r at 2 r and its B form (X2, -X1) at 2 r + 1 (also the
-// epilogue's staging of the four waves' [2 kNR][kNP] outputs), then each
+// epilogue's staging of the waves' [2 kNR][kNP] outputs), then each
 // wave's coefficient band, zero-padded by kPadL entries before and kPadR
 // after, so that the operand loads need no range tests.
 constexpr int kPadL = 32, kPadR = 48;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
   const int hfirst = active ? n.t.head[iw].x : 0, hnr = active ? n.t.head[iw].y : 0;
   const int lo_w = active ? n.t.info[hfirst].x : 0x7fffffff;
   uint2* myband = coefP + wave * band;
-  // union of the four discs' rings
+  // union of the stack's discs' rings
   __shared__ int s_lo[kStack], s_hi[kStack];
   if (lane == 0) {
     s_lo[wave] = active ? lo_w : 0x7fffffff;
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
       __syncthreads();
       continue;
     }
-    // every window holds at most 32 + cnt_max - 1 pixels and the four windows
+    // every window holds at most 32 + cnt_max - 1 pixels and the stack's windows
     // are centred within half a pixel of each other, so the union fits
     const int Lu = min(ue - us, slab_max);
     // realisations of the union slab: wave w generates realisations w, w + 4, ...
