@@ -40,7 +40,7 @@ ALU_PEAK = 256 * 64 * 2.4e9
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0)
 # counter runs of the default workload (the committed counter summary of the pixel kernels); valid
 # for that kernel version and workload only
-TRAFFIC_BYTES = {"k_pixel_f32 (20 arcmin)": 1.644e10}
+TRAFFIC_BYTES = {"k_pixel_f32 (20 arcmin)": 1.627e10}
 
 
 def parse():
