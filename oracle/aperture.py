@@ -36,6 +36,16 @@ with A the aperture area: the spherical cap 2 pi (1 - cos theta_ap) for the
 galaxy variant; N_occ * Omega_pix (occupied pixels in the aperture times the
 pixel area) for the pixel variant. W = 0 gives M = sigma = 0.
 
+Averaged normalisation (Sect. 2.4, the "averaged approach"): each galaxy
+is normalised by the effective density of its own pixel, W_j / Omega_pix,
+instead of the aperture's mean density. Summing the galaxies of pixel j
+gives the pixel the weight c_j = Omega_pix / W_j on its shear sum, so
+  M_E = (1 / theta_ap^2) sum_j q_j c_j G+_j,   M_B likewise with Gx,
+  sigma = (1 / theta_ap^2) sqrt(sum_j q_j^2 c_j^2 E2_j / 2)
+(Eq. map_noise with per-galaxy weights c_j / theta_ap^2); empty pixels add
+nothing; W and N are the summed maps' channels. Pixel variant only, with
+Omega_pix the area of a source pixel.
+
 Membership is decided in FP64 on the squared chord against
 C_ap = 4 sin^2(theta_ap/2). Pairs within TIE_REL * C_ap of the boundary are
 reported as ties: the decision there depends on last-bit rounding, so
@@ -46,7 +56,10 @@ built on tangent-plane vectors rather than the polar-angle formula; the
 closed-form aperture mass of a singular isothermal sphere integrated by
 quadrature; B-mode nulling for a purely tangential field; E<->B duality;
 linearity; invariance under the HEALPix symmetries; pixel variant equal to
-the galaxy variant on a catalogue of pixel centres.
+the galaxy variant on a catalogue of pixel centres; averaged maps equal to
+the galaxy variant with per-galaxy weights Omega_pix / (galaxies in the
+pixel), to the summed pixel-count maps when every occupied pixel holds one
+galaxy, and unchanged when every galaxy of a pixel is repeated.
 """
 from __future__ import annotations
 
@@ -69,6 +82,7 @@ COINCIDENT_C2 = 1e-20
 NORM_SUMMED_CAP = 0
 NORM_SUMMED_PIXCOUNT = 1
 NORM_RAW = 2
+NORM_AVERAGED = 3
 
 
 def radec2vec(ra, dec):
@@ -283,13 +297,35 @@ def aperture_mass_galaxy(cat, c_ra, c_dec, theta_ap, filter_kind, norm=NORM_SUMM
     return out
 
 
+def averaged_sources(nside, W, G1, G2, E2):
+    """The pixel sums of the averaged approach (Sect. 2.4): pixel j's galaxies
+    are each divided by the pixel's effective density W_j / Omega_pix, so its
+    shear sum takes the factor c_j = Omega_pix / W_j and its sum of squared
+    shears (the variance term) c_j^2; c_j = 0 for an empty pixel. Returns
+    (G1 c, G2 c, E2 c^2)."""
+    omega_pix = 4.0 * math.pi / hp.npix(nside)
+    W = np.asarray(W, np.float64)
+    c = np.where(W > 0, omega_pix / np.where(W > 0, W, 1.0), 0.0)
+    return (c * np.asarray(G1, np.float64), c * np.asarray(G2, np.float64),
+            c * c * np.asarray(E2, np.float64))
+
+
 def aperture_mass_pixel(pmap, out_pix, theta_ap, filter_kind, norm=NORM_SUMMED_PIXCOUNT, filter_params=None,
                         candidates="rings"):
-    """Pixel-based variant (Sect. 3.2, label sphS_pix)."""
+    """Pixel-based variant (Sect. 3.2, label sphS_pix); summed (Sect. 3.1
+    step 5) or averaged (Sect. 2.4) normalisation."""
     nside = pmap["nside"]
-    s = sums_pixel(nside, pmap["pix"], pmap["W"], pmap["G1"], pmap["G2"], pmap["E2"], out_pix, theta_ap,
+    G1, G2, E2 = pmap["G1"], pmap["G2"], pmap["E2"]
+    if norm == NORM_AVERAGED:
+        G1, G2, E2 = averaged_sources(nside, pmap["W"], G1, G2, E2)
+    s = sums_pixel(nside, pmap["pix"], pmap["W"], G1, G2, E2, out_pix, theta_ap,
                    q_of(filter_kind, filter_params), candidates=candidates)
-    out = normalise(s, theta_ap, norm, omega_pix=4.0 * math.pi / hp.npix(nside))
+    if norm == NORM_AVERAGED:
+        # the sums already carry Omega_pix / W_j: only Q = q / theta_ap^2 is left
+        out = {"M_E": s["S_E"] / theta_ap ** 2, "M_B": s["S_B"] / theta_ap ** 2,
+               "sigma": np.sqrt(0.5 * s["V"]) / theta_ap ** 2, "W": s["W"], "N": s["N"]}
+    else:
+        out = normalise(s, theta_ap, norm, omega_pix=4.0 * math.pi / hp.npix(nside))
     out["tie"] = s["tie"]
     out["pairs"] = s["pairs"]
     return out

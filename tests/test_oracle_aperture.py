@@ -325,6 +325,94 @@ def test_pixel_equals_galaxy_on_centres():
         assert np.max(np.abs(p[k] - g[k])) < 1e-12 * sc, k
 
 
+# ----------------------------------------------------------------------------
+# Averaged normalisation (Sect. 2.4): three routes that do not use the
+# pixel-level weighting of the oracle
+# ----------------------------------------------------------------------------
+
+def test_averaged_equals_galaxy_variant_with_pixel_density_weights():
+    """Galaxy by galaxy, the averaged approach divides each galaxy's filtered
+    shear by the effective density of its pixel, n_j = (galaxies in pixel j) /
+    Omega_pix: a galaxy-variant sum with weights w_i = Omega_pix / n_gal(j)
+    over galaxies placed at their pixel centres, divided by theta_ap^2.
+    A wrong power of the weight in the variance or a weight taken from the
+    wrong pixel fails here."""
+    nside = 32
+    rng = np.random.default_rng(21)
+    pix = np.arange(hp.npix(nside))
+    ngal = rng.poisson(2.0, pix.size)          # about 13% of the pixels are empty
+    gpix = np.repeat(pix, ngal)
+    g1 = rng.normal(0, 0.3, gpix.size) + 0.05
+    g2 = rng.normal(0, 0.3, gpix.size)
+    omega = 4 * math.pi / hp.npix(nside)
+    ra, dec = hp.pix2radec(nside, gpix)
+    cat = {"ra": ra, "dec": dec, "g1": g1, "g2": g2, "w": omega / ngal[gpix]}
+    m = {"nside": nside, "pix": pix, "W": ngal.astype(np.float64),
+         "G1": np.bincount(gpix, g1, pix.size), "G2": np.bincount(gpix, g2, pix.size),
+         "E2": np.bincount(gpix, g1 * g1 + g2 * g2, pix.size)}
+    out = np.concatenate([np.arange(0, 20), rng.choice(hp.npix(nside), 150, replace=False)])
+    cra, cdec = hp.pix2radec(nside, out)
+    for th, kind in [(5 * DEG, F.TANH), (12 * DEG, F.POLY)]:
+        a = A.aperture_mass_pixel(m, out, th, kind, norm=A.NORM_AVERAGED)
+        g = A.aperture_mass_galaxy(cat, cra, cdec, th, kind, norm=A.NORM_RAW)
+        ok = ~(a["tie"] | g["tie"])
+        assert ok.sum() > 100
+        ref = {"M_E": g["M_E"] / th ** 2, "M_B": g["M_B"] / th ** 2,
+               "sigma": np.sqrt(0.5 * g["sigma"]) / th ** 2}   # RAW: the sigma channel is V
+        for k in ("M_E", "M_B", "sigma"):
+            sc = np.abs(ref[k][ok]).max()
+            assert np.max(np.abs(a[k][ok] - ref[k][ok])) < 1e-12 * sc, k
+        assert np.array_equal(a["W"], A.aperture_mass_pixel(m, out, th, kind)["W"])
+
+
+def test_averaged_equals_summed_with_one_galaxy_per_pixel():
+    """With one galaxy in every occupied pixel the density of each pixel,
+    1 / Omega_pix, is also the aperture's mean density N / (N Omega_pix), so
+    the averaged maps equal the summed pixel-count maps."""
+    nside = 64
+    rng = np.random.default_rng(22)
+    pix = np.arange(hp.npix(nside))
+    W = (rng.uniform(size=pix.size) < 0.7).astype(np.float64)
+    G1 = W * rng.normal(0, 0.3, pix.size)
+    G2 = W * rng.normal(0, 0.3, pix.size)
+    m = {"nside": nside, "pix": pix, "W": W, "G1": G1, "G2": G2, "E2": G1 * G1 + G2 * G2}
+    out = rng.choice(hp.npix(nside), 200, replace=False)
+    th = 4 * DEG
+    a = A.aperture_mass_pixel(m, out, th, F.TANH, norm=A.NORM_AVERAGED)
+    b = A.aperture_mass_pixel(m, out, th, F.TANH, norm=A.NORM_SUMMED_PIXCOUNT)
+    ok = ~a["tie"]
+    for k in ("M_E", "M_B", "sigma", "W", "N"):
+        sc = np.abs(b[k][ok]).max()
+        assert np.max(np.abs(a[k][ok] - b[k][ok])) < 1e-12 * sc, k
+
+
+def test_averaged_unchanged_when_galaxies_repeat():
+    """Repeating every galaxy of pixel j k_j times multiplies the pixel's G, W
+    and E2 by k_j: its mean shear, and so the averaged M_E and M_B, stay as
+    they are (the summed maps move), while the variance term of the pixel
+    scales by 1 / k_j."""
+    nside = 32
+    m = _rand_pixmap(nside, 23)
+    rng = np.random.default_rng(24)
+    k = rng.integers(1, 5, m["pix"].size).astype(np.float64)
+    m2 = dict(m, W=m["W"] * k, G1=m["G1"] * k, G2=m["G2"] * k, E2=m["E2"] * k)
+    out = rng.choice(hp.npix(nside), 150, replace=False)
+    th = 8 * DEG
+    a = A.aperture_mass_pixel(m, out, th, F.TANH, norm=A.NORM_AVERAGED)
+    b = A.aperture_mass_pixel(m2, out, th, F.TANH, norm=A.NORM_AVERAGED)
+    ok = ~a["tie"]
+    for key in ("M_E", "M_B"):
+        sc = np.abs(a[key][ok]).max()
+        assert np.max(np.abs(a[key][ok] - b[key][ok])) < 1e-12 * sc, key
+    s1 = A.aperture_mass_pixel(m, out, th, F.TANH)
+    s2 = A.aperture_mass_pixel(m2, out, th, F.TANH)
+    assert np.max(np.abs(s1["M_E"][ok] - s2["M_E"][ok])) > 1e-3 * np.abs(s1["M_E"][ok]).max()
+    # uniform repetition: sigma scales by 1 / sqrt(k)
+    m3 = dict(m, W=m["W"] * 4, G1=m["G1"] * 4, G2=m["G2"] * 4, E2=m["E2"] * 4)
+    c = A.aperture_mass_pixel(m3, out, th, F.TANH, norm=A.NORM_AVERAGED)
+    assert np.max(np.abs(c["sigma"][ok] - 0.5 * a["sigma"][ok])) < 1e-12 * np.abs(a["sigma"][ok]).max()
+
+
 @pytest.mark.parametrize("nside,th", [(32, 6 * DEG), (64, 30 * DEG), (8, 50 * DEG)])
 def test_ring_candidates_match_kdtree(nside, th):
     m = _rand_pixmap(nside, 1)
