@@ -25,6 +25,16 @@
  * A_ap = 2 pi (1 - cos theta_ap) (SMART_NORM_SUMMED_CAP) or N * Omega_pix
  * (SMART_NORM_SUMMED_PIXCOUNT); W = 0 yields zeros.
  *
+ * The averaged approach (SMART_NORM_AVERAGED, Sect. 2.4 "summed vs
+ * averaged") normalises each source pixel j by its own effective density
+ * W_j / Omega_pix instead of the aperture's mean density:
+ *
+ *   M_E = (1 / theta_ap^2) sum_j Q_j gamma_t(G_j) Omega_pix / W_j,  M_B likewise,
+ *   sigma = (1 / theta_ap^2) sqrt(sum_j Q_j^2 E2_j (Omega_pix / W_j)^2 / 2),
+ *
+ * with Omega_pix the area of a source pixel; pixels with W_j = 0 add nothing.
+ * The W and N channels are those of the summed maps.
+ *
  * Conventions
  *   - Angles in radians. Right ascension in [0, 2 pi), declination in
  *     [-pi/2, pi/2]. Shear components in the local frame x = East (+ra),
@@ -96,7 +106,11 @@ enum {
 enum {
   SMART_NORM_SUMMED_CAP = 0,      /* A_ap = spherical cap area               */
   SMART_NORM_SUMMED_PIXCOUNT = 1, /* A_ap = N * pixel area                   */
-  SMART_NORM_RAW = 2              /* channels are S_E, S_B, V, W, N          */
+  SMART_NORM_RAW = 2,             /* channels are S_E, S_B, V, W, N          */
+  SMART_NORM_AVERAGED = 3         /* averaged approach: pixel-variant FP32
+                                     plans only (smart_run, smart_noise_batch,
+                                     smart_mixed_batch); SMART_EINVAL for
+                                     galaxy-variant and FP64 plans            */
 };
 
 /* Output channel order of smart_run: [n_scales][5][n_out].                  */
@@ -222,6 +236,11 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
  * float for SMART_PREC_FP32_GEO64 and double for SMART_PREC_FP64, laid out
  * [scale][channel][output] with channels SMART_CH_*. */
 int smart_run(smart_plan plan, int norm, void* d_out, void* stream);
+/* With norm = SMART_NORM_AVERAGED the first call on a map also builds the
+ * map's averaged records (G_j Omega_pix / W_j, E2_j (Omega_pix / W_j)^2:
+ * 16 bytes per dense pixel, kept until smart_data_free) and synchronises
+ * `stream` once; later calls, on any plan of the map, only launch the pair
+ * kernels on them. */
 
 /* Total number of source-centre pairs inside the apertures of the last
  * smart_run (sum of the N channel over outputs and scales; the pixel

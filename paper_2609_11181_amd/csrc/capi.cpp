@@ -35,6 +35,15 @@ int set_device(smart_ctx ctx) {
   return SMART_OK;
 }
 
+// a normalisation the plan accepts: the summed and raw forms on every plan,
+// the averaged approach on pixel-variant FP32 plans (its records are FP32)
+int check_norm(smart_plan p, int norm) {
+  if (norm < SMART_NORM_SUMMED_CAP || norm > SMART_NORM_AVERAGED) return fail(SMART_EINVAL, "unknown normalisation");
+  if (norm == SMART_NORM_AVERAGED && (p->variant != SMART_VAR_PIXEL || p->precision != SMART_PREC_FP32_GEO64))
+    return fail(SMART_EINVAL, "averaged normalisation needs a pixel-variant FP32 plan");
+  return SMART_OK;
+}
+
 #define CHECK_HIP(x)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (x);                                                               \
@@ -124,7 +133,7 @@ void smart_data_free(smart_data d) {
   // the blocks go back to the library's cache: no work may still use them
   (void)hipDeviceSynchronize();
   for (void* q : {(void*)d->P, (void*)d->F, (void*)d->G, (void*)d->order, (void*)d->offsets, (void*)d->sums,
-                  (void*)d->wd, (void*)d->wn, (void*)d->cidx, (void*)d->src_pix})
+                  (void*)d->wd, (void*)d->wn, (void*)d->cidx, (void*)d->src_pix, (void*)d->avg})
     smart::dev_release(q);
   delete d;
 }
@@ -312,11 +321,12 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
 
 int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
   if (!p || (!d_out && p->n_out > 0)) return fail(SMART_EINVAL, "NULL plan or output");
-  if (norm < SMART_NORM_SUMMED_CAP || norm > SMART_NORM_RAW) return fail(SMART_EINVAL, "unknown normalisation");
   int rc;
+  if ((rc = check_norm(p, norm))) return rc;
   if ((rc = set_device(p->ctx))) return rc;
   hipStream_t st = (hipStream_t)stream;
   smart_data d = p->data;
+  if (norm == SMART_NORM_AVERAGED && (rc = ensure_averaged(d, st))) return rc;
   const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
   for (int k = 0; k < (int)p->theta_ap.size(); ++k) {
     const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);
@@ -326,7 +336,7 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.out_pix = p->out_pix;
       a.n_out = p->n_out;
       a.nside_out = p->nside_out;
-      a.map = d->sums;
+      a.map = map_for(d, norm);
       a.wn = d->wn;
       a.nside_in = d->nside;
       a.ring_lo = d->ring_lo;
@@ -446,11 +456,12 @@ int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int 
   if (p->variant != SMART_VAR_PIXEL || p->precision != SMART_PREC_FP32_GEO64)
     return fail(SMART_EINVAL, "noise batches need a pixel-variant FP32 plan");
   if (n_real < 1) return fail(SMART_EINVAL, "n_real must be >= 1");
-  if (norm < SMART_NORM_SUMMED_CAP || norm > SMART_NORM_RAW) return fail(SMART_EINVAL, "unknown normalisation");
   int rc;
+  if ((rc = check_norm(p, norm))) return rc;
   if ((rc = set_device(p->ctx))) return rc;
   hipStream_t st = (hipStream_t)stream;
   smart_data d = p->data;
+  if (norm == SMART_NORM_AVERAGED && (rc = ensure_averaged(d, st))) return rc;
   if (precision == SMART_PREC_BF16X3) return noise_bf16x3(p, d_u, n_real, norm, d_out, st);
   if (precision != SMART_PREC_FP32_GEO64) return fail(SMART_EINVAL, "noise precision must be FP32 or BF16X3");
   // plain path: rotate the map, then one ordinary pair-sum pass per realisation
@@ -469,7 +480,7 @@ int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int 
   if (scratch_alloc(&stage, sizeof(float) * 5 * p->n_out, st) != hipSuccess)
     return fail(SMART_ENOMEM, "allocation failed for staging");
   for (int r = 0; r < n_real; ++r) {
-    hipError_t e = launch_rotate_map(d->sums, d->cidx, d_u + (int64_t)r * d->n_src, d->n_dense, p->rot_map, st);
+    hipError_t e = launch_rotate_map(map_for(d, norm), d->cidx, d_u + (int64_t)r * d->n_src, d->n_dense, p->rot_map, st);
     if (e != hipSuccess) return fail(SMART_EDEVICE, "rotation kernel failed");
     for (int k = 0; k < ns; ++k) {
       const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);
@@ -505,10 +516,13 @@ int smart_mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const
     if (plans[k]->ctx != ctx) return fail(SMART_EINVAL, "plan belongs to another context");
     if (plans[k]->variant != SMART_VAR_PIXEL || plans[k]->precision != SMART_PREC_FP32_GEO64)
       return fail(SMART_EINVAL, "mixed batches take pixel-variant FP32 plans");
-    if (norms[k] < SMART_NORM_SUMMED_CAP || norms[k] > SMART_NORM_RAW) return fail(SMART_EINVAL, "unknown normalisation");
   }
   int rc;
+  for (int k = 0; k < n_plans; ++k)
+    if ((rc = check_norm(plans[k], norms[k]))) return rc;
   if ((rc = set_device(ctx))) return rc;
+  for (int k = 0; k < n_plans; ++k)
+    if (norms[k] == SMART_NORM_AVERAGED && (rc = ensure_averaged(plans[k]->data, (hipStream_t)stream))) return rc;
   return mixed_batch(ctx, n_plans, plans, norms, d_outs, (hipStream_t)stream);
 }
 

@@ -475,7 +475,40 @@ __global__ __launch_bounds__(kBlock) void k_wn_write_w(const float* w, int64_t n
   }
 }
 
+// Averaged approach (Sect. 2.4): every galaxy of pixel j is normalised by
+// the pixel's own effective density W_j / Omega_pix, so the pixel enters
+// the aperture sums with its shear sum times c = Omega_pix / W_j and, in
+// the variance, its sum of squared shears times c^2. W stays as it is (the
+// W channel and the prefix sums are those of the summed maps).
+__global__ void k_average(const float4* sums, int64_t n, double omega, float4* avg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 g = sums[i];
+  const double c = g.w > 0.f ? omega / (double)g.w : 0.0;
+  avg[i] = make_float4((float)(c * g.x), (float)(c * g.y), (float)(c * c * g.z), g.w);
+}
+
 }  // namespace
+
+int ensure_averaged(smart_data d, hipStream_t st) {
+  if (d->avg || d->n_dense <= 0) return SMART_OK;
+  float4* avg = nullptr;
+  if (dev_alloc(&avg, sizeof(float4) * d->n_dense) != hipSuccess) {
+    set_error("out of device memory (averaged records)");
+    return SMART_ENOMEM;
+  }
+  const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
+  hipLaunchKernelGGL(k_average, dim3(grid_of(d->n_dense)), dim3(kBlock), 0, st, d->sums, d->n_dense, omega, avg);
+  // plans of the map may run on other streams: the records are complete
+  // before any of them can see the pointer
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    dev_release(avg);
+    set_error("averaging kernel failed");
+    return SMART_EDEVICE;
+  }
+  d->avg = avg;
+  return SMART_OK;
+}
 
 int build_wn_prefix(smart_ctx ctx, smart_data d, hipStream_t st) {
   (void)ctx;

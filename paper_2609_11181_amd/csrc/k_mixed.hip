@@ -164,7 +164,7 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
       J.a.out_pix = P->out_pix;
       J.a.n_out = P->n_out;
       J.a.nside_out = P->nside_out;
-      J.a.map = d->sums;
+      J.a.map = map_for(d, norms[p]);
       J.a.wn = d->wn;
       J.a.nside_in = d->nside;
       J.a.ring_lo = d->ring_lo;

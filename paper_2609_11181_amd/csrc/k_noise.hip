@@ -327,10 +327,12 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
     __syncthreads();  // xs, the bands and the windows are rewritten for the next ring
   }
 
-  // epilogue: summed normalisation per centre, staged for coalesced writes
+  // epilogue: normalisation per centre, staged for coalesced writes
   if (lane < kNP) {
     float f = 1.f;
-    if (a.norm != SMART_NORM_RAW) {
+    if (a.norm == SMART_NORM_AVERAGED) {
+      f = (float)s.inv_theta2;
+    } else if (a.norm != SMART_NORM_RAW) {
       const double area = a.norm == SMART_NORM_SUMMED_CAP ? s.area_cap : np_occ * s.omega_pix;
       f = wp > 0.0 ? (float)(area * s.inv_theta2 / wp) : 0.f;
     }
@@ -464,7 +466,9 @@ __global__ __launch_bounds__(kBlock) void k_noise_rest_walk(RestArgs n, ScaleArg
     }
   }
   float f = 1.f;
-  if (a.norm != SMART_NORM_RAW) {
+  if (a.norm == SMART_NORM_AVERAGED) {
+    f = (float)s.inv_theta2;
+  } else if (a.norm != SMART_NORM_RAW) {
     const double area = a.norm == SMART_NORM_SUMMED_CAP ? s.area_cap : tot.sn * s.omega_pix;
     f = tot.sw > 0.0 ? (float)(area * s.inv_theta2 / tot.sw) : 0.f;
   }
@@ -574,7 +578,7 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
     a.out_pix = p->out_pix;
     a.n_out = p->n_out;
     a.nside_out = p->nside_out;
-    a.map = d->sums;
+    a.map = map_for(d, norm);
     a.wn = d->wn;
     a.nside_in = d->nside;
     a.ring_lo = d->ring_lo;

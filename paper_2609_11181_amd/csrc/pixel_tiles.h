@@ -21,6 +21,10 @@ __device__ __forceinline__ void write_out(void* out, int64_t n_out, int scale, i
     v0 = t.se;
     v1 = t.sb;
     v2 = t.sv;
+  } else if (norm == SMART_NORM_AVERAGED) {  // the records carry Omega_pix / W_j already
+    v0 = s.inv_theta2 * t.se;
+    v1 = s.inv_theta2 * t.sb;
+    v2 = s.inv_theta2 * sqrt(0.5 * t.sv);
   } else {
     const double area = norm == SMART_NORM_SUMMED_CAP ? s.area_cap : t.sn * s.omega_pix;
     const double f = t.sw > 0.0 ? area * s.inv_theta2 / t.sw : 0.0;

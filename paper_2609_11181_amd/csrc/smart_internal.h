@@ -97,6 +97,9 @@ struct smart_data_s {
   int64_t pix_first = 0, n_dense = 0;
   float4* sums = nullptr;  // (G1, G2, E2, W): the pair kernels read the first three
   float* wd = nullptr;     // pixel maps: W of the dense range again, contiguous (prefix-sum input)
+  // averaged approach: (G1 c, G2 c, E2 c^2, W) with c = Omega_pix / W (zero
+  // where W = 0), built at the first averaged call
+  float4* avg = nullptr;
   // prefix sums over the dense range: wn[i] = (sum of W, number of pixels
   // with W > 0) over dense pixels [0, i); n_dense + 1 entries
   double2* wn = nullptr;
@@ -312,6 +315,10 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
 int ensure_temp(smart_ctx ctx, size_t bytes);
 // Builds d->wn from d->sums (smart_data_s::wn).
 int build_wn_prefix(smart_ctx ctx, smart_data d, hipStream_t st);
+// the averaged records of a map (built once, synchronising `st`)
+int ensure_averaged(smart_data d, hipStream_t st);
+// the records the pair kernels read under normalisation `norm`
+inline const float4* map_for(smart_data d, int norm) { return norm == SMART_NORM_AVERAGED ? d->avg : d->sums; }
 int pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const float* W, const float* G1,
               const float* G2, const float* E2, hipStream_t st, smart_data d);
 hipError_t launch_check_pixels(const int64_t* pix, int64_t n, int64_t npix, int* d_flag, hipStream_t st);
