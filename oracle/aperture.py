@@ -342,3 +342,13 @@ def rotate_realisation(G1, G2, u):
     G1 = np.asarray(G1, np.float64)
     G2 = np.asarray(G2, np.float64)
     return G1 * c - G2 * s, G1 * s + G2 * c
+
+
+def rotate_galaxies(cat, u):
+    """One galaxy-level shape-noise realisation (the random orientations of
+    Sect. 1 / Sect. 5.3 given to every galaxy): galaxy i's shear is rotated by
+    the spin-2 phase exp(2 i pi u_i); positions and weights stay. The pixel
+    variant bins the rotated catalogue again (Sect. 3.2 step 2). Returns a
+    new catalogue dict."""
+    g1, g2 = rotate_realisation(cat["g1"], cat["g2"], u)
+    return dict(cat, g1=g1, g2=g2)

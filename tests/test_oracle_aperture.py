@@ -454,3 +454,70 @@ def test_noise_realisations_statistics():
     ratio = var / base["sigma"] ** 2
     assert abs(ratio.mean() - 1.0) < 4 * math.sqrt(2.0 / R) / math.sqrt(out.size) + 0.01
     assert np.abs(acc.mean(0)).mean() < 4 * base["sigma"].mean() / math.sqrt(R)
+
+
+# ----------------------------------------------------------------------------
+# Galaxy-level shape-noise realisations (random orientation of every galaxy)
+# ----------------------------------------------------------------------------
+
+def _gal_cat(n, seed, cap=10 * DEG):
+    rng = np.random.default_rng(seed)
+    ra = rng.uniform(-cap, cap, n) % (2 * math.pi)
+    dec = rng.uniform(-cap, cap, n)
+    return {"ra": ra, "dec": dec, "g1": rng.normal(0, 0.3, n) + 0.05, "g2": rng.normal(0, 0.3, n),
+            "w": rng.uniform(0.5, 1.5, n)}
+
+
+def test_galaxy_realisations_quarter_turns_and_statistics():
+    """Exact identities of the spin-2 phase: u + 1/2 negates the E and B maps,
+    and the four quarter-turn shifts of any u sum to zero. Over independent
+    uniform angles the mean of M_E vanishes and its variance is sigma^2 of
+    Eq. map_noise (the expectation of cos^2 of a uniform angle is 1/2)."""
+    cat = _gal_cat(3000, 31)
+    rng = np.random.default_rng(32)
+    c_ra = rng.uniform(-5 * DEG, 5 * DEG, 40) % (2 * math.pi)
+    c_dec = rng.uniform(-5 * DEG, 5 * DEG, 40)
+    th = 3 * DEG
+    u = rng.random(3000)
+    maps = [A.aperture_mass_galaxy(A.rotate_galaxies(cat, (u + k / 4) % 1.0), c_ra, c_dec, th, F.TANH)
+            for k in range(4)]
+    sc = np.abs(maps[0]["M_E"]).max()
+    for key in ("M_E", "M_B"):
+        assert np.max(np.abs(maps[2][key] + maps[0][key])) < 1e-12 * sc
+        assert np.max(np.abs(sum(mp[key] for mp in maps))) < 1e-12 * sc
+    base = A.aperture_mass_galaxy(cat, c_ra, c_dec, th, F.TANH)
+    assert np.allclose(maps[1]["sigma"], base["sigma"], rtol=1e-12)
+    R = 300
+    acc = np.array([A.aperture_mass_galaxy(A.rotate_galaxies(cat, np.random.default_rng([33, r]).random(3000)),
+                                           c_ra, c_dec, th, F.TANH)["M_E"] for r in range(R)])
+    ratio = acc.var(0) / base["sigma"] ** 2
+    assert abs(ratio.mean() - 1.0) < 4 * math.sqrt(2.0 / R) / math.sqrt(c_ra.size) + 0.01
+    assert np.abs(acc.mean(0)).mean() < 4 * base["sigma"].mean() / math.sqrt(R)
+
+
+def test_galaxy_realisation_binned_equals_pixel_realisation_at_one_galaxy_per_pixel():
+    """With one galaxy in each occupied pixel, rotating the galaxies and
+    binning them again gives the pixel sums rotated by the same angles: the
+    galaxy-level realisation of the pixel variant equals the pixel-level one."""
+    from oracle import binning as B
+
+    nside = 64
+    rng = np.random.default_rng(34)
+    pix = np.sort(rng.choice(hp.npix(nside), 20000, replace=False))
+    ra, dec = hp.pix2radec(nside, pix)
+    cat = {"ra": ra, "dec": dec, "g1": rng.normal(0, 0.3, pix.size), "g2": rng.normal(0, 0.3, pix.size),
+           "w": np.ones(pix.size)}
+    u = rng.random(pix.size)
+    out = rng.choice(hp.npix(nside), 150, replace=False)
+    th = 4 * DEG
+    rc = A.rotate_galaxies(cat, u)
+    p_u, W, G1, G2, E2 = B.pixel_sums(nside, rc["ra"], rc["dec"], rc["g1"], rc["g2"], rc["w"])
+    assert np.array_equal(p_u, pix)
+    a = A.aperture_mass_pixel({"nside": nside, "pix": p_u, "W": W, "G1": G1, "G2": G2, "E2": E2}, out, th, F.TANH)
+    H1, H2 = A.rotate_realisation(cat["g1"], cat["g2"], u)
+    b = A.aperture_mass_pixel({"nside": nside, "pix": pix, "W": np.ones(pix.size), "G1": H1, "G2": H2,
+                               "E2": cat["g1"] ** 2 + cat["g2"] ** 2}, out, th, F.TANH)
+    ok = ~a["tie"]
+    for key in ("M_E", "M_B", "sigma", "W", "N"):
+        sc = np.abs(b[key][ok]).max()
+        assert np.max(np.abs(a[key][ok] - b[key][ok])) < 1e-12 * sc, key
