@@ -303,6 +303,25 @@ int smart_plan_kernel_ms(smart_plan plan, int scale, double* belt_ms, double* ge
 int smart_noise_batch(smart_plan plan, const float* d_u, int n_real, int norm, int precision, float* d_out,
                       void* stream);
 
+/* Galaxy-level shape-noise realisations (the random orientations of the
+ * individual galaxies, Sect. 1 and Sect. 5.3): in realisation r galaxy i's
+ * shear is rotated by the spin-2 phase exp(2 i pi u[r][i]). For a
+ * galaxy-variant plan the pair sums run over the rotated galaxies; for a
+ * pixel-variant plan the pixel sums are re-formed from the rotated galaxies
+ * (Sect. 3.2 step 2) before the maps are recomputed. Weights, W, N and V
+ * (up to rounding) do not change.
+ *   d_u    : n_real * n_gal floats in [0,1); row r for realisation r,
+ *            column i for the galaxy's index in the catalogue passed to
+ *            smart_bin_galaxies
+ *   d_out  : float, [n_scales][n_real][2][n_out] (E then B)
+ * The plan must be an FP32 plan (SMART_PREC_FP32_GEO64) on data from
+ * smart_bin_galaxies, with pixel sums for the pixel variant. One call
+ * costs n_real x (one rotation pass over the galaxies [+ one pixel-sum
+ * pass] + the plan's pair kernels); the first call allocates the plan's
+ * rotation buffers (16 bytes per galaxy [+ 16 per dense pixel]), kept until
+ * smart_plan_free. */
+int smart_noise_galaxy_batch(smart_plan plan, const float* d_u, int n_real, int norm, float* d_out, void* stream);
+
 /* Several plans in one persistent launch (pixel variant, FP32): a single
  * kernel drains a work list holding the tiles of every plan and scale,
  * longest first. outs[k] is the smart_run output buffer of plans[k]. */

@@ -210,6 +210,14 @@ class Plan:
                                                _stream(self.ctx.device)))
         return out
 
+    def noise_galaxy_batch(self, u, n_real: int, norm: int, out=None):
+        """Galaxy-level realisations: u is [n_real][n_gal] in catalogue order."""
+        if out is None:
+            out = torch.empty(self.n_scales, n_real, 2, self.n_out, dtype=torch.float32, device=self.ctx.device)
+        L.check(self.ctx.lib.smart_noise_galaxy_batch(self.h, _ptr(u), n_real, norm, _ptr(out),
+                                                      _stream(self.ctx.device)))
+        return out
+
     def free(self):
         if self.h:
             self.ctx.lib.smart_plan_free(self.h)

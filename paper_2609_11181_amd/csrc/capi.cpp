@@ -238,6 +238,7 @@ void smart_plan_free(smart_plan p) {
   smart::dev_release(p->d_pairs);
   smart::dev_release(p->d_work);
   smart::dev_release(p->rot_map);
+  smart::dev_release(p->rot_gal);
   smart::dev_release(p->runs_block);
   for (smart::PixelSched* sc : p->sched) delete sc;
   for (hipEvent_t e : p->events) hipEventDestroy(e);
@@ -502,6 +503,92 @@ int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int 
       float* dst = d_out + (((int64_t)k * n_real + r) * 2) * p->n_out;
       e = hipMemcpyAsync(dst, stage, sizeof(float) * 2 * p->n_out, hipMemcpyDeviceToDevice, st);
       if (e != hipSuccess) return fail(SMART_EDEVICE, "copy failed");
+    }
+  }
+  scratch_free(stage, st);
+  return SMART_OK;
+}
+
+int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int norm, float* d_out, void* stream) {
+  if (!p || !d_u || !d_out) return fail(SMART_EINVAL, "NULL argument");
+  if (p->precision != SMART_PREC_FP32_GEO64) return fail(SMART_EINVAL, "galaxy-level realisations need an FP32 plan");
+  smart_data d = p->data;
+  if (d->kind != 0 || !d->G) return fail(SMART_EINVAL, "galaxy-level realisations need a binned catalogue");
+  if (p->variant == SMART_VAR_PIXEL && !d->sums)
+    return fail(SMART_EINVAL, "the pixel variant needs the catalogue's pixel sums (want_pixel_sums)");
+  if (n_real < 1) return fail(SMART_EINVAL, "n_real must be >= 1");
+  int rc;
+  if ((rc = check_norm(p, norm))) return rc;
+  if ((rc = set_device(p->ctx))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (p->n_out == 0) return SMART_OK;
+  // buffers of the plan, sized by its catalogue (fixed for the plan's life):
+  // allocated at the first call, kept until smart_plan_free
+  if (!p->rot_gal && d->n_gal > 0) {
+    if (dev_alloc(&p->rot_gal, sizeof(float4) * d->n_gal) != hipSuccess)
+      return fail(SMART_ENOMEM, "allocation failed for the rotated galaxies");
+    p->rot_gal_len = d->n_gal;
+  }
+  if (p->variant == SMART_VAR_PIXEL && !p->rot_map && d->n_dense > 0) {
+    if (dev_alloc(&p->rot_map, sizeof(float4) * d->n_dense) != hipSuccess)
+      return fail(SMART_ENOMEM, "allocation failed for the rotated pixel sums");
+    p->rot_len = d->n_dense;
+  }
+  const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
+  const int ns = (int)p->theta_ap.size();
+  float* stage = nullptr;
+  if (scratch_alloc(&stage, sizeof(float) * 5 * p->n_out, st) != hipSuccess)
+    return fail(SMART_ENOMEM, "allocation failed for staging");
+  for (int r = 0; r < n_real; ++r) {
+    hipError_t e = launch_rotate_galaxies(d->G, d->order, d_u + (int64_t)r * d->n_gal, d->n_gal, p->rot_gal, st);
+    if (e == hipSuccess && p->variant == SMART_VAR_PIXEL) {
+      e = launch_pixel_sums(d, p->rot_gal, p->rot_map, st);  // the pixel sums of the rotated catalogue
+      if (e == hipSuccess && norm == SMART_NORM_AVERAGED) e = launch_average(p->rot_map, d->n_dense, omega, p->rot_map, st);
+    }
+    if (e != hipSuccess) {
+      scratch_free(stage, st);
+      return fail(SMART_EDEVICE, "rotation kernel failed");
+    }
+    for (int k = 0; k < ns; ++k) {
+      const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);
+      if (p->variant == SMART_VAR_PIXEL) {
+        PixelArgs a{};
+        a.out_pix = p->out_pix;
+        a.n_out = p->n_out;
+        a.nside_out = p->nside_out;
+        a.map = p->rot_map;
+        a.wn = d->wn;
+        a.nside_in = d->nside;
+        a.ring_lo = d->ring_lo;
+        a.ring_hi = d->ring_hi;
+        a.pix_first = d->pix_first;
+        a.out = stage;
+        a.norm = norm;
+        a.scale = 0;
+        e = launch_pixel_sched(a, s, *p->sched[k], st);
+      } else {
+        GalaxyArgs a{};
+        a.out_pix = p->out_pix;
+        a.n_out = p->n_out;
+        a.nside_out = p->nside_out;
+        a.P = d->P;
+        a.F = d->F;
+        a.G = p->rot_gal;
+        a.offsets = d->offsets;
+        a.nside_bin = d->nside;
+        a.r_bin = d->r_bin;
+        a.out = stage;
+        a.norm = norm;
+        a.scale = 0;
+        e = launch_galaxy(a, s, p->precision, st);
+      }
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(d_out + (((int64_t)k * n_real + r) * 2) * p->n_out, stage, sizeof(float) * 2 * p->n_out,
+                           hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) {
+        scratch_free(stage, st);
+        return fail(SMART_EDEVICE, "pair kernel failed");
+      }
     }
   }
   scratch_free(stage, st);

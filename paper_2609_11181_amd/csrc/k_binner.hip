@@ -490,6 +490,19 @@ __global__ void k_average(const float4* sums, int64_t n, double omega, float4* a
 
 }  // namespace
 
+hipError_t launch_pixel_sums(smart_data d, const float4* G, float4* sums, hipStream_t st) {
+  if (d->n_dense <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sums, dim3(grid_of(d->n_dense)), dim3(kBlock), 0, st, d->n_dense, d->pix_first, d->offsets,
+                     d->P, G, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_average(const float4* in, int64_t n, double omega, float4* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_average, dim3(grid_of(n)), dim3(kBlock), 0, st, in, n, omega, out);
+  return hipGetLastError();
+}
+
 int ensure_averaged(smart_data d, hipStream_t st) {
   if (d->avg || d->n_dense <= 0) return SMART_OK;
   float4* avg = nullptr;

@@ -129,6 +129,19 @@ __global__ void k_noise_rest_pix(const int64_t* pos, int n, const int64_t* out_p
   if (i < n) pix[i] = out_pix[pos[i]];
 }
 
+// Galaxy-level realisation: each galaxy's shear is rotated by its own
+// spin-2 phase (the per-galaxy random orientations of Sect. 1); the weight,
+// and with it W, |g| and V, is unchanged. Galaxy records are in partition
+// order, the angles in catalogue order.
+__global__ void k_rotate_gal(const float4* G, const int64_t* order, const float* u, int64_t n, float4* out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float4 g = G[k];
+  float s, c;
+  sincospif(2.0f * u[order[k]], &s, &c);
+  out[k] = make_float4(g.x * c - g.y * s, g.x * s + g.y * c, g.z, g.w);
+}
+
 struct NoiseArgs {
   PixelArgs a;
   BeltTab t;
@@ -485,6 +498,13 @@ __global__ __launch_bounds__(kBlock) void k_noise_rest_walk(RestArgs n, ScaleArg
 unsigned grid_of(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
+
+hipError_t launch_rotate_galaxies(const float4* G, const int64_t* order, const float* u, int64_t n, float4* out,
+                                  hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rotate_gal, dim3(grid_of(n)), dim3(kBlock), 0, st, G, order, u, n, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_rotate_map(const float4* map, const int* cidx, const float* u, int64_t n, float4* out,
                              hipStream_t st) {

@@ -139,6 +139,9 @@ struct smart_plan_s {
   // scratch for the noise batch (rotated map), grown on demand
   float4* rot_map = nullptr;
   int64_t rot_len = 0;
+  // galaxy-level realisations: the rotated galaxy records, grown on demand
+  float4* rot_gal = nullptr;
+  int64_t rot_gal_len = 0;
 };
 
 namespace smart {
@@ -324,6 +327,14 @@ int pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const flo
 hipError_t launch_check_pixels(const int64_t* pix, int64_t n, int64_t npix, int* d_flag, hipStream_t st);
 
 // noise realisations (k_noise.hip)
+// galaxy-level realisations: G'[k] = rotation of sorted galaxy k by the
+// spin-2 phase of u[order[k]]
+hipError_t launch_rotate_galaxies(const float4* G, const int64_t* order, const float* u, int64_t n, float4* out,
+                                  hipStream_t st);
+// pixel sums (G1, G2, E2, W) of a binned catalogue from galaxy records G
+hipError_t launch_pixel_sums(smart_data d, const float4* G, float4* sums, hipStream_t st);
+// averaged records (G1 c, G2 c, E2 c^2, W), c = omega / W; in may equal out
+hipError_t launch_average(const float4* in, int64_t n, double omega, float4* out, hipStream_t st);
 hipError_t launch_rotate_map(const float4* map, const int* cidx, const float* u, int64_t n, float4* out,
                              hipStream_t st);
 int noise_bf16x3(smart_plan plan, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st);
