@@ -316,9 +316,10 @@ int smart_noise_batch(smart_plan plan, const float* d_u, int n_real, int norm, i
  *   d_out  : float, [n_scales][n_real][2][n_out] (E then B)
  * The plan must be an FP32 plan (SMART_PREC_FP32_GEO64) on data from
  * smart_bin_galaxies, with pixel sums for the pixel variant. One call
- * costs n_real x (one rotation pass over the galaxies [+ one pixel-sum
- * pass] + the plan's pair kernels); the first call allocates the plan's
- * rotation buffers (16 bytes per galaxy [+ 16 per dense pixel]), kept until
+ * costs n_real x (one pass over the galaxies + the plan's pair kernels): the
+ * pixel variant rotates and sums in one pass into rotated pixel sums (16
+ * bytes per dense pixel), the galaxy variant writes rotated galaxy records
+ * (16 bytes per galaxy); the first call allocates that buffer, kept until
  * smart_plan_free. */
 int smart_noise_galaxy_batch(smart_plan plan, const float* d_u, int n_real, int norm, float* d_out, void* stream);
 

@@ -524,7 +524,7 @@ int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int nor
   if (p->n_out == 0) return SMART_OK;
   // buffers of the plan, sized by its catalogue (fixed for the plan's life):
   // allocated at the first call, kept until smart_plan_free
-  if (!p->rot_gal && d->n_gal > 0) {
+  if (p->variant == SMART_VAR_GALAXY && !p->rot_gal && d->n_gal > 0) {
     if (dev_alloc(&p->rot_gal, sizeof(float4) * d->n_gal) != hipSuccess)
       return fail(SMART_ENOMEM, "allocation failed for the rotated galaxies");
     p->rot_gal_len = d->n_gal;
@@ -540,10 +540,13 @@ int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int nor
   if (scratch_alloc(&stage, sizeof(float) * 5 * p->n_out, st) != hipSuccess)
     return fail(SMART_ENOMEM, "allocation failed for staging");
   for (int r = 0; r < n_real; ++r) {
-    hipError_t e = launch_rotate_galaxies(d->G, d->order, d_u + (int64_t)r * d->n_gal, d->n_gal, p->rot_gal, st);
-    if (e == hipSuccess && p->variant == SMART_VAR_PIXEL) {
-      e = launch_pixel_sums(d, p->rot_gal, p->rot_map, st);  // the pixel sums of the rotated catalogue
+    const float* ur = d_u + (int64_t)r * d->n_gal;
+    hipError_t e;
+    if (p->variant == SMART_VAR_PIXEL) {
+      e = launch_pixel_sums(d, ur, p->rot_map, st);  // pixel sums of the rotated catalogue, rotation fused
       if (e == hipSuccess && norm == SMART_NORM_AVERAGED) e = launch_average(p->rot_map, d->n_dense, omega, p->rot_map, st);
+    } else {
+      e = launch_rotate_galaxies(d->G, d->order, ur, d->n_gal, p->rot_gal, st);
     }
     if (e != hipSuccess) {
       scratch_free(stage, st);

@@ -71,23 +71,46 @@ __global__ void k_gather(int64_t n, const uint32_t* skeys, const uint32_t* sidx,
   atomicMax(max_chord_bits, __float_as_uint(c));
 }
 
-__global__ void k_sums(int64_t n_dense, int64_t pix_first, const int64_t* off, const double4* P, const float4* G,
-                       float4* sums) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_dense) return;
+// Pixel sums of a partitioned catalogue: kSumLanes lanes per pixel stride
+// over its galaxies (contiguous records, so a group's loads are coalesced),
+// then a butterfly reduction within the group; FP64 partial sums. With ROT
+// each galaxy's shear is first rotated by the spin-2 phase of its angle
+// u[order[k]] (a galaxy-level noise realisation, weights unchanged).
+constexpr int kSumLanes = 16;
+
+template <bool ROT>
+__global__ __launch_bounds__(kBlock) void k_sums(int64_t n_dense, int64_t pix_first, const int64_t* off,
+                                                 const float4* G, const int64_t* order, const float* u,
+                                                 float4* sums) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = t / kSumLanes;
+  const int sub = (int)(t % kSumLanes);
+  if (p >= n_dense) return;  // whole groups leave together (kBlock is a multiple of kSumLanes)
   const int64_t a = off[pix_first + p], b = off[pix_first + p + 1];
   double W = 0, G1 = 0, G2 = 0, E2 = 0;
-  for (int64_t k = a; k < b; ++k) {
-    const float4 g = G[k];
+  for (int64_t k = a + sub; k < b; k += kSumLanes) {
+    float4 g = G[k];
+    if (ROT) {
+      float sn, cs;
+      sincospif(2.0f * u[order[k]], &sn, &cs);
+      g = make_float4(g.x * cs - g.y * sn, g.x * sn + g.y * cs, g.z, g.w);
+    }
     const double w = g.z, x = g.x, y = g.y;
     W += w;
     G1 += w * x;
     G2 += w * y;
     E2 += w * w * (x * x + y * y);
   }
-  sums[p] = make_float4((float)G1, (float)G2, (float)E2, (float)W);
-  (void)P;
+#pragma unroll
+  for (int m = kSumLanes / 2; m > 0; m >>= 1) {
+    W += __shfl_xor(W, m, kSumLanes);
+    G1 += __shfl_xor(G1, m, kSumLanes);
+    G2 += __shfl_xor(G2, m, kSumLanes);
+    E2 += __shfl_xor(E2, m, kSumLanes);
+  }
+  if (sub == 0) sums[p] = make_float4((float)G1, (float)G2, (float)E2, (float)W);
 }
+static_assert(kBlock % kSumLanes == 0, "pixel-sum groups must not straddle blocks");
 
 __global__ void k_check_pix(const int64_t* pix, int64_t n, int64_t npix, int* flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -267,8 +290,8 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
   }
   if (want_sums && d->n_dense > 0) {
     if ((rc = dmalloc(&d->sums, d->n_dense))) return fail(rc);
-    hipLaunchKernelGGL(k_sums, dim3(grid_of(d->n_dense)), dim3(kBlock), 0, st, d->n_dense, d->pix_first, d->offsets,
-                       d->P, d->G, d->sums);
+    hipLaunchKernelGGL(k_sums<false>, dim3(grid_of(d->n_dense * kSumLanes)), dim3(kBlock), 0, st, d->n_dense,
+                       d->pix_first, d->offsets, d->G, nullptr, nullptr, d->sums);
     if (hipGetLastError() != hipSuccess) {
       set_error("pixel-sum kernel failed to launch");
       return fail(SMART_EDEVICE);
@@ -490,10 +513,13 @@ __global__ void k_average(const float4* sums, int64_t n, double omega, float4* a
 
 }  // namespace
 
-hipError_t launch_pixel_sums(smart_data d, const float4* G, float4* sums, hipStream_t st) {
+hipError_t launch_pixel_sums(smart_data d, const float* u, float4* sums, hipStream_t st) {
   if (d->n_dense <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sums, dim3(grid_of(d->n_dense)), dim3(kBlock), 0, st, d->n_dense, d->pix_first, d->offsets,
-                     d->P, G, sums);
+  const dim3 grid(grid_of(d->n_dense * kSumLanes)), block(kBlock);
+  if (u) hipLaunchKernelGGL(k_sums<true>, grid, block, 0, st, d->n_dense, d->pix_first, d->offsets, d->G, d->order,
+                            u, sums);
+  else hipLaunchKernelGGL(k_sums<false>, grid, block, 0, st, d->n_dense, d->pix_first, d->offsets, d->G, nullptr,
+                          nullptr, sums);
   return hipGetLastError();
 }
 

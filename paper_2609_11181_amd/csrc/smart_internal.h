@@ -331,8 +331,9 @@ hipError_t launch_check_pixels(const int64_t* pix, int64_t n, int64_t npix, int*
 // spin-2 phase of u[order[k]]
 hipError_t launch_rotate_galaxies(const float4* G, const int64_t* order, const float* u, int64_t n, float4* out,
                                   hipStream_t st);
-// pixel sums (G1, G2, E2, W) of a binned catalogue from galaxy records G
-hipError_t launch_pixel_sums(smart_data d, const float4* G, float4* sums, hipStream_t st);
+// pixel sums (G1, G2, E2, W) of a binned catalogue; with u (angles in
+// catalogue order) of the catalogue with every galaxy rotated by its angle
+hipError_t launch_pixel_sums(smart_data d, const float* u, float4* sums, hipStream_t st);
 // averaged records (G1 c, G2 c, E2 c^2, W), c = omega / W; in may equal out
 hipError_t launch_average(const float4* in, int64_t n, double omega, float4* out, hipStream_t st);
 hipError_t launch_rotate_map(const float4* map, const int* cidx, const float* u, int64_t n, float4* out,
