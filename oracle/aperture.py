@@ -138,6 +138,43 @@ def pixel_sources(nside, pix, W, G1, G2, E2) -> Sources:
                    np.asarray(E2, np.float64), (W > 0).astype(np.float64))
 
 
+def barycentre_sources(nside, ra, dec, g1, g2, w=None) -> Sources:
+    """Pixel-based variant with barycentre positions (Sect. 3.3, label
+    sphS_pixB): the galaxies of each occupied pixel are summed as in the
+    pixel variant (Sect. 3.2 step 2) and the sums are placed at the pixel's
+    barycentre instead of its centre. The barycentre is the normalised mean
+    of the galaxies' unit vectors (the paper averages RA and Dec; that mean
+    breaks across RA = 0 and near the poles, and elsewhere the two agree to
+    second order in the pixel size). Every occupied pixel counts once in N."""
+    from . import binning
+
+    ra = np.asarray(ra, np.float64)
+    dec = np.asarray(dec, np.float64)
+    pix = hp.radec2pix(nside, ra, dec)
+    v = radec2vec(ra, dec)
+    occ, inv = np.unique(pix, return_inverse=True)
+    m = np.stack([np.bincount(inv, v[:, k], occ.size) for k in range(3)], axis=1)
+    m /= np.linalg.norm(m, axis=1)[:, None]
+    b_ra = np.arctan2(m[:, 1], m[:, 0]) % (2 * math.pi)
+    b_dec = np.arctan2(m[:, 2], np.hypot(m[:, 0], m[:, 1]))
+    p_u, W, G1, G2, E2 = binning.pixel_sums(nside, ra, dec, g1, g2, w)
+    assert np.array_equal(p_u, occ)
+    return Sources(b_ra, b_dec, G1, G2, W, E2, np.ones(occ.size))
+
+
+def aperture_mass_barycentre(cat, nside, c_ra, c_dec, theta_ap, filter_kind, norm=NORM_SUMMED_PIXCOUNT,
+                             filter_params=None):
+    """sphS_pixB (Sect. 3.3): pixel sums at their pixels' barycentres, every
+    source within theta_ap of the centre, summed normalisation with
+    A = (occupied pixels in the aperture) x Omega_pix or the cap area."""
+    src = barycentre_sources(nside, cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat.get("w"))
+    s = sums_kdtree(src, c_ra, c_dec, theta_ap, q_of(filter_kind, filter_params))
+    out = normalise(s, theta_ap, norm, omega_pix=4.0 * math.pi / hp.npix(nside))
+    out["tie"] = s["tie"]
+    out["pairs"] = s["pairs"]
+    return out
+
+
 def _pair_sums(src: Sources, src_vec, cand_centre, cand_src, c_ra, c_dec, c_vec, theta_ap, qfun, n_cen):
     """Sums over the candidate pairs (centre index, source index) that pass
     the FP64 membership test."""

@@ -521,3 +521,92 @@ def test_galaxy_realisation_binned_equals_pixel_realisation_at_one_galaxy_per_pi
     for key in ("M_E", "M_B", "sigma", "W", "N"):
         sc = np.abs(b[key][ok]).max()
         assert np.max(np.abs(a[key][ok] - b[key][ok])) < 1e-12 * sc, key
+
+
+# ----------------------------------------------------------------------------
+# sphS_pixB: pixel sums at the barycentre of their galaxies (Sect. 3.3)
+# ----------------------------------------------------------------------------
+
+def test_barycentre_one_galaxy_per_pixel_is_the_brute_force():
+    """A pixel holding one galaxy has that galaxy as its barycentre and its
+    sums as its values: pixB equals the galaxy variant."""
+    nside = 64
+    rng = np.random.default_rng(41)
+    pix = np.sort(rng.choice(hp.npix(nside), 8000, replace=False))
+    c = hp.pix2vec(nside, pix)
+    # one galaxy inside each pixel, off its centre
+    t = np.cross(c, rng.normal(size=c.shape))
+    t /= np.linalg.norm(t, axis=1)[:, None]
+    v = c + 0.2 * math.sqrt(4 * math.pi / hp.npix(nside)) * t
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    ra = np.arctan2(v[:, 1], v[:, 0]) % (2 * math.pi)
+    dec = np.arcsin(np.clip(v[:, 2], -1, 1))
+    assert np.array_equal(np.sort(hp.radec2pix(nside, ra, dec)), pix)
+    cat = {"ra": ra, "dec": dec, "g1": rng.normal(0, 0.3, pix.size), "g2": rng.normal(0, 0.3, pix.size),
+           "w": rng.uniform(0.5, 1.5, pix.size)}
+    out = rng.choice(hp.npix(nside), 200, replace=False)
+    c_ra, c_dec = hp.pix2radec(nside, out)
+    th = 4 * DEG
+    a = A.aperture_mass_barycentre(cat, nside, c_ra, c_dec, th, F.TANH, norm=A.NORM_SUMMED_CAP)
+    g = A.aperture_mass_galaxy(cat, c_ra, c_dec, th, F.TANH, norm=A.NORM_SUMMED_CAP)
+    ok = ~(a["tie"] | g["tie"])
+    for key in ("M_E", "M_B", "sigma", "W", "N"):
+        sc = np.abs(g[key][ok]).max()
+        assert np.max(np.abs(a[key][ok] - g[key][ok])) < 1e-12 * sc, key
+
+
+def test_barycentre_of_symmetric_pairs_is_the_pixel_centre():
+    """Two galaxies at the same small distance on either side of a pixel
+    centre along a great circle have the centre as barycentre: pixB equals
+    the pixel variant with the same sums."""
+    nside = 32
+    rng = np.random.default_rng(42)
+    pix = np.sort(rng.choice(hp.npix(nside), 3000, replace=False))
+    c = hp.pix2vec(nside, pix)
+    t = np.cross(c, rng.normal(size=c.shape))
+    t /= np.linalg.norm(t, axis=1)[:, None]
+    eps = 0.15 * math.sqrt(4 * math.pi / hp.npix(nside))
+    v = np.concatenate([math.cos(eps) * c + math.sin(eps) * t, math.cos(eps) * c - math.sin(eps) * t])
+    ra = np.arctan2(v[:, 1], v[:, 0]) % (2 * math.pi)
+    dec = np.arcsin(np.clip(v[:, 2], -1, 1))
+    n = v.shape[0]
+    cat = {"ra": ra, "dec": dec, "g1": rng.normal(0, 0.3, n), "g2": rng.normal(0, 0.3, n), "w": np.ones(n)}
+    from oracle import binning as B
+
+    p_u, W, G1, G2, E2 = B.pixel_sums(nside, ra, dec, cat["g1"], cat["g2"], cat["w"])
+    assert np.array_equal(p_u, pix) and np.all(W == 2)
+    out = rng.choice(hp.npix(nside), 200, replace=False)
+    c_ra, c_dec = hp.pix2radec(nside, out)
+    th = 6 * DEG
+    a = A.aperture_mass_barycentre(cat, nside, c_ra, c_dec, th, F.POLY)
+    b = A.aperture_mass_pixel({"nside": nside, "pix": p_u, "W": W, "G1": G1, "G2": G2, "E2": E2}, out, th, F.POLY)
+    ok = ~(a["tie"] | b["tie"])
+    for key in ("M_E", "M_B", "sigma", "W", "N"):
+        sc = np.abs(b[key][ok]).max()
+        assert np.max(np.abs(a[key][ok] - b[key][ok])) < 1e-9 * sc, key
+
+
+def test_barycentre_across_ra_zero_and_at_the_pole():
+    """The barycentre of galaxies on both sides of RA = 0, or around a pole,
+    lies among them (a mean of RA would put it half a turn away)."""
+    nside = 16
+    pra, pdec = hp.pix2radec(nside, np.arange(hp.npix(nside)))
+    k = np.nonzero((pra == 0.0) & (np.abs(pdec) < 0.2))[0][0]   # a pixel centred on RA = 0
+    ra = np.array([0.01, 2 * math.pi - 0.01, 0.005, 2 * math.pi - 0.02])
+    dec = pdec[k] + np.array([0.01, -0.01, 0.0, 0.005])
+    assert np.all(hp.radec2pix(nside, ra, dec) == k)
+    src = A.barycentre_sources(nside, ra, dec, np.zeros(4), np.zeros(4))
+    assert src.ra.size == 1
+    d = min(src.ra[0], 2 * math.pi - src.ra[0])
+    assert d < 0.01 and abs(src.dec[0] - pdec[k]) < 0.01
+    # two galaxies of the first polar pixel, far apart in RA: the barycentre is
+    # the midpoint of the great-circle arc, nearer the pole than either galaxy
+    # (a mean of Dec would stay at their declination)
+    ra = np.array([0.1, 1.4])
+    dec = np.full(2, 0.5 * math.pi - 0.02)
+    assert np.all(hp.radec2pix(nside, ra, dec) == 0)
+    src = A.barycentre_sources(nside, ra, dec, np.zeros(2), np.zeros(2))
+    half = 0.5 * math.acos(np.clip(A.radec2vec(ra[:1], dec[:1]) @ A.radec2vec(ra[1:], dec[1:])[0], -1, 1)[0])
+    expect = math.acos(math.cos(0.02) / math.cos(half))   # colatitude of the arc's midpoint
+    assert src.ra.size == 1 and abs(src.ra[0] - 0.75) < 1e-12
+    assert abs((0.5 * math.pi - src.dec[0]) - expect) < 1e-9 and src.dec[0] > dec[0] + 1e-3
