@@ -164,6 +164,21 @@ int smart_bin_galaxies(smart_ctx ctx, int64_t n, const double* d_ra, const doubl
                        const float* d_g2, const float* d_w, int nside_bin, int want_pixel_sums, void* stream,
                        smart_data* out);
 
+/* Pixel-based variant with barycentre positions (Sect. 3.3, sphS_pixB):
+ * from a catalogue binned with want_pixel_sums = 1, a new data handle whose
+ * sources are its occupied pixels, each with the pixel's sums (shear sum,
+ * weight W, squared-shear sum E2; Sect. 3.2 step 2) placed at the
+ * barycentre of the pixel's galaxies, the normalised mean of their unit
+ * vectors (well defined across RA = 0 and at the poles). Plans on it are
+ * galaxy-variant FP32 plans (SMART_VAR_GALAXY, SMART_PREC_FP32_GEO64; others
+ * give SMART_EINVAL): every source within theta_ap of a centre counts, N
+ * counts occupied pixels, SMART_NORM_SUMMED_PIXCOUNT uses the pixel area of
+ * the binning NSIDE. The handle owns its memory (about 72 bytes per occupied
+ * pixel) and is released with smart_data_free; `galaxies` stays valid and
+ * unchanged. Synchronises `stream` once. SMART_EINVAL if `galaxies` has no
+ * pixel sums or is itself barycentre data. */
+int smart_barycentre_map(smart_data galaxies, void* stream, smart_data* out);
+
 /* Wrap an already binned shear map (Sect. 3.2 step 2) given as n entries of
  * strictly increasing RING pixels with their sums. The library copies it
  * into a dense ring-range layout it owns. Synchronises `stream` once.

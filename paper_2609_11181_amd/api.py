@@ -126,6 +126,12 @@ class Data:
         L.check(self.ctx.lib.smart_data_info(self.h, C.byref(n), C.byref(ns), C.byref(pf), C.byref(nd), C.byref(rb)))
         return {"n_gal": n.value, "nside": ns.value, "pix_first": pf.value, "n_dense": nd.value, "r_bin": rb.value}
 
+    def barycentre(self) -> "Data":
+        """sphS_pixB data: the occupied pixels at their galaxies' barycentres (see smart_barycentre_map)."""
+        h = C.c_void_p()
+        L.check(self.ctx.lib.smart_barycentre_map(self.h, _stream(self.ctx.device), C.byref(h)))
+        return Data(self.ctx, h)
+
     def sources(self):
         """Occupied source pixels of the pixel variant (device int64 tensor)."""
         n = C.c_int64()

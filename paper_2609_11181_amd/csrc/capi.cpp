@@ -160,6 +160,25 @@ int smart_bin_galaxies(smart_ctx ctx, int64_t n, const double* d_ra, const doubl
   return SMART_OK;
 }
 
+int smart_barycentre_map(smart_data galaxies, void* stream, smart_data* out) {
+  if (!galaxies || !out) return fail(SMART_EINVAL, "NULL data or out");
+  *out = nullptr;
+  if (galaxies->kind != 0 || galaxies->explicit_v || !galaxies->src_pix)
+    return fail(SMART_EINVAL, "barycentres need a binned catalogue with pixel sums (want_pixel_sums)");
+  int rc;
+  if ((rc = set_device(galaxies->ctx))) return rc;
+  smart_data d = new smart_data_s();
+  d->ctx = galaxies->ctx;
+  d->kind = 0;
+  rc = smart::barycentre_data(galaxies, (hipStream_t)stream, d);
+  if (rc) {
+    smart_data_free(d);
+    return rc;
+  }
+  *out = d;
+  return SMART_OK;
+}
+
 int smart_pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* d_ring_pix, const float* d_W,
                     const float* d_G1, const float* d_G2, const float* d_E2, void* stream, smart_data* out) {
   if (!ctx || !out) return fail(SMART_EINVAL, "NULL context or out");
@@ -254,6 +273,8 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
   if (variant != SMART_VAR_GALAXY && variant != SMART_VAR_PIXEL) return fail(SMART_EINVAL, "unknown variant");
   if (precision != SMART_PREC_FP64 && precision != SMART_PREC_FP32_GEO64)
     return fail(SMART_EINVAL, "plan precision must be SMART_PREC_FP64 or SMART_PREC_FP32_GEO64");
+  if (data && data->explicit_v && (variant != SMART_VAR_GALAXY || precision != SMART_PREC_FP32_GEO64))
+    return fail(SMART_EINVAL, "barycentre data takes galaxy-variant FP32 plans");
   if (!is_pow2(nside_out) || nside_out > kMaxNside) return fail(SMART_EINVAL, "nside_out must be a power of two <= 8192");
   if (n_out < 0 || n_out > 12LL * nside_out * nside_out * 4) return fail(SMART_EINVAL, "bad output count");
   if (n_out > 0 && !d_out_pix) return fail(SMART_EINVAL, "NULL output pixel list");
@@ -363,6 +384,7 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.out = d_out;
       a.norm = norm;
       a.scale = k;
+      a.explicit_v = d->explicit_v ? 1 : 0;
       e = launch_galaxy(a, s, p->precision, st);
     }
     if (e != hipSuccess) return fail(SMART_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -583,6 +605,7 @@ int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int nor
         a.out = stage;
         a.norm = norm;
         a.scale = 0;
+        a.explicit_v = d->explicit_v ? 1 : 0;
         e = launch_galaxy(a, s, p->precision, st);
       }
       if (e == hipSuccess)

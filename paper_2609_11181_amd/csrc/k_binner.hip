@@ -513,6 +513,93 @@ __global__ void k_average(const float4* sums, int64_t n, double omega, float4* a
 
 }  // namespace
 
+// sphS_pixB (Sect. 3.3): one group of kSumLanes lanes per occupied pixel
+// sums its galaxies' unit vectors and shear sums (FP64) and writes the pixel
+// as a source at the normalised mean position (the barycentre on the
+// sphere) with g = G / W, weight W and variance term E2.
+__global__ __launch_bounds__(kBlock) void k_barycentre(int64_t n_src, const int64_t* src_pix, const int64_t* off,
+                                                       const double4* P, const float4* G, double* ra, double* dec,
+                                                       float* g1, float* g2, float* w, float* v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / kSumLanes;
+  const int sub = (int)(t % kSumLanes);
+  if (i >= n_src) return;  // whole groups leave together
+  const int64_t pix = src_pix[i];
+  const int64_t a = off[pix], b = off[pix + 1];
+  double x = 0, y = 0, z = 0, W = 0, G1 = 0, G2 = 0, E2 = 0;
+  for (int64_t k = a + sub; k < b; k += kSumLanes) {
+    const double4 p = P[k];
+    const float4 g = G[k];
+    const double wk = g.z, gx = g.x, gy = g.y;
+    x += p.x;
+    y += p.y;
+    z += p.z;
+    W += wk;
+    G1 += wk * gx;
+    G2 += wk * gy;
+    E2 += wk * wk * (gx * gx + gy * gy);
+  }
+#pragma unroll
+  for (int m = kSumLanes / 2; m > 0; m >>= 1) {
+    x += __shfl_xor(x, m, kSumLanes);
+    y += __shfl_xor(y, m, kSumLanes);
+    z += __shfl_xor(z, m, kSumLanes);
+    W += __shfl_xor(W, m, kSumLanes);
+    G1 += __shfl_xor(G1, m, kSumLanes);
+    G2 += __shfl_xor(G2, m, kSumLanes);
+    E2 += __shfl_xor(E2, m, kSumLanes);
+  }
+  if (sub != 0) return;
+  double phi = atan2(y, x);
+  if (phi < 0.0) phi += 2.0 * M_PI;
+  ra[i] = phi;
+  dec[i] = atan2(z, sqrt(x * x + y * y));
+  g1[i] = W != 0.0 ? (float)(G1 / W) : 0.f;
+  g2[i] = W != 0.0 ? (float)(G2 / W) : 0.f;
+  w[i] = (float)W;
+  v[i] = (float)E2;
+}
+
+__global__ void k_set_v(int64_t n, const int64_t* order, const float* v, float4* G) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) G[k].w = v[order[k]];
+}
+
+int barycentre_data(smart_data src, hipStream_t st, smart_data out) {
+  const int64_t n = src->n_src;
+  double *ra = nullptr, *dec = nullptr;
+  float* cols = nullptr;  // g1, g2, w, v
+  if (n > 0 && (scratch_alloc(&ra, sizeof(double) * n, st) != hipSuccess ||
+                scratch_alloc(&dec, sizeof(double) * n, st) != hipSuccess ||
+                scratch_alloc(&cols, sizeof(float) * 4 * n, st) != hipSuccess)) {
+    scratch_free(ra, st);
+    scratch_free(dec, st);
+    set_error("out of device memory (barycentres)");
+    return SMART_ENOMEM;
+  }
+  if (n > 0) {
+    hipLaunchKernelGGL(k_barycentre, dim3(grid_of(n * kSumLanes)), dim3(kBlock), 0, st, n, src->src_pix,
+                       src->offsets, src->P, src->G, ra, dec, cols, cols + n, cols + 2 * n, cols + 3 * n);
+    if (hipGetLastError() != hipSuccess) {
+      set_error("barycentre kernel failed to launch");
+      return SMART_EDEVICE;
+    }
+  }
+  int rc = bin_galaxies(src->ctx, n, ra, dec, cols, cols + n, cols + 2 * n, src->nside, 0, st, out);
+  if (rc == SMART_OK && n > 0) {
+    hipLaunchKernelGGL(k_set_v, dim3(grid_of(n)), dim3(kBlock), 0, st, n, out->order, cols + 3 * n, out->G);
+    if (hipGetLastError() != hipSuccess) {
+      set_error("barycentre kernel failed to launch");
+      rc = SMART_EDEVICE;
+    }
+  }
+  out->explicit_v = true;
+  scratch_free(ra, st);
+  scratch_free(dec, st);
+  scratch_free(cols, st);
+  return rc;
+}
+
 hipError_t launch_pixel_sums(smart_data d, const float* u, float4* sums, hipStream_t st) {
   if (d->n_dense <= 0) return hipSuccess;
   const dim3 grid(grid_of(d->n_dense * kSumLanes)), block(kBlock);

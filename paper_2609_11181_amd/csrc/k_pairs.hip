@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
           const float w = G.z;
           const double wd = (double)w;
           accumulate(q * c2p, q * s2p, (float)q, wd * (double)G.x, wd * (double)G.y, w,
-                     w * w * fmaf(G.x, G.x, G.y * G.y), 1, tot, acc);
+                     a.explicit_v ? G.w : w * w * fmaf(G.x, G.x, G.y * G.y), 1, tot, acc);
           if (++nacc == kChunk) {
             tot.add(acc);
             acc = Acc32();

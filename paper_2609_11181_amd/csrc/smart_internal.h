@@ -100,6 +100,10 @@ struct smart_data_s {
   // averaged approach: (G1 c, G2 c, E2 c^2, W) with c = Omega_pix / W (zero
   // where W = 0), built at the first averaged call
   float4* avg = nullptr;
+  // barycentre data (sphS_pixB): each "galaxy" is an occupied pixel of a
+  // catalogue at its galaxies' barycentre, with G = (G1/W, G2/W, W, E2):
+  // the pair kernels take V from G.w instead of w^2 |g|^2
+  bool explicit_v = false;
   // prefix sums over the dense range: wn[i] = (sum of W, number of pixels
   // with W > 0) over dense pixels [0, i); n_dense + 1 entries
   double2* wn = nullptr;
@@ -221,6 +225,7 @@ struct GalaxyArgs {
   void* out;
   int norm;
   int scale;
+  int explicit_v;  // V of a source is G.w (barycentre data)
 };
 
 // Belt tables of one scale (built by k_belt.hip): for every belt ring that
@@ -318,6 +323,8 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
 int ensure_temp(smart_ctx ctx, size_t bytes);
 // Builds d->wn from d->sums (smart_data_s::wn).
 int build_wn_prefix(smart_ctx ctx, smart_data d, hipStream_t st);
+// sphS_pixB: the barycentre data of a binned catalogue with pixel sums
+int barycentre_data(smart_data src, hipStream_t st, smart_data out);
 // the averaged records of a map (built once, synchronising `st`)
 int ensure_averaged(smart_data d, hipStream_t st);
 // the records the pair kernels read under normalisation `norm`

@@ -18,7 +18,7 @@ NORM_SUMMED_CAP, NORM_SUMMED_PIXCOUNT, NORM_RAW, NORM_AVERAGED = 0, 1, 2, 3
 EXPORTS = [
     "smart_init", "smart_finalize", "smart_last_error", "smart_version", "smart_filter_define",
     "smart_filter_table", "smart_bin_galaxies", "smart_pixel_map", "smart_data_info", "smart_data_sources",
-    "smart_data_export",
+    "smart_data_export", "smart_barycentre_map",
     "smart_data_free", "smart_plan_create", "smart_run", "smart_last_pairs", "smart_plan_free",
     "smart_noise_batch", "smart_noise_galaxy_batch", "smart_mixed_batch", "smart_plan_tiles",
     "smart_plan_set_timing", "smart_plan_kernel_ms", "smart_autotune",
@@ -56,6 +56,7 @@ _SIGS = {
     "smart_plan_free": (None, [_vp]),
     "smart_noise_batch": (_int, [_vp, _vp, _int, _int, _int, _vp, _vp]),
     "smart_noise_galaxy_batch": (_int, [_vp, _vp, _int, _int, _vp, _vp]),
+    "smart_barycentre_map": (_int, [_vp, _vp, _vp]),
     "smart_mixed_batch": (_int, [_vp, _int, C.POINTER(_vp), C.POINTER(_int), C.POINTER(_vp), _vp]),
     "smart_plan_tiles": (_int, [_vp, _int, C.POINTER(_int), C.POINTER(_int), _vp, _vp, _vp]),
     "smart_plan_set_timing": (_int, [_vp, _int]),
