@@ -211,6 +211,34 @@ def batched_leg(ctx, args):
     torch.cuda.synchronize()
     t_g = ev0.elapsed_time(ev1) / 1e3
     del ug, outg
+    # sphS_pixB: the same catalogue's occupied pixels at their barycentres,
+    # galaxy-variant FP32 plan with the pixel centres as outputs
+    ev0.record(stream)
+    bdata = data.barycentre()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    bary_build_ms = ev0.elapsed_time(ev1)
+    bplan = ctx.plan(bdata, L.VAR_GALAXY, 2048, src, scales, [fid] * 3)
+    bout = bplan.run(L.NORM_SUMMED_PIXCOUNT)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(3):
+        bplan.run(L.NORM_SUMMED_PIXCOUNT, bout)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    bary_ms = ev0.elapsed_time(ev1) / 3
+    bary_pairs = bplan.last_pairs()
+    barycentre = {
+        "workload": f"sphS_pixB: {n_src} occupied pixels at their barycentres, outputs at the pixel centres, "
+                    "3 scales (5/10/20 arcmin), tanh filter",
+        "build_ms": bary_build_ms,
+        "run_ms": bary_ms,
+        "pairs": bary_pairs,
+        "pair_evals_per_s": bary_pairs / (bary_ms / 1e3),
+    }
+    bplan.free()
+    bdata.free()
+    del bout
     maps_b = 3 * R / t_b
     maps_p = 3 * Rp / t_p
     flops = 8.0 * pairs1 * R  # one complex multiply-add per pair and realisation
@@ -231,6 +259,7 @@ def batched_leg(ctx, args):
                  "frac": flops / t_b / 2.5e15,
                  "note": "algorithmic 8 flop per (pair, realisation); split-BF16 issues 3 products per term"},
         "binning_ms": bin_ms,
+        "barycentre": barycentre,
     }
     if not args.no_cpu:
         res.update(batched_accuracy(data, src, u, out, outp, scales, R))
