@@ -175,6 +175,70 @@ def aperture_mass_barycentre(cat, nside, c_ra, c_dec, theta_ap, filter_kind, nor
     return out
 
 
+def aperture_mass_posB(cat, nside, c_ra, c_dec, theta_ap, filter_kind, norm=NORM_SUMMED_CAP, filter_params=None):
+    """sphS_posB (Sect. 3.4, catalogue partitioned by HEALPix pixel): the
+    aperture is retrieved as the pixels whose centres lie within theta_ap of
+    the aperture centre, and every galaxy of those pixels is a member (W, V,
+    N); its filter is evaluated at its own position, q(theta_i / theta_ap),
+    and is zero beyond theta_ap (the filter's support). Galaxies inside the
+    aperture in pixels centred outside it are not counted."""
+    ra = np.asarray(cat["ra"], np.float64)
+    dec = np.asarray(cat["dec"], np.float64)
+    src = galaxy_sources(ra, dec, cat["g1"], cat["g2"], cat.get("w"))
+    src_vec = src.vec
+    qfun = q_of(filter_kind, filter_params)
+    c_ra = np.asarray(c_ra, np.float64)
+    c_dec = np.asarray(c_dec, np.float64)
+    n_cen = c_ra.size
+    c_vec = radec2vec(c_ra, c_dec)
+    C_ap = 4.0 * math.sin(0.5 * theta_ap) ** 2
+    gpix = hp.radec2pix(nside, ra, dec)
+    order = np.argsort(gpix, kind="stable")
+    occ, first, count = np.unique(gpix[order], return_index=True, return_counts=True)
+    pc = hp.pix2vec(nside, occ)
+    tree = cKDTree(pc)
+    lists = tree.query_ball_point(c_vec, 2.0 * math.sin(0.5 * theta_ap) * (1.0 + 1e-9) + 1e-15)
+    cc, pp = [], []
+    for i, lst in enumerate(lists):
+        cc.append(np.full(len(lst), i, np.int64))
+        pp.append(np.asarray(lst, np.int64))
+    cc = np.concatenate(cc)
+    pp = np.concatenate(pp)
+    d = c_vec[cc] - pc[pp]
+    pc2 = np.einsum("ij,ij->i", d, d)
+    tie_pix = np.abs(pc2 - C_ap) <= TIE_REL * C_ap
+    keep = pc2 < C_ap
+    tie = np.bincount(cc[tie_pix], minlength=n_cen) > 0
+    cc, pp = cc[keep], pp[keep]
+    # every galaxy of every retrieved pixel
+    n_g = count[pp]
+    ci = np.repeat(cc, n_g)
+    start = np.repeat(first[pp], n_g)
+    within = np.arange(ci.size) - np.repeat(np.cumsum(n_g) - n_g, n_g)
+    si = order[start + within]
+    d = c_vec[ci] - src_vec[si]
+    c2 = np.einsum("ij,ij->i", d, d)
+    tie |= np.bincount(ci[np.abs(c2 - C_ap) <= TIE_REL * C_ap], minlength=n_cen) > 0
+    theta = 2.0 * np.arcsin(np.sqrt(c2) * 0.5)
+    q = np.where(c2 < C_ap, qfun(np.minimum(theta / theta_ap, 1.0)), 0.0)
+    psi = polar_angle(src.ra[si], src.dec[si], c_ra[ci], c_dec[ci])
+    gp, gx = tangential_cross(src.A1[si], src.A2[si], psi)
+    at_centre = c2 < COINCIDENT_C2
+    gp = np.where(at_centre, 0.0, gp)
+    gx = np.where(at_centre, 0.0, gx)
+    sums = {
+        "S_E": np.bincount(ci, weights=q * gp, minlength=n_cen),
+        "S_B": np.bincount(ci, weights=q * gx, minlength=n_cen),
+        "W": np.bincount(ci, weights=src.Wsrc[si], minlength=n_cen),
+        "V": np.bincount(ci, weights=q * q * src.Vsrc[si], minlength=n_cen),
+        "N": np.bincount(ci, weights=src.Nsrc[si], minlength=n_cen),
+    }
+    out = normalise(sums, theta_ap, norm)
+    out["tie"] = tie
+    out["pairs"] = int(ci.size)
+    return out
+
+
 def _pair_sums(src: Sources, src_vec, cand_centre, cand_src, c_ra, c_dec, c_vec, theta_ap, qfun, n_cen):
     """Sums over the candidate pairs (centre index, source index) that pass
     the FP64 membership test."""

@@ -610,3 +610,64 @@ def test_barycentre_across_ra_zero_and_at_the_pole():
     expect = math.acos(math.cos(0.02) / math.cos(half))   # colatitude of the arc's midpoint
     assert src.ra.size == 1 and abs(src.ra[0] - 0.75) < 1e-12
     assert abs((0.5 * math.pi - src.dec[0]) - expect) < 1e-9 and src.dec[0] > dec[0] + 1e-3
+
+
+# ----------------------------------------------------------------------------
+# sphS_posB: pixels retrieved by their centres, galaxies at their own positions
+# ----------------------------------------------------------------------------
+
+def test_posB_with_galaxies_at_pixel_centres_is_the_brute_force():
+    """A galaxy at its pixel's centre is inside the aperture exactly when the
+    centre is: posB equals the galaxy variant."""
+    nside = 64
+    rng = np.random.default_rng(51)
+    pix = np.sort(rng.choice(hp.npix(nside), 6000, replace=False))
+    pix = np.repeat(pix, rng.integers(1, 4, pix.size))       # 1-3 galaxies per pixel
+    ra, dec = hp.pix2radec(nside, pix)
+    cat = {"ra": ra, "dec": dec, "g1": rng.normal(0, 0.3, pix.size), "g2": rng.normal(0, 0.3, pix.size),
+           "w": rng.uniform(0.5, 1.5, pix.size)}
+    out = rng.choice(hp.npix(nside), 200, replace=False)
+    c_ra, c_dec = hp.pix2radec(nside, out)
+    th = 5 * DEG
+    a = A.aperture_mass_posB(cat, nside, c_ra, c_dec, th, F.TANH)
+    g = A.aperture_mass_galaxy(cat, c_ra, c_dec, th, F.TANH)
+    ok = ~(a["tie"] | g["tie"])
+    for key in ("M_E", "M_B", "sigma", "W", "N"):
+        sc = np.abs(g[key][ok]).max()
+        assert np.max(np.abs(a[key][ok] - g[key][ok])) < 1e-12 * sc, key
+
+
+def test_posB_boundary_galaxies():
+    """Membership follows the pixel centre: a galaxy outside the aperture in a
+    pixel centred inside it counts in W and N with a zero filter; a galaxy
+    inside the aperture in a pixel centred outside it does not count. The
+    member count differs from the brute force only by galaxies of pixels
+    that cross the aperture's edge."""
+    nside = 32
+    th = 6 * DEG
+    rng = np.random.default_rng(52)
+    n = 40000
+    z = rng.uniform(math.cos(15 * DEG), 1.0, n)
+    phi = rng.uniform(0, 2 * math.pi, n)
+    ra = phi
+    dec = np.arcsin(z)
+    cat = {"ra": ra, "dec": dec, "g1": rng.normal(0, 0.3, n), "g2": rng.normal(0, 0.3, n)}
+    c_ra, c_dec = np.array([0.3]), np.array([0.5 * math.pi - 0.05])
+    a = A.aperture_mass_posB(cat, nside, c_ra, c_dec, th, F.POLY, norm=A.NORM_RAW)
+    g = A.aperture_mass_galaxy(cat, c_ra, c_dec, th, F.POLY, norm=A.NORM_RAW)
+    cv = A.radec2vec(c_ra, c_dec)[0]
+    gv = A.radec2vec(ra, dec)
+    gpix = hp.radec2pix(nside, ra, dec)
+    C = 4 * math.sin(0.5 * th) ** 2
+    pin = np.sum((hp.pix2vec(nside, gpix) - cv) ** 2, axis=1) < C
+    gin = np.sum((gv - cv) ** 2, axis=1) < C
+    assert a["N"][0] == pin.sum() and g["N"][0] == gin.sum()
+    assert (pin & ~gin).sum() > 0 and (gin & ~pin).sum() > 0
+    # E sums: the same filter on the galaxies inside both, nothing from the others
+    both = A.aperture_mass_galaxy({k: v[pin & gin] for k, v in cat.items()}, c_ra, c_dec, th, F.POLY,
+                                  norm=A.NORM_RAW)
+    assert abs(a["M_E"][0] - both["M_E"][0]) < 1e-12 * abs(g["M_E"][0]) + 1e-15
+    # the boundary pixels bound the difference: half a pixel diagonal around the edge
+    r = np.arccos(np.clip(gv @ cv, -1, 1))
+    edge = np.abs(r - th) < 2.0 * math.sqrt(4 * math.pi / hp.npix(nside))
+    assert np.all(edge[pin != gin])
