@@ -89,8 +89,16 @@ enum {
 /* Variants (Table 1 of the paper).                                           */
 enum {
   SMART_VAR_GALAXY = 0, /* brute force on galaxy positions (sphS_pos)         */
-  SMART_VAR_PIXEL = 1   /* shear summed per pixel, filter at pixel centres
+  SMART_VAR_PIXEL = 1,  /* shear summed per pixel, filter at pixel centres
                            (sphS_pix)                                        */
+  SMART_VAR_GALAXY_POSB = 2 /* catalogue partitioning (sphS_posB, Sect. 3.4):
+                           the aperture is the binning pixels whose centres
+                           lie within theta_ap of the centre; every galaxy
+                           of those pixels counts in W, V and N, with its
+                           filter at its own position (zero beyond
+                           theta_ap). FP32 plans on binned catalogues only;
+                           the plan behaves as a galaxy-variant plan
+                           otherwise (smart_noise_galaxy_batch included)  */
 };
 
 /* Arithmetic of the pair sums.                                               */

@@ -270,7 +270,11 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
   if (!ctx || !data || !out) return fail(SMART_EINVAL, "NULL context, data or out");
   *out = nullptr;
   if (data->ctx != ctx) return fail(SMART_EINVAL, "data belongs to another context");
-  if (variant != SMART_VAR_GALAXY && variant != SMART_VAR_PIXEL) return fail(SMART_EINVAL, "unknown variant");
+  if (variant != SMART_VAR_GALAXY && variant != SMART_VAR_PIXEL && variant != SMART_VAR_GALAXY_POSB)
+    return fail(SMART_EINVAL, "unknown variant");
+  const bool posb = variant == SMART_VAR_GALAXY_POSB;
+  if (posb && precision != SMART_PREC_FP32_GEO64) return fail(SMART_EINVAL, "sphS_posB plans are FP32 plans");
+  if (posb) variant = SMART_VAR_GALAXY;
   if (precision != SMART_PREC_FP64 && precision != SMART_PREC_FP32_GEO64)
     return fail(SMART_EINVAL, "plan precision must be SMART_PREC_FP64 or SMART_PREC_FP32_GEO64");
   if (data && data->explicit_v && (variant != SMART_VAR_GALAXY || precision != SMART_PREC_FP32_GEO64))
@@ -301,6 +305,7 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
   p->ctx = ctx;
   p->data = data;
   p->variant = variant;
+  p->posb = posb;
   p->precision = precision;
   p->nside_out = nside_out;
   p->n_out = n_out;
@@ -385,6 +390,7 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.norm = norm;
       a.scale = k;
       a.explicit_v = d->explicit_v ? 1 : 0;
+      a.posb = p->posb ? 1 : 0;
       e = launch_galaxy(a, s, p->precision, st);
     }
     if (e != hipSuccess) return fail(SMART_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -606,6 +612,7 @@ int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int nor
         a.norm = norm;
         a.scale = 0;
         a.explicit_v = d->explicit_v ? 1 : 0;
+        a.posb = p->posb ? 1 : 0;
         e = launch_galaxy(a, s, p->precision, st);
       }
       if (e == hipSuccess)

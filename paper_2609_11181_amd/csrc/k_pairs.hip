@@ -200,12 +200,14 @@ __global__ __launch_bounds__(kBlock) void k_pixel_f64(PixelArgs a, ScaleArgs s) 
 
 // ---- galaxy variant -----------------------------------------------------------
 
-// Catalogue slices of one partition ring that may hold members: the ring
-// window for radius theta_ap + r_bin, widened by one pixel, split at the
-// ring seam into at most two index ranges.
-__device__ __forceinline__ int ring_slices(const Ring& Q, int64_t jlo, int cnt, int64_t* ja, int64_t* jb) {
+// Catalogue slices of one partition ring: the ring window (radius theta_ap
+// + r_bin, widened by `widen` pixels on each side as a margin when every
+// galaxy is tested; exact, widen = 0, when the window is the membership),
+// split at the ring seam into at most two index ranges.
+__device__ __forceinline__ int ring_slices(const Ring& Q, int64_t jlo, int cnt, int widen, int64_t* ja,
+                                           int64_t* jb) {
   const int nq = Q.n;
-  int64_t l = jlo - 1, h = jlo + cnt;  // widened
+  int64_t l = jlo - widen, h = jlo + cnt - 1 + widen;
   if (h - l + 1 >= nq) {
     ja[0] = 0;
     jb[0] = nq - 1;
@@ -256,9 +258,13 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
   double sphi, cphi;
   sincospi((double)ip2 / (double)R.n, &sphi, &cphi);  // phi_p = pi ip2 / n
   const double px = sp * cphi, py = sp * sphi, pz = zp;
-  const double rad = s.theta_ap + a.r_bin * (1.0 + 1e-9) + 1e-12;
+  // candidate pixels: those within theta_ap + r_bin (every galaxy within
+  // theta_ap lies in one), or, for sphS_posB, exactly the pixels whose
+  // centres lie within theta_ap (all of their galaxies are members)
+  const bool posb = a.posb != 0;
+  const double rad = posb ? s.theta_ap * (1.0 + 1e-9) + 1e-12 : s.theta_ap + a.r_bin * (1.0 + 1e-9) + 1e-12;
   const double sh = sin(0.5 * rad);
-  const double Cw = 4.0 * sh * sh;
+  const double Cw = posb ? s.C_ap : 4.0 * sh * sh;
   int lo, hi;
   ring_span(a.nside_bin, atan2(sp, zp), rad, &lo, &hi);
 
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
     int cnt;
     if (!ring_window(zp, sp, ip2, R.n, Q, Cw, &jlo, &cnt)) continue;
     int64_t ja[2], jb[2];
-    const int ns = ring_slices(Q, jlo, cnt, ja, jb);
+    const int ns = ring_slices(Q, jlo, cnt, posb ? 0 : 1, ja, jb);
     for (int t = 0; t < ns; ++t) {
       const int64_t g0 = a.offsets[Q.first + ja[t]];
       const int64_t g1 = a.offsets[Q.first + jb[t] + 1];
@@ -279,7 +285,8 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
         const double4 P = a.P[g];
         const double dx = px - P.x, dy = py - P.y, dz = pz - P.z;
         const double c2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        if (c2 < s.C_ap) {
+        const bool inside = c2 < s.C_ap;
+        if (inside || posb) {
           const float4 G = a.G[g];
           // tangent-plane components at the galaxy, unnormalised (both
           // scaled by cos dec, which cancels in the rotation):
@@ -301,7 +308,9 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
           const double rc0 = (double)__builtin_amdgcn_rsqf((float)c2);
           const double rc = rc0 * fma(-0.5 * c2, rc0 * rc0, 1.5);
           const double cd = c2 >= (double)kCoincidentS2 ? c2 * rc : 0.0;
-          const double q = filter_q<TABLE>(theta_ratio<BIG>(cd, c2, cp), tab);
+          // beyond theta_ap (sphS_posB members only) the filter is zero; the
+          // table lookup clamps its index, so the evaluation stays in range
+          const double q = inside ? filter_q<TABLE>(theta_ratio<BIG>(cd, c2, cp), tab) : 0.0;
           const float w = G.z;
           const double wd = (double)w;
           accumulate(q * c2p, q * s2p, (float)q, wd * (double)G.x, wd * (double)G.y, w,
@@ -342,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f64(GalaxyArgs a, ScaleArgs s
     int cnt;
     if (!ring_window(zp, sp, ip2, R.n, Q, Cw, &jlo, &cnt)) continue;
     int64_t ja[2], jb[2];
-    const int ns = ring_slices(Q, jlo, cnt, ja, jb);
+    const int ns = ring_slices(Q, jlo, cnt, 1, ja, jb);
     for (int t = 0; t < ns; ++t) {
       const int64_t g0 = a.offsets[Q.first + ja[t]];
       const int64_t g1 = a.offsets[Q.first + jb[t] + 1];

@@ -121,6 +121,7 @@ struct smart_plan_s {
   smart_ctx ctx = nullptr;
   smart_data data = nullptr;
   int variant = 0;
+  bool posb = false;  // galaxy variant with pixel-centre membership (sphS_posB)
   int precision = 0;
   int nside_out = 0;
   int64_t n_out = 0;
@@ -226,6 +227,7 @@ struct GalaxyArgs {
   int norm;
   int scale;
   int explicit_v;  // V of a source is G.w (barycentre data)
+  int posb;        // membership by the binning pixel's centre (sphS_posB)
 };
 
 // Belt tables of one scale (built by k_belt.hip): for every belt ring that

@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libsmartap.so")
 # enums of include/smartap.h
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5
 FILTER_POLY, FILTER_TANH, FILTER_TABLE = 0, 1, 2
-VAR_GALAXY, VAR_PIXEL = 0, 1
+VAR_GALAXY, VAR_PIXEL, VAR_GALAXY_POSB = 0, 1, 2
 PREC_FP64, PREC_FP32_GEO64, PREC_BF16X3 = 0, 1, 2
 NORM_SUMMED_CAP, NORM_SUMMED_PIXCOUNT, NORM_RAW, NORM_AVERAGED = 0, 1, 2, 3
 
