@@ -107,8 +107,16 @@ enum {
   SMART_PREC_FP32_GEO64 = 1,  /* membership, geometry, spin-2 rotation and
                                  E/B sums in FP64; filter table, W and V
                                  sums in FP32; outputs float                */
-  SMART_PREC_BF16X3 = 2       /* batched realisations only: split-BF16 MFMA
+  SMART_PREC_BF16X3 = 2,      /* batched realisations only: split-BF16 MFMA
                                  with FP32 accumulation                      */
+  SMART_PREC_FP32_OUT64 = 3   /* the arithmetic of SMART_PREC_FP32_GEO64
+                                 (same kernels, same FP64 E/B sums), with
+                                 the maps of smart_run and smart_mixed_batch
+                                 written as double: an FP32 store rounds a
+                                 map value to 2^-24 of itself, which at a
+                                 peak of 20 map RMS is 1.2e-6 of the RMS;
+                                 the plan is an FP32 plan everywhere else
+                                 (noise maps stay float)                    */
 };
 
 enum {
@@ -143,7 +151,7 @@ const char* smart_last_error(void);
 const char* smart_version(void);
 
 /* Define a filter (Sect. 3.1 step 3). Builds, on the host in FP64, a
- * piecewise-cubic table in x with 2048 intervals (error below 1e-8 of the
+ * piecewise-cubic table in x with 2048 intervals (error below 3e-9 of the
  * filter maximum for the built-in kinds) and uploads it. Synchronous.
  * filter_id receives a small non-negative integer. */
 int smart_filter_define(smart_ctx ctx, int kind, const double* h_params, int n_params, int* filter_id);
@@ -152,6 +160,27 @@ int smart_filter_define(smart_ctx ctx, int kind, const double* h_params, int n_p
  * (cubic coefficients c0..c3 in the local coordinate f in [0,1) of each
  * interval); n_intervals receives the count. h_coef may be NULL to query. */
 int smart_filter_table(smart_ctx ctx, int filter_id, float* h_coef, int* n_intervals);
+
+/* The cubic pieces the kernels evaluate (Sect. 3.1 step 3), as stored:
+ * h_coef receives 4 * n_pieces doubles (c0 in FP64; c1, c2, c3 FP32 values
+ * widened), q = c0 + f (c1 + f (c2 + f c3)) with f in [0, 1) the local
+ * coordinate of the piece.
+ *   theta_ap = 0 : the table in x = theta / theta_ap, n_pieces = 2048 uniform
+ *                  pieces on [0, 1) (belt tables, batched noise walk, galaxy
+ *                  kernels)
+ *   theta_ap > 0 : the table of the general pixel walk for that aperture,
+ *                  uniform in y = sin(theta): n_pieces = 2049, piece i on
+ *                  [i, i + 1) sin(theta_ap) / 2048, the last one the constant
+ *                  q(1-) (built on the host, as the walk builds it)
+ * Each piece interpolates the filter at its four Chebyshev nodes: below
+ * 3e-9 of the maximum for the built-in filters. For table filters the x
+ * table reproduces the Catmull-Rom interpolant up to coefficient rounding
+ * when (n_params - 1) divides 2048; a table in y adds the interpolation
+ * error of a piece that holds a spline knot (a jump of the second
+ * derivative), small when the samples resolve the filter. h_coef may be
+ * NULL to query n_pieces.
+ * theta_ap in [0, 0.25]. Synchronous. */
+int smart_filter_pieces(smart_ctx ctx, int filter_id, double theta_ap, double* h_coef, int* n_pieces);
 
 /* ------------------------------------------------------------------------ */
 /* Input data                                                                */
@@ -235,7 +264,8 @@ void smart_data_free(smart_data data);
  *   variant   : SMART_VAR_GALAXY (data from smart_bin_galaxies) or
  *               SMART_VAR_PIXEL (pixel sums; nside_out must equal the
  *               data's NSIDE)
- *   precision : SMART_PREC_FP64 or SMART_PREC_FP32_GEO64
+ *   precision : SMART_PREC_FP64, SMART_PREC_FP32_GEO64 or
+ *               SMART_PREC_FP32_OUT64
  *   d_out_pix : n_out int64 RING pixels (copied; any order, duplicates ok)
  *   theta_ap  : 0 < theta_ap <= 0.25 rad (about 14.3 degrees)
  * The plan references `data`, which must outlive it. Synchronises `stream`
@@ -256,8 +286,9 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
                       int precision, void* stream, smart_plan* out);
 
 /* Compute the maps. out is a device buffer of n_scales * 5 * n_out values,
- * float for SMART_PREC_FP32_GEO64 and double for SMART_PREC_FP64, laid out
- * [scale][channel][output] with channels SMART_CH_*. */
+ * float for SMART_PREC_FP32_GEO64 and double for SMART_PREC_FP64 and
+ * SMART_PREC_FP32_OUT64, laid out [scale][channel][output] with channels
+ * SMART_CH_*. */
 int smart_run(smart_plan plan, int norm, void* d_out, void* stream);
 /* With norm = SMART_NORM_AVERAGED the first call on a map also builds the
  * map's averaged records (G_j Omega_pix / W_j, E2_j (Omega_pix / W_j)^2:
@@ -325,6 +356,35 @@ int smart_plan_kernel_ms(smart_plan plan, int scale, double* belt_ms, double* ge
  * The plan must be a pixel-variant FP32 plan. */
 int smart_noise_batch(smart_plan plan, const float* d_u, int n_real, int norm, int precision, float* d_out,
                       void* stream);
+
+/* The realisation angles of smart_noise_seeded (random orientations,
+ * Sect. 1): d_u[r][j] for r < n_real, j < n_src is the angle fraction of
+ * source j in realisation r_first + r: k = word j of the Philox4x64-10
+ * stream keyed by (seed, r_first + r) (Salmon et al. 2011; word j is output
+ * j mod 4 of the block at counter (j / 4 + 1, 0, 0, 0), the stream that
+ * numpy.random.Philox(key=[seed, r]).random_raw() draws), and
+ * u = ((k >> 41) + 0.5) 2^-23, a float in (0, 1); the rotation angle is pi u.
+ * d_u holds n_real * n_src floats. Asynchronous on `stream`. */
+int smart_noise_angles(smart_ctx ctx, uint64_t seed, int64_t r_first, int n_real, int64_t n_src, float* d_u,
+                       void* stream);
+
+/* smart_noise_batch with the angles drawn on the device (those of
+ * smart_noise_angles for (seed, r_first, n_real, n_src of the map)), in
+ * chunks of 32 realisations, so no angle array is held by the caller and
+ * realisations can be computed in any split over calls.
+ *   moments_only = 0 : d_out float [n_scales][n_real][2][n_out], realisation
+ *                      r_first + r at index r (as smart_noise_batch)
+ *   moments_only = 1 : d_out double [n_scales][4][n_out]; the call ADDS the
+ *                      sums over its realisations of M_E, M_E^2, M_B, M_B^2
+ *                      (zero d_out before the first call; calls over
+ *                      disjoint realisation ranges accumulate), so the mean
+ *                      and variance per pixel need no map per realisation
+ *                      (the BF16X3 path updates them in its epilogue)
+ *   precision    : SMART_PREC_FP32_GEO64 or SMART_PREC_BF16X3
+ * The plan must be a pixel-variant FP32 plan. Allocates n_src x 32 floats of
+ * stream-ordered scratch for the angles of a chunk. */
+int smart_noise_seeded(smart_plan plan, uint64_t seed, int64_t r_first, int n_real, int norm, int precision,
+                       int moments_only, void* d_out, void* stream);
 
 /* Galaxy-level shape-noise realisations (the random orientations of the
  * individual galaxies, Sect. 1 and Sect. 5.3): in realisation r galaxy i's

@@ -23,6 +23,23 @@ def _ptr(t):
     return C.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _buf(t, device, dtype, numel, what):
+    """Pointer of a caller buffer that a kernel reads or writes whole: it
+    must be a contiguous tensor on the context's device with the element
+    type and at least the element count the call uses."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if t.device != device:
+        raise ValueError(f"{what} is on {t.device}, the context is on {device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{what} holds {t.numel()} elements, the call uses {numel}")
+    return _ptr(t)
+
+
 def _dev(t, device, dtype):
     t = torch.as_tensor(t)
     return t.to(device=device, dtype=dtype).contiguous()
@@ -69,6 +86,16 @@ class Context:
         L.check(self.lib.smart_filter_table(self.h, fid, buf, C.byref(n)))
         return np.frombuffer(buf, dtype=np.float32).reshape(n.value, 4).copy()
 
+    def filter_pieces(self, fid: int, theta_ap: float = 0.0) -> np.ndarray:
+        """The filter's cubic pieces as the kernels read them ([n, 4] float64;
+        see smart_filter_pieces): the table in x for theta_ap = 0, else the
+        general walk's table in sin(theta) for that aperture."""
+        n = C.c_int()
+        L.check(self.lib.smart_filter_pieces(self.h, fid, float(theta_ap), None, C.byref(n)))
+        buf = (C.c_double * (4 * n.value))()
+        L.check(self.lib.smart_filter_pieces(self.h, fid, float(theta_ap), buf, C.byref(n)))
+        return np.frombuffer(buf, dtype=np.float64).reshape(n.value, 4).copy()
+
     # -- data ----------------------------------------------------------------
     def bin_galaxies(self, ra, dec, g1, g2, w=None, nside_bin=4096, pixel_sums=False) -> "Data":
         d = self.device
@@ -104,11 +131,22 @@ class Context:
                                            len(thetas), th, fi, precision, _stream(d), C.byref(h)))
         return Plan(self, h, data, out_pix.numel(), len(thetas), precision)
 
+    def noise_angles(self, seed: int, r_first: int, n_real: int, n_src: int, out=None):
+        """Counter-based realisation angles (see smart_noise_angles): [n_real][n_src] float32."""
+        if out is None:
+            out = torch.empty(n_real, n_src, dtype=torch.float32, device=self.device)
+        p = _buf(out, self.device, torch.float32, n_real * n_src, "out")
+        L.check(self.lib.smart_noise_angles(self.h, seed, r_first, n_real, n_src, p, _stream(self.device)))
+        return out
+
     def mixed_batch(self, plans, norms, outs):
         n = len(plans)
+        if len(norms) != n or len(outs) != n:
+            raise ValueError("plans, norms and outs must have the same length")
         ph = (C.c_void_p * n)(*[p.h.value for p in plans])
         nh = (C.c_int * n)(*norms)
-        oh = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        oh = (C.c_void_p * n)(*[_buf(o, self.device, p.out_dtype, p.n_scales * 5 * p.n_out, "out").value or 0
+                                for p, o in zip(plans, outs)])
         L.check(self.lib.smart_mixed_batch(self.h, n, ph, nh, oh, _stream(self.device)))
 
 
@@ -131,6 +169,12 @@ class Data:
         h = C.c_void_p()
         L.check(self.ctx.lib.smart_barycentre_map(self.h, _stream(self.ctx.device), C.byref(h)))
         return Data(self.ctx, h)
+
+    def n_sources(self) -> int:
+        """Number of occupied source pixels (columns of the realisation angles)."""
+        n = C.c_int64()
+        L.check(self.ctx.lib.smart_data_sources(self.h, C.byref(n), None, None))
+        return n.value
 
     def sources(self):
         """Occupied source pixels of the pixel variant (device int64 tensor)."""
@@ -170,14 +214,19 @@ class Plan:
         self.n_scales = n_scales
         self.precision = precision
 
+    @property
+    def out_dtype(self):
+        """Element type of the maps of run() and mixed batches."""
+        return torch.float64 if self.precision in (L.PREC_FP64, L.PREC_FP32_OUT64) else torch.float32
+
     def empty_out(self):
-        dt = torch.float64 if self.precision == L.PREC_FP64 else torch.float32
-        return torch.empty(self.n_scales, 5, self.n_out, dtype=dt, device=self.ctx.device)
+        return torch.empty(self.n_scales, 5, self.n_out, dtype=self.out_dtype, device=self.ctx.device)
 
     def run(self, norm: int, out=None):
         if out is None:
             out = self.empty_out()
-        L.check(self.ctx.lib.smart_run(self.h, norm, _ptr(out), _stream(self.ctx.device)))
+        p = _buf(out, self.ctx.device, self.out_dtype, self.n_scales * 5 * self.n_out, "out")
+        L.check(self.ctx.lib.smart_run(self.h, norm, p, _stream(self.ctx.device)))
         return out
 
     def last_pairs(self) -> float:
@@ -210,18 +259,41 @@ class Plan:
         return b.value, g.value
 
     def noise_batch(self, u, n_real: int, norm: int, precision: int, out=None):
+        """Pixel-level realisations: u is [n_real][n_src] (see Data.sources)."""
+        dev = self.ctx.device
         if out is None:
-            out = torch.empty(self.n_scales, n_real, 2, self.n_out, dtype=torch.float32, device=self.ctx.device)
-        L.check(self.ctx.lib.smart_noise_batch(self.h, _ptr(u), n_real, norm, precision, _ptr(out),
-                                               _stream(self.ctx.device)))
+            out = torch.empty(self.n_scales, n_real, 2, self.n_out, dtype=torch.float32, device=dev)
+        pu = _buf(u, dev, torch.float32, n_real * self.data.n_sources(), "u")
+        po = _buf(out, dev, torch.float32, self.n_scales * n_real * 2 * self.n_out, "out")
+        L.check(self.ctx.lib.smart_noise_batch(self.h, pu, n_real, norm, precision, po, _stream(dev)))
+        return out
+
+    def noise_seeded(self, seed: int, r_first: int, n_real: int, norm: int, precision: int, moments=False,
+                     out=None):
+        """Realisations with device-drawn angles (see smart_noise_seeded). Maps:
+        [n_scales][n_real][2][n_out] float32; moments: [n_scales][4][n_out]
+        float64 sums of E, E^2, B, B^2, added to `out` (zeros when None)."""
+        dev = self.ctx.device
+        if moments:
+            if out is None:
+                out = torch.zeros(self.n_scales, 4, self.n_out, dtype=torch.float64, device=dev)
+            po = _buf(out, dev, torch.float64, self.n_scales * 4 * self.n_out, "out")
+        else:
+            if out is None:
+                out = torch.empty(self.n_scales, n_real, 2, self.n_out, dtype=torch.float32, device=dev)
+            po = _buf(out, dev, torch.float32, self.n_scales * n_real * 2 * self.n_out, "out")
+        L.check(self.ctx.lib.smart_noise_seeded(self.h, seed, r_first, n_real, norm, precision, 1 if moments else 0,
+                                                po, _stream(dev)))
         return out
 
     def noise_galaxy_batch(self, u, n_real: int, norm: int, out=None):
         """Galaxy-level realisations: u is [n_real][n_gal] in catalogue order."""
+        dev = self.ctx.device
         if out is None:
-            out = torch.empty(self.n_scales, n_real, 2, self.n_out, dtype=torch.float32, device=self.ctx.device)
-        L.check(self.ctx.lib.smart_noise_galaxy_batch(self.h, _ptr(u), n_real, norm, _ptr(out),
-                                                      _stream(self.ctx.device)))
+            out = torch.empty(self.n_scales, n_real, 2, self.n_out, dtype=torch.float32, device=dev)
+        pu = _buf(u, dev, torch.float32, n_real * self.data.info()["n_gal"], "u")
+        po = _buf(out, dev, torch.float32, self.n_scales * n_real * 2 * self.n_out, "out")
+        L.check(self.ctx.lib.smart_noise_galaxy_batch(self.h, pu, n_real, norm, po, _stream(dev)))
         return out
 
     def free(self):

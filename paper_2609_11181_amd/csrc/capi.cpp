@@ -35,10 +35,15 @@ int set_device(smart_ctx ctx) {
   return SMART_OK;
 }
 
-// a normalisation the plan accepts: the summed and raw forms on every plan,
-// the averaged approach on pixel-variant FP32 plans (its records are FP32)
+// a normalisation the plan accepts: the cap area and raw forms on every
+// plan; the pixel-count area where the sources are pixels (pixel variant,
+// barycentre data; on a galaxy catalogue N counts galaxies, and N Omega_pix
+// is not the aperture area, Sect. 3.1 step 5); the averaged approach on
+// pixel-variant FP32 plans (its records are FP32)
 int check_norm(smart_plan p, int norm) {
   if (norm < SMART_NORM_SUMMED_CAP || norm > SMART_NORM_AVERAGED) return fail(SMART_EINVAL, "unknown normalisation");
+  if (norm == SMART_NORM_SUMMED_PIXCOUNT && p->variant != SMART_VAR_PIXEL && !p->data->explicit_v)
+    return fail(SMART_EINVAL, "the pixel-count area needs pixel sources (pixel variant or barycentre data)");
   if (norm == SMART_NORM_AVERAGED && (p->variant != SMART_VAR_PIXEL || p->precision != SMART_PREC_FP32_GEO64))
     return fail(SMART_EINVAL, "averaged normalisation needs a pixel-variant FP32 plan");
   return SMART_OK;
@@ -49,6 +54,65 @@ int check_norm(smart_plan p, int norm) {
     hipError_t e_ = (x);                                                               \
     if (e_ != hipSuccess) return fail(SMART_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// Plain FP32 realisations: rotate the map by each realisation's angles,
+// then one ordinary pair-sum pass per realisation and scale; E and B go to
+// out [n_scales][r_stride][2][n_out] at realisation r_base + r, or with mom
+// non-null their moments are added to mom [n_scales][4][n_out].
+int noise_plain(smart_plan p, const float* d_u, int n_real, int norm, float* out, int r_stride, int r_base,
+                double* mom, hipStream_t st) {
+  smart_data d = p->data;
+  if (!p->rot_map && d->n_dense > 0) {  // sized by the map, kept until smart_plan_free
+    if (dev_alloc(&p->rot_map, sizeof(float4) * d->n_dense) != hipSuccess)
+      return fail(SMART_ENOMEM, "allocation failed for the rotated map");
+    p->rot_len = d->n_dense;
+  }
+  const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
+  const int ns = (int)p->theta_ap.size();
+  // each pass writes 5 channels; E and B are copied out of a staging buffer
+  float* stage = nullptr;
+  if (scratch_alloc(&stage, sizeof(float) * 5 * p->n_out, st) != hipSuccess)
+    return fail(SMART_ENOMEM, "allocation failed for staging");
+  int rc = SMART_OK;
+  for (int r = 0; r < n_real && rc == SMART_OK; ++r) {
+    hipError_t e = launch_rotate_map(map_for(d, norm), d->cidx, d_u + (int64_t)r * d->n_src, d->n_dense, p->rot_map, st);
+    if (e != hipSuccess) {
+      rc = fail(SMART_EDEVICE, "rotation kernel failed");
+      break;
+    }
+    for (int k = 0; k < ns; ++k) {
+      const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);
+      PixelArgs a{};
+      a.out_pix = p->out_pix;
+      a.n_out = p->n_out;
+      a.nside_out = p->nside_out;
+      a.map = p->rot_map;
+      a.wn = d->wn;
+      a.nside_in = d->nside;
+      a.ring_lo = d->ring_lo;
+      a.ring_hi = d->ring_hi;
+      a.pix_first = d->pix_first;
+      a.out = stage;
+      a.norm = norm;
+      a.scale = 0;
+      e = launch_pixel_sched(a, s, *p->sched[k], st);
+      if (e == hipSuccess) {
+        if (mom) {
+          e = launch_moments_add(stage, p->n_out, mom + (int64_t)k * 4 * p->n_out, st);
+        } else {
+          float* dst = out + (((int64_t)k * r_stride + r_base + r) * 2) * p->n_out;
+          e = hipMemcpyAsync(dst, stage, sizeof(float) * 2 * p->n_out, hipMemcpyDeviceToDevice, st);
+        }
+      }
+      if (e != hipSuccess) {
+        rc = fail(SMART_EDEVICE, "pair kernel failed");
+        break;
+      }
+    }
+  }
+  scratch_free(stage, st);
+  return rc;
+}
 
 }  // namespace
 
@@ -124,6 +188,37 @@ int smart_filter_table(smart_ctx ctx, int filter_id, float* h_coef, int* n_inter
   if (filter_id < 0 || filter_id >= (int)ctx->filters.size()) return fail(SMART_EINVAL, "unknown filter id");
   *n_intervals = kFilterIntervals;
   if (h_coef) memcpy(h_coef, ctx->filters[filter_id].h_table.data(), sizeof(float) * 4 * kFilterIntervals);
+  return SMART_OK;
+}
+
+int smart_filter_pieces(smart_ctx ctx, int filter_id, double theta_ap, double* h_coef, int* n_pieces) {
+  if (!ctx || !n_pieces) return fail(SMART_EINVAL, "NULL argument");
+  if (filter_id < 0 || filter_id >= (int)ctx->filters.size()) return fail(SMART_EINVAL, "unknown filter id");
+  if (!(theta_ap >= 0.0) || theta_ap > kMaxThetaAp) return fail(SMART_EINVAL, "theta_ap must be 0 or in (0, 0.25]");
+  const FilterDef& f = ctx->filters[filter_id];
+  if (theta_ap == 0.0) {  // the table in x, as the belt tables, noise walk and galaxy kernels read it
+    *n_pieces = kFilterIntervals;
+    if (h_coef) {
+      std::vector<double> c0(kFilterIntervals);
+      if (hipMemcpy(c0.data(), f.d_table_c0, sizeof(double) * kFilterIntervals, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(SMART_EDEVICE, "copy of a filter table failed");
+      for (int i = 0; i < kFilterIntervals; ++i) {
+        h_coef[4 * i] = c0[i];
+        for (int j = 1; j < 4; ++j) h_coef[4 * i + j] = (double)f.h_table[4 * i + j];
+      }
+    }
+    return SMART_OK;
+  }
+  *n_pieces = kFilterIntervals + 1;
+  if (h_coef) {
+    const std::vector<FilterPiece> pc = sin_pieces_host(f, theta_ap);
+    for (int i = 0; i <= kFilterIntervals; ++i) {
+      h_coef[4 * i] = pc[i].c0;
+      h_coef[4 * i + 1] = (double)pc[i].c1;
+      h_coef[4 * i + 2] = (double)pc[i].c2;
+      h_coef[4 * i + 3] = (double)pc[i].c3;
+    }
+  }
   return SMART_OK;
 }
 
@@ -272,11 +367,15 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
   if (data->ctx != ctx) return fail(SMART_EINVAL, "data belongs to another context");
   if (variant != SMART_VAR_GALAXY && variant != SMART_VAR_PIXEL && variant != SMART_VAR_GALAXY_POSB)
     return fail(SMART_EINVAL, "unknown variant");
+  const bool out64 = precision == SMART_PREC_FP32_OUT64;  // an FP32 plan with double maps
+  if (out64) precision = SMART_PREC_FP32_GEO64;
+  if (precision != SMART_PREC_FP64 && precision != SMART_PREC_FP32_GEO64)
+    return fail(SMART_EINVAL, "plan precision must be SMART_PREC_FP64, SMART_PREC_FP32_GEO64 or SMART_PREC_FP32_OUT64");
   const bool posb = variant == SMART_VAR_GALAXY_POSB;
   if (posb && precision != SMART_PREC_FP32_GEO64) return fail(SMART_EINVAL, "sphS_posB plans are FP32 plans");
+  if (posb && data->explicit_v)
+    return fail(SMART_EINVAL, "sphS_posB selects galaxies of a binned catalogue, not barycentre data");
   if (posb) variant = SMART_VAR_GALAXY;
-  if (precision != SMART_PREC_FP64 && precision != SMART_PREC_FP32_GEO64)
-    return fail(SMART_EINVAL, "plan precision must be SMART_PREC_FP64 or SMART_PREC_FP32_GEO64");
   if (data && data->explicit_v && (variant != SMART_VAR_GALAXY || precision != SMART_PREC_FP32_GEO64))
     return fail(SMART_EINVAL, "barycentre data takes galaxy-variant FP32 plans");
   if (!is_pow2(nside_out) || nside_out > kMaxNside) return fail(SMART_EINVAL, "nside_out must be a power of two <= 8192");
@@ -307,6 +406,7 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
   p->variant = variant;
   p->posb = posb;
   p->precision = precision;
+  p->out64 = out64;
   p->nside_out = nside_out;
   p->n_out = n_out;
   p->theta_ap.assign(h_theta_ap, h_theta_ap + n_scales);
@@ -372,6 +472,7 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.out = d_out;
       a.norm = norm;
       a.scale = k;
+      a.out64 = p->out64 ? 1 : 0;
       hipEvent_t* ev = p->timing ? &p->events[4 * k] : nullptr;
       e = p->precision == SMART_PREC_FP32_GEO64 ? launch_pixel_sched(a, s, *p->sched[k], st, ev)
                                                 : launch_pixel(a, s, p->precision, st, p->d_work);
@@ -389,6 +490,7 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.out = d_out;
       a.norm = norm;
       a.scale = k;
+      a.out64 = p->out64 ? 1 : 0;
       a.explicit_v = d->explicit_v ? 1 : 0;
       a.posb = p->posb ? 1 : 0;
       e = launch_galaxy(a, s, p->precision, st);
@@ -473,7 +575,7 @@ int smart_last_pairs(smart_plan p, void* stream, double* pairs) {
   int rc;
   if ((rc = set_device(p->ctx))) return rc;
   hipStream_t st = (hipStream_t)stream;
-  CHECK_HIP(launch_sum_n(p->last_out, p->precision, p->n_out, (int)p->theta_ap.size(), p->d_pairs, st));
+  CHECK_HIP(launch_sum_n(p->last_out, p->out64 ? SMART_PREC_FP64 : p->precision, p->n_out, (int)p->theta_ap.size(), p->d_pairs, st));
   CHECK_HIP(hipMemcpyAsync(pairs, p->d_pairs, sizeof(double), hipMemcpyDeviceToHost, st));
   CHECK_HIP(hipStreamSynchronize(st));
   return SMART_OK;
@@ -493,48 +595,53 @@ int smart_noise_batch(smart_plan p, const float* d_u, int n_real, int norm, int 
   if (norm == SMART_NORM_AVERAGED && (rc = ensure_averaged(d, st))) return rc;
   if (precision == SMART_PREC_BF16X3) return noise_bf16x3(p, d_u, n_real, norm, d_out, st);
   if (precision != SMART_PREC_FP32_GEO64) return fail(SMART_EINVAL, "noise precision must be FP32 or BF16X3");
-  // plain path: rotate the map, then one ordinary pair-sum pass per realisation
-  if (p->rot_len < d->n_dense) {
-    hipFree(p->rot_map);
-    p->rot_map = nullptr;
-    p->rot_len = 0;
-    if (hipMalloc(&p->rot_map, sizeof(float4) * d->n_dense) != hipSuccess)
-      return fail(SMART_ENOMEM, "allocation failed for the rotated map");
-    p->rot_len = d->n_dense;
-  }
-  const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
-  const int ns = (int)p->theta_ap.size();
-  // each pass writes 5 channels; E and B are copied out of a staging buffer
-  float* stage = nullptr;
-  if (scratch_alloc(&stage, sizeof(float) * 5 * p->n_out, st) != hipSuccess)
-    return fail(SMART_ENOMEM, "allocation failed for staging");
-  for (int r = 0; r < n_real; ++r) {
-    hipError_t e = launch_rotate_map(map_for(d, norm), d->cidx, d_u + (int64_t)r * d->n_src, d->n_dense, p->rot_map, st);
-    if (e != hipSuccess) return fail(SMART_EDEVICE, "rotation kernel failed");
-    for (int k = 0; k < ns; ++k) {
-      const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);
-      PixelArgs a{};
-      a.out_pix = p->out_pix;
-      a.n_out = p->n_out;
-      a.nside_out = p->nside_out;
-      a.map = p->rot_map;
-      a.wn = d->wn;
-      a.nside_in = d->nside;
-      a.ring_lo = d->ring_lo;
-      a.ring_hi = d->ring_hi;
-      a.pix_first = d->pix_first;
-      a.out = stage;
-      a.norm = norm;
-      a.scale = 0;
-      e = launch_pixel_sched(a, s, *p->sched[k], st);
-      if (e != hipSuccess) return fail(SMART_EDEVICE, "pair kernel failed");
-      float* dst = d_out + (((int64_t)k * n_real + r) * 2) * p->n_out;
-      e = hipMemcpyAsync(dst, stage, sizeof(float) * 2 * p->n_out, hipMemcpyDeviceToDevice, st);
-      if (e != hipSuccess) return fail(SMART_EDEVICE, "copy failed");
-    }
-  }
-  scratch_free(stage, st);
+  return noise_plain(p, d_u, n_real, norm, d_out, n_real, 0, nullptr, st);
+}
+
+int smart_noise_angles(smart_ctx ctx, uint64_t seed, int64_t r_first, int n_real, int64_t n_src, float* d_u,
+                       void* stream) {
+  if (!ctx || (!d_u && n_real > 0 && n_src > 0)) return fail(SMART_EINVAL, "NULL argument");
+  if (n_real < 0 || n_src < 0 || r_first < 0) return fail(SMART_EINVAL, "negative count or realisation index");
+  int rc;
+  if ((rc = set_device(ctx))) return rc;
+  CHECK_HIP(launch_philox_u(seed, r_first, n_real, n_src, d_u, (hipStream_t)stream));
   return SMART_OK;
+}
+
+int smart_noise_seeded(smart_plan p, uint64_t seed, int64_t r_first, int n_real, int norm, int precision,
+                       int moments_only, void* d_out, void* stream) {
+  if (!p || !d_out) return fail(SMART_EINVAL, "NULL argument");
+  if (p->variant != SMART_VAR_PIXEL || p->precision != SMART_PREC_FP32_GEO64)
+    return fail(SMART_EINVAL, "noise batches need a pixel-variant FP32 plan");
+  if (n_real < 1) return fail(SMART_EINVAL, "n_real must be >= 1");
+  if (r_first < 0) return fail(SMART_EINVAL, "r_first must be >= 0");
+  if (precision != SMART_PREC_BF16X3 && precision != SMART_PREC_FP32_GEO64)
+    return fail(SMART_EINVAL, "noise precision must be FP32 or BF16X3");
+  int rc;
+  if ((rc = check_norm(p, norm))) return rc;
+  if ((rc = set_device(p->ctx))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  smart_data d = p->data;
+  if (norm == SMART_NORM_AVERAGED && (rc = ensure_averaged(d, st))) return rc;
+  if (p->n_out == 0) return SMART_OK;
+  // angles of one chunk of realisations at a time (n_src x 32 floats)
+  const int C = kNoiseChunk;
+  float* u = nullptr;
+  if (scratch_alloc(&u, sizeof(float) * (size_t)std::max<int64_t>(d->n_src, 1) * C, st) != hipSuccess)
+    return fail(SMART_ENOMEM, "allocation failed for the realisation angles");
+  double* mom = moments_only ? (double*)d_out : nullptr;
+  float* maps = moments_only ? nullptr : (float*)d_out;
+  for (int c0 = 0; c0 < n_real && rc == SMART_OK; c0 += C) {
+    const int nc = std::min(C, n_real - c0);
+    if (launch_philox_u(seed, r_first + c0, nc, d->n_src, u, st) != hipSuccess) {
+      rc = fail(SMART_EDEVICE, "angle generator failed to launch");
+      break;
+    }
+    rc = precision == SMART_PREC_BF16X3 ? noise_bf16x3(p, u, nc, norm, maps, st, n_real, c0, mom)
+                                        : noise_plain(p, u, nc, norm, maps, n_real, c0, mom, st);
+  }
+  scratch_free(u, st);
+  return rc;
 }
 
 int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int norm, float* d_out, void* stream) {

@@ -2,11 +2,15 @@
 //
 // The aperture filter is evaluated at every source from its distance to the
 // aperture centre (Sect. 3.1 step 3; Sect. 3.2 step 4). Device kernels read
-// q(x), x = theta/theta_ap in [0, 1), from a piecewise-cubic Hermite table
-// with kFilterIntervals uniform pieces built here from exact values and
-// exact derivatives; for the built-in filters the interpolation error is
-// below 1e-8 of the filter maximum (the fourth derivative of the steepest
-// part, the logistic switch of slope 150 in the NFW-like filter, bounds it).
+// q(x), x = theta/theta_ap in [0, 1), from a piecewise-cubic table with
+// kFilterIntervals uniform pieces built here: each piece is the cubic that
+// interpolates the exact filter at the four Chebyshev nodes of the piece,
+// whose error bound, h^4 max|q^(4)| / 3072, is an eighth of that of the
+// Hermite cubic from the values and derivatives at the ends; for the
+// built-in filters the error is below 3e-9 of the filter maximum (the
+// fourth derivative of the steepest part, the logistic switch of slope 150
+// in the NFW-like filter, sets it; Hermite pieces reached 1.07e-8).
+// Neighbouring pieces differ at their common end by about that error.
 #include <math.h>
 #include <string.h>
 
@@ -78,6 +82,31 @@ void eval_both(const FilterDef& f, double x, double* q, double* dq) {
   }
 }
 
+// Abscissa m of the four Chebyshev nodes of [0, 1]: (1 - cos((2m + 1) pi / 8)) / 2.
+inline double cheb_node(int m) { return 0.5 * (1.0 - cos((2 * m + 1) * M_PI / 8.0)); }
+
+// The cubic c0 + c1 f + c2 f^2 + c3 f^3 through (cheb_node(m), v[m]): the
+// Lagrange basis expanded into monomials.
+void cheb_cubic(const double v[4], double c[4]) {
+  double f[4];
+  for (int m = 0; m < 4; ++m) f[m] = cheb_node(m);
+  for (int k = 0; k < 4; ++k) c[k] = 0.0;
+  for (int m = 0; m < 4; ++m) {
+    // prod over l != m of (f - f_l) / (f_m - f_l), as monomial coefficients
+    double b[4] = {1.0, 0.0, 0.0, 0.0};
+    double den = 1.0;
+    int deg = 0;
+    for (int l = 0; l < 4; ++l) {
+      if (l == m) continue;
+      for (int k = deg + 1; k > 0; --k) b[k] = b[k - 1] - f[l] * b[k];
+      b[0] = -f[l] * b[0];
+      ++deg;
+      den *= f[m] - f[l];
+    }
+    for (int k = 0; k < 4; ++k) c[k] += v[m] * b[k] / den;
+  }
+}
+
 }  // namespace
 
 double filter_eval(const FilterDef& f, double x) {
@@ -90,17 +119,15 @@ double filter_eval(const FilterDef& f, double x) {
 int build_filter(FilterDef& f) {
   const int K = kFilterIntervals;
   const double h = 1.0 / K;
-  std::vector<double> qv(K + 1), dv(K + 1);
-  for (int i = 0; i <= K; ++i) eval_both(f, i * h, &qv[i], &dv[i]);  // x = 1: left limit
   f.h_table.resize(4 * K);
   std::vector<double> c0(K);
   for (int i = 0; i < K; ++i) {
-    const double q0 = qv[i], q1 = qv[i + 1], d0 = dv[i] * h, d1 = dv[i + 1] * h;
-    f.h_table[4 * i + 0] = (float)q0;
-    c0[i] = q0;
-    f.h_table[4 * i + 1] = (float)d0;
-    f.h_table[4 * i + 2] = (float)(3.0 * (q1 - q0) - 2.0 * d0 - d1);
-    f.h_table[4 * i + 3] = (float)(2.0 * (q0 - q1) + d0 + d1);
+    double v[4], c[4], dq;
+    for (int m = 0; m < 4; ++m) eval_both(f, (i + cheb_node(m)) * h, &v[m], &dq);
+    cheb_cubic(v, c);
+    f.h_table[4 * i + 0] = (float)c[0];
+    c0[i] = c[0];
+    for (int k = 1; k < 4; ++k) f.h_table[4 * i + k] = (float)c[k];
   }
   if (hipMalloc(&f.d_table, sizeof(float) * 4 * K) != hipSuccess) {
     set_error("hipMalloc failed for a filter table");
@@ -120,29 +147,29 @@ int build_filter(FilterDef& f) {
 
 // The filter of one aperture as a table in y = sin(theta) for the general
 // pixel walk, which gets sin(theta) of every pair from its tangent-plane
-// components: Hermite pieces over [0, sin theta_ap] from the exact values
-// q(asin(y) / theta_ap) and derivatives dq/dx / (theta_ap cos theta), and a
-// constant piece q(1) at index kFilterIntervals (y = sin theta_ap exactly,
-// and its rounding, index no further). Device copy, or null on failure.
-FilterPiece* build_sin_pieces(const FilterDef& f, double theta_ap) {
+// components: pieces over [0, sin theta_ap] interpolating the exact
+// q(asin(y) / theta_ap) at their Chebyshev nodes, and a constant piece q(1) at index kFilterIntervals (y = sin theta_ap exactly,
+// and its rounding, index no further).
+std::vector<FilterPiece> sin_pieces_host(const FilterDef& f, double theta_ap) {
   const int K = kFilterIntervals;
   const double ymax = sin(theta_ap), h = ymax / K;
-  std::vector<double> qv(K + 1), dv(K + 1);
-  for (int i = 0; i <= K; ++i) {
-    const double y = i == K ? ymax : i * h;
-    const double x = i == K ? 1.0 : asin(y) / theta_ap;  // x = 1: left limit
-    double q, dq;
-    eval_both(f, x, &q, &dq);
-    qv[i] = q;
-    dv[i] = dq / (theta_ap * sqrt(1.0 - y * y));
-  }
   std::vector<FilterPiece> pieces(K + 1);
   for (int i = 0; i < K; ++i) {
-    const double q0 = qv[i], q1 = qv[i + 1], d0 = dv[i] * h, d1 = dv[i + 1] * h;
-    pieces[i] = FilterPiece{q0, (float)d0, (float)(3.0 * (q1 - q0) - 2.0 * d0 - d1),
-                            (float)(2.0 * (q0 - q1) + d0 + d1), 0.f};
+    double v[4], c[4], dq;
+    for (int m = 0; m < 4; ++m) eval_both(f, asin((i + cheb_node(m)) * h) / theta_ap, &v[m], &dq);
+    cheb_cubic(v, c);
+    pieces[i] = FilterPiece{c[0], (float)c[1], (float)c[2], (float)c[3], 0.f};
   }
-  pieces[K] = FilterPiece{qv[K], 0.f, 0.f, 0.f, 0.f};
+  double q1, dq;
+  eval_both(f, 1.0, &q1, &dq);  // x = 1: left limit
+  pieces[K] = FilterPiece{q1, 0.f, 0.f, 0.f, 0.f};
+  return pieces;
+}
+
+// The same table in device memory, or null on failure.
+FilterPiece* build_sin_pieces(const FilterDef& f, double theta_ap) {
+  const int K = kFilterIntervals;
+  const std::vector<FilterPiece> pieces = sin_pieces_host(f, theta_ap);
   FilterPiece* d = nullptr;
   if (dev_alloc(&d, sizeof(FilterPiece) * (K + 1)) != hipSuccess) return nullptr;
   if (hipMemcpy(d, pieces.data(), sizeof(FilterPiece) * (K + 1), hipMemcpyHostToDevice) != hipSuccess) {
@@ -153,7 +180,7 @@ FilterPiece* build_sin_pieces(const FilterDef& f, double theta_ap) {
   return d;
 }
 
-ScaleArgs make_scale(smart_ctx ctx, double theta_ap, int filter_id, double omega_pix) {
+ScaleArgs make_scale(smart_ctx ctx, double theta_ap, int filter_id, double omega_pix, bool may_build) {
   ScaleArgs s{};
   const FilterDef& f = ctx->filters[filter_id];
   const double sh = sin(0.5 * theta_ap);
@@ -171,9 +198,15 @@ ScaleArgs make_scale(smart_ctx ctx, double theta_ap, int filter_id, double omega
   if (f.kind != SMART_FILTER_POLY) {
     uint64_t bits;
     memcpy(&bits, &theta_ap, sizeof bits);
-    auto& slot = ctx->sin_pieces[{filter_id, bits}];
-    if (!slot) slot = build_sin_pieces(f, theta_ap);
-    s.pieces = slot;
+    const auto key = std::make_pair(filter_id, bits);
+    if (may_build) {
+      auto& slot = ctx->sin_pieces[key];
+      if (!slot) slot = build_sin_pieces(f, theta_ap);
+      s.pieces = slot;
+    } else {
+      const auto it = ctx->sin_pieces.find(key);
+      s.pieces = it == ctx->sin_pieces.end() ? nullptr : it->second;
+    }
   }
   // asin(y) / y = sum c_k y^(2k), divided by theta_ap so that x = y * P(y^2);
   // for tabulated filters also multiplied by the number of table pieces, so

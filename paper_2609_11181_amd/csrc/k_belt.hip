@@ -166,19 +166,19 @@ __global__ __launch_bounds__(kBlock) void k_belt_fill(PixelArgs a, ScaleArgs s, 
   const Ring R = ring_info(N, rp);
   int lo, hi;
   belt_span(a, s.theta_ap, rp, &lo, &hi);
-  if (tid < c.x) {
-    const Ring Q = ring_info(N, lo + tid);
+  for (int i = tid; i < c.x; i += kBlock) {  // c.x <= kRingCap table rings
+    const Ring Q = ring_info(N, lo + i);
     int64_t jlo = 0;
     int cnt = 0;
     if (!ring_window(R.z, R.s, R.twice_o, n, Q, s.C_ap, &jlo, &cnt)) {
       jlo = 0;
       cnt = 0;
     }
-    s_off[tid + 1] = cnt;
-    s_m0[tid] = (int)((int64_t)R.twice_o * n - (2 * jlo + Q.twice_o) * (int64_t)n);
-    s_y0[tid] = ring_y0(Q.s, Q.z, R.z, R.s);
-    s_kz[tid] = 2.0 * Q.z * R.s;
-    info[base.x + tid] = make_int4(lo + tid, (int)jlo, cnt, 0);  // offset filled below
+    s_off[i + 1] = cnt;
+    s_m0[i] = (int)((int64_t)R.twice_o * n - (2 * jlo + Q.twice_o) * (int64_t)n);
+    s_y0[i] = ring_y0(Q.s, Q.z, R.z, R.s);
+    s_kz[i] = 2.0 * Q.z * R.s;
+    info[base.x + i] = make_int4(lo + i, (int)jlo, cnt, 0);  // offset filled below
   }
   __syncthreads();
   if (tid == 0) {
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_belt_fill(PixelArgs a, ScaleArgs s, 
     for (int i = 0; i < c.x; ++i) s_off[i + 1] += s_off[i];
   }
   __syncthreads();
-  if (tid < c.x) info[base.x + tid].w = base.y + s_off[tid];
+  for (int i = tid; i < c.x; i += kBlock) info[base.x + i].w = base.y + s_off[i];
   const double cphi = kPi / ((double)n * (double)n);
   const int mstep = 2 * n;
   double tp[7];

@@ -581,6 +581,9 @@ int barycentre_data(smart_data src, hipStream_t st, smart_data out) {
     hipLaunchKernelGGL(k_barycentre, dim3(grid_of(n * kSumLanes)), dim3(kBlock), 0, st, n, src->src_pix,
                        src->offsets, src->P, src->G, ra, dec, cols, cols + n, cols + 2 * n, cols + 3 * n);
     if (hipGetLastError() != hipSuccess) {
+      scratch_free(ra, st);
+      scratch_free(dec, st);
+      scratch_free(cols, st);
       set_error("barycentre kernel failed to launch");
       return SMART_EDEVICE;
     }

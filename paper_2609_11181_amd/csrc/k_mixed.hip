@@ -136,9 +136,10 @@ int mixed_grid() {
     }                                                                            \
   } while (0)
 
-int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,
-                hipStream_t st) {
-  // jobs and their item groups
+namespace {
+
+// Jobs, item groups and the order of one mixed batch, built on the host.
+struct MixPlan {
   struct Grp {
     int job, kind, count;
     const void* list;
@@ -146,6 +147,12 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
   };
   std::vector<MixJob> jobs;
   std::vector<Grp> groups;
+  int64_t n_items = 0;
+  int span_j = 5;  // LDS spans wide enough for every job's windows (0: none)
+};
+
+int prepare_mixed(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,
+                  bool may_build, MixPlan* mp) {
   std::vector<smart_plan> plans_of_job;
   std::vector<int> scale_of_job;
   for (int p = 0; p < n_plans; ++p) {
@@ -156,7 +163,7 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
     for (int k = 0; k < (int)P->theta_ap.size(); ++k) {
       const PixelSched& sc = *P->sched[k];
       MixJob J{};
-      J.s = make_scale(ctx, P->theta_ap[k], P->filter_ids[k], omega);
+      J.s = make_scale(ctx, P->theta_ap[k], P->filter_ids[k], omega, may_build);
       if (J.s.filter_kind != SMART_FILTER_POLY && !J.s.pieces) {
         set_error("mixed batch: no device memory for a filter table");
         return SMART_ENOMEM;
@@ -171,40 +178,50 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
       J.a.ring_hi = d->ring_hi;
       J.a.pix_first = d->pix_first;
       J.a.out = outs[p];
+      J.a.out64 = P->out64 ? 1 : 0;
       J.a.norm = norms[p];
       J.a.scale = k;
       J.a.gt_head = sc.gt_head;
       J.a.gt_pair = sc.gt_pair;
       J.a.gt_ring = sc.gt_ring;
       J.t = sc.tab();
-      const int j = (int)jobs.size();
-      jobs.push_back(J);
+      const int j = (int)mp->jobs.size();
+      mp->jobs.push_back(J);
       plans_of_job.push_back(P);
       scale_of_job.push_back(k);
       const double members = 2.0 * M_PI * (1.0 - cos(P->theta_ap[k])) / omega;  // sources per disc
       // a belt pair costs about an eighth of a general pair
-      if (sc.counts[0] > 0) groups.push_back({j, 0, sc.counts[0], sc.belt, 256.0 * members});
-      if (sc.counts[1] > 0) groups.push_back({j, 1, sc.counts[1], sc.general, 8.0 * 64.0 * members});
+      if (sc.counts[0] > 0) mp->groups.push_back({j, 0, sc.counts[0], sc.belt, 256.0 * members});
+      if (sc.counts[1] > 0) mp->groups.push_back({j, 1, sc.counts[1], sc.general, 8.0 * 64.0 * members});
     }
   }
-  if (groups.empty()) return SMART_OK;
-  std::stable_sort(groups.begin(), groups.end(), [](const Grp& x, const Grp& y) { return x.cost > y.cost; });
-  int64_t n_items = 0;
-  for (const Grp& g : groups) n_items += g.kind == 0 ? g.count : 4 * (int64_t)g.count;
-  if (n_items > 0x7fffffff) {
+  std::stable_sort(mp->groups.begin(), mp->groups.end(),
+                   [](const MixPlan::Grp& x, const MixPlan::Grp& y) { return x.cost > y.cost; });
+  for (const MixPlan::Grp& g : mp->groups) mp->n_items += g.kind == 0 ? g.count : 4 * (int64_t)g.count;
+  if (mp->n_items > 0x7fffffff) {
     set_error("mixed batch: too many work items");
     return SMART_EINVAL;
   }
-  int4* items = nullptr;
-  MixJob* d_jobs = nullptr;
-  int* counter = nullptr;
-  MCHK(scratch_alloc(&items, sizeof(int4) * (size_t)n_items, st));
-  MCHK(scratch_alloc(&d_jobs, sizeof(MixJob) * jobs.size(), st));
-  MCHK(scratch_alloc(&counter, sizeof(int) * kQueueInts, st));
-  MCHK(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(MixJob) * jobs.size(), hipMemcpyHostToDevice, st));
-  MCHK(hipMemsetAsync(counter, 0, sizeof(int) * kQueueInts, st));
+  for (const MixPlan::Grp& g : mp->groups)
+    if (g.kind == 0) {
+      const int j = belt_span_j(plans_of_job[g.job]->sched[scale_of_job[g.job]]->belt_cnt_max);
+      mp->span_j = j == 0 ? 0 : (mp->span_j == 0 ? 0 : std::max(mp->span_j, j));
+    }
+  return SMART_OK;
+}
+
+__global__ void k_zero_ints(int* v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = 0;
+}
+
+// Work list, jobs and counters in device memory the caller provides; the
+// claim counters are cleared by a kernel (no memset node when captured).
+int launch_mixed(const MixPlan& mp, int4* items, MixJob* d_jobs, int* counter, hipStream_t st) {
+  MCHK(hipMemcpyAsync(d_jobs, mp.jobs.data(), sizeof(MixJob) * mp.jobs.size(), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_zero_ints, dim3(grid_of(kQueueInts)), dim3(kBlock), 0, st, counter, kQueueInts);
   int64_t off = 0;
-  for (const Grp& g : groups) {
+  for (const MixPlan::Grp& g : mp.groups) {
     const int n = g.kind == 0 ? g.count : 4 * g.count;
     if (g.kind == 0)
       hipLaunchKernelGGL(k_fill_belt, dim3(grid_of(n)), dim3(kBlock), 0, st, (const int2*)g.list, g.count, g.job,
@@ -215,27 +232,37 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
     off += n;
   }
   MCHK(hipGetLastError());
-  // LDS spans wide enough for every job's windows (or none when one is too wide)
-  int span_j = 5;
-  for (const Grp& g : groups)
-    if (g.kind == 0) {
-      const int j = belt_span_j(plans_of_job[g.job]->sched[scale_of_job[g.job]]->belt_cnt_max);
-      span_j = j == 0 ? 0 : (span_j == 0 ? 0 : std::max(span_j, j));
-    }
   auto launch = [&](auto kern, int grid) {
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, st, d_jobs, items, (int)n_items, counter);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, st, d_jobs, items, (int)mp.n_items, counter);
   };
-  switch (span_j) {
+  switch (mp.span_j) {
     case 5: launch(k_mixed<5>, mixed_grid<5>()); break;
     case 6: launch(k_mixed<6>, mixed_grid<6>()); break;
     case 7: launch(k_mixed<7>, mixed_grid<7>()); break;
     default: launch(k_mixed<0>, mixed_grid<0>());
   }
   MCHK(hipGetLastError());
+  return SMART_OK;
+}
+
+}  // namespace
+
+int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,
+                hipStream_t st) {
+  MixPlan mp;
+  int rc = prepare_mixed(ctx, n_plans, plans, norms, outs, true, &mp);
+  if (rc || mp.groups.empty()) return rc;
+  int4* items = nullptr;
+  MixJob* d_jobs = nullptr;
+  int* counter = nullptr;
+  MCHK(scratch_alloc(&items, sizeof(int4) * (size_t)mp.n_items, st));
+  MCHK(scratch_alloc(&d_jobs, sizeof(MixJob) * mp.jobs.size(), st));
+  MCHK(scratch_alloc(&counter, sizeof(int) * kQueueInts, st));
+  rc = launch_mixed(mp, items, d_jobs, counter, st);
   scratch_free(items, st);
   scratch_free(d_jobs, st);
   scratch_free(counter, st);
-  return SMART_OK;
+  return rc;
 }
 
 }  // namespace smart

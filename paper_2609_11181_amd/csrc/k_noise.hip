@@ -49,6 +49,7 @@ constexpr int kNP = 32;     // centres per segment (MFMA rows)
 constexpr int kNR = 32;     // realisations per block (E and B: two 32-column MFMA halves)
 constexpr int kStack = 8;   // segments per block, one per wave
 constexpr int kCntMax = 96;                    // members per disc ring of an eligible segment
+static_assert(kNR == kNoiseChunk, "seeded batches run one realisation block per chunk");
 
 __global__ void k_rotate(const float4* map, const int* cidx, const float* u, int64_t n, float4* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,7 +154,9 @@ struct NoiseArgs {
   int64_t n_src;
   int n_real;
   int n_grp;          // realisation blocks of kNR
-  float* out;         // [n_scales][n_real][2][n_out]
+  float* out;         // [n_scales][r_stride][2][n_out]: realisation r at r_base + r
+  int r_stride, r_base;
+  double* mom;        // moments mode (out unused): [n_scales][4][n_out] += sum of E, E^2, B, B^2
 };
 
 // two BF16 words per 32-bit lane of an MFMA operand
@@ -360,12 +363,30 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
     cst[(32 + col) * kNP + row] = acc1[i] * fnorm[wave][row]; // r' >= 16
   }
   __syncthreads();
-  if (active) {  // centres sg.y .. sg.z - 1 of the segment are list entries o_w, o_w + 1, ...
+  if (active && n.mom) {
+    // moments: centre pp sums its realisations of this block; every output
+    // of a segment run belongs to one wave of one block, and the launches of
+    // one call run in stream order, so the update needs no atomics
+    const int nr = min(kNR, n.n_real - rg * kNR);
+    if (lane < kNP && lane >= sg.y && lane < sg.z) {
+      double m[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int rr = 0; rr < nr; ++rr) {
+        const double e = (double)cst[(2 * rr) * kNP + lane], b = (double)cst[(2 * rr + 1) * kNP + lane];
+        m[0] += e;
+        m[1] += e * e;
+        m[2] += b;
+        m[3] += b * b;
+      }
+      double* mp = n.mom + (int64_t)a.scale * 4 * a.n_out + o_w + (lane - sg.y);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) mp[(int64_t)q * a.n_out] += m[q];
+    }
+  } else if (active) {  // centres sg.y .. sg.z - 1 of the segment are list entries o_w, o_w + 1, ...
     for (int v = lane; v < 2 * kNR * kNP; v += 64) {
       const int ci = v / kNP, pp = v % kNP;
       const int rr = rg * kNR + (ci >> 1), e = ci & 1;
       if (rr < n.n_real && pp >= sg.y && pp < sg.z)
-        n.out[(((int64_t)a.scale * n.n_real + rr) * 2 + e) * a.n_out + o_w + (pp - sg.y)] = cst[v];
+        n.out[(((int64_t)a.scale * n.r_stride + n.r_base + rr) * 2 + e) * a.n_out + o_w + (pp - sg.y)] = cst[v];
     }
   }
 }
@@ -388,7 +409,9 @@ struct RestArgs {
   const int* cidx;     // dense pixel -> source index (-1: empty)
   int64_t n_src;
   int n_real;
-  float* out;          // [n_scales][n_real][2][n_out]
+  float* out;          // [n_scales][r_stride][2][n_out]: realisation r at r_base + r
+  int r_stride, r_base;
+  double* mom;         // moments mode (out unused): [n_scales][4][n_out] += sum of E, E^2, B, B^2
 };
 
 template <bool TABLE, bool BIG>
@@ -485,19 +508,104 @@ __global__ __launch_bounds__(kBlock) void k_noise_rest_walk(RestArgs n, ScaleArg
     const double area = a.norm == SMART_NORM_SUMMED_CAP ? s.area_cap : tot.sn * s.omega_pix;
     f = tot.sw > 0.0 ? (float)(area * s.inv_theta2 / tot.sw) : 0.f;
   }
+  if (n.mom) {
+    // moments: the realisation groups of one output run in different
+    // threads of the launch, so they add atomically (device-scope FP64 add)
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < kRestReal; ++q) {
+      if (q < nr) {
+        const double e = (double)(f * se[q]), b = (double)(f * sb[q]);
+        m[0] += e;
+        m[1] += e * e;
+        m[2] += b;
+        m[3] += b * b;
+      }
+    }
+    double* mp = n.mom + (int64_t)a.scale * 4 * a.n_out + o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) unsafeAtomicAdd(mp + (int64_t)q * a.n_out, m[q]);
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < kRestReal; ++q) {
     if (q < nr) {
-      const int64_t base = ((int64_t)a.scale * n.n_real + r0 + q) * 2 * a.n_out;
+      const int64_t base = ((int64_t)a.scale * n.r_stride + n.r_base + r0 + q) * 2 * a.n_out;
       n.out[base + o] = f * se[q];
       n.out[base + a.n_out + o] = f * sb[q];
     }
   }
 }
 
+// Counter-based angles: realisation r, source j takes the 64-bit word j of
+// the Philox4x64-10 stream keyed by (seed, r) (Salmon et al. 2011): the
+// block of four words j / 4 comes from counter (j / 4 + 1, 0, 0, 0), ten
+// rounds of two 64 x 64 -> 128-bit products with the published multipliers,
+// the key bumped by the published Weyl constants between rounds; then
+// u = ((k >> 41) + 0.5) 2^-23, exact in float, in (0, 1).
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t h0 = __umul64hi(M0, c[0]), l0 = M0 * c[0];
+    const uint64_t h1 = __umul64hi(M1, c[2]), l1 = M1 * c[2];
+    const uint64_t x0 = h1 ^ c[1] ^ k0, x2 = h0 ^ c[3] ^ k1;
+    c[0] = x0;
+    c[1] = l1;
+    c[2] = x2;
+    c[3] = l0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+__device__ __forceinline__ float philox_unit(uint64_t k) { return ((float)(k >> 41) + 0.5f) * 0x1p-23f; }
+
+// u[r][j] for r < n_real, j < n_src (realisation r_first + r): one thread per
+// block of four words
+__global__ void k_philox_u(uint64_t seed, int64_t r_first, int n_real, int64_t n_src, float* u) {
+  const int64_t nb = (n_src + 3) / 4;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nb * n_real) return;
+  const int r = (int)(id / nb);
+  const int64_t b = id % nb;
+  uint64_t c[4] = {(uint64_t)b + 1, 0, 0, 0};
+  philox4x64_10(c, seed, (uint64_t)(r_first + r));
+  float* row = u + (int64_t)r * n_src + 4 * b;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (4 * b + q < n_src) row[q] = philox_unit(c[q]);
+}
+
+// moments of plain-path maps: [4][n_out] += (E, E^2, B, B^2) of one
+// realisation's [2][n_out] float maps
+__global__ void k_moments_add(const float* eb, int64_t n_out, double* mom) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_out) return;
+  const double e = (double)eb[o], b = (double)eb[n_out + o];
+  mom[o] += e;
+  mom[n_out + o] += e * e;
+  mom[2 * n_out + o] += b;
+  mom[3 * n_out + o] += b * b;
+}
+
 unsigned grid_of(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
+
+hipError_t launch_philox_u(uint64_t seed, int64_t r_first, int n_real, int64_t n_src, float* u, hipStream_t st) {
+  const int64_t threads = (n_src + 3) / 4 * n_real;
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_philox_u, dim3(grid_of(threads)), dim3(kBlock), 0, st, seed, r_first, n_real, n_src, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_add(const float* eb, int64_t n_out, double* mom, hipStream_t st) {
+  if (n_out == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_moments_add, dim3(grid_of(n_out)), dim3(kBlock), 0, st, eb, n_out, mom);
+  return hipGetLastError();
+}
 
 hipError_t launch_rotate_galaxies(const float4* G, const int64_t* order, const float* u, int64_t n, float4* out,
                                   hipStream_t st) {
@@ -586,7 +694,9 @@ static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, h
   return SMART_OK;
 }
 
-int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st) {
+int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st, int r_stride,
+                 int r_base, double* mom) {
+  if (r_stride < 0) r_stride = n_real;
   smart_data d = p->data;
   const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
   const int ns = (int)p->theta_ap.size();
@@ -634,6 +744,9 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
       na.n_real = n_real;
       na.n_grp = (n_real + kNR - 1) / kNR;
       na.out = d_out;
+      na.r_stride = r_stride;
+      na.r_base = r_base;
+      na.mom = mom;
       const dim3 grid((unsigned)((int64_t)sc.noise_n_stacks * na.n_grp)), block(64 * kStack);
       hipLaunchKernelGGL(k_noise_stack, grid, block, stack_lds_bytes(sc.noise_cnt_max), st, na, s,
                          sc.noise_cnt_max);
@@ -650,6 +763,9 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
       ra.n_src = d->n_src;
       ra.n_real = n_real;
       ra.out = d_out;
+      ra.r_stride = r_stride;
+      ra.r_base = r_base;
+      ra.mom = mom;
       const int64_t blocks = (int64_t)grid_of(ra.n_rest) * ((n_real + kRestReal - 1) / kRestReal);
       if (blocks > 0x7fffffff) {
         set_error("noise batch: too many outputs outside the stacks");

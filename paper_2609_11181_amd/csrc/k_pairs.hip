@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
       tot.add(acc);
     }
   }
-  write_out<float>(a.out, a.n_out, a.scale, o, a.norm, tot, s);
+  write_map(a.out, a.out64, a.n_out, a.scale, o, a.norm, tot, s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_galaxy_f64(GalaxyArgs a, ScaleArgs s) {

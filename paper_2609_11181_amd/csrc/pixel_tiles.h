@@ -39,6 +39,14 @@ __device__ __forceinline__ void write_out(void* out, int64_t n_out, int scale, i
   base[4 * n_out + o] = (T)t.sn;
 }
 
+// Maps of an FP32 plan: float, or double for SMART_PREC_FP32_OUT64 plans
+// (the sums are FP64 either way; a uniform branch).
+__device__ __forceinline__ void write_map(void* out, int out64, int64_t n_out, int scale, int64_t o, int norm,
+                                          const Acc64& t, const ScaleArgs& s) {
+  if (out64) write_out<double>(out, n_out, scale, o, norm, t, s);
+  else write_out<float>(out, n_out, scale, o, norm, t, s);
+}
+
 // ---- pixel variant, mixed precision: tiles ---------------------------------------
 //
 // Outputs are cut into tiles of 256 consecutive list entries. A tile whose
@@ -50,7 +58,11 @@ __device__ __forceinline__ void write_out(void* out, int64_t n_out, int scale, i
 // scale into a table (k_belt.hip). All other tiles are general: each centre
 // evaluates its own pairs.
 
-constexpr int kRingCap = 160;  // rings of one belt disc
+// Rings of one belt disc. About 3 N theta_ap rings, so belt discs reach
+// N theta_ap = 128 and windows of up to about 200 members per ring (at the
+// belt's edge); a scale's tables then hold at most (2N + 1) x 3 (N
+// theta_ap)^2 < 2^31 coefficients (the int offsets of the tables).
+constexpr int kRingCap = 384;
 constexpr int kCoefPad = 8;    // padding entries after the belt coefficient tables
 
 // Persistent blocks (or waves) drain a tile list. The list is cut into eight
@@ -265,7 +277,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
   }
   tot.se = fma(-2.0, e2, tot.se);
   tot.sb = fma(2.0, b2, tot.sb);
-  write_out<float>(a.out, a.n_out, a.scale, o, a.norm, tot, s);
+  write_map(a.out, a.out64, a.n_out, a.scale, o, a.norm, tot, s);
 }
 
 // ---- pixel variant, mixed precision: belt tile ------------------------------------
@@ -465,7 +477,7 @@ __device__ __forceinline__ void belt_tile(const PixelArgs& a, const ScaleArgs& s
     t.sv = A.sv[c];
     t.sw = A.sw[c];
     t.sn = (double)A.sn[c];
-    write_out<float>(a.out, a.n_out, a.scale, o0 + 4 * lane + c, a.norm, t, s);
+    write_map(a.out, a.out64, a.n_out, a.scale, o0 + 4 * lane + c, a.norm, t, s);
   }
 }
 
@@ -618,7 +630,7 @@ __device__ __forceinline__ void belt_tile_staged(const PixelArgs& a, const Scale
     t.sv = A.sv[c];
     t.sw = A.sw[c];
     t.sn = (double)A.sn[c];
-    write_out<float>(a.out, a.n_out, a.scale, o0 + 4 * lane + c, a.norm, t, s);
+    write_map(a.out, a.out64, a.n_out, a.scale, o0 + 4 * lane + c, a.norm, t, s);
   }
 }
 

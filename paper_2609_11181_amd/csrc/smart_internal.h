@@ -122,7 +122,8 @@ struct smart_plan_s {
   smart_data data = nullptr;
   int variant = 0;
   bool posb = false;  // galaxy variant with pixel-centre membership (sphS_posB)
-  int precision = 0;
+  int precision = 0;  // SMART_PREC_FP64 or SMART_PREC_FP32_GEO64
+  bool out64 = false;  // FP32 plan whose smart_run maps are double (SMART_PREC_FP32_OUT64)
   int nside_out = 0;
   int64_t n_out = 0;
   int64_t* out_pix = nullptr;
@@ -207,6 +208,7 @@ struct PixelArgs {
   void* out;          // [scale][5][n_out]
   int norm;
   int scale;
+  int out64;          // maps written as double (SMART_PREC_FP32_OUT64 plans)
   // general-walk tables of the scale (null: computed per centre)
   const int4* gt_head;      // [centre ring] = (first pair entry, first source ring, last source ring)
   const GenPair* gt_pair;
@@ -226,6 +228,7 @@ struct GalaxyArgs {
   void* out;
   int norm;
   int scale;
+  int out64;       // maps written as double (SMART_PREC_FP32_OUT64 plans)
   int explicit_v;  // V of a source is G.w (barycentre data)
   int posb;        // membership by the binning pixel's centre (sphS_posB)
 };
@@ -347,7 +350,19 @@ hipError_t launch_pixel_sums(smart_data d, const float* u, float4* sums, hipStre
 hipError_t launch_average(const float4* in, int64_t n, double omega, float4* out, hipStream_t st);
 hipError_t launch_rotate_map(const float4* map, const int* cidx, const float* u, int64_t n, float4* out,
                              hipStream_t st);
-int noise_bf16x3(smart_plan plan, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st);
+// Batched realisations through the split-BF16 stacks and the per-output
+// walks. Maps go to d_out laid out [n_scales][r_stride][2][n_out] with
+// realisation r at r_base + r (r_stride < 0: n_real); with mom non-null
+// the maps are not written and mom [n_scales][4][n_out] accumulates the sums
+// of E, E^2, B, B^2 over the realisations (n_real <= 32 per call then: one
+// realisation block per stack, so no two blocks update one output).
+int noise_bf16x3(smart_plan plan, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st,
+                 int r_stride = -1, int r_base = 0, double* mom = nullptr);
+constexpr int kNoiseChunk = 32;  // realisations per stack block (and per seeded chunk)
+// u[r][j] = Philox4x64-10 word j of key (seed, r_first + r), mapped to (0, 1)
+hipError_t launch_philox_u(uint64_t seed, int64_t r_first, int n_real, int64_t n_src, float* u, hipStream_t st);
+// mom [4][n_out] += (E, E^2, B, B^2) of the float maps eb [2][n_out]
+hipError_t launch_moments_add(const float* eb, int64_t n_out, double* mom, hipStream_t st);
 
 // autotuner (tune.cpp)
 int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st);
@@ -358,8 +373,12 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
 
 // filter tables (filters.cpp)
 int build_filter(FilterDef& f);
+// the general pixel walk's table in sin(theta) for one aperture, on the host
+std::vector<FilterPiece> sin_pieces_host(const FilterDef& f, double theta_ap);
 double filter_eval(const FilterDef& f, double x);
-ScaleArgs make_scale(smart_ctx ctx, double theta_ap, int filter_id, double omega_pix);
+// may_build = false: never allocate; a table filter whose sin(theta) table
+// was not built before (by plan creation) gets pieces = null
+ScaleArgs make_scale(smart_ctx ctx, double theta_ap, int filter_id, double omega_pix, bool may_build = true);
 
 // XCD-aware block order: the hardware deals consecutive workgroups to the
 // eight XCDs in turn; remap so that each XCD walks one contiguous range of

@@ -134,7 +134,7 @@ int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st
     }
     if (budget_ms <= 0 || spent_ms() > budget_ms) continue;  // keep the defaults
     if (!out) {
-      if (hipMalloc(&out, sizeof(float) * 5 * (size_t)p->n_out) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      if (hipMalloc(&out, (p->out64 ? sizeof(double) : sizeof(float)) * 5 * (size_t)p->n_out) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
           hipEventCreate(&e1) != hipSuccess) {
         cleanup();
         set_error("autotune: allocation failed");
@@ -153,6 +153,7 @@ int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st
     a.ring_hi = d->ring_hi;
     a.pix_first = d->pix_first;
     a.out = out;
+    a.out64 = p->out64 ? 1 : 0;
     a.norm = SMART_NORM_RAW;
     a.scale = 0;
     // median of three timed runs after one warm-up

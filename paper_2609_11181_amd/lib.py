@@ -12,15 +12,15 @@ LIB_PATH = os.path.join(HERE, "libsmartap.so")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5
 FILTER_POLY, FILTER_TANH, FILTER_TABLE = 0, 1, 2
 VAR_GALAXY, VAR_PIXEL, VAR_GALAXY_POSB = 0, 1, 2
-PREC_FP64, PREC_FP32_GEO64, PREC_BF16X3 = 0, 1, 2
+PREC_FP64, PREC_FP32_GEO64, PREC_BF16X3, PREC_FP32_OUT64 = 0, 1, 2, 3
 NORM_SUMMED_CAP, NORM_SUMMED_PIXCOUNT, NORM_RAW, NORM_AVERAGED = 0, 1, 2, 3
 
 EXPORTS = [
     "smart_init", "smart_finalize", "smart_last_error", "smart_version", "smart_filter_define",
-    "smart_filter_table", "smart_bin_galaxies", "smart_pixel_map", "smart_data_info", "smart_data_sources",
+    "smart_filter_table", "smart_filter_pieces", "smart_bin_galaxies", "smart_pixel_map", "smart_data_info", "smart_data_sources",
     "smart_data_export", "smart_barycentre_map",
     "smart_data_free", "smart_plan_create", "smart_run", "smart_last_pairs", "smart_plan_free",
-    "smart_noise_batch", "smart_noise_galaxy_batch", "smart_mixed_batch", "smart_plan_tiles",
+    "smart_noise_batch", "smart_noise_angles", "smart_noise_seeded", "smart_noise_galaxy_batch", "smart_mixed_batch", "smart_plan_tiles",
     "smart_plan_set_timing", "smart_plan_kernel_ms", "smart_autotune",
 ]
 
@@ -42,6 +42,7 @@ _SIGS = {
     "smart_version": (C.c_char_p, []),
     "smart_filter_define": (_int, [_vp, _int, C.POINTER(C.c_double), _int, C.POINTER(_int)]),
     "smart_filter_table": (_int, [_vp, _int, C.POINTER(C.c_float), C.POINTER(_int)]),
+    "smart_filter_pieces": (_int, [_vp, _int, C.c_double, C.POINTER(C.c_double), C.POINTER(_int)]),
     "smart_bin_galaxies": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, C.POINTER(_vp)]),
     "smart_pixel_map": (_int, [_vp, _int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
     "smart_data_info": (_int, [_vp, C.POINTER(_i64), C.POINTER(_int), C.POINTER(_i64), C.POINTER(_i64),
@@ -56,6 +57,8 @@ _SIGS = {
     "smart_plan_free": (None, [_vp]),
     "smart_noise_batch": (_int, [_vp, _vp, _int, _int, _int, _vp, _vp]),
     "smart_noise_galaxy_batch": (_int, [_vp, _vp, _int, _int, _vp, _vp]),
+    "smart_noise_angles": (_int, [_vp, C.c_uint64, _i64, _int, _i64, _vp, _vp]),
+    "smart_noise_seeded": (_int, [_vp, C.c_uint64, _i64, _int, _int, _int, _int, _vp, _vp]),
     "smart_barycentre_map": (_int, [_vp, _vp, _vp]),
     "smart_mixed_batch": (_int, [_vp, _int, C.POINTER(_vp), C.POINTER(_int), C.POINTER(_vp), _vp]),
     "smart_plan_tiles": (_int, [_vp, _int, C.POINTER(_int), C.POINTER(_int), _vp, _vp, _vp]),

@@ -42,7 +42,8 @@ def test_enums_match_header():
     src = open(os.path.join(ROOT, "include", "smartap.h")).read()
     for name, val in [("SMART_FILTER_TANH", L.FILTER_TANH), ("SMART_VAR_PIXEL", L.VAR_PIXEL),
                       ("SMART_PREC_BF16X3", L.PREC_BF16X3), ("SMART_NORM_RAW", L.NORM_RAW),
-                      ("SMART_EUNSUPPORTED", L.EUNSUPPORTED)]:
+                      ("SMART_EUNSUPPORTED", L.EUNSUPPORTED), ("SMART_PREC_FP32_OUT64", L.PREC_FP32_OUT64),
+                      ("SMART_FILTER_TABLE", L.FILTER_TABLE), ("SMART_NORM_AVERAGED", L.NORM_AVERAGED)]:
         m = re.search(rf"{name}\s*=\s*(-?\d+)", src)
         assert m and int(m.group(1)) == val, name
 

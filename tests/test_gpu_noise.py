@@ -99,3 +99,56 @@ def test_noise_batch_matches_plain_map_statistics(ctx):
     var = noise[:, 0].var(0)
     ratio = np.mean(var / main[2] ** 2)
     assert abs(ratio - 1.0) < 0.05, ratio
+
+
+def test_device_angles_bit_exact():
+    """smart_noise_angles draws exactly the oracle's counter-based angles,
+    for large seeds and realisation offsets and a ragged source count."""
+    import torch
+    from oracle import rng as R
+    from paper_2609_11181_amd import api
+
+    c = api.Context(0)
+    for seed, r0, nr, ns in [(7, 0, 3, 1001), (2 ** 63 + 12345, 1000, 2, 4099), (0, 5, 1, 3)]:
+        got = c.noise_angles(seed, r0, nr, ns).cpu().numpy()
+        assert np.array_equal(got, R.noise_angles(seed, r0, nr, ns)), (seed, r0, nr, ns)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [2, 1])
+def test_seeded_maps_and_moments(ctx, prec):
+    """smart_noise_seeded: the maps equal smart_noise_batch's on the angles
+    of smart_noise_angles (same kernels, bit for bit), for a realisation
+    range that starts past zero and ends in a partial chunk; the moments of
+    two calls over split ranges equal the sums over the maps; and one
+    realisation against the oracle with the oracle's own angles."""
+    import torch
+    from oracle import rng as R
+
+    L, m, data, inf, out_pix, _, _ = _setup(ctx, n_real=1, seed=7)
+    ths = [20 * ARCMIN, 45 * ARCMIN]
+    kinds = [F.TANH, F.POLY]
+    plan = ctx.plan(data, L.VAR_PIXEL, m["nside"], out_pix, ths, [ctx.filter(k) for k in kinds])
+    seed, r0, nr = 99, 30, 37 if prec == 2 else 5
+    n_src = data.n_sources()
+    maps = plan.noise_seeded(seed, r0, nr, L.NORM_SUMMED_PIXCOUNT, prec)
+    u = ctx.noise_angles(seed, r0, nr, n_src)
+    ref_maps = plan.noise_batch(u, nr, L.NORM_SUMMED_PIXCOUNT, prec)
+    assert torch.equal(maps, ref_maps)
+    mom = plan.noise_seeded(seed, r0, 3, L.NORM_SUMMED_PIXCOUNT, prec, moments=True)
+    plan.noise_seeded(seed, r0 + 3, nr - 3, L.NORM_SUMMED_PIXCOUNT, prec, moments=True, out=mom)
+    md = maps.double()
+    want = torch.stack([md[:, :, 0].sum(1), (md[:, :, 0] ** 2).sum(1), md[:, :, 1].sum(1), (md[:, :, 1] ** 2).sum(1)],
+                       dim=1)
+    scale = torch.abs(want).amax(dim=2, keepdim=True)
+    assert torch.max(torch.abs(mom - want) / scale) < 1e-9
+    # realisation r0 + 1 against the oracle, angles drawn by the oracle
+    ur = R.noise_angles(seed, r0 + 1, 1, n_src)[0].astype(np.float64)
+    out = maps.cpu().numpy()
+    tol = 1e-4 if prec == 2 else 1e-6
+    for k, (th, kind) in enumerate(zip(ths, kinds)):
+        ref = _oracle_real(m, inf, ur, out_pix, th, kind)
+        ok = ~ref["tie"]
+        for e, key in enumerate(["M_E", "M_B"]):
+            rms = math.sqrt(np.mean(ref[key][ok] ** 2))
+            assert np.max(np.abs(out[k, 1, e][ok] - ref[key][ok])) / rms <= tol, (k, key)

@@ -70,3 +70,24 @@ def test_posB_rejects_fp64(ctx):
     data = ctx.bin_galaxies(cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat["w"], nside_bin=128)
     with pytest.raises(L.SmartError):
         ctx.plan(data, L.VAR_GALAXY_POSB, 128, np.arange(10), [30 * ARCMIN], [ctx.filter(F.TANH)], precision=0)
+
+
+def test_plan_and_norm_refusals(ctx):
+    """sphS_posB selects galaxies of a binned catalogue: barycentre data
+    (already one source per pixel) is refused; the pixel-count area is
+    refused for galaxy sources (N counts galaxies there, not pixels), and
+    accepted for barycentre data."""
+    from paper_2609_11181_amd import lib as L
+
+    cat = small_catalogue(5000, seed=3, cap_radius=3 * DEG, centre=(1.0, 0.3))
+    data = ctx.bin_galaxies(cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat["w"], nside_bin=128, pixel_sums=True)
+    fid = ctx.filter(F.TANH)
+    bary = data.barycentre()
+    with pytest.raises(L.SmartError):
+        ctx.plan(bary, L.VAR_GALAXY_POSB, 128, np.arange(10), [30 * ARCMIN], [fid])
+    for var in (L.VAR_GALAXY, L.VAR_GALAXY_POSB):
+        plan = ctx.plan(data, var, 128, np.arange(10), [30 * ARCMIN], [fid])
+        with pytest.raises(L.SmartError):
+            plan.run(L.NORM_SUMMED_PIXCOUNT)
+        plan.run(L.NORM_SUMMED_CAP)
+    ctx.plan(bary, L.VAR_GALAXY, 128, np.arange(10), [30 * ARCMIN], [fid]).run(L.NORM_SUMMED_PIXCOUNT)
