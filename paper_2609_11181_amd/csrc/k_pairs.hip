@@ -232,6 +232,69 @@ __device__ __forceinline__ int ring_slices(const Ring& Q, int64_t jlo, int cnt, 
   return 1;
 }
 
+// One galaxy of a candidate slice for the centre at (px, py, pz): the exact
+// FP64 chord test (the brute-force membership, Sect. 3.1), then the spin-2
+// rotation from unnormalised tangent-plane components, the filter from the
+// chord and the sums.
+template <bool TABLE, bool BIG>
+__device__ __forceinline__ void galaxy_member(const GalaxyArgs& a, const ScaleArgs& s, int64_t g, double px,
+                                              double py, double pz, bool posb, const double* cp, Tab tab,
+                                              Acc64& tot, Acc32& acc, int& nacc) {
+  const double4 P = a.P[g];
+  const double dx = px - P.x, dy = py - P.y, dz = pz - P.z;
+  const double c2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  const bool inside = c2 < s.C_ap;
+  if (!(inside || posb)) return;
+  const float4 G = a.G[g];
+  // tangent-plane components at the galaxy, unnormalised (both scaled by
+  // cos dec, which cancels in the rotation):
+  //   X = x dy - y dx,  Y = (x^2 + y^2) dz - z (x dx + y dy)
+  double X = P.x * dy - P.y * dx;
+  double Y = fma(P.x, P.x, P.y * P.y) * dz - P.z * fma(P.x, dx, P.y * dy);
+  if (P.x == 0.0 && P.y == 0.0) {  // galaxy on a pole: frame from its ra
+    const float4 F = a.F[g];
+    X = dy * F.x - dx * F.y;
+    Y = -P.z * (dx * F.x + dy * F.y);
+  }
+  const double D = fma(X, X, Y * Y);
+  const double i0 = (double)__builtin_amdgcn_rcpf((float)D);
+  double inv = i0 * fma(-D, i0, 2.0);
+  inv = c2 >= (double)kCoincidentS2 ? inv : 0.0;
+  const double c2p = fma(Y, Y, -X * X) * inv;
+  const double s2p = -2.0 * X * Y * inv;
+  // x = 2 asin(c/2) / theta_ap from the chord c
+  const double rc0 = (double)__builtin_amdgcn_rsqf((float)c2);
+  const double rc = rc0 * fma(-0.5 * c2, rc0 * rc0, 1.5);
+  const double cd = c2 >= (double)kCoincidentS2 ? c2 * rc : 0.0;
+  // beyond theta_ap (sphS_posB members only) the filter is zero; the table
+  // lookup clamps its index, so the evaluation stays in range
+  const double q = inside ? filter_q<TABLE>(theta_ratio<BIG>(cd, c2, cp), tab) : 0.0;
+  const float w = G.z;
+  const double wd = (double)w;
+  accumulate(q * c2p, q * s2p, (float)q, wd * (double)G.x, wd * (double)G.y, w,
+             a.explicit_v ? G.w : w * w * fmaf(G.x, G.x, G.y * G.y), 1, tot, acc);
+  if (++nacc == kChunk) {
+    tot.add(acc);
+    acc = Acc32();
+    nacc = 0;
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Galaxy variant, FP32 plans: one wave per aperture centre. The lanes first
+// find the centre's catalogue slices together (lane l the window of
+// partition ring lo + l, 64 rings per pass; Sect. 3.4: each window of
+// binning pixels is a contiguous run of sorted rows), then stream every
+// slice with consecutive lanes on consecutive rows (coalesced 48-byte
+// records, neighbouring centres of the wave's XCD reading the same rows
+// from its L2), and finally reduce their partial sums across the wave.
+// Persistent: waves take centres in a fixed interleave within their XCD's
+// contiguous eighth of the output list.
 template <bool TABLE, bool BIG>
 __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s) {
   __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
@@ -244,88 +307,71 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
     __syncthreads();
   }
   const Tab tab{tab_c, tab_c0};
-  const int64_t o = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (o >= a.n_out) return;
   double cp[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) cp[k] = s.cpoly[k];
-
-  int rp, ip;
-  pixel_ring(a.nside_out, a.out_pix[o], &rp, &ip);
-  const Ring R = ring_info(a.nside_out, rp);
-  const double zp = R.z, sp = R.s;
-  const int64_t ip2 = 2 * (int64_t)ip + R.twice_o;
-  double sphi, cphi;
-  sincospi((double)ip2 / (double)R.n, &sphi, &cphi);  // phi_p = pi ip2 / n
-  const double px = sp * cphi, py = sp * sphi, pz = zp;
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int xcd = blockIdx.x & 7;
+  const int64_t waves_x = (int64_t)(gridDim.x >> 3) * wpb;  // waves per XCD (grid is a multiple of 8)
+  const int64_t wid = (int64_t)(blockIdx.x >> 3) * wpb + (threadIdx.x >> 6);
+  const int64_t o_begin = a.n_out * xcd / 8, o_end = a.n_out * (xcd + 1) / 8;
+  const bool posb = a.posb != 0;
   // candidate pixels: those within theta_ap + r_bin (every galaxy within
   // theta_ap lies in one), or, for sphS_posB, exactly the pixels whose
   // centres lie within theta_ap (all of their galaxies are members)
-  const bool posb = a.posb != 0;
   const double rad = posb ? s.theta_ap * (1.0 + 1e-9) + 1e-12 : s.theta_ap + a.r_bin * (1.0 + 1e-9) + 1e-12;
   const double sh = sin(0.5 * rad);
   const double Cw = posb ? s.C_ap : 4.0 * sh * sh;
-  int lo, hi;
-  ring_span(a.nside_bin, atan2(sp, zp), rad, &lo, &hi);
-
-  Acc64 tot;
-  for (int r = lo; r <= hi; ++r) {
-    const Ring Q = ring_info(a.nside_bin, r);
-    int64_t jlo;
-    int cnt;
-    if (!ring_window(zp, sp, ip2, R.n, Q, Cw, &jlo, &cnt)) continue;
-    int64_t ja[2], jb[2];
-    const int ns = ring_slices(Q, jlo, cnt, posb ? 0 : 1, ja, jb);
-    for (int t = 0; t < ns; ++t) {
-      const int64_t g0 = a.offsets[Q.first + ja[t]];
-      const int64_t g1 = a.offsets[Q.first + jb[t] + 1];
-      Acc32 acc;
-      int nacc = 0;
-      for (int64_t g = g0; g < g1; ++g) {
-        const double4 P = a.P[g];
-        const double dx = px - P.x, dy = py - P.y, dz = pz - P.z;
-        const double c2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const bool inside = c2 < s.C_ap;
-        if (inside || posb) {
-          const float4 G = a.G[g];
-          // tangent-plane components at the galaxy, unnormalised (both
-          // scaled by cos dec, which cancels in the rotation):
-          //   X = x dy - y dx,  Y = (x^2 + y^2) dz - z (x dx + y dy)
-          double X = P.x * dy - P.y * dx;
-          double Y = fma(P.x, P.x, P.y * P.y) * dz - P.z * fma(P.x, dx, P.y * dy);
-          if (P.x == 0.0 && P.y == 0.0) {  // galaxy on a pole: frame from its ra
-            const float4 F = a.F[g];
-            X = dy * F.x - dx * F.y;
-            Y = -P.z * (dx * F.x + dy * F.y);
-          }
-          const double D = fma(X, X, Y * Y);
-          const double i0 = (double)__builtin_amdgcn_rcpf((float)D);
-          double inv = i0 * fma(-D, i0, 2.0);
-          inv = c2 >= (double)kCoincidentS2 ? inv : 0.0;
-          const double c2p = fma(Y, Y, -X * X) * inv;
-          const double s2p = -2.0 * X * Y * inv;
-          // x = 2 asin(c/2) / theta_ap from the chord c
-          const double rc0 = (double)__builtin_amdgcn_rsqf((float)c2);
-          const double rc = rc0 * fma(-0.5 * c2, rc0 * rc0, 1.5);
-          const double cd = c2 >= (double)kCoincidentS2 ? c2 * rc : 0.0;
-          // beyond theta_ap (sphS_posB members only) the filter is zero; the
-          // table lookup clamps its index, so the evaluation stays in range
-          const double q = inside ? filter_q<TABLE>(theta_ratio<BIG>(cd, c2, cp), tab) : 0.0;
-          const float w = G.z;
-          const double wd = (double)w;
-          accumulate(q * c2p, q * s2p, (float)q, wd * (double)G.x, wd * (double)G.y, w,
-                     a.explicit_v ? G.w : w * w * fmaf(G.x, G.x, G.y * G.y), 1, tot, acc);
-          if (++nacc == kChunk) {
-            tot.add(acc);
-            acc = Acc32();
-            nacc = 0;
+  for (int64_t o = o_begin + wid; o < o_end; o += waves_x) {
+    int rp, ip;
+    pixel_ring(a.nside_out, a.out_pix[o], &rp, &ip);
+    const Ring R = ring_info(a.nside_out, rp);
+    const double zp = R.z, sp = R.s;
+    const int64_t ip2 = 2 * (int64_t)ip + R.twice_o;
+    double sphi, cphi;
+    sincospi((double)ip2 / (double)R.n, &sphi, &cphi);  // phi_p = pi ip2 / n
+    const double px = sp * cphi, py = sp * sphi, pz = zp;
+    int lo, hi;
+    ring_span(a.nside_bin, atan2(sp, zp), rad, &lo, &hi);
+    Acc64 tot;
+    Acc32 acc;
+    int nacc = 0;
+    for (int r0 = lo; r0 <= hi; r0 += 64) {
+      // this lane's ring: its window as at most two row ranges
+      int64_t ga[2] = {0, 0}, gb[2] = {0, 0};
+      const int r = r0 + lane;
+      if (r <= hi) {
+        const Ring Q = ring_info(a.nside_bin, r);
+        int64_t jlo;
+        int cnt;
+        if (ring_window(zp, sp, ip2, R.n, Q, Cw, &jlo, &cnt)) {
+          int64_t ja[2], jb[2];
+          const int ns = ring_slices(Q, jlo, cnt, 0, ja, jb);
+          for (int t = 0; t < ns; ++t) {
+            ga[t] = a.offsets[Q.first + ja[t]];
+            gb[t] = a.offsets[Q.first + jb[t] + 1];
           }
         }
       }
-      tot.add(acc);
+      const int nl = min(64, hi - r0 + 1);
+      for (int l = 0; l < nl; ++l) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int64_t g0 = __shfl(ga[t], l, 64), g1 = __shfl(gb[t], l, 64);
+          for (int64_t g = g0 + lane; g < g1; g += 64)
+            galaxy_member<TABLE, BIG>(a, s, g, px, py, pz, posb, cp, tab, tot, acc, nacc);
+        }
+      }
     }
+    tot.add(acc);
+    tot.se = wave_sum(tot.se);
+    tot.sb = wave_sum(tot.sb);
+    tot.sw = wave_sum(tot.sw);
+    tot.sv = wave_sum(tot.sv);
+    tot.sn = wave_sum(tot.sn);
+    if (lane == 0) write_map(a.out, a.out64, a.n_out, a.scale, o, a.norm, tot, s);
   }
-  write_map(a.out, a.out64, a.n_out, a.scale, o, a.norm, tot, s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_galaxy_f64(GalaxyArgs a, ScaleArgs s) {
@@ -543,11 +589,23 @@ hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision,
   if (precision == SMART_PREC_FP64) {
     hipLaunchKernelGGL(k_galaxy_f64, grid, block, 0, st, a, s);
   } else {
+    // persistent waves: the occupancy maximum on every compute unit, a
+    // multiple of the eight XCDs
     const bool table = s.filter_kind != SMART_FILTER_POLY;
-    if (table && s.big) hipLaunchKernelGGL((k_galaxy_f32<true, true>), grid, block, 0, st, a, s);
-    else if (table) hipLaunchKernelGGL((k_galaxy_f32<true, false>), grid, block, 0, st, a, s);
-    else if (s.big) hipLaunchKernelGGL((k_galaxy_f32<false, true>), grid, block, 0, st, a, s);
-    else hipLaunchKernelGGL((k_galaxy_f32<false, false>), grid, block, 0, st, a, s);
+    auto go = [&](auto kern, int per_cu) {
+      const int64_t need = (a.n_out + kBlock / 64 - 1) / (kBlock / 64);  // one wave per centre at most
+      int64_t blocks = std::min<int64_t>((int64_t)device_cus() * per_cu, need);
+      blocks = std::max<int64_t>(8, (blocks + 7) / 8 * 8);
+      hipLaunchKernelGGL(kern, dim3((unsigned)blocks), block, 0, st, a, s);
+    };
+    static const int occ[4] = {persistent_per_cu(k_galaxy_f32<false, false>),
+                               persistent_per_cu(k_galaxy_f32<false, true>),
+                               persistent_per_cu(k_galaxy_f32<true, false>),
+                               persistent_per_cu(k_galaxy_f32<true, true>)};
+    if (table && s.big) go(k_galaxy_f32<true, true>, occ[3]);
+    else if (table) go(k_galaxy_f32<true, false>, occ[2]);
+    else if (s.big) go(k_galaxy_f32<false, true>, occ[1]);
+    else go(k_galaxy_f32<false, false>, occ[0]);
   }
   return hipGetLastError();
 }
