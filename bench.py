@@ -60,6 +60,8 @@ def parse():
     p.add_argument("--no-mixed", action="store_true", help="skip the uneven mixed-batch leg")
     p.add_argument("--no-averaged", action="store_true", help="skip the averaged-normalisation leg")
     p.add_argument("--only-mixed", action="store_true", help="run only the uneven mixed-batch leg")
+    p.add_argument("--no-config2", action="store_true", help="skip the brute-force galaxy-variant leg")
+    p.add_argument("--only-config2", action="store_true", help="run only the brute-force galaxy-variant leg")
     p.add_argument("--mixed-area-scale", type=float, default=1.0, help="scale of the mixed-batch cap areas")
     p.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                    help="only run a plain device copy of GIB GiB three times (HBM counter calibration)")
@@ -152,6 +154,113 @@ def cpu_baseline(pm, R, scales, n_out, workers, seed=11):
     avg_pix = out_pix[:1000]
     avg_ref = A.aperture_mass_pixel(sub, avg_pix, scales[0], F.TANH, norm=A.NORM_AVERAGED)
     return out_pix, refs, pairs, dt, (avg_pix, avg_ref)
+
+
+def config2_leg(ctx, args):
+    """Brute-force galaxy variant (Sect. 3.1): 5e7 galaxies in a 1000 deg^2
+    cap (about 14 galaxies/arcmin^2, 500 SIS halos), maps at every NSIDE-2048
+    pixel centre in the cap, theta_ap = 10', tanh filter, FP32 pair sums with
+    FP64 geometry and double maps; catalogue partitioned at NSIDE 4096 (the
+    partition only selects candidates; every galaxy gets the exact test).
+    Also the sphS_posB / sphS_pos ratio on an NSIDE-2048 partition (posB
+    selects the binning pixels centred in the aperture, Sect. 3.4)."""
+    import torch
+
+    from oracle import healpix_ref as hp
+    from paper_2609_11181_amd import lib as L
+    from synth import config2_catalogue
+
+    t = time.perf_counter()
+    cat, R = config2_catalogue()
+    log(f"config-2 leg: generated {cat['ra'].size} galaxies in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda", 0)
+    cols = [torch.from_numpy(cat[k]).to(dev) for k in ("ra", "dec", "g1", "g2", "w")]
+    nside = 2048
+    rt = hp.ring_table(nside)
+    rings = np.nonzero(np.abs(np.arcsin(rt["z"])) < R)[0]
+    pix = np.arange(rt["first"][rings[0]], rt["first"][rings[-1]] + rt["n"][rings[-1]])
+    v = hp.pix2vec(nside, pix)
+    out_pix = pix[v[:, 0] > math.cos(R)]
+    th = 10 * ARCMIN
+    fid = ctx.filter(L.FILTER_TANH)
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {"workload": f"sphS_pos brute force, {cat['ra'].size:.3g} galaxies in a 1000 deg2 cap, "
+                       f"{out_pix.size} NSIDE-2048 centres, theta_ap 10 arcmin, tanh filter, double maps"}
+
+    def timed(plan, out, n=3):
+        plan.run(L.NORM_SUMMED_CAP, out)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(n):
+            plan.run(L.NORM_SUMMED_CAP, out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / n
+
+    data = ctx.bin_galaxies(*cols, nside_bin=4096)
+    plan = ctx.plan(data, L.VAR_GALAXY, nside, out_pix, [th], [fid], precision=L.PREC_FP32_OUT64)
+    out = plan.empty_out()
+    ms = timed(plan, out)
+    pairs = plan.last_pairs()
+    achieved = pairs * OPS_PER_PAIR / (ms / 1e3)
+    res.update({"run_ms": ms, "pairs": pairs, "pair_evals_per_s": pairs / (ms / 1e3),
+                "roofline": {"bound": "alu", "kernel": "k_galaxy_f32", "achieved": achieved / 1e12,
+                             "peak": ALU_PEAK / 1e12, "unit": "Tlane-op/s", "frac": achieved / ALU_PEAK,
+                             "ops_per_pair": OPS_PER_PAIR}})
+    log(f"config-2: {ms:.2f} ms, {pairs:.4e} pairs, {pairs / (ms / 1e3):.3e} pair-evals/s")
+    if not args.no_cpu:
+        res.update(config2_accuracy(cat, R, out_pix, out[0].cpu().numpy(), th))
+    del out
+    plan.free()
+    data.free()
+    # posB against the brute force on the map's own NSIDE partition
+    data2 = ctx.bin_galaxies(*cols, nside_bin=nside)
+    for name, var in (("pos", L.VAR_GALAXY), ("posB", L.VAR_GALAXY_POSB)):
+        p2 = ctx.plan(data2, var, nside, out_pix, [th], [fid], precision=L.PREC_FP32_OUT64)
+        o2 = p2.empty_out()
+        res[f"{name}_nside2048_partition_ms"] = timed(p2, o2)
+        p2.free()
+    res["posB_speedup_vs_pos"] = res["pos_nside2048_partition_ms"] / res["posB_nside2048_partition_ms"]
+    res["posB_note"] = "the paper reports about 2x for posB over pos on its CPU (Table 2)"
+    data2.free()
+    del cols
+    return res
+
+
+def config2_accuracy(cat, R, out_pix, out, th, n_check=1024, seed=21):
+    """Oracle on 768 apertures in a 1-degree patch inside the field and 256
+    at its edge: max error over the whole-map RMS and the paper's relative
+    difference (Sect. 5.1) per channel."""
+    from oracle import aperture as A
+    from oracle import filters as F
+    from oracle import healpix_ref as hp
+
+    rng = np.random.default_rng(seed)
+    vo = hp.pix2vec(2048, out_pix)
+    gv = A.radec2vec(cat["ra"], cat["dec"])
+    sels, refs = [], []
+    for anchor, n in ((A.radec2vec(0.1, -0.05), 3 * n_check // 4), (A.radec2vec(R - 0.2 * math.pi / 180, 0.0),
+                                                                     n_check // 4)):
+        near = np.nonzero(vo @ anchor > math.cos(math.pi / 180))[0]
+        sel = np.sort(rng.choice(near, n, replace=False))
+        keep = gv @ anchor > math.cos(math.pi / 180 + th + 0.002)
+        sub = {k: cat[k][keep] for k in ("ra", "dec", "g1", "g2", "w")}
+        ra, dec = hp.pix2radec(2048, out_pix[sel])
+        sels.append(sel)
+        refs.append(A.aperture_mass_galaxy(sub, ra, dec, th, F.TANH))
+    sel = np.concatenate(sels)
+    errs, eps = {}, {}
+    for ch, key in enumerate(("M_E", "M_B", "sigma")):
+        ref = np.concatenate([r[key] for r in refs])
+        ok = ~np.concatenate([r["tie"] for r in refs])
+        full = out[ch]
+        d = out[ch][sel][ok] - ref[ok]
+        errs[key] = float(np.max(np.abs(d)) / math.sqrt(np.mean(full * full)))
+        eps[key] = {"mean": float(np.mean(d / np.std(full))), "std": float(np.std(d / np.std(full)))}
+    return {"max_rel_err_vs_oracle": errs, "epsilon_vs_oracle": eps,
+            "accuracy_sample": f"{sel.size} apertures (768 in a 1-degree patch, 256 at the field edge), "
+                               "error over the whole-map RMS"}
 
 
 def batched_leg(ctx, args):
@@ -457,7 +566,7 @@ def main():
 
     from synth import config3_pixelmap
 
-    if not (args.only_batched or args.only_mixed):
+    if not (args.only_batched or args.only_mixed or args.only_config2):
         t = time.perf_counter()
         pm, R = config3_pixelmap(area_deg2=args.area, nside=args.nside)
         log(f"generated {pm['pix'].size} pixels in {time.perf_counter() - t:.1f}s")
@@ -476,6 +585,9 @@ def main():
         return
     if args.only_mixed:
         print(json.dumps({"mixed": mixed_leg(api.Context(0), args)}), flush=True)
+        return
+    if args.only_config2:
+        print(json.dumps({"config2": config2_leg(api.Context(0), args)}), flush=True)
         return
 
     dev = torch.device("cuda", 0)
@@ -679,6 +791,12 @@ def main():
             "sample": f"{out_pix.size} apertures x 3 scales in a 2-degree patch of the same map "
                       f"({cpairs} pairs, {cdt:.1f} s wall, numpy FP64, apertures split over {workers} processes)",
         }
+    if not args.no_config2:
+        keep.clear()
+        del outs, out3, cols, pix, out_avg
+        outs = out3 = cols = pix = out_avg = None
+        torch.cuda.empty_cache()
+        res["config2"] = config2_leg(ctx, args)
     if not args.no_batched:
         keep.clear()
         del outs, out3, cols, pix, out_avg
