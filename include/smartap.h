@@ -412,6 +412,25 @@ int smart_noise_galaxy_batch(smart_plan plan, const float* d_u, int n_real, int 
 int smart_mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* d_outs,
                       void* stream);
 
+/* smart_mixed_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid
+ * allocation): the same launch and results, with the work list, the jobs and
+ * the claim counters in a fixed workspace that the library keeps per device
+ * for the life of the process (64.2 MiB; its address is resolved at
+ * smart_init), instead of stream-ordered scratch. Allocates nothing and
+ * copies the job table from host memory on `stream`.
+ *   Limits: at most 4194304 work items (a belt item or a quarter of a general
+ *   tile of 256 outputs) and 512 jobs (plan-scale pairs); SMART_EINVAL beyond
+ *   them, nothing launched.
+ *   Averaged normalisation only when the map's averaged records already
+ *   exist (an earlier averaged smart_run, smart_noise_batch or
+ *   smart_mixed_batch built them), SMART_EINVAL otherwise.
+ * Every call on a device shares that device's workspace: calls that overlap
+ * on one device (different streams, or threads) race and must be ordered by
+ * the caller; calls on one stream are ordered. */
+int smart_mixed_batch_noalloc(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms,
+                              void* const* d_outs, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

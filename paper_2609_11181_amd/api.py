@@ -139,7 +139,9 @@ class Context:
         L.check(self.lib.smart_noise_angles(self.h, seed, r_first, n_real, n_src, p, _stream(self.device)))
         return out
 
-    def mixed_batch(self, plans, norms, outs):
+    def mixed_batch(self, plans, norms, outs, noalloc=False):
+        """All plans in one persistent launch (smart_mixed_batch, or with
+        noalloc=True smart_mixed_batch_noalloc: no device allocation)."""
         n = len(plans)
         if len(norms) != n or len(outs) != n:
             raise ValueError("plans, norms and outs must have the same length")
@@ -147,7 +149,8 @@ class Context:
         nh = (C.c_int * n)(*norms)
         oh = (C.c_void_p * n)(*[_buf(o, self.device, p.out_dtype, p.n_scales * 5 * p.n_out, "out").value or 0
                                 for p, o in zip(plans, outs)])
-        L.check(self.lib.smart_mixed_batch(self.h, n, ph, nh, oh, _stream(self.device)))
+        fn = self.lib.smart_mixed_batch_noalloc if noalloc else self.lib.smart_mixed_batch
+        L.check(fn(self.h, n, ph, nh, oh, _stream(self.device)))
 
 
 class Data:

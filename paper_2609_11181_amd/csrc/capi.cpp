@@ -129,6 +129,8 @@ int smart_init(int hip_device, smart_ctx* out) {
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(SMART_EDEVICE, "no HIP device");
   if (hip_device < 0 || hip_device >= count) return fail(SMART_EINVAL, "device index out of range");
   if (hipSetDevice(hip_device) != hipSuccess) return fail(SMART_EDEVICE, "hipSetDevice failed");
+  int rc = mixed_workspace_setup(hip_device);  // the fixed workspace's address on this device
+  if (rc) return rc;
   smart_ctx c = new smart_ctx_s();
   c->device = hip_device;
   *out = c;
@@ -751,6 +753,26 @@ int smart_mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const
   for (int k = 0; k < n_plans; ++k)
     if (norms[k] == SMART_NORM_AVERAGED && (rc = ensure_averaged(plans[k]->data, (hipStream_t)stream))) return rc;
   return mixed_batch(ctx, n_plans, plans, norms, d_outs, (hipStream_t)stream);
+}
+
+int smart_mixed_batch_noalloc(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms,
+                              void* const* d_outs, void* stream) {
+  if (!ctx || n_plans < 1 || !plans || !norms || !d_outs) return fail(SMART_EINVAL, "bad arguments");
+  for (int k = 0; k < n_plans; ++k) {
+    if (!plans[k] || !d_outs[k]) return fail(SMART_EINVAL, "NULL plan or output");
+    if (plans[k]->ctx != ctx) return fail(SMART_EINVAL, "plan belongs to another context");
+    if (plans[k]->variant != SMART_VAR_PIXEL || plans[k]->precision != SMART_PREC_FP32_GEO64)
+      return fail(SMART_EINVAL, "mixed batches take pixel-variant FP32 plans");
+  }
+  int rc;
+  for (int k = 0; k < n_plans; ++k) {
+    if ((rc = check_norm(plans[k], norms[k]))) return rc;
+    // the averaged records are built (and allocated) by an allocating call
+    if (norms[k] == SMART_NORM_AVERAGED && !plans[k]->data->avg && plans[k]->data->n_dense > 0)
+      return fail(SMART_EINVAL, "the map's averaged records do not exist yet: run an allocating averaged call first");
+  }
+  if ((rc = set_device(ctx))) return rc;
+  return mixed_batch_noalloc(ctx, n_plans, plans, norms, d_outs, (hipStream_t)stream);
 }
 
 }  // extern "C"

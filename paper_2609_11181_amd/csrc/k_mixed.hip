@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -245,7 +246,39 @@ int launch_mixed(const MixPlan& mp, int4* items, MixJob* d_jobs, int* counter, h
   return SMART_OK;
 }
 
+// Fixed workspace of the allocation-free entry point: the work list (16
+// bytes per item), the jobs and the claim counters of one launch. Each
+// device holds its own copy for the life of the process; host code reaches
+// it only through the address resolved per device (g_ws).
+constexpr int64_t kWsItems = int64_t(1) << 22;
+constexpr int kWsJobs = 512;
+constexpr size_t kWsItemBytes = sizeof(int4) * (size_t)kWsItems;
+constexpr size_t kWsJobBytes = (sizeof(MixJob) * kWsJobs + 255) & ~(size_t)255;
+constexpr size_t kWsBytes = kWsItemBytes + kWsJobBytes + sizeof(int) * kQueueInts;
+static __device__ __align__(256) unsigned char scratch[kWsBytes];
+
+constexpr int kWsDevices = 64;
+void* g_ws[kWsDevices] = {};
+std::mutex g_ws_mutex;
+
 }  // namespace
+
+int mixed_workspace_setup(int device) {
+  if (device < 0 || device >= kWsDevices) {
+    set_error("mixed batch workspace: device index beyond the supported count");
+    return SMART_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_ws_mutex);
+  if (g_ws[device]) return SMART_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    set_error(std::string("mixed batch workspace: hipGetSymbolAddress failed: ") + hipGetErrorString(e));
+    return SMART_EDEVICE;
+  }
+  g_ws[device] = p;
+  return SMART_OK;
+}
 
 int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,
                 hipStream_t st) {
@@ -263,6 +296,26 @@ int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* 
   scratch_free(d_jobs, st);
   scratch_free(counter, st);
   return rc;
+}
+
+int mixed_batch_noalloc(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,
+                        hipStream_t st) {
+  void* ws = (ctx->device >= 0 && ctx->device < kWsDevices) ? g_ws[ctx->device] : nullptr;
+  if (!ws) {
+    set_error("mixed batch workspace not set up on this device");
+    return SMART_EINTERNAL;
+  }
+  MixPlan mp;
+  int rc = prepare_mixed(ctx, n_plans, plans, norms, outs, false, &mp);
+  if (rc || mp.groups.empty()) return rc;
+  if (mp.n_items > kWsItems || (int64_t)mp.jobs.size() > kWsJobs) {
+    set_error("mixed batch without allocation: " + std::to_string(mp.n_items) + " work items and " +
+              std::to_string(mp.jobs.size()) + " jobs exceed the fixed workspace (" + std::to_string(kWsItems) +
+              " items, " + std::to_string(kWsJobs) + " jobs)");
+    return SMART_EINVAL;
+  }
+  unsigned char* b = (unsigned char*)ws;
+  return launch_mixed(mp, (int4*)b, (MixJob*)(b + kWsItemBytes), (int*)(b + kWsItemBytes + kWsJobBytes), st);
 }
 
 }  // namespace smart

@@ -370,6 +370,13 @@ int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st
 // mixed batch (k_mixed.hip)
 int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,
                 hipStream_t st);
+// The same launch with its work list, jobs and claim counters in the
+// library's fixed per-device workspace instead of allocated scratch.
+int mixed_batch_noalloc(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,
+                        hipStream_t st);
+// Resolves the fixed workspace's address on the current device (once per
+// device; smart_init calls it).
+int mixed_workspace_setup(int device);
 
 // filter tables (filters.cpp)
 int build_filter(FilterDef& f);
