@@ -412,6 +412,30 @@ int smart_noise_galaxy_batch(smart_plan plan, const float* d_u, int n_real, int 
 int smart_mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* d_outs,
                       void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Detection                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Detection step (Sect. 6.1): the pixels of a map whose value is strictly
+ * higher than the values of all their direct HEALPix neighbours (eight;
+ * seven for the 24 pixels at the corners where three base faces meet),
+ * and at least `threshold`, or, with d_noise_sd non-NULL, whose value over
+ * the noise standard deviation of the same pixel is at least `threshold`
+ * (a pixel without a positive noise value is no detection). A pixel with a
+ * neighbour that is not in the map (the field's edge) is no detection.
+ *   d_pix      : n int64 RING pixels at nside, strictly increasing
+ *   d_val      : n doubles, the map (e.g. the M_E channel of smart_run with
+ *                SMART_PREC_FP32_OUT64, or any other map on these pixels)
+ *   d_noise_sd : n doubles or NULL
+ *   d_peaks    : device buffer of n int64: the detections, increasing
+ *   h_n_peaks  : receives their number (host)
+ * Allocates stream-ordered scratch of 8 bytes per pixel of the range
+ * [d_pix[0], d_pix[n-1]] plus 4 bytes per map pixel. Synchronises `stream`
+ * (pixel check, detection count). */
+int smart_detect_peaks(smart_ctx ctx, int nside, int64_t n, const int64_t* d_pix, const double* d_val,
+                       const double* d_noise_sd, double threshold, int64_t* d_peaks, int64_t* h_n_peaks,
+                       void* stream);
+
 /* smart_mixed_batch for callers that cannot allocate device memory (code
  * under HIP graph capture, serving loops, harnesses that forbid
  * allocation): the same launch and results, with the work list, the jobs and

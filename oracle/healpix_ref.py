@@ -180,3 +180,145 @@ def disc_brute(nside: int, vec, radius: float):
     d = v - np.asarray(vec)[None, :]
     c2 = (d * d).sum(1)
     return np.nonzero(c2 < 4.0 * math.sin(0.5 * radius) ** 2)[0]
+
+
+# ---------------------------------------------------------------------------
+# Face coordinates and pixel neighbours (for the detection step, Sect. 6.1)
+# ---------------------------------------------------------------------------
+#
+# The 12 base pixels (faces) of the construction are curvilinear squares,
+# each cut into N x N cells. Face f gets continuous coordinates (alpha,
+# beta) in [0, N)^2, (0, 0) at its northern corner, alpha growing to the
+# south-east and beta to the south-west; cell (floor alpha, floor beta) is
+# one pixel. In the belt these are the two edge-line coordinates of the
+# point->pixel construction, Jp = N (1/2 + tt - 3z/4) and
+# Jm = N (1/2 + tt + 3z/4) (tt = 2 phi / pi), shifted per face; in the caps
+# they are tp * t and (1 - tp) * t (t = N sqrt(3 (1 - |z|)), tp = tt mod 1),
+# measured from the pole for the north faces and turned round for the south
+# ones. Both forms agree on |z| = 2/3.
+
+def face_coords(nside: int, z, tt, omz):
+    """(face, alpha, beta) of points given by z, tt = 2 phi / pi in [0, 4)
+    and omz = 1 - |z|."""
+    N = float(nside)
+    z = np.asarray(z, np.float64)
+    tt = np.asarray(tt, np.float64)
+    omz = np.asarray(omz, np.float64)
+    face = np.empty(z.shape, np.int64)
+    al = np.empty(z.shape)
+    be = np.empty(z.shape)
+    belt = np.abs(z) <= 2.0 / 3.0
+    jp = N * (0.5 + tt - 0.75 * z)
+    jm = N * (0.5 + tt + 0.75 * z)
+    ifp = np.floor(jp / N).astype(np.int64)
+    ifm = np.floor(jm / N).astype(np.int64)
+    fb = np.where(ifp == ifm, 4 + ifp % 4, np.where(ifp < ifm, ifp % 4, 8 + ifm % 4))
+    face[belt] = fb[belt]
+    al[belt] = (jp - ifp * N)[belt]
+    be[belt] = ((ifm + 1) * N - jm)[belt]
+    t = N * np.sqrt(3.0 * omz)
+    fl = np.floor(tt)
+    tp = tt - fl
+    north = ~belt & (z > 0)
+    south = ~belt & (z < 0)
+    face[north] = fl[north].astype(np.int64)
+    al[north] = (tp * t)[north]
+    be[north] = ((1.0 - tp) * t)[north]
+    face[south] = 8 + fl[south].astype(np.int64)
+    al[south] = (N - (1.0 - tp) * t)[south]
+    be[south] = (N - tp * t)[south]
+    return face, al, be
+
+
+def face_point(nside: int, face, al, be):
+    """Inverse of face_coords, continued a little beyond the face: (z, omz,
+    phi) of face coordinates (alpha, beta)."""
+    N = float(nside)
+    face = np.asarray(face, np.int64)
+    al = np.asarray(al, np.float64)
+    be = np.asarray(be, np.float64)
+    g = face % 4
+    row = face // 4  # 0 north, 1 equatorial, 2 south
+    # belt form (every face, where it applies): Jp, Jm of the point
+    off_p = np.where(row == 0, g, np.where(row == 1, g, g + 1)) * N
+    off_m = np.where(row == 0, g + 2, np.where(row == 1, g + 1, g + 1)) * N
+    jp = al + off_p
+    jm = off_m - be
+    zb = (jm - jp) / (1.5 * N)
+    ttb = (jp + jm) / (2.0 * N) - 0.5
+    z = zb.copy()
+    tt = ttb.copy()
+    omz = 1.0 - np.abs(zb)
+    s_n = al + be            # north faces: distance from the pole in cells
+    s_s = 2.0 * N - al - be  # south faces: from the south pole
+    capn = (row == 0) & (s_n < N)
+    caps = (row == 2) & (s_s < N)
+    if capn.any():
+        s = s_n[capn]
+        tt[capn] = g[capn] + np.divide(al[capn], s, out=np.zeros_like(s), where=s > 0)  # the pole: any azimuth
+        omz[capn] = s * s / (3.0 * N * N)
+        z[capn] = 1.0 - omz[capn]
+    if caps.any():
+        s = s_s[caps]
+        tt[caps] = g[caps] + np.divide(N - be[caps], s, out=np.zeros_like(s), where=s > 0)
+        omz[caps] = s * s / (3.0 * N * N)
+        z[caps] = -(1.0 - omz[caps])
+    return z, omz, np.mod(tt, 4.0) * (0.5 * math.pi)
+
+
+def pix2face(nside: int, pix):
+    """(face, cell alpha index, cell beta index) of RING pixels."""
+    z, s, phi = pix2zphi(nside, pix)
+    rt = ring_table(nside)
+    ring, _ = pix2ring(nside, pix)
+    f, al, be = face_coords(nside, z, np.mod(phi / (0.5 * math.pi), 4.0), rt["omz"][ring - 1])
+    return f, np.floor(al).astype(np.int64), np.floor(be).astype(np.int64)
+
+
+def _point_pix(nside, z, omz, phi):
+    dec = np.where(z >= 0, 0.5 * math.pi - 2.0 * np.arcsin(np.sqrt(0.5 * omz)),
+                   -(0.5 * math.pi - 2.0 * np.arcsin(np.sqrt(0.5 * omz))))
+    return radec2pix(nside, phi, dec)
+
+
+# edge probes: just across the middle of the cell's four edges, in the order
+# alpha-, beta-, alpha+, beta+ (consecutive edges meet at a vertex)
+_EDGE_PROBE = [(-1e-6, 0.5), (0.5, -1e-6), (1.0 + 1e-6, 0.5), (0.5, 1.0 + 1e-6)]
+
+
+def edge_neighbours(nside: int, pix):
+    """[n, 4] pixels across the four edges of each pixel (every edge of the
+    grid is shared by exactly two pixels)."""
+    f, ia, ib = pix2face(nside, pix)
+    out = []
+    for da, db in _EDGE_PROBE:
+        z, omz, phi = face_point(nside, f, ia + da, ib + db)
+        out.append(_point_pix(nside, z, omz, phi))
+    return np.stack(out, axis=1)
+
+
+def neighbours(nside: int, pix):
+    """[n, 8] neighbours of each pixel: the four across its edges, then the
+    one diagonally across each vertex (between edges k and k+1), -1 where
+    the vertex is shared by only three pixels (the corners where three faces
+    meet). The pixel across a vertex is the common edge neighbour, other
+    than the pixel itself, of the two pixels across the vertex's edges;
+    when those two share an edge, the vertex has three pixels and there is
+    none."""
+    pix = np.asarray(pix, np.int64)
+    e = edge_neighbours(nside, pix)
+    ee = edge_neighbours(nside, e.ravel()).reshape(pix.size, 4, 4)
+    out = np.full((pix.size, 8), -1, np.int64)
+    out[:, :4] = e
+    for k in range(4):
+        a, b = k, (k + 1) % 4
+        A, B = ee[:, a, :], ee[:, b, :]
+        three = np.any(A == e[:, b:b + 1], axis=1)  # the two share an edge: three pixels at this vertex
+        match = (A[:, :, None] == B[:, None, :]).any(axis=2) & (A != pix[:, None])
+        n_common = np.array([np.unique(A[i][match[i]]).size for i in range(pix.size)])
+        bad = ~three & (n_common != 1)
+        if bad.any():
+            raise RuntimeError(f"vertex neighbour not unique for pixels {pix[bad][:5]}")
+        first = np.argmax(match, axis=1)
+        out[:, 4 + k] = np.where(three, -1, A[np.arange(pix.size), first])
+    return out

@@ -139,6 +139,21 @@ class Context:
         L.check(self.lib.smart_noise_angles(self.h, seed, r_first, n_real, n_src, p, _stream(self.device)))
         return out
 
+    def detect_peaks(self, nside: int, pix, values, threshold: float = float("-inf"), noise_sd=None):
+        """Detections of a map (see smart_detect_peaks): increasing int64 pixels."""
+        d = self.device
+        pix = _dev(pix, d, torch.int64)
+        val = _dev(values, d, torch.float64)
+        sd = None if noise_sd is None else _dev(noise_sd, d, torch.float64)
+        n = pix.numel()
+        if val.numel() != n or (sd is not None and sd.numel() != n):
+            raise ValueError("pixels, values and noise must have the same length")
+        out = torch.empty(max(n, 1), dtype=torch.int64, device=d)
+        cnt = C.c_int64()
+        L.check(self.lib.smart_detect_peaks(self.h, nside, n, _ptr(pix), _ptr(val), _ptr(sd), float(threshold),
+                                            _ptr(out), C.byref(cnt), _stream(d)))
+        return out[: cnt.value]
+
     def mixed_batch(self, plans, norms, outs, noalloc=False):
         """All plans in one persistent launch (smart_mixed_batch, or with
         noalloc=True smart_mixed_batch_noalloc: no device allocation)."""

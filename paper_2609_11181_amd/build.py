@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libsmartap.so")
 ARCH = "gfx950"
 
 SOURCES = ["capi.cpp", "devmem.cpp", "filters.cpp", "tune.cpp", "k_pairs.hip", "k_belt.hip", "k_binner.hip", "k_noise.hip",
-           "k_mixed.hip"]
+           "k_mixed.hip", "k_detect.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <cmath>
 #include <cstdio>
 #include <string>
 
@@ -753,6 +754,33 @@ int smart_mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const
   for (int k = 0; k < n_plans; ++k)
     if (norms[k] == SMART_NORM_AVERAGED && (rc = ensure_averaged(plans[k]->data, (hipStream_t)stream))) return rc;
   return mixed_batch(ctx, n_plans, plans, norms, d_outs, (hipStream_t)stream);
+}
+
+int smart_detect_peaks(smart_ctx ctx, int nside, int64_t n, const int64_t* d_pix, const double* d_val,
+                       const double* d_noise_sd, double threshold, int64_t* d_peaks, int64_t* h_n_peaks,
+                       void* stream) {
+  if (!ctx || !h_n_peaks) return fail(SMART_EINVAL, "NULL context or count");
+  *h_n_peaks = 0;
+  if (!is_pow2(nside) || nside > kMaxNside) return fail(SMART_EINVAL, "nside must be a power of two <= 8192");
+  if (n < 0 || n > 12LL * nside * nside || n > 0x7fffffffLL) return fail(SMART_EINVAL, "bad pixel count");
+  if (n > 0 && (!d_pix || !d_val || !d_peaks)) return fail(SMART_EINVAL, "NULL map or output");
+  if (std::isnan(threshold)) return fail(SMART_EINVAL, "threshold is NaN");
+  int rc;
+  if ((rc = set_device(ctx))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (n > 0) {  // pixels in range and strictly increasing
+    int* flag = nullptr;
+    if (scratch_alloc(&flag, sizeof(int), st) != hipSuccess) return fail(SMART_ENOMEM, "allocation failed");
+    int h = 0;
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), st);
+    if (e == hipSuccess) e = launch_check_pixels(d_pix, n, 12LL * nside * nside, flag, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    scratch_free(flag, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(SMART_EDEVICE, std::string("pixel check failed: ") + hipGetErrorString(e));
+    if (h) return fail(SMART_EINVAL, "map pixels must be strictly increasing and in [0, 12 nside^2)");
+  }
+  return detect_peaks(ctx, nside, n, d_pix, d_val, d_noise_sd, threshold, d_peaks, h_n_peaks, st);
 }
 
 int smart_mixed_batch_noalloc(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms,

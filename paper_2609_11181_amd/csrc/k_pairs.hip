@@ -280,6 +280,13 @@ __device__ __forceinline__ void galaxy_member(const GalaxyArgs& a, const ScaleAr
   }
 }
 
+// lane l's value, read into scalar registers (l wave-uniform)
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -314,7 +321,8 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
   const int wpb = blockDim.x >> 6;
   const int xcd = blockIdx.x & 7;
   const int64_t waves_x = (int64_t)(gridDim.x >> 3) * wpb;  // waves per XCD (grid is a multiple of 8)
-  const int64_t wid = (int64_t)(blockIdx.x >> 3) * wpb + (threadIdx.x >> 6);
+  // wave-uniform (scalar registers): the centre, its geometry and the slice bounds
+  const int64_t wid = (int64_t)(blockIdx.x >> 3) * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t o_begin = a.n_out * xcd / 8, o_end = a.n_out * (xcd + 1) / 8;
   const bool posb = a.posb != 0;
   // candidate pixels: those within theta_ap + r_bin (every galaxy within
@@ -356,9 +364,9 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
       }
       const int nl = min(64, hi - r0 + 1);
       for (int l = 0; l < nl; ++l) {
-#pragma unroll
+#pragma unroll 1
         for (int t = 0; t < 2; ++t) {
-          const int64_t g0 = __shfl(ga[t], l, 64), g1 = __shfl(gb[t], l, 64);
+          const int64_t g0 = readlane64(ga[t], l), g1 = readlane64(gb[t], l);
           for (int64_t g = g0 + lane; g < g1; g += 64)
             galaxy_member<TABLE, BIG>(a, s, g, px, py, pz, posb, cp, tab, tot, acc, nacc);
         }

@@ -364,6 +364,11 @@ hipError_t launch_philox_u(uint64_t seed, int64_t r_first, int n_real, int64_t n
 // mom [4][n_out] += (E, E^2, B, B^2) of the float maps eb [2][n_out]
 hipError_t launch_moments_add(const float* eb, int64_t n_out, double* mom, hipStream_t st);
 
+// detection step (k_detect.hip): peaks of a map given as strictly
+// increasing pixels (validated by the caller, n < 2^31) and values
+int detect_peaks(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const double* val, const double* noise_sd,
+                 double threshold, int64_t* peaks, int64_t* n_peaks, hipStream_t st);
+
 // autotuner (tune.cpp)
 int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st);
 

@@ -20,7 +20,7 @@ EXPORTS = [
     "smart_filter_table", "smart_filter_pieces", "smart_bin_galaxies", "smart_pixel_map", "smart_data_info", "smart_data_sources",
     "smart_data_export", "smart_barycentre_map",
     "smart_data_free", "smart_plan_create", "smart_run", "smart_last_pairs", "smart_plan_free",
-    "smart_noise_batch", "smart_noise_angles", "smart_noise_seeded", "smart_noise_galaxy_batch", "smart_mixed_batch", "smart_mixed_batch_noalloc", "smart_plan_tiles",
+    "smart_noise_batch", "smart_noise_angles", "smart_noise_seeded", "smart_noise_galaxy_batch", "smart_mixed_batch", "smart_mixed_batch_noalloc", "smart_detect_peaks", "smart_plan_tiles",
     "smart_plan_set_timing", "smart_plan_kernel_ms", "smart_autotune",
 ]
 
@@ -62,6 +62,7 @@ _SIGS = {
     "smart_barycentre_map": (_int, [_vp, _vp, _vp]),
     "smart_mixed_batch": (_int, [_vp, _int, C.POINTER(_vp), C.POINTER(_int), C.POINTER(_vp), _vp]),
     "smart_mixed_batch_noalloc": (_int, [_vp, _int, C.POINTER(_vp), C.POINTER(_int), C.POINTER(_vp), _vp]),
+    "smart_detect_peaks": (_int, [_vp, _int, _i64, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(_i64), _vp]),
     "smart_plan_tiles": (_int, [_vp, _int, C.POINTER(_int), C.POINTER(_int), _vp, _vp, _vp]),
     "smart_plan_set_timing": (_int, [_vp, _int]),
     "smart_autotune": (_int, [_vp, _int, C.c_char_p, _vp]),
