@@ -288,7 +288,6 @@ def batched_leg(ctx, args):
     torch.cuda.synchronize()
     bin_ms = ev0.elapsed_time(ev1)
     n_gal = cols[0].numel()
-    del cols
     src = data.sources()
     n_src = src.numel()
     scales = [5 * ARCMIN, 10 * ARCMIN, 20 * ARCMIN]
@@ -379,6 +378,9 @@ def batched_leg(ctx, args):
         del gout
     posb["workload"] = (f"galaxy-level variants over {n_gal:.3g} galaxies (NSIDE-2048 partition), "
                         f"{sub.numel()} output pixels, 3 scales (5/10/20 arcmin), tanh filter")
+    table3 = table3_leg(ctx, cols, data, fid)
+    log(f"table 3: {json.dumps({k: v for k, v in table3.items() if k.startswith('nside')})}")
+    del cols
     maps_b = 3 * R / t_b
     maps_p = 3 * Rp / t_p
     flops = 8.0 * pairs1 * R  # one complex multiply-add per pair and realisation
@@ -401,10 +403,66 @@ def batched_leg(ctx, args):
         "binning_ms": bin_ms,
         "barycentre": barycentre,
         "galaxy_variants": posb,
+        "table3_epsilon": table3,
     }
     if not args.no_cpu:
         res.update(batched_accuracy(data, src, u, out, outp, scales, R))
     return res
+
+
+def table3_leg(ctx, cols, data2048, fid, th=10 * ARCMIN):
+    """The paper's Table 3 comparison (Sect. 5.1) on the synthetic catalogue:
+    eps_X = (M_E^X - M_E^pos) / std(M_E^pos) for X = sphS_pix, sphS_pixB and
+    sphS_posB against the brute force sphS_pos, mean and standard deviation
+    over the map, at NSIDE 2048 (every occupied pixel within 8 degrees of the
+    field centre) and NSIDE 4096 (within 4 degrees; the catalogue binned
+    again), theta_ap 10', tanh filter, summed approach."""
+    import torch
+
+    from oracle import healpix_ref as hp
+    from paper_2609_11181_amd import lib as L
+
+    out = {}
+    for nside, rad in ((2048, 8.0), (4096, 4.0)):
+        data = data2048 if nside == 2048 else ctx.bin_galaxies(*cols, None, nside_bin=4096, pixel_sums=True)
+        srcs = data.sources().cpu().numpy()
+        sel = srcs[hp.pix2vec(nside, srcs)[:, 0] > math.cos(math.radians(rad))]
+        bdata = data.barycentre()
+        maps, ms = {}, {}
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        for name, d, var, norm in (("pos", data, L.VAR_GALAXY, L.NORM_SUMMED_CAP),
+                                   ("pix", data, L.VAR_PIXEL, L.NORM_SUMMED_PIXCOUNT),
+                                   ("pixB", bdata, L.VAR_GALAXY, L.NORM_SUMMED_PIXCOUNT),
+                                   ("posB", data, L.VAR_GALAXY_POSB, L.NORM_SUMMED_CAP)):
+            plan = ctx.plan(d, var, nside, sel, [th], [fid], precision=L.PREC_FP32_OUT64)
+            o = plan.run(norm)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            plan.run(norm, o)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms[name] = ev0.elapsed_time(ev1)
+            maps[name] = o[0, 0].cpu().numpy()
+            plan.free()
+        ref = maps["pos"]
+        sd = float(np.std(ref))
+        out[f"nside{nside}"] = {
+            "outputs": int(sel.size),
+            **{f"eps_{k}": {"mean": float(np.mean((maps[k] - ref) / sd)), "std": float(np.std((maps[k] - ref) / sd))}
+               for k in ("pix", "pixB", "posB")},
+            "run_ms": ms,
+        }
+        bdata.free()
+        if nside != 2048:
+            data.free()
+    out["workload"] = ("eps of sphS_pix / sphS_pixB / sphS_posB against sphS_pos (Table 3 definition), theta_ap 10 "
+                       "arcmin, tanh filter, on the 2.5e8-galaxy catalogue")
+    out["paper_table3"] = {"nside2048": {"pix": [2.00e-5, 3.30e-2], "pixB": [2.00e-5, 3.22e-2], "posB": [1.54e-6, 8.02e-3]},
+                           "nside4096": {"pix": [4.29e-6, 8.58e-3], "pixB": [4.36e-6, 7.51e-3],
+                                         "posB": [-3.62e-7, 3.53e-3]},
+                           "note": "mean, std on the paper's mock (Jarvis filter at 4 arcmin); context for the ordering"}
+    return out
 
 
 def batched_accuracy(data, src, u, out, outp, scales, R, n_check=512, seed=12):
@@ -740,6 +798,48 @@ def main():
                     "the per-map averaged records are built by the first call, outside the timed runs",
         }
         log(f"averaged normalisation: run {avg_ms:.2f} ms (summed {run_ms:.2f} ms)")
+    # detection step (Sect. 6.1) on the 5' M_E map of the last step: every
+    # local maximum over the eight neighbours, and a signal-to-noise cut
+    # (M_E / sigma >= 4) with the sigma channel
+    me, sg = out3[0, 0].contiguous(), out3[0, 2].contiguous()
+    ctx.detect_peaks(args.nside, pix, me)  # warm-up
+    torch.cuda.synchronize()
+    ev_d = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev_d[0].record(stream)
+    n_peaks = ctx.detect_peaks(args.nside, pix, me).numel()
+    ev_d[1].record(stream)
+    n_snr = ctx.detect_peaks(args.nside, pix, me, 4.0, sg).numel()
+    ev_d[2].record(stream)
+    torch.cuda.synchronize()
+    res["detection"] = {
+        "workload": f"local maxima of the 5 arcmin M_E map ({n_out} pixels, NSIDE {args.nside})",
+        "ms_per_map": ev_d[0].elapsed_time(ev_d[1]),
+        "peaks": n_peaks,
+        "snr4_ms_per_map": ev_d[1].elapsed_time(ev_d[2]),
+        "snr4_peaks": n_snr,
+        "note": "smart_detect_peaks: value above its 8 (7 at the 24 three-face corners) neighbours; the second cut "
+                "also needs M_E / sigma >= 4; times include the pixel check and the dense scatter",
+    }
+    log(f"detection: {res['detection']['ms_per_map']:.2f} ms per map, {n_peaks} peaks, {n_snr} above S/N 4")
+    # the single map through the split-BF16 MFMA path: one realisation with
+    # zero angles (the identity rotation), E and B of the three scales
+    zero_u = torch.zeros(1, n_out, dtype=torch.float32, device=dev)
+    out_bf = torch.empty(len(scales), 1, 2, n_out, dtype=torch.float32, device=dev)
+    last_plan.noise_batch(zero_u, 1, L.NORM_SUMMED_PIXCOUNT, L.PREC_BF16X3, out_bf)  # builds the noise schedule
+    torch.cuda.synchronize()
+    ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev_b[0].record(stream)
+    last_plan.noise_batch(zero_u, 1, L.NORM_SUMMED_PIXCOUNT, L.PREC_BF16X3, out_bf)
+    ev_b[1].record(stream)
+    torch.cuda.synchronize()
+    res["bf16x3_single_map"] = {
+        "run_ms": ev_b[0].elapsed_time(ev_b[1]),
+        "fp32_run_ms": run_ms,
+        "note": "one zero-angle realisation through the batched split-BF16x3 MFMA kernels (E and B of the three "
+                "scales); a single map is a sparse matrix-vector product, so the 32-wide realisation tile is 1/32 "
+                "used and this path loses to the plain FP32 kernels",
+    }
+    del zero_u
     default_workload = args.nside == 4096 and args.area == 15000.0
     res["roofline"]["traffic"] = TRAFFIC_BYTES.get(res["roofline"]["kernel"]) if default_workload else None
     # accuracy on the oracle sample + CPU baseline
@@ -766,6 +866,14 @@ def main():
             eps.append({"mean": float(np.mean(e)), "std": float(np.std(e))})
         res["max_rel_err_vs_oracle"] = errs
         res["epsilon_vs_oracle"] = eps
+        bf_errs = []
+        for k, r in enumerate(refs):
+            full = outs[k][0, 0].double()
+            map_rms = float(torch.sqrt(torch.mean(full * full)))
+            ok = ~r["tie"]
+            g = out_bf[k, 0, 0].double().cpu().numpy()[idx]
+            bf_errs.append(float(np.max(np.abs(g[ok] - r["M_E"][ok]))) / map_rms)
+        res["bf16x3_single_map"]["max_rel_err_vs_oracle"] = bf_errs
         res["accuracy"] = {
             "metric": "max |M_E - oracle| over the sample / RMS of the whole M_E map, per scale",
             "max_err_over_patch_rms": errs_patch,
@@ -793,8 +901,8 @@ def main():
         }
     if not args.no_config2:
         keep.clear()
-        del outs, out3, cols, pix, out_avg
-        outs = out3 = cols = pix = out_avg = None
+        del outs, out3, cols, pix, out_avg, out_bf, me, sg
+        outs = out3 = cols = pix = out_avg = out_bf = me = sg = None
         torch.cuda.empty_cache()
         res["config2"] = config2_leg(ctx, args)
     if not args.no_batched:

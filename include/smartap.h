@@ -33,7 +33,9 @@
  *   sigma = (1 / theta_ap^2) sqrt(sum_j Q_j^2 E2_j (Omega_pix / W_j)^2 / 2),
  *
  * with Omega_pix the area of a source pixel; pixels with W_j = 0 add nothing.
- * The W and N channels are those of the summed maps.
+ * For galaxy sources G_j is the galaxy's w g, E2_j its w^2 |g|^2 and W_j the
+ * summed weight of the galaxies in its pixel of the final map. The W and N
+ * channels are those of the summed maps.
  *
  * Conventions
  *   - Angles in radians. Right ascension in [0, 2 pi), declination in
@@ -123,10 +125,16 @@ enum {
   SMART_NORM_SUMMED_CAP = 0,      /* A_ap = spherical cap area               */
   SMART_NORM_SUMMED_PIXCOUNT = 1, /* A_ap = N * pixel area                   */
   SMART_NORM_RAW = 2,             /* channels are S_E, S_B, V, W, N          */
-  SMART_NORM_AVERAGED = 3         /* averaged approach: pixel-variant FP32
-                                     plans only (smart_run, smart_noise_batch,
-                                     smart_mixed_batch); SMART_EINVAL for
-                                     galaxy-variant and FP64 plans            */
+  SMART_NORM_AVERAGED = 3         /* averaged approach, FP32 plans: pixel
+                                     variant (smart_run, smart_noise_batch,
+                                     smart_mixed_batch), and galaxy sources
+                                     (smart_run, smart_noise_galaxy_batch;
+                                     brute force, posB, barycentre data) when
+                                     nside_out equals the binning NSIDE: each
+                                     galaxy divided by the density of its
+                                     pixel of the final map, W_pix / Omega_pix
+                                     (a barycentre source by its own);
+                                     SMART_EINVAL for FP64 plans              */
 };
 
 /* Output channel order of smart_run: [n_scales][5][n_out].                  */

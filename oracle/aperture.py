@@ -168,8 +168,12 @@ def aperture_mass_barycentre(cat, nside, c_ra, c_dec, theta_ap, filter_kind, nor
     source within theta_ap of the centre, summed normalisation with
     A = (occupied pixels in the aperture) x Omega_pix or the cap area."""
     src = barycentre_sources(nside, cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat.get("w"))
+    if norm == NORM_AVERAGED:  # each pixel by its own density (Sect. 2.4), as in the pixel variant
+        W = src.Wsrc
+        src = _averaged(src, np.where(W > 0, 4.0 * math.pi / hp.npix(nside) / np.where(W > 0, W, 1.0), 0.0))
     s = sums_kdtree(src, c_ra, c_dec, theta_ap, q_of(filter_kind, filter_params))
-    out = normalise(s, theta_ap, norm, omega_pix=4.0 * math.pi / hp.npix(nside))
+    out = (_averaged_out(s, theta_ap) if norm == NORM_AVERAGED
+           else normalise(s, theta_ap, norm, omega_pix=4.0 * math.pi / hp.npix(nside)))
     out["tie"] = s["tie"]
     out["pairs"] = s["pairs"]
     return out
@@ -185,6 +189,8 @@ def aperture_mass_posB(cat, nside, c_ra, c_dec, theta_ap, filter_kind, norm=NORM
     ra = np.asarray(cat["ra"], np.float64)
     dec = np.asarray(cat["dec"], np.float64)
     src = galaxy_sources(ra, dec, cat["g1"], cat["g2"], cat.get("w"))
+    if norm == NORM_AVERAGED:  # per galaxy by its pixel's density (Sect. 2.4); the partition is the final map's grid
+        src = _averaged(src, galaxy_density_factors(nside, ra, dec, cat.get("w")))
     src_vec = src.vec
     qfun = q_of(filter_kind, filter_params)
     c_ra = np.asarray(c_ra, np.float64)
@@ -233,7 +239,7 @@ def aperture_mass_posB(cat, nside, c_ra, c_dec, theta_ap, filter_kind, norm=NORM
         "V": np.bincount(ci, weights=q * q * src.Vsrc[si], minlength=n_cen),
         "N": np.bincount(ci, weights=src.Nsrc[si], minlength=n_cen),
     }
-    out = normalise(sums, theta_ap, norm)
+    out = _averaged_out(sums, theta_ap) if norm == NORM_AVERAGED else normalise(sums, theta_ap, norm)
     out["tie"] = tie
     out["pairs"] = int(ci.size)
     return out
@@ -388,11 +394,40 @@ def normalise(sums, theta_ap, mode, omega_pix=None):
     }
 
 
-def aperture_mass_galaxy(cat, c_ra, c_dec, theta_ap, filter_kind, norm=NORM_SUMMED_CAP, filter_params=None):
-    """Brute-force galaxy variant (Sect. 3.1, label sphS_pos)."""
+def galaxy_density_factors(nside, ra, dec, w=None):
+    """Averaged approach for galaxies (Sect. 2.4): each galaxy is divided by
+    the effective density of its pixel of the final map, W_pix / Omega_pix,
+    i.e. multiplied by c_i = Omega_pix / W_pix(i), with W_pix the summed
+    weight of the galaxies in that pixel (NSIDE of the map)."""
+    ra = np.asarray(ra, np.float64)
+    w = np.ones_like(ra) if w is None else np.asarray(w, np.float64)
+    pix = hp.radec2pix(nside, ra, np.asarray(dec, np.float64))
+    occ, inv = np.unique(pix, return_inverse=True)
+    W = np.bincount(inv, weights=w, minlength=occ.size)
+    omega = 4.0 * math.pi / hp.npix(nside)
+    return np.where(W[inv] > 0, omega / np.where(W[inv] > 0, W[inv], 1.0), 0.0)
+
+
+def _averaged(src: Sources, c) -> Sources:
+    """Sources whose shear terms carry the factor c and squared terms c^2
+    (W and N unchanged: those channels stay the summed ones)."""
+    return Sources(src.ra, src.dec, c * src.A1, c * src.A2, src.Wsrc, c * c * src.Vsrc, src.Nsrc)
+
+
+def _averaged_out(s, theta_ap):
+    return {"M_E": s["S_E"] / theta_ap ** 2, "M_B": s["S_B"] / theta_ap ** 2,
+            "sigma": np.sqrt(0.5 * s["V"]) / theta_ap ** 2, "W": s["W"], "N": s["N"]}
+
+
+def aperture_mass_galaxy(cat, c_ra, c_dec, theta_ap, filter_kind, norm=NORM_SUMMED_CAP, filter_params=None,
+                         avg_nside=None):
+    """Brute-force galaxy variant (Sect. 3.1, label sphS_pos); the averaged
+    normalisation (Sect. 2.4) needs the NSIDE of the final map, avg_nside."""
     src = galaxy_sources(cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat.get("w"))
+    if norm == NORM_AVERAGED:
+        src = _averaged(src, galaxy_density_factors(avg_nside, cat["ra"], cat["dec"], cat.get("w")))
     s = sums_kdtree(src, c_ra, c_dec, theta_ap, q_of(filter_kind, filter_params))
-    out = normalise(s, theta_ap, norm)
+    out = _averaged_out(s, theta_ap) if norm == NORM_AVERAGED else normalise(s, theta_ap, norm)
     out["tie"] = s["tie"]
     out["pairs"] = s["pairs"]
     return out

@@ -45,8 +45,13 @@ int check_norm(smart_plan p, int norm) {
   if (norm < SMART_NORM_SUMMED_CAP || norm > SMART_NORM_AVERAGED) return fail(SMART_EINVAL, "unknown normalisation");
   if (norm == SMART_NORM_SUMMED_PIXCOUNT && p->variant != SMART_VAR_PIXEL && !p->data->explicit_v)
     return fail(SMART_EINVAL, "the pixel-count area needs pixel sources (pixel variant or barycentre data)");
-  if (norm == SMART_NORM_AVERAGED && (p->variant != SMART_VAR_PIXEL || p->precision != SMART_PREC_FP32_GEO64))
-    return fail(SMART_EINVAL, "averaged normalisation needs a pixel-variant FP32 plan");
+  if (norm == SMART_NORM_AVERAGED) {
+    if (p->precision != SMART_PREC_FP32_GEO64) return fail(SMART_EINVAL, "averaged normalisation needs an FP32 plan");
+    // galaxy sources: each is divided by the density of its pixel of the
+    // final map, so the binning grid must be the map's grid
+    if (p->variant != SMART_VAR_PIXEL && p->nside_out != p->data->nside)
+      return fail(SMART_EINVAL, "averaged normalisation of galaxy sources needs nside_out equal to the binning NSIDE");
+  }
   return SMART_OK;
 }
 
@@ -231,7 +236,7 @@ void smart_data_free(smart_data d) {
   // the blocks go back to the library's cache: no work may still use them
   (void)hipDeviceSynchronize();
   for (void* q : {(void*)d->P, (void*)d->F, (void*)d->G, (void*)d->order, (void*)d->offsets, (void*)d->sums,
-                  (void*)d->wd, (void*)d->wn, (void*)d->cidx, (void*)d->src_pix, (void*)d->avg})
+                  (void*)d->wd, (void*)d->wn, (void*)d->cidx, (void*)d->src_pix, (void*)d->avg, (void*)d->gavg})
     smart::dev_release(q);
   delete d;
 }
@@ -456,7 +461,9 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
   if ((rc = set_device(p->ctx))) return rc;
   hipStream_t st = (hipStream_t)stream;
   smart_data d = p->data;
-  if (norm == SMART_NORM_AVERAGED && (rc = ensure_averaged(d, st))) return rc;
+  if (norm == SMART_NORM_AVERAGED &&
+      (rc = p->variant == SMART_VAR_PIXEL ? ensure_averaged(d, st) : ensure_gal_averaged(d, st)))
+    return rc;
   const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
   for (int k = 0; k < (int)p->theta_ap.size(); ++k) {
     const ScaleArgs s = make_scale(p->ctx, p->theta_ap[k], p->filter_ids[k], omega);
@@ -496,6 +503,7 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.out64 = p->out64 ? 1 : 0;
       a.explicit_v = d->explicit_v ? 1 : 0;
       a.posb = p->posb ? 1 : 0;
+      a.cavg = norm == SMART_NORM_AVERAGED ? d->gavg : nullptr;
       e = launch_galaxy(a, s, p->precision, st);
     }
     if (e != hipSuccess) return fail(SMART_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -660,6 +668,7 @@ int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int nor
   if ((rc = set_device(p->ctx))) return rc;
   hipStream_t st = (hipStream_t)stream;
   if (p->n_out == 0) return SMART_OK;
+  if (norm == SMART_NORM_AVERAGED && p->variant != SMART_VAR_PIXEL && (rc = ensure_gal_averaged(d, st))) return rc;
   // buffers of the plan, sized by its catalogue (fixed for the plan's life):
   // allocated at the first call, kept until smart_plan_free
   if (p->variant == SMART_VAR_GALAXY && !p->rot_gal && d->n_gal > 0) {
@@ -723,6 +732,7 @@ int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int nor
         a.scale = 0;
         a.explicit_v = d->explicit_v ? 1 : 0;
         a.posb = p->posb ? 1 : 0;
+        a.cavg = norm == SMART_NORM_AVERAGED ? d->gavg : nullptr;
         e = launch_galaxy(a, s, p->precision, st);
       }
       if (e == hipSuccess)

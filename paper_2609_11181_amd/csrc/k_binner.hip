@@ -639,6 +639,45 @@ int ensure_averaged(smart_data d, hipStream_t st) {
   return SMART_OK;
 }
 
+// Averaged approach for galaxy sources (Sect. 2.4): every row of binning
+// pixel q gets c = Omega_pix / W_q with W_q the summed weight of the pixel's
+// rows, or, for barycentre data (one row per pixel, its W in G.z), its own
+// Omega_pix / W.
+__global__ void k_gal_density(const int64_t* offsets, int64_t n_pix, const float4* G, int own, double omega, float* c) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_pix) return;
+  const int64_t r0 = offsets[q], r1 = offsets[q + 1];
+  if (r0 == r1) return;
+  double W = 0.0;
+  if (!own)
+    for (int64_t r = r0; r < r1; ++r) W += (double)G[r].z;
+  for (int64_t r = r0; r < r1; ++r) {
+    const double w = own ? (double)G[r].z : W;
+    c[r] = w > 0.0 ? (float)(omega / w) : 0.f;
+  }
+}
+
+int ensure_gal_averaged(smart_data d, hipStream_t st) {
+  if (d->gavg || d->n_gal <= 0) return SMART_OK;
+  float* c = nullptr;
+  if (dev_alloc(&c, sizeof(float) * d->n_gal) != hipSuccess) {
+    set_error("out of device memory (averaged galaxy factors)");
+    return SMART_ENOMEM;
+  }
+  const int64_t n_pix = 12LL * d->nside * d->nside;
+  const double omega = 4.0 * M_PI / (double)n_pix;
+  hipLaunchKernelGGL(k_gal_density, dim3(grid_of(n_pix)), dim3(kBlock), 0, st, d->offsets, n_pix, d->G,
+                     d->explicit_v ? 1 : 0, omega, c);
+  // plans on other streams may read the factors once the pointer is set
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    dev_release(c);
+    set_error("averaging kernel failed");
+    return SMART_EDEVICE;
+  }
+  d->gavg = c;
+  return SMART_OK;
+}
+
 int build_wn_prefix(smart_ctx ctx, smart_data d, hipStream_t st) {
   (void)ctx;
   if (d->n_dense <= 0) return SMART_OK;

@@ -270,9 +270,14 @@ __device__ __forceinline__ void galaxy_member(const GalaxyArgs& a, const ScaleAr
   // lookup clamps its index, so the evaluation stays in range
   const double q = inside ? filter_q<TABLE>(theta_ratio<BIG>(cd, c2, cp), tab) : 0.0;
   const float w = G.z;
-  const double wd = (double)w;
-  accumulate(q * c2p, q * s2p, (float)q, wd * (double)G.x, wd * (double)G.y, w,
-             a.explicit_v ? G.w : w * w * fmaf(G.x, G.x, G.y * G.y), 1, tot, acc);
+  double wd = (double)w;
+  float v = a.explicit_v ? G.w : w * w * fmaf(G.x, G.x, G.y * G.y);
+  if (a.cavg) {  // averaged approach: the galaxy divided by its pixel's density
+    const float c = a.cavg[g];
+    wd *= (double)c;
+    v *= c * c;
+  }
+  accumulate(q * c2p, q * s2p, (float)q, wd * (double)G.x, wd * (double)G.y, w, v, 1, tot, acc);
   if (++nacc == kChunk) {
     tot.add(acc);
     acc = Acc32();

@@ -104,6 +104,10 @@ struct smart_data_s {
   // catalogue at its galaxies' barycentre, with G = (G1/W, G2/W, W, E2):
   // the pair kernels take V from G.w instead of w^2 |g|^2
   bool explicit_v = false;
+  // averaged approach on galaxy sources: per sorted row the factor
+  // Omega_pix / W of its binning pixel (the row's own W for barycentre
+  // data), built at the first averaged call
+  float* gavg = nullptr;
   // prefix sums over the dense range: wn[i] = (sum of W, number of pixels
   // with W > 0) over dense pixels [0, i); n_dense + 1 entries
   double2* wn = nullptr;
@@ -231,6 +235,7 @@ struct GalaxyArgs {
   int out64;       // maps written as double (SMART_PREC_FP32_OUT64 plans)
   int explicit_v;  // V of a source is G.w (barycentre data)
   int posb;        // membership by the binning pixel's centre (sphS_posB)
+  const float* cavg;  // averaged approach: per-row density factor (shear terms x c, V x c^2), or null
 };
 
 // Belt tables of one scale (built by k_belt.hip): for every belt ring that
@@ -332,6 +337,8 @@ int build_wn_prefix(smart_ctx ctx, smart_data d, hipStream_t st);
 int barycentre_data(smart_data src, hipStream_t st, smart_data out);
 // the averaged records of a map (built once, synchronising `st`)
 int ensure_averaged(smart_data d, hipStream_t st);
+// the per-row density factors of a binned catalogue (built once, synchronising `st`)
+int ensure_gal_averaged(smart_data d, hipStream_t st);
 // the records the pair kernels read under normalisation `norm`
 inline const float4* map_for(smart_data d, int norm) { return norm == SMART_NORM_AVERAGED ? d->avg : d->sums; }
 int pixel_map(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const float* W, const float* G1,

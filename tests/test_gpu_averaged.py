@@ -130,7 +130,8 @@ def test_averaged_in_mixed_batch_and_rejections(ctx):
     torch.cuda.synchronize()
     for k, (o, s) in enumerate(zip(outs, singles)):
         assert np.array_equal(o.cpu().numpy(), s), k
-    # galaxy-variant and FP64 plans reject the averaged form
+    # FP64 plans reject the averaged form, and galaxy plans whose output grid
+    # is not the binning grid (each galaxy needs its pixel of the final map)
     m = _cap_map(64, 20 * DEG, 50)
     data = ctx.pixel_map(64, m["pix"], m["W"], m["G1"], m["G2"], m["E2"])
     p64 = ctx.plan(data, L.VAR_PIXEL, 64, m["pix"][:100], [3 * DEG], [ctx.filter(F.TANH)], precision=0)
@@ -139,7 +140,46 @@ def test_averaged_in_mixed_batch_and_rejections(ctx):
     with pytest.raises(L.SmartError):
         p64.run(4)
     ra, dec = hp.pix2radec(64, m["pix"])
-    gdata = ctx.bin_galaxies(ra, dec, np.zeros(ra.size), np.zeros(ra.size), nside_bin=64)
+    gdata = ctx.bin_galaxies(ra, dec, np.zeros(ra.size), np.zeros(ra.size), nside_bin=128)
     pg = ctx.plan(gdata, L.VAR_GALAXY, 64, m["pix"][:100], [3 * DEG], [ctx.filter(F.TANH)])
     with pytest.raises(L.SmartError):
         pg.run(L.NORM_AVERAGED)
+
+
+@pytest.mark.parametrize("variant", ["pos", "posB", "pixB"])
+def test_averaged_galaxy_sources(ctx, variant):
+    """Averaged approach (Sect. 2.4) with galaxy sources: the brute force,
+    posB and barycentre data, every galaxy (barycentre source) divided by
+    the density of its pixel of the final map, against the oracle; output
+    NSIDE = binning NSIDE (another NSIDE is refused)."""
+    from paper_2609_11181_amd import lib as L
+    from synth import small_catalogue
+
+    nside = 128
+    cat = small_catalogue(120000, seed=71, cap_radius=5 * DEG, centre=(0.03, 0.01))
+    data = ctx.bin_galaxies(cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat["w"], nside_bin=nside, pixel_sums=True)
+    v = hp.pix2vec(nside, np.arange(hp.npix(nside)))
+    out_pix = np.nonzero(v[:, 0] > math.cos(4 * DEG))[0]
+    th = 50 * ARCMIN
+    fid = ctx.filter(F.TANH)
+    c_ra, c_dec = hp.pix2radec(nside, out_pix)
+    if variant == "pixB":
+        d = data.barycentre()
+        plan = ctx.plan(d, L.VAR_GALAXY, nside, out_pix, [th], [fid])
+        ref = A.aperture_mass_barycentre(cat, nside, c_ra, c_dec, th, F.TANH, norm=A.NORM_AVERAGED)
+    elif variant == "posB":
+        plan = ctx.plan(data, L.VAR_GALAXY_POSB, nside, out_pix, [th], [fid])
+        ref = A.aperture_mass_posB(cat, nside, c_ra, c_dec, th, F.TANH, norm=A.NORM_AVERAGED)
+    else:
+        plan = ctx.plan(data, L.VAR_GALAXY, nside, out_pix, [th], [fid])
+        ref = A.aperture_mass_galaxy(cat, c_ra, c_dec, th, F.TANH, norm=A.NORM_AVERAGED, avg_nside=nside)
+    out = plan.run(L.NORM_AVERAGED).cpu().numpy()[0]
+    ok = ~ref["tie"]
+    for ch, key in enumerate(("M_E", "M_B", "sigma")):
+        rms = math.sqrt(np.mean(ref[key][ok] ** 2))
+        assert np.max(np.abs(out[ch][ok] - ref[key][ok])) <= 1e-6 * rms, key
+    assert np.array_equal(out[4][ok], ref["N"][ok])
+    if variant == "pos":
+        other = ctx.plan(data, L.VAR_GALAXY, 64, out_pix[:10] // 4, [th], [fid])
+        with pytest.raises(L.SmartError):
+            other.run(L.NORM_AVERAGED)

@@ -671,3 +671,36 @@ def test_posB_boundary_galaxies():
     r = np.arccos(np.clip(gv @ cv, -1, 1))
     edge = np.abs(r - th) < 2.0 * math.sqrt(4 * math.pi / hp.npix(nside))
     assert np.all(edge[pin != gin])
+
+
+def test_averaged_galaxy_route_equals_pixel_route():
+    """Averaged approach for galaxies (density of each galaxy's final-map
+    pixel) against the pinned averaged pixel variant: one galaxy per pixel at
+    the pixel centre with weight W_j and shear G_j / W_j is the same source
+    set, so the maps must agree; and with several galaxies per pixel the
+    factor is Omega_pix over the pixel's summed weight."""
+    from oracle import aperture as A
+    from oracle import filters as F
+    from oracle import healpix_ref as hp
+
+    nside = 32
+    rng = np.random.default_rng(5)
+    pix = np.arange(hp.npix(nside))
+    pix = pix[hp.pix2vec(nside, pix)[:, 0] > np.cos(0.5)]
+    W = rng.uniform(5, 30, pix.size)
+    G1 = rng.normal(0, 0.3, pix.size) * W
+    G2 = rng.normal(0, 0.3, pix.size) * W
+    E2 = (G1 ** 2 + G2 ** 2) / W
+    ra, dec = hp.pix2radec(nside, pix)
+    cat = {"ra": ra, "dec": dec, "g1": G1 / W, "g2": G2 / W, "w": W}
+    out_pix = pix[:: 7]
+    th = 6 * np.pi / 180
+    c_ra, c_dec = hp.pix2radec(nside, out_pix)
+    g = A.aperture_mass_galaxy(cat, c_ra, c_dec, th, F.TANH, norm=A.NORM_AVERAGED, avg_nside=nside)
+    p = A.aperture_mass_pixel({"nside": nside, "pix": pix, "W": W, "G1": G1, "G2": G2, "E2": W * E2},
+                              out_pix, th, F.TANH, norm=A.NORM_AVERAGED)
+    for k in ("M_E", "M_B", "sigma"):
+        assert np.max(np.abs(g[k] - p[k])) <= 1e-12 * np.max(np.abs(p[k]))
+    c = A.galaxy_density_factors(nside, np.repeat(ra[:3], 2), np.repeat(dec[:3], 2), np.array([1, 3, 2, 2, 5, 5.0]))
+    omega = 4 * np.pi / hp.npix(nside)
+    assert np.allclose(c, omega / np.array([4, 4, 4, 4, 10, 10.0]), rtol=1e-15)
