@@ -305,6 +305,19 @@ def batched_leg(ctx, args):
     ev1.record(stream)
     torch.cuda.synchronize()
     t_b = ev0.elapsed_time(ev1) / 1e3
+    # the same batch captured once in a HIP graph and replayed (the schedule
+    # was built by the first call; the launches allocate nothing)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.noise_batch(u, R, L.NORM_SUMMED_PIXCOUNT, L.PREC_BF16X3, out)
+    graph.replay()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    graph.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_graph = ev0.elapsed_time(ev1) / 1e3
+    del graph
     # pairs of one realisation set (N summed over centres and scales)
     main = plan.run(L.NORM_SUMMED_PIXCOUNT)
     pairs1 = plan.last_pairs()
@@ -390,6 +403,8 @@ def batched_leg(ctx, args):
         "maps": 3 * R,
         "bf16x3_s": t_b,
         "bf16x3_maps_per_s": maps_b,
+        "bf16x3_graph_replay_s": t_graph,
+        "bf16x3_graph_maps_per_s": 3 * R / t_graph,
         "plain_fp32_maps_per_s": maps_p,
         "plain_fp32_timed_realisations": Rp,
         "galaxy_level_fp32_maps_per_s": 3 * Rp / t_g,
@@ -401,6 +416,9 @@ def batched_leg(ctx, args):
                  "frac": flops / t_b / 2.5e15,
                  "note": "algorithmic 8 flop per (pair, realisation); split-BF16 issues 3 products per term"},
         "binning_ms": bin_ms,
+        "binning_gb_per_s": (n_gal * (28 + 72) + 12 * 2048 ** 2 * 8) / (bin_ms / 1e3) / 1e9,
+        "binning_note": "algorithmic bytes: 28 read + 72 written per galaxy (sorted unit vector, frame, shear, "
+                        "catalogue order) + 8 per pixel of the offset table, over the smart_bin_galaxies time",
         "barycentre": barycentre,
         "galaxy_variants": posb,
         "table3_epsilon": table3,
@@ -559,6 +577,9 @@ def mixed_leg(ctx, args):
         "mixed_ms": t_mix * 1e3,
         "pair_evals_per_s": pairs / t_mix,
         "one_by_one_ms": t_seq * 1e3,
+        "scheduler_efficiency": pairs * OPS_PER_PAIR / (t_mix * ALU_PEAK),
+        "scheduler_efficiency_note": "sum of the jobs' ideal times (pairs x 31 lane-ops at the ALU peak) over the "
+                                     "launch's makespan x peak",
     }
     if not args.no_cpu:
         res.update(mixed_accuracy(inst, maps, outs))

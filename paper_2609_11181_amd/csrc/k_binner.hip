@@ -41,25 +41,48 @@ __global__ void k_keys(int64_t n, const double* ra, const double* dec, int nside
   idx[i] = (uint32_t)i;
 }
 
-__global__ void k_count(int64_t n, const uint32_t* keys, uint32_t* counts) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&counts[keys[i]], 1u);
+// Offset table from the sorted keys (Sect. 3.4: pixel q owns rows
+// [off[q], off[q+1])), without counting: off[q] is the first row whose key
+// is at least q. The pixels up to the first key get 0 and those past the
+// last key get n (k_offsets_ends); every run start k writes its own key and
+// the keys skipped since the previous run (empty pixels inside the
+// footprint, k_offsets_runs).
+__global__ void k_offsets_ends(int64_t n, const uint32_t* skeys, int64_t npix, int64_t* off) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q > npix) return;
+  if (n == 0) {
+    off[q] = 0;
+  } else if (q <= (int64_t)skeys[0]) {
+    off[q] = 0;
+  } else if (q > (int64_t)skeys[n - 1]) {
+    off[q] = n;
+  }
+}
+
+__global__ void k_offsets_runs(int64_t n, const uint32_t* skeys, int64_t* off) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0 || k >= n) return;
+  const int64_t a = skeys[k - 1], b = skeys[k];
+  for (int64_t q = a + 1; q <= b; ++q) off[q] = k;
 }
 
 __global__ void k_gather(int64_t n, const uint32_t* skeys, const uint32_t* sidx, const double* ra, const double* dec,
                          const float* g1, const float* g2, const float* w, int nside, double4* P, float4* F,
                          float4* G, int64_t* order, unsigned int* max_chord_bits) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  const int64_t k0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = k0 < n;
+  const int64_t k = live ? k0 : n - 1;  // a lane past the end repeats the last row (no store)
   const uint32_t i = sidx[k];
   double sa, ca, sd, cd;
   sincos(ra[i], &sa, &ca);
   sincos(dec[i], &sd, &cd);
   const double x = cd * ca, y = cd * sa, z = sd;
-  P[k] = make_double4(x, y, z, 0.0);
-  F[k] = make_float4((float)ca, (float)sa, (float)sd, (float)cd);
-  G[k] = make_float4(g1[i], g2[i], w ? w[i] : 1.0f, 0.0f);
-  order[k] = (int64_t)i;
+  if (live) {
+    P[k] = make_double4(x, y, z, 0.0);
+    F[k] = make_float4((float)ca, (float)sa, (float)sd, (float)cd);
+    G[k] = make_float4(g1[i], g2[i], w ? w[i] : 1.0f, 0.0f);
+    order[k] = (int64_t)i;
+  }
   // distance to the centre of the galaxy's pixel (bounds the disc search)
   int rr, jj;
   pixel_ring(nside, (int64_t)skeys[k], &rr, &jj);
@@ -67,8 +90,12 @@ __global__ void k_gather(int64_t n, const uint32_t* skeys, const uint32_t* sidx,
   double sp, cp;
   sincospi((double)(2 * jj + R.twice_o) / (double)R.n, &sp, &cp);
   const double dx = x - R.s * cp, dy = y - R.s * sp, dz = z - R.z;
-  const float c = (float)sqrt(dx * dx + dy * dy + dz * dz) * 1.0000002f;
-  atomicMax(max_chord_bits, __float_as_uint(c));
+  float c = (float)sqrt(dx * dx + dy * dy + dz * dz) * 1.0000002f;
+  // the largest distance: a wave maximum, then one atomic per wave (a
+  // non-negative float orders like its bit pattern)
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) c = fmaxf(c, __shfl_xor(c, m, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(max_chord_bits, __float_as_uint(c));
 }
 
 // Pixel sums of a partitioned catalogue: kSumLanes lanes per pixel stride
@@ -203,17 +230,17 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
   const int64_t npix = 12LL * nside * nside;
   int nbits = 1;
   while ((1LL << nbits) < npix) ++nbits;
-  uint32_t *keys = nullptr, *idx = nullptr, *skeys = nullptr, *sidx = nullptr, *counts = nullptr;
+  uint32_t *keys = nullptr, *idx = nullptr, *skeys = nullptr, *sidx = nullptr;
   int* flag = nullptr;
   unsigned int* mc = nullptr;
   int rc = SMART_OK;
   auto cleanup = [&]() {
     (void)hipDeviceSynchronize();  // the blocks go back to the cache idle
-    for (void* q : {(void*)keys, (void*)idx, (void*)skeys, (void*)sidx, (void*)counts, (void*)flag, (void*)mc})
+    for (void* q : {(void*)keys, (void*)idx, (void*)skeys, (void*)sidx, (void*)flag, (void*)mc})
       dev_release(q);
   };
   if ((rc = dmalloc(&keys, n)) || (rc = dmalloc(&idx, n)) || (rc = dmalloc(&skeys, n)) || (rc = dmalloc(&sidx, n)) ||
-      (rc = dmalloc(&counts, npix + 1)) || (rc = dmalloc(&flag, 1)) || (rc = dmalloc(&mc, 1)) ||
+      (rc = dmalloc(&flag, 1)) || (rc = dmalloc(&mc, 1)) ||
       (rc = dmalloc(&d->P, n)) || (rc = dmalloc(&d->F, n)) || (rc = dmalloc(&d->G, n)) ||
       (rc = dmalloc(&d->order, n)) || (rc = dmalloc(&d->offsets, npix + 1))) {
     cleanup();
@@ -225,8 +252,7 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
     cleanup();
     return code;
   };
-  if (hipMemsetAsync(flag, 0, sizeof(int), st) != hipSuccess || hipMemsetAsync(mc, 0, sizeof(unsigned), st) != hipSuccess ||
-      hipMemsetAsync(counts, 0, sizeof(uint32_t) * (npix + 1), st) != hipSuccess) {
+  if (hipMemsetAsync(flag, 0, sizeof(int), st) != hipSuccess || hipMemsetAsync(mc, 0, sizeof(unsigned), st) != hipSuccess) {
     set_error("memset failed");
     return fail(SMART_EDEVICE);
   }
@@ -234,26 +260,20 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
     hipLaunchKernelGGL(k_keys, dim3(grid_of(n)), dim3(kBlock), 0, st, n, ra, dec, nside, keys, idx, flag);
     size_t tb = 0;
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, skeys, idx, sidx, (int)n, 0, nbits, st);
-    size_t tb2 = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, counts, d->offsets, (int)(npix + 1), st);
-    if ((rc = ensure_temp(ctx, tb > tb2 ? tb : tb2))) return fail(rc);
+    if ((rc = ensure_temp(ctx, tb))) return fail(rc);
     tb = ctx->temp_bytes;
     if (hipcub::DeviceRadixSort::SortPairs(ctx->d_temp, tb, keys, skeys, idx, sidx, (int)n, 0, nbits, st) !=
         hipSuccess) {
       set_error("radix sort failed");
       return fail(SMART_EDEVICE);
     }
-    hipLaunchKernelGGL(k_count, dim3(grid_of(n)), dim3(kBlock), 0, st, n, skeys, counts);
     hipLaunchKernelGGL(k_gather, dim3(grid_of(n)), dim3(kBlock), 0, st, n, skeys, sidx, ra, dec, g1, g2, w, nside,
                        d->P, d->F, d->G, d->order, mc);
-  } else {
-    size_t tb2 = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, counts, d->offsets, (int)(npix + 1), st);
-    if ((rc = ensure_temp(ctx, tb2))) return fail(rc);
   }
-  size_t tb = ctx->temp_bytes;
-  if (hipcub::DeviceScan::ExclusiveSum(ctx->d_temp, tb, counts, d->offsets, (int)(npix + 1), st) != hipSuccess) {
-    set_error("offset scan failed");
+  hipLaunchKernelGGL(k_offsets_ends, dim3(grid_of(npix + 1)), dim3(kBlock), 0, st, n, skeys, npix, d->offsets);
+  if (n > 1) hipLaunchKernelGGL(k_offsets_runs, dim3(grid_of(n)), dim3(kBlock), 0, st, n, skeys, d->offsets);
+  if (hipGetLastError() != hipSuccess) {
+    set_error("offset kernels failed to launch");
     return fail(SMART_EDEVICE);
   }
   int hflag = 0;
