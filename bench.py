@@ -38,9 +38,10 @@ OPS_PER_PAIR = 31
 # plain-ALU peak: 256 CUs x 64 lanes x 2.4 GHz, one lane op per clock
 ALU_PEAK = 256 * 64 * 2.4e9
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0)
-# counter runs of the default workload (the committed counter summary of the pixel kernels); valid
-# for that kernel version and workload only
-TRAFFIC_BYTES = {"k_pixel_f32 (20 arcmin)": 1.627e10}
+# counter runs of the default workload, double maps (profiles/pixel_kernels_nside4096_15000deg2_3scales.md,
+# which names the source version it was measured on); valid for that kernel version and workload only
+TRAFFIC_BYTES = {"k_pixel_f32 (20 arcmin)": 1.680e10}
+TRAFFIC_SOURCE = "profiles/pixel_kernels_nside4096_15000deg2_3scales.md"
 
 
 def parse():
@@ -863,6 +864,8 @@ def main():
     del zero_u
     default_workload = args.nside == 4096 and args.area == 15000.0
     res["roofline"]["traffic"] = TRAFFIC_BYTES.get(res["roofline"]["kernel"]) if default_workload else None
+    if res["roofline"]["traffic"] is not None:
+        res["roofline"]["traffic_source"] = TRAFFIC_SOURCE
     # accuracy on the oracle sample + CPU baseline
     if cpu is not None:
         out_pix, refs, cpairs, cdt, avg_check, workers = cpu
