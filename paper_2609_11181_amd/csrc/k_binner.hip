@@ -66,26 +66,36 @@ __global__ void k_offsets_runs(int64_t n, const uint32_t* skeys, int64_t* off) {
   for (int64_t q = a + 1; q <= b; ++q) off[q] = k;
 }
 
-__global__ void k_gather(int64_t n, const uint32_t* skeys, const uint32_t* sidx, const double* ra, const double* dec,
-                         const float* g1, const float* g2, const float* w, int nside, double4* P, float4* F,
-                         float4* G, int64_t* order, unsigned int* max_chord_bits) {
-  const int64_t k0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = k0 < n;
-  const int64_t k = live ? k0 : n - 1;  // a lane past the end repeats the last row (no store)
-  const uint32_t i = sidx[k];
+// Sorted position of every catalogue row: rank[sidx[k]] = k.
+__global__ void k_rank(int64_t n, const uint32_t* sidx, uint32_t* rank) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) rank[sidx[k]] = (uint32_t)k;
+}
+
+// The sorted records, written from catalogue order: row i is read with
+// coalesced loads (position, shear, weight) and its records are stored at
+// its sorted position rank[i] (the permutation costs scattered stores of
+// whole records instead of scattered loads of every column).
+__global__ void k_place(int64_t n, const uint32_t* keys, const uint32_t* rank, const double* ra, const double* dec,
+                        const float* g1, const float* g2, const float* w, int nside, double4* P, float4* F,
+                        float4* G, int64_t* order, unsigned int* max_chord_bits) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i0 < n;
+  const int64_t i = live ? i0 : n - 1;  // a lane past the end repeats the last row (no store)
   double sa, ca, sd, cd;
   sincos(ra[i], &sa, &ca);
   sincos(dec[i], &sd, &cd);
   const double x = cd * ca, y = cd * sa, z = sd;
   if (live) {
+    const int64_t k = rank[i];
     P[k] = make_double4(x, y, z, 0.0);
     F[k] = make_float4((float)ca, (float)sa, (float)sd, (float)cd);
     G[k] = make_float4(g1[i], g2[i], w ? w[i] : 1.0f, 0.0f);
-    order[k] = (int64_t)i;
+    order[k] = i;
   }
   // distance to the centre of the galaxy's pixel (bounds the disc search)
   int rr, jj;
-  pixel_ring(nside, (int64_t)skeys[k], &rr, &jj);
+  pixel_ring(nside, (int64_t)keys[i], &rr, &jj);
   const Ring R = ring_info(nside, rr);
   double sp, cp;
   sincospi((double)(2 * jj + R.twice_o) / (double)R.n, &sp, &cp);
@@ -267,7 +277,9 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
       set_error("radix sort failed");
       return fail(SMART_EDEVICE);
     }
-    hipLaunchKernelGGL(k_gather, dim3(grid_of(n)), dim3(kBlock), 0, st, n, skeys, sidx, ra, dec, g1, g2, w, nside,
+    // idx (the unsorted row numbers) is free after the sort: it takes the ranks
+    hipLaunchKernelGGL(k_rank, dim3(grid_of(n)), dim3(kBlock), 0, st, n, sidx, idx);
+    hipLaunchKernelGGL(k_place, dim3(grid_of(n)), dim3(kBlock), 0, st, n, keys, idx, ra, dec, g1, g2, w, nside,
                        d->P, d->F, d->G, d->order, mc);
   }
   hipLaunchKernelGGL(k_offsets_ends, dim3(grid_of(npix + 1)), dim3(kBlock), 0, st, n, skeys, npix, d->offsets);
