@@ -329,15 +329,34 @@ int smart_plan_tiles(smart_plan plan, int scale, int* n_belt, int* n_general, in
  * `stream`): the general kernel with its per-ring set-up inline or out of
  * line, and the persistent grid (blocks per compute unit) of the general and
  * belt kernels; the fastest stays in the plan for later smart_run and
- * smart_mixed_batch calls. Results are identical for every choice. Stops
- * measuring after about budget_ms of host time (scales not reached keep the
- * defaults). With cache_path non-NULL, choices are first looked up in that
- * text file (one line per workload and scale; the key holds NSIDE, n_out,
- * the tile counts, theta_ap and the filter kind) and new results are
- * appended to it; budget_ms = 0 only looks up. Synchronises `stream`;
- * allocates one scratch output of 5 x n_out floats while measuring. Other
- * plans return SMART_OK unchanged. */
+ * smart_mixed_batch calls. Results are identical for every choice. For every
+ * scale of a galaxy-variant FP32 plan (sphS_pos, sphS_posB, barycentre
+ * data) it times the two forms of the galaxy kernel (below) and keeps the
+ * faster; the forms sum the same members in different orders, so results
+ * agree to FP32 rounding. Stops measuring after about budget_ms of host
+ * time (scales not reached keep the defaults). With cache_path non-NULL,
+ * choices are first looked up in that text file (one line per workload and
+ * scale; the key holds NSIDE, n_out, the tile counts (pixel plans) or the
+ * binning NSIDE and catalogue size (galaxy plans), theta_ap and the filter
+ * kind) and new results are appended to it; budget_ms = 0 only looks up.
+ * Synchronises `stream`; allocates one scratch output of 5 x n_out values
+ * while measuring. Other plans return SMART_OK unchanged. */
 int smart_autotune(smart_plan plan, int budget_ms, const char* cache_path, void* stream);
+
+/* Galaxy kernel form of one scale of a galaxy-variant FP32 plan:
+ * SMART_GAL_LANE (one lane per aperture centre; each row load is shared by
+ * 64 centres: small discs) or SMART_GAL_WAVE (one wave per centre streaming
+ * the disc's catalogue rows coalesced: discs of thousands of galaxies).
+ * Plan creation picks the form from the candidate rows of up to 1024
+ * sampled centres (the wave form from 256 rows per centre in runs of 48
+ * consecutive rows or more on average); smart_autotune
+ * measures it; the setter overrides it for later smart_run and
+ * smart_noise_galaxy_batch calls. SMART_EINVAL for other plans, a scale out
+ * of range or an unknown form. */
+#define SMART_GAL_LANE 0
+#define SMART_GAL_WAVE 1
+int smart_plan_galaxy_form(smart_plan plan, int scale, int* form);
+int smart_plan_set_galaxy_form(smart_plan plan, int scale, int form);
 
 /* Kernel timing (tracing). With enable != 0, later smart_run calls on a
  * pixel-variant FP32 plan record HIP events on the run's stream around the

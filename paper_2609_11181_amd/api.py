@@ -267,6 +267,15 @@ class Plan:
         path = None if cache_path is None else str(cache_path).encode()
         L.check(self.ctx.lib.smart_autotune(self.h, int(budget_ms), path, _stream(self.ctx.device)))
 
+    def galaxy_form(self, scale: int = 0) -> int:
+        """Galaxy kernel form of a scale (GAL_LANE or GAL_WAVE; galaxy-variant FP32 plans)."""
+        f = C.c_int()
+        L.check(self.ctx.lib.smart_plan_galaxy_form(self.h, scale, C.byref(f)))
+        return f.value
+
+    def set_galaxy_form(self, scale: int, form: int):
+        L.check(self.ctx.lib.smart_plan_set_galaxy_form(self.h, scale, form))
+
     def set_timing(self, enable: bool = True):
         L.check(self.ctx.lib.smart_plan_set_timing(self.h, 1 if enable else 0))
 

@@ -441,6 +441,10 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
     if (e != hipSuccess) return bail(SMART_EDEVICE, std::string("plan validation failed: ") + hipGetErrorString(e));
     if (h & 1) return bail(SMART_EINVAL, "output pixel out of range for nside_out");
   }
+  if (variant == SMART_VAR_GALAXY && precision == SMART_PREC_FP32_GEO64 && (rc = smart::choose_galaxy_forms(p, st))) {
+    smart_plan_free(p);
+    return rc;
+  }
   if (variant == SMART_VAR_PIXEL && precision == SMART_PREC_FP32_GEO64) {
     for (int k = 0; k < n_scales; ++k) {
       p->sched.push_back(new smart::PixelSched());
@@ -504,7 +508,7 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.explicit_v = d->explicit_v ? 1 : 0;
       a.posb = p->posb ? 1 : 0;
       a.cavg = norm == SMART_NORM_AVERAGED ? d->gavg : nullptr;
-      e = launch_galaxy(a, s, p->precision, st);
+      e = launch_galaxy(a, s, p->precision, p->gal_form.empty() ? kGalWave : p->gal_form[k], st);
     }
     if (e != hipSuccess) return fail(SMART_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
   }
@@ -549,6 +553,23 @@ int smart_autotune(smart_plan p, int budget_ms, const char* cache_path, void* st
   int rc;
   if ((rc = set_device(p->ctx))) return rc;
   return smart::autotune(p, budget_ms, cache_path, (hipStream_t)stream);
+}
+
+int smart_plan_galaxy_form(smart_plan p, int scale, int* form) {
+  if (!p || !form) return fail(SMART_EINVAL, "NULL plan or form");
+  if (p->gal_form.empty()) return fail(SMART_EINVAL, "not a galaxy-variant FP32 plan");
+  if (scale < 0 || scale >= (int)p->gal_form.size()) return fail(SMART_EINVAL, "scale out of range");
+  *form = p->gal_form[scale];
+  return SMART_OK;
+}
+
+int smart_plan_set_galaxy_form(smart_plan p, int scale, int form) {
+  if (!p) return fail(SMART_EINVAL, "NULL plan");
+  if (p->gal_form.empty()) return fail(SMART_EINVAL, "not a galaxy-variant FP32 plan");
+  if (scale < 0 || scale >= (int)p->gal_form.size()) return fail(SMART_EINVAL, "scale out of range");
+  if (form != SMART_GAL_LANE && form != SMART_GAL_WAVE) return fail(SMART_EINVAL, "unknown galaxy kernel form");
+  p->gal_form[scale] = form;
+  return SMART_OK;
 }
 
 int smart_plan_set_timing(smart_plan p, int enable) {
@@ -733,7 +754,7 @@ int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int nor
         a.explicit_v = d->explicit_v ? 1 : 0;
         a.posb = p->posb ? 1 : 0;
         a.cavg = norm == SMART_NORM_AVERAGED ? d->gavg : nullptr;
-        e = launch_galaxy(a, s, p->precision, st);
+        e = launch_galaxy(a, s, p->precision, p->gal_form[k], st);
       }
       if (e == hipSuccess)
         e = hipMemcpyAsync(d_out + (((int64_t)k * n_real + r) * 2) * p->n_out, stage, sizeof(float) * 2 * p->n_out,

@@ -298,19 +298,60 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Galaxy variant, FP32 plans: one wave per aperture centre. The lanes first
-// find the centre's catalogue slices together (lane l the window of
-// partition ring lo + l, 64 rings per pass; Sect. 3.4: each window of
-// binning pixels is a contiguous run of sorted rows), then stream every
-// slice with consecutive lanes on consecutive rows (coalesced 48-byte
-// records, neighbouring centres of the wave's XCD reading the same rows
-// from its L2), and finally reduce their partial sums across the wave.
-// Persistent: waves take centres in a fixed interleave within their XCD's
-// contiguous eighth of the output list.
-template <bool TABLE, bool BIG>
-__global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s) {
-  __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
-  __shared__ double tab_c0[TABLE ? kFilterIntervals : 1];
+// Geometry of one aperture centre of a galaxy plan: its unit vector and
+// the partition rings [lo, hi] its candidate pixels lie on. The candidate
+// pixels are those within theta_ap + r_bin (every galaxy within theta_ap
+// lies in one), or, for sphS_posB, exactly the pixels whose centres lie
+// within theta_ap (all of their galaxies are members).
+struct GalCentre {
+  double px, py, pz, zp, sp;
+  int64_t ip2;
+  int np, lo, hi;
+};
+
+__device__ __forceinline__ double gal_radius(const GalaxyArgs& a, double theta_ap) {
+  return a.posb ? theta_ap * (1.0 + 1e-9) + 1e-12 : theta_ap + a.r_bin * (1.0 + 1e-9) + 1e-12;
+}
+
+__device__ __forceinline__ GalCentre gal_centre(const GalaxyArgs& a, int64_t o, double rad) {
+  GalCentre c;
+  int rp, ip;
+  pixel_ring(a.nside_out, a.out_pix[o], &rp, &ip);
+  const Ring R = ring_info(a.nside_out, rp);
+  c.zp = R.z;
+  c.sp = R.s;
+  c.np = R.n;
+  c.ip2 = 2 * (int64_t)ip + R.twice_o;
+  double sphi, cphi;
+  sincospi((double)c.ip2 / (double)R.n, &sphi, &cphi);  // phi_p = pi ip2 / n
+  c.px = c.sp * cphi;
+  c.py = c.sp * sphi;
+  c.pz = c.zp;
+  ring_span(a.nside_bin, atan2(c.sp, c.zp), rad, &c.lo, &c.hi);
+  return c;
+}
+
+// Row ranges [ga, gb) of partition ring r inside the centre's window of
+// squared chord Cw (at most two: the window may wrap round the ring's seam);
+// returns the number of candidate rows
+__device__ __forceinline__ int64_t gal_ring_rows(const GalaxyArgs& a, const GalCentre& c, int r, double Cw,
+                                                 int64_t ga[2], int64_t gb[2]) {
+  ga[0] = ga[1] = gb[0] = gb[1] = 0;
+  const Ring Q = ring_info(a.nside_bin, r);
+  int64_t jlo;
+  int cnt;
+  if (!ring_window(c.zp, c.sp, c.ip2, c.np, Q, Cw, &jlo, &cnt)) return 0;
+  int64_t ja[2], jb[2];
+  const int ns = ring_slices(Q, jlo, cnt, 0, ja, jb);
+  for (int t = 0; t < ns; ++t) {
+    ga[t] = a.offsets[Q.first + ja[t]];
+    gb[t] = a.offsets[Q.first + jb[t] + 1];
+  }
+  return (gb[0] - ga[0]) + (gb[1] - ga[1]);
+}
+
+template <bool TABLE>
+__device__ __forceinline__ Tab stage_table(const ScaleArgs& s, float4* tab_c, double* tab_c0) {
   if (TABLE) {
     for (int k = threadIdx.x; k < kFilterIntervals; k += blockDim.x) {
       tab_c[k] = s.table[k];
@@ -318,7 +359,61 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
     }
     __syncthreads();
   }
-  const Tab tab{tab_c, tab_c0};
+  return Tab{tab_c, tab_c0};
+}
+
+// Galaxy variant, FP32 plans, one lane per aperture centre: for discs of a
+// few hundred candidates, where a wave of 64 centres keeps its lanes busy
+// and the latency of each row load is shared by 64 apertures.
+template <bool TABLE, bool BIG>
+__global__ __launch_bounds__(kBlock) void k_galaxy_f32_lane(GalaxyArgs a, ScaleArgs s) {
+  __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
+  __shared__ double tab_c0[TABLE ? kFilterIntervals : 1];
+  const Tab tab = stage_table<TABLE>(s, tab_c, tab_c0);
+  const int64_t o = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (o >= a.n_out) return;
+  double cp[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) cp[k] = s.cpoly[k];
+  const bool posb = a.posb != 0;
+  const double rad = gal_radius(a, s.theta_ap);
+  const double sh = sin(0.5 * rad);
+  const double Cw = posb ? s.C_ap : 4.0 * sh * sh;
+  const GalCentre c = gal_centre(a, o, rad);
+  Acc64 tot;
+  Acc32 acc;
+  int nacc = 0;
+  for (int r = c.lo; r <= c.hi; ++r) {
+    int64_t ga[2], gb[2];
+    gal_ring_rows(a, c, r, Cw, ga, gb);
+#pragma unroll 1
+    for (int t = 0; t < 2; ++t)
+      for (int64_t g = ga[t]; g < gb[t]; ++g)
+        galaxy_member<TABLE, BIG>(a, s, g, c.px, c.py, c.pz, posb, cp, tab, tot, acc, nacc);
+  }
+  tot.add(acc);
+  write_map(a.out, a.out64, a.n_out, a.scale, o, a.norm, tot, s);
+}
+
+// Galaxy variant, FP32 plans, one wave per aperture centre: for discs of
+// thousands of candidates. The lanes first find the centre's catalogue
+// slices together (lane l the window of partition ring lo + l, 64 rings per
+// pass; Sect. 3.4: each window of binning pixels is a contiguous run of
+// sorted rows) and list the non-empty ones with their running row counts in
+// the wave's LDS; the pass's rows then form one sequence, which the lanes
+// stream 64 consecutive rows at a time (lane l takes row l of each step and
+// moves its own cursor over the list): coalesced 48-byte records,
+// no partly filled steps between slices, and neighbouring centres of the
+// wave's XCD read the same rows from its L2. The partial sums are finally
+// reduced across the wave. Persistent: waves take centres in a fixed
+// interleave within their XCD's contiguous eighth of the output list.
+template <bool TABLE, bool BIG>
+__global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s) {
+  __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
+  __shared__ double tab_c0[TABLE ? kFilterIntervals : 1];
+  __shared__ int64_t sl_row[kBlock / 64][128];  // first row of each listed slice
+  __shared__ int64_t sl_pre[kBlock / 64][128];  // rows of the pass before it
+  const Tab tab = stage_table<TABLE>(s, tab_c, tab_c0);
   double cp[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) cp[k] = s.cpoly[k];
@@ -327,55 +422,76 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
   const int xcd = blockIdx.x & 7;
   const int64_t waves_x = (int64_t)(gridDim.x >> 3) * wpb;  // waves per XCD (grid is a multiple of 8)
   // wave-uniform (scalar registers): the centre, its geometry and the slice bounds
-  const int64_t wid = (int64_t)(blockIdx.x >> 3) * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t wid = (int64_t)(blockIdx.x >> 3) * wpb + wv;
   const int64_t o_begin = a.n_out * xcd / 8, o_end = a.n_out * (xcd + 1) / 8;
   const bool posb = a.posb != 0;
-  // candidate pixels: those within theta_ap + r_bin (every galaxy within
-  // theta_ap lies in one), or, for sphS_posB, exactly the pixels whose
-  // centres lie within theta_ap (all of their galaxies are members)
-  const double rad = posb ? s.theta_ap * (1.0 + 1e-9) + 1e-12 : s.theta_ap + a.r_bin * (1.0 + 1e-9) + 1e-12;
+  const double rad = gal_radius(a, s.theta_ap);
   const double sh = sin(0.5 * rad);
   const double Cw = posb ? s.C_ap : 4.0 * sh * sh;
+  int64_t* const row = sl_row[wv];
+  int64_t* const pre = sl_pre[wv];
   for (int64_t o = o_begin + wid; o < o_end; o += waves_x) {
-    int rp, ip;
-    pixel_ring(a.nside_out, a.out_pix[o], &rp, &ip);
-    const Ring R = ring_info(a.nside_out, rp);
-    const double zp = R.z, sp = R.s;
-    const int64_t ip2 = 2 * (int64_t)ip + R.twice_o;
-    double sphi, cphi;
-    sincospi((double)ip2 / (double)R.n, &sphi, &cphi);  // phi_p = pi ip2 / n
-    const double px = sp * cphi, py = sp * sphi, pz = zp;
-    int lo, hi;
-    ring_span(a.nside_bin, atan2(sp, zp), rad, &lo, &hi);
+    const GalCentre c = gal_centre(a, o, rad);
     Acc64 tot;
     Acc32 acc;
     int nacc = 0;
-    for (int r0 = lo; r0 <= hi; r0 += 64) {
+    for (int r0 = c.lo; r0 <= c.hi; r0 += 64) {
       // this lane's ring: its window as at most two row ranges
       int64_t ga[2] = {0, 0}, gb[2] = {0, 0};
       const int r = r0 + lane;
-      if (r <= hi) {
-        const Ring Q = ring_info(a.nside_bin, r);
-        int64_t jlo;
-        int cnt;
-        if (ring_window(zp, sp, ip2, R.n, Q, Cw, &jlo, &cnt)) {
-          int64_t ja[2], jb[2];
-          const int ns = ring_slices(Q, jlo, cnt, 0, ja, jb);
-          for (int t = 0; t < ns; ++t) {
-            ga[t] = a.offsets[Q.first + ja[t]];
-            gb[t] = a.offsets[Q.first + jb[t] + 1];
+      if (r <= c.hi) gal_ring_rows(a, c, r, Cw, ga, gb);
+      const int64_t c0 = gb[0] - ga[0], c1 = gb[1] - ga[1];
+      const int n_own = (c0 > 0) + (c1 > 0);
+      // inclusive scans over the lanes of (listed slices, rows)
+      int sn = n_own;
+      int64_t sm = c0 + c1;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int tn = __shfl_up(sn, d, 64);
+        const int64_t tm = __shfl_up(sm, d, 64);
+        if (lane >= d) {
+          sn += tn;
+          sm += tm;
+        }
+      }
+      const int n_sl = __builtin_amdgcn_readlane(sn, 63);
+      const int64_t n_rows = readlane64(sm, 63);
+      int k = sn - n_own;
+      int64_t m = sm - (c0 + c1);
+      if (c0 > 0) {
+        row[k] = ga[0];
+        pre[k] = m;
+        ++k;
+        m += c0;
+      }
+      if (c1 > 0) {
+        row[k] = ga[1];
+        pre[k] = m;
+      }
+      // the list is read by other lanes of this wave only
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (n_rows > 0) {
+        // the lane's cursor in the list: slice j, the row of sequence
+        // position 0 in its numbering (base) and where slice j + 1 starts
+        // (n_rows after the last); positions only grow, so it moves forward
+        int j = 0;
+        int64_t base = row[0], nxt = n_sl > 1 ? pre[1] : n_rows;
+        for (int64_t v = lane; v < n_rows; v += 64) {
+          while (v >= nxt) {
+            ++j;
+            base = row[j] - nxt;
+            nxt = j + 1 < n_sl ? pre[j + 1] : n_rows;
           }
+          galaxy_member<TABLE, BIG>(a, s, base + v, c.px, c.py, c.pz, posb, cp, tab, tot, acc, nacc);
         }
       }
-      const int nl = min(64, hi - r0 + 1);
-      for (int l = 0; l < nl; ++l) {
-#pragma unroll 1
-        for (int t = 0; t < 2; ++t) {
-          const int64_t g0 = readlane64(ga[t], l), g1 = readlane64(gb[t], l);
-          for (int64_t g = g0 + lane; g < g1; g += 64)
-            galaxy_member<TABLE, BIG>(a, s, g, px, py, pz, posb, cp, tab, tot, acc, nacc);
-        }
-      }
+      // every lane is done with the list before the next pass rewrites it
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     tot.add(acc);
     tot.se = wave_sum(tot.se);
@@ -385,6 +501,28 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
     tot.sn = wave_sum(tot.sn);
     if (lane == 0) write_map(a.out, a.out64, a.n_out, a.scale, o, a.norm, tot, s);
   }
+}
+
+// Candidate rows (every galaxy of the ring windows) and non-empty row
+// ranges of sampled centres, for the choice between the lane and the wave
+// form of the galaxy kernel: cand[i] and cand[n_samp + i] for centre
+// i * n_out / n_samp.
+__global__ void k_gal_candidates(GalaxyArgs a, double theta_ap, double C_ap, int n_samp, int64_t* cand) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_samp) return;
+  const int64_t o = (int64_t)i * a.n_out / n_samp;
+  const double rad = gal_radius(a, theta_ap);
+  const double sh = sin(0.5 * rad);
+  const double Cw = a.posb ? C_ap : 4.0 * sh * sh;
+  const GalCentre c = gal_centre(a, o, rad);
+  int64_t n = 0, m = 0;
+  for (int r = c.lo; r <= c.hi; ++r) {
+    int64_t ga[2], gb[2];
+    n += gal_ring_rows(a, c, r, Cw, ga, gb);
+    m += (gb[0] > ga[0]) + (gb[1] > ga[1]);
+  }
+  cand[i] = n;
+  cand[n_samp + i] = m;
 }
 
 __global__ __launch_bounds__(kBlock) void k_galaxy_f64(GalaxyArgs a, ScaleArgs s) {
@@ -596,15 +734,20 @@ size_t pixel_work_ints(int64_t n_out) {
   return kQueueInts;
 }
 
-hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, hipStream_t st) {
+hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, int form, hipStream_t st) {
   const dim3 grid((unsigned)blocks_for(a.n_out)), block(kBlock);
   if (a.n_out == 0) return hipSuccess;
+  const bool table = s.filter_kind != SMART_FILTER_POLY;
   if (precision == SMART_PREC_FP64) {
     hipLaunchKernelGGL(k_galaxy_f64, grid, block, 0, st, a, s);
+  } else if (form == kGalLane) {
+    if (table && s.big) hipLaunchKernelGGL((k_galaxy_f32_lane<true, true>), grid, block, 0, st, a, s);
+    else if (table) hipLaunchKernelGGL((k_galaxy_f32_lane<true, false>), grid, block, 0, st, a, s);
+    else if (s.big) hipLaunchKernelGGL((k_galaxy_f32_lane<false, true>), grid, block, 0, st, a, s);
+    else hipLaunchKernelGGL((k_galaxy_f32_lane<false, false>), grid, block, 0, st, a, s);
   } else {
     // persistent waves: the occupancy maximum on every compute unit, a
     // multiple of the eight XCDs
-    const bool table = s.filter_kind != SMART_FILTER_POLY;
     auto go = [&](auto kern, int per_cu) {
       const int64_t need = (a.n_out + kBlock / 64 - 1) / (kBlock / 64);  // one wave per centre at most
       int64_t blocks = std::min<int64_t>((int64_t)device_cus() * per_cu, need);
@@ -620,6 +763,14 @@ hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision,
     else if (s.big) go(k_galaxy_f32<false, true>, occ[1]);
     else go(k_galaxy_f32<false, false>, occ[0]);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gal_candidates(const GalaxyArgs& a, double theta_ap, double C_ap, int n_samp, int64_t* cand,
+                                 hipStream_t st) {
+  if (n_samp <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gal_candidates, dim3((unsigned)((n_samp + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a,
+                     theta_ap, C_ap, n_samp, cand);
   return hipGetLastError();
 }
 

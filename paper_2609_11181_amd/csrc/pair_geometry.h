@@ -20,10 +20,10 @@ constexpr float kCoincidentS2 = 1e-20f;
 // their rounding error stays that of a 32-term sum whatever the disc size.
 constexpr int kChunk = 32;
 
-// Weight, noise and count sums of a run of members, in FP32 (flushed into
+// Noise and count sums of a run of members, in FP32 / int32 (flushed into
 // the FP64 totals every kChunk members).
 struct Acc32 {
-  float sw = 0.f, sv = 0.f;
+  float sv = 0.f;
   int sn = 0;
 };
 
@@ -31,7 +31,6 @@ struct Acc64 {
   double se = 0.0, sb = 0.0, sw = 0.0, sv = 0.0;
   double sn = 0.0;
   __device__ void add(const Acc32& a) {
-    sw += a.sw;
     sv += a.sv;
     sn += a.sn;
   }
@@ -116,12 +115,12 @@ struct Coef {
   float q2, pad;
 };
 
-// Accumulation of one galaxy member: E/B in FP64; W, V and N in FP32 runs.
+// Accumulation of one galaxy member: E/B and W in FP64; V and N in FP32 / int32 runs.
 __device__ __forceinline__ void accumulate(double qc, double qs, float q, double a1, double a2, float Ws, float Vs,
                                            int occ, Acc64& tot, Acc32& acc) {
   tot.se = fma(qc, a1, fma(qs, a2, tot.se));
   tot.sb = fma(qc, a2, fma(-qs, a1, tot.sb));
-  acc.sw += Ws;
+  tot.sw += (double)Ws;
   acc.sv = fmaf(q * q, Vs, acc.sv);
   acc.sn += occ;
 }

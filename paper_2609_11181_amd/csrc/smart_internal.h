@@ -128,6 +128,7 @@ struct smart_plan_s {
   bool posb = false;  // galaxy variant with pixel-centre membership (sphS_posB)
   int precision = 0;  // SMART_PREC_FP64 or SMART_PREC_FP32_GEO64
   bool out64 = false;  // FP32 plan whose smart_run maps are double (SMART_PREC_FP32_OUT64)
+  std::vector<int> gal_form;  // galaxy FP32 plans: kernel form per scale (kGalLane / kGalWave)
   int nside_out = 0;
   int64_t n_out = 0;
   int64_t* out_pix = nullptr;
@@ -322,7 +323,15 @@ hipError_t launch_belt(const PixelArgs& a, const ScaleArgs& s, const BeltTab& t,
                        int* cursors, int blocks_per_cu, int cnt_max, hipStream_t st);
 // Compute units of the current device.
 int device_cus();
-hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, hipStream_t st);
+// galaxy kernel forms of FP32 plans: one lane or one wave per centre
+constexpr int kGalLane = SMART_GAL_LANE, kGalWave = SMART_GAL_WAVE;
+// a plan starts with the wave form where the sampled centres have at least
+// kGalWaveMinRows candidate rows on average in runs of kGalWaveMinRun rows
+// or more (smart_autotune measures the choice)
+constexpr double kGalWaveMinRows = 256.0, kGalWaveMinRun = 48.0;
+hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, int form, hipStream_t st);
+hipError_t launch_gal_candidates(const GalaxyArgs& a, double theta_ap, double C_ap, int n_samp, int64_t* cand,
+                                 hipStream_t st);
 hipError_t launch_sum_n(const void* out, int precision, int64_t n_out, int n_scales, double* d_acc,
                         hipStream_t st);
 
@@ -378,6 +387,9 @@ int detect_peaks(smart_ctx ctx, int nside, int64_t n, const int64_t* pix, const 
 
 // autotuner (tune.cpp)
 int autotune(smart_plan p, int budget_ms, const char* cache_path, hipStream_t st);
+// galaxy FP32 plans: the kernel form of every scale from the candidate rows
+// of up to 1024 sampled centres (one synchronisation)
+int choose_galaxy_forms(smart_plan p, hipStream_t st);
 
 // mixed batch (k_mixed.hip)
 int mixed_batch(smart_ctx ctx, int n_plans, const smart_plan* plans, const int* norms, void* const* outs,

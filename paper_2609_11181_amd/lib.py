@@ -14,6 +14,7 @@ FILTER_POLY, FILTER_TANH, FILTER_TABLE = 0, 1, 2
 VAR_GALAXY, VAR_PIXEL, VAR_GALAXY_POSB = 0, 1, 2
 PREC_FP64, PREC_FP32_GEO64, PREC_BF16X3, PREC_FP32_OUT64 = 0, 1, 2, 3
 NORM_SUMMED_CAP, NORM_SUMMED_PIXCOUNT, NORM_RAW, NORM_AVERAGED = 0, 1, 2, 3
+GAL_LANE, GAL_WAVE = 0, 1
 
 EXPORTS = [
     "smart_init", "smart_finalize", "smart_last_error", "smart_version", "smart_filter_define",
@@ -21,7 +22,8 @@ EXPORTS = [
     "smart_data_export", "smart_barycentre_map",
     "smart_data_free", "smart_plan_create", "smart_run", "smart_last_pairs", "smart_plan_free",
     "smart_noise_batch", "smart_noise_angles", "smart_noise_seeded", "smart_noise_galaxy_batch", "smart_mixed_batch", "smart_mixed_batch_noalloc", "smart_detect_peaks", "smart_plan_tiles",
-    "smart_plan_set_timing", "smart_plan_kernel_ms", "smart_autotune",
+    "smart_plan_set_timing", "smart_plan_kernel_ms", "smart_autotune", "smart_plan_galaxy_form",
+    "smart_plan_set_galaxy_form",
 ]
 
 
@@ -65,6 +67,8 @@ _SIGS = {
     "smart_detect_peaks": (_int, [_vp, _int, _i64, _vp, _vp, _vp, C.c_double, _vp, C.POINTER(_i64), _vp]),
     "smart_plan_tiles": (_int, [_vp, _int, C.POINTER(_int), C.POINTER(_int), _vp, _vp, _vp]),
     "smart_plan_set_timing": (_int, [_vp, _int]),
+    "smart_plan_galaxy_form": (_int, [_vp, _int, C.POINTER(_int)]),
+    "smart_plan_set_galaxy_form": (_int, [_vp, _int, _int]),
     "smart_autotune": (_int, [_vp, _int, C.c_char_p, _vp]),
     "smart_plan_kernel_ms": (_int, [_vp, _int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 }
