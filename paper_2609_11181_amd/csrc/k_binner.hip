@@ -14,6 +14,7 @@
 #include <hipcub/hipcub.hpp>
 #include <math.h>
 
+#include <algorithm>
 #include <string>
 
 #include "hpx_ring.h"
@@ -25,20 +26,39 @@ namespace {
 
 constexpr double kHalfPi = 1.57079632679489661923;
 
-__global__ void k_keys(int64_t n, const double* ra, const double* dec, int nside, uint32_t* keys, uint32_t* idx,
-                       int* flag) {
+// One catalogue row as one aligned 32-byte record (position, shear,
+// weight, catalogue index), written in catalogue order next to the sort
+// keys: the sort moves (key, row) pairs only, and the sorted records are
+// built from one record load per row through the sorted row numbers
+// instead of one random load per column.
+struct alignas(16) GalRec {
+  double ra, dec;
+  float g1, g2, w;
+  uint32_t i;
+};
+static_assert(sizeof(GalRec) == 32, "sort record layout");
+
+__global__ void k_keys(int64_t n, const double* ra, const double* dec, const float* g1, const float* g2,
+                       const float* w, int nside, uint32_t* keys, uint32_t* idx, GalRec* rec, int* flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double a = ra[i], d = dec[i];
+  GalRec r;
+  r.ra = a;
+  r.dec = d;
+  r.g1 = g1[i];
+  r.g2 = g2[i];
+  r.w = w ? w[i] : 1.0f;
+  r.i = (uint32_t)i;
+  rec[i] = r;
+  idx[i] = (uint32_t)i;
   if (!isfinite(a) || !isfinite(d) || d < -kHalfPi || d > kHalfPi) {
     atomicOr(flag, 1);
     keys[i] = 0;
-    idx[i] = (uint32_t)i;
     return;
   }
   const double s = sin(0.5 * (kHalfPi - fabs(d)));
   keys[i] = (uint32_t)pixel_of(nside, sin(d), 2.0 * s * s, a);
-  idx[i] = (uint32_t)i;
 }
 
 // Offset table from the sorted keys (Sect. 3.4: pixel q owns rows
@@ -66,46 +86,45 @@ __global__ void k_offsets_runs(int64_t n, const uint32_t* skeys, int64_t* off) {
   for (int64_t q = a + 1; q <= b; ++q) off[q] = k;
 }
 
-// Sorted position of every catalogue row: rank[sidx[k]] = k.
-__global__ void k_rank(int64_t n, const uint32_t* sidx, uint32_t* rank) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) rank[sidx[k]] = (uint32_t)k;
-}
-
-// The sorted records, written from catalogue order: row i is read with
-// coalesced loads (position, shear, weight) and its records are stored at
-// its sorted position rank[i] (the permutation costs scattered stores of
-// whole records instead of scattered loads of every column).
-__global__ void k_place(int64_t n, const uint32_t* keys, const uint32_t* rank, const double* ra, const double* dec,
-                        const float* g1, const float* g2, const float* w, int nside, double4* P, float4* F,
-                        float4* G, int64_t* order, unsigned int* max_chord_bits) {
-  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = i0 < n;
-  const int64_t i = live ? i0 : n - 1;  // a lane past the end repeats the last row (no store)
-  double sa, ca, sd, cd;
-  sincos(ra[i], &sa, &ca);
-  sincos(dec[i], &sd, &cd);
-  const double x = cd * ca, y = cd * sa, z = sd;
-  if (live) {
-    const int64_t k = rank[i];
+// The sorted records: row k is catalogue row sidx[k] (one 32-byte record
+// load), written as unit vector, local frame, shear and weight, catalogue
+// index; and the largest distance of a galaxy from the centre of its pixel,
+// which bounds the disc search. Grid-stride over a bounded grid: each
+// thread keeps a running maximum, and the block's maximum goes to memory
+// with one atomic (a non-negative float orders like its bit pattern;
+// atomics on one address are serialised, so one per wave of a
+// catalogue-sized grid would take longer than the whole pass).
+__global__ __launch_bounds__(kBlock) void k_finish(int64_t n, const uint32_t* skeys, const uint32_t* sidx,
+                                                   const GalRec* rec, int nside, double4* P, float4* F, float4* G,
+                                                   int64_t* order, unsigned int* max_chord_bits) {
+  __shared__ float wave_max[kBlock / 64];
+  float c = 0.0f;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const GalRec r = rec[sidx[k]];
+    double sa, ca, sd, cd;
+    sincos(r.ra, &sa, &ca);
+    sincos(r.dec, &sd, &cd);
+    const double x = cd * ca, y = cd * sa, z = sd;
     P[k] = make_double4(x, y, z, 0.0);
     F[k] = make_float4((float)ca, (float)sa, (float)sd, (float)cd);
-    G[k] = make_float4(g1[i], g2[i], w ? w[i] : 1.0f, 0.0f);
-    order[k] = i;
+    G[k] = make_float4(r.g1, r.g2, r.w, 0.0f);
+    order[k] = (int64_t)r.i;
+    int rr, jj;
+    pixel_ring(nside, (int64_t)skeys[k], &rr, &jj);
+    const Ring R = ring_info(nside, rr);
+    double sp, cp;
+    sincospi((double)(2 * jj + R.twice_o) / (double)R.n, &sp, &cp);
+    const double dx = x - R.s * cp, dy = y - R.s * sp, dz = z - R.z;
+    c = fmaxf(c, (float)sqrt(dx * dx + dy * dy + dz * dz) * 1.0000002f);
   }
-  // distance to the centre of the galaxy's pixel (bounds the disc search)
-  int rr, jj;
-  pixel_ring(nside, (int64_t)keys[i], &rr, &jj);
-  const Ring R = ring_info(nside, rr);
-  double sp, cp;
-  sincospi((double)(2 * jj + R.twice_o) / (double)R.n, &sp, &cp);
-  const double dx = x - R.s * cp, dy = y - R.s * sp, dz = z - R.z;
-  float c = (float)sqrt(dx * dx + dy * dy + dz * dz) * 1.0000002f;
-  // the largest distance: a wave maximum, then one atomic per wave (a
-  // non-negative float orders like its bit pattern)
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) c = fmaxf(c, __shfl_xor(c, m, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(max_chord_bits, __float_as_uint(c));
+  if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 1; v < kBlock / 64; ++v) c = fmaxf(c, wave_max[v]);
+    atomicMax(max_chord_bits, __float_as_uint(c));
+  }
 }
 
 // Pixel sums of a partitioned catalogue: kSumLanes lanes per pixel stride
@@ -241,15 +260,17 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
   int nbits = 1;
   while ((1LL << nbits) < npix) ++nbits;
   uint32_t *keys = nullptr, *idx = nullptr, *skeys = nullptr, *sidx = nullptr;
+  GalRec* rec = nullptr;
   int* flag = nullptr;
   unsigned int* mc = nullptr;
   int rc = SMART_OK;
   auto cleanup = [&]() {
     (void)hipDeviceSynchronize();  // the blocks go back to the cache idle
-    for (void* q : {(void*)keys, (void*)idx, (void*)skeys, (void*)sidx, (void*)flag, (void*)mc})
+    for (void* q : {(void*)keys, (void*)idx, (void*)skeys, (void*)sidx, (void*)rec, (void*)flag, (void*)mc})
       dev_release(q);
   };
   if ((rc = dmalloc(&keys, n)) || (rc = dmalloc(&idx, n)) || (rc = dmalloc(&skeys, n)) || (rc = dmalloc(&sidx, n)) ||
+      (rc = dmalloc(&rec, n)) ||
       (rc = dmalloc(&flag, 1)) || (rc = dmalloc(&mc, 1)) ||
       (rc = dmalloc(&d->P, n)) || (rc = dmalloc(&d->F, n)) || (rc = dmalloc(&d->G, n)) ||
       (rc = dmalloc(&d->order, n)) || (rc = dmalloc(&d->offsets, npix + 1))) {
@@ -267,7 +288,8 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
     return fail(SMART_EDEVICE);
   }
   if (n > 0) {
-    hipLaunchKernelGGL(k_keys, dim3(grid_of(n)), dim3(kBlock), 0, st, n, ra, dec, nside, keys, idx, flag);
+    hipLaunchKernelGGL(k_keys, dim3(grid_of(n)), dim3(kBlock), 0, st, n, ra, dec, g1, g2, w, nside, keys, idx, rec,
+                       flag);
     size_t tb = 0;
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, skeys, idx, sidx, (int)n, 0, nbits, st);
     if ((rc = ensure_temp(ctx, tb))) return fail(rc);
@@ -277,10 +299,9 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
       set_error("radix sort failed");
       return fail(SMART_EDEVICE);
     }
-    // idx (the unsorted row numbers) is free after the sort: it takes the ranks
-    hipLaunchKernelGGL(k_rank, dim3(grid_of(n)), dim3(kBlock), 0, st, n, sidx, idx);
-    hipLaunchKernelGGL(k_place, dim3(grid_of(n)), dim3(kBlock), 0, st, n, keys, idx, ra, dec, g1, g2, w, nside,
-                       d->P, d->F, d->G, d->order, mc);
+    const int64_t blocks = std::min<int64_t>(grid_of(n), (int64_t)device_cus() * 8);
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, skeys, sidx, rec, nside, d->P, d->F,
+                       d->G, d->order, mc);
   }
   hipLaunchKernelGGL(k_offsets_ends, dim3(grid_of(npix + 1)), dim3(kBlock), 0, st, n, skeys, npix, d->offsets);
   if (n > 1) hipLaunchKernelGGL(k_offsets_runs, dim3(grid_of(n)), dim3(kBlock), 0, st, n, skeys, d->offsets);
