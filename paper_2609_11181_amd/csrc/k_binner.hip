@@ -86,37 +86,50 @@ __global__ void k_offsets_runs(int64_t n, const uint32_t* skeys, int64_t* off) {
   for (int64_t q = a + 1; q <= b; ++q) off[q] = k;
 }
 
+// Sorted row k from its catalogue record: unit vector, local frame, shear
+// and weight, catalogue index; returns the distance of the galaxy from the
+// centre of its pixel.
+__device__ inline float finish_row(int64_t k, const GalRec& r, uint32_t key, int nside, double4* P, float4* F,
+                                   float4* G, int64_t* order) {
+  double sa, ca, sd, cd;
+  sincos(r.ra, &sa, &ca);
+  sincos(r.dec, &sd, &cd);
+  const double x = cd * ca, y = cd * sa, z = sd;
+  P[k] = make_double4(x, y, z, 0.0);
+  F[k] = make_float4((float)ca, (float)sa, (float)sd, (float)cd);
+  G[k] = make_float4(r.g1, r.g2, r.w, 0.0f);
+  order[k] = (int64_t)r.i;
+  int rr, jj;
+  pixel_ring(nside, (int64_t)key, &rr, &jj);
+  const Ring R = ring_info(nside, rr);
+  double sp, cp;
+  sincospi((double)(2 * jj + R.twice_o) / (double)R.n, &sp, &cp);
+  const double dx = x - R.s * cp, dy = y - R.s * sp, dz = z - R.z;
+  return (float)sqrt(dx * dx + dy * dy + dz * dz) * 1.0000002f;
+}
+
 // The sorted records: row k is catalogue row sidx[k] (one 32-byte record
-// load), written as unit vector, local frame, shear and weight, catalogue
-// index; and the largest distance of a galaxy from the centre of its pixel,
-// which bounds the disc search. Grid-stride over a bounded grid: each
-// thread keeps a running maximum, and the block's maximum goes to memory
-// with one atomic (a non-negative float orders like its bit pattern;
-// atomics on one address are serialised, so one per wave of a
-// catalogue-sized grid would take longer than the whole pass).
+// load), and the largest distance of a galaxy from the centre of its
+// pixel, which bounds the disc search. Grid-stride over a bounded grid, two
+// rows per step (both record loads in flight together): each thread keeps a
+// running maximum, and the block's maximum goes to memory with one atomic
+// (a non-negative float orders like its bit pattern; atomics on one address
+// are serialised, so one per wave of a catalogue-sized grid would take
+// longer than the whole pass).
 __global__ __launch_bounds__(kBlock) void k_finish(int64_t n, const uint32_t* skeys, const uint32_t* sidx,
                                                    const GalRec* rec, int nside, double4* P, float4* F, float4* G,
                                                    int64_t* order, unsigned int* max_chord_bits) {
   __shared__ float wave_max[kBlock / 64];
   float c = 0.0f;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
-    const GalRec r = rec[sidx[k]];
-    double sa, ca, sd, cd;
-    sincos(r.ra, &sa, &ca);
-    sincos(r.dec, &sd, &cd);
-    const double x = cd * ca, y = cd * sa, z = sd;
-    P[k] = make_double4(x, y, z, 0.0);
-    F[k] = make_float4((float)ca, (float)sa, (float)sd, (float)cd);
-    G[k] = make_float4(r.g1, r.g2, r.w, 0.0f);
-    order[k] = (int64_t)r.i;
-    int rr, jj;
-    pixel_ring(nside, (int64_t)skeys[k], &rr, &jj);
-    const Ring R = ring_info(nside, rr);
-    double sp, cp;
-    sincospi((double)(2 * jj + R.twice_o) / (double)R.n, &sp, &cp);
-    const double dx = x - R.s * cp, dy = y - R.s * sp, dz = z - R.z;
-    c = fmaxf(c, (float)sqrt(dx * dx + dy * dy + dz * dz) * 1.0000002f);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; k + stride < n; k += 2 * stride) {
+    const uint32_t i0 = sidx[k], i1 = sidx[k + stride];
+    const GalRec r0 = rec[i0], r1 = rec[i1];
+    c = fmaxf(c, finish_row(k, r0, skeys[k], nside, P, F, G, order));
+    c = fmaxf(c, finish_row(k + stride, r1, skeys[k + stride], nside, P, F, G, order));
   }
+  if (k < n) c = fmaxf(c, finish_row(k, rec[sidx[k]], skeys[k], nside, P, F, G, order));
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) c = fmaxf(c, __shfl_xor(c, m, 64));
   if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = c;
