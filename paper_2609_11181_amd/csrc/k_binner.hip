@@ -365,7 +365,7 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
     // source index of the occupied pixels
     int *occ = nullptr, *scan = nullptr;
     if ((rc = dmalloc(&occ, d->n_dense + 1)) || (rc = dmalloc(&scan, d->n_dense + 1)) ||
-        (rc = dmalloc(&d->cidx, d->n_dense)) || (rc = dmalloc(&d->src_pix, n))) {
+        (rc = dmalloc(&d->cidx, d->n_dense))) {
       dev_release(occ);  // nothing has used them yet
       dev_release(scan);
       return fail(rc);
@@ -380,8 +380,8 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
       set_error("source scan failed");
       return fail(SMART_EDEVICE);
     }
-    hipLaunchKernelGGL(k_sources, dim3(grid_of(d->n_dense)), dim3(kBlock), 0, st, d->n_dense, d->pix_first, occ,
-                       scan, d->cidx, d->src_pix);
+    // the source count first, so that the source list holds the occupied
+    // pixels only
     int last_scan = 0, last_occ = 0;
     if (hipMemcpyAsync(&last_scan, scan + (d->n_dense - 1), 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(&last_occ, occ + (d->n_dense - 1), 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -390,6 +390,19 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
       return fail(SMART_EDEVICE);
     }
     d->n_src = (int64_t)last_scan + last_occ;
+    if ((rc = dmalloc(&d->src_pix, d->n_src > 0 ? d->n_src : 1))) {
+      dev_release(occ);  // idle after the synchronisation above
+      dev_release(scan);
+      return fail(rc);
+    }
+    hipLaunchKernelGGL(k_sources, dim3(grid_of(d->n_dense)), dim3(kBlock), 0, st, d->n_dense, d->pix_first, occ,
+                       scan, d->cidx, d->src_pix);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+      dev_release(occ);
+      dev_release(scan);
+      set_error("source index kernel failed");
+      return fail(SMART_EDEVICE);
+    }
     dev_release(occ);  // idle after the synchronisation above
     dev_release(scan);
     if ((rc = build_wn_prefix(ctx, d, st))) return fail(rc);
