@@ -180,32 +180,37 @@ __device__ __forceinline__ uint32_t bmode(uint32_t x) { return ((x >> 16) | (x <
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Dynamic LDS of one stack block for windows of at most cnt_max members:
-// the slab, [slot][2 kNR] split words with the E form (X1, X2) of
-// realisation r at 2 r and its B form (X2, -X1) at 2 r + 1 (also the
-// epilogue's staging of the waves' [2 kNR][kNP] outputs), then each
-// wave's coefficient band, zero-padded by kPadL entries before and kPadR
-// after, so that the operand loads need no range tests.
+// the slab as two planes of packed BF16 words (hi words, then the rounding
+// remainders), each [2 kNR][row] with the E form (X1, X2) of realisation r
+// in row 2 r and its B form (X2, -X1) in row 2 r + 1, slot s of the union
+// window at column s (also the epilogue's staging of the waves'
+// [2 kNR][kNP] outputs); then each wave's coefficient band as a hi and a lo
+// plane, zero-padded by kPadL entries before and kPadR after, so that the
+// operand loads need no range tests. With these layouts the four k values
+// of every MFMA operand register quadruple are four consecutive words of
+// one plane, loaded straight into the operand registers.
 constexpr int kPadL = 32, kPadR = 48;
-// slab row stride in entries: one entry of padding after the 2 kNR entries
-// of a slot, so the 64 lanes of a wave writing 64 consecutive slots spread
-// over the LDS banks
-constexpr int kRowE = 2 * kNR + 1;
 __host__ __device__ constexpr int stack_slab(int cnt_max) { return kNP + cnt_max + 16; }
+// slab row length in words: the union window, the up to seven slots that the
+// last operand step reads past it (their coefficients are zero), and odd so
+// that the 32 rows an MFMA operand load touches start on different banks
+__host__ __device__ constexpr int stack_row(int cnt_max) { return (stack_slab(cnt_max) + 8) | 1; }
 __host__ __device__ constexpr int stack_band(int cnt_max) { return kPadL + cnt_max + kPadR; }
 __host__ __device__ constexpr size_t stack_slab_bytes(int cnt_max) {
-  return (size_t)stack_slab(cnt_max) * kRowE * sizeof(uint2) > (size_t)kStack * 2 * kNR * kNP * sizeof(float)
-             ? (size_t)stack_slab(cnt_max) * kRowE * sizeof(uint2)
+  return (size_t)2 * 2 * kNR * stack_row(cnt_max) * sizeof(uint32_t) > (size_t)kStack * 2 * kNR * kNP * sizeof(float)
+             ? (size_t)2 * 2 * kNR * stack_row(cnt_max) * sizeof(uint32_t)
              : (size_t)kStack * 2 * kNR * kNP * sizeof(float);
 }
 __host__ __device__ constexpr size_t stack_lds_bytes(int cnt_max) {
-  return stack_slab_bytes(cnt_max) + (size_t)kStack * stack_band(cnt_max) * sizeof(uint2);
+  return stack_slab_bytes(cnt_max) + (size_t)kStack * 2 * stack_band(cnt_max) * sizeof(uint32_t);
 }
 
 __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleArgs s, int cnt_max) {
   extern __shared__ uint2 smem[];
-  const int slab_max = stack_slab(cnt_max), band = stack_band(cnt_max);
-  uint2* xs = smem;                                                    // [slab_max][kRowE]
-  uint2* coefP = smem + stack_slab_bytes(cnt_max) / sizeof(uint2);    // [kStack][band]
+  const int slab_max = stack_slab(cnt_max), band = stack_band(cnt_max), RS = stack_row(cnt_max);
+  uint32_t* const xh = reinterpret_cast<uint32_t*>(smem);  // [2 kNR][RS] hi words
+  uint32_t* const xl = xh + 2 * kNR * RS;                   // [2 kNR][RS] remainders
+  uint32_t* const coefP = reinterpret_cast<uint32_t*>(smem) + stack_slab_bytes(cnt_max) / sizeof(uint32_t);
   __shared__ int s_ws[kStack], s_we[kStack];   // per wave window [start, end) on the current ring
   __shared__ float fnorm[kStack][kNP];
   const PixelArgs& a = n.a;
@@ -221,13 +226,17 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
   const bool active = o_w >= 0;
   const int hfirst = active ? n.t.head[iw].x : 0, hnr = active ? n.t.head[iw].y : 0;
   const int lo_w = active ? n.t.info[hfirst].x : 0x7fffffff;
-  uint2* myband = coefP + wave * band;
+  uint32_t* const bandh = coefP + wave * 2 * band;  // [band] hi words of (q cos, q sin)
+  uint32_t* const bandl = bandh + band;              // [band] remainders
   // union of the stack's discs' rings
   __shared__ int s_lo[kStack], s_hi[kStack];
   if (lane == 0) {
     s_lo[wave] = active ? lo_w : 0x7fffffff;
     s_hi[wave] = active ? lo_w + hnr - 1 : -1;
   }
+  // slots past a ring's union window keep finite words (zero, or an earlier
+  // ring's), which the zero coefficients there cancel
+  for (int i = tid; i < 2 * 2 * kNR * RS; i += 64 * kStack) xh[i] = 0u;
   __syncthreads();
   int lo = s_lo[0], hi = s_hi[0];
   for (int w = 1; w < kStack; ++w) {
@@ -257,8 +266,10 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
     // the band's coefficients, zero outside [0, cnt)
     for (int k = lane; k < band; k += 64) {
       const int m = k - kPadL;
-      myband[k] = (m >= 0 && m < cnt) ? split_pair((float)n.t.qc[coff + m], (float)n.t.qs[coff + m])
-                                      : make_uint2(0u, 0u);
+      const uint2 w = (m >= 0 && m < cnt) ? split_pair((float)n.t.qc[coff + m], (float)n.t.qs[coff + m])
+                                          : make_uint2(0u, 0u);
+      bandh[k] = w.x;
+      bandl[k] = w.y;
     }
     const int64_t dring = 2 * (int64_t)N * (N - 1) + (int64_t)nring * (r - N) - a.pix_first;
     if (cnt > 0 && lane < kNP) {  // W and N_occ of the window of centre `lane`
@@ -300,8 +311,10 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
           const float uu = (ci >= 0 && rreal < n.n_real) ? n.u[(int64_t)rreal * n.n_src + ci] : 0.f;
           const float sn = __builtin_amdgcn_sinf(uu), cs = __builtin_amdgcn_cosf(uu);  // of 2 pi u
           const uint2 e = split_pair(gr.x * cs - gr.y * sn, gr.x * sn + gr.y * cs);
-          xs[sl * kRowE + 2 * rr] = e;
-          xs[sl * kRowE + 2 * rr + 1] = make_uint2(bmode(e.x), bmode(e.y));
+          xh[2 * rr * RS + sl] = e.x;
+          xl[2 * rr * RS + sl] = e.y;
+          xh[(2 * rr + 1) * RS + sl] = bmode(e.x);
+          xl[(2 * rr + 1) * RS + sl] = bmode(e.y);
         }
       }
     }
@@ -309,25 +322,28 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
     if (cnt > 0) {
       const int base = ws - us;       // slab slot of this wave's first window pixel
       const int L = kNP + cnt - 1;    // centre t uses window pixels [t, t + cnt)
-      // B column col: realisation col / 2 (E form for even col, B form for
-      // odd) in slab entry col, realisation 16 + col / 2 in entry 32 + col
-      const uint2* bp = xs + col;
-      const uint2* ap = myband + kPadL - col;  // A row col: coefficient js - col
+      // lane (col, half) holds window pixels js = s0 + 4 half + q, q < 4.
+      // A row col: coefficient js - col (zero outside [0, cnt)). B column
+      // col: slab row col (realisation col / 2, E form for even col, B
+      // form for odd) for acc0 and row 32 + col (realisation 16 + col / 2)
+      // for acc1, at slot base + js (past the window the coefficients are
+      // zero and the slots finite)
+      const uint32_t* const ahp = bandh + kPadL - col + 4 * half;
+      const uint32_t* const alp = bandl + kPadL - col + 4 * half;
+      const uint32_t* const b0hp = xh + col * RS + base + 4 * half;
+      const uint32_t* const b0lp = xl + col * RS + base + 4 * half;
+      const uint32_t* const b1hp = b0hp + 32 * RS;
+      const uint32_t* const b1lp = b0lp + 32 * RS;
       for (int s0 = 0; s0 < L; s0 += 8) {
         u32x4 ah, al, b0h, b0l, b1h, b1l;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int js = s0 + half * 4 + q;  // pixel within the window
-          const uint2 w = ap[js];            // zero where js - col is outside [0, cnt)
-          ah[q] = w.x;
-          al[q] = w.y;
-          const int slot = min(base + js, Lu - 1);  // beyond the window A is zero
-          const uint2 x0 = bp[slot * kRowE];
-          const uint2 x1v = bp[slot * kRowE + 32];
-          b0h[q] = x0.x;
-          b0l[q] = x0.y;
-          b1h[q] = x1v.x;
-          b1l[q] = x1v.y;
+          ah[q] = ahp[s0 + q];
+          al[q] = alp[s0 + q];
+          b0h[q] = b0hp[s0 + q];
+          b0l[q] = b0lp[s0 + q];
+          b1h[q] = b1hp[s0 + q];
+          b1l[q] = b1lp[s0 + q];
         }
         const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah), Al = __builtin_bit_cast(bf16x8, al);
         const bf16x8 B0h = __builtin_bit_cast(bf16x8, b0h), B0l = __builtin_bit_cast(bf16x8, b0l);
@@ -355,7 +371,7 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
     fnorm[wave][lane] = f;
   }
   __syncthreads();
-  float* cst = reinterpret_cast<float*>(xs) + wave * (2 * kNR * kNP);  // [2 kNR][kNP] of this wave
+  float* cst = reinterpret_cast<float*>(smem) + wave * (2 * kNR * kNP);  // [2 kNR][kNP] of this wave
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int row = 8 * (i / 4) + 4 * half + (i % 4);  // centre
