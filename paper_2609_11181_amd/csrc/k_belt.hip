@@ -277,7 +277,7 @@ PixelSched::~PixelSched() {
   // the owning plan's free has synchronised the device
   for (void* q : {(void*)gt_head, (void*)gt_pair, (void*)gt_ring, (void*)belt, (void*)general, (void*)cursors,
                   (void*)head, (void*)info, (void*)qc, (void*)qs, (void*)q2, (void*)noise_seg, (void*)noise_stacks,
-                  (void*)noise_rest})
+                  (void*)noise_rest, (void*)noise_qsplit, (void*)noise_wn})
     dev_release(q);
 }
 
@@ -461,6 +461,7 @@ int build_pixel_sched(smart_plan p, int k, hipStream_t st, PixelSched* sc) {
   // out-of-line per-ring set-up pays off for discs of many members per ring
   sc->general_ool = s.theta_ap * (double)N >= 16.0 * 0.75 ? 1 : 0;
   const int n_info = last_o.x + last_c.x, n_coef = last_o.y + last_c.y;
+  sc->n_coef = n_coef;
   BCHK(dev_alloc(&sc->info, sizeof(int4) * std::max(n_info, 1)));
   // coefficient tables with kCoefPad entries of padding (the belt kernel
   // requests the next four members' coefficients ahead of their use)

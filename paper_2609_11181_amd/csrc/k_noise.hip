@@ -119,6 +119,40 @@ __global__ void k_noise_stacks(int n_groups, int ncol, int n_rings, const int4* 
   flags[id] = any;
 }
 
+// W and N_occ of the disc of every list entry that a stack segment covers
+// (segment row i, column c; the entry of centre pixel 32c + l of the
+// segment's run): the prefix-sum differences over its window on each disc
+// ring, rings in ascending order.
+__global__ void k_noise_wn(PixelArgs a, BeltTab t, int ncol, const int4* seg, double2* wn_out) {
+  const int N = a.nside_in, nring = 4 * N;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)(2 * N + 1) * ncol * kNP) return;
+  const int64_t sidx = id / kNP;
+  const int l = (int)(id % kNP);
+  const int i = (int)(sidx / ncol), c = (int)(sidx % ncol);
+  const int4 sg = seg[sidx];
+  if (sg.x < 0 || l < sg.y || l >= sg.z) return;
+  const int first = t.head[i].x, nr = t.head[i].y;
+  double wp = 0.0, np_occ = 0.0;
+  for (int k = 0; k < nr; ++k) {
+    const int4 inf = t.info[first + k];
+    const int cnt = inf.z;
+    if (cnt <= 0) continue;
+    const int64_t dring = 2 * (int64_t)N * (N - 1) + (int64_t)nring * (inf.x - N) - a.pix_first;
+    const int j0 = (kNP * c + inf.y + l) & (nring - 1);
+    const int run = min(cnt, nring - j0);
+    const double2 l1 = a.wn[dring + j0], h1 = a.wn[dring + j0 + run];
+    wp += h1.x - l1.x;
+    np_occ += h1.y - l1.y;
+    if (run < cnt) {
+      const double2 l2 = a.wn[dring], h2 = a.wn[dring + cnt - run];
+      wp += h2.x - l2.x;
+      np_occ += h2.y - l2.y;
+    }
+  }
+  wn_out[sg.x + (l - sg.y)] = make_double2(wp, np_occ);
+}
+
 // outputs outside every stack: list positions and pixels
 __global__ void k_noise_rest(const int* covered, const int64_t* out_pix, int64_t n_out, int* flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -156,6 +190,8 @@ struct NoiseArgs {
   int n_grp;          // realisation blocks of kNR
   float* out;         // [n_scales][r_stride][2][n_out]: realisation r at r_base + r
   int r_stride, r_base;
+  const uint2* qsplit;    // belt coefficients (q cos, q sin) as split BF16 words
+  const double2* wn_out;  // (W, N_occ) of each list entry that a stack segment covers
   double* mom;        // moments mode (out unused): [n_scales][4][n_out] += sum of E, E^2, B, B^2
 };
 
@@ -205,27 +241,59 @@ __host__ __device__ constexpr size_t stack_lds_bytes(int cnt_max) {
   return stack_slab_bytes(cnt_max) + (size_t)kStack * 2 * stack_band(cnt_max) * sizeof(uint32_t);
 }
 
-__global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleArgs s, int cnt_max) {
+// Belt coefficients (q cos 2psi, q sin 2psi) as the split BF16 words of the
+// stack kernel's A operand (hi words, then the rounding remainders).
+__global__ void k_split_coef(const double* qc, const double* qs, int n, uint2* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = split_pair((float)qc[i], (float)qs[i]);
+}
+
+// Block barrier for LDS traffic only: waits for this wave's LDS operations,
+// not for its global loads, so that the next ring's operands (requested
+// before the current ring's MFMA steps) stay in flight across it. The
+// kernel's global data are read-only inputs.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Inputs of one 64-slot chunk of a ring's slab, one slot per lane: source
+// index, shear sums and the angles of the wave's realisations.
+constexpr int kWaveReal = kNR / kStack;  // realisations each wave generates
+struct SlabIn {
+  int ci;
+  float2 g;
+  float u[kWaveReal];
+};
+
+// Ring loop, software-pipelined: while the MFMA steps of ring r run, the
+// coefficient band, source indices, shear sums and angles of ring r + 1 are
+// already requested, and the windows of ring r + 1 were published one
+// barrier earlier, so a ring costs two LDS barriers and no exposed global
+// load.
+__global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))) void k_noise_stack(NoiseArgs n, ScaleArgs s,
+                                                                                                  int cnt_max) {
   extern __shared__ uint2 smem[];
   const int slab_max = stack_slab(cnt_max), band = stack_band(cnt_max), RS = stack_row(cnt_max);
   uint32_t* const xh = reinterpret_cast<uint32_t*>(smem);  // [2 kNR][RS] hi words
   uint32_t* const xl = xh + 2 * kNR * RS;                   // [2 kNR][RS] remainders
   uint32_t* const coefP = reinterpret_cast<uint32_t*>(smem) + stack_slab_bytes(cnt_max) / sizeof(uint32_t);
-  __shared__ int s_ws[kStack], s_we[kStack];   // per wave window [start, end) on the current ring
+  __shared__ int2 s_win[2][kStack];  // per wave window [start, end] on a ring, by ring parity
   __shared__ float fnorm[kStack][kNP];
   const PixelArgs& a = n.a;
   const int N = a.nside_in, nring = 4 * N;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
+  const int lane = tid & 63;
+  // wave-uniform values are kept in scalar registers
+  auto uni_i = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+  const int wave = uni_i(tid >> 6);
   const int sid = n.stacks[blockIdx.x / n.n_grp];
   const int rg = blockIdx.x % n.n_grp;  // realisation block
   const int c = sid / n.n_groups, g = sid % n.n_groups;
   const int iw = kStack * g + wave;     // belt ring index of this wave (ring N + iw)
-  const int4 sg = iw <= 2 * N ? n.seg[(int64_t)iw * n.ncol + c] : make_int4(-1, 0, 0, 0);
+  const int4 sg4 = iw <= 2 * N ? n.seg[(int64_t)iw * n.ncol + c] : make_int4(-1, 0, 0, 0);
+  const int4 sg = make_int4(uni_i(sg4.x), uni_i(sg4.y), uni_i(sg4.z), 0);
   const int o_w = sg.x;
   const bool active = o_w >= 0;
-  const int hfirst = active ? n.t.head[iw].x : 0, hnr = active ? n.t.head[iw].y : 0;
-  const int lo_w = active ? n.t.info[hfirst].x : 0x7fffffff;
+  const int hfirst = uni_i(active ? n.t.head[iw].x : 0), hnr = uni_i(active ? n.t.head[iw].y : 0);
+  const int lo_w = uni_i(active ? n.t.info[hfirst].x : 0x7fffffff);
   uint32_t* const bandh = coefP + wave * 2 * band;  // [band] hi words of (q cos, q sin)
   uint32_t* const bandl = bandh + band;              // [band] remainders
   // union of the stack's discs' rings
@@ -243,85 +311,132 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
     lo = min(lo, s_lo[w]);
     hi = max(hi, s_hi[w]);
   }
+  lo = uni_i(lo);
+  hi = uni_i(hi);
 
-  f32x16 acc0 = {0}, acc1 = {0};
-  double wp = 0.0, np_occ = 0.0;  // lanes 0..31: W and N_occ of centre o_w + lane
-  const int col = lane & 31;      // MFMA row (A) / column (B)
-  const int half = lane >> 5;     // k-slice of the lane
-
-  for (int r = lo; r <= hi; ++r) {
-    // this wave's window on ring r for its first centre (pixel 32c of ring N + iw)
-    int cnt = 0, coff = 0, ws = 0;
+  // this wave's window on ring r for its first centre (pixel 32c of ring N + iw)
+  auto own = [&](int r, int& cnt, int& coff, int& ws) {
+    cnt = 0;
+    coff = 0;
+    ws = 0;
     if (active && r >= lo_w && r < lo_w + hnr) {
       const int4 inf = n.t.info[hfirst + (r - lo_w)];
-      cnt = inf.z;
-      coff = inf.w;
-      ws = kNP * c + inf.y;
+      cnt = uni_i(inf.z);
+      coff = uni_i(inf.w);
+      ws = uni_i(kNP * c + inf.y);
     }
-    const int we = cnt > 0 ? ws + kNP + cnt - 1 : ws;
-    if (lane == 0) {
-      s_ws[wave] = cnt > 0 ? ws : 0x7fffffff;
-      s_we[wave] = cnt > 0 ? we : -0x7fffffff;
+  };
+  auto post = [&](int r, int cnt, int ws) {
+    if (lane == 0) s_win[r & 1][wave] = cnt > 0 ? make_int2(ws, ws + kNP + cnt - 1) : make_int2(0x7fffffff, -0x7fffffff);
+  };
+  // the union window [us, ue) of the stack's waves on ring r, and its slots
+  auto uni = [&](int r, int& us, int& Lu) {
+    int ue = -0x7fffffff;
+    us = 0x7fffffff;
+    for (int w = 0; w < kStack; ++w) {
+      const int2 v = s_win[r & 1][w];
+      us = min(us, v.x);
+      ue = max(ue, v.y);
     }
-    // the band's coefficients, zero outside [0, cnt)
-    for (int k = lane; k < band; k += 64) {
-      const int m = k - kPadL;
-      const uint2 w = (m >= 0 && m < cnt) ? split_pair((float)n.t.qc[coff + m], (float)n.t.qs[coff + m])
-                                          : make_uint2(0u, 0u);
-      bandh[k] = w.x;
-      bandl[k] = w.y;
-    }
-    const int64_t dring = 2 * (int64_t)N * (N - 1) + (int64_t)nring * (r - N) - a.pix_first;
-    if (cnt > 0 && lane < kNP) {  // W and N_occ of the window of centre `lane`
-      const int j0 = (ws + lane) & (nring - 1);
-      const int run = min(cnt, nring - j0);
-      const double2 l1 = a.wn[dring + j0], h1 = a.wn[dring + j0 + run];
-      wp += h1.x - l1.x;
-      np_occ += h1.y - l1.y;
-      if (run < cnt) {
-        const double2 l2 = a.wn[dring], h2 = a.wn[dring + cnt - run];
-        wp += h2.x - l2.x;
-        np_occ += h2.y - l2.y;
-      }
-    }
-    __syncthreads();
-    int us = s_ws[0], ue = s_we[0];
-    for (int w = 1; w < kStack; ++w) {
-      us = min(us, s_ws[w]);
-      ue = max(ue, s_we[w]);
-    }
-    if (ue <= us) {  // no wave reaches ring r
-      __syncthreads();
-      continue;
-    }
-    // every window holds at most 32 + cnt_max - 1 pixels and the stack's windows
-    // are centred within half a pixel of each other, so the union fits
-    const int Lu = min(ue - us, slab_max);
-    // realisations of the union slab: wave w generates realisations w, w + 4, ...
-    for (int s0 = 0; s0 < Lu; s0 += 64) {
-      const int sl = s0 + lane;
-      if (sl < Lu) {
-        const int j = (us + sl) & (nring - 1);
-        const int ci = n.cidx[dring + j];
-        const float4 gr = ci >= 0 ? a.map[dring + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // every window holds at most 32 + cnt_max - 1 pixels and the stack's
+    // windows are centred within half a pixel of each other, so the union fits
+    Lu = uni_i(ue > us ? min(ue - us, slab_max) : 0);
+    us = uni_i(us);
+  };
+  // the wave's band words (zero outside [0, cnt)), kBandSlots per lane
+  constexpr int kBandSlots = (kPadL + kCntMax + kPadR + 63) / 64;
+  auto load_band = [&](int cnt, int coff, uint2* bw) {
 #pragma unroll
-        for (int t = 0; t < kNR / kStack; ++t) {
-          const int rr = wave + kStack * t;
-          const int rreal = rg * kNR + rr;
-          const float uu = (ci >= 0 && rreal < n.n_real) ? n.u[(int64_t)rreal * n.n_src + ci] : 0.f;
-          const float sn = __builtin_amdgcn_sinf(uu), cs = __builtin_amdgcn_cosf(uu);  // of 2 pi u
-          const uint2 e = split_pair(gr.x * cs - gr.y * sn, gr.x * sn + gr.y * cs);
-          xh[2 * rr * RS + sl] = e.x;
-          xl[2 * rr * RS + sl] = e.y;
-          xh[(2 * rr + 1) * RS + sl] = bmode(e.x);
-          xl[(2 * rr + 1) * RS + sl] = bmode(e.y);
-        }
+    for (int j = 0; j < kBandSlots; ++j) {
+      const int m = lane + 64 * j - kPadL;
+      bw[j] = (lane + 64 * j < band && m >= 0 && m < cnt) ? n.qsplit[coff + m] : make_uint2(0u, 0u);
+    }
+  };
+  auto ring_base = [&](int r) { return 2 * (int64_t)N * (N - 1) + (int64_t)nring * (r - N) - a.pix_first; };
+  // slab inputs of slot us + sl of ring r: source index and shear sums, then
+  // (once the index is known) the angles
+  auto load_src = [&](int r, int us, int sl, SlabIn& in) {
+    const int64_t j = ring_base(r) + ((us + sl) & (nring - 1));
+    in.ci = n.cidx[j];
+    in.g = *reinterpret_cast<const float2*>(a.map + j);
+  };
+  auto load_ang = [&](SlabIn& in) {
+#pragma unroll
+    for (int t = 0; t < kWaveReal; ++t) {
+      const int rreal = rg * kNR + wave + kStack * t;
+      in.u[t] = (in.ci >= 0 && rreal < n.n_real) ? n.u[(int64_t)rreal * n.n_src + in.ci] : 0.f;
+    }
+  };
+  // realisations of slab slot sl: wave w generates realisations w, w + 8, ...
+  auto gen = [&](int sl, const SlabIn& in) {
+    const float gx = in.ci >= 0 ? in.g.x : 0.f, gy = in.ci >= 0 ? in.g.y : 0.f;
+#pragma unroll
+    for (int t = 0; t < kWaveReal; ++t) {
+      const int rr = wave + kStack * t;
+      const float sn = __builtin_amdgcn_sinf(in.u[t]), cs = __builtin_amdgcn_cosf(in.u[t]);  // of 2 pi u
+      const uint2 e = split_pair(gx * cs - gy * sn, gx * sn + gy * cs);
+      xh[2 * rr * RS + sl] = e.x;
+      xl[2 * rr * RS + sl] = e.y;
+      xh[(2 * rr + 1) * RS + sl] = bmode(e.x);
+      xl[(2 * rr + 1) * RS + sl] = bmode(e.y);
+    }
+  };
+
+  f32x16 acc0 = {0}, acc1 = {0};
+  const int col = lane & 31;   // MFMA row (A) / column (B)
+  const int half = lane >> 5;  // k-slice of the lane
+
+  // ring lo: windows, band words, first slab chunk
+  int cnt, coff, ws, us, Lu;
+  own(lo, cnt, coff, ws);
+  post(lo, cnt, ws);
+  uint2 bw[kBandSlots];
+  load_band(cnt, coff, bw);
+  __syncthreads();
+  uni(lo, us, Lu);
+  SlabIn in;
+  in.ci = -1;
+  if (lane < Lu) load_src(lo, us, lane, in);
+  load_ang(in);
+
+  for (int r = lo; r <= hi; ++r) {
+    // ring r: band and slab into LDS (the previous ring's readers are past
+    // the last barrier)
+#pragma unroll
+    for (int j = 0; j < kBandSlots; ++j) {
+      const int k = lane + 64 * j;
+      if (k < band) {
+        bandh[k] = bw[j].x;
+        bandl[k] = bw[j].y;
       }
     }
-    __syncthreads();
+    if (lane < Lu) gen(lane, in);
+    for (int s0 = 64; s0 < Lu; s0 += 64) {  // windows over 64 slots: the rest loaded here
+      SlabIn x;
+      x.ci = -1;
+      if (s0 + lane < Lu) load_src(r, us, s0 + lane, x);
+      load_ang(x);
+      if (s0 + lane < Lu) gen(s0 + lane, x);
+    }
+    // ring r + 1: this wave's window, published for the union
+    int cnt1 = 0, coff1 = 0, ws1 = 0;
+    if (r < hi) {
+      own(r + 1, cnt1, coff1, ws1);
+      post(r + 1, cnt1, ws1);
+    }
+    lds_barrier();
+    // ring r + 1: band words and slab sources requested now, used after the
+    // MFMA steps of ring r
+    int us1 = 0, Lu1 = 0;
+    if (r < hi) {
+      uni(r + 1, us1, Lu1);
+      load_band(cnt1, coff1, bw);
+      in.ci = -1;
+      if (lane < Lu1) load_src(r + 1, us1, lane, in);
+    }
     if (cnt > 0) {
-      const int base = ws - us;       // slab slot of this wave's first window pixel
-      const int L = kNP + cnt - 1;    // centre t uses window pixels [t, t + cnt)
+      const int base = ws - us;     // slab slot of this wave's first window pixel
+      const int L = kNP + cnt - 1;  // centre t uses window pixels [t, t + cnt)
       // lane (col, half) holds window pixels js = s0 + 4 half + q, q < 4.
       // A row col: coefficient js - col (zero outside [0, cnt)). B column
       // col: slab row col (realisation col / 2, E form for even col, B
@@ -356,7 +471,13 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, B1h, acc1, 0, 0, 0);
       }
     }
-    __syncthreads();  // xs, the bands and the windows are rewritten for the next ring
+    if (r < hi) load_ang(in);  // ring r + 1's angles (its source indices have arrived)
+    lds_barrier();             // the slab and bands are rewritten for the next ring
+    cnt = cnt1;
+    coff = coff1;
+    ws = ws1;
+    us = us1;
+    Lu = Lu1;
   }
 
   // epilogue: normalisation per centre, staged for coalesced writes
@@ -365,8 +486,11 @@ __global__ __launch_bounds__(64 * kStack) void k_noise_stack(NoiseArgs n, ScaleA
     if (a.norm == SMART_NORM_AVERAGED) {
       f = (float)s.inv_theta2;
     } else if (a.norm != SMART_NORM_RAW) {
-      const double area = a.norm == SMART_NORM_SUMMED_CAP ? s.area_cap : np_occ * s.omega_pix;
-      f = wp > 0.0 ? (float)(area * s.inv_theta2 / wp) : 0.f;
+      // W and N_occ of the centre's disc (computed with the schedule); only
+      // the segment's run is written
+      const double2 wn = (active && lane >= sg.y && lane < sg.z) ? n.wn_out[o_w + (lane - sg.y)] : make_double2(0.0, 0.0);
+      const double area = a.norm == SMART_NORM_SUMMED_CAP ? s.area_cap : wn.y * s.omega_pix;
+      f = wn.x > 0.0 ? (float)(area * s.inv_theta2 / wn.x) : 0.f;
     }
     fnorm[wave][lane] = f;
   }
@@ -695,6 +819,16 @@ static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, h
   }
   sc.noise_ncol = ncol;
   sc.noise_n_groups = n_groups;
+  if (h[0] > 0) {  // the stacks' A-operand words and the W, N_occ of their outputs
+    NCHK(dev_alloc(&sc.noise_qsplit, sizeof(uint2) * std::max(sc.n_coef, 1)));
+    NCHK(dev_alloc(&sc.noise_wn, sizeof(double2) * p->n_out));
+    if (sc.n_coef > 0)
+      hipLaunchKernelGGL(k_split_coef, dim3(grid_of(sc.n_coef)), dim3(kBlock), 0, st, sc.qc, sc.qs, sc.n_coef,
+                         sc.noise_qsplit);
+    hipLaunchKernelGGL(k_noise_wn, dim3(grid_of(n_seg * kNP)), dim3(kBlock), 0, st, a, sc.tab(), ncol, sc.noise_seg,
+                       sc.noise_wn);
+    NCHK(hipGetLastError());
+  }
   if (h[1] > 0) {
     NCHK(dev_alloc(&sc.noise_rest, sizeof(int64_t) * 2 * (size_t)h[1]));
     NCHK(hipMemcpyAsync(sc.noise_rest, pos, sizeof(int64_t) * h[1], hipMemcpyDeviceToDevice, st));
@@ -763,6 +897,8 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
       na.r_stride = r_stride;
       na.r_base = r_base;
       na.mom = mom;
+      na.qsplit = sc.noise_qsplit;
+      na.wn_out = sc.noise_wn;
       const dim3 grid((unsigned)((int64_t)sc.noise_n_stacks * na.n_grp)), block(64 * kStack);
       hipLaunchKernelGGL(k_noise_stack, grid, block, stack_lds_bytes(sc.noise_cnt_max), st, na, s,
                          sc.noise_cnt_max);

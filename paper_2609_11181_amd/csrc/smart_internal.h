@@ -278,6 +278,9 @@ struct PixelSched {
   int4* noise_seg = nullptr;       // per belt segment: (list position of its run, first, end), or -1
   int* noise_stacks = nullptr;     // stacks of segments, column-major
   int64_t* noise_rest = nullptr;   // [2][noise_n_rest]: list positions and pixels of the other outputs
+  uint2* noise_qsplit = nullptr;   // per belt coefficient: (q cos, q sin) split into BF16 hi and lo words
+  double2* noise_wn = nullptr;     // per list entry of a stack segment: (W, N_occ) of its disc
+  int n_coef = 0;                  // belt coefficients (without the padding)
   BeltTab tab() const { return BeltTab{head, info, qc, qs, q2}; }
   ~PixelSched();
 };
