@@ -232,10 +232,15 @@ __host__ __device__ constexpr int stack_slab(int cnt_max) { return kNP + cnt_max
 // that the 32 rows an MFMA operand load touches start on different banks
 __host__ __device__ constexpr int stack_row(int cnt_max) { return (stack_slab(cnt_max) + 8) | 1; }
 __host__ __device__ constexpr int stack_band(int cnt_max) { return kPadL + cnt_max + kPadR; }
+// epilogue staging row of one output column: kNP centres and one padding
+// word, so that the 32 columns a wave writes for one centre fall on
+// different LDS banks
+constexpr int kStageRow = kNP + 1;
 __host__ __device__ constexpr size_t stack_slab_bytes(int cnt_max) {
-  return (size_t)2 * 2 * kNR * stack_row(cnt_max) * sizeof(uint32_t) > (size_t)kStack * 2 * kNR * kNP * sizeof(float)
+  return (size_t)2 * 2 * kNR * stack_row(cnt_max) * sizeof(uint32_t) >
+                 (size_t)kStack * 2 * kNR * kStageRow * sizeof(float)
              ? (size_t)2 * 2 * kNR * stack_row(cnt_max) * sizeof(uint32_t)
-             : (size_t)kStack * 2 * kNR * kNP * sizeof(float);
+             : (size_t)kStack * 2 * kNR * kStageRow * sizeof(float);
 }
 __host__ __device__ constexpr size_t stack_lds_bytes(int cnt_max) {
   return stack_slab_bytes(cnt_max) + (size_t)kStack * 2 * stack_band(cnt_max) * sizeof(uint32_t);
@@ -495,12 +500,12 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
     fnorm[wave][lane] = f;
   }
   __syncthreads();
-  float* cst = reinterpret_cast<float*>(smem) + wave * (2 * kNR * kNP);  // [2 kNR][kNP] of this wave
+  float* cst = reinterpret_cast<float*>(smem) + wave * (2 * kNR * kStageRow);  // [2 kNR][kStageRow] of this wave
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int row = 8 * (i / 4) + 4 * half + (i % 4);  // centre
-    cst[col * kNP + row] = acc0[i] * fnorm[wave][row];        // column 2 r' + e, r' < 16
-    cst[(32 + col) * kNP + row] = acc1[i] * fnorm[wave][row]; // r' >= 16
+    cst[col * kStageRow + row] = acc0[i] * fnorm[wave][row];         // column 2 r' + e, r' < 16
+    cst[(32 + col) * kStageRow + row] = acc1[i] * fnorm[wave][row];  // r' >= 16
   }
   __syncthreads();
   if (active && n.mom) {
@@ -511,7 +516,7 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
     if (lane < kNP && lane >= sg.y && lane < sg.z) {
       double m[4] = {0.0, 0.0, 0.0, 0.0};
       for (int rr = 0; rr < nr; ++rr) {
-        const double e = (double)cst[(2 * rr) * kNP + lane], b = (double)cst[(2 * rr + 1) * kNP + lane];
+        const double e = (double)cst[(2 * rr) * kStageRow + lane], b = (double)cst[(2 * rr + 1) * kStageRow + lane];
         m[0] += e;
         m[1] += e * e;
         m[2] += b;
@@ -526,7 +531,8 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
       const int ci = v / kNP, pp = v % kNP;
       const int rr = rg * kNR + (ci >> 1), e = ci & 1;
       if (rr < n.n_real && pp >= sg.y && pp < sg.z)
-        n.out[(((int64_t)a.scale * n.r_stride + n.r_base + rr) * 2 + e) * a.n_out + o_w + (pp - sg.y)] = cst[v];
+        n.out[(((int64_t)a.scale * n.r_stride + n.r_base + rr) * 2 + e) * a.n_out + o_w + (pp - sg.y)] =
+            cst[ci * kStageRow + pp];
     }
   }
 }
