@@ -236,16 +236,15 @@ __device__ __forceinline__ int ring_slices(const Ring& Q, int64_t jlo, int cnt, 
 // FP64 chord test (the brute-force membership, Sect. 3.1), then the spin-2
 // rotation from unnormalised tangent-plane components, the filter from the
 // chord and the sums.
+// P and G are row g's unit vector and (g1, g2, w, V).
 template <bool TABLE, bool BIG>
-__device__ __forceinline__ void galaxy_member(const GalaxyArgs& a, const ScaleArgs& s, int64_t g, double px,
-                                              double py, double pz, bool posb, const double* cp, Tab tab,
-                                              Acc64& tot, Acc32& acc, int& nacc) {
-  const double4 P = a.P[g];
+__device__ __forceinline__ void galaxy_pair(const GalaxyArgs& a, const ScaleArgs& s, int64_t g, const double4& P,
+                                            const float4& G, double px, double py, double pz, bool posb,
+                                            const double* cp, Tab tab, Acc64& tot, Acc32& acc, int& nacc) {
   const double dx = px - P.x, dy = py - P.y, dz = pz - P.z;
   const double c2 = fma(dx, dx, fma(dy, dy, dz * dz));
   const bool inside = c2 < s.C_ap;
   if (!(inside || posb)) return;
-  const float4 G = a.G[g];
   // tangent-plane components at the galaxy, unnormalised (both scaled by
   // cos dec, which cancels in the rotation):
   //   X = x dy - y dx,  Y = (x^2 + y^2) dz - z (x dx + y dy)
@@ -283,6 +282,15 @@ __device__ __forceinline__ void galaxy_member(const GalaxyArgs& a, const ScaleAr
     acc = Acc32();
     nacc = 0;
   }
+}
+
+template <bool TABLE, bool BIG>
+__device__ __forceinline__ void galaxy_member(const GalaxyArgs& a, const ScaleArgs& s, int64_t g, double px,
+                                              double py, double pz, bool posb, const double* cp, Tab tab,
+                                              Acc64& tot, Acc32& acc, int& nacc) {
+  const double4 P = a.P[g];
+  const float4 G = a.G[g];
+  galaxy_pair<TABLE, BIG>(a, s, g, P, G, px, py, pz, posb, cp, tab, tot, acc, nacc);
 }
 
 // lane l's value, read into scalar registers (l wave-uniform)
@@ -479,13 +487,34 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32(GalaxyArgs a, ScaleArgs s
         // (n_rows after the last); positions only grow, so it moves forward
         int j = 0;
         int64_t base = row[0], nxt = n_sl > 1 ? pre[1] : n_rows;
-        for (int64_t v = lane; v < n_rows; v += 64) {
+        auto row_of = [&](int64_t v) {
           while (v >= nxt) {
             ++j;
             base = row[j] - nxt;
             nxt = j + 1 < n_sl ? pre[j + 1] : n_rows;
           }
-          galaxy_member<TABLE, BIG>(a, s, base + v, c.px, c.py, c.pz, posb, cp, tab, tot, acc, nacc);
+          return base + v;
+        };
+        // the next step's records are requested before this step's member
+        // is evaluated, so the loads of one step overlap the work of another
+        int64_t v = lane, gn = 0;
+        double4 Pn = make_double4(0.0, 0.0, 0.0, 0.0);
+        float4 Gn = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (v < n_rows) {
+          gn = row_of(v);
+          Pn = a.P[gn];
+          Gn = a.G[gn];
+        }
+        for (; v < n_rows; v += 64) {
+          const int64_t gc = gn;
+          const double4 Pc = Pn;
+          const float4 Gc = Gn;
+          if (v + 64 < n_rows) {
+            gn = row_of(v + 64);
+            Pn = a.P[gn];
+            Gn = a.G[gn];
+          }
+          galaxy_pair<TABLE, BIG>(a, s, gc, Pc, Gc, c.px, c.py, c.pz, posb, cp, tab, tot, acc, nacc);
         }
       }
       // every lane is done with the list before the next pass rewrites it
