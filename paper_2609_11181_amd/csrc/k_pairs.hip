@@ -284,15 +284,6 @@ __device__ __forceinline__ void galaxy_pair(const GalaxyArgs& a, const ScaleArgs
   }
 }
 
-template <bool TABLE, bool BIG>
-__device__ __forceinline__ void galaxy_member(const GalaxyArgs& a, const ScaleArgs& s, int64_t g, double px,
-                                              double py, double pz, bool posb, const double* cp, Tab tab,
-                                              Acc64& tot, Acc32& acc, int& nacc) {
-  const double4 P = a.P[g];
-  const float4 G = a.G[g];
-  galaxy_pair<TABLE, BIG>(a, s, g, P, G, px, py, pz, posb, cp, tab, tot, acc, nacc);
-}
-
 // lane l's value, read into scalar registers (l wave-uniform)
 __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -395,9 +386,25 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f32_lane(GalaxyArgs a, ScaleA
     int64_t ga[2], gb[2];
     gal_ring_rows(a, c, r, Cw, ga, gb);
 #pragma unroll 1
-    for (int t = 0; t < 2; ++t)
-      for (int64_t g = ga[t]; g < gb[t]; ++g)
-        galaxy_member<TABLE, BIG>(a, s, g, c.px, c.py, c.pz, posb, cp, tab, tot, acc, nacc);
+    for (int t = 0; t < 2; ++t) {
+      // the next row's records are requested before this row is evaluated
+      int64_t g = ga[t];
+      double4 Pn = make_double4(0.0, 0.0, 0.0, 0.0);
+      float4 Gn = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (g < gb[t]) {
+        Pn = a.P[g];
+        Gn = a.G[g];
+      }
+      for (; g < gb[t]; ++g) {
+        const double4 Pc = Pn;
+        const float4 Gc = Gn;
+        if (g + 1 < gb[t]) {
+          Pn = a.P[g + 1];
+          Gn = a.G[g + 1];
+        }
+        galaxy_pair<TABLE, BIG>(a, s, g, Pc, Gc, c.px, c.py, c.pz, posb, cp, tab, tot, acc, nacc);
+      }
+    }
   }
   tot.add(acc);
   write_map(a.out, a.out64, a.n_out, a.scale, o, a.norm, tot, s);
