@@ -122,16 +122,16 @@ __device__ __attribute__((noinline)) void general_sin_hav(double av, double* sa,
 // ring_coef, arranged for fewer operations: y^2 - x^2 = 2 y^2 - sin^2 theta,
 // and the factor -2 of q sin 2psi is applied once to its sums (E gets
 // sum qc g1 - 2 sum qh g2, B gets sum qc g2 + 2 sum qh g1 with
-// qh = q x y / sin^2 theta; doubling is exact).
+// qh = q x y / sin^2 theta; doubling is exact). The member is not the
+// centre itself (sin theta > 0: distinct pixel centres).
 template <bool TABLE, bool BIG>
 __device__ __forceinline__ void general_member(double xt, double yt, float4 g, const double* tp,
                                                const FilterPiece* tab, double t_sin, Acc64& tot, double& e2,
                                                double& b2) {
   const double yy = yt * yt;
   const double S2 = fma(xt, xt, yy);
-  const double S2c = fmax(S2, (double)kCoincidentS2);
-  const double r0 = (double)__builtin_amdgcn_rsqf((float)S2c);
-  const double r = r0 * fma(-0.5 * S2c, r0 * r0, 1.5);
+  const double r0 = (double)__builtin_amdgcn_rsqf((float)S2);
+  const double r = r0 * fma(-0.5 * S2, r0 * r0, 1.5);
   // table filters: q from the table in sin(theta); the polynomial filter
   // takes theta / theta_ap from the asin series
   const double q = filter_piece<TABLE>(TABLE ? (S2 * r) * t_sin : theta_ratio<BIG>(S2 * r, S2, tp), tab);
@@ -143,6 +143,14 @@ __device__ __forceinline__ void general_member(double xt, double yt, float4 g, c
   e2 = fma(qh, a2, e2);
   tot.sb = fma(qc, a2, tot.sb);
   b2 = fma(qh, a1, b2);
+  tot.sv = fma(q * q, (double)g.z, tot.sv);
+}
+
+// The centre's own pixel as a member: its polar angle is undefined and its
+// shear term vanishes; it adds q(0)^2 E2 to V.
+template <bool TABLE, bool BIG>
+__device__ __forceinline__ void general_self(float4 g, const double* tp, const FilterPiece* tab, Acc64& tot) {
+  const double q = filter_piece<TABLE>(TABLE ? 0.0 : theta_ratio<BIG>(0.0, 0.0, tp), tab);
   tot.sv = fma(q * q, (double)g.z, tot.sv);
 }
 
@@ -255,6 +263,11 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
       run_wn(a.wn, dring + jw, run, tot);
       const float4* p = a.map + dring + jw;
       int k = 0;
+      if (kdone == kc) {  // the run starts at the centre itself
+        general_self<TABLE, BIG>(p[0], tp, tab, tot);
+        w.advance();
+        k = 1;
+      }
       constexpr int U = OOL ? 2 : 4;  // members in flight
       for (; k + U <= run; k += U) {
         float4 g[U];
