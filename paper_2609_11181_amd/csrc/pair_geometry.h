@@ -281,22 +281,27 @@ struct XStep {
 // relative for the few hundred members of a window).
 struct XYWalk3 {
   double c2, cy, x0, x1, y0, y1;
-  // members k, k + 1 from member k's x and sin^2(a/2)
-  __device__ __forceinline__ void start(const XStep& st, double x, double h, double Y0, double Kz) {
+  // members k, k + 1 from member k's x and sin^2(a/2); the walk carries x
+  // and y multiplied by t (the recurrences are linear, so the constant term
+  // cy is multiplied too)
+  __device__ __forceinline__ void start(const XStep& st, double x, double h, double Y0, double Kz, double t) {
     c2 = 2.0 * st.cd;
-    cy = (2.0 * st.hd) * fma(2.0, Y0, Kz);
+    cy = ((2.0 * st.hd) * fma(2.0, Y0, Kz)) * t;
     double h1 = h;
-    x0 = x1 = x;
-    st.advance(&x1, &h1);
-    y0 = fma(Kz, h, Y0);
-    y1 = fma(Kz, h1, Y0);
+    double xa = x, xb = x;
+    st.advance(&xb, &h1);
+    x0 = xa * t;
+    x1 = xb * t;
+    y0 = fma(Kz, h, Y0) * t;
+    y1 = fma(Kz, h1, Y0) * t;
   }
-  // restart at an azimuth offset of exactly zero (then y = Y0)
-  __device__ __forceinline__ void restart(const XStep& st, double Y0, double Kz) {
+  // restart at an azimuth offset of exactly zero (then y = Y0), with the
+  // factor t of start (cy is start's and stays)
+  __device__ __forceinline__ void restart(const XStep& st, double Y0, double Kz, double t) {
     x0 = 0.0;
-    y0 = Y0;
-    x1 = -st.xs1;
-    y1 = fma(Kz, st.hd, Y0);
+    y0 = Y0 * t;
+    x1 = -st.xs1 * t;
+    y1 = fma(Kz, st.hd, Y0) * t;
   }
   __device__ __forceinline__ void advance() {
     const double x2 = fma(c2, x1, -x0);

@@ -123,7 +123,10 @@ __device__ __attribute__((noinline)) void general_sin_hav(double av, double* sa,
 // and the factor -2 of q sin 2psi is applied once to its sums (E gets
 // sum qc g1 - 2 sum qh g2, B gets sum qc g2 + 2 sum qh g1 with
 // qh = q x y / sin^2 theta; doubling is exact). The member is not the
-// centre itself (sin theta > 0: distinct pixel centres).
+// centre itself (sin theta > 0: distinct pixel centres). Table filters: the
+// walk carries x and y scaled by the table's t_sin, so that S2 r is the
+// table coordinate sin(theta) t_sin directly (the scale cancels in
+// (2 y^2 - S2) / S2 and x y / S2).
 template <bool TABLE, bool BIG>
 __device__ __forceinline__ void general_member(double xt, double yt, float4 g, const double* tp,
                                                const FilterPiece* tab, double t_sin, Acc64& tot, double& e2,
@@ -134,7 +137,7 @@ __device__ __forceinline__ void general_member(double xt, double yt, float4 g, c
   const double r = r0 * fma(-0.5 * S2, r0 * r0, 1.5);
   // table filters: q from the table in sin(theta); the polynomial filter
   // takes theta / theta_ap from the asin series
-  const double q = filter_piece<TABLE>(TABLE ? (S2 * r) * t_sin : theta_ratio<BIG>(S2 * r, S2, tp), tab);
+  const double q = filter_piece<TABLE>(TABLE ? S2 * r : theta_ratio<BIG>(S2 * r, S2, tp), tab);
   const double qn = q * (r * r);
   const double qc = qn * fma(2.0, yy, -S2);
   const double qh = qn * (xt * yt);
@@ -242,8 +245,10 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     const double av = (u0 - (double)(int)jlo) * ((2.0 * kPi) * rnq);  // jlo in [-nq, 2 nq]
     if (OOL) general_sin_hav(av, &sa, &h);
     else sin_hav(av, &sa, &h);
+    // table filters: the walk in units of the table coordinate
+    const double wt = TABLE ? s.t_sin : 1.0;
     XYWalk3 w;
-    w.start(step, sp * sa, h, Y0, Kz);
+    w.start(step, sp * sa, h, Y0, Kz, wt);
     // the member at the centre itself (same colatitude, dphi = 0), if any,
     // from the exact integer offset pi m / (np nq): the walk restarts there
     // from exact zeros, so its shear term vanishes exactly
@@ -259,7 +264,7 @@ __device__ __forceinline__ void general_centre(const PixelArgs& a, const ScaleAr
     while (kdone < cnt) {
       int run = min(cnt - kdone, nq - jw);
       if (kc > kdone && kc < kdone + run) run = kc - kdone;
-      if (kdone == kc) w.restart(step, Y0, Kz);
+      if (kdone == kc) w.restart(step, Y0, Kz, wt);
       run_wn(a.wn, dring + jw, run, tot);
       const float4* p = a.map + dring + jw;
       int k = 0;
