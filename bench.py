@@ -40,7 +40,7 @@ ALU_PEAK = 256 * 64 * 2.4e9
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0)
 # counter runs of the default workload, double maps (profiles/pixel_kernels_nside4096_15000deg2_3scales.md,
 # which names the source version it was measured on); valid for that kernel version and workload only
-TRAFFIC_BYTES = {"k_pixel_f32 (20 arcmin)": 1.680e10}
+TRAFFIC_BYTES = {"k_pixel_f32 (20 arcmin)": 1.689e10}
 TRAFFIC_SOURCE = "profiles/pixel_kernels_nside4096_15000deg2_3scales.md"
 
 
