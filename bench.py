@@ -352,6 +352,16 @@ def batched_leg(ctx, args):
     torch.cuda.synchronize()
     t_g = ev0.elapsed_time(ev1) / 1e3
     del ug, outg
+    # galaxy-level realisations on the matrix cores: per-galaxy angles drawn
+    # on the device, the rotated pixel sums of each chunk of 32 realisations
+    # contracted by the split-BF16x3 kernels (all R realisations)
+    plan.noise_galaxy_seeded(11, 0, R, L.NORM_SUMMED_PIXCOUNT, out=out)  # warm-up
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    plan.noise_galaxy_seeded(11, 0, R, L.NORM_SUMMED_PIXCOUNT, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_gs = ev0.elapsed_time(ev1) / 1e3
     # sphS_pixB: the same catalogue's occupied pixels at their barycentres,
     # galaxy-variant FP32 plan with the pixel centres as outputs
     ev0.record(stream)
@@ -419,6 +429,11 @@ def batched_leg(ctx, args):
         "galaxy_level_fp32_maps_per_s": 3 * Rp / t_g,
         "galaxy_level_note": "smart_noise_galaxy_batch: per-galaxy rotation, re-binned pixel sums, plain FP32 "
                              "pair kernels; same realisation count as the plain pixel-level timing",
+        "galaxy_level_bf16x3_s": t_gs,
+        "galaxy_level_bf16x3_maps_per_s": 3 * R / t_gs,
+        "galaxy_level_bf16x3_note": "smart_noise_galaxy_seeded: Philox4x32-10 angles per galaxy drawn on the "
+                                    "device, rotated pixel sums per chunk of 32 realisations, split-BF16x3 "
+                                    "stack; all realisations of the leg",
         "speedup_vs_plain": maps_b / maps_p,
         "realisation_pair_evals_per_s": pairs1 * R / t_b,
         "mfma": {"bound": "mfma", "achieved": flops / t_b / 1e12, "peak": 2500.0, "unit": "TFLOP/s",

@@ -433,6 +433,30 @@ int smart_noise_seeded(smart_plan plan, uint64_t seed, int64_t r_first, int n_re
  * smart_plan_free. */
 int smart_noise_galaxy_batch(smart_plan plan, const float* d_u, int n_real, int norm, float* d_out, void* stream);
 
+/* Galaxy-level realisations with device-drawn angles (Sect. 1 and Sect. 5.3),
+ * batched on the matrix cores: realisation r rotates galaxy i (its index in
+ * the catalogue passed to smart_bin_galaxies) by exp(2 i pi u[r][i]) with
+ * u[r][i] from word r mod 4 of the Philox4x32-10 generator (Salmon et al.
+ * 2011) at counter (i mod 2^32, i / 2^32, r / 4, 0) and key (seed mod 2^32,
+ * seed / 2^32), u = ((x >> 9) + 0.5) 2^-23 in (0, 1) (one generator call
+ * serves four consecutive realisations of a galaxy).
+ * smart_noise_galaxy_angles writes u[r][i] for realisations r_first ..
+ * r_first + n_real - 1 to d_u (float [n_real][n_gal]); it is the angle
+ * array smart_noise_galaxy_batch takes for the same realisations.
+ * smart_noise_galaxy_seeded computes the maps of a pixel-variant FP32 plan
+ * on a binned catalogue with pixel sums: for each chunk of 32 realisations
+ * it forms the rotated pixel sums of every occupied pixel (eight lanes per
+ * pixel over its galaxies, FP64 sums; times Omega_pix / W for the averaged
+ * approach) and contracts them with the plan's aperture operator in the
+ * split-BF16x3 MFMA kernels of smart_noise_batch (about 2^-16 relative per
+ * term). d_out and moments_only as for smart_noise_seeded. Allocates
+ * n_src x 32 x 8 bytes of stream-ordered scratch. SMART_EINVAL for other
+ * plans or data, n_real < 1, or realisation indices outside [0, 2^33). */
+int smart_noise_galaxy_angles(smart_ctx ctx, uint64_t seed, int64_t r_first, int n_real, int64_t n_gal, float* d_u,
+                              void* stream);
+int smart_noise_galaxy_seeded(smart_plan plan, uint64_t seed, int64_t r_first, int n_real, int norm, int moments_only,
+                              void* d_out, void* stream);
+
 /* Several plans in one persistent launch (pixel variant, FP32): a single
  * kernel drains a work list holding the tiles of every plan and scale,
  * longest first. outs[k] is the smart_run output buffer of plans[k]. */

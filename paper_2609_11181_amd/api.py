@@ -139,6 +139,14 @@ class Context:
         L.check(self.lib.smart_noise_angles(self.h, seed, r_first, n_real, n_src, p, _stream(self.device)))
         return out
 
+    def noise_galaxy_angles(self, seed: int, r_first: int, n_real: int, n_gal: int, out=None):
+        """Galaxy-level angles (see smart_noise_galaxy_angles): [n_real][n_gal] float32."""
+        if out is None:
+            out = torch.empty(n_real, n_gal, dtype=torch.float32, device=self.device)
+        p = _buf(out, self.device, torch.float32, n_real * n_gal, "out")
+        L.check(self.lib.smart_noise_galaxy_angles(self.h, seed, r_first, n_real, n_gal, p, _stream(self.device)))
+        return out
+
     def detect_peaks(self, nside: int, pix, values, threshold: float = float("-inf"), noise_sd=None):
         """Detections of a map (see smart_detect_peaks): increasing int64 pixels."""
         d = self.device
@@ -321,6 +329,22 @@ class Plan:
         pu = _buf(u, dev, torch.float32, n_real * self.data.info()["n_gal"], "u")
         po = _buf(out, dev, torch.float32, self.n_scales * n_real * 2 * self.n_out, "out")
         L.check(self.ctx.lib.smart_noise_galaxy_batch(self.h, pu, n_real, norm, po, _stream(dev)))
+        return out
+
+    def noise_galaxy_seeded(self, seed: int, r_first: int, n_real: int, norm: int, moments=False, out=None):
+        """Galaxy-level realisations with device-drawn angles on the matrix cores
+        (see smart_noise_galaxy_seeded); outputs as for noise_seeded."""
+        dev = self.ctx.device
+        if moments:
+            if out is None:
+                out = torch.zeros(self.n_scales, 4, self.n_out, dtype=torch.float64, device=dev)
+            po = _buf(out, dev, torch.float64, self.n_scales * 4 * self.n_out, "out")
+        else:
+            if out is None:
+                out = torch.empty(self.n_scales, n_real, 2, self.n_out, dtype=torch.float32, device=dev)
+            po = _buf(out, dev, torch.float32, self.n_scales * n_real * 2 * self.n_out, "out")
+        L.check(self.ctx.lib.smart_noise_galaxy_seeded(self.h, seed, r_first, n_real, norm, 1 if moments else 0, po,
+                                                       _stream(dev)))
         return out
 
     def free(self):

@@ -676,6 +676,52 @@ int smart_noise_seeded(smart_plan p, uint64_t seed, int64_t r_first, int n_real,
   return rc;
 }
 
+int smart_noise_galaxy_angles(smart_ctx ctx, uint64_t seed, int64_t r_first, int n_real, int64_t n_gal, float* d_u,
+                              void* stream) {
+  if (!ctx || (!d_u && n_real > 0 && n_gal > 0)) return fail(SMART_EINVAL, "NULL argument");
+  if (n_real < 0 || n_gal < 0 || r_first < 0) return fail(SMART_EINVAL, "negative count or realisation index");
+  if (r_first + n_real > (int64_t(1) << 33)) return fail(SMART_EINVAL, "realisation index beyond 2^33");
+  int rc;
+  if ((rc = set_device(ctx))) return rc;
+  CHECK_HIP(launch_gal_angles(seed, r_first, n_real, n_gal, d_u, (hipStream_t)stream));
+  return SMART_OK;
+}
+
+int smart_noise_galaxy_seeded(smart_plan p, uint64_t seed, int64_t r_first, int n_real, int norm, int moments_only,
+                              void* d_out, void* stream) {
+  if (!p || !d_out) return fail(SMART_EINVAL, "NULL argument");
+  if (p->variant != SMART_VAR_PIXEL || p->precision != SMART_PREC_FP32_GEO64)
+    return fail(SMART_EINVAL, "galaxy-level MFMA realisations need a pixel-variant FP32 plan");
+  smart_data d = p->data;
+  if (d->kind != 0 || !d->G || !d->sums || !d->src_pix)
+    return fail(SMART_EINVAL, "galaxy-level realisations need a binned catalogue with pixel sums");
+  if (n_real < 1) return fail(SMART_EINVAL, "n_real must be >= 1");
+  if (r_first < 0 || r_first + n_real > (int64_t(1) << 33))
+    return fail(SMART_EINVAL, "realisation indices must lie in [0, 2^33)");
+  int rc;
+  if ((rc = check_norm(p, norm))) return rc;
+  if ((rc = set_device(p->ctx))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (p->n_out == 0) return SMART_OK;
+  // rotated pixel sums of one chunk of realisations at a time (n_src x 32 complex floats)
+  const int C = kNoiseChunk;
+  float2* X = nullptr;
+  if (scratch_alloc(&X, sizeof(float2) * (size_t)std::max<int64_t>(d->n_src, 1) * C, st) != hipSuccess)
+    return fail(SMART_ENOMEM, "allocation failed for the rotated pixel sums");
+  double* mom = moments_only ? (double*)d_out : nullptr;
+  float* maps = moments_only ? nullptr : (float*)d_out;
+  for (int c0 = 0; c0 < n_real && rc == SMART_OK; c0 += C) {
+    const int nc = std::min(C, n_real - c0);
+    if (launch_gal_rot_sums(d, norm == SMART_NORM_AVERAGED ? 1 : 0, seed, r_first + c0, nc, X, st) != hipSuccess) {
+      rc = fail(SMART_EDEVICE, "rotated pixel sums failed to launch");
+      break;
+    }
+    rc = noise_bf16x3(p, nullptr, nc, norm, maps, st, n_real, c0, mom, X);
+  }
+  scratch_free(X, st);
+  return rc;
+}
+
 int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int norm, float* d_out, void* stream) {
   if (!p || !d_u || !d_out) return fail(SMART_EINVAL, "NULL argument");
   if (p->precision != SMART_PREC_FP32_GEO64) return fail(SMART_EINVAL, "galaxy-level realisations need an FP32 plan");

@@ -192,6 +192,7 @@ struct NoiseArgs {
   int r_stride, r_base;
   const uint2* qsplit;    // belt coefficients (q cos, q sin) as split BF16 words
   const double2* wn_out;  // (W, N_occ) of each list entry that a stack segment covers
+  const float2* xsum;     // galaxy-level realisations: [n_real][n_src] rotated pixel sums (else null)
   double* mom;        // moments mode (out unused): [n_scales][4][n_out] += sum of E, E^2, B, B^2
 };
 
@@ -262,17 +263,26 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // Inputs of one 64-slot chunk of a ring's slab, one slot per lane: source
 // index, shear sums and the angles of the wave's realisations.
 constexpr int kWaveReal = kNR / kStack;  // realisations each wave generates
+template <bool XS>
 struct SlabIn {
   int ci;
   float2 g;
   float u[kWaveReal];
+};
+// galaxy-level realisations: the rotated sums themselves
+template <>
+struct SlabIn<true> {
+  int ci;
+  float2 x[kWaveReal];
 };
 
 // Ring loop, software-pipelined: while the MFMA steps of ring r run, the
 // coefficient band, source indices, shear sums and angles of ring r + 1 are
 // already requested, and the windows of ring r + 1 were published one
 // barrier earlier, so a ring costs two LDS barriers and no exposed global
-// load.
+// load. XS: galaxy-level realisations, whose slab values are the rotated
+// pixel sums of each realisation (read instead of generated).
+template <bool XS>
 __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))) void k_noise_stack(NoiseArgs n, ScaleArgs s,
                                                                                                   int cnt_max) {
   extern __shared__ uint2 smem[];
@@ -360,26 +370,33 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
   auto ring_base = [&](int r) { return 2 * (int64_t)N * (N - 1) + (int64_t)nring * (r - N) - a.pix_first; };
   // slab inputs of slot us + sl of ring r: source index and shear sums, then
   // (once the index is known) the angles
-  auto load_src = [&](int r, int us, int sl, SlabIn& in) {
+  auto load_src = [&](int r, int us, int sl, SlabIn<XS>& in) {
     const int64_t j = ring_base(r) + ((us + sl) & (nring - 1));
     in.ci = n.cidx[j];
-    in.g = *reinterpret_cast<const float2*>(a.map + j);
+    if constexpr (!XS) in.g = *reinterpret_cast<const float2*>(a.map + j);
   };
-  auto load_ang = [&](SlabIn& in) {
+  auto load_ang = [&](SlabIn<XS>& in) {
 #pragma unroll
     for (int t = 0; t < kWaveReal; ++t) {
       const int rreal = rg * kNR + wave + kStack * t;
-      in.u[t] = (in.ci >= 0 && rreal < n.n_real) ? n.u[(int64_t)rreal * n.n_src + in.ci] : 0.f;
+      const bool ok = in.ci >= 0 && rreal < n.n_real;
+      if constexpr (XS) in.x[t] = ok ? n.xsum[(int64_t)rreal * n.n_src + in.ci] : make_float2(0.f, 0.f);
+      else in.u[t] = ok ? n.u[(int64_t)rreal * n.n_src + in.ci] : 0.f;
     }
   };
   // realisations of slab slot sl: wave w generates realisations w, w + 8, ...
-  auto gen = [&](int sl, const SlabIn& in) {
-    const float gx = in.ci >= 0 ? in.g.x : 0.f, gy = in.ci >= 0 ? in.g.y : 0.f;
+  auto gen = [&](int sl, const SlabIn<XS>& in) {
 #pragma unroll
     for (int t = 0; t < kWaveReal; ++t) {
       const int rr = wave + kStack * t;
-      const float sn = __builtin_amdgcn_sinf(in.u[t]), cs = __builtin_amdgcn_cosf(in.u[t]);  // of 2 pi u
-      const uint2 e = split_pair(gx * cs - gy * sn, gx * sn + gy * cs);
+      uint2 e;
+      if constexpr (XS) {
+        e = split_pair(in.x[t].x, in.x[t].y);
+      } else {
+        const float gx = in.ci >= 0 ? in.g.x : 0.f, gy = in.ci >= 0 ? in.g.y : 0.f;
+        const float sn = __builtin_amdgcn_sinf(in.u[t]), cs = __builtin_amdgcn_cosf(in.u[t]);  // of 2 pi u
+        e = split_pair(gx * cs - gy * sn, gx * sn + gy * cs);
+      }
       xh[2 * rr * RS + sl] = e.x;
       xl[2 * rr * RS + sl] = e.y;
       xh[(2 * rr + 1) * RS + sl] = bmode(e.x);
@@ -399,7 +416,7 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
   load_band(cnt, coff, bw);
   __syncthreads();
   uni(lo, us, Lu);
-  SlabIn in;
+  SlabIn<XS> in;
   in.ci = -1;
   if (lane < Lu) load_src(lo, us, lane, in);
   load_ang(in);
@@ -417,7 +434,7 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
     }
     if (lane < Lu) gen(lane, in);
     for (int s0 = 64; s0 < Lu; s0 += 64) {  // windows over 64 slots: the rest loaded here
-      SlabIn x;
+      SlabIn<XS> x;
       x.ci = -1;
       if (s0 + lane < Lu) load_src(r, us, s0 + lane, x);
       load_ang(x);
@@ -558,9 +575,10 @@ struct RestArgs {
   float* out;          // [n_scales][r_stride][2][n_out]: realisation r at r_base + r
   int r_stride, r_base;
   double* mom;         // moments mode (out unused): [n_scales][4][n_out] += sum of E, E^2, B, B^2
+  const float2* xsum;  // galaxy-level realisations: [n_real][n_src] rotated pixel sums (else null)
 };
 
-template <bool TABLE, bool BIG>
+template <bool TABLE, bool BIG, bool XS>
 __global__ __launch_bounds__(kBlock) void k_noise_rest_walk(RestArgs n, ScaleArgs s) {
   __shared__ float4 tab_c[TABLE ? kFilterIntervals : 1];
   __shared__ double tab_c0[TABLE ? kFilterIntervals : 1];
@@ -628,17 +646,29 @@ __global__ __launch_bounds__(kBlock) void k_noise_rest_walk(RestArgs n, ScaleArg
         const int64_t d = dring + jw + k;
         const int ci = n.cidx[d];
         if (ci < 0) continue;  // empty pixel: no shear
-        const float4 g = a.map[d];
         const float qc = (float)c.qc, qs = (float)c.qs;
-        const float* up = n.u + (int64_t)r0 * n.n_src + ci;
+        if constexpr (XS) {  // the realisation's rotated pixel sums
+          const float2* xp = n.xsum + (int64_t)r0 * n.n_src + ci;
 #pragma unroll
-        for (int q = 0; q < kRestReal; ++q) {
-          if (q < nr) {
-            const float uu = up[(int64_t)q * n.n_src];
-            const float sn = __builtin_amdgcn_sinf(uu), cs = __builtin_amdgcn_cosf(uu);  // of 2 pi u
-            const float x1 = g.x * cs - g.y * sn, x2 = g.x * sn + g.y * cs;
-            se[q] = fmaf(qc, x1, fmaf(qs, x2, se[q]));
-            sb[q] = fmaf(qc, x2, fmaf(-qs, x1, sb[q]));
+          for (int q = 0; q < kRestReal; ++q) {
+            if (q < nr) {
+              const float2 x = xp[(int64_t)q * n.n_src];
+              se[q] = fmaf(qc, x.x, fmaf(qs, x.y, se[q]));
+              sb[q] = fmaf(qc, x.y, fmaf(-qs, x.x, sb[q]));
+            }
+          }
+        } else {
+          const float4 g = a.map[d];
+          const float* up = n.u + (int64_t)r0 * n.n_src + ci;
+#pragma unroll
+          for (int q = 0; q < kRestReal; ++q) {
+            if (q < nr) {
+              const float uu = up[(int64_t)q * n.n_src];
+              const float sn = __builtin_amdgcn_sinf(uu), cs = __builtin_amdgcn_cosf(uu);  // of 2 pi u
+              const float x1 = g.x * cs - g.y * sn, x2 = g.x * sn + g.y * cs;
+              se[q] = fmaf(qc, x1, fmaf(qs, x2, se[q]));
+              sb[q] = fmaf(qc, x2, fmaf(-qs, x1, sb[q]));
+            }
           }
         }
       }
@@ -736,6 +766,103 @@ __global__ void k_moments_add(const float* eb, int64_t n_out, double* mom) {
   mom[3 * n_out + o] += b * b;
 }
 
+// Galaxy-level angles: realisation r, galaxy i (its catalogue index) takes
+// word r mod 4 of Philox4x32-10 (Salmon et al. 2011) with counter
+// (i mod 2^32, i / 2^32, r / 4, 0) and key (seed mod 2^32, seed / 2^32): ten
+// rounds of two 32 x 32 -> 64-bit products with the published multipliers,
+// the key bumped by the published Weyl constants between rounds; then
+// u = ((x >> 9) + 0.5) 2^-23, exact in float, in (0, 1). One block of four
+// words serves four consecutive realisations of a galaxy.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t p0 = (uint64_t)M0 * c[0], p1 = (uint64_t)M1 * c[2];
+    const uint32_t x0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, x2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = x0;
+    c[1] = (uint32_t)p1;
+    c[2] = x2;
+    c[3] = (uint32_t)p0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+__device__ __forceinline__ float philox32_unit(uint32_t x) { return ((float)(x >> 9) + 0.5f) * 0x1p-23f; }
+
+// angles of realisations r0 .. r0 + 3 of galaxy i
+__device__ __forceinline__ void gal_angles4(uint64_t seed, int64_t i, int64_t r0, float u[4]) {
+  uint32_t c[4] = {0u, 0u, 0u, 0u};
+  int64_t blk = -1;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t r = r0 + t;
+    if ((r >> 2) != blk) {
+      blk = r >> 2;
+      c[0] = (uint32_t)i;
+      c[1] = (uint32_t)((uint64_t)i >> 32);
+      c[2] = (uint32_t)blk;
+      c[3] = 0u;
+      philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    }
+    u[t] = philox32_unit(c[r & 3]);
+  }
+}
+
+// u[r][i] for r < n_real, i < n_gal (realisation r_first + r): one thread
+// per (galaxy, block of four realisations)
+__global__ void k_gal_angles(uint64_t seed, int64_t r_first, int n_real, int64_t n_gal, float* u) {
+  const int nb = (n_real + 3) / 4;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)nb * n_gal) return;
+  const int64_t i = id % n_gal;
+  const int q = (int)(id / n_gal);
+  float v[4];
+  gal_angles4(seed, i, r_first + 4 * q, v);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    if (4 * q + t < n_real) u[(int64_t)(4 * q + t) * n_gal + i] = v[t];
+}
+
+// Rotated pixel sums of a chunk of galaxy-level realisations (Sect. 3.2
+// step 2 on the rotated catalogue): X[l][j] = sum over the galaxies of
+// source pixel j of w (g1 + i g2) e^(2 i pi u[r][i]), realisation
+// r = r0 + l, l < nc; the rotation in FP32 as for a single realisation,
+// the sums in FP64; for the averaged approach X is multiplied by
+// Omega_pix / W_j. Eight lanes per source, four realisations per lane.
+__global__ __launch_bounds__(kBlock) void k_gal_rot_sums(int64_t n_src, const int64_t* src_pix, const int64_t* off,
+                                                         const float4* G, const int64_t* order, const float4* sums,
+                                                         int64_t pix_first, int averaged, double omega,
+                                                         uint64_t seed, int64_t r0, int nc, float2* X) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = t / 8;
+  const int l0 = 4 * (int)(t % 8);
+  if (j >= n_src || l0 >= nc) return;
+  const int64_t p = src_pix[j];
+  const int64_t a = off[p], b = off[p + 1];
+  double x1[4] = {0.0, 0.0, 0.0, 0.0}, x2[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t g = a; g < b; ++g) {
+    const float4 gg = G[g];
+    float u[4];
+    gal_angles4(seed, order[g], r0 + l0, u);
+    const double w = (double)gg.z;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float sn = __builtin_amdgcn_sinf(u[q]), cs = __builtin_amdgcn_cosf(u[q]);  // of 2 pi u
+      x1[q] = fma(w, (double)(gg.x * cs - gg.y * sn), x1[q]);
+      x2[q] = fma(w, (double)(gg.x * sn + gg.y * cs), x2[q]);
+    }
+  }
+  double cj = 1.0;
+  if (averaged) {
+    const float W = sums[p - pix_first].w;
+    cj = W > 0.f ? omega / (double)W : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (l0 + q < nc) X[(int64_t)(l0 + q) * n_src + j] = make_float2((float)(x1[q] * cj), (float)(x2[q] * cj));
+}
+
 unsigned grid_of(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -744,6 +871,22 @@ hipError_t launch_philox_u(uint64_t seed, int64_t r_first, int n_real, int64_t n
   const int64_t threads = (n_src + 3) / 4 * n_real;
   if (threads == 0) return hipSuccess;
   hipLaunchKernelGGL(k_philox_u, dim3(grid_of(threads)), dim3(kBlock), 0, st, seed, r_first, n_real, n_src, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_gal_angles(uint64_t seed, int64_t r_first, int n_real, int64_t n_gal, float* u, hipStream_t st) {
+  const int64_t threads = (int64_t)((n_real + 3) / 4) * n_gal;
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gal_angles, dim3(grid_of(threads)), dim3(kBlock), 0, st, seed, r_first, n_real, n_gal, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_gal_rot_sums(smart_data d, int averaged, uint64_t seed, int64_t r0, int nc, float2* X,
+                               hipStream_t st) {
+  if (d->n_src == 0 || nc <= 0) return hipSuccess;
+  const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
+  hipLaunchKernelGGL(k_gal_rot_sums, dim3(grid_of(d->n_src * 8)), dim3(kBlock), 0, st, d->n_src, d->src_pix,
+                     d->offsets, d->G, d->order, d->sums, d->pix_first, averaged, omega, seed, r0, nc, X);
   return hipGetLastError();
 }
 
@@ -820,7 +963,9 @@ static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, h
   sc.noise_cnt_max = h[2];
   if (h[0] > 0) {  // the stack kernel's LDS is sized from the widest window
     static_assert(stack_lds_bytes(kCntMax) <= 160 * 1024 - 1024, "LDS of the widest stack");
-    NCHK(hipFuncSetAttribute((const void*)k_noise_stack, hipFuncAttributeMaxDynamicSharedMemorySize,
+    NCHK(hipFuncSetAttribute((const void*)k_noise_stack<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)stack_lds_bytes(kCntMax)));
+    NCHK(hipFuncSetAttribute((const void*)k_noise_stack<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)stack_lds_bytes(kCntMax)));
   }
   sc.noise_ncol = ncol;
@@ -851,7 +996,7 @@ static int build_noise_sched(smart_plan p, PixelSched& sc, const PixelArgs& a, h
 }
 
 int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st, int r_stride,
-                 int r_base, double* mom) {
+                 int r_base, double* mom, const float2* xsum) {
   if (r_stride < 0) r_stride = n_real;
   smart_data d = p->data;
   const double omega = 4.0 * M_PI / (12.0 * (double)d->nside * (double)d->nside);
@@ -905,8 +1050,10 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
       na.mom = mom;
       na.qsplit = sc.noise_qsplit;
       na.wn_out = sc.noise_wn;
+      na.xsum = xsum;
       const dim3 grid((unsigned)((int64_t)sc.noise_n_stacks * na.n_grp)), block(64 * kStack);
-      hipLaunchKernelGGL(k_noise_stack, grid, block, stack_lds_bytes(sc.noise_cnt_max), st, na, s,
+      hipLaunchKernelGGL(xsum ? k_noise_stack<true> : k_noise_stack<false>, grid, block,
+                         stack_lds_bytes(sc.noise_cnt_max), st, na, s,
                          sc.noise_cnt_max);
       NCHK(hipGetLastError());
     }
@@ -931,10 +1078,19 @@ int noise_bf16x3(smart_plan p, const float* d_u, int n_real, int norm, float* d_
       }
       const dim3 grid((unsigned)blocks), block(kBlock);
       const bool table = s.filter_kind != SMART_FILTER_POLY;
-      if (table && s.big) hipLaunchKernelGGL((k_noise_rest_walk<true, true>), grid, block, 0, st, ra, s);
-      else if (table) hipLaunchKernelGGL((k_noise_rest_walk<true, false>), grid, block, 0, st, ra, s);
-      else if (s.big) hipLaunchKernelGGL((k_noise_rest_walk<false, true>), grid, block, 0, st, ra, s);
-      else hipLaunchKernelGGL((k_noise_rest_walk<false, false>), grid, block, 0, st, ra, s);
+      ra.xsum = xsum;
+      auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, block, 0, st, ra, s); };
+      if (xsum) {
+        if (table && s.big) go(k_noise_rest_walk<true, true, true>);
+        else if (table) go(k_noise_rest_walk<true, false, true>);
+        else if (s.big) go(k_noise_rest_walk<false, true, true>);
+        else go(k_noise_rest_walk<false, false, true>);
+      } else {
+        if (table && s.big) go(k_noise_rest_walk<true, true, false>);
+        else if (table) go(k_noise_rest_walk<true, false, false>);
+        else if (s.big) go(k_noise_rest_walk<false, true, false>);
+        else go(k_noise_rest_walk<false, false, false>);
+      }
       NCHK(hipGetLastError());
     }
   }

@@ -376,9 +376,16 @@ hipError_t launch_rotate_map(const float4* map, const int* cidx, const float* u,
 // of E, E^2, B, B^2 over the realisations (n_real <= 32 per call then: one
 // realisation block per stack, so no two blocks update one output).
 int noise_bf16x3(smart_plan plan, const float* d_u, int n_real, int norm, float* d_out, hipStream_t st,
-                 int r_stride = -1, int r_base = 0, double* mom = nullptr);
+                 int r_stride = -1, int r_base = 0, double* mom = nullptr,
+                 const float2* xsum = nullptr);
 constexpr int kNoiseChunk = 32;  // realisations per stack block (and per seeded chunk)
 // u[r][j] = Philox4x64-10 word j of key (seed, r_first + r), mapped to (0, 1)
+// galaxy-level seeded realisations (k_noise.hip): angles u[r][i] of
+// realisations r_first .. r_first + n_real - 1 of every galaxy, and the
+// rotated pixel sums X[l][source] of realisations r0 .. r0 + nc - 1 (nc <= 32)
+hipError_t launch_gal_angles(uint64_t seed, int64_t r_first, int n_real, int64_t n_gal, float* u, hipStream_t st);
+hipError_t launch_gal_rot_sums(smart_data d, int averaged, uint64_t seed, int64_t r0, int nc, float2* X,
+                               hipStream_t st);
 hipError_t launch_philox_u(uint64_t seed, int64_t r_first, int n_real, int64_t n_src, float* u, hipStream_t st);
 // mom [4][n_out] += (E, E^2, B, B^2) of the float maps eb [2][n_out]
 hipError_t launch_moments_add(const float* eb, int64_t n_out, double* mom, hipStream_t st);

@@ -21,7 +21,8 @@ EXPORTS = [
     "smart_filter_table", "smart_filter_pieces", "smart_bin_galaxies", "smart_pixel_map", "smart_data_info", "smart_data_sources",
     "smart_data_export", "smart_barycentre_map",
     "smart_data_free", "smart_plan_create", "smart_run", "smart_last_pairs", "smart_plan_free",
-    "smart_noise_batch", "smart_noise_angles", "smart_noise_seeded", "smart_noise_galaxy_batch", "smart_mixed_batch", "smart_mixed_batch_noalloc", "smart_detect_peaks", "smart_plan_tiles",
+    "smart_noise_batch", "smart_noise_angles", "smart_noise_seeded", "smart_noise_galaxy_batch",
+    "smart_noise_galaxy_angles", "smart_noise_galaxy_seeded", "smart_mixed_batch", "smart_mixed_batch_noalloc", "smart_detect_peaks", "smart_plan_tiles",
     "smart_plan_set_timing", "smart_plan_kernel_ms", "smart_autotune", "smart_plan_galaxy_form",
     "smart_plan_set_galaxy_form",
 ]
@@ -61,6 +62,8 @@ _SIGS = {
     "smart_noise_galaxy_batch": (_int, [_vp, _vp, _int, _int, _vp, _vp]),
     "smart_noise_angles": (_int, [_vp, C.c_uint64, _i64, _int, _i64, _vp, _vp]),
     "smart_noise_seeded": (_int, [_vp, C.c_uint64, _i64, _int, _int, _int, _int, _vp, _vp]),
+    "smart_noise_galaxy_angles": (_int, [_vp, C.c_uint64, _i64, _int, _i64, _vp, _vp]),
+    "smart_noise_galaxy_seeded": (_int, [_vp, C.c_uint64, _i64, _int, _int, _int, _vp, _vp]),
     "smart_barycentre_map": (_int, [_vp, _vp, _vp]),
     "smart_mixed_batch": (_int, [_vp, _int, C.POINTER(_vp), C.POINTER(_int), C.POINTER(_vp), _vp]),
     "smart_mixed_batch_noalloc": (_int, [_vp, _int, C.POINTER(_vp), C.POINTER(_int), C.POINTER(_vp), _vp]),
