@@ -211,21 +211,25 @@ __device__ __forceinline__ uint2 split_pair(float a, float b) {
   return make_uint2(hi, pack_bf16(a - bf16_lo_word(hi), b - bf16_hi_word(hi)));
 }
 
-// (X1, X2) -> (X2, -X1) in a packed word: the B-mode column
-__device__ __forceinline__ uint32_t bmode(uint32_t x) { return ((x >> 16) | (x << 16)) ^ 0x80000000u; }
+// (q cos, q sin) -> (-q sin, q cos) in a packed coefficient word: the A
+// operand of the B-mode rows (B = q cos X2 - q sin X1)
+__device__ __forceinline__ uint32_t bmode_coef(uint32_t w) { return ((w >> 16) | (w << 16)) ^ 0x00008000u; }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Dynamic LDS of one stack block for windows of at most cnt_max members:
-// the slab as two planes of packed BF16 words (hi words, then the rounding
-// remainders), each [2 kNR][row] with the E form (X1, X2) of realisation r
-// in row 2 r and its B form (X2, -X1) in row 2 r + 1, slot s of the union
-// window at column s (also the epilogue's staging of the waves'
-// [2 kNR][kNP] outputs); then each wave's coefficient band as a hi and a lo
-// plane, zero-padded by kPadL entries before and kPadR after, so that the
-// operand loads need no range tests. With these layouts the four k values
-// of every MFMA operand register quadruple are four consecutive words of
-// one plane, loaded straight into the operand registers.
+// two buffers (by ring parity), each holding
+//  - the slab: the union window's rotated sums as two planes of packed
+//    BF16 words (hi words, then the rounding remainders), each [kNR][row]
+//    with (X1, X2) of realisation r in row r and slot s of the window at
+//    column s;
+//  - each wave's coefficient band in four planes, the hi and lo words of
+//    (q cos, q sin) (E rows) and of (-q sin, q cos) (B rows), zero-padded by
+//    kPadL entries before and kPadR after, so that the operand loads need no
+//    range tests.
+// With these layouts the four k values of every MFMA operand register
+// quadruple are four consecutive words of one plane. The epilogue stages
+// the waves' [2 kNR][kNP] outputs over the same memory.
 constexpr int kPadL = 32, kPadR = 48;
 __host__ __device__ constexpr int stack_slab(int cnt_max) { return kNP + cnt_max + 16; }
 // slab row length in words: the union window, the up to seven slots that the
@@ -233,18 +237,19 @@ __host__ __device__ constexpr int stack_slab(int cnt_max) { return kNP + cnt_max
 // that the 32 rows an MFMA operand load touches start on different banks
 __host__ __device__ constexpr int stack_row(int cnt_max) { return (stack_slab(cnt_max) + 8) | 1; }
 __host__ __device__ constexpr int stack_band(int cnt_max) { return kPadL + cnt_max + kPadR; }
+// words of one buffer: slab planes, then the waves' band planes
+__host__ __device__ constexpr int stack_buf_words(int cnt_max) {
+  return 2 * kNR * stack_row(cnt_max) + kStack * 4 * stack_band(cnt_max);
+}
 // epilogue staging row of one output column: kNP centres and one padding
 // word, so that the 32 columns a wave writes for one centre fall on
 // different LDS banks
 constexpr int kStageRow = kNP + 1;
-__host__ __device__ constexpr size_t stack_slab_bytes(int cnt_max) {
-  return (size_t)2 * 2 * kNR * stack_row(cnt_max) * sizeof(uint32_t) >
-                 (size_t)kStack * 2 * kNR * kStageRow * sizeof(float)
-             ? (size_t)2 * 2 * kNR * stack_row(cnt_max) * sizeof(uint32_t)
-             : (size_t)kStack * 2 * kNR * kStageRow * sizeof(float);
-}
 __host__ __device__ constexpr size_t stack_lds_bytes(int cnt_max) {
-  return stack_slab_bytes(cnt_max) + (size_t)kStack * 2 * stack_band(cnt_max) * sizeof(uint32_t);
+  return (size_t)2 * stack_buf_words(cnt_max) * sizeof(uint32_t) >
+                 (size_t)kStack * 2 * kNR * kStageRow * sizeof(float)
+             ? (size_t)2 * stack_buf_words(cnt_max) * sizeof(uint32_t)
+             : (size_t)kStack * 2 * kNR * kStageRow * sizeof(float);
 }
 
 // Belt coefficients (q cos 2psi, q sin 2psi) as the split BF16 words of the
@@ -260,37 +265,39 @@ __global__ void k_split_coef(const double* qc, const double* qs, int n, uint2* o
 // kernel's global data are read-only inputs.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Inputs of one 64-slot chunk of a ring's slab, one slot per lane: source
-// index, shear sums and the angles of the wave's realisations.
-constexpr int kWaveReal = kNR / kStack;  // realisations each wave generates
+// Realisations each wave generates per slab slot: wave w takes
+// realisations w, w + kStack, ... of the block.
+constexpr int kWaveReal = kNR / kStack;
+// the values of one slab slot for the wave's realisations: the pixel's shear
+// sum and angles, or (galaxy-level realisations) the rotated sums themselves
 template <bool XS>
 struct SlabIn {
-  int ci;
   float2 g;
   float u[kWaveReal];
 };
-// galaxy-level realisations: the rotated sums themselves
 template <>
 struct SlabIn<true> {
-  int ci;
   float2 x[kWaveReal];
 };
 
-// Ring loop, software-pipelined: while the MFMA steps of ring r run, the
-// coefficient band, source indices, shear sums and angles of ring r + 1 are
-// already requested, and the windows of ring r + 1 were published one
-// barrier earlier, so a ring costs two LDS barriers and no exposed global
-// load. XS: galaxy-level realisations, whose slab values are the rotated
-// pixel sums of each realisation (read instead of generated).
+// Ring loop, software-pipelined over a double-buffered slab: in the
+// iteration of ring r every wave first writes ring r + 1's slab values and
+// band into the other buffer, then requests ring r + 2's band words, shear
+// sums and angles and ring r + 3's source indices, then runs ring r's MFMA
+// steps, then publishes its window on ring r + 4; one LDS barrier per ring
+// then hands both buffers over. Every global load thus has a whole ring
+// iteration to arrive, and the slab generation of one ring shares the CU
+// with the MFMA steps of the previous one. XS: galaxy-level realisations,
+// whose slab values are the rotated pixel sums of each realisation (read
+// instead of generated).
 template <bool XS>
 __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))) void k_noise_stack(NoiseArgs n, ScaleArgs s,
                                                                                                   int cnt_max) {
   extern __shared__ uint2 smem[];
-  const int slab_max = stack_slab(cnt_max), band = stack_band(cnt_max), RS = stack_row(cnt_max);
-  uint32_t* const xh = reinterpret_cast<uint32_t*>(smem);  // [2 kNR][RS] hi words
-  uint32_t* const xl = xh + 2 * kNR * RS;                   // [2 kNR][RS] remainders
-  uint32_t* const coefP = reinterpret_cast<uint32_t*>(smem) + stack_slab_bytes(cnt_max) / sizeof(uint32_t);
-  __shared__ int2 s_win[2][kStack];  // per wave window [start, end] on a ring, by ring parity
+  uint32_t* const lds = reinterpret_cast<uint32_t*>(smem);
+  const int slab_max = stack_slab(cnt_max), BW = stack_band(cnt_max), RS = stack_row(cnt_max);
+  const int buf_words = stack_buf_words(cnt_max);
+  __shared__ int2 s_win[4][kStack];  // per wave window [start, end] on a ring, by ring mod 4
   __shared__ float fnorm[kStack][kNP];
   const PixelArgs& a = n.a;
   const int N = a.nside_in, nring = 4 * N;
@@ -309,8 +316,13 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
   const bool active = o_w >= 0;
   const int hfirst = uni_i(active ? n.t.head[iw].x : 0), hnr = uni_i(active ? n.t.head[iw].y : 0);
   const int lo_w = uni_i(active ? n.t.info[hfirst].x : 0x7fffffff);
-  uint32_t* const bandh = coefP + wave * 2 * band;  // [band] hi words of (q cos, q sin)
-  uint32_t* const bandl = bandh + band;              // [band] remainders
+  // the table entries of the wave's first 64 disc rings, one per lane, so
+  // that the ring loop reads its windows from registers
+  int3 inf_l = make_int3(0, 0, 0);
+  if (active && lane < hnr) {
+    const int4 v = n.t.info[hfirst + lane];
+    inf_l = make_int3(v.y, v.z, v.w);
+  }
   // union of the stack's discs' rings
   __shared__ int s_lo[kStack], s_hi[kStack];
   if (lane == 0) {
@@ -319,7 +331,7 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
   }
   // slots past a ring's union window keep finite words (zero, or an earlier
   // ring's), which the zero coefficients there cancel
-  for (int i = tid; i < 2 * 2 * kNR * RS; i += 64 * kStack) xh[i] = 0u;
+  for (int i = tid; i < 2 * buf_words; i += 64 * kStack) lds[i] = 0u;
   __syncthreads();
   int lo = s_lo[0], hi = s_hi[0];
   for (int w = 1; w < kStack; ++w) {
@@ -328,6 +340,9 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
   }
   lo = uni_i(lo);
   hi = uni_i(hi);
+  // buffer b: slab planes, then this wave's four band planes
+  auto slab_h = [&](int b) { return lds + b * buf_words; };
+  auto band_of = [&](int b) { return lds + b * buf_words + 2 * kNR * RS + wave * 4 * BW; };
 
   // this wave's window on ring r for its first centre (pixel 32c of ring N + iw)
   auto own = [&](int r, int& cnt, int& coff, int& ws) {
@@ -335,21 +350,31 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
     coff = 0;
     ws = 0;
     if (active && r >= lo_w && r < lo_w + hnr) {
-      const int4 inf = n.t.info[hfirst + (r - lo_w)];
-      cnt = uni_i(inf.z);
-      coff = uni_i(inf.w);
-      ws = uni_i(kNP * c + inf.y);
+      const int k = r - lo_w;
+      int3 inf;
+      if (k < 64) {
+        inf = make_int3(__builtin_amdgcn_readlane(inf_l.x, k), __builtin_amdgcn_readlane(inf_l.y, k),
+                        __builtin_amdgcn_readlane(inf_l.z, k));
+      } else {
+        const int4 v = n.t.info[hfirst + k];
+        inf = make_int3(uni_i(v.y), uni_i(v.z), uni_i(v.w));
+      }
+      cnt = inf.y;
+      coff = inf.z;
+      ws = kNP * c + inf.x;
     }
   };
-  auto post = [&](int r, int cnt, int ws) {
-    if (lane == 0) s_win[r & 1][wave] = cnt > 0 ? make_int2(ws, ws + kNP + cnt - 1) : make_int2(0x7fffffff, -0x7fffffff);
+  auto post = [&](int r) {
+    int cnt, coff, ws;
+    own(r, cnt, coff, ws);
+    if (lane == 0) s_win[r & 3][wave] = cnt > 0 ? make_int2(ws, ws + kNP + cnt - 1) : make_int2(0x7fffffff, -0x7fffffff);
   };
-  // the union window [us, ue) of the stack's waves on ring r, and its slots
+  // the union window [us, us + Lu) of the stack's waves on ring r, and its slots
   auto uni = [&](int r, int& us, int& Lu) {
     int ue = -0x7fffffff;
     us = 0x7fffffff;
     for (int w = 0; w < kStack; ++w) {
-      const int2 v = s_win[r & 1][w];
+      const int2 v = s_win[r & 3][w];
       us = min(us, v.x);
       ue = max(ue, v.y);
     }
@@ -364,28 +389,50 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
 #pragma unroll
     for (int j = 0; j < kBandSlots; ++j) {
       const int m = lane + 64 * j - kPadL;
-      bw[j] = (lane + 64 * j < band && m >= 0 && m < cnt) ? n.qsplit[coff + m] : make_uint2(0u, 0u);
+      bw[j] = (lane + 64 * j < BW && m >= 0 && m < cnt) ? n.qsplit[coff + m] : make_uint2(0u, 0u);
+    }
+  };
+  auto store_band = [&](int b, const uint2* bw) {
+    uint32_t* const bp = band_of(b);
+#pragma unroll
+    for (int j = 0; j < kBandSlots; ++j) {
+      const int k = lane + 64 * j;
+      if (k < BW) {
+        bp[k] = bw[j].x;
+        bp[BW + k] = bw[j].y;
+        bp[2 * BW + k] = bmode_coef(bw[j].x);
+        bp[3 * BW + k] = bmode_coef(bw[j].y);
+      }
     }
   };
   auto ring_base = [&](int r) { return 2 * (int64_t)N * (N - 1) + (int64_t)nring * (r - N) - a.pix_first; };
-  // slab inputs of slot us + sl of ring r: source index and shear sums, then
-  // (once the index is known) the angles
-  auto load_src = [&](int r, int us, int sl, SlabIn<XS>& in) {
-    const int64_t j = ring_base(r) + ((us + sl) & (nring - 1));
-    in.ci = n.cidx[j];
-    if constexpr (!XS) in.g = *reinterpret_cast<const float2*>(a.map + j);
-  };
-  auto load_ang = [&](SlabIn<XS>& in) {
+  auto dense = [&](int r, int us, int sl) { return ring_base(r) + ((us + sl) & (nring - 1)); };
+  // slab slot sl of ring r: the source index (-1 for an empty pixel)
+  auto load_ci = [&](int r, int us, int sl) { return n.cidx[dense(r, us, sl)]; };
+  // the shear sum of slot sl (zero for an empty pixel) and the angles or
+  // rotated sums of the wave's realisations
+  auto load_in = [&](int r, int us, int sl, int ci, SlabIn<XS>& in) {
+    if constexpr (!XS) in.g = *reinterpret_cast<const float2*>(a.map + dense(r, us, sl));
 #pragma unroll
     for (int t = 0; t < kWaveReal; ++t) {
       const int rreal = rg * kNR + wave + kStack * t;
-      const bool ok = in.ci >= 0 && rreal < n.n_real;
-      if constexpr (XS) in.x[t] = ok ? n.xsum[(int64_t)rreal * n.n_src + in.ci] : make_float2(0.f, 0.f);
-      else in.u[t] = ok ? n.u[(int64_t)rreal * n.n_src + in.ci] : 0.f;
+      const bool ok = ci >= 0 && rreal < n.n_real;
+      if constexpr (XS) in.x[t] = ok ? n.xsum[(int64_t)rreal * n.n_src + ci] : make_float2(0.f, 0.f);
+      else in.u[t] = ok ? n.u[(int64_t)rreal * n.n_src + ci] : 0.f;
     }
   };
-  // realisations of slab slot sl: wave w generates realisations w, w + 8, ...
-  auto gen = [&](int sl, const SlabIn<XS>& in) {
+  auto clear_in = [&](SlabIn<XS>& in) {
+    if constexpr (!XS) in.g = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < kWaveReal; ++t) {
+      if constexpr (XS) in.x[t] = make_float2(0.f, 0.f);
+      else in.u[t] = 0.f;
+    }
+  };
+  // the wave's realisations of slab slot sl into buffer b
+  auto gen = [&](int b, int sl, const SlabIn<XS>& in) {
+    uint32_t* const xh = slab_h(b);
+    uint32_t* const xl = xh + kNR * RS;
 #pragma unroll
     for (int t = 0; t < kWaveReal; ++t) {
       const int rr = wave + kStack * t;
@@ -393,113 +440,127 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
       if constexpr (XS) {
         e = split_pair(in.x[t].x, in.x[t].y);
       } else {
-        const float gx = in.ci >= 0 ? in.g.x : 0.f, gy = in.ci >= 0 ? in.g.y : 0.f;
         const float sn = __builtin_amdgcn_sinf(in.u[t]), cs = __builtin_amdgcn_cosf(in.u[t]);  // of 2 pi u
-        e = split_pair(gx * cs - gy * sn, gx * sn + gy * cs);
+        e = split_pair(in.g.x * cs - in.g.y * sn, in.g.x * sn + in.g.y * cs);
       }
-      xh[2 * rr * RS + sl] = e.x;
-      xl[2 * rr * RS + sl] = e.y;
-      xh[(2 * rr + 1) * RS + sl] = bmode(e.x);
-      xl[(2 * rr + 1) * RS + sl] = bmode(e.y);
+      xh[rr * RS + sl] = e.x;
+      xl[rr * RS + sl] = e.y;
+    }
+  };
+  // the whole slab of ring r (Lu slots) into buffer b: the first 64 slots
+  // from `in`, the rest (windows over 64 slots) loaded here
+  auto gen_ring = [&](int b, int r, int us, int Lu, const SlabIn<XS>& in) {
+    if (lane < Lu) gen(b, lane, in);
+    for (int s0 = 64; s0 < Lu; s0 += 64) {
+      SlabIn<XS> x;
+      clear_in(x);
+      if (s0 + lane < Lu) load_in(r, us, s0 + lane, load_ci(r, us, s0 + lane), x);
+      if (s0 + lane < Lu) gen(b, s0 + lane, x);
     }
   };
 
-  f32x16 acc0 = {0}, acc1 = {0};
+  f32x16 accE = {0}, accB = {0};
   const int col = lane & 31;   // MFMA row (A) / column (B)
   const int half = lane >> 5;  // k-slice of the lane
 
-  // ring lo: windows, band words, first slab chunk
+  // prologue: the windows of rings lo .. lo + 3, ring lo's slab and band,
+  // ring lo + 1's inputs, ring lo + 2's source indices
+  for (int k = 0; k < 4; ++k)
+    if (lo + k <= hi) post(lo + k);
+  __syncthreads();
   int cnt, coff, ws, us, Lu;
   own(lo, cnt, coff, ws);
-  post(lo, cnt, ws);
-  uint2 bw[kBandSlots];
-  load_band(cnt, coff, bw);
-  __syncthreads();
   uni(lo, us, Lu);
+  uint2 bw[kBandSlots];
   SlabIn<XS> in;
-  in.ci = -1;
-  if (lane < Lu) load_src(lo, us, lane, in);
-  load_ang(in);
+  clear_in(in);
+  load_band(cnt, coff, bw);
+  if (lane < Lu) load_in(lo, us, lane, load_ci(lo, us, lane), in);
+  store_band(lo & 1, bw);
+  gen_ring(lo & 1, lo, us, Lu, in);
+  int cnt1 = 0, coff1 = 0, ws1 = 0, us1 = 0, Lu1 = 0;
+  clear_in(in);
+  if (lo + 1 <= hi) {
+    own(lo + 1, cnt1, coff1, ws1);
+    uni(lo + 1, us1, Lu1);
+    load_band(cnt1, coff1, bw);
+    if (lane < Lu1) load_in(lo + 1, us1, lane, load_ci(lo + 1, us1, lane), in);
+  }
+  int us2 = 0, Lu2 = 0, ci_n = -1;
+  if (lo + 2 <= hi) {
+    uni(lo + 2, us2, Lu2);
+    if (lane < Lu2) ci_n = load_ci(lo + 2, us2, lane);
+  }
+  lds_barrier();
 
   for (int r = lo; r <= hi; ++r) {
-    // ring r: band and slab into LDS (the previous ring's readers are past
-    // the last barrier)
-#pragma unroll
-    for (int j = 0; j < kBandSlots; ++j) {
-      const int k = lane + 64 * j;
-      if (k < band) {
-        bandh[k] = bw[j].x;
-        bandl[k] = bw[j].y;
-      }
+    const int b = r & 1;
+    // ring r + 1: slab and band into the other buffer (its readers, ring
+    // r - 1's MFMA steps, are past the last barrier)
+    if (r + 1 <= hi) {
+      store_band(b ^ 1, bw);
+      gen_ring(b ^ 1, r + 1, us1, Lu1, in);
     }
-    if (lane < Lu) gen(lane, in);
-    for (int s0 = 64; s0 < Lu; s0 += 64) {  // windows over 64 slots: the rest loaded here
-      SlabIn<XS> x;
-      x.ci = -1;
-      if (s0 + lane < Lu) load_src(r, us, s0 + lane, x);
-      load_ang(x);
-      if (s0 + lane < Lu) gen(s0 + lane, x);
+    // ring r + 2: band words, shear sums and angles requested; ring r + 3:
+    // source indices requested
+    int cnt2 = 0, coff2 = 0, ws2 = 0;
+    clear_in(in);
+    if (r + 2 <= hi) {
+      own(r + 2, cnt2, coff2, ws2);
+      load_band(cnt2, coff2, bw);
+      if (lane < Lu2) load_in(r + 2, us2, lane, ci_n, in);
     }
-    // ring r + 1: this wave's window, published for the union
-    int cnt1 = 0, coff1 = 0, ws1 = 0;
-    if (r < hi) {
-      own(r + 1, cnt1, coff1, ws1);
-      post(r + 1, cnt1, ws1);
-    }
-    lds_barrier();
-    // ring r + 1: band words and slab sources requested now, used after the
-    // MFMA steps of ring r
-    int us1 = 0, Lu1 = 0;
-    if (r < hi) {
-      uni(r + 1, us1, Lu1);
-      load_band(cnt1, coff1, bw);
-      in.ci = -1;
-      if (lane < Lu1) load_src(r + 1, us1, lane, in);
+    int us3 = 0, Lu3 = 0;
+    ci_n = -1;
+    if (r + 3 <= hi) {
+      uni(r + 3, us3, Lu3);
+      if (lane < Lu3) ci_n = load_ci(r + 3, us3, lane);
     }
     if (cnt > 0) {
       const int base = ws - us;     // slab slot of this wave's first window pixel
       const int L = kNP + cnt - 1;  // centre t uses window pixels [t, t + cnt)
       // lane (col, half) holds window pixels js = s0 + 4 half + q, q < 4.
-      // A row col: coefficient js - col (zero outside [0, cnt)). B column
-      // col: slab row col (realisation col / 2, E form for even col, B
-      // form for odd) for acc0 and row 32 + col (realisation 16 + col / 2)
-      // for acc1, at slot base + js (past the window the coefficients are
-      // zero and the slots finite)
-      const uint32_t* const ahp = bandh + kPadL - col + 4 * half;
-      const uint32_t* const alp = bandl + kPadL - col + 4 * half;
-      const uint32_t* const b0hp = xh + col * RS + base + 4 * half;
-      const uint32_t* const b0lp = xl + col * RS + base + 4 * half;
-      const uint32_t* const b1hp = b0hp + 32 * RS;
-      const uint32_t* const b1lp = b0lp + 32 * RS;
+      // A row col: coefficient js - col (zero outside [0, cnt)) of the E
+      // and of the B band. B column col: slab row col (realisation col) at
+      // slot base + js (past the window the coefficients are zero and the
+      // slots finite)
+      const uint32_t* const ap = band_of(b) + kPadL - col + 4 * half;
+      const uint32_t* const xhp = slab_h(b) + col * RS + base + 4 * half;
+      const uint32_t* const xlp = xhp + kNR * RS;
       for (int s0 = 0; s0 < L; s0 += 8) {
-        u32x4 ah, al, b0h, b0l, b1h, b1l;
+        u32x4 eh, el, bh, bl, xh, xl;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          ah[q] = ahp[s0 + q];
-          al[q] = alp[s0 + q];
-          b0h[q] = b0hp[s0 + q];
-          b0l[q] = b0lp[s0 + q];
-          b1h[q] = b1hp[s0 + q];
-          b1l[q] = b1lp[s0 + q];
+          eh[q] = ap[s0 + q];
+          el[q] = ap[BW + s0 + q];
+          bh[q] = ap[2 * BW + s0 + q];
+          bl[q] = ap[3 * BW + s0 + q];
+          xh[q] = xhp[s0 + q];
+          xl[q] = xlp[s0 + q];
         }
-        const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah), Al = __builtin_bit_cast(bf16x8, al);
-        const bf16x8 B0h = __builtin_bit_cast(bf16x8, b0h), B0l = __builtin_bit_cast(bf16x8, b0l);
-        const bf16x8 B1h = __builtin_bit_cast(bf16x8, b1h), B1l = __builtin_bit_cast(bf16x8, b1l);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, B0h, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, B1h, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, B0l, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, B1l, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, B0h, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, B1h, acc1, 0, 0, 0);
+        const bf16x8 Eh = __builtin_bit_cast(bf16x8, eh), El = __builtin_bit_cast(bf16x8, el);
+        const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh), Bl = __builtin_bit_cast(bf16x8, bl);
+        const bf16x8 Xh = __builtin_bit_cast(bf16x8, xh), Xl = __builtin_bit_cast(bf16x8, xl);
+        accE = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Eh, Xh, accE, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bh, Xh, accB, 0, 0, 0);
+        accE = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Eh, Xl, accE, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bh, Xl, accB, 0, 0, 0);
+        accE = __builtin_amdgcn_mfma_f32_32x32x16_bf16(El, Xh, accE, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bl, Xh, accB, 0, 0, 0);
       }
     }
-    if (r < hi) load_ang(in);  // ring r + 1's angles (its source indices have arrived)
-    lds_barrier();             // the slab and bands are rewritten for the next ring
+    // ring r + 4: this wave's window, published for the union
+    if (r + 4 <= hi) post(r + 4);
+    lds_barrier();  // ring r + 1's buffer is complete, ring r's is free
     cnt = cnt1;
-    coff = coff1;
     ws = ws1;
     us = us1;
-    Lu = Lu1;
+    cnt1 = cnt2;
+    ws1 = ws2;
+    us1 = us2;
+    Lu1 = Lu2;
+    us2 = us3;
+    Lu2 = Lu3;
   }
 
   // epilogue: normalisation per centre, staged for coalesced writes
@@ -521,8 +582,8 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int row = 8 * (i / 4) + 4 * half + (i % 4);  // centre
-    cst[col * kStageRow + row] = acc0[i] * fnorm[wave][row];         // column 2 r' + e, r' < 16
-    cst[(32 + col) * kStageRow + row] = acc1[i] * fnorm[wave][row];  // r' >= 16
+    cst[col * kStageRow + row] = accE[i] * fnorm[wave][row];         // E of realisation col
+    cst[(kNR + col) * kStageRow + row] = accB[i] * fnorm[wave][row];  // B of realisation col
   }
   __syncthreads();
   if (active && n.mom) {
@@ -533,7 +594,7 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
     if (lane < kNP && lane >= sg.y && lane < sg.z) {
       double m[4] = {0.0, 0.0, 0.0, 0.0};
       for (int rr = 0; rr < nr; ++rr) {
-        const double e = (double)cst[(2 * rr) * kStageRow + lane], b = (double)cst[(2 * rr + 1) * kStageRow + lane];
+        const double e = (double)cst[rr * kStageRow + lane], b = (double)cst[(kNR + rr) * kStageRow + lane];
         m[0] += e;
         m[1] += e * e;
         m[2] += b;
@@ -546,7 +607,7 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
   } else if (active) {  // centres sg.y .. sg.z - 1 of the segment are list entries o_w, o_w + 1, ...
     for (int v = lane; v < 2 * kNR * kNP; v += 64) {
       const int ci = v / kNP, pp = v % kNP;
-      const int rr = rg * kNR + (ci >> 1), e = ci & 1;
+      const int rr = rg * kNR + (ci % kNR), e = ci / kNR;
       if (rr < n.n_real && pp >= sg.y && pp < sg.z)
         n.out[(((int64_t)a.scale * n.r_stride + n.r_base + rr) * 2 + e) * a.n_out + o_w + (pp - sg.y)] =
             cst[ci * kStageRow + pp];
