@@ -196,10 +196,13 @@ struct NoiseArgs {
   double* mom;        // moments mode (out unused): [n_scales][4][n_out] += sum of E, E^2, B, B^2
 };
 
-// two BF16 words per 32-bit lane of an MFMA operand
+// two BF16 words per 32-bit lane of an MFMA operand (one paired conversion,
+// round to nearest even)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
-  const __bf16 ha = (__bf16)a, hb = (__bf16)b;
-  return (uint32_t)__builtin_bit_cast(uint16_t, ha) | ((uint32_t)__builtin_bit_cast(uint16_t, hb) << 16);
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 
 __device__ __forceinline__ float bf16_lo_word(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
@@ -281,15 +284,15 @@ struct SlabIn<true> {
 };
 
 // Ring loop, software-pipelined over a double-buffered slab: in the
-// iteration of ring r every wave first writes ring r + 1's slab values and
-// band into the other buffer, then requests ring r + 2's band words, shear
-// sums and angles and ring r + 3's source indices, then runs ring r's MFMA
-// steps, then publishes its window on ring r + 4; one LDS barrier per ring
-// then hands both buffers over. Every global load thus has a whole ring
-// iteration to arrive, and the slab generation of one ring shares the CU
-// with the MFMA steps of the previous one. XS: galaxy-level realisations,
-// whose slab values are the rotated pixel sums of each realisation (read
-// instead of generated).
+// iteration of ring r every wave writes ring r + 1's band into the other
+// buffer, requests ring r + 2's band words, shear sums and angles and ring
+// r + 3's source indices, then runs ring r's MFMA steps with ring r + 1's
+// slab values generated between them (one realisation per early step, so
+// that the VALU work runs while the products do), then publishes its window
+// on ring r + 4; one LDS barrier per ring then hands both buffers over.
+// Every global load thus has a whole ring iteration to arrive. XS:
+// galaxy-level realisations, whose slab values are the rotated pixel sums of
+// each realisation (read instead of generated).
 template <bool XS>
 __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))) void k_noise_stack(NoiseArgs n, ScaleArgs s,
                                                                                                   int cnt_max) {
@@ -429,34 +432,38 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
       else in.u[t] = 0.f;
     }
   };
-  // the wave's realisations of slab slot sl into buffer b
-  auto gen = [&](int b, int sl, const SlabIn<XS>& in) {
+  // the wave's realisation t of slab slot sl into buffer b
+  auto gen_t = [&](int b, int sl, const SlabIn<XS>& in, int t) {
     uint32_t* const xh = slab_h(b);
     uint32_t* const xl = xh + kNR * RS;
-#pragma unroll
-    for (int t = 0; t < kWaveReal; ++t) {
-      const int rr = wave + kStack * t;
-      uint2 e;
-      if constexpr (XS) {
-        e = split_pair(in.x[t].x, in.x[t].y);
-      } else {
-        const float sn = __builtin_amdgcn_sinf(in.u[t]), cs = __builtin_amdgcn_cosf(in.u[t]);  // of 2 pi u
-        e = split_pair(in.g.x * cs - in.g.y * sn, in.g.x * sn + in.g.y * cs);
-      }
-      xh[rr * RS + sl] = e.x;
-      xl[rr * RS + sl] = e.y;
+    const int rr = wave + kStack * t;
+    uint2 e;
+    if constexpr (XS) {
+      e = split_pair(in.x[t].x, in.x[t].y);
+    } else {
+      const float sn = __builtin_amdgcn_sinf(in.u[t]), cs = __builtin_amdgcn_cosf(in.u[t]);  // of 2 pi u
+      e = split_pair(in.g.x * cs - in.g.y * sn, in.g.x * sn + in.g.y * cs);
     }
+    xh[rr * RS + sl] = e.x;
+    xl[rr * RS + sl] = e.y;
   };
-  // the whole slab of ring r (Lu slots) into buffer b: the first 64 slots
-  // from `in`, the rest (windows over 64 slots) loaded here
-  auto gen_ring = [&](int b, int r, int us, int Lu, const SlabIn<XS>& in) {
-    if (lane < Lu) gen(b, lane, in);
+  auto gen = [&](int b, int sl, const SlabIn<XS>& in) {
+#pragma unroll
+    for (int t = 0; t < kWaveReal; ++t) gen_t(b, sl, in, t);
+  };
+  // slots 64 .. Lu - 1 of ring r's slab (windows over 64 slots), loaded here
+  auto gen_rest = [&](int b, int r, int us, int Lu) {
     for (int s0 = 64; s0 < Lu; s0 += 64) {
       SlabIn<XS> x;
       clear_in(x);
       if (s0 + lane < Lu) load_in(r, us, s0 + lane, load_ci(r, us, s0 + lane), x);
       if (s0 + lane < Lu) gen(b, s0 + lane, x);
     }
+  };
+  // the whole slab of ring r (Lu slots) into buffer b, the first 64 slots from `in`
+  auto gen_ring = [&](int b, int r, int us, int Lu, const SlabIn<XS>& in) {
+    if (lane < Lu) gen(b, lane, in);
+    gen_rest(b, r, us, Lu);
   };
 
   f32x16 accE = {0}, accB = {0};
@@ -495,12 +502,13 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
 
   for (int r = lo; r <= hi; ++r) {
     const int b = r & 1;
-    // ring r + 1: slab and band into the other buffer (its readers, ring
-    // r - 1's MFMA steps, are past the last barrier)
-    if (r + 1 <= hi) {
-      store_band(b ^ 1, bw);
-      gen_ring(b ^ 1, r + 1, us1, Lu1, in);
-    }
+    const bool next = r + 1 <= hi;
+    // ring r + 1: band into the other buffer (its readers, ring r - 1's MFMA
+    // steps, are past the last barrier); its slab values follow below,
+    // between ring r's MFMA steps
+    if (next) store_band(b ^ 1, bw);
+    const SlabIn<XS> in1 = in;
+    const bool gen1 = next && lane < Lu1;
     // ring r + 2: band words, shear sums and angles requested; ring r + 3:
     // source indices requested
     int cnt2 = 0, coff2 = 0, ws2 = 0;
@@ -527,7 +535,7 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
       const uint32_t* const ap = band_of(b) + kPadL - col + 4 * half;
       const uint32_t* const xhp = slab_h(b) + col * RS + base + 4 * half;
       const uint32_t* const xlp = xhp + kNR * RS;
-      for (int s0 = 0; s0 < L; s0 += 8) {
+      auto step = [&](int s0, int t) {
         u32x4 eh, el, bh, bl, xh, xl;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -543,12 +551,22 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
         const bf16x8 Xh = __builtin_bit_cast(bf16x8, xh), Xl = __builtin_bit_cast(bf16x8, xl);
         accE = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Eh, Xh, accE, 0, 0, 0);
         accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bh, Xh, accB, 0, 0, 0);
+        // one realisation of ring r + 1's slab while the products run
+        if (t >= 0 && gen1) gen_t(b ^ 1, lane, in1, t);
         accE = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Eh, Xl, accE, 0, 0, 0);
         accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bh, Xl, accB, 0, 0, 0);
         accE = __builtin_amdgcn_mfma_f32_32x32x16_bf16(El, Xh, accE, 0, 0, 0);
         accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bl, Xh, accB, 0, 0, 0);
-      }
+      };
+      // L >= kNP, so there are at least kWaveReal = 4 steps
+      static_assert(8 * kWaveReal <= kNP, "one realisation per early step");
+#pragma unroll
+      for (int t = 0; t < kWaveReal; ++t) step(8 * t, t);
+      for (int s0 = 8 * kWaveReal; s0 < L; s0 += 8) step(s0, -1);
+    } else if (gen1) {
+      gen(b ^ 1, lane, in1);
     }
+    if (next) gen_rest(b ^ 1, r + 1, us1, Lu1);
     // ring r + 4: this wave's window, published for the union
     if (r + 4 <= hi) post(r + 4);
     lds_barrier();  // ring r + 1's buffer is complete, ring r's is free
