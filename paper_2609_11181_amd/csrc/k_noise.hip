@@ -43,7 +43,7 @@ namespace smart {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNP = 32;     // centres per segment (MFMA rows)
 constexpr int kNR = 32;     // realisations per block (E and B: two 32-column MFMA halves)
@@ -235,10 +235,10 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // the waves' [2 kNR][kNP] outputs over the same memory.
 constexpr int kPadL = 32, kPadR = 48;
 __host__ __device__ constexpr int stack_slab(int cnt_max) { return kNP + cnt_max + 16; }
-// slab row length in words: the union window, the up to seven slots that the
-// last operand step reads past it (their coefficients are zero), and odd so
-// that the 32 rows an MFMA operand load touches start on different banks
-__host__ __device__ constexpr int stack_row(int cnt_max) { return (stack_slab(cnt_max) + 8) | 1; }
+// slab row length in words: the union window, the up to fifteen slots that
+// the last operand step reads past it (their coefficients are zero), and odd
+// so that the rows an MFMA operand load touches start on different banks
+__host__ __device__ constexpr int stack_row(int cnt_max) { return (stack_slab(cnt_max) + 16) | 1; }
 __host__ __device__ constexpr int stack_band(int cnt_max) { return kPadL + cnt_max + kPadR; }
 // words of one buffer: slab planes, then the waves' band planes
 __host__ __device__ constexpr int stack_buf_words(int cnt_max) {
@@ -466,9 +466,11 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
     gen_rest(b, r, us, Lu);
   };
 
-  f32x16 accE = {0}, accB = {0};
-  const int col = lane & 31;   // MFMA row (A) / column (B)
-  const int half = lane >> 5;  // k-slice of the lane
+  f32x4 acc[2][2][2];  // [row tile][column tile][E, B]
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i / 4][(i / 2) % 2][i % 2] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int t16 = lane & 15;  // MFMA row (A) / column (B) within a 16-tile
+  const int qt = lane >> 4;   // k-quarter of the lane (A, B) / row quarter (result)
 
   // prologue: the windows of rings lo .. lo + 3, ring lo's slab and band,
   // ring lo + 1's inputs, ring lo + 2's source indices
@@ -525,44 +527,65 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
       if (lane < Lu3) ci_n = load_ci(r + 3, us3, lane);
     }
     if (cnt > 0) {
-      const int base = ws - us;     // slab slot of this wave's first window pixel
-      const int L = kNP + cnt - 1;  // centre t uses window pixels [t, t + cnt)
-      // lane (col, half) holds window pixels js = s0 + 4 half + q, q < 4.
-      // A row col: coefficient js - col (zero outside [0, cnt)) of the E
-      // and of the B band. B column col: slab row col (realisation col) at
-      // slot base + js (past the window the coefficients are zero and the
-      // slots finite)
-      const uint32_t* const ap = band_of(b) + kPadL - col + 4 * half;
-      const uint32_t* const xhp = slab_h(b) + col * RS + base + 4 * half;
-      const uint32_t* const xlp = xhp + kNR * RS;
-      auto step = [&](int s0, int t) {
-        u32x4 eh, el, bh, bl, xh, xl;
+      // two 16-row tiles of 16 x 16 x 32 products: tile T holds centres
+      // 16 T + t, t < 16, whose window pixels are [16 T + t, 16 T + t + cnt).
+      // Step k of tile T covers window pixels 16 (T + k) + 4 qt + q (the lane's
+      // k-quarter qt, q < 4), so the coefficient of row t is band word
+      // 16 k + 4 qt + q - t for both tiles (Toeplitz), and tile 1's slab
+      // operand of step k is tile 0's of step k + 1. B column: slab row of
+      // realisation 16 C + t (column tile C).
+      const int base = ws - us;             // slab slot of this wave's first window pixel
+      const int K0 = (15 + cnt + 15) / 16;  // steps per tile
+      const uint32_t* const ap = band_of(b) + kPadL - t16 + 4 * qt;
+      const uint32_t* const xp = slab_h(b) + t16 * RS + base + 4 * qt;
+      auto load_x = [&](int j, u32x4* x) {  // slab operands of window pixels 16 j + ..: C = 0, 1, hi and lo
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          eh[q] = ap[s0 + q];
-          el[q] = ap[BW + s0 + q];
-          bh[q] = ap[2 * BW + s0 + q];
-          bl[q] = ap[3 * BW + s0 + q];
-          xh[q] = xhp[s0 + q];
-          xl[q] = xlp[s0 + q];
+          x[0][q] = xp[16 * j + q];
+          x[1][q] = xp[kNR * RS + 16 * j + q];
+          x[2][q] = xp[16 * RS + 16 * j + q];
+          x[3][q] = xp[kNR * RS + 16 * RS + 16 * j + q];
         }
-        const bf16x8 Eh = __builtin_bit_cast(bf16x8, eh), El = __builtin_bit_cast(bf16x8, el);
-        const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh), Bl = __builtin_bit_cast(bf16x8, bl);
-        const bf16x8 Xh = __builtin_bit_cast(bf16x8, xh), Xl = __builtin_bit_cast(bf16x8, xl);
-        accE = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Eh, Xh, accE, 0, 0, 0);
-        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bh, Xh, accB, 0, 0, 0);
-        // one realisation of ring r + 1's slab while the products run
-        if (t >= 0 && gen1) gen_t(b ^ 1, lane, in1, t);
-        accE = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Eh, Xl, accE, 0, 0, 0);
-        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bh, Xl, accB, 0, 0, 0);
-        accE = __builtin_amdgcn_mfma_f32_32x32x16_bf16(El, Xh, accE, 0, 0, 0);
-        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bl, Xh, accB, 0, 0, 0);
       };
-      // L >= kNP, so there are at least kWaveReal = 4 steps
-      static_assert(8 * kWaveReal <= kNP, "one realisation per early step");
+      auto tile = [&](int T, const u32x4* A, const u32x4* X) {
+        const bf16x8 Eh = __builtin_bit_cast(bf16x8, A[0]), El = __builtin_bit_cast(bf16x8, A[1]);
+        const bf16x8 Bh = __builtin_bit_cast(bf16x8, A[2]), Bl = __builtin_bit_cast(bf16x8, A[3]);
 #pragma unroll
-      for (int t = 0; t < kWaveReal; ++t) step(8 * t, t);
-      for (int s0 = 8 * kWaveReal; s0 < L; s0 += 8) step(s0, -1);
+        for (int C = 0; C < 2; ++C) {
+          const bf16x8 Xh = __builtin_bit_cast(bf16x8, X[2 * C]), Xl = __builtin_bit_cast(bf16x8, X[2 * C + 1]);
+          acc[T][C][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Eh, Xh, acc[T][C][0], 0, 0, 0);
+          acc[T][C][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bh, Xh, acc[T][C][1], 0, 0, 0);
+          acc[T][C][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Eh, Xl, acc[T][C][0], 0, 0, 0);
+          acc[T][C][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bh, Xl, acc[T][C][1], 0, 0, 0);
+          acc[T][C][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(El, Xh, acc[T][C][0], 0, 0, 0);
+          acc[T][C][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Bl, Xh, acc[T][C][1], 0, 0, 0);
+        }
+      };
+      u32x4 X0[4], X1[4], A[4];
+      load_x(0, X0);
+      for (int k = 0; k < K0; ++k) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          A[0][q] = ap[16 * k + q];
+          A[1][q] = ap[BW + 16 * k + q];
+          A[2][q] = ap[2 * BW + 16 * k + q];
+          A[3][q] = ap[3 * BW + 16 * k + q];
+        }
+        load_x(k + 1, X1);
+        tile(0, A, X0);
+        // realisations of ring r + 1's slab while the products run
+        if (k == 0 && gen1) {
+          gen_t(b ^ 1, lane, in1, 0);
+          gen_t(b ^ 1, lane, in1, 1);
+        }
+        tile(1, A, X1);
+        if (k == 0 && gen1) {
+          gen_t(b ^ 1, lane, in1, 2);
+          gen_t(b ^ 1, lane, in1, 3);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) X0[i] = X1[i];
+      }
     } else if (gen1) {
       gen(b ^ 1, lane, in1);
     }
@@ -597,12 +620,18 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
   }
   __syncthreads();
   float* cst = reinterpret_cast<float*>(smem) + wave * (2 * kNR * kStageRow);  // [2 kNR][kStageRow] of this wave
+  // result register i of lane (t16, qt) in tile (T, C): centre 16 T + 4 qt + i,
+  // realisation 16 C + t16
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int row = 8 * (i / 4) + 4 * half + (i % 4);  // centre
-    cst[col * kStageRow + row] = accE[i] * fnorm[wave][row];         // E of realisation col
-    cst[(kNR + col) * kStageRow + row] = accB[i] * fnorm[wave][row];  // B of realisation col
-  }
+  for (int T = 0; T < 2; ++T)
+#pragma unroll
+    for (int C = 0; C < 2; ++C)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * T + 4 * qt + i, col = 16 * C + t16;
+        cst[col * kStageRow + row] = acc[T][C][0][i] * fnorm[wave][row];         // E of realisation col
+        cst[(kNR + col) * kStageRow + row] = acc[T][C][1][i] * fnorm[wave][row];  // B of realisation col
+      }
   __syncthreads();
   if (active && n.mom) {
     // moments: centre pp sums its realisations of this block; every output
