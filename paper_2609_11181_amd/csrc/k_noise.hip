@@ -471,6 +471,16 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
   for (int i = 0; i < 8; ++i) acc[i / 4][(i / 2) % 2][i % 2] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int t16 = lane & 15;  // MFMA row (A) / column (B) within a 16-tile
   const int qt = lane >> 4;   // k-quarter of the lane (A, B) / row quarter (result)
+  // realisation of column t16 of column tile C: the one whose slab row starts
+  // on bank (mod 32) (t16 mod 4) + 8 (t16 / 4) + 4 C, so that the lanes of
+  // each half-wave (k-quarters 0, 1 or 2, 3, four words apart) read 32
+  // different banks (RS is odd, so rows r RS are distinct mod 32)
+  unsigned rs_inv = (unsigned)RS;  // RS^-1 mod 32 by Newton steps (exact for odd RS)
+#pragma unroll
+  for (int i = 0; i < 3; ++i) rs_inv *= 2u - (unsigned)RS * rs_inv;
+  int rho[2];
+#pragma unroll
+  for (int C = 0; C < 2; ++C) rho[C] = (int)((rs_inv * (unsigned)((t16 & 3) + 8 * (t16 >> 2) + 4 * C)) & 31u);
 
   // prologue: the windows of rings lo .. lo + 3, ring lo's slab and band,
   // ring lo + 1's inputs, ring lo + 2's source indices
@@ -532,19 +542,20 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
       // Step k of tile T covers window pixels 16 (T + k) + 4 qt + q (the lane's
       // k-quarter qt, q < 4), so the coefficient of row t is band word
       // 16 k + 4 qt + q - t for both tiles (Toeplitz), and tile 1's slab
-      // operand of step k is tile 0's of step k + 1. B column: slab row of
-      // realisation 16 C + t (column tile C).
+      // operand of step k is tile 0's of step k + 1. B column t of column
+      // tile C: slab row of realisation rho[C].
       const int base = ws - us;             // slab slot of this wave's first window pixel
       const int K0 = (15 + cnt + 15) / 16;  // steps per tile
       const uint32_t* const ap = band_of(b) + kPadL - t16 + 4 * qt;
-      const uint32_t* const xp = slab_h(b) + t16 * RS + base + 4 * qt;
+      const uint32_t* const xp0 = slab_h(b) + rho[0] * RS + base + 4 * qt;
+      const uint32_t* const xp1 = slab_h(b) + rho[1] * RS + base + 4 * qt;
       auto load_x = [&](int j, u32x4* x) {  // slab operands of window pixels 16 j + ..: C = 0, 1, hi and lo
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          x[0][q] = xp[16 * j + q];
-          x[1][q] = xp[kNR * RS + 16 * j + q];
-          x[2][q] = xp[16 * RS + 16 * j + q];
-          x[3][q] = xp[kNR * RS + 16 * RS + 16 * j + q];
+          x[0][q] = xp0[16 * j + q];
+          x[1][q] = xp0[kNR * RS + 16 * j + q];
+          x[2][q] = xp1[16 * j + q];
+          x[3][q] = xp1[kNR * RS + 16 * j + q];
         }
       };
       auto tile = [&](int T, const u32x4* A, const u32x4* X) {
@@ -621,14 +632,14 @@ __global__ __launch_bounds__(64 * kStack) __attribute__((amdgpu_waves_per_eu(4))
   __syncthreads();
   float* cst = reinterpret_cast<float*>(smem) + wave * (2 * kNR * kStageRow);  // [2 kNR][kStageRow] of this wave
   // result register i of lane (t16, qt) in tile (T, C): centre 16 T + 4 qt + i,
-  // realisation 16 C + t16
+  // realisation rho[C]
 #pragma unroll
   for (int T = 0; T < 2; ++T)
 #pragma unroll
     for (int C = 0; C < 2; ++C)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = 16 * T + 4 * qt + i, col = 16 * C + t16;
+        const int row = 16 * T + 4 * qt + i, col = rho[C];
         cst[col * kStageRow + row] = acc[T][C][0][i] * fnorm[wave][row];         // E of realisation col
         cst[(kNR + col) * kStageRow + row] = acc[T][C][1][i] * fnorm[wave][row];  // B of realisation col
       }
