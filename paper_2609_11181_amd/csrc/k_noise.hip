@@ -9,14 +9,15 @@
 // Batched form. For one scale, with K_pj = q_pj e^{-2 i psi_pj} and
 // X_jr = G_j e^{2 i pi u_rj}:   E_pr + i B_pr = f_p sum_j K_pj X_jr,
 // i.e. in real arithmetic
-//   [E B] = [Qc Qs] [[X1  X2], [X2  -X1]]
-// a sparse aperture operator (outputs x 2 inputs) times a dense realisation
-// matrix (2 inputs x 2 realisations). On a segment of 32 consecutive centres
-// of a belt ring the operator restricted to one source ring is a band
-// (Toeplitz) matrix of that ring's disc coefficients, which the plan's belt
-// table holds. The contraction runs as MFMA 32x32x16 BF16 products with each
-// operand split into two BF16 words (hi + lo) and three products per step
-// (hi.hi + hi.lo + lo.hi), accumulated in FP32: about 2^-16 relative per term.
+//   E = Qc X1 + Qs X2,   B = Qc X2 - Qs X1,
+// a sparse aperture operator (2 outputs x 2 inputs per pair) times a dense
+// realisation matrix. On a segment of 32 consecutive centres of a belt ring
+// the operator restricted to one source ring is a band (Toeplitz) matrix of
+// that ring's disc coefficients, which the plan's belt table holds. The
+// contraction runs as MFMA 16x16x32 BF16 products (two 16-row tiles per
+// segment) with each operand split into two BF16 words (hi + lo) and three
+// products per step (hi.hi + hi.lo + lo.hi), accumulated in FP32: about 2^-16
+// relative per term.
 //
 // A block owns a stack of kStack = 8 segments (the same 32-pixel column of
 // eight consecutive belt rings, one per wave) and 32 realisations. The
