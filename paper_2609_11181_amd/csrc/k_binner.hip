@@ -12,6 +12,7 @@
 // dense range of whole rings.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 #include <math.h>
 
 #include <algorithm>
@@ -23,6 +24,15 @@
 namespace smart {
 
 namespace {
+
+// Radix sort of the (ring pixel, row) pairs: onesweep passes of nine bits
+// (three passes for the 26 key bits of NSIDE 2048, against four of eight
+// bits: 23.4 against 25.1 ms for binning 2.5e8 galaxies on MI355X), ranks
+// by match, 1024-thread blocks of 16 items for the histogram and the sort.
+using SortConfig = rocprim::radix_sort_config<
+    rocprim::default_config, rocprim::default_config,
+    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<1024, 16>, rocprim::kernel_config<1024, 16>, 9,
+                                        rocprim::block_radix_rank_algorithm::match>>;
 
 constexpr double kHalfPi = 1.57079632679489661923;
 
@@ -66,7 +76,7 @@ __global__ void k_keys(int64_t n, const double* ra, const double* dec, const flo
 // is at least q. The pixels up to the first key get 0 and those past the
 // last key get n (k_offsets_ends); every run start k writes its own key and
 // the keys skipped since the previous run (empty pixels inside the
-// footprint, k_offsets_runs).
+// footprint, offsets_run, in the pass that writes the sorted rows).
 __global__ void k_offsets_ends(int64_t n, const uint32_t* skeys, int64_t npix, int64_t* off) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q > npix) return;
@@ -79,11 +89,9 @@ __global__ void k_offsets_ends(int64_t n, const uint32_t* skeys, int64_t npix, i
   }
 }
 
-__global__ void k_offsets_runs(int64_t n, const uint32_t* skeys, int64_t* off) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k == 0 || k >= n) return;
-  const int64_t a = skeys[k - 1], b = skeys[k];
-  for (int64_t q = a + 1; q <= b; ++q) off[q] = k;
+__device__ inline void offsets_run(int64_t k, const uint32_t* skeys, uint32_t key, int64_t* off) {
+  if (k == 0) return;
+  for (int64_t q = (int64_t)skeys[k - 1] + 1; q <= (int64_t)key; ++q) off[q] = k;
 }
 
 // Sorted row k from its catalogue record: unit vector, local frame, shear
@@ -109,8 +117,9 @@ __device__ inline float finish_row(int64_t k, const GalRec& r, uint32_t key, int
 }
 
 // The sorted records: row k is catalogue row sidx[k] (one 32-byte record
-// load), and the largest distance of a galaxy from the centre of its
-// pixel, which bounds the disc search. Grid-stride over a bounded grid, two
+// load), the offset table entries that row k starts, and the largest
+// distance of a galaxy from the centre of its pixel, which bounds the disc
+// search. Grid-stride over a bounded grid, two
 // rows per step (both record loads in flight together): each thread keeps a
 // running maximum, and the block's maximum goes to memory with one atomic
 // (a non-negative float orders like its bit pattern; atomics on one address
@@ -118,7 +127,7 @@ __device__ inline float finish_row(int64_t k, const GalRec& r, uint32_t key, int
 // longer than the whole pass).
 __global__ __launch_bounds__(kBlock) void k_finish(int64_t n, const uint32_t* skeys, const uint32_t* sidx,
                                                    const GalRec* rec, int nside, double4* P, float4* F, float4* G,
-                                                   int64_t* order, unsigned int* max_chord_bits) {
+                                                   int64_t* order, int64_t* off, unsigned int* max_chord_bits) {
   __shared__ float wave_max[kBlock / 64];
   float c = 0.0f;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -126,10 +135,17 @@ __global__ __launch_bounds__(kBlock) void k_finish(int64_t n, const uint32_t* sk
   for (; k + stride < n; k += 2 * stride) {
     const uint32_t i0 = sidx[k], i1 = sidx[k + stride];
     const GalRec r0 = rec[i0], r1 = rec[i1];
-    c = fmaxf(c, finish_row(k, r0, skeys[k], nside, P, F, G, order));
-    c = fmaxf(c, finish_row(k + stride, r1, skeys[k + stride], nside, P, F, G, order));
+    const uint32_t k0 = skeys[k], k1 = skeys[k + stride];
+    c = fmaxf(c, finish_row(k, r0, k0, nside, P, F, G, order));
+    c = fmaxf(c, finish_row(k + stride, r1, k1, nside, P, F, G, order));
+    offsets_run(k, skeys, k0, off);
+    offsets_run(k + stride, skeys, k1, off);
   }
-  if (k < n) c = fmaxf(c, finish_row(k, rec[sidx[k]], skeys[k], nside, P, F, G, order));
+  if (k < n) {
+    const uint32_t k0 = skeys[k];
+    c = fmaxf(c, finish_row(k, rec[sidx[k]], k0, nside, P, F, G, order));
+    offsets_run(k, skeys, k0, off);
+  }
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) c = fmaxf(c, __shfl_xor(c, m, 64));
   if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = c;
@@ -304,20 +320,19 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
     hipLaunchKernelGGL(k_keys, dim3(grid_of(n)), dim3(kBlock), 0, st, n, ra, dec, g1, g2, w, nside, keys, idx, rec,
                        flag);
     size_t tb = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, skeys, idx, sidx, (int)n, 0, nbits, st);
+    (void)rocprim::radix_sort_pairs<SortConfig>(nullptr, tb, keys, skeys, idx, sidx, (size_t)n, 0u, (unsigned)nbits, st);
     if ((rc = ensure_temp(ctx, tb))) return fail(rc);
     tb = ctx->temp_bytes;
-    if (hipcub::DeviceRadixSort::SortPairs(ctx->d_temp, tb, keys, skeys, idx, sidx, (int)n, 0, nbits, st) !=
-        hipSuccess) {
+    if (rocprim::radix_sort_pairs<SortConfig>(ctx->d_temp, tb, keys, skeys, idx, sidx, (size_t)n, 0u, (unsigned)nbits,
+                                              st) != hipSuccess) {
       set_error("radix sort failed");
       return fail(SMART_EDEVICE);
     }
     const int64_t blocks = std::min<int64_t>(grid_of(n), (int64_t)device_cus() * 8);
     hipLaunchKernelGGL(k_finish, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, skeys, sidx, rec, nside, d->P, d->F,
-                       d->G, d->order, mc);
+                       d->G, d->order, d->offsets, mc);
   }
   hipLaunchKernelGGL(k_offsets_ends, dim3(grid_of(npix + 1)), dim3(kBlock), 0, st, n, skeys, npix, d->offsets);
-  if (n > 1) hipLaunchKernelGGL(k_offsets_runs, dim3(grid_of(n)), dim3(kBlock), 0, st, n, skeys, d->offsets);
   if (hipGetLastError() != hipSuccess) {
     set_error("offset kernels failed to launch");
     return fail(SMART_EDEVICE);
