@@ -443,9 +443,10 @@ def batched_leg(ctx, args):
                  "note": "algorithmic 8 flop per (pair, realisation); split-BF16 issues 3 products per term"},
         "binning_ms": bin_ms,
         "binning_first_call_ms": bin_cold_ms,
-        "binning_gb_per_s": (n_gal * (28 + 72) + 12 * 2048 ** 2 * 8) / (bin_ms / 1e3) / 1e9,
-        "binning_note": "algorithmic bytes: 28 read + 72 written per galaxy (sorted unit vector, frame, shear, "
-                        "catalogue order) + 8 per pixel of the offset table, over the time of a second "
+        "binning_gb_per_s": (n_gal * (28 + 56) + 12 * 2048 ** 2 * 8) / (bin_ms / 1e3) / 1e9,
+        "binning_note": "algorithmic bytes: 28 read + 56 written per galaxy (sorted unit vector with right "
+                        "ascension, shear and weight, catalogue order) + 8 per pixel of the offset table, over "
+                        "the time of a second "
                         "smart_bin_galaxies call (device blocks from the library's cache; the first call, which "
                         "allocates them, is binning_first_call_ms, host clock)",
         "barycentre": barycentre,

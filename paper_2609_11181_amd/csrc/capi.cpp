@@ -235,7 +235,7 @@ void smart_data_free(smart_data d) {
   if (d->ctx) hipSetDevice(d->ctx->device);
   // the blocks go back to the library's cache: no work may still use them
   (void)hipDeviceSynchronize();
-  for (void* q : {(void*)d->P, (void*)d->F, (void*)d->G, (void*)d->order, (void*)d->offsets, (void*)d->sums,
+  for (void* q : {(void*)d->P, (void*)d->G, (void*)d->order, (void*)d->offsets, (void*)d->sums,
                   (void*)d->wd, (void*)d->wn, (void*)d->cidx, (void*)d->src_pix, (void*)d->avg, (void*)d->gavg})
     smart::dev_release(q);
   delete d;
@@ -496,7 +496,6 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.n_out = p->n_out;
       a.nside_out = p->nside_out;
       a.P = d->P;
-      a.F = d->F;
       a.G = d->G;
       a.offsets = d->offsets;
       a.nside_bin = d->nside;
@@ -789,8 +788,7 @@ int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int nor
         a.n_out = p->n_out;
         a.nside_out = p->nside_out;
         a.P = d->P;
-        a.F = d->F;
-        a.G = p->rot_gal;
+          a.G = p->rot_gal;
         a.offsets = d->offsets;
         a.nside_bin = d->nside;
         a.r_bin = d->r_bin;

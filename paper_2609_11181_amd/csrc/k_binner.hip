@@ -94,17 +94,17 @@ __device__ inline void offsets_run(int64_t k, const uint32_t* skeys, uint32_t ke
   for (int64_t q = (int64_t)skeys[k - 1] + 1; q <= (int64_t)key; ++q) off[q] = k;
 }
 
-// Sorted row k from its catalogue record: unit vector, local frame, shear
-// and weight, catalogue index; returns the distance of the galaxy from the
-// centre of its pixel.
-__device__ inline float finish_row(int64_t k, const GalRec& r, uint32_t key, int nside, double4* P, float4* F,
-                                   float4* G, int64_t* order) {
+// Sorted row k from its catalogue record: unit vector and right ascension
+// (which gives the local frame of a galaxy on a pole), shear and weight,
+// catalogue index; returns the distance of the galaxy from the centre of
+// its pixel.
+__device__ inline float finish_row(int64_t k, const GalRec& r, uint32_t key, int nside, double4* P, float4* G,
+                                   int64_t* order) {
   double sa, ca, sd, cd;
   sincos(r.ra, &sa, &ca);
   sincos(r.dec, &sd, &cd);
   const double x = cd * ca, y = cd * sa, z = sd;
-  P[k] = make_double4(x, y, z, 0.0);
-  F[k] = make_float4((float)ca, (float)sa, (float)sd, (float)cd);
+  P[k] = make_double4(x, y, z, r.ra);
   G[k] = make_float4(r.g1, r.g2, r.w, 0.0f);
   order[k] = (int64_t)r.i;
   int rr, jj;
@@ -126,7 +126,7 @@ __device__ inline float finish_row(int64_t k, const GalRec& r, uint32_t key, int
 // are serialised, so one per wave of a catalogue-sized grid would take
 // longer than the whole pass).
 __global__ __launch_bounds__(kBlock) void k_finish(int64_t n, const uint32_t* skeys, const uint32_t* sidx,
-                                                   const GalRec* rec, int nside, double4* P, float4* F, float4* G,
+                                                   const GalRec* rec, int nside, double4* P, float4* G,
                                                    int64_t* order, int64_t* off, unsigned int* max_chord_bits) {
   __shared__ float wave_max[kBlock / 64];
   float c = 0.0f;
@@ -136,14 +136,14 @@ __global__ __launch_bounds__(kBlock) void k_finish(int64_t n, const uint32_t* sk
     const uint32_t i0 = sidx[k], i1 = sidx[k + stride];
     const GalRec r0 = rec[i0], r1 = rec[i1];
     const uint32_t k0 = skeys[k], k1 = skeys[k + stride];
-    c = fmaxf(c, finish_row(k, r0, k0, nside, P, F, G, order));
-    c = fmaxf(c, finish_row(k + stride, r1, k1, nside, P, F, G, order));
+    c = fmaxf(c, finish_row(k, r0, k0, nside, P, G, order));
+    c = fmaxf(c, finish_row(k + stride, r1, k1, nside, P, G, order));
     offsets_run(k, skeys, k0, off);
     offsets_run(k + stride, skeys, k1, off);
   }
   if (k < n) {
     const uint32_t k0 = skeys[k];
-    c = fmaxf(c, finish_row(k, rec[sidx[k]], k0, nside, P, F, G, order));
+    c = fmaxf(c, finish_row(k, rec[sidx[k]], k0, nside, P, G, order));
     offsets_run(k, skeys, k0, off);
   }
 #pragma unroll
@@ -301,7 +301,7 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
   if ((rc = dmalloc(&keys, n)) || (rc = dmalloc(&idx, n)) || (rc = dmalloc(&skeys, n)) || (rc = dmalloc(&sidx, n)) ||
       (rc = dmalloc(&rec, n)) ||
       (rc = dmalloc(&flag, 1)) || (rc = dmalloc(&mc, 1)) ||
-      (rc = dmalloc(&d->P, n)) || (rc = dmalloc(&d->F, n)) || (rc = dmalloc(&d->G, n)) ||
+      (rc = dmalloc(&d->P, n)) || (rc = dmalloc(&d->G, n)) ||
       (rc = dmalloc(&d->order, n)) || (rc = dmalloc(&d->offsets, npix + 1))) {
     cleanup();
     return rc;
@@ -329,8 +329,8 @@ int bin_galaxies(smart_ctx ctx, int64_t n, const double* ra, const double* dec, 
       return fail(SMART_EDEVICE);
     }
     const int64_t blocks = std::min<int64_t>(grid_of(n), (int64_t)device_cus() * 8);
-    hipLaunchKernelGGL(k_finish, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, skeys, sidx, rec, nside, d->P, d->F,
-                       d->G, d->order, d->offsets, mc);
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, skeys, sidx, rec, nside, d->P, d->G,
+                       d->order, d->offsets, mc);
   }
   hipLaunchKernelGGL(k_offsets_ends, dim3(grid_of(npix + 1)), dim3(kBlock), 0, st, n, skeys, npix, d->offsets);
   if (hipGetLastError() != hipSuccess) {

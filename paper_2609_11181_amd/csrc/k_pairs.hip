@@ -250,10 +250,11 @@ __device__ __forceinline__ void galaxy_pair(const GalaxyArgs& a, const ScaleArgs
   //   X = x dy - y dx,  Y = (x^2 + y^2) dz - z (x dx + y dy)
   double X = P.x * dy - P.y * dx;
   double Y = fma(P.x, P.x, P.y * P.y) * dz - P.z * fma(P.x, dx, P.y * dy);
-  if (P.x == 0.0 && P.y == 0.0) {  // galaxy on a pole: frame from its ra
-    const float4 F = a.F[g];
-    X = dy * F.x - dx * F.y;
-    Y = -P.z * (dx * F.x + dy * F.y);
+  if (P.x == 0.0 && P.y == 0.0) {  // galaxy on a pole: frame from its ra (P.w)
+    double sa, ca;
+    sincos(P.w, &sa, &ca);
+    X = dy * ca - dx * sa;
+    Y = -P.z * (dx * ca + dy * sa);
   }
   const double D = fma(X, X, Y * Y);
   const double i0 = (double)__builtin_amdgcn_rcpf((float)D);
@@ -598,10 +599,8 @@ __global__ __launch_bounds__(kBlock) void k_galaxy_f64(GalaxyArgs a, ScaleArgs s
           if (cd > 0.0) {
             ca = P.x / cd;
             sa = P.y / cd;
-          } else {
-            const float4 F = a.F[g];
-            ca = F.x;
-            sa = F.y;
+          } else {  // galaxy on a pole: frame from its ra (P.w)
+            sincos(P.w, &sa, &ca);
           }
           const double xt = -dx * sa + dy * ca;
           const double yt = dz * cd - P.z * (dx * ca + dy * sa);

@@ -86,8 +86,7 @@ struct smart_data_s {
   int nside = 0;
   int64_t n_gal = 0;
   // galaxy partition (sorted rows)
-  double4* P = nullptr;   // unit vector (x, y, z, 0)
-  float4* F = nullptr;    // (cos ra, sin ra, sin dec, cos dec)
+  double4* P = nullptr;   // unit vector and right ascension (x, y, z, ra)
   float4* G = nullptr;    // (g1, g2, w, 0)
   int64_t* order = nullptr;
   int64_t* offsets = nullptr;  // 12 nside^2 + 1
@@ -225,7 +224,6 @@ struct GalaxyArgs {
   int64_t n_out;
   int nside_out;
   const double4* P;
-  const float4* F;
   const float4* G;
   const int64_t* offsets;
   int nside_bin;

@@ -129,7 +129,6 @@ GalaxyArgs galaxy_args(smart_plan p, void* out) {
   a.n_out = p->n_out;
   a.nside_out = p->nside_out;
   a.P = d->P;
-  a.F = d->F;
   a.G = d->G;
   a.offsets = d->offsets;
   a.nside_bin = d->nside;
