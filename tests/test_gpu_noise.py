@@ -152,3 +152,37 @@ def test_seeded_maps_and_moments(ctx, prec):
         for e, key in enumerate(["M_E", "M_B"]):
             rms = math.sqrt(np.mean(ref[key][ok] ** 2))
             assert np.max(np.abs(out[k, 1, e][ok] - ref[key][ok])) / rms <= tol, (k, key)
+
+
+def test_noise_stack_wide_discs(ctx):
+    """Discs whose union windows hold more than 64 slots (the slab slots past
+    the first 64 lanes) and that span more than 64 rings (belt windows read
+    from the table instead of registers): NSIDE 512 at 3 and 4.5 degrees,
+    eight consecutive belt rings of outputs, BF16x3 against the oracle."""
+    from paper_2609_11181_amd import lib as L
+
+    _, m, data, inf, _, u, u_dev = _setup(ctx, n_real=40, seed=11)
+    nside = m["nside"]
+    ra, dec = hp.pix2radec(nside, m["pix"])
+    ra = np.where(ra > math.pi, ra - 2 * math.pi, ra)
+    # the equator ring and the seven above it, 1.5 degrees either side of ra = 0
+    sel = (np.abs(ra) < 1.5 * DEG) & (dec >= -0.01 * DEG) & (dec < 0.56 * DEG)
+    out_pix = np.sort(m["pix"][sel])
+    assert 100 < out_pix.size < 600, out_pix.size
+    ths = [3 * DEG, 4.5 * DEG]
+    kinds = [F.TANH, F.POLY]
+    plan = ctx.plan(data, L.VAR_PIXEL, nside, out_pix, ths, [ctx.filter(k) for k in kinds])
+    out = plan.noise_batch(u_dev, u.shape[0], L.NORM_SUMMED_PIXCOUNT, 2).cpu().numpy()
+    assert np.isfinite(out).all()
+    # the outputs went through the BF16x3 stacks (split-BF16 rounding visible
+    # against the plain FP32 path), not only through the per-output walk
+    plain = plan.noise_batch(u_dev, u.shape[0], L.NORM_SUMMED_PIXCOUNT, 1).cpu().numpy()
+    assert np.max(np.abs(out - plain)) > 1e-7 * np.max(np.abs(plain))
+    for k, (th, kind) in enumerate(zip(ths, kinds)):
+        for r in (0, 33, 39):
+            ref = _oracle_real(m, inf, u[r], out_pix, th, kind)
+            ok = ~ref["tie"]
+            for e, key in enumerate(["M_E", "M_B"]):
+                rms = math.sqrt(np.mean(ref[key][ok] ** 2))
+                err = np.max(np.abs(out[k, r, e][ok] - ref[key][ok])) / rms
+                assert err <= 1e-4, (k, r, key, err)
