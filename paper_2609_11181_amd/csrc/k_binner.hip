@@ -95,8 +95,8 @@ __device__ inline void offsets_run(int64_t k, const uint32_t* skeys, uint32_t ke
 }
 
 // Sorted row k from its catalogue record: unit vector and right ascension
-// (which gives the local frame of a galaxy on a pole), shear and weight,
-// catalogue index; returns the distance of the galaxy from the centre of
+// (which gives the local frame of a galaxy on a pole), shear, weight and
+// the variance term w^2 |g|^2, catalogue index; returns the distance of the galaxy from the centre of
 // its pixel.
 __device__ inline float finish_row(int64_t k, const GalRec& r, uint32_t key, int nside, double4* P, float4* G,
                                    int64_t* order) {
@@ -105,7 +105,7 @@ __device__ inline float finish_row(int64_t k, const GalRec& r, uint32_t key, int
   sincos(r.dec, &sd, &cd);
   const double x = cd * ca, y = cd * sa, z = sd;
   P[k] = make_double4(x, y, z, r.ra);
-  G[k] = make_float4(r.g1, r.g2, r.w, 0.0f);
+  G[k] = make_float4(r.g1, r.g2, r.w, r.w * r.w * fmaf(r.g1, r.g1, r.g2 * r.g2));  // V = w^2 |g|^2
   order[k] = (int64_t)r.i;
   int rr, jj;
   pixel_ring(nside, (int64_t)key, &rr, &jj);

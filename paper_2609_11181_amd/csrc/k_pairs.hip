@@ -271,7 +271,7 @@ __device__ __forceinline__ void galaxy_pair(const GalaxyArgs& a, const ScaleArgs
   const double q = inside ? filter_q<TABLE>(theta_ratio<BIG>(cd, c2, cp), tab) : 0.0;
   const float w = G.z;
   double wd = (double)w;
-  float v = a.explicit_v ? G.w : w * w * fmaf(G.x, G.x, G.y * G.y);
+  float v = G.w;  // w^2 |g|^2 from binning (or the explicit V of barycentre data)
   if (a.cavg) {  // averaged approach: the galaxy divided by its pixel's density
     const float c = a.cavg[g];
     wd *= (double)c;

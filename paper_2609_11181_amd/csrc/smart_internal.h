@@ -87,7 +87,7 @@ struct smart_data_s {
   int64_t n_gal = 0;
   // galaxy partition (sorted rows)
   double4* P = nullptr;   // unit vector and right ascension (x, y, z, ra)
-  float4* G = nullptr;    // (g1, g2, w, 0)
+  float4* G = nullptr;    // (g1, g2, w, V): V = w^2 |g|^2, or the explicit V of barycentre data
   int64_t* order = nullptr;
   int64_t* offsets = nullptr;  // 12 nside^2 + 1
   double r_bin = 0.0;
@@ -101,7 +101,7 @@ struct smart_data_s {
   float4* avg = nullptr;
   // barycentre data (sphS_pixB): each "galaxy" is an occupied pixel of a
   // catalogue at its galaxies' barycentre, with G = (G1/W, G2/W, W, E2):
-  // the pair kernels take V from G.w instead of w^2 |g|^2
+  // V is its E2 instead of w^2 |g|^2
   bool explicit_v = false;
   // averaged approach on galaxy sources: per sorted row the factor
   // Omega_pix / W of its binning pixel (the row's own W for barycentre
