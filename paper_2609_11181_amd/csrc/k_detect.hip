@@ -16,7 +16,10 @@
 // a corner is the common edge neighbour, other than the pixel itself, of
 // the two edge neighbours beside that corner; if those two share an edge,
 // only three pixels meet there (the 24 pixels at the eight corners where
-// three faces meet have seven neighbours).
+// three faces meet have seven neighbours). A cell away from its face's
+// border has all eight neighbours in its own face, the cells at (alpha +- 1,
+// beta +- 1), which integer arithmetic finds (cell_pixel); only the cells on
+// a face border take the chart probes.
 //
 // A pixel with a neighbour that is not in the map is not a detection, and
 // "higher" is strict.
@@ -91,6 +94,31 @@ __device__ inline int64_t chart_pixel(int nside, int f, double al, double be) {
   return pixel_of(nside, z, omz, tt * (0.5 * 3.141592653589793238462643383279502884));
 }
 
+// RING pixel of cell (a, b) of face f, 0 <= a, b < N: the integer form of
+// chart_pixel at the cell's centre (the inverse of pixel_cell). North cap
+// cells lie on ring a + b + 1 at position g i + a of the ring; south cap
+// cells on ring 4N - k, k = 2N - 1 - a - b, at position g k + N - 1 - b; belt
+// cells have edge-line indices j_p = a + off_p and j_m = off_m - b - 1, so
+// their ring is 2N - (j_m - j_p) and their position j_p - (i - N) / 2
+// (mod 4N).
+__device__ inline int64_t cell_pixel(int nside, int f, int a, int b) {
+  const int64_t N = nside;
+  const int g = f & 3, row = f >> 2;
+  if (row == 0 && a + b + 1 < nside) {
+    const int64_t i = a + b + 1;
+    return 2 * i * (i - 1) + g * i + a;
+  }
+  if (row == 2 && a + b >= nside) {
+    const int64_t k = 2 * N - 1 - a - b;
+    return 12 * N * N - 2 * k * (k + 1) + g * k + (N - 1 - b);
+  }
+  const int64_t off_p = (row == 2 ? g + 1 : g) * N, off_m = (row == 0 ? g + 2 : g + 1) * N;
+  const int64_t jp = a + off_p, jm = off_m - b - 1;
+  const int64_t i = 2 * N - (jm - jp);
+  const int64_t j = (jp - ((i - N) >> 1)) & (4 * N - 1);  // 4N is a power of two
+  return 2 * N * (N - 1) + 4 * N * (i - N) + j;
+}
+
 // Pixels across the four edges (alpha-, beta-, alpha+, beta+).
 __device__ inline void edge_neighbours(int nside, int64_t p, int64_t e[4]) {
   int f, a, b;
@@ -130,6 +158,16 @@ __global__ void k_detect(int nside, const int64_t* pix, const double* val, const
     ok = ok && sd > 0.0 && v / sd >= threshold;
   } else {
     ok = ok && v >= threshold;
+  }
+  int f, ca, cb;
+  pixel_cell(nside, p, &f, &ca, &cb);
+  if (ok && ca > 0 && cb > 0 && ca < nside - 1 && cb < nside - 1) {
+    // inside its face: the eight neighbours are the cells around it
+    for (int da = -1; da <= 1 && ok; ++da)
+      for (int db = -1; db <= 1 && ok; ++db)
+        if (da != 0 || db != 0) ok = v > map_value(dense, d0, dn, cell_pixel(nside, f, ca + da, cb + db));
+    flags[i] = ok;
+    return;
   }
   int64_t e[4];
   if (ok) {
