@@ -357,6 +357,7 @@ void smart_plan_free(smart_plan p) {
   // the blocks go back to the library's cache: no work may still use them
   (void)hipDeviceSynchronize();
   smart::dev_release(p->out_pix);
+  smart::dev_release(p->gal_order);
   smart::dev_release(p->d_pairs);
   smart::dev_release(p->d_work);
   smart::dev_release(p->rot_map);
@@ -441,7 +442,8 @@ int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out
     if (e != hipSuccess) return bail(SMART_EDEVICE, std::string("plan validation failed: ") + hipGetErrorString(e));
     if (h & 1) return bail(SMART_EINVAL, "output pixel out of range for nside_out");
   }
-  if (variant == SMART_VAR_GALAXY && precision == SMART_PREC_FP32_GEO64 && (rc = smart::choose_galaxy_forms(p, st))) {
+  if (variant == SMART_VAR_GALAXY && precision == SMART_PREC_FP32_GEO64 &&
+      ((rc = smart::choose_galaxy_forms(p, st)) || (rc = smart::build_gal_order(p, st)))) {
     smart_plan_free(p);
     return rc;
   }
@@ -507,6 +509,7 @@ int smart_run(smart_plan p, int norm, void* d_out, void* stream) {
       a.explicit_v = d->explicit_v ? 1 : 0;
       a.posb = p->posb ? 1 : 0;
       a.cavg = norm == SMART_NORM_AVERAGED ? d->gavg : nullptr;
+      a.order = p->gal_order;
       e = launch_galaxy(a, s, p->precision, p->gal_form.empty() ? kGalWave : p->gal_form[k], st);
     }
     if (e != hipSuccess) return fail(SMART_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -798,6 +801,7 @@ int smart_noise_galaxy_batch(smart_plan p, const float* d_u, int n_real, int nor
         a.explicit_v = d->explicit_v ? 1 : 0;
         a.posb = p->posb ? 1 : 0;
         a.cavg = norm == SMART_NORM_AVERAGED ? d->gavg : nullptr;
+        a.order = p->gal_order;
         e = launch_galaxy(a, s, p->precision, p->gal_form[k], st);
       }
       if (e == hipSuccess)

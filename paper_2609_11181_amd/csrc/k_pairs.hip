@@ -25,6 +25,7 @@
 // N; FP32 terms are accumulated per ring slice and flushed to FP64 totals.
 // The epilogue applies the summed normalisation (Sect. 2.4).
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 #include <math.h>
 
 #include "hpx_ring.h"
@@ -452,7 +453,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_galaxy_f32(GalaxyArgs a, ScaleArg
   const double Cw = posb ? s.C_ap : 4.0 * sh * sh;
   int* const row = sl_row[wv];
   int* const pre = sl_pre[wv];
-  for (int64_t o = o_begin + wid; o < o_end; o += waves_x) {
+  for (int64_t k = o_begin + wid; k < o_end; k += waves_x) {
+    const int64_t o = a.order ? (int64_t)a.order[k] : k;
     const GalCentre c = gal_centre(a, o, rad);
     Acc64 tot;
     Acc32 acc;
@@ -636,7 +638,71 @@ __global__ void k_sum_n(const void* out, int is_double, int64_t n_out, int n_sca
   if (threadIdx.x == 0) atomicAdd(acc, part[0]);
 }
 
+// Tile key of each output centre for the wave form's visiting order: tiles
+// of kOrderTile rings by kOrderTile azimuth units, an azimuth unit being one
+// pixel step of the equatorial rings (the index on a ring scaled to 4 nside
+// pixels), so that a tile is a compact patch at every latitude; key = ring
+// tile x (tiles per ring + 1) + azimuth tile.
+constexpr int kOrderTile = 16;
+__global__ void k_order_keys(const int64_t* out_pix, int64_t n_out, int nside, uint32_t* keys, int* pos) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_out) return;
+  int rp, ip;
+  pixel_ring(nside, out_pix[o], &rp, &ip);
+  const int n = ring_info(nside, rp).n;
+  const int64_t col = (int64_t)ip * (4 * (int64_t)nside) / n;
+  const uint32_t per_ring = (uint32_t)(4 * nside / kOrderTile + 1);
+  keys[o] = (uint32_t)(rp / kOrderTile) * per_ring + (uint32_t)(col / kOrderTile);
+  pos[o] = (int)o;
+}
+
 }  // namespace
+
+// The wave form keeps its persistent waves on a contiguous stretch of the
+// visiting order per XCD; in list (ring) order the few hundred centres in
+// flight on one XCD form a strip along a ring whose discs hold more rows than
+// the XCD's L2. Visiting the centres tile by tile (a stable sort of the list
+// positions by tile key; list order within a tile) keeps the discs in flight
+// overlapping. Each centre's sums are unchanged: only the schedule differs.
+int build_gal_order(smart_plan p, hipStream_t st) {
+  if (p->n_out == 0 || p->n_out >= (int64_t)1 << 31) return SMART_OK;
+  const int n = (int)p->n_out;
+  uint32_t *keys = nullptr, *skeys = nullptr;
+  int* pos = nullptr;
+  if (dev_alloc(&p->gal_order, sizeof(int) * (size_t)n) != hipSuccess ||
+      scratch_alloc(&keys, sizeof(uint32_t) * (size_t)n, st) != hipSuccess ||
+      scratch_alloc(&skeys, sizeof(uint32_t) * (size_t)n, st) != hipSuccess ||
+      scratch_alloc(&pos, sizeof(int) * (size_t)n, st) != hipSuccess) {
+    scratch_free(keys, st);
+    scratch_free(skeys, st);
+    scratch_free(pos, st);
+    set_error("allocation failed for the galaxy plan's visiting order");
+    return SMART_ENOMEM;
+  }
+  const uint32_t max_key = (uint32_t)(4 * p->nside_out / kOrderTile) * (uint32_t)(4 * p->nside_out / kOrderTile + 1) +
+                           (uint32_t)(4 * p->nside_out / kOrderTile);
+  int bits = 1;
+  while (bits < 32 && (max_key >> bits) != 0) ++bits;
+  hipLaunchKernelGGL(k_order_keys, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, p->out_pix,
+                     p->n_out, p->nside_out, keys, pos);
+  hipError_t e = hipGetLastError();
+  size_t tb = 0;
+  int rc = SMART_OK;
+  if (e == hipSuccess) e = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, skeys, pos, p->gal_order, n, 0, bits, st);
+  if (e == hipSuccess && (rc = ensure_temp(p->ctx, tb)) == SMART_OK) {
+    tb = p->ctx->temp_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(p->ctx->d_temp, tb, keys, skeys, pos, p->gal_order, n, 0, bits, st);
+  }
+  scratch_free(keys, st);
+  scratch_free(skeys, st);
+  scratch_free(pos, st);
+  if (rc != SMART_OK) return rc;
+  if (e != hipSuccess) {
+    set_error(std::string("visiting order of the galaxy plan failed: ") + hipGetErrorString(e));
+    return SMART_EDEVICE;
+  }
+  return SMART_OK;
+}
 
 static int64_t blocks_for(int64_t n) { return (n + kBlock - 1) / kBlock; }
 

@@ -131,6 +131,10 @@ struct smart_plan_s {
   int nside_out = 0;
   int64_t n_out = 0;
   int64_t* out_pix = nullptr;
+  // galaxy FP32 plans: the list positions in the wave form's visiting order
+  // (compact tiles of centres, so that the discs of the centres in flight on
+  // one XCD share its L2), or null
+  int* gal_order = nullptr;
   std::vector<double> theta_ap;
   std::vector<int> filter_ids;
   // last run, for smart_last_pairs
@@ -235,6 +239,7 @@ struct GalaxyArgs {
   int explicit_v;  // V of a source is G.w (barycentre data)
   int posb;        // membership by the binning pixel's centre (sphS_posB)
   const float* cavg;  // averaged approach: per-row density factor (shear terms x c, V x c^2), or null
+  const int* order;   // wave form: list position of the k-th centre visited (tile order), or null (list order)
 };
 
 // Belt tables of one scale (built by k_belt.hip): for every belt ring that
@@ -331,6 +336,9 @@ constexpr int kGalLane = SMART_GAL_LANE, kGalWave = SMART_GAL_WAVE;
 // or more (smart_autotune measures the choice)
 constexpr double kGalWaveMinRows = 256.0, kGalWaveMinRun = 48.0;
 hipError_t launch_galaxy(const GalaxyArgs& a, const ScaleArgs& s, int precision, int form, hipStream_t st);
+// the wave form's visiting order of a galaxy plan's centres into p->gal_order
+// (allocated here; n_out < 2^31)
+int build_gal_order(smart_plan p, hipStream_t st);
 hipError_t launch_gal_candidates(const GalaxyArgs& a, double theta_ap, double C_ap, int n_samp, int64_t* cand,
                                  hipStream_t st);
 hipError_t launch_sum_n(const void* out, int precision, int64_t n_out, int n_scales, double* d_acc,

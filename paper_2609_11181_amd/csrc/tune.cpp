@@ -140,6 +140,7 @@ GalaxyArgs galaxy_args(smart_plan p, void* out) {
   a.explicit_v = d->explicit_v ? 1 : 0;
   a.posb = p->posb ? 1 : 0;
   a.cavg = nullptr;
+  a.order = p->gal_order;
   return a;
 }
 
