@@ -172,6 +172,10 @@ __global__ __launch_bounds__(kBlock) void k_sums(int64_t n_dense, int64_t pix_fi
   const int sub = (int)(t % kSumLanes);
   if (p >= n_dense) return;  // whole groups leave together (kBlock is a multiple of kSumLanes)
   const int64_t a = off[pix_first + p], b = off[pix_first + p + 1];
+  if (a == b) {  // empty pixel (most of the dense ring range): its group leaves together
+    if (sub == 0) sums[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
   double W = 0, G1 = 0, G2 = 0, E2 = 0;
   for (int64_t k = a + sub; k < b; k += kSumLanes) {
     float4 g = G[k];
