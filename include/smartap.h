@@ -286,7 +286,12 @@ void smart_data_free(smart_data data);
  * other tiles are general. This costs one more synchronisation per scale
  * and device memory of about (number of belt rings) x (pixels per disc) x
  * 20 bytes per scale; the tables are filled asynchronously on `stream`, so
- * the plan is used on `stream` (or after synchronising it). Table filters
+ * the plan is used on `stream` (or after synchronising it). Galaxy-variant
+ * FP32 plans get the visiting order of their centres for the wave form of
+ * the galaxy kernel (tiles of 16 rings x 16 azimuth units, so that the
+ * discs in flight on one XCD share its L2; 4 bytes of device memory per
+ * output; complete on return; lists of 2^31 outputs or more keep list
+ * order). Table filters
  * also get a 48 KB table in sin(theta) per (filter, aperture), built on the
  * host at its first use and kept by the context. */
 int smart_plan_create(smart_ctx ctx, smart_data data, int variant, int nside_out, int64_t n_out,

@@ -697,6 +697,8 @@ int build_gal_order(smart_plan p, hipStream_t st) {
   scratch_free(skeys, st);
   scratch_free(pos, st);
   if (rc != SMART_OK) return rc;
+  // the plan may be run on another stream: the order is complete on return
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     set_error(std::string("visiting order of the galaxy plan failed: ") + hipGetErrorString(e));
     return SMART_EDEVICE;

@@ -161,3 +161,36 @@ def _centres_near(no, anchor, rad, n, seed):
     if pix.size > n:
         pix = np.sort(np.random.default_rng(seed).choice(pix, n, replace=False))
     return pix
+
+
+def test_visiting_order_covers_every_output(ctx):
+    """The wave form visits a plan's centres in tiles of rings and azimuth
+    (an order built at plan creation); every output is written once with the
+    sums of its own centre. Whole maps, bit for bit: a shuffled output list
+    (with a repeated pixel) gives the sorted list's values at the permuted
+    positions, for both forms, over more centres than one tile row holds."""
+    import torch
+    from paper_2609_11181_amd import lib as L
+
+    cat = small_catalogue(100000, seed=7, cap_radius=4 * DEG, centre=(0.0, 0.0))
+    data = ctx.bin_galaxies(cat["ra"], cat["dec"], cat["g1"], cat["g2"], cat["w"], nside_bin=512)
+    v = hp.pix2vec(256, np.arange(hp.npix(256)))
+    pix = np.nonzero(v[:, 0] > math.cos(3.5 * DEG))[0]  # about 2000 centres over many tiles
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(pix.size)
+    shuffled = np.concatenate([pix[perm], pix[perm[:1]]])
+    th = 20 * ARCMIN
+    fid = ctx.filter(F.TANH)
+    a = ctx.plan(data, L.VAR_GALAXY, 256, pix, [th], [fid])
+    b = ctx.plan(data, L.VAR_GALAXY, 256, shuffled, [th], [fid])
+    for form in (L.GAL_WAVE, L.GAL_LANE):
+        a.set_galaxy_form(0, form)
+        b.set_galaxy_form(0, form)
+        oa = a.run(L.NORM_SUMMED_CAP)
+        ob = b.run(L.NORM_SUMMED_CAP)
+        torch.cuda.synchronize()
+        oa = oa.cpu().numpy()[0]
+        ob = ob.cpu().numpy()[0]
+        assert np.array_equal(ob[:, : pix.size], oa[:, perm]), form
+        assert np.array_equal(ob[:, pix.size], oa[:, perm[0]]), form
+        assert np.all(oa[4] > 0), form
