@@ -145,12 +145,12 @@ int smart_init(int hip_device, smart_ctx* out) {
 
 void smart_finalize(smart_ctx ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   for (auto& f : ctx->filters) {
-    hipFree(f.d_table);
-    hipFree(f.d_table_c0);
+    (void)hipFree(f.d_table);
+    (void)hipFree(f.d_table_c0);
   }
-  if (ctx->d_temp) hipFree(ctx->d_temp);
+  if (ctx->d_temp) (void)hipFree(ctx->d_temp);
   (void)hipDeviceSynchronize();
   for (auto& kv : ctx->sin_pieces) smart::dev_release(kv.second);
   smart::dev_trim(ctx->device);  // cached handle blocks go back to HIP
@@ -232,7 +232,7 @@ int smart_filter_pieces(smart_ctx ctx, int filter_id, double theta_ap, double* h
 
 void smart_data_free(smart_data d) {
   if (!d) return;
-  if (d->ctx) hipSetDevice(d->ctx->device);
+  if (d->ctx) (void)hipSetDevice(d->ctx->device);
   // the blocks go back to the library's cache: no work may still use them
   (void)hipDeviceSynchronize();
   for (void* q : {(void*)d->P, (void*)d->G, (void*)d->order, (void*)d->offsets, (void*)d->sums,
@@ -353,7 +353,7 @@ int smart_data_export(smart_data d, int64_t* d_order, int64_t* d_offsets, float*
 
 void smart_plan_free(smart_plan p) {
   if (!p) return;
-  if (p->ctx) hipSetDevice(p->ctx->device);
+  if (p->ctx) (void)hipSetDevice(p->ctx->device);
   // the blocks go back to the library's cache: no work may still use them
   (void)hipDeviceSynchronize();
   smart::dev_release(p->out_pix);

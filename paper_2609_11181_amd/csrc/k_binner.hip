@@ -275,7 +275,9 @@ int ring_range(int nside, int64_t pmin, int64_t pmax, smart_data d) {
 
 int ensure_temp(smart_ctx ctx, size_t bytes) {
   if (bytes <= ctx->temp_bytes) return SMART_OK;
-  if (ctx->d_temp) hipFree(ctx->d_temp);
+  // hipFree waits for the device's outstanding work, including earlier sorts
+  // that used this workspace
+  if (ctx->d_temp) (void)hipFree(ctx->d_temp);
   ctx->d_temp = nullptr;
   ctx->temp_bytes = 0;
   if (hipMalloc(&ctx->d_temp, bytes) != hipSuccess) {
