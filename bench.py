@@ -62,6 +62,16 @@ def belt_pairs_of(plan, n_out_ch, scale=0):
 # which names the source version it was measured on); valid for that kernel version and workload only
 TRAFFIC_BYTES = {"k_pixel_f32 (20 arcmin)": 1.689e10}
 TRAFFIC_SOURCE = "profiles/pixel_kernels_nside4096_15000deg2_3scales.md"
+# counter-measured utilisation of the same kernel versions (rocprofv3 SQ counters of the committed profiles,
+# which name the source version): VALU issue share = SQ_INSTS_VALU / (duration x 256 CU x 2.4 GHz); MFMA busy =
+# SQ_VALU_MFMA_BUSY_CYCLES / (4 x CU-cycles). Valid for those kernel versions and workloads only.
+COUNTERS = {
+    "k_pixel_f32 (20 arcmin)": {"valu_issue_share": 0.88, "source": TRAFFIC_SOURCE},
+    "k_galaxy_f32": {"valu_issue_share": 0.66, "fetch_bytes": 4.4e10,
+                     "source": "profiles/galaxy_kernel_5e7gal_1000deg2_nside2048_10arcmin.md"},
+    "k_noise_stack": {"mfma_busy_5_10_20_arcmin": [0.21, 0.31, 0.37], "valu_per_mfma_5_10_20_arcmin": [10.8, 7.6, 6.2],
+                      "source": "profiles/noise_stack_nside2048_5000deg2_256real.md"},
+}
 
 
 def parse():
@@ -228,7 +238,7 @@ def config2_leg(ctx, args):
     res.update({"run_ms": ms, "pairs": pairs, "pair_evals_per_s": pairs / (ms / 1e3),
                 "roofline": {"bound": "alu", "kernel": "k_galaxy_f32", "achieved": achieved / 1e12,
                              "peak": ALU_PEAK / 1e12, "unit": "Tlane-op/s", "frac": achieved / ALU_PEAK,
-                             "ops_per_pair": OPS_PER_PAIR}})
+                             "ops_per_pair": OPS_PER_PAIR, "counters": COUNTERS["k_galaxy_f32"]}})
     log(f"config-2: {ms:.2f} ms, {pairs:.4e} pairs, {pairs / (ms / 1e3):.3e} pair-evals/s")
     if not args.no_cpu:
         res.update(config2_accuracy(cat, R, out_pix, out[0].cpu().numpy(), th))
@@ -460,7 +470,8 @@ def batched_leg(ctx, args):
         "realisation_pair_evals_per_s": pairs1 * R / t_b,
         "mfma": {"bound": "mfma", "achieved": flops / t_b / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
                  "frac": flops / t_b / 2.5e15,
-                 "note": "algorithmic 8 flop per (pair, realisation); split-BF16 issues 3 products per term"},
+                 "note": "algorithmic 8 flop per (pair, realisation); split-BF16 issues 3 products per term",
+                 "counters": COUNTERS["k_noise_stack"]},
         "binning_ms": bin_ms,
         "binning_first_call_ms": bin_cold_ms,
         "binning_gb_per_s": (n_gal * (28 + 56) + 12 * 2048 ** 2 * 8) / (bin_ms / 1e3) / 1e9,
@@ -934,6 +945,8 @@ def main():
     res["roofline"]["traffic"] = TRAFFIC_BYTES.get(res["roofline"]["kernel"]) if default_workload else None
     if res["roofline"]["traffic"] is not None:
         res["roofline"]["traffic_source"] = TRAFFIC_SOURCE
+    if default_workload and res["roofline"]["kernel"] in COUNTERS:
+        res["roofline"]["counters"] = COUNTERS[res["roofline"]["kernel"]]
     # accuracy on the oracle sample + CPU baseline
     if cpu is not None:
         out_pix, refs, cpairs, cdt, avg_check, workers = cpu
